@@ -1,0 +1,345 @@
+"""Pins of the CPU reference against what the paper and the mathematics fix.
+
+Each test names the property and the passage it comes from.  None of them
+re-types the reference's formulas: they check moment identities, exact
+invariants, closed-form wave speeds, exact uniform solutions, symmetry, a
+second formulation of the step in moment space, and numbers the paper prints.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, equilibrium
+from slbm_workloads import geometry as G
+from slbm_workloads import configs
+import closed_forms as CF
+from naive_moment_lbm import NaiveLBM
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def moments_of(f):
+    """rho, j, P of populations f[9, ...] (eq:moments without the S/2 part)."""
+    rho = f.sum(0)
+    jx = np.tensordot(CX, f, 1)
+    jy = np.tensordot(CY, f, 1)
+    pxx = np.tensordot(CX * CX, f, 1)
+    pyy = np.tensordot(CY * CY, f, 1)
+    pxy = np.tensordot(CX * CY, f, 1)
+    return rho, jx, jy, pxx, pyy, pxy
+
+
+# ------------------------------------------------------------- eq:fieq --
+
+def test_equilibrium_has_the_prescribed_moments():
+    """eq:fieq is built so that its moments are rho, j and P (section 3)."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.standard_normal()
+        j = 0.05 * rng.standard_normal(2)
+        P = 0.05 * rng.standard_normal(3)
+        f = equilibrium(rho, j, P)
+        r, jx, jy, pxx, pyy, pxy = moments_of(f[:, None])
+        np.testing.assert_allclose([r[0], jx[0], jy[0], pxx[0], pyy[0], pxy[0]],
+                                   [rho, j[0], j[1], P[0], P[1], P[2]], atol=1e-15, rtol=1e-14)
+
+
+def test_rest_equilibrium_is_the_unstressed_state():
+    """At rest (rho = 1, j = 0, no stress) the Poisson stress is zero
+    (eq:poissonstress), so f_eq = w_i (2 - 3|c_i|^2/2)."""
+    f = equilibrium(1.0, np.zeros(2), np.zeros(3))
+    expect = [8 / 9] + [1 / 18] * 4 + [-1 / 36] * 4
+    np.testing.assert_allclose(f, expect, rtol=0, atol=1e-16)
+
+
+# ------------------------------------------------------------- eq:coll --
+
+def test_collision_conserves_rho_and_P_and_adds_S_to_momentum():
+    """With eq:moments, BGK with the forcing of eq:coll leaves rho and P
+    unchanged and raises sum f c by exactly S.  On a 1x1 periodic lattice the
+    streaming maps every population onto itself and grad rho = 0, so S = F."""
+    F = (2e-4, -3e-4)
+    p = G.periodic_box(1, 1, lam=0.07, mu=0.05, tau=0.55, force=F)
+    o = Oracle(p)
+    rng = np.random.default_rng(2)
+    f0 = equilibrium(1.0, np.zeros(2), np.zeros(3)) + 1e-3 * rng.standard_normal(9)
+    o.set_populations(f0.reshape(9, 1, 1))
+    o.step(1)
+    f1 = o.populations()[:, 0, 0]
+    m0 = moments_of(f0[:, None])
+    m1 = moments_of(f1[:, None])
+    S = np.array(F) / (3 * 0.05)
+    assert abs(m1[0][0] - m0[0][0]) < 1e-15
+    np.testing.assert_allclose([m1[3][0], m1[4][0], m1[5][0]], [m0[3][0], m0[4][0], m0[5][0]], atol=1e-15)
+    np.testing.assert_allclose([m1[1][0] - m0[1][0], m1[2][0] - m0[2][0]], S, rtol=1e-12, atol=1e-17)
+
+
+# ------------------------------------------------------ invariants --
+
+def test_periodic_mass_conservation():
+    """Streaming and collision conserve sum rho exactly in a periodic box
+    (eq:coll, eq:stream), for any lambda/mu."""
+    p = G.periodic_box(24, 20, lam=0.08, mu=0.05, tau=0.6)
+    o = Oracle(p, extended=True)
+    rng = np.random.default_rng(3)
+    o.init_fields(rho=1 + 1e-3 * rng.standard_normal((20, 24)),
+                  vel=1e-3 * rng.standard_normal((2, 20, 24)))
+    m0 = o.moments()[0].sum()
+    o.step(50)
+    assert abs(o.moments()[0].sum() - m0) < 1e-12 * m0
+
+
+def test_periodic_momentum_conservation_when_lambda_equals_mu():
+    """With lambda = mu the source term is F alone (eq:sourceterm), so in a
+    periodic box sum j changes by exactly N F per step."""
+    for F in [(0.0, 0.0), (3e-6, -2e-6)]:
+        p = G.periodic_box(16, 12, lam=0.05, mu=0.05, tau=0.55, force=F)
+        o = Oracle(p, extended=True)
+        rng = np.random.default_rng(4)
+        o.init_fields(vel=1e-3 * rng.standard_normal((2, 12, 16)),
+                      sigma=1e-4 * rng.standard_normal((3, 12, 16)))
+        j0 = o.moments()[1].sum(axis=(1, 2))
+        o.step(40)
+        j1 = o.moments()[1].sum(axis=(1, 2))
+        # user units: j changes by F * dt per step and site
+        dt = math.sqrt(1.0 / (3 * 0.05))
+        np.testing.assert_allclose(j1 - j0, 16 * 12 * 40 * dt * np.array(F), atol=1e-13)
+
+
+# ---------------------------------------------- closed-form wave speeds --
+
+def _phase_speed(lam, mu, tau, pol):
+    """Phase speed of a plane wave k = 2 pi/64 along x in a periodic box,
+    from the zero crossings of the velocity amplitude (in cells per step)."""
+    n = 64
+    p = G.periodic_box(n, 1, lam=lam, mu=mu, tau=tau)
+    o = Oracle(p)
+    x = np.arange(n)
+    v = np.zeros((2, 1, n))
+    v[pol, 0] = 1e-4 * np.sin(2 * np.pi * x / n)
+    o.init_fields(vel=v)
+    s = np.sin(2 * np.pi * x / n)
+    amp = []
+    for _ in range(1400):
+        o.step(1)
+        amp.append(np.dot(o.moments()[1][pol, 0], s))
+    amp = np.array(amp)
+    t = np.arange(1, len(amp) + 1)
+    z = [t[i] - amp[i] / (amp[i + 1] - amp[i]) for i in range(len(amp) - 1) if amp[i] * amp[i + 1] < 0]
+    half = np.diff(z)[2:].mean()          # skip the first crossings (start-up)
+    omega = np.pi / half
+    return omega / (2 * np.pi / n)
+
+
+@pytest.mark.parametrize("lam_over_mu,tau", [(1.0, 0.55), (0.769, 0.55), (2.0, 0.6)])
+def test_plane_wave_speeds_match_the_lame_navier_equation(lam_over_mu, tau):
+    """Lame-Navier (eq:navier): c_s^2 = mu/rho, c_d^2 = (lambda + 2 mu)/rho.
+    In lattice units mu = 1/3 (c_s^2 = 1/3, section 5.1)."""
+    mu_L, lam_L = 1 / 3, lam_over_mu / 3
+    cs, cd = CF.wave_speeds(lam_L, mu_L)
+    c_p = _phase_speed(lam_over_mu * 0.05, 0.05, tau, pol=0)
+    c_s = _phase_speed(lam_over_mu * 0.05, 0.05, tau, pol=1)
+    assert abs(c_p / cd - 1) < 1e-3, (c_p, cd)
+    assert abs(c_s / cs - 1) < 1e-3, (c_s, cs)
+
+
+# ------------------------------------------------- exact uniform states --
+
+def _patch_plate(neumann_order, with_dirichlet):
+    """A plate with straight edges and an off-centre circular hole: every
+    kind of link (q = 1/2, q in (0,1), corners, diagonals)."""
+    n = 30
+    walls = G.edge_walls(n, n, left=0, right=1, bottom=2, top=3)
+    walls.append(G.Circle(13.3, 15.8, 5.7, 4))
+    groups = [G.BCGroup(G.NEUMANN)] * 5
+    p = G.build_plate(n, n, lam=0.08, mu=0.05, tau=0.55, walls=walls, groups=groups,
+                      neumann_order=neumann_order)
+    return p
+
+
+@pytest.mark.parametrize("neumann_order", [1, 0])
+@pytest.mark.parametrize("with_dirichlet", [False, True])
+def test_uniform_state_with_consistent_boundary_data_is_exact(neumann_order, with_dirichlet):
+    """A uniform state (rho0, j0, sigma0) solves the moment chain exactly.
+    With j* = j0 on Dirichlet links and t* = sigma0 n on Neumann links, the
+    bounce-back rules reproduce it for every wall fraction q (the Bouzidi-type
+    terms cancel because l - 2s and 2l enter as (l-2s)/(l+2s) - 2l/(l+2s) = -1),
+    and the displacement grows as t * j0/rho0.  Exact up to rounding."""
+    p = _patch_plate(neumann_order, with_dirichlet)
+    rho0, v0 = 1.0 + 2e-3, np.array([3e-4, -2e-4])
+    sig0 = np.array([[4e-5, -1.5e-5], [-1.5e-5, 2.5e-5]])
+    L = p.links.copy()
+    groups = []
+    rng = np.random.default_rng(5)
+    for i in range(len(L)):
+        # a random mix of Dirichlet and Neumann links, each with its own data
+        dirichlet = with_dirichlet and rng.uniform() < 0.5
+        if dirichlet:
+            groups.append(G.BCGroup(G.DIRICHLET, tuple(v0)))
+        else:
+            groups.append(G.BCGroup(G.NEUMANN, tuple(sig0 @ L["normal"][i])))
+        L["group"][i] = len(groups) - 1
+        if L["group2"][i] >= 0:
+            groups.append(G.BCGroup(G.NEUMANN, tuple(sig0 @ L["normal2"][i])))
+            L["group2"][i] = len(groups) - 1
+    p.links, p.groups = L, groups
+    o = Oracle(p, extended=True)
+    m = p.mask
+    o.init_fields(rho=np.where(m, rho0, 1.0), vel=v0[:, None, None] * m,
+                  sigma=np.array([sig0[0, 0], sig0[1, 1], sig0[0, 1]])[:, None, None] * m)
+    f0 = o.populations()
+    o.step(25)
+    f1 = o.populations()
+    assert np.abs(f1 - f0).max() < 1e-15
+    u = o.displacement()
+    dt = math.sqrt(1 / (3 * 0.05))
+    np.testing.assert_allclose(u[:, m.astype(bool)], (25 * v0 * dt)[:, None] * np.ones((2, int(m.sum()))),
+                               rtol=1e-12)
+
+
+# --------------------------------------------------------- symmetry --
+
+def _loaded_plate(order):
+    n = 36
+    groups = [G.BCGroup(G.DIRICHLET, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (1e-3 * 0.05, 0.0)),
+              G.BCGroup(G.NEUMANN, (0.0, 0.0))]
+    walls = G.edge_walls(n, n, left=0, right=1, bottom=2, top=2)
+    walls.append(G.Circle(20.2, (n - 1) / 2, 6.3, 2))
+    return G.build_plate(n, n, lam=0.04, mu=0.05, tau=0.55, walls=walls, groups=groups,
+                         neumann_order=order)
+
+
+@pytest.mark.parametrize("order", [1, 0])
+def test_mirror_symmetry(order):
+    """The step commutes with reflection about the mid-line: a problem
+    symmetric about y = (ny-1)/2 keeps u_x even and u_y odd."""
+    p = _loaded_plate(order)
+    o = Oracle(p)
+    o.step(120)
+    u = o.displacement()
+    scale = np.abs(u).max()
+    assert scale > 1e-4
+    np.testing.assert_allclose(u[0], u[0, ::-1], atol=1e-11 * scale)
+    np.testing.assert_allclose(u[1], -u[1, ::-1], atol=1e-11 * scale)
+
+
+def test_rotation_equivariance():
+    """Rotating the problem by 90 degrees rotates the solution."""
+    p = _loaded_plate(1)
+    walls = G.edge_walls(p.nx, p.ny, left=0, right=1, bottom=2, top=2)
+    walls.append(G.Circle(20.2, 13.1, 6.3, 2))    # break the mirror symmetry
+    p = G.build_plate(p.nx, p.ny, lam=0.04, mu=0.05, tau=0.55, walls=walls, groups=p.groups)
+    q = G.rotate90(p)
+    a, b = Oracle(p), Oracle(q)
+    a.step(80)
+    b.step(80)
+    ua, ub = a.displacement(), b.displacement()
+    # rotated field: ub[:, x, ny-1-y] = R ua[:, y, x], R (ux, uy) = (-uy, ux)
+    yy, xx = np.mgrid[0:p.ny, 0:p.nx]
+    rot = np.empty_like(ub)
+    rot[0][xx, p.ny - 1 - yy] = -ua[1]
+    rot[1][xx, p.ny - 1 - yy] = ua[0]
+    scale = np.abs(ua).max()
+    np.testing.assert_allclose(ub, rot, atol=1e-11 * scale)
+
+
+# ------------------------------------------- second formulation, tiny --
+
+def _tiny_plate(seed):
+    rng = np.random.default_rng(seed)
+    n = 9
+    groups = []
+    for _ in range(6):
+        if rng.uniform() < 0.4:
+            groups.append(G.BCGroup(G.DIRICHLET, tuple(1e-3 * rng.standard_normal(2)),
+                                    int(rng.integers(0, 2)), float(rng.uniform(3, 20))))
+        else:
+            groups.append(G.BCGroup(G.NEUMANN, tuple(1e-4 * rng.standard_normal(2)),
+                                    int(rng.integers(0, 2)), float(rng.uniform(3, 20))))
+    walls = G.edge_walls(n, n, left=0, right=1, bottom=2, top=3)
+    walls.append(G.Circle(rng.uniform(3.5, 5.5), rng.uniform(3.5, 5.5), rng.uniform(1.2, 2.2), 4))
+    walls.append(G.HLine(7.5, 5, x_lo=-0.5, x_hi=float(rng.integers(2, 5)) - 0.5))
+    return G.build_plate(n, n, lam=rng.uniform(0.5, 2.0) * 0.05, mu=0.05, rho=rng.uniform(0.8, 1.5),
+                         tau=0.6, walls=walls, groups=groups, force=tuple(1e-5 * rng.standard_normal(2)),
+                         neumann_order=int(seed % 2))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_reference_agrees_with_moment_space_formulation(seed):
+    """The population-space reference and an independent moment-space,
+    dict-of-sites formulation of the same step agree on tiny random plates
+    (curved and straight walls, a crack slit, corners, both rule kinds, step
+    and ramp profiles, body force) to rounding."""
+    p = _tiny_plate(seed)
+    o = Oracle(p)
+    nv = NaiveLBM(p)
+    rng = np.random.default_rng(100 + seed)
+    f0 = o.populations() + 1e-3 * rng.standard_normal((9, p.ny, p.nx)) * p.mask
+    o.set_populations(f0)
+    nv.set_f(f0)
+    for _ in range(12):
+        o.step(1)
+        nv.step()
+    np.testing.assert_allclose(o.populations(), nv.get_f(), atol=2e-14)
+
+
+# ------------------------------------------------- 1-D step traction --
+
+def test_step_traction_launches_the_dilatational_wave():
+    """A strip pulled at one end by a step traction sigma0 carries a
+    dilatational wave with particle velocity sigma0/(rho c_d) behind the
+    front, moving at c_d; at a clamped end the stress doubles."""
+    nx, ny = 200, 2
+    mu, lam, load = 0.05, 0.05, 1e-4 * 0.05
+    groups = [G.BCGroup(G.DIRICHLET, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (load, 0.0))]
+    p = G.build_plate(nx, ny, lam=lam, mu=mu, tau=0.55,
+                      walls=G.edge_walls(nx, ny, left=0, right=1), groups=groups, periodic_y=True)
+    o = Oracle(p)
+    cd = math.sqrt((lam + 2 * mu) / 1.0)        # user units (dx = 1)
+    dt = math.sqrt(1.0 / (3 * mu))
+    steps = 100                                  # c_d = 1 cell per step for lambda = mu
+    o.step(steps)
+    rho, j, P, s = o.moments()
+    front = nx - 1 - steps * cd * dt
+    behind = slice(int(front) + 15, nx - 15)
+    v = j[0, 0, behind]
+    # the pulled end moves outward: v = +sigma0/(rho c_d) behind a tensile
+    # wave travelling toward -x ...
+    np.testing.assert_allclose(v, load / cd, rtol=2e-2)
+    np.testing.assert_allclose(s[0, 0, behind], load, rtol=2e-2)
+    ahead = slice(0, int(front) - 15)
+    assert np.abs(j[0, 0, ahead]).max() < 1e-3 * load / cd
+    # ... and after reflection at the clamped end the stress there doubles
+    o.step(220)
+    rho, j, P, s = o.moments()
+    np.testing.assert_allclose(s[0, 0, 5:40], 2 * load, rtol=3e-2)
+
+
+# ------------------------------------------------ unit mapping (paper) --
+
+def test_time_step_matches_the_paper():
+    """(1/sqrt 3) dx/dt = c_s with dx = 0.0125 l gives dt = 7.217e-3 l/c_s
+    (section 5.1), and the speed ratios give the printed Poisson ratios."""
+    g = json.load(open(os.path.join(HERE, "golden", "paper_numbers.json")))
+    p = configs.paper_hole_plate(3.0)
+    o = Oracle(p)
+    dt = o.lattice_params()["dt_user"]
+    l = p.nx * 1.0          # dx = 1 cell = 0.0125 l
+    cs = math.sqrt(p.mu / p.rho)
+    assert abs(dt * cs / l - g["hole_plate_dt_over_l_per_cs"]["value"]) < 5e-7
+    assert abs(CF.nu_from_speed_ratio(g["poisson_solid"]["cd2_over_cs2"]) - g["poisson_solid"]["nu"]) < 1e-12
+    assert abs(CF.nu_from_speed_ratio(g["non_poisson_solid"]["cd2_over_cs2"]) - g["non_poisson_solid"]["nu"]) < 1e-12
+    assert abs(CF.nu_from_speed_ratio(1 / g["crack_solid"]["cs2_over_cd2"]) - g["crack_solid"]["nu"]) < 1e-4
+
+
+def test_rayleigh_root_closed_form():
+    """The Rayleigh equation the paper solves for the surface-wave speed has
+    the classical root c_R = 0.9194 c_s at nu = 1/4."""
+    cs, cd = CF.wave_speeds(1.0, 1.0)
+    assert abs(CF.rayleigh_speed(cs, cd) / cs - 0.91940) < 1e-5
