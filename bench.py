@@ -1,0 +1,170 @@
+"""Throughput of the solid-LBM step on one MI355X.
+
+A bench step is one lattice-Boltzmann time step of the whole plate: pull
+streaming with the boundary rules, moments, density-gradient source term,
+equilibrium, collision, displacement update and the non-finite guard, all in
+the fused kernel.  The default workload is the 1024 x 512 edge-crack plate
+(fp32 populations, fp64 displacement), run for its 10k steps.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  `value` is material-site updates per second (MLUPS)
+with the state resident in HBM; the roofline object relates the fused
+kernel's algorithmic bytes to the 8 TB/s HBM peak; cpu_baseline times the
+plain CPU reference on a bounded sample of the same plate.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from slbm_workloads import configs
+    table = {
+        "crack1024x512": (lambda: configs.edge_crack_plate(), "fp32"),
+        "hole2048": (lambda: configs.hole_plate(), "fp32"),
+        "square128": (lambda: configs.square_clamped_pulled(), "fp64"),
+        "square4096": (lambda: configs.square_clamped_pulled(4096, steps=2000), "fp32"),
+    }
+    if name not in table:
+        raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}")
+    f, prec = table[name]
+    return f(), prec
+
+
+def bytes_per_site(prec):
+    # populations read once and written once, displacement (2 x fp64) read and written once
+    return 9 * 2 * (4 if prec == "fp32" else 8) + 2 * 2 * 8
+
+
+def cpu_baseline(plate, budget_s=12.0):
+    """The plain CPU reference (fp64) on a bounded number of steps of the
+    same plate, all host threads it is allowed."""
+    from oracle import Oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(cores)
+    o = Oracle(plate)
+    t = time.perf_counter()
+    o.step(2)
+    per = (time.perf_counter() - t) / 2
+    n = max(2, int(budget_s / max(per, 1e-9)))
+    t = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t
+    return {"value": round(plate.n_material * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle", "sample": f"{n} steps of {plate.name} ({plate.n_material} material sites) "
+                                        f"from rest, fp64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--workload", default="crack1024x512")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--seg", type=int, default=0, help="rows per wave (0: library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_04088_amd import slbm
+
+    plate, prec = workload(args.workload)
+    prec = args.precision or prec
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
+    if args.seg:
+        s.set_launch(args.seg)
+    s.step(args.warmup)
+    s.sync()
+    torch.cuda.synchronize()
+
+    # timed region: K steps queued back to back on one stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    region_ms = ev0.elapsed_time(ev1)
+
+    # per-launch kernel time: events around single launches
+    n_probe = min(200, max(20, args.steps // 50))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_probe)]
+    for a, b in evs:
+        a.record(stream)
+        s.step(1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    launch_med_ms = launch_ms[len(launch_ms) // 2]
+    s.sync()
+
+    u = s.displacement()
+    import numpy as np
+    assert np.isfinite(u).all()
+
+    sites = plate.n_material
+    t_step = region_ms / 1e3 / args.steps
+    mlups = sites / t_step / 1e6
+    bps = bytes_per_site(prec)
+    traffic_note = None
+    achieved = sites * bps / t_step / 1e9
+    result = {
+        "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": plate.name, "nx": plate.nx, "ny": plate.ny, "material_sites": sites,
+            "precision": "fp32 populations and arithmetic, fp64 displacement" if prec == "fp32" else "fp64",
+            "lambda_over_mu": plate.lam / plate.mu, "tau": plate.tau, "neumann_order": plate.neumann_order,
+            "bench_step": "one lattice-Boltzmann time step of the whole plate",
+            "wall_s": round(wall, 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_note,
+            "kernel": "k_step",
+            "bytes_per_site": bps,
+            "avg_launch_us": round(t_step * 1e6, 3),
+            "single_launch_median_us": round(launch_med_ms * 1e3, 3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(plate)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

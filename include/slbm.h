@@ -1,0 +1,175 @@
+/*
+ * slbm.h -- C ABI of the MI355X solid lattice-Boltzmann library (libslbm.so).
+ *
+ * The library advances plates of isotropic linear-elastic material with the
+ * lattice-Boltzmann method of Faust, Schlueter, H. Mueller and R. Mueller,
+ * "Dirichlet and Neumann boundary conditions in a Lattice Boltzmann Method
+ * for Elastodynamics" (2022).  The problem it accepts is the paper's
+ * statement in section 2: a domain, Lame parameters lambda and mu, density
+ * rho, a body force F, and Dirichlet (eq:bcdir, given as the wall velocity
+ * d(u*)/dt, eq:bcchaindir) or Neumann (eq:bcneu, traction t*) data on the
+ * boundary.  One time step (section 3) is: moments (eq:moments), source term
+ * with the density gradient (eq:sourceterm), equilibrium (eq:fieq), BGK
+ * collision with forcing (eq:coll), streaming (eq:stream), integration of
+ * the displacement from j, and the local boundary rules of section 4 on
+ * every cut link (eq:bbcon/eq:bbnoncon, eq:abbcon/eq:abbnoncon, with the
+ * boundary Poisson stress of eq:trafocauchy, eq:bcchainneum, eq:approxdiv).
+ *
+ * Conventions
+ *   Sites sit at integer coordinates (ix, iy), 0 <= ix < nx, 0 <= iy < ny;
+ *   host arrays are row-major with site index iy*nx + ix.  D2Q9 directions:
+ *   0 (0,0), 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1),
+ *   7 (-1,-1), 8 (1,-1).  A link (x, k) is cut when the segment from x to
+ *   x + c_k crosses a wall; q = s_k/l_k in (0, 1] is the fraction of the link
+ *   between x and the wall (1/2 for a straight wall half-way between sites).
+ *
+ * Units
+ *   User units with dx = 1 cell.  The lattice runs at c_s^2 = 1/3, so the
+ *   time step is dt = sqrt(rho/(3 mu)) (paper, section 5.1).  Stresses and
+ *   tractions scale with 3 mu, velocities with dx/dt.  Displacements are
+ *   returned in cells.
+ *
+ * Ownership and threading
+ *   The library copies every input during slbm_create; the caller may free
+ *   them on return.  It owns all device memory and frees it in slbm_destroy.
+ *   Output buffers belong to the caller.  A handle must not be used from two
+ *   threads at once.  Work is queued on the handle's HIP stream; calls that
+ *   return data to the host synchronise that stream.
+ *
+ * Errors
+ *   Every function returns an slbm_status.  Nothing throws across the ABI.
+ *   slbm_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef SLBM_H
+#define SLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLBM_OK = 0,
+    SLBM_E_INVAL = -1,       /* invalid argument or inconsistent geometry */
+    SLBM_E_NOMEM = -2,       /* device or host allocation failed */
+    SLBM_E_DEVICE = -3,      /* a HIP call failed */
+    SLBM_E_DIVERGED = -4,    /* a non-finite or huge value appeared */
+    SLBM_E_UNSUPPORTED = -5, /* valid request this build does not handle */
+    SLBM_E_BUDGET = -6       /* a batch has no room for the plate */
+} slbm_status;
+
+typedef enum {
+    SLBM_FP64 = 0,           /* fp64 populations and arithmetic */
+    SLBM_FP32 = 1            /* fp32 populations and arithmetic, fp64 displacement */
+} slbm_precision;
+
+typedef enum { SLBM_DIRICHLET = 1, SLBM_NEUMANN = 2 } slbm_bc_kind;
+typedef enum { SLBM_PROFILE_STEP = 0, SLBM_PROFILE_RAMP = 1 } slbm_profile;
+
+/* A boundary-condition group.  DIRICHLET: value = wall velocity d(u*)/dt;
+ * NEUMANN: value = traction t* = sigma n.  Both in user units.  STEP: on
+ * from t = 0.  RAMP: scaled by min(t/ramp_time, 1). */
+typedef struct {
+    int32_t kind;
+    int32_t profile;
+    double value[2];
+    double ramp_time;
+} slbm_bc_group;
+
+/* A cut link (x, dir).  normal is the outward unit normal of the material at
+ * the crossing.  A link through the meeting point of two walls (a plate
+ * corner, the mouth of an edge crack) names the second wall in group2 and
+ * normal2; otherwise group2 = -1.  At such a link a Dirichlet wall wins over
+ * a Neumann one; two Neumann walls fix the whole boundary stress,
+ * sigma* = sym(t_A n_A + t_B n_B). */
+typedef struct {
+    int32_t site;            /* iy*nx + ix of the material site x */
+    int32_t dir;             /* 1..8 */
+    double q;                /* (0, 1] */
+    int32_t group;
+    int32_t group2;
+    double normal[2];
+    double normal2[2];
+} slbm_link;
+
+typedef struct {
+    int32_t nx, ny;
+    double lambda, mu, rho;  /* user units, dx = 1 cell */
+    double tau;              /* BGK relaxation time in units of dt, > 1/2 */
+    double body_force[2];    /* uniform body force per volume, user units */
+    int32_t periodic_x, periodic_y;  /* 1: wrap; cut links never cross a periodic seam */
+    int32_t precision;       /* slbm_precision */
+    int32_t neumann_order;   /* 1: boundary density and tangential stress
+                                extrapolated along the link (the paper's rule);
+                                0: taken at the boundary site */
+    const uint8_t* mask;     /* [ny*nx] 1 = material */
+    int32_t n_links;
+    const slbm_link* links;  /* every cut link of every material site, any order */
+    int32_t n_groups;
+    const slbm_bc_group* groups;
+    int32_t device;          /* HIP device ordinal */
+    void* stream;            /* hipStream_t to queue work on; NULL: the library's own */
+} slbm_params;
+
+typedef struct slbm_s* slbm_handle;
+
+/* Validates and copies the problem, uploads it and sets the rest state
+ * (zero displacement and velocity, unstressed).  SLBM_E_INVAL when a cut link
+ * names a void site, an uncut link leaves the material, q is outside (0, 1],
+ * a normal is not a unit vector, a group index is out of range, tau <= 1/2,
+ * or mu, rho <= 0. */
+int slbm_create(const slbm_params* params, slbm_handle* out);
+
+/* Replaces the state by the equilibrium of given fields (section 2: P from
+ * eq:poissonstress with div u from eq:approxdiv; j = rho v).  Host arrays in
+ * user units, each may be NULL for its rest value: rho [n], vel [2][n],
+ * sigma [3][n] (xx, yy, xy), u [2][n] cells.  Resets the step counter. */
+int slbm_init_fields(slbm_handle h, const double* rho, const double* vel,
+                     const double* sigma, const double* u);
+
+/* Queues nsteps time steps on the handle's stream and returns. */
+int slbm_step(slbm_handle h, int64_t nsteps);
+
+/* Waits for queued work; SLBM_E_DIVERGED once any step produced a value
+ * that is not finite (checked on every site at every step). */
+int slbm_sync(slbm_handle h);
+
+/* Moments of the current state in user units, host arrays [n] / [2][n] /
+ * [3][n] (xx, yy, xy); any pointer may be NULL.  j includes the S/2 part of
+ * eq:moments; sigma = -P + (lambda - mu)(rho0 - rho)/rho0 I.  Void sites
+ * read zero.  Synchronises. */
+int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma);
+
+/* Displacement [2][n] in cells: the integral of j/rho with the trapezoid
+ * rule.  Synchronises. */
+int slbm_displacement(slbm_handle h, double* u);
+
+/* Same as slbm_displacement into device memory u_dev ([2][n] doubles) on
+ * the handle's stream, without synchronising. */
+int slbm_displacement_device(slbm_handle h, void* u_dev);
+
+/* Step count and physical time of the current state. */
+int slbm_time(slbm_handle h, int64_t* step, double* t_user);
+
+/* Launch shape of the fused step: rows per wave (seg_rows >= 1).  0 keeps
+ * the library's choice.  Results do not depend on it. */
+int slbm_set_launch(slbm_handle h, int32_t seg_rows);
+
+/* Checkpoint: the full state in an opaque buffer.  With buf = NULL,
+ * slbm_save only reports the size in *bytes. */
+int slbm_save(slbm_handle h, void* buf, size_t* bytes);
+int slbm_load(slbm_handle h, const void* buf, size_t bytes);
+
+/* HBM bytes the handle holds on the device. */
+int slbm_device_bytes(slbm_handle h, int64_t* bytes);
+
+int slbm_destroy(slbm_handle h);
+
+const char* slbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

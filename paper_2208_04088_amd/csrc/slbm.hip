@@ -1,0 +1,1168 @@
+// slbm.hip -- solid lattice-Boltzmann step for MI355X (gfx950) behind the C
+// ABI declared in include/slbm.h.
+//
+// Method: Faust, Schlueter, H. Mueller, R. Mueller, "Dirichlet and Neumann
+// boundary conditions in a Lattice Boltzmann Method for Elastodynamics"
+// (2022), sections 2-4.  See include/slbm.h for the problem statement and
+// conventions.
+//
+// Data layout in HBM (one plate):
+//   populations  two buffers of [9][ny][ld] `real`, structure of arrays, row
+//                pitch ld = nx rounded up to 64 elements.  They hold shifted
+//                populations g_i = f_i - r_i, r_i the rest equilibrium
+//                (8/9, 1/18 x4, -1/36 x4), so that fp32 resolves the small
+//                deviation from rest instead of the O(1) rest values.
+//   U            [2][ny][ld] double, the running sum of j/rho.
+//   flags        [ny][ld] uint8: 0 = material site with no cut link,
+//                0xFF = no state (void or padding), otherwise bit k-1 set
+//                when the link toward x + c_k is cut.
+//   bidx         [ny][ld] int32, index of the site's first cut-link record
+//                (read only at boundary sites).
+//   links        one record per cut link, sorted by (site, direction), with
+//                the coefficients of its boundary rule precomputed.
+//
+// A buffer holds, after a step, the post-collision populations of that step
+// at their own site.  The next step pulls g_i(x) from x - c_i and, for a cut
+// link (x, k), evaluates the boundary rule of section 4 from the
+// post-collision values at x and x - c_k -- the rule the paper applies right
+// after streaming, moved to the start of the next step so that streaming,
+// boundary rules, moments, collision and displacement update are one pass
+// over HBM.  Density and Poisson stress at time t, which the Neumann rule
+// needs, are sums of post-collision populations because the collision
+// conserves both.  After slbm_create or slbm_init_fields a buffer holds the
+// populations themselves ("local" state) and the first step reads them in
+// place.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "slbm.h"
+
+namespace {
+
+// ------------------------------------------------------------------ errors
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(SLBM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ----------------------------------------------------------------- lattice
+
+// D2Q9 velocities, paper section 3 (numbering as in include/slbm.h).
+__host__ __device__ constexpr int CX(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0); }
+__host__ __device__ constexpr int CY(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
+__host__ __device__ constexpr int OPP(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5); }
+__host__ __device__ constexpr double WD(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+constexpr int kStrip = 62;     // output columns per wave (64 lanes, one halo lane each side)
+constexpr unsigned kVoid = 0xFFu;
+
+struct GroupDev {
+    int32_t profile;           // SLBM_PROFILE_*
+    int32_t pad;
+    double ramp_steps;         // ramp length in steps
+};
+
+// Coefficients of the boundary rule of one cut link (x, k); see build_links.
+template <typename real>
+struct LinkDev {
+    real kappa;                // (l - 2s)/(l + 2s), 0 with no site behind x
+    real wx, wy;               // weights of rho and sigma_tt at x and x - c_k
+    real D;                    // Dirichlet: -beta (2/c_s^2) w_k c_k.v
+    real be[4];                // Neumann: beta d(E_k - 2 r_k)/d(drho_bd, Pxx*, Pyy*, Pxy*)
+    real K1[3], K2[3], E3[3];  // Neumann: known boundary stress per unit profile; e_t e_t
+    int32_t g1, g2;            // groups whose profiles scale D or K1, K2
+    int32_t kind;              // SLBM_DIRICHLET | SLBM_NEUMANN
+    int32_t behind;            // 1: x - c_k is a material site reached by an uncut link
+    int32_t k, dx, dy, pad;
+};
+
+template <typename real>
+struct StepArgs {
+    const real* src;
+    real* dst;
+    double* U;
+    const uint8_t* flags;
+    const int32_t* bidx;
+    const LinkDev<real>* links;
+    const GroupDev* groups;
+    unsigned int* diverged;
+    long long plane;           // ny * ld
+    long long t_prev;          // step whose post-collision state src holds
+    int nx, ny, ld;
+    int seg, nstrips, ntiles;
+    int px, py;
+    int local;                 // src holds the populations themselves
+    real omega, cpsi;          // 1/tau, 1 - 1/(2 tau)
+    real lm, ml;               // lambda - mu, mu - lambda (lattice units)
+    real Fx, Fy;
+};
+
+template <typename real>
+__device__ __forceinline__ real profile_at(const GroupDev* g, int gi, long long t)
+{
+    const GroupDev G = g[gi];
+    if (G.profile == SLBM_PROFILE_RAMP) {
+        real r = real((double)t / G.ramp_steps);
+        return r < real(1) ? r : real(1);
+    }
+    return real(1);
+}
+
+// Shifted equilibrium g_eq,i = f_eq,i - r_i of eq:fieq, drho = rho - 1:
+// w_i [drho (2 - 3|c|^2/2) + 3 c.j + 9/2 (Pxx (cx^2 - 1/3) + Pyy (cy^2 - 1/3) + 2 Pxy cx cy)]
+template <int i, typename real>
+__device__ __forceinline__ real geq(real dr, real jx, real jy, real pxx, real pyy, real pxy)
+{
+    constexpr int cx = CX(i), cy = CY(i);
+    constexpr double w = WD(i);
+    constexpr double a0 = w * (2.0 - 1.5 * (cx * cx + cy * cy));
+    constexpr double ax = 3.0 * w * cx, ay = 3.0 * w * cy;
+    constexpr double axx = 4.5 * w * (cx * cx - 1.0 / 3.0);
+    constexpr double ayy = 4.5 * w * (cy * cy - 1.0 / 3.0);
+    constexpr double axy = 9.0 * w * cx * cy;
+    real v = real(a0) * dr;
+    if (cx != 0) v += real(ax) * jx;
+    if (cy != 0) v += real(ay) * jy;
+    v += real(axx) * pxx + real(ayy) * pyy;
+    if (cx * cy != 0) v += real(axy) * pxy;
+    return v;
+}
+
+template <typename real>
+__device__ __forceinline__ void moments9(const real g[9], real& dr, real& jx, real& jy,
+                                         real& pxx, real& pyy, real& pxy)
+{
+    // eq:moments on shifted populations (the rest state has rho = 1, j = 0, P = 0)
+    const real d57 = g[5] + g[7], d68 = g[6] + g[8];
+    dr = g[0] + g[1] + g[2] + g[3] + g[4] + d57 + d68;
+    jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
+    jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
+    pxx = g[1] + g[3] + d57 + d68;
+    pyy = g[2] + g[4] + d57 + d68;
+    pxy = d57 - d68;
+}
+
+template <bool PER>
+__device__ __forceinline__ int wrap_off(int x, int y, int dx, int dy, int nx, int ny, int ld, int px, int py)
+{
+    int xx = x + dx, yy = y + dy;
+    if (PER) {
+        if (px) xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+        if (py) yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    }
+    return yy * ld + xx;
+}
+
+// Moments of the post-collision populations stored at site offset s.
+template <typename real>
+__device__ __forceinline__ void stored_moments(const StepArgs<real>& a, int s, real& dr,
+                                               real& pxx, real& pyy, real& pxy)
+{
+    real h[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) h[j] = a.src[j * a.plane + s];
+    real jx, jy;
+    moments9(h, dr, jx, jy, pxx, pyy, pxy);
+}
+
+// The boundary rule of section 4 for the cut link (x, k): the population
+// arriving at x in direction kbar at the current step, from the post-collision
+// state of the previous step (time t_prev).
+template <typename real, bool PER>
+__device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, int x, int y, int s,
+                               real drx, real pxxx, real pyyx, real pxyx)
+{
+    const int k = L.k, kb = OPP(k);
+    const real gk = a.src[k * a.plane + s];
+    const real gkb = a.src[kb * a.plane + s];
+    int sb = 0;
+    real gky = real(0);
+    if (L.behind) {
+        sb = wrap_off<PER>(x, y, -L.dx, -L.dy, a.nx, a.ny, a.ld, a.px, a.py);
+        gky = a.src[k * a.plane + sb];
+    }
+    if (L.kind == SLBM_DIRICHLET) {
+        // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
+        const real p = profile_at<real>(a.groups, L.g1, a.t_prev);
+        return gk + L.kappa * (gky - gkb) + L.D * (real(1) + drx) * p;
+    }
+    // eq:abbcon / eq:abbnoncon.  Cauchy stress from the Poisson stress with the
+    // divergence approximation (eq:poissonstress, eq:approxdiv):
+    // sigma = -P - (lambda - mu) drho I.
+    real drbd = L.wx * drx;
+    real stt = L.wx * (L.E3[0] * (-pxxx - a.lm * drx) + L.E3[1] * (-pyyx - a.lm * drx)
+                       - real(2) * L.E3[2] * pxyx);
+    if (L.wy != real(0)) {
+        real dry, pxxy, pyyy, pxyy;
+        stored_moments(a, sb, dry, pxxy, pyyy, pxyy);
+        drbd += L.wy * dry;
+        stt += L.wy * (L.E3[0] * (-pxxy - a.lm * dry) + L.E3[1] * (-pyyy - a.lm * dry)
+                       - real(2) * L.E3[2] * pxyy);
+    }
+    const real p1 = profile_at<real>(a.groups, L.g1, a.t_prev);
+    const real p2 = L.g2 >= 0 ? profile_at<real>(a.groups, L.g2, a.t_prev) : real(0);
+    // boundary Cauchy stress (eq:trafocauchy) and Poisson stress (eq:bcchainneum)
+    const real sxx = p1 * L.K1[0] + p2 * L.K2[0] + stt * L.E3[0];
+    const real syy = p1 * L.K1[1] + p2 * L.K2[1] + stt * L.E3[1];
+    const real sxy = p1 * L.K1[2] + p2 * L.K2[2] + stt * L.E3[2];
+    const real Pxx = -sxx - a.lm * drbd;
+    const real Pyy = -syy - a.lm * drbd;
+    const real Pxy = -sxy;
+    return -gk - L.kappa * (gky + gkb) + L.be[0] * drbd + L.be[1] * Pxx + L.be[2] * Pyy + L.be[3] * Pxy;
+}
+
+// Populations at site (x, y) for the current step.  Returns false for sites
+// without state.  x, y are in range (wrapped by the caller where periodic).
+template <typename real, bool PER>
+__device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y, real g[9], unsigned& flo)
+{
+    const int s = y * a.ld + x;
+    const unsigned fl = a.flags[s];
+    flo = fl;
+    if (fl == kVoid) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = real(0);
+        return false;
+    }
+    if (a.local) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = a.src[i * a.plane + s];
+        return true;
+    }
+    if (fl == 0) {
+        // bulk site: eq:stream as a pull from x - c_i
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            g[i] = a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
+        return true;
+    }
+    // boundary site: pull along uncut links, rules on cut ones
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int k = OPP(i);
+        const bool cut = (i != 0) && ((fl >> (k - 1)) & 1u);
+        g[i] = cut ? real(0)
+                   : a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
+    }
+    real drx, pxxx, pyyx, pxyx;
+    stored_moments(a, s, drx, pxxx, pyyx, pxyx);
+    int li = a.bidx[s];
+    unsigned m = fl;
+    while (m) {
+        const int k = __builtin_ctz(m) + 1;
+        m &= m - 1;
+        const LinkDev<real> L = a.links[li++];
+        const real v = boundary_value<real, PER>(a, L, x, y, s, drx, pxxx, pyyx, pxyx);
+        const int i = OPP(k);
+#pragma unroll
+        for (int j = 1; j < 9; ++j)
+            if (j == i) g[j] = v;
+    }
+    return true;
+}
+
+// Row loader of the sliding window: state of site (x, y) or "no state".
+template <typename real, bool PER>
+__device__ __forceinline__ bool fetch_row(const StepArgs<real>& a, int x, bool xin, int y, real g[9],
+                                          unsigned& fl, real& dr)
+{
+    bool ok = xin;
+    if (y < 0 || y >= a.ny) {
+        if (PER && a.py) y = y < 0 ? y + a.ny : y - a.ny;
+        else ok = false;
+    }
+    if (ok) ok = fetch_site<real, PER>(a, x, y, g, fl);
+    if (!ok) {
+        fl = kVoid;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = real(0);
+        dr = real(0);
+        return false;
+    }
+    dr = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+    return true;
+}
+
+// One time step of the whole lattice (section 3 and section 4).  One wave per
+// workgroup; a wave owns a strip of 62 columns (lanes 1..62, lanes 0 and 63
+// only supply density to the gradient stencil) and marches up `seg` rows,
+// keeping the densities of three rows in registers for the stencil.
+template <typename real, bool PER>
+__global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
+{
+    const int lane = threadIdx.x;
+    const int B = gridDim.x;                  // a multiple of 8
+    const int b = blockIdx.x;
+    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous band of tiles so that shared halo rows and columns stay in
+    // one L2
+    const int tile = (b & 7) * (B >> 3) + (b >> 3);
+    if (tile >= a.ntiles) return;
+    const int strip = tile % a.nstrips;
+    const int segm = tile / a.nstrips;
+    const int x0 = strip * kStrip - 1 + lane;
+    int x = x0;
+    bool xin = x >= 0 && x < a.nx;
+    if (PER && a.px && !xin) {
+        x = x < 0 ? x + a.nx : x - a.nx;
+        xin = x >= 0 && x < a.nx;
+    }
+    const bool out = lane >= 1 && lane <= kStrip && x0 < a.nx;
+    const int y0 = segm * a.seg;
+    const int y1 = min(y0 + a.seg, a.ny);
+
+    real g[9], gn[9];
+    unsigned fl, fln;
+    real rm, rc, rp;
+    fetch_row<real, PER>(a, x, xin, y0 - 1, gn, fln, rm);
+    bool vc = fetch_row<real, PER>(a, x, xin, y0, g, fl, rc);
+    real rm_l = __shfl_up(rm, 1), rm_r = __shfl_down(rm, 1);
+    real rc_l = __shfl_up(rc, 1), rc_r = __shfl_down(rc, 1);
+    bool bad = false;
+
+    for (int y = y0; y < y1; ++y) {
+        const bool vn = fetch_row<real, PER>(a, x, xin, y + 1, gn, fln, rp);
+        const real rp_l = __shfl_up(rp, 1), rp_r = __shfl_down(rp, 1);
+        if (out && vc) {
+            real dr, jx, jy, pxx, pyy, pxy;
+            moments9(g, dr, jx, jy, pxx, pyy, pxy);
+            // eq:sourceterm: isotropic D2Q9 gradient of rho; across a cut link
+            // the neighbour is extrapolated from the opposite side
+            real nb[9];
+            nb[1] = rc_r; nb[2] = rp; nb[3] = rc_l; nb[4] = rm;
+            nb[5] = rp_r; nb[6] = rp_l; nb[7] = rm_l; nb[8] = rm_r;
+            real rt[9];
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const bool ci = (fl >> (i - 1)) & 1u;
+                const bool co = (fl >> (OPP(i) - 1)) & 1u;
+                rt[i] = ci ? (co ? dr : real(2) * dr - nb[OPP(i)]) : nb[i];
+            }
+            const real gx = real(1.0 / 3.0) * (rt[1] - rt[3]) + real(1.0 / 12.0) * (rt[5] - rt[6] - rt[7] + rt[8]);
+            const real gy = real(1.0 / 3.0) * (rt[2] - rt[4]) + real(1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
+            const real rho = real(1) + dr;
+            const real c = a.ml / rho;
+            const real Sx = a.Fx + c * gx, Sy = a.Fy + c * gy;
+            jx += real(0.5) * Sx;
+            jy += real(0.5) * Sy;
+            // eq:coll with eq:fieq and psi_i = w_i c_i.S / c_s^2
+            real e[9];
+            e[0] = geq<0>(dr, jx, jy, pxx, pyy, pxy);
+            e[1] = geq<1>(dr, jx, jy, pxx, pyy, pxy);
+            e[2] = geq<2>(dr, jx, jy, pxx, pyy, pxy);
+            e[3] = geq<3>(dr, jx, jy, pxx, pyy, pxy);
+            e[4] = geq<4>(dr, jx, jy, pxx, pyy, pxy);
+            e[5] = geq<5>(dr, jx, jy, pxx, pyy, pxy);
+            e[6] = geq<6>(dr, jx, jy, pxx, pyy, pxy);
+            e[7] = geq<7>(dr, jx, jy, pxx, pyy, pxy);
+            e[8] = geq<8>(dr, jx, jy, pxx, pyy, pxy);
+            const real px1 = a.cpsi * real(1.0 / 3.0) * Sx, py1 = a.cpsi * real(1.0 / 3.0) * Sy;
+            const real pd = a.cpsi * real(1.0 / 12.0);
+            real psi[9];
+            psi[0] = real(0);
+            psi[1] = px1; psi[3] = -px1; psi[2] = py1; psi[4] = -py1;
+            psi[5] = pd * (Sx + Sy); psi[7] = -psi[5];
+            psi[6] = pd * (Sy - Sx); psi[8] = -psi[6];
+            const int s = y * a.ld + x;
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                a.dst[i * a.plane + s] = g[i] + a.omega * (e[i] - g[i]) + psi[i];
+            // displacement: U += j/rho (fp64 accumulation)
+            const double ir = 1.0 / (double)rho;
+            a.U[s] += (double)jx * ir;
+            a.U[a.plane + s] += (double)jy * ir;
+            bad |= !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
+        }
+        rm = rc; rm_l = rc_l; rm_r = rc_r;
+        rc = rp; rc_l = rp_l; rc_r = rp_r;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = gn[i];
+        fl = fln;
+        vc = vn;
+    }
+    if (bad) atomicOr(a.diverged, 1u);
+}
+
+// ------------------------------------------------------ output kernels
+
+// delta-rho of the current state at every site (0 where there is no state).
+template <typename real, bool PER>
+__global__ __launch_bounds__(256) void k_density(StepArgs<real> a, double* dr_out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ny * a.ld) return;
+    const int y = idx / a.ld, x = idx - y * a.ld;
+    double v = 0.0;
+    if (x < a.nx) {
+        real g[9];
+        unsigned fl;
+        if (fetch_site<real, PER>(a, x, y, g, fl)) {
+            double s = 0.0;
+            for (int i = 0; i < 9; ++i) s += (double)g[i];
+            v = s;
+        }
+    }
+    dr_out[idx] = v;
+}
+
+// Density-gradient stencil at a site from a delta-rho field (same closure as
+// the step kernel).
+template <bool PER>
+__device__ void grad_rho(const double* dr, const uint8_t* flags, int x, int y, int nx, int ny, int ld,
+                         int px, int py, double& gx, double& gy)
+{
+    const unsigned fl = flags[y * ld + x];
+    const double d0 = dr[y * ld + x];
+    double nb[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const bool ci = (fl >> (i - 1)) & 1u;
+        nb[i] = ci ? 0.0 : dr[wrap_off<PER>(x, y, CX(i), CY(i), nx, ny, ld, px, py)];
+    }
+    double rt[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const bool ci = (fl >> (i - 1)) & 1u;
+        const bool co = (fl >> (OPP(i) - 1)) & 1u;
+        rt[i] = ci ? (co ? d0 : 2.0 * d0 - nb[OPP(i)]) : nb[i];
+    }
+    gx = (1.0 / 3.0) * (rt[1] - rt[3]) + (1.0 / 12.0) * (rt[5] - rt[6] - rt[7] + rt[8]);
+    gy = (1.0 / 3.0) * (rt[2] - rt[4]) + (1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
+}
+
+// Lattice-unit moments and displacement: out[11][ny][ld] =
+// rho, jx, jy, Pxx, Pyy, Pxy, sxx, syy, sxy, ux, uy.
+template <typename real, bool PER>
+__global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double* dr, double* out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long P = (long long)a.ny * a.ld;
+    if (idx >= P) return;
+    const int y = idx / a.ld, x = idx - y * a.ld;
+    double o[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < a.nx && a.flags[idx] != kVoid) {
+        real g[9];
+        unsigned fl;
+        fetch_site<real, PER>(a, x, y, g, fl);
+        double gd[9];
+        for (int i = 0; i < 9; ++i) gd[i] = (double)g[i];
+        double d, jx, jy, pxx, pyy, pxy;
+        moments9(gd, d, jx, jy, pxx, pyy, pxy);
+        double gx, gy;
+        grad_rho<PER>(dr, a.flags, x, y, a.nx, a.ny, a.ld, a.px, a.py, gx, gy);
+        const double rho = 1.0 + d;
+        const double c = (double)a.ml / rho;
+        jx += 0.5 * ((double)a.Fx + c * gx);
+        jy += 0.5 * ((double)a.Fy + c * gy);
+        const double lm = (double)a.lm;
+        o[0] = rho; o[1] = jx; o[2] = jy; o[3] = pxx; o[4] = pyy; o[5] = pxy;
+        o[6] = -pxx - lm * d; o[7] = -pyy - lm * d; o[8] = -pxy;
+        // trapezoid readout: U holds u0 - v0/2 + sum of earlier j/rho
+        o[9] = a.U[idx] + 0.5 * jx / rho;
+        o[10] = a.U[P + idx] + 0.5 * jy / rho;
+    }
+    for (int c = 0; c < 11; ++c) out[c * P + idx] = o[c];
+}
+
+// Displacement into a caller's unpadded [2][ny][nx] device array.
+__global__ __launch_bounds__(256) void k_unpad_u(const double* out, int nx, int ny, int ld, double* u)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nx * ny) return;
+    const int y = idx / nx, x = idx - y * nx;
+    const long long P = (long long)ny * ld;
+    u[idx] = out[9 * P + (long long)y * ld + x];
+    u[(long long)nx * ny + idx] = out[10 * P + (long long)y * ld + x];
+}
+
+// ------------------------------------------------------- initial state
+
+// Equilibrium of given lattice-unit fields (drho, j, P) with j the physical
+// momentum: the populations carry j - S/2 so that eq:moments returns j.
+template <typename real, bool PER>
+__global__ __launch_bounds__(256) void k_init(StepArgs<real> a, const double* dr, const double* jf,
+                                              const double* Pf, const double* uf, real* g_out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long P = (long long)a.ny * a.ld;
+    if (idx >= P) return;
+    const int y = idx / a.ld, x = idx - y * a.ld;
+    double gi[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double ux = 0, uy = 0;
+    if (x < a.nx && a.flags[idx] != kVoid) {
+        double gx, gy;
+        grad_rho<PER>(dr, a.flags, x, y, a.nx, a.ny, a.ld, a.px, a.py, gx, gy);
+        const double d = dr[idx], rho = 1.0 + d;
+        const double c = (double)a.ml / rho;
+        const double Sx = (double)a.Fx + c * gx, Sy = (double)a.Fy + c * gy;
+        const double jx = jf[idx], jy = jf[P + idx];
+        const double rx = jx - 0.5 * Sx, ry = jy - 0.5 * Sy;
+        const double pxx = Pf[idx], pyy = Pf[P + idx], pxy = Pf[2 * P + idx];
+        gi[0] = geq<0>(d, rx, ry, pxx, pyy, pxy);
+        gi[1] = geq<1>(d, rx, ry, pxx, pyy, pxy);
+        gi[2] = geq<2>(d, rx, ry, pxx, pyy, pxy);
+        gi[3] = geq<3>(d, rx, ry, pxx, pyy, pxy);
+        gi[4] = geq<4>(d, rx, ry, pxx, pyy, pxy);
+        gi[5] = geq<5>(d, rx, ry, pxx, pyy, pxy);
+        gi[6] = geq<6>(d, rx, ry, pxx, pyy, pxy);
+        gi[7] = geq<7>(d, rx, ry, pxx, pyy, pxy);
+        gi[8] = geq<8>(d, rx, ry, pxx, pyy, pxy);
+        ux = uf[idx] - 0.5 * jx / rho;
+        uy = uf[P + idx] - 0.5 * jy / rho;
+    }
+    for (int i = 0; i < 9; ++i) g_out[i * P + idx] = (real)gi[i];
+    a.U[idx] = ux;
+    a.U[P + idx] = uy;
+}
+
+}  // namespace
+
+// ======================================================= host side (C ABI)
+
+struct slbm_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int nx = 0, ny = 0, ld = 0;
+    long long plane = 0;
+    int precision = SLBM_FP64;
+    int px = 0, py = 0, norder = 1;
+    double lamL = 0, muL = 1.0 / 3.0, tau = 0.55, FL[2] = {0, 0};
+    double dt_user = 1, s_sigma = 1, s_v = 1, rho_user = 1;
+    size_t esize = 8;
+    void* buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    double* U = nullptr;
+    uint8_t* flags = nullptr;
+    int32_t* bidx = nullptr;
+    void* links = nullptr;
+    GroupDev* groups = nullptr;
+    unsigned int* diverged = nullptr;
+    double* scratch = nullptr;       // outputs and initial fields, allocated on demand
+    int n_links = 0;
+    int64_t step = 0;
+    bool local = true;
+    int seg = 0;
+    std::vector<uint8_t> mask;
+};
+
+namespace {
+
+int pick_seg(const slbm_s* h)
+{
+    if (h->seg > 0) return h->seg;
+    // aim for at least ~8 waves per CU on 256 CUs, rows per wave in [4, 64]
+    const int nstrips = (h->nx + kStrip - 1) / kStrip;
+    const long long target = 8LL * 256;
+    long long segs = (target + nstrips - 1) / nstrips;
+    int seg = (int)std::max<long long>(1, (h->ny + segs - 1) / segs);
+    return std::min(64, std::max(4, seg));
+}
+
+template <typename real>
+StepArgs<real> make_args(const slbm_s* h, int src)
+{
+    StepArgs<real> a{};
+    a.src = (const real*)h->buf[src];
+    a.dst = (real*)h->buf[src ^ 1];
+    a.U = h->U;
+    a.flags = h->flags;
+    a.bidx = h->bidx;
+    a.links = (const LinkDev<real>*)h->links;
+    a.groups = h->groups;
+    a.diverged = h->diverged;
+    a.plane = h->plane;
+    a.t_prev = h->step - 1;
+    a.nx = h->nx; a.ny = h->ny; a.ld = h->ld;
+    a.seg = pick_seg(h);
+    a.nstrips = (h->nx + kStrip - 1) / kStrip;
+    a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
+    a.px = h->px; a.py = h->py;
+    a.local = h->local ? 1 : 0;
+    a.omega = (real)(1.0 / h->tau);
+    a.cpsi = (real)(1.0 - 0.5 / h->tau);
+    a.lm = (real)(h->lamL - h->muL);
+    a.ml = (real)(h->muL - h->lamL);
+    a.Fx = (real)h->FL[0];
+    a.Fy = (real)h->FL[1];
+    return a;
+}
+
+template <typename real>
+int launch_step(slbm_s* h)
+{
+    StepArgs<real> a = make_args<real>(h, h->cur);
+    const int grid = ((a.ntiles + 7) / 8) * 8;
+    if (h->px || h->py)
+        hipLaunchKernelGGL((k_step<real, true>), dim3(grid), dim3(64), 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_step<real, false>), dim3(grid), dim3(64), 0, h->stream, a);
+    HIP_TRY(hipGetLastError());
+    h->cur ^= 1;
+    h->local = false;
+    h->step += 1;
+    return SLBM_OK;
+}
+
+int ensure_scratch(slbm_s* h)
+{
+    if (h->scratch) return SLBM_OK;
+    HIP_TRY(hipMalloc((void**)&h->scratch, (size_t)12 * h->plane * sizeof(double)));
+    return SLBM_OK;
+}
+
+// outputs in lattice units into scratch[1..11]; scratch[0] holds delta-rho
+template <typename real>
+int launch_outputs(slbm_s* h)
+{
+    int rc = ensure_scratch(h);
+    if (rc) return rc;
+    StepArgs<real> a = make_args<real>(h, h->cur);
+    const int n = (int)h->plane;
+    const int grid = (n + 255) / 256;
+    double* dr = h->scratch;
+    double* out = h->scratch + h->plane;
+    if (h->px || h->py) {
+        hipLaunchKernelGGL((k_density<real, true>), dim3(grid), dim3(256), 0, h->stream, a, dr);
+        hipLaunchKernelGGL((k_outputs<real, true>), dim3(grid), dim3(256), 0, h->stream, a, dr, out);
+    } else {
+        hipLaunchKernelGGL((k_density<real, false>), dim3(grid), dim3(256), 0, h->stream, a, dr);
+        hipLaunchKernelGGL((k_outputs<real, false>), dim3(grid), dim3(256), 0, h->stream, a, dr, out);
+    }
+    HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
+int outputs(slbm_s* h)
+{
+    return h->precision == SLBM_FP32 ? launch_outputs<float>(h) : launch_outputs<double>(h);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+void free_all(slbm_s* h)
+{
+    for (void*& p : h->buf) { if (p) (void)hipFree(p); p = nullptr; }
+    if (h->U) (void)hipFree(h->U);
+    if (h->flags) (void)hipFree(h->flags);
+    if (h->bidx) (void)hipFree(h->bidx);
+    if (h->links) (void)hipFree(h->links);
+    if (h->groups) (void)hipFree(h->groups);
+    if (h->diverged) (void)hipFree(h->diverged);
+    if (h->scratch) (void)hipFree(h->scratch);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+template <typename real>
+void fill_link(LinkDev<real>& d, const slbm_link& l, bool behind, const slbm_params* p, const slbm_s* h)
+{
+    // Coefficients of the section 4 rules for link (x, k), in lattice units.
+    const int k = l.dir;
+    const double q = l.q;
+    const double cx = CX(k), cy = CY(k), w = WD(k);
+    const double kappa = behind ? (1.0 - 2.0 * q) / (1.0 + 2.0 * q) : 0.0;
+    const double beta = behind ? 2.0 / (1.0 + 2.0 * q) : 1.0;
+    std::memset(&d, 0, sizeof d);
+    d.k = k; d.dx = (int)cx; d.dy = (int)cy;
+    d.behind = behind ? 1 : 0;
+    d.kappa = (real)kappa;
+    d.g2 = -1;
+    const slbm_bc_group& G1 = p->groups[l.group];
+    const slbm_bc_group* G2 = l.group2 >= 0 ? &p->groups[l.group2] : nullptr;
+    int gd = -1;
+    if (G1.kind == SLBM_DIRICHLET) gd = l.group;
+    else if (G2 && G2->kind == SLBM_DIRICHLET) gd = l.group2;
+    if (gd >= 0) {
+        const slbm_bc_group& G = p->groups[gd];
+        const double vx = G.value[0] / h->s_v, vy = G.value[1] / h->s_v;
+        d.kind = SLBM_DIRICHLET;
+        d.g1 = gd;
+        d.D = (real)(-beta * 6.0 * w * (cx * vx + cy * vy));
+        return;
+    }
+    d.kind = SLBM_NEUMANN;
+    const bool extrap = behind && h->norder == 1;
+    d.wx = (real)(extrap ? 1.0 + q : 1.0);
+    d.wy = (real)(extrap ? -q : 0.0);
+    // d(E_k - 2 r_k)/d(drho_bd, Pxx, Pyy, Pxy), E_k of eq:abbcon, times beta
+    d.be[0] = (real)(beta * 2.0 * w * (2.0 - 1.5 * (cx * cx + cy * cy)));
+    d.be[1] = (real)(beta * 9.0 * w * (cx * cx - 1.0 / 3.0));
+    d.be[2] = (real)(beta * 9.0 * w * (cy * cy - 1.0 / 3.0));
+    d.be[3] = (real)(beta * 18.0 * w * cx * cy);
+    d.g1 = l.group;
+    const double nx_ = l.normal[0], ny_ = l.normal[1];
+    const double tx = G1.value[0] / h->s_sigma, ty = G1.value[1] / h->s_sigma;
+    if (G2) {
+        // two walls: sigma* = sym(t_A n_A + t_B n_B), nothing extrapolated
+        const double ux = G2->value[0] / h->s_sigma, uy = G2->value[1] / h->s_sigma;
+        const double mx = l.normal2[0], my = l.normal2[1];
+        d.K1[0] = (real)(tx * nx_); d.K1[1] = (real)(ty * ny_); d.K1[2] = (real)(0.5 * (tx * ny_ + ty * nx_));
+        d.K2[0] = (real)(ux * mx); d.K2[1] = (real)(uy * my); d.K2[2] = (real)(0.5 * (ux * my + uy * mx));
+        d.g2 = l.group2;
+        return;
+    }
+    // eq:trafocauchy: sigma* = t_n n n + t_t (n e + e n) + sigma_tt e e, e = (-n_y, n_x)
+    const double ex = -ny_, ey = nx_;
+    const double tn = tx * nx_ + ty * ny_, tt = tx * ex + ty * ey;
+    d.K1[0] = (real)(tn * nx_ * nx_ + 2.0 * tt * nx_ * ex);
+    d.K1[1] = (real)(tn * ny_ * ny_ + 2.0 * tt * ny_ * ey);
+    d.K1[2] = (real)(tn * nx_ * ny_ + tt * (nx_ * ey + ex * ny_));
+    d.E3[0] = (real)(ex * ex); d.E3[1] = (real)(ey * ey); d.E3[2] = (real)(ex * ey);
+}
+
+template <typename real>
+int upload_links(slbm_s* h, const std::vector<slbm_link>& L, const std::vector<uint8_t>& cutmask,
+                 const slbm_params* p)
+{
+    const int n = h->nx * h->ny;
+    std::vector<LinkDev<real>> d(L.size());
+    for (size_t i = 0; i < L.size(); ++i) {
+        const slbm_link& l = L[i];
+        const int k = l.dir;
+        const bool behind = !((cutmask[l.site] >> (OPP(k) - 1)) & 1u);
+        fill_link(d[i], l, behind, p, h);
+    }
+    (void)n;
+    if (!d.empty()) {
+        HIP_TRY(hipMalloc(&h->links, d.size() * sizeof(LinkDev<real>)));
+        HIP_TRY(hipMemcpy(h->links, d.data(), d.size() * sizeof(LinkDev<real>), hipMemcpyHostToDevice));
+    }
+    return SLBM_OK;
+}
+
+int create_impl(const slbm_params* p, slbm_handle* out)
+{
+    if (!p || !out) return fail(SLBM_E_INVAL, "null argument");
+    *out = nullptr;
+    if (p->nx < 1 || p->ny < 1) return fail(SLBM_E_INVAL, "grid must be at least 1x1");
+    if ((long long)p->nx * p->ny > (1LL << 28)) return fail(SLBM_E_UNSUPPORTED, "grid larger than 2^28 sites");
+    if (!(p->mu > 0) || !(p->rho > 0)) return fail(SLBM_E_INVAL, "mu and rho must be positive");
+    if (!(p->tau > 0.5)) return fail(SLBM_E_INVAL, "tau must exceed 1/2");
+    if (!std::isfinite(p->lambda)) return fail(SLBM_E_INVAL, "lambda must be finite");
+    if (p->precision != SLBM_FP64 && p->precision != SLBM_FP32) return fail(SLBM_E_INVAL, "unknown precision");
+    if (p->neumann_order != 0 && p->neumann_order != 1) return fail(SLBM_E_INVAL, "neumann_order must be 0 or 1");
+    if (!p->mask) return fail(SLBM_E_INVAL, "mask is required");
+    if (p->n_links < 0 || (p->n_links > 0 && !p->links)) return fail(SLBM_E_INVAL, "bad link list");
+    if (p->n_groups < 0 || (p->n_groups > 0 && !p->groups)) return fail(SLBM_E_INVAL, "bad group list");
+    for (int g = 0; g < p->n_groups; ++g) {
+        const slbm_bc_group& G = p->groups[g];
+        if (G.kind != SLBM_DIRICHLET && G.kind != SLBM_NEUMANN) return fail(SLBM_E_INVAL, "group %d: bad kind", g);
+        if (G.profile != SLBM_PROFILE_STEP && G.profile != SLBM_PROFILE_RAMP) return fail(SLBM_E_INVAL, "group %d: bad profile", g);
+        if (G.profile == SLBM_PROFILE_RAMP && !(G.ramp_time > 0)) return fail(SLBM_E_INVAL, "group %d: ramp time must be positive", g);
+        if (!std::isfinite(G.value[0]) || !std::isfinite(G.value[1])) return fail(SLBM_E_INVAL, "group %d: value not finite", g);
+    }
+    const int nx = p->nx, ny = p->ny, n = nx * ny;
+    std::vector<uint8_t> mat(n), cut(n, 0);
+    for (int s = 0; s < n; ++s) mat[s] = p->mask[s] ? 1 : 0;
+    std::vector<slbm_link> L(p->links, p->links + p->n_links);
+    for (int i = 0; i < p->n_links; ++i) {
+        const slbm_link& l = L[i];
+        if (l.site < 0 || l.site >= n || !mat[l.site]) return fail(SLBM_E_INVAL, "link %d: site is not material", i);
+        if (l.dir < 1 || l.dir > 8) return fail(SLBM_E_INVAL, "link %d: direction must be 1..8", i);
+        if (!(l.q > 0 && l.q <= 1)) return fail(SLBM_E_INVAL, "link %d: q outside (0,1]", i);
+        if (l.group < 0 || l.group >= p->n_groups) return fail(SLBM_E_INVAL, "link %d: bad group", i);
+        if (l.group2 >= p->n_groups || l.group2 < -1) return fail(SLBM_E_INVAL, "link %d: bad second group", i);
+        const double nn = l.normal[0] * l.normal[0] + l.normal[1] * l.normal[1];
+        if (!(std::fabs(nn - 1.0) < 1e-9)) return fail(SLBM_E_INVAL, "link %d: normal is not a unit vector", i);
+        if (l.group2 >= 0) {
+            const double m2 = l.normal2[0] * l.normal2[0] + l.normal2[1] * l.normal2[1];
+            if (!(std::fabs(m2 - 1.0) < 1e-9)) return fail(SLBM_E_INVAL, "link %d: second normal is not a unit vector", i);
+        }
+        const uint8_t bit = (uint8_t)(1u << (l.dir - 1));
+        if (cut[l.site] & bit) return fail(SLBM_E_INVAL, "link %d: duplicate", i);
+        cut[l.site] |= bit;
+    }
+    for (int s = 0; s < n; ++s) {
+        if (!mat[s]) continue;
+        if (cut[s] == 0xFF) return fail(SLBM_E_INVAL, "site %d: every link is cut", s);
+        const int x = s % nx, y = s / nx;
+        for (int k = 1; k <= 8; ++k) {
+            if (cut[s] & (1u << (k - 1))) continue;
+            int tx = x + CX(k), ty = y + CY(k);
+            if (p->periodic_x) tx = (tx + nx) % nx;
+            if (p->periodic_y) ty = (ty + ny) % ny;
+            if (tx < 0 || tx >= nx || ty < 0 || ty >= ny || !mat[ty * nx + tx])
+                return fail(SLBM_E_INVAL, "site (%d,%d): uncut link %d leaves the material", x, y, k);
+            if (cut[ty * nx + tx] & (1u << (OPP(k) - 1)))
+                return fail(SLBM_E_INVAL, "site (%d,%d): link %d is cut from one end only", x, y, k);
+        }
+    }
+    std::sort(L.begin(), L.end(), [](const slbm_link& a, const slbm_link& b) {
+        return a.site != b.site ? a.site < b.site : a.dir < b.dir;
+    });
+
+    slbm_s* h = new (std::nothrow) slbm_s();
+    if (!h) return fail(SLBM_E_NOMEM, "out of host memory");
+    h->device = p->device;
+    h->nx = nx; h->ny = ny;
+    h->ld = (nx + 63) / 64 * 64;
+    h->plane = (long long)h->ld * ny;
+    h->precision = p->precision;
+    h->px = p->periodic_x ? 1 : 0;
+    h->py = p->periodic_y ? 1 : 0;
+    h->norder = p->neumann_order;
+    // units (section 5.1): c_s = sqrt(mu/rho) = dx/(sqrt 3 dt)
+    h->rho_user = p->rho;
+    h->dt_user = std::sqrt(p->rho / (3.0 * p->mu));
+    h->s_sigma = 3.0 * p->mu;
+    h->s_v = 1.0 / h->dt_user;
+    h->muL = 1.0 / 3.0;
+    h->lamL = p->lambda / h->s_sigma;
+    h->tau = p->tau;
+    h->FL[0] = p->body_force[0] / h->s_sigma;
+    h->FL[1] = p->body_force[1] / h->s_sigma;
+    h->esize = p->precision == SLBM_FP32 ? 4 : 8;
+    h->n_links = p->n_links;
+    h->mask = mat;
+
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
+        delete h;
+        return fail(SLBM_E_DEVICE, "no HIP device");
+    }
+    if (p->device < 0 || p->device >= dev_count) {
+        delete h;
+        return fail(SLBM_E_INVAL, "device %d out of range", p->device);
+    }
+    DeviceGuard dg(h->device);
+    auto bail = [&](int rc) { free_all(h); delete h; return rc; };
+#define TRY_OR_BAIL(expr)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            int rc_ = (e_ == hipErrorOutOfMemory) ? SLBM_E_NOMEM : SLBM_E_DEVICE;       \
+            fail(rc_, "%s failed: %s", #expr, hipGetErrorString(e_));                   \
+            return bail(rc_);                                                           \
+        }                                                                               \
+    } while (0)
+    if (p->stream) {
+        h->stream = (hipStream_t)p->stream;
+    } else {
+        TRY_OR_BAIL(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    const size_t pop_bytes = (size_t)9 * h->plane * h->esize;
+    TRY_OR_BAIL(hipMalloc(&h->buf[0], pop_bytes));
+    TRY_OR_BAIL(hipMalloc(&h->buf[1], pop_bytes));
+    TRY_OR_BAIL(hipMalloc((void**)&h->U, (size_t)2 * h->plane * sizeof(double)));
+    TRY_OR_BAIL(hipMalloc((void**)&h->flags, (size_t)h->plane));
+    TRY_OR_BAIL(hipMalloc((void**)&h->bidx, (size_t)h->plane * sizeof(int32_t)));
+    TRY_OR_BAIL(hipMalloc((void**)&h->diverged, sizeof(unsigned int)));
+    {
+        std::vector<uint8_t> fl((size_t)h->plane, (uint8_t)kVoid);
+        std::vector<int32_t> bi((size_t)h->plane, -1);
+        for (int s = 0; s < n; ++s) {
+            if (!mat[s]) continue;
+            const size_t d = (size_t)(s / nx) * h->ld + (s % nx);
+            fl[d] = cut[s];
+        }
+        for (size_t i = 0; i < L.size(); ++i) {
+            const int s = L[i].site;
+            const size_t d = (size_t)(s / nx) * h->ld + (s % nx);
+            if (bi[d] < 0) bi[d] = (int32_t)i;
+        }
+        TRY_OR_BAIL(hipMemcpy(h->flags, fl.data(), fl.size(), hipMemcpyHostToDevice));
+        TRY_OR_BAIL(hipMemcpy(h->bidx, bi.data(), bi.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<GroupDev> gd(std::max(1, p->n_groups));
+        for (int g = 0; g < p->n_groups; ++g) {
+            gd[g].profile = p->groups[g].profile;
+            gd[g].ramp_steps = p->groups[g].profile == SLBM_PROFILE_RAMP ? p->groups[g].ramp_time / h->dt_user : 1.0;
+        }
+        TRY_OR_BAIL(hipMalloc((void**)&h->groups, gd.size() * sizeof(GroupDev)));
+        TRY_OR_BAIL(hipMemcpy(h->groups, gd.data(), gd.size() * sizeof(GroupDev), hipMemcpyHostToDevice));
+    }
+    {
+        int rc = h->precision == SLBM_FP32 ? upload_links<float>(h, L, cut, p) : upload_links<double>(h, L, cut, p);
+        if (rc) return bail(rc);
+    }
+    // rest state: g = 0 (f = r), U = 0
+    TRY_OR_BAIL(hipMemsetAsync(h->buf[0], 0, pop_bytes, h->stream));
+    TRY_OR_BAIL(hipMemsetAsync(h->buf[1], 0, pop_bytes, h->stream));
+    TRY_OR_BAIL(hipMemsetAsync(h->U, 0, (size_t)2 * h->plane * sizeof(double), h->stream));
+    TRY_OR_BAIL(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
+    TRY_OR_BAIL(hipStreamSynchronize(h->stream));
+#undef TRY_OR_BAIL
+    h->cur = 0;
+    h->step = 0;
+    h->local = true;
+    *out = h;
+    return SLBM_OK;
+}
+
+int copy_out(slbm_s* h, int comp, double scale, double offset, double* dst)
+{
+    // lattice field comp of scratch (after outputs()) -> unpadded host array
+    const double* src = h->scratch + (size_t)(1 + comp) * h->plane;
+    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)h->nx * sizeof(double), src, (size_t)h->ld * sizeof(double),
+                             (size_t)h->nx * sizeof(double), h->ny, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const int n = h->nx * h->ny;
+    for (int s = 0; s < n; ++s) dst[s] = h->mask[s] ? dst[s] * scale + offset : 0.0;
+    return SLBM_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+int slbm_create(const slbm_params* params, slbm_handle* out)
+{
+    try {
+        return create_impl(params, out);
+    } catch (...) {
+        return fail(SLBM_E_NOMEM, "host allocation failed");
+    }
+}
+
+int slbm_destroy(slbm_handle h)
+{
+    if (!h) return SLBM_OK;
+    DeviceGuard dg(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+    return SLBM_OK;
+}
+
+int slbm_step(slbm_handle h, int64_t nsteps)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
+    DeviceGuard dg(h->device);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        int rc = h->precision == SLBM_FP32 ? launch_step<float>(h) : launch_step<double>(h);
+        if (rc) return rc;
+    }
+    return SLBM_OK;
+}
+
+int slbm_sync(slbm_handle h)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    DeviceGuard dg(h->device);
+    unsigned int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (flag) return fail(SLBM_E_DIVERGED, "a non-finite value appeared by step %lld", (long long)h->step);
+    return SLBM_OK;
+}
+
+int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    DeviceGuard dg(h->device);
+    int rc = outputs(h);
+    if (rc) return rc;
+    const size_t n = (size_t)h->nx * h->ny;
+    const double sj = h->rho_user * h->s_v;
+    if (rho && (rc = copy_out(h, 0, h->rho_user, 0.0, rho))) return rc;
+    if (j && ((rc = copy_out(h, 1, sj, 0.0, j)) || (rc = copy_out(h, 2, sj, 0.0, j + n)))) return rc;
+    if (P && ((rc = copy_out(h, 3, h->s_sigma, 0.0, P)) || (rc = copy_out(h, 4, h->s_sigma, 0.0, P + n)) ||
+              (rc = copy_out(h, 5, h->s_sigma, 0.0, P + 2 * n))))
+        return rc;
+    if (sigma && ((rc = copy_out(h, 6, h->s_sigma, 0.0, sigma)) || (rc = copy_out(h, 7, h->s_sigma, 0.0, sigma + n)) ||
+                  (rc = copy_out(h, 8, h->s_sigma, 0.0, sigma + 2 * n))))
+        return rc;
+    return SLBM_OK;
+}
+
+int slbm_displacement(slbm_handle h, double* u)
+{
+    if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
+    DeviceGuard dg(h->device);
+    int rc = outputs(h);
+    if (rc) return rc;
+    const size_t n = (size_t)h->nx * h->ny;
+    if ((rc = copy_out(h, 9, 1.0, 0.0, u)) || (rc = copy_out(h, 10, 1.0, 0.0, u + n))) return rc;
+    return SLBM_OK;
+}
+
+int slbm_displacement_device(slbm_handle h, void* u_dev)
+{
+    if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
+    DeviceGuard dg(h->device);
+    int rc = outputs(h);
+    if (rc) return rc;
+    const int n = h->nx * h->ny;
+    hipLaunchKernelGGL(k_unpad_u, dim3((n + 255) / 256), dim3(256), 0, h->stream,
+                       (const double*)(h->scratch + h->plane), h->nx, h->ny, h->ld, (double*)u_dev);
+    HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
+int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const double* sigma, const double* u)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    DeviceGuard dg(h->device);
+    int rc = ensure_scratch(h);
+    if (rc) return rc;
+    const int nx = h->nx, ny = h->ny, n = nx * ny;
+    const size_t P = (size_t)h->plane;
+    // lattice-unit fields on the host, padded layout: dr, jx, jy, pxx, pyy, pxy, ux, uy
+    std::vector<double> f((size_t)8 * P, 0.0);
+    const double lm = h->lamL - h->muL;
+    for (int s = 0; s < n; ++s) {
+        if (!h->mask[s]) continue;
+        const size_t d = (size_t)(s / nx) * h->ld + (s % nx);
+        const double rL = rho ? rho[s] / h->rho_user : 1.0;
+        if (!(rL > 0) || !std::isfinite(rL)) return fail(SLBM_E_INVAL, "density must be positive");
+        const double vx = vel ? vel[s] / h->s_v : 0.0, vy = vel ? vel[n + s] / h->s_v : 0.0;
+        const double sxx = sigma ? sigma[s] / h->s_sigma : 0.0, syy = sigma ? sigma[n + s] / h->s_sigma : 0.0;
+        const double sxy = sigma ? sigma[2 * n + s] / h->s_sigma : 0.0;
+        const double div = 1.0 - rL;   // eq:approxdiv
+        f[d] = rL - 1.0;
+        f[P + d] = rL * vx;
+        f[2 * P + d] = rL * vy;
+        f[3 * P + d] = -sxx + lm * div;   // eq:poissonstress
+        f[4 * P + d] = -syy + lm * div;
+        f[5 * P + d] = -sxy;
+        f[6 * P + d] = u ? u[s] : 0.0;
+        f[7 * P + d] = u ? u[n + s] : 0.0;
+    }
+    double* dev = h->scratch;   // 12 planes: fields use 8
+    HIP_TRY(hipMemcpyAsync(dev, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    h->cur = 0;
+    h->local = true;
+    h->step = 0;
+    const int grid = (int)((P + 255) / 256);
+    if (h->precision == SLBM_FP32) {
+        StepArgs<float> a = make_args<float>(h, 0);
+        if (h->px || h->py)
+            hipLaunchKernelGGL((k_init<float, true>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (float*)h->buf[0]);
+        else
+            hipLaunchKernelGGL((k_init<float, false>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (float*)h->buf[0]);
+    } else {
+        StepArgs<double> a = make_args<double>(h, 0);
+        if (h->px || h->py)
+            hipLaunchKernelGGL((k_init<double, true>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (double*)h->buf[0]);
+        else
+            hipLaunchKernelGGL((k_init<double, false>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (double*)h->buf[0]);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SLBM_OK;
+}
+
+int slbm_time(slbm_handle h, int64_t* step, double* t_user)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    if (step) *step = h->step;
+    if (t_user) *t_user = (double)h->step * h->dt_user;
+    return SLBM_OK;
+}
+
+int slbm_set_launch(slbm_handle h, int32_t seg_rows)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
+    h->seg = seg_rows;
+    return SLBM_OK;
+}
+
+int slbm_device_bytes(slbm_handle h, int64_t* bytes)
+{
+    if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
+    int64_t b = 2 * (int64_t)9 * h->plane * (int64_t)h->esize + 2 * h->plane * 8 + h->plane * 5;
+    b += (int64_t)h->n_links * (h->esize == 4 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>));
+    if (h->scratch) b += 12 * h->plane * 8;
+    *bytes = b;
+    return SLBM_OK;
+}
+
+namespace {
+struct SaveHeader {
+    uint64_t magic;
+    int32_t nx, ny, ld, precision;
+    int64_t step;
+    int32_t local, diverged;
+};
+constexpr uint64_t kMagic = 0x31304d424c53ULL;  // "SLBM01"
+}  // namespace
+
+int slbm_save(slbm_handle h, void* buf, size_t* bytes)
+{
+    if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
+    const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
+    const size_t need = sizeof(SaveHeader) + pop + ub;
+    if (!buf) { *bytes = need; return SLBM_OK; }
+    if (*bytes < need) return fail(SLBM_E_INVAL, "buffer too small: %zu < %zu", *bytes, need);
+    DeviceGuard dg(h->device);
+    SaveHeader hd{kMagic, h->nx, h->ny, h->ld, h->precision, h->step, h->local ? 1 : 0, 0};
+    unsigned int flag = 0;
+    char* p = (char*)buf;
+    HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(p + sizeof hd, h->buf[h->cur], pop, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(p + sizeof hd + pop, h->U, ub, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hd.diverged = (int32_t)flag;
+    std::memcpy(p, &hd, sizeof hd);
+    *bytes = need;
+    return SLBM_OK;
+}
+
+int slbm_load(slbm_handle h, const void* buf, size_t bytes)
+{
+    if (!h || !buf) return fail(SLBM_E_INVAL, "null argument");
+    const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
+    SaveHeader hd;
+    if (bytes < sizeof hd + pop + ub) return fail(SLBM_E_INVAL, "checkpoint too short");
+    std::memcpy(&hd, buf, sizeof hd);
+    if (hd.magic != kMagic || hd.nx != h->nx || hd.ny != h->ny || hd.ld != h->ld || hd.precision != h->precision)
+        return fail(SLBM_E_INVAL, "checkpoint does not match this plate");
+    DeviceGuard dg(h->device);
+    const char* p = (const char*)buf;
+    h->cur = 0;
+    HIP_TRY(hipMemcpyAsync(h->buf[0], p + sizeof hd, pop, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->U, p + sizeof hd + pop, ub, hipMemcpyHostToDevice, h->stream));
+    unsigned int flag = (unsigned int)hd.diverged;
+    HIP_TRY(hipMemcpyAsync(h->diverged, &flag, sizeof flag, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->step = hd.step;
+    h->local = hd.local != 0;
+    return SLBM_OK;
+}
+
+const char* slbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+"""ctypes binding of libslbm.so (include/slbm.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.
+
+The library is loaded from this package directory.  There is no fallback: if
+libslbm.so is missing or fails to load, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslbm.so")
+
+SLBM_OK = 0
+STATUS = {0: "SLBM_OK", -1: "SLBM_E_INVAL", -2: "SLBM_E_NOMEM", -3: "SLBM_E_DEVICE",
+          -4: "SLBM_E_DIVERGED", -5: "SLBM_E_UNSUPPORTED", -6: "SLBM_E_BUDGET"}
+FP64, FP32 = 0, 1
+PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
+
+EXPORTS = [
+    "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
+    "slbm_displacement", "slbm_displacement_device", "slbm_time", "slbm_set_launch",
+    "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_last_error",
+]
+
+LINK_DTYPE = np.dtype([("site", "<i4"), ("dir", "<i4"), ("q", "<f8"), ("group", "<i4"),
+                       ("group2", "<i4"), ("normal", "<f8", (2,)), ("normal2", "<f8", (2,))],
+                      align=True)
+GROUP_DTYPE = np.dtype([("kind", "<i4"), ("profile", "<i4"), ("value", "<f8", (2,)),
+                        ("ramp_time", "<f8")], align=True)
+
+
+class SlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("lam", C.c_double), ("mu", C.c_double), ("rho", C.c_double),
+        ("tau", C.c_double), ("body_force", C.c_double * 2),
+        ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+        ("precision", C.c_int32), ("neumann_order", C.c_int32),
+        ("mask", C.c_void_p),
+        ("n_links", C.c_int32), ("links", C.c_void_p),
+        ("n_groups", C.c_int32), ("groups", C.c_void_p),
+        ("device", C.c_int32), ("stream", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libslbm.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libslbm.so not built at {LIB_PATH}; run `python -m paper_2208_04088_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
+    sig = {
+        "slbm_create": [C.POINTER(Params), C.POINTER(vp)],
+        "slbm_init_fields": [vp, dp, dp, dp, dp],
+        "slbm_step": [vp, i64],
+        "slbm_sync": [vp],
+        "slbm_moments": [vp, dp, dp, dp, dp],
+        "slbm_displacement": [vp, dp],
+        "slbm_displacement_device": [vp, vp],
+        "slbm_time": [vp, C.POINTER(i64), C.POINTER(C.c_double)],
+        "slbm_set_launch": [vp, i32],
+        "slbm_save": [vp, vp, C.POINTER(C.c_size_t)],
+        "slbm_load": [vp, vp, C.c_size_t],
+        "slbm_device_bytes": [vp, C.POINTER(i64)],
+        "slbm_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.slbm_last_error.argtypes = []
+    L.slbm_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != SLBM_OK:
+        raise SlbmError(rc, lib().slbm_last_error().decode())
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def marshal(plate, precision=FP32, device=0, stream=None):
+    """slbm_params for a :class:`slbm_workloads.Plate`, plus the arrays it points to."""
+    if isinstance(precision, str):
+        precision = PRECISION[precision]
+    mask = np.ascontiguousarray(plate.mask.ravel(), dtype=np.uint8)
+    links = np.zeros(len(plate.links), dtype=LINK_DTYPE)
+    for f in LINK_DTYPE.names:
+        links[f] = plate.links[f]
+    groups = np.zeros(max(len(plate.groups), 1), dtype=GROUP_DTYPE)
+    for i, g in enumerate(plate.groups):
+        groups[i] = (g.kind, g.profile, g.value, g.ramp_time)
+    prm = Params(nx=plate.nx, ny=plate.ny, lam=plate.lam, mu=plate.mu, rho=plate.rho, tau=plate.tau,
+                 body_force=(C.c_double * 2)(*plate.force), periodic_x=int(plate.periodic_x),
+                 periodic_y=int(plate.periodic_y), precision=int(precision),
+                 neumann_order=int(plate.neumann_order), mask=mask.ctypes.data,
+                 n_links=len(links), links=links.ctypes.data if len(links) else None,
+                 n_groups=len(plate.groups), groups=groups.ctypes.data,
+                 device=int(device), stream=stream)
+    return prm, (mask, links, groups)
+
+
+class Solver:
+    """One plate resident on the GPU (slbm_create ... slbm_destroy)."""
+
+    def __init__(self, plate, precision="fp32", device=0, stream=None):
+        L = lib()
+        self.plate = plate
+        prm, keep = marshal(plate, precision, device, stream)
+        h = C.c_void_p()
+        _check(L.slbm_create(C.byref(prm), C.byref(h)))
+        self.h = h
+        self.n = plate.nx * plate.ny
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().slbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def init_fields(self, rho=None, vel=None, sigma=None, u=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).ravel()
+                for a in (rho, vel, sigma, u)]
+        _check(lib().slbm_init_fields(self.h, *[_p(a) for a in arrs]))
+
+    def step(self, n=1):
+        _check(lib().slbm_step(self.h, int(n)))
+
+    def sync(self):
+        _check(lib().slbm_sync(self.h))
+
+    def moments(self):
+        ny, nx = self.plate.ny, self.plate.nx
+        rho = np.empty(self.n)
+        j = np.empty(2 * self.n)
+        P = np.empty(3 * self.n)
+        s = np.empty(3 * self.n)
+        _check(lib().slbm_moments(self.h, _p(rho), _p(j), _p(P), _p(s)))
+        return rho.reshape(ny, nx), j.reshape(2, ny, nx), P.reshape(3, ny, nx), s.reshape(3, ny, nx)
+
+    def displacement(self):
+        u = np.empty(2 * self.n)
+        _check(lib().slbm_displacement(self.h, _p(u)))
+        return u.reshape(2, self.plate.ny, self.plate.nx)
+
+    def displacement_device(self, ptr):
+        """Writes [2][ny][nx] doubles to device pointer ``ptr`` (e.g. a torch
+        tensor's data_ptr()) on the handle's stream."""
+        _check(lib().slbm_displacement_device(self.h, C.c_void_p(int(ptr))))
+
+    def time(self):
+        st = C.c_int64()
+        t = C.c_double()
+        _check(lib().slbm_time(self.h, C.byref(st), C.byref(t)))
+        return st.value, t.value
+
+    def set_launch(self, seg_rows):
+        _check(lib().slbm_set_launch(self.h, int(seg_rows)))
+
+    def save(self):
+        n = C.c_size_t(0)
+        _check(lib().slbm_save(self.h, None, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib().slbm_save(self.h, buf.ctypes.data, C.byref(n)))
+        return buf
+
+    def load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().slbm_load(self.h, buf.ctypes.data, buf.size))
+
+    def device_bytes(self):
+        b = C.c_int64()
+        _check(lib().slbm_device_bytes(self.h, C.byref(b)))
+        return b.value

@@ -156,14 +156,18 @@ def _circle_crossing(px, py, k, c: Circle):
     inside the hole (a chord with both ends outside is not a cut link)."""
     cx, cy = float(CX[k]), float(CY[k])
     dx, dy = px - c.cx, py - c.cy
-    ex, ey = dx + cx, dy + cy
-    inside_far = ex * ex + ey * ey < c.R * c.R
+    # the far end's test uses the same expression as the void mask
+    ex, ey = (px + cx) - c.cx, (py + cy) - c.cy
+    inside_far = ex * ex + ey * ey < c.R ** 2
     a = cx * cx + cy * cy
     b = dx * cx + dy * cy
     cc = dx * dx + dy * dy - c.R * c.R
     disc = np.maximum(b * b - a * cc, 0.0)
     t = (-b - np.sqrt(disc)) / a
-    s = np.where(inside_far & (t > 0) & (t <= 1), t, np.inf)
+    # the far end is inside and the near end outside, so the entry lies on the
+    # link; keep rounding at a site that sits on the circle from pushing it off
+    t = np.clip(t, 1e-9, 1.0)
+    s = np.where(inside_far, t, np.inf)
     wx, wy = px + t * cx, py + t * cy
     nrm = np.stack([(c.cx - wx) / c.R, (c.cy - wy) / c.R], axis=-1)
     return s, nrm
@@ -195,7 +199,7 @@ def build_plate(nx, ny, *, lam, mu, rho=1.0, tau, walls: Sequence, groups: Seque
             x0, x1 = max(int(np.floor(w.cx - w.R)), 0), min(int(np.ceil(w.cx + w.R)) + 1, nx)
             yy, xx = np.mgrid[y0:y1, x0:x1]
             sub = mask[y0:y1, x0:x1]
-            sub[(xx - w.cx) ** 2 + (yy - w.cy) ** 2 < w.R ** 2] = 0
+            sub[(xx - w.cx) * (xx - w.cx) + (yy - w.cy) * (yy - w.cy) < w.R ** 2] = 0
     # only sites within one cell of a wall can own a cut link
     near = np.zeros((ny, nx), dtype=bool)
     for w in walls:

@@ -1,0 +1,140 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, its structs have the layout the header states, and invalid
+problems are rejected on the host before any device call."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2208_04088_amd import slbm as S
+from slbm_workloads import geometry as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = S.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(S.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    fields = {
+        "slbm_params": [f for f, _ in S.Params._fields_],
+        "slbm_link": list(S.LINK_DTYPE.names),
+        "slbm_bc_group": list(S.GROUP_DTYPE.names),
+    }
+    cname = {"lam": "lambda"}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "slbm.h"', "int main(void){"]
+    for st, fl in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fl:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {cname.get(f, f)}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.split("\n") if l)
+    assert int(out["slbm_params"]) == C.sizeof(S.Params)
+    for f, _ in S.Params._fields_:
+        assert int(out[f"slbm_params.{f}"]) == getattr(S.Params, f).offset, f
+    for dt, st in ((S.LINK_DTYPE, "slbm_link"), (S.GROUP_DTYPE, "slbm_bc_group")):
+        assert int(out[st]) == dt.itemsize
+        for f in dt.names:
+            assert int(out[f"{st}.{f}"]) == dt.fields[f][1], f
+
+
+def _plate():
+    n = 12
+    walls = G.edge_walls(n, n, left=0, right=1, bottom=1, top=1)
+    walls.append(G.Circle(6.2, 5.8, 2.3, 1))
+    return G.build_plate(n, n, lam=0.05, mu=0.05, tau=0.55, walls=walls,
+                         groups=[G.BCGroup(G.DIRICHLET), G.BCGroup(G.NEUMANN, (1e-5, 0.0))])
+
+
+def _create(plate, **over):
+    prm, keep = S.marshal(plate, "fp32")
+    for k, v in over.items():
+        setattr(prm, k, v)
+    h = C.c_void_p()
+    rc = S.lib().slbm_create(C.byref(prm), C.byref(h))
+    if rc == 0:
+        S.lib().slbm_destroy(h)
+    return rc, S.lib().slbm_last_error().decode()
+
+
+def _mutated(fn):
+    p = _plate()
+    L = p.links.copy()
+    fn(p, L)
+    p.links = L
+    return p
+
+
+@pytest.mark.parametrize("case", [
+    "q_zero", "q_big", "bad_group", "bad_group2", "normal", "dup", "void_site", "dir",
+    "uncut_leaves", "one_sided", "tau", "mu", "rho", "order", "precision"])
+def test_invalid_problems_are_rejected_on_the_host(case):
+    over = {}
+    p = _plate()
+    if case == "q_zero":
+        p = _mutated(lambda p, L: L["q"].__setitem__(0, 0.0))
+    elif case == "q_big":
+        p = _mutated(lambda p, L: L["q"].__setitem__(3, 1.5))
+    elif case == "bad_group":
+        p = _mutated(lambda p, L: L["group"].__setitem__(1, 7))
+    elif case == "bad_group2":
+        p = _mutated(lambda p, L: L["group2"].__setitem__(1, 9))
+    elif case == "normal":
+        p = _mutated(lambda p, L: L["normal"].__setitem__(2, (0.5, 0.5)))
+    elif case == "dup":
+        p.links = np.concatenate([p.links, p.links[:1]])
+    elif case == "void_site":
+        p = _mutated(lambda p, L: None)
+        p.mask = p.mask.copy()
+        p.mask.flat[int(p.links["site"][0])] = 0
+    elif case == "dir":
+        p = _mutated(lambda p, L: L["dir"].__setitem__(0, 9))
+    elif case == "uncut_leaves":
+        p.links = p.links[1:]
+    elif case == "one_sided":
+        # cut an interior link from one end only
+        extra = np.zeros(1, dtype=p.links.dtype)
+        extra[0] = (5 * 12 + 2, 1, 0.5, 1, -1, (1.0, 0.0), (0.0, 0.0))
+        p.links = np.concatenate([p.links, extra])
+    elif case == "tau":
+        over["tau"] = 0.5
+    elif case == "mu":
+        over["mu"] = 0.0
+    elif case == "rho":
+        over["rho"] = -1.0
+    elif case == "order":
+        over["neumann_order"] = 2
+    elif case == "precision":
+        over["precision"] = 7
+    rc, msg = _create(p, **over)
+    assert rc == -1, (rc, msg)
+    assert msg
+
+
+def test_valid_problem_without_a_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, msg = _create(_plate())
+    assert rc == -3, (rc, msg)

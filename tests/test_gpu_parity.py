@@ -1,0 +1,272 @@
+"""HIP path (through the C ABI) against the CPU reference, element by element.
+
+Tolerances: the fp64 path must match to 1e-12 relative (of the field's
+largest value, and in relative L2); the fp32 path (fp32 populations and
+arithmetic, fp64 displacement) to 1e-4 relative L2 on displacement, the
+accuracy the method has to hold after 10k steps.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from slbm_workloads import configs
+from slbm_workloads import geometry as G
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def slbm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2208_04088_amd import slbm as S
+    S.lib()
+    return S
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def compare(solver, ref, prec, what="all"):
+    u, u_ref = solver.displacement(), ref.displacement()
+    tol = FP64_TOL if prec == "fp64" else FP32_TOL
+    assert np.isfinite(u).all()
+    e = rel_l2(u, u_ref)
+    assert e <= tol, f"u rel L2 {e:.3e} > {tol}"
+    if prec == "fp64":
+        scale = np.abs(u_ref).max()
+        assert np.abs(u - u_ref).max() <= 4 * tol * scale
+    if what == "all":
+        for a, b, name in zip(solver.moments(), ref.moments(), ("rho", "j", "P", "sigma")):
+            if name == "rho":
+                a, b = a - 1.0 * (b != 0), b - 1.0 * (b != 0)   # compare the deviation from rest
+            sc = np.abs(b).max()
+            if sc == 0:
+                continue
+            d = np.abs(a - b).max() / sc
+            lim = 4 * FP64_TOL if prec == "fp64" else 1e-3
+            assert d <= lim, f"{name}: max deviation {d:.3e} of scale {sc:.3e}"
+    return e
+
+
+def mixed_plate(nx, ny, seed, order=0, periodic=False):
+    """Straight edges (Dirichlet and Neumann, step and ramp), a curved hole,
+    an edge crack, corners, body force."""
+    rng = np.random.default_rng(seed)
+    mu = 0.05
+    groups = [G.BCGroup(G.DIRICHLET, (0.0, 0.0)),
+              G.BCGroup(G.NEUMANN, (1e-3 * mu, 2e-4 * mu)),
+              G.BCGroup(G.NEUMANN, (0.0, 0.0)),
+              G.BCGroup(G.NEUMANN, (0.0, -5e-4 * mu), G.PROFILE_RAMP, 40.0),
+              G.BCGroup(G.DIRICHLET, (1e-4, -2e-4), G.PROFILE_RAMP, 30.0)]
+    if periodic:
+        walls = [G.Circle(nx * 0.45, ny * 0.55, min(nx, ny) * 0.18, 2)]
+        return G.build_plate(nx, ny, lam=0.04, mu=mu, tau=0.55, walls=walls, groups=groups,
+                             force=(1e-6, -2e-6), periodic_x=True, periodic_y=True,
+                             neumann_order=order, name=f"periodic{nx}x{ny}")
+    walls = G.edge_walls(nx, ny, left=0, right=1, bottom=3, top=4)
+    walls.append(G.Circle(nx * 0.62 + rng.uniform(-1, 1), ny * 0.5 + rng.uniform(-1, 1),
+                          min(nx, ny) * 0.17, 2))
+    walls.append(G.HLine(math.floor(ny * 0.3) + 0.5, 2, x_lo=-0.5, x_hi=nx * 0.3 - 0.5))
+    return G.build_plate(nx, ny, lam=0.045, mu=mu, tau=0.55, walls=walls, groups=groups,
+                         force=(1e-6, 0.0), neumann_order=order, name=f"mixed{nx}x{ny}")
+
+
+# --------------------------------------------------------------- small --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("shape", [(70, 45), (130, 67)])
+def test_mixed_plate_matches_reference(slbm, prec, order, shape):
+    """Several strips and row segments, a ragged last strip, every link kind."""
+    p = mixed_plate(*shape, seed=shape[0], order=order)
+    steps = 150
+    ref = Oracle(p, extended=True)
+    ref.step(steps)
+    s = slbm.Solver(p, prec)
+    s.step(steps)
+    s.sync()
+    compare(s, ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_periodic_plate_with_hole_and_force(slbm, prec):
+    p = mixed_plate(64, 40, seed=1, periodic=True)
+    ref = Oracle(p, extended=True)
+    ref.step(120)
+    s = slbm.Solver(p, prec)
+    s.step(120)
+    s.sync()
+    compare(s, ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_initial_fields_match_reference(slbm, prec):
+    """slbm_init_fields: the equilibrium of given density, velocity, stress
+    and displacement fields, then stepping."""
+    p = mixed_plate(66, 50, seed=3, order=0)
+    rng = np.random.default_rng(7)
+    m = p.mask.astype(float)
+    yy, xx = np.mgrid[0:p.ny, 0:p.nx]
+    rho = 1.0 + 1e-3 * np.sin(xx / 7.0) * np.cos(yy / 5.0)
+    vel = 1e-3 * np.stack([np.sin(yy / 9.0), np.cos(xx / 6.0)]) * m
+    sig = 1e-5 * rng.standard_normal((3, p.ny, p.nx)) * m
+    u0 = 1e-2 * rng.standard_normal((2, p.ny, p.nx)) * m
+    ref = Oracle(p, extended=True)
+    ref.init_fields(rho, vel, sig, u0)
+    s = slbm.Solver(p, prec)
+    s.init_fields(rho, vel, sig, u0)
+    compare(s, ref, prec)          # the state itself, before any step
+    ref.step(60)
+    s.step(60)
+    compare(s, ref, prec)
+
+
+def test_square_config_fp64_full_length(slbm):
+    """128 x 128 plate, left edge clamped, right edge pulled, 2000 steps (fp64)."""
+    p = configs.square_clamped_pulled()
+    ref = Oracle(p, extended=True)
+    ref.step(p.steps)
+    s = slbm.Solver(p, "fp64")
+    s.step(p.steps)
+    s.sync()
+    e = compare(s, ref, "fp64")
+    print(f"square128 fp64 {p.steps} steps: rel L2 u = {e:.3e}")
+
+
+def test_square_config_fp32_10k_steps(slbm):
+    """Same plate in fp32 for 10k steps: displacement within 1e-4 relative L2."""
+    p = configs.square_clamped_pulled(steps=10000)
+    ref = Oracle(p)
+    ref.step(p.steps)
+    s = slbm.Solver(p, "fp32")
+    s.step(p.steps)
+    s.sync()
+    e = compare(s, ref, "fp32", what="u")
+    print(f"square128 fp32 10000 steps: rel L2 u = {e:.3e}")
+
+
+# ------------------------------------------------------ launch shapes --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_result_does_not_depend_on_launch_shape(slbm, prec):
+    """Every site's arithmetic is independent of how rows are split between
+    waves, so any rows-per-wave gives bit-identical state."""
+    p = mixed_plate(150, 97, seed=5, order=1)
+    out = []
+    for seg in (1, 3, 8, 64, 200):
+        s = slbm.Solver(p, prec)
+        s.set_launch(seg)
+        s.step(37)
+        out.append((s.displacement(), s.moments()[2]))
+    for u, P in out[1:]:
+        assert np.array_equal(u, out[0][0])
+        assert np.array_equal(P, out[0][1])
+
+
+@pytest.mark.parametrize("shape", [(1, 7), (2, 2), (3, 5), (61, 9), (62, 3), (63, 4), (64, 65), (124, 2), (125, 33)])
+def test_small_and_ragged_grids(slbm, shape):
+    """Degenerate and ragged sizes around the 62-column strip and the 64-element pitch."""
+    nx, ny = shape
+    p = G.build_plate(nx, ny, lam=0.06, mu=0.05, tau=0.6, periodic_x=True,
+                      walls=[G.HLine(-0.5, 0), G.HLine(ny - 0.5, 1)],
+                      groups=[G.BCGroup(G.DIRICHLET, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (3e-5, 1e-5))],
+                      neumann_order=0)
+    ref = Oracle(p, extended=True)
+    ref.step(40)
+    s = slbm.Solver(p, "fp64")
+    s.step(40)
+    compare(s, ref, "fp64")
+
+
+def test_zero_steps_and_rest_state(slbm):
+    p = mixed_plate(40, 30, seed=9)
+    s = slbm.Solver(p, "fp32")
+    s.step(0)
+    u = s.displacement()
+    assert np.array_equal(u, np.zeros_like(u))
+    assert s.time()[0] == 0
+
+
+# ----------------------------------------------------- state handling --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_resume_is_bitwise(slbm, prec):
+    p = mixed_plate(90, 60, seed=11, order=1)
+    a = slbm.Solver(p, prec)
+    a.step(80)
+    ua = a.displacement()
+    b = slbm.Solver(p, prec)
+    b.step(40)
+    buf = b.save()
+    c = slbm.Solver(p, prec)
+    c.load(buf)
+    assert c.time()[0] == 40
+    c.step(40)
+    assert np.array_equal(c.displacement(), ua)
+
+
+def test_divergence_is_reported(slbm):
+    """lambda/mu = 2 with traction-free walls and the paper's extrapolation
+    is linearly unstable; the non-finite guard must catch the blow-up."""
+    n = 40
+    p = G.build_plate(n, n, lam=0.1, mu=0.05, tau=0.6, walls=G.edge_walls(n, n, 0, 0, 1, 1),
+                      groups=[G.BCGroup(G.NEUMANN, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (0.0, 1e-4))],
+                      neumann_order=1)
+    s = slbm.Solver(p, "fp32")
+    s.step(3000)
+    with pytest.raises(slbm.SlbmError) as e:
+        s.sync()
+    assert e.value.code == -4
+
+
+def test_displacement_to_device_memory(slbm):
+    import torch
+    p = mixed_plate(70, 40, seed=13)
+    stream = torch.cuda.current_stream()
+    s = slbm.Solver(p, "fp32", stream=stream.cuda_stream)
+    s.step(30)
+    t = torch.empty((2, p.ny, p.nx), dtype=torch.float64, device="cuda")
+    s.displacement_device(t.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), s.displacement())
+
+
+# ------------------------------------------------------- full sizes --
+
+@pytest.mark.slow
+def test_crack_config_fp32_full_length(slbm):
+    """1024 x 512 edge-crack plate, fp32 populations, fp64 displacement, 10k
+    steps: displacement within 1e-4 relative L2 of the fp64 reference."""
+    p = configs.edge_crack_plate()
+    s = slbm.Solver(p, "fp32")
+    s.step(p.steps)
+    s.sync()
+    u = s.displacement()
+    ref = Oracle(p)
+    ref.step(p.steps)
+    e = rel_l2(u, ref.displacement())
+    print(f"crack1024x512 fp32 {p.steps} steps: rel L2 u = {e:.3e}")
+    assert e <= FP32_TOL
+
+
+@pytest.mark.slow
+def test_hole_config_full_size_early_window(slbm):
+    """2048 x 2048 plate with the curved hole at its full size, over the first
+    200 steps (lambda/mu = 2 grows a boundary mode later): fp32 within 1e-4."""
+    p = configs.hole_plate()
+    s = slbm.Solver(p, "fp32")
+    s.step(200)
+    s.sync()
+    ref = Oracle(p)
+    ref.step(200)
+    e = rel_l2(s.displacement(), ref.displacement())
+    print(f"hole2048 fp32 200 steps: rel L2 u = {e:.3e}")
+    assert e <= FP32_TOL
