@@ -48,6 +48,7 @@ struct oracle_s {
     double rho_user, mu_user, dt_user, s_sigma, s_v;
     uint8_t* mat;          /* [n] */
     int32_t* link_at;      /* [9][n]: index of cut link (x,k), else -1 */
+    uint8_t* cutm;         /* [n]: bit k-1 set when link (x,k) is cut */
     int nl;
     int32_t *lsite, *ldir, *lgroup, *lgroup2;
     real *lq, *ln, *ln2;   /* q, normal [nl][2], normal2 [nl][2] */
@@ -61,15 +62,21 @@ struct oracle_s {
     int64_t step;
 };
 
-/* neighbour of site s along +c_k (sign = 1) or -c_k (sign = -1); -1 outside */
-static int neighbour(const oracle_t* o, int s, int k, int sign)
+/* neighbour of site (x, y) along +c_k (sign = 1) or -c_k (sign = -1);
+ * -1 outside the grid */
+static int neighbour_xy(const oracle_t* o, int x, int y, int k, int sign)
 {
-    int x = s % o->nx + sign * CX[k];
-    int y = s / o->nx + sign * CY[k];
+    x += sign * CX[k];
+    y += sign * CY[k];
     if (o->px) x = (x + o->nx) % o->nx;
     if (o->py) y = (y + o->ny) % o->ny;
     if (x < 0 || x >= o->nx || y < 0 || y >= o->ny) return -1;
     return y * o->nx + x;
+}
+
+static int neighbour(const oracle_t* o, int s, int k, int sign)
+{
+    return neighbour_xy(o, s % o->nx, s / o->nx, k, sign);
 }
 
 static void* xcalloc(size_t n, size_t sz)
@@ -160,6 +167,7 @@ oracle_t* oracle_create(const oracle_problem* p, char* err, int errlen)
 
     o->link_at = (int32_t*)xcalloc((size_t)9 * n, sizeof(int32_t));
     for (size_t i = 0; i < (size_t)9 * n; i++) o->link_at[i] = -1;
+    o->cutm = (uint8_t*)xcalloc(n, 1);
     o->nl = p->n_links;
     o->lsite = (int32_t*)xcalloc(o->nl, sizeof(int32_t));
     o->ldir = (int32_t*)xcalloc(o->nl, sizeof(int32_t));
@@ -183,6 +191,7 @@ oracle_t* oracle_create(const oracle_problem* p, char* err, int errlen)
             if (fabs(n2 - 1.0) > 1e-9) FAIL("link %d: second normal is not a unit vector", l);
         }
         o->link_at[(size_t)k * n + s] = l;
+        o->cutm[s] |= (uint8_t)(1u << (k - 1));
         o->lsite[l] = s; o->ldir[l] = k;
         o->lq[l] = (real)p->link_q[l];
         o->lgroup[l] = p->link_group[l]; o->lgroup2[l] = p->link_group2[l];
@@ -225,7 +234,7 @@ oracle_t* oracle_create(const oracle_problem* p, char* err, int errlen)
 void oracle_destroy(oracle_t* o)
 {
     if (!o) return;
-    free(o->mat); free(o->link_at);
+    free(o->mat); free(o->link_at); free(o->cutm);
     free(o->lsite); free(o->ldir); free(o->lgroup); free(o->lgroup2);
     free(o->lq); free(o->ln); free(o->ln2);
     free(o->gkind); free(o->gprof); free(o->gval); free(o->gramp);
@@ -274,13 +283,14 @@ static void source_term(oracle_t* o)
 #pragma omp parallel for schedule(static)
     for (int s = 0; s < n; s++) {
         if (!o->mat[s]) continue;
+        int x = s % o->nx, y = s / o->nx;
         real gx = 0, gy = 0;
         for (int i = 1; i < 9; i++) {
             real r;
-            if (o->link_at[(size_t)i * n + s] < 0) {
-                r = o->rho[neighbour(o, s, i, +1)];
-            } else if (o->link_at[(size_t)OPP[i] * n + s] < 0) {
-                r = 2 * o->rho[s] - o->rho[neighbour(o, s, i, -1)];
+            if (!(o->cutm[s] >> (i - 1) & 1)) {
+                r = o->rho[neighbour_xy(o, x, y, i, +1)];
+            } else if (!(o->cutm[s] >> (OPP[i] - 1) & 1)) {
+                r = 2 * o->rho[s] - o->rho[neighbour_xy(o, x, y, i, -1)];
             } else {
                 r = o->rho[s];
             }
@@ -422,10 +432,11 @@ void oracle_step(oracle_t* o, int64_t nsteps)
 #pragma omp parallel for schedule(static)
         for (int s = 0; s < n; s++) {
             if (!o->mat[s]) continue;
+            int x = s % o->nx, y = s / o->nx;
             o->fnew[s] = o->fcol[s];
             for (int i = 1; i < 9; i++)
-                if (o->link_at[(size_t)i * n + s] < 0)
-                    o->fnew[(size_t)i * n + neighbour(o, s, i, +1)] = o->fcol[(size_t)i * n + s];
+                if (!(o->cutm[s] >> (i - 1) & 1))
+                    o->fnew[(size_t)i * n + neighbour_xy(o, x, y, i, +1)] = o->fcol[(size_t)i * n + s];
         }
         /* section 4: cut links get their returning population from the rules */
 #pragma omp parallel for schedule(static)
