@@ -59,9 +59,11 @@ def edge_crack_plate(nx: int = 1024, ny: int = 512, crack: int = 256, *, mu: flo
               BCGroup(NEUMANN, (0.0, -load * mu))]     # 2 bottom, pulled down
     walls = edge_walls(nx, ny, left=0, right=0, bottom=2, top=1)
     walls.append(HLine(yc, 0, x_lo=-0.5, x_hi=crack - 0.5))
-    return build_plate(nx, ny, lam=lam, mu=mu, tau=tau, walls=walls, groups=groups,
-                       name=f"crack{nx}x{ny}-a{crack}", steps=steps,
-                       neumann_order=neumann_order)
+    plate = build_plate(nx, ny, lam=lam, mu=mu, tau=tau, walls=walls, groups=groups,
+                        name=f"crack{nx}x{ny}-a{crack}", steps=steps,
+                        neumann_order=neumann_order)
+    plate.crack_tip_x = crack - 0.5
+    return plate
 
 
 def hole_plate(n: int = 2048, R: float = 256.0, *, mu: float = 0.05, lam: float = 0.1,

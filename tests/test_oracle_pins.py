@@ -343,3 +343,20 @@ def test_rayleigh_root_closed_form():
     the classical root c_R = 0.9194 c_s at nu = 1/4."""
     cs, cd = CF.wave_speeds(1.0, 1.0)
     assert abs(CF.rayleigh_speed(cs, cd) / cs - 0.91940) < 1e-5
+
+
+# ------------------------------------------------ Freund's K^0 (crack) --
+
+def test_crack_tip_sif_follows_freund_k0():
+    """Suddenly loaded stationary crack (section 5.2): until waves from the
+    crack mouth arrive, the mode-I stress intensity factor of a semi-infinite
+    crack grows as K^0 = 2 t* sqrt(1 - 2 nu)/(1 - nu) sqrt(c_d t/pi).  On the
+    1024 x 512 edge-crack plate the sqrt(t) coefficient must match within 5 %
+    and the onset may lag the wave arrival by at most 40 steps."""
+    from crack_sif import sif_series
+    p = configs.edge_crack_plate(steps=400)
+    o = Oracle(p)
+    t1 = p.ny // 2          # c_d = 1 cell per step at lambda = mu
+    ratio, lag = sif_series(o.step, lambda: o.moments()[3][1], p, 1e-3 * p.mu, t1)
+    assert abs(ratio - 1) < 0.05, ratio
+    assert 0 <= lag <= 40, lag
