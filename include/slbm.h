@@ -153,9 +153,18 @@ int slbm_displacement_device(slbm_handle h, void* u_dev);
 /* Step count and physical time of the current state. */
 int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 
-/* Launch shape of the fused step: rows per wave (seg_rows >= 1).  0 keeps
- * the library's choice.  Results do not depend on it. */
-int slbm_set_launch(slbm_handle h, int32_t seg_rows);
+/* Launch shape of the fused step: rows each wave marches (seg_rows >= 1)
+ * and strip width (64: aligned columns, one per lane; 62: unaligned, two
+ * halo lanes per wave).  0 keeps the library's choice for either.  Results
+ * do not depend on the shape. */
+int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
+
+/* Times the fused step on this plate for each strip width and a range of
+ * rows per wave (short bursts of launches, the state restored after each)
+ * and keeps the fastest; reports it and its time per step in microseconds
+ * (any pointer may be NULL).  Synchronises.  The state and step count are
+ * unchanged. */
+int slbm_autotune(slbm_handle h, int32_t* seg_rows, int32_t* strip, double* us_per_step);
 
 /* Checkpoint: the full state in an opaque buffer.  With buf = NULL,
  * slbm_save only reports the size in *bytes. */

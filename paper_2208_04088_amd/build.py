@@ -15,6 +15,10 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed fp32 instructions stay off (the compiler would otherwise form them)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no fused multiply-add contraction: every launch shape and code path
+    # rounds the same expressions the same way, so results are bit-identical
+    # whatever the strip width or rows per wave
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
 

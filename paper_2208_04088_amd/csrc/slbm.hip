@@ -7,16 +7,22 @@
 // conventions.
 //
 // Data layout in HBM (one plate):
-//   populations  two buffers of [9][ny][ld] `real`, structure of arrays, row
-//                pitch ld = nx rounded up to 64 elements.  They hold shifted
+//   populations  two buffers of [9][ny+2][ld] `real`, structure of arrays:
+//                site (x, y) sits at row y+1, column x+64 of each plane, inside
+//                a padding ring that no step writes (one row above and below,
+//                64 columns left, at least one right), so that the pull
+//                addresses of every in-grid site stay inside the allocation
+//                and can be issued before the site's flags arrive, and so
+//                that the 64 columns a wave owns start on a 256-byte
+//                boundary.  The row pitch ld is a multiple of 64.  They hold shifted
 //                populations g_i = f_i - r_i, r_i the rest equilibrium
 //                (8/9, 1/18 x4, -1/36 x4), so that fp32 resolves the small
 //                deviation from rest instead of the O(1) rest values.
-//   U            [2][ny][ld] double, the running sum of j/rho.
-//   flags        [ny][ld] uint8: 0 = material site with no cut link,
-//                0xFF = no state (void or padding), otherwise bit k-1 set
+//   U            [2][ny+2][ld] double, the running sum of j/rho.
+//   flags        [ny+2][ld] uint8: 0 = material site with no cut link,
+//                0xFF = no state (void or the ring), otherwise bit k-1 set
 //                when the link toward x + c_k is cut.
-//   bidx         [ny][ld] int32, index of the site's first cut-link record
+//   bidx         [ny+2][ld] int32, index of the site's first cut-link record
 //                (read only at boundary sites).
 //   links        one record per cut link, sorted by (site, direction), with
 //                the coefficients of its boundary rule precomputed.
@@ -78,7 +84,15 @@ __host__ __device__ constexpr int CY(int i) { return (i == 2 || i == 5 || i == 6
 __host__ __device__ constexpr int OPP(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5); }
 __host__ __device__ constexpr double WD(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
-constexpr int kStrip = 62;     // output columns per wave (64 lanes, one halo lane each side)
+constexpr int kPadL = 64;      // padding columns left of the grid: keeps wide strips 256-byte aligned
+
+// Two strip shapes for the fused step (the autotuner picks per plate):
+//   wide   64 output columns per wave, 256-byte aligned; the two density-halo
+//          sites are fetched by the half-waves;
+//   narrow 62 output columns per wave (lanes 1..62); lanes 0 and 63 sit on
+//          the halo columns and only supply density.  Fewer registers, more
+//          waves in flight, unaligned rows: faster on small plates.
+template <bool WIDE> constexpr int strip_width() { return WIDE ? 64 : 62; }
 constexpr unsigned kVoid = 0xFFu;
 
 struct GroupDev {
@@ -167,6 +181,10 @@ __device__ __forceinline__ void moments9(const real g[9], real& dr, real& jx, re
     pxy = d57 - d68;
 }
 
+// Offset of site (x, y) in a padded plane.
+__host__ __device__ __forceinline__ int sidx(int x, int y, int ld) { return (y + 1) * ld + (x + kPadL); }
+
+// Offset of the site at (x + dx, y + dy), wrapped on periodic axes.
 template <bool PER>
 __device__ __forceinline__ int wrap_off(int x, int y, int dx, int dy, int nx, int ny, int ld, int px, int py)
 {
@@ -175,7 +193,7 @@ __device__ __forceinline__ int wrap_off(int x, int y, int dx, int dy, int nx, in
         if (px) xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
         if (py) yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     }
-    return yy * ld + xx;
+    return sidx(xx, yy, ld);
 }
 
 // Moments of the post-collision populations stored at site offset s.
@@ -236,39 +254,11 @@ __device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, 
     return -gk - L.kappa * (gky + gkb) + L.be[0] * drbd + L.be[1] * Pxx + L.be[2] * Pyy + L.be[3] * Pxy;
 }
 
-// Populations at site (x, y) for the current step.  Returns false for sites
-// without state.  x, y are in range (wrapped by the caller where periodic).
+// Replaces the populations of cut links of a boundary site by the section 4
+// rules.  g already holds the pulls along uncut links.
 template <typename real, bool PER>
-__device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y, real g[9], unsigned& flo)
+__device__ void boundary_fixup(const StepArgs<real>& a, int x, int y, int s, unsigned fl, real g[9])
 {
-    const int s = y * a.ld + x;
-    const unsigned fl = a.flags[s];
-    flo = fl;
-    if (fl == kVoid) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = real(0);
-        return false;
-    }
-    if (a.local) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = a.src[i * a.plane + s];
-        return true;
-    }
-    if (fl == 0) {
-        // bulk site: eq:stream as a pull from x - c_i
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            g[i] = a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
-        return true;
-    }
-    // boundary site: pull along uncut links, rules on cut ones
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int k = OPP(i);
-        const bool cut = (i != 0) && ((fl >> (k - 1)) & 1u);
-        g[i] = cut ? real(0)
-                   : a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
-    }
     real drx, pxxx, pyyx, pxyx;
     stored_moments(a, s, drx, pxxx, pyyx, pxyx);
     int li = a.bidx[s];
@@ -283,36 +273,219 @@ __device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y
         for (int j = 1; j < 9; ++j)
             if (j == i) g[j] = v;
     }
+}
+
+// Populations at site (x, y) for the current step (x, y in the grid, wrapped
+// by the caller on periodic axes).  Returns false for sites without state.
+template <typename real, bool PER>
+__device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y, real g[9], unsigned& flo)
+{
+    const int s = sidx(x, y, a.ld);
+    const unsigned fl = a.flags[s];
+    flo = fl;
+    if (fl == kVoid) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = real(0);
+        return false;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        g[i] = a.local ? a.src[i * a.plane + s]
+                       : a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
+    if (!a.local && fl != 0) boundary_fixup<real, PER>(a, x, y, s, fl, g);
     return true;
 }
 
-// Row loader of the sliding window: state of site (x, y) or "no state".
+// One row of the sliding window: loads in flight, then completed.  Besides
+// its own site, every lane fetches one density-halo site of its wave's strip:
+// lanes 0-31 the site left of the strip, lanes 32-63 the one right of it
+// (lane 0 and lane 63 use them).
+template <typename real, bool WIDE>
+struct Row {
+    real g[9];                 // own site
+    real h[WIDE ? 9 : 1];      // halo site (wide strips)
+    double ux, uy;
+    unsigned fl, flh;
+    int y, yh;
+    bool in, inh;
+};
+
+// Loads of one site, unconditional: a site outside the grid loads from a
+// clamped in-grid site and is masked when completed (a conditional load
+// would make the compiler wait for earlier loads before initialising its
+// target registers).  The padding ring keeps the pull addresses of any
+// in-grid site inside the allocation.
 template <typename real, bool PER>
-__device__ __forceinline__ bool fetch_row(const StepArgs<real>& a, int x, bool xin, int y, real g[9],
-                                          unsigned& fl, real& dr)
+__device__ __forceinline__ void site_issue(const StepArgs<real>& a, int x, int y, real g[9], unsigned& fl,
+                                           int& ys, bool& in, int& s_out)
 {
-    bool ok = xin;
+    in = true;
+    if (x < 0 || x >= a.nx) {
+        if (PER && a.px) x = x < 0 ? x + a.nx : x - a.nx;
+        if (x < 0 || x >= a.nx) {
+            in = false;
+            x = x < 0 ? 0 : a.nx - 1;
+        }
+    }
     if (y < 0 || y >= a.ny) {
-        if (PER && a.py) y = y < 0 ? y + a.ny : y - a.ny;
-        else ok = false;
+        if (PER && a.py) {
+            y = y < 0 ? y + a.ny : y - a.ny;
+        } else {
+            in = false;
+            y = y < 0 ? 0 : a.ny - 1;
+        }
     }
-    if (ok) ok = fetch_site<real, PER>(a, x, y, g, fl);
-    if (!ok) {
-        fl = kVoid;
+    ys = y;
+    const int s = sidx(x, y, a.ld);
+    s_out = s;
+    fl = a.flags[s];
+    if (a.local) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = real(0);
-        dr = real(0);
-        return false;
+        for (int i = 0; i < 9; ++i) g[i] = a.src[i * a.plane + s];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            g[i] = a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
     }
-    dr = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-    return true;
+}
+
+template <typename real, bool PER, bool WIDE>
+__device__ __forceinline__ void row_issue(const StepArgs<real>& a, int x, int xh, int y, Row<real, WIDE>& r)
+{
+    int s, sh;
+    site_issue<real, PER>(a, x, y, r.g, r.fl, r.y, r.in, s);
+    if constexpr (WIDE) site_issue<real, PER>(a, xh, y, r.h, r.flh, r.yh, r.inh, sh);
+    r.ux = a.U[s];
+    r.uy = a.U[a.plane + s];
+}
+
+// Completes one site: boundary rules on cut links, nothing for void sites.
+// Returns delta-rho (0 without state).
+template <typename real, bool PER>
+__device__ __forceinline__ real site_finish(const StepArgs<real>& a, int x, int y, bool in, bool want,
+                                            unsigned& fl, real g[9])
+{
+    if (!in) fl = kVoid;
+    const bool live = fl != kVoid;
+    if (want && live && !a.local && fl != 0) {
+        int xx = x;
+        if (PER && a.px) xx = xx < 0 ? xx + a.nx : (xx >= a.nx ? xx - a.nx : xx);
+        boundary_fixup<real, PER>(a, xx, y, sidx(xx, y, a.ld), fl, g);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = live ? g[i] : real(0);
+    return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+}
+
+// Density window of the gradient stencil: delta-rho of rows y-1, y at this
+// lane and its two neighbours.
+template <typename real>
+struct Window {
+    real m, m_l, m_r;
+    real c, c_l, c_r;
+};
+
+// Collision, source term and displacement update of one site (row B), given
+// the density window and the next row's densities.
+template <typename real, bool WIDE>
+__device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const Row<real, WIDE>& B,
+                                             const Window<real>& w, real rp, real rp_l, real rp_r)
+{
+    const unsigned fl = B.fl;
+    const real* g = B.g;
+    real dr, jx, jy, pxx, pyy, pxy;
+    moments9(g, dr, jx, jy, pxx, pyy, pxy);
+    // eq:sourceterm: isotropic D2Q9 gradient of rho; across a cut link the
+    // neighbour is extrapolated from the opposite side
+    real nb[9];
+    nb[1] = w.c_r; nb[2] = rp; nb[3] = w.c_l; nb[4] = w.m;
+    nb[5] = rp_r; nb[6] = rp_l; nb[7] = w.m_l; nb[8] = w.m_r;
+    real rt[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const bool ci = (fl >> (i - 1)) & 1u;
+        const bool co = (fl >> (OPP(i) - 1)) & 1u;
+        rt[i] = ci ? (co ? dr : real(2) * dr - nb[OPP(i)]) : nb[i];
+    }
+    const real gx = real(1.0 / 3.0) * (rt[1] - rt[3]) + real(1.0 / 12.0) * (rt[5] - rt[6] - rt[7] + rt[8]);
+    const real gy = real(1.0 / 3.0) * (rt[2] - rt[4]) + real(1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
+    const real rho = real(1) + dr;
+    const real c = a.ml / rho;
+    const real Sx = a.Fx + c * gx, Sy = a.Fy + c * gy;
+    jx += real(0.5) * Sx;
+    jy += real(0.5) * Sy;
+    // eq:coll with eq:fieq and psi_i = w_i c_i.S / c_s^2
+    real e[9];
+    e[0] = geq<0>(dr, jx, jy, pxx, pyy, pxy);
+    e[1] = geq<1>(dr, jx, jy, pxx, pyy, pxy);
+    e[2] = geq<2>(dr, jx, jy, pxx, pyy, pxy);
+    e[3] = geq<3>(dr, jx, jy, pxx, pyy, pxy);
+    e[4] = geq<4>(dr, jx, jy, pxx, pyy, pxy);
+    e[5] = geq<5>(dr, jx, jy, pxx, pyy, pxy);
+    e[6] = geq<6>(dr, jx, jy, pxx, pyy, pxy);
+    e[7] = geq<7>(dr, jx, jy, pxx, pyy, pxy);
+    e[8] = geq<8>(dr, jx, jy, pxx, pyy, pxy);
+    const real px1 = a.cpsi * real(1.0 / 3.0) * Sx, py1 = a.cpsi * real(1.0 / 3.0) * Sy;
+    const real pd = a.cpsi * real(1.0 / 12.0);
+    real psi[9];
+    psi[0] = real(0);
+    psi[1] = px1; psi[3] = -px1; psi[2] = py1; psi[4] = -py1;
+    psi[5] = pd * (Sx + Sy); psi[7] = -psi[5];
+    psi[6] = pd * (Sy - Sx); psi[8] = -psi[6];
+    const int s = sidx(x, y, a.ld);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        a.dst[i * a.plane + s] = g[i] + a.omega * (e[i] - g[i]) + psi[i];
+    // displacement: U += j/rho (fp64 accumulation)
+    const double ir = 1.0 / (double)rho;
+    a.U[s] = B.ux + (double)jx * ir;
+    a.U[a.plane + s] = B.uy + (double)jy * ir;
+    return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
+}
+
+// Densities of a completed row as seen by this lane: own site, and the sites
+// left and right of it (from the neighbouring lanes, or the halo site at the
+// ends of the strip).
+template <typename real, bool PER, bool WIDE>
+__device__ __forceinline__ void row_density(const StepArgs<real>& a, int lane, int x, int xh, Row<real, WIDE>& r,
+                                            real& d, real& d_l, real& d_r)
+{
+    d = site_finish<real, PER>(a, x, r.y, r.in, true, r.fl, r.g);
+    const real up = __shfl_up(d, 1), dn = __shfl_down(d, 1);
+    if constexpr (WIDE) {
+        const real dh = site_finish<real, PER>(a, xh, r.yh, r.inh, lane == 0 || lane == 63, r.flh, r.h);
+        d_l = lane == 0 ? dh : up;
+        d_r = lane == 63 ? dh : dn;
+    } else {
+        d_l = up;
+        d_r = dn;
+    }
+}
+
+// One row of the march: issue row y+2 into D, complete row y+1 (C), compute
+// row y (B).  Called with the three rows in rotating roles so that no row's
+// registers are ever copied while its loads are in flight.
+template <typename real, bool PER, bool WIDE>
+__device__ __forceinline__ bool march_row(const StepArgs<real>& a, int lane, int x, int xh, bool out, int y,
+                                          Row<real, WIDE>& B, Row<real, WIDE>& C, Row<real, WIDE>& D,
+                                          Window<real>& w)
+{
+    row_issue<real, PER, WIDE>(a, x, xh, y + 2, D);
+    real rp, rp_l, rp_r;
+    row_density<real, PER, WIDE>(a, lane, x, xh, C, rp, rp_l, rp_r);
+    bool bad = false;
+    if (out && B.fl != kVoid) bad = collide_site<real, WIDE>(a, x, y, B, w, rp, rp_l, rp_r);
+    w.m = w.c; w.m_l = w.c_l; w.m_r = w.c_r;
+    w.c = rp; w.c_l = rp_l; w.c_r = rp_r;
+    return bad;
 }
 
 // One time step of the whole lattice (section 3 and section 4).  One wave per
-// workgroup; a wave owns a strip of 62 columns (lanes 1..62, lanes 0 and 63
-// only supply density to the gradient stencil) and marches up `seg` rows,
-// keeping the densities of three rows in registers for the stencil.
-template <typename real, bool PER>
+// workgroup; a wave owns a strip of columns (wide or narrow, see
+// strip_width) and marches up `seg` rows with a three-row density window in
+// registers.  The loads of row y+2 are issued before row y is computed, so a
+// row's memory latency overlaps the previous row's arithmetic.
+template <typename real, bool PER, bool WIDE>
 __global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
 {
     const int lane = threadIdx.x;
@@ -325,85 +498,27 @@ __global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
     if (tile >= a.ntiles) return;
     const int strip = tile % a.nstrips;
     const int segm = tile / a.nstrips;
-    const int x0 = strip * kStrip - 1 + lane;
-    int x = x0;
-    bool xin = x >= 0 && x < a.nx;
-    if (PER && a.px && !xin) {
-        x = x < 0 ? x + a.nx : x - a.nx;
-        xin = x >= 0 && x < a.nx;
-    }
-    const bool out = lane >= 1 && lane <= kStrip && x0 < a.nx;
+    constexpr int W = strip_width<WIDE>();
+    const int x = WIDE ? strip * W + lane : strip * W - 1 + lane;
+    const int xh = lane < 32 ? strip * W - 1 : strip * W + W;
+    const bool out = x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
     const int y0 = segm * a.seg;
     const int y1 = min(y0 + a.seg, a.ny);
 
-    real g[9], gn[9];
-    unsigned fl, fln;
-    real rm, rc, rp;
-    fetch_row<real, PER>(a, x, xin, y0 - 1, gn, fln, rm);
-    bool vc = fetch_row<real, PER>(a, x, xin, y0, g, fl, rc);
-    real rm_l = __shfl_up(rm, 1), rm_r = __shfl_down(rm, 1);
-    real rc_l = __shfl_up(rc, 1), rc_r = __shfl_down(rc, 1);
+    Row<real, WIDE> R0, R1, R2;
+    Window<real> w;
+    row_issue<real, PER, WIDE>(a, x, xh, y0 - 1, R2);
+    row_issue<real, PER, WIDE>(a, x, xh, y0, R0);
+    row_issue<real, PER, WIDE>(a, x, xh, y0 + 1, R1);
+    row_density<real, PER, WIDE>(a, lane, x, xh, R2, w.m, w.m_l, w.m_r);
+    row_density<real, PER, WIDE>(a, lane, x, xh, R0, w.c, w.c_l, w.c_r);
     bool bad = false;
-
-    for (int y = y0; y < y1; ++y) {
-        const bool vn = fetch_row<real, PER>(a, x, xin, y + 1, gn, fln, rp);
-        const real rp_l = __shfl_up(rp, 1), rp_r = __shfl_down(rp, 1);
-        if (out && vc) {
-            real dr, jx, jy, pxx, pyy, pxy;
-            moments9(g, dr, jx, jy, pxx, pyy, pxy);
-            // eq:sourceterm: isotropic D2Q9 gradient of rho; across a cut link
-            // the neighbour is extrapolated from the opposite side
-            real nb[9];
-            nb[1] = rc_r; nb[2] = rp; nb[3] = rc_l; nb[4] = rm;
-            nb[5] = rp_r; nb[6] = rp_l; nb[7] = rm_l; nb[8] = rm_r;
-            real rt[9];
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const bool ci = (fl >> (i - 1)) & 1u;
-                const bool co = (fl >> (OPP(i) - 1)) & 1u;
-                rt[i] = ci ? (co ? dr : real(2) * dr - nb[OPP(i)]) : nb[i];
-            }
-            const real gx = real(1.0 / 3.0) * (rt[1] - rt[3]) + real(1.0 / 12.0) * (rt[5] - rt[6] - rt[7] + rt[8]);
-            const real gy = real(1.0 / 3.0) * (rt[2] - rt[4]) + real(1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
-            const real rho = real(1) + dr;
-            const real c = a.ml / rho;
-            const real Sx = a.Fx + c * gx, Sy = a.Fy + c * gy;
-            jx += real(0.5) * Sx;
-            jy += real(0.5) * Sy;
-            // eq:coll with eq:fieq and psi_i = w_i c_i.S / c_s^2
-            real e[9];
-            e[0] = geq<0>(dr, jx, jy, pxx, pyy, pxy);
-            e[1] = geq<1>(dr, jx, jy, pxx, pyy, pxy);
-            e[2] = geq<2>(dr, jx, jy, pxx, pyy, pxy);
-            e[3] = geq<3>(dr, jx, jy, pxx, pyy, pxy);
-            e[4] = geq<4>(dr, jx, jy, pxx, pyy, pxy);
-            e[5] = geq<5>(dr, jx, jy, pxx, pyy, pxy);
-            e[6] = geq<6>(dr, jx, jy, pxx, pyy, pxy);
-            e[7] = geq<7>(dr, jx, jy, pxx, pyy, pxy);
-            e[8] = geq<8>(dr, jx, jy, pxx, pyy, pxy);
-            const real px1 = a.cpsi * real(1.0 / 3.0) * Sx, py1 = a.cpsi * real(1.0 / 3.0) * Sy;
-            const real pd = a.cpsi * real(1.0 / 12.0);
-            real psi[9];
-            psi[0] = real(0);
-            psi[1] = px1; psi[3] = -px1; psi[2] = py1; psi[4] = -py1;
-            psi[5] = pd * (Sx + Sy); psi[7] = -psi[5];
-            psi[6] = pd * (Sy - Sx); psi[8] = -psi[6];
-            const int s = y * a.ld + x;
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                a.dst[i * a.plane + s] = g[i] + a.omega * (e[i] - g[i]) + psi[i];
-            // displacement: U += j/rho (fp64 accumulation)
-            const double ir = 1.0 / (double)rho;
-            a.U[s] += (double)jx * ir;
-            a.U[a.plane + s] += (double)jy * ir;
-            bad |= !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
-        }
-        rm = rc; rm_l = rc_l; rm_r = rc_r;
-        rc = rp; rc_l = rp_l; rc_r = rp_r;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = gn[i];
-        fl = fln;
-        vc = vn;
+    for (int y = y0; y < y1; y += 3) {
+        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y, R0, R1, R2, w);
+        if (y + 1 >= y1) break;
+        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y + 1, R1, R2, R0, w);
+        if (y + 2 >= y1) break;
+        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y + 2, R2, R0, R1, w);
     }
     if (bad) atomicOr(a.diverged, 1u);
 }
@@ -415,10 +530,10 @@ template <typename real, bool PER>
 __global__ __launch_bounds__(256) void k_density(StepArgs<real> a, double* dr_out)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.ny * a.ld) return;
-    const int y = idx / a.ld, x = idx - y * a.ld;
+    if (idx >= a.plane) return;
+    const int y = idx / a.ld - 1, x = idx % a.ld - kPadL;
     double v = 0.0;
-    if (x < a.nx) {
+    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny) {
         real g[9];
         unsigned fl;
         if (fetch_site<real, PER>(a, x, y, g, fl)) {
@@ -436,8 +551,8 @@ template <bool PER>
 __device__ void grad_rho(const double* dr, const uint8_t* flags, int x, int y, int nx, int ny, int ld,
                          int px, int py, double& gx, double& gy)
 {
-    const unsigned fl = flags[y * ld + x];
-    const double d0 = dr[y * ld + x];
+    const unsigned fl = flags[sidx(x, y, ld)];
+    const double d0 = dr[sidx(x, y, ld)];
     double nb[9];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
@@ -455,17 +570,17 @@ __device__ void grad_rho(const double* dr, const uint8_t* flags, int x, int y, i
     gy = (1.0 / 3.0) * (rt[2] - rt[4]) + (1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
 }
 
-// Lattice-unit moments and displacement: out[11][ny][ld] =
+// Lattice-unit moments and displacement, padded planes out[11] =
 // rho, jx, jy, Pxx, Pyy, Pxy, sxx, syy, sxy, ux, uy.
 template <typename real, bool PER>
 __global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double* dr, double* out)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const long long P = (long long)a.ny * a.ld;
+    const long long P = a.plane;
     if (idx >= P) return;
-    const int y = idx / a.ld, x = idx - y * a.ld;
+    const int y = idx / a.ld - 1, x = idx % a.ld - kPadL;
     double o[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (x < a.nx && a.flags[idx] != kVoid) {
+    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && a.flags[idx] != kVoid) {
         real g[9];
         unsigned fl;
         fetch_site<real, PER>(a, x, y, g, fl);
@@ -495,9 +610,9 @@ __global__ __launch_bounds__(256) void k_unpad_u(const double* out, int nx, int 
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nx * ny) return;
     const int y = idx / nx, x = idx - y * nx;
-    const long long P = (long long)ny * ld;
-    u[idx] = out[9 * P + (long long)y * ld + x];
-    u[(long long)nx * ny + idx] = out[10 * P + (long long)y * ld + x];
+    const long long P = (long long)(ny + 2) * ld;
+    u[idx] = out[9 * P + sidx(x, y, ld)];
+    u[(long long)nx * ny + idx] = out[10 * P + sidx(x, y, ld)];
 }
 
 // ------------------------------------------------------- initial state
@@ -509,12 +624,12 @@ __global__ __launch_bounds__(256) void k_init(StepArgs<real> a, const double* dr
                                               const double* Pf, const double* uf, real* g_out)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const long long P = (long long)a.ny * a.ld;
+    const long long P = a.plane;
     if (idx >= P) return;
-    const int y = idx / a.ld, x = idx - y * a.ld;
+    const int y = idx / a.ld - 1, x = idx % a.ld - kPadL;
     double gi[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double ux = 0, uy = 0;
-    if (x < a.nx && a.flags[idx] != kVoid) {
+    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && a.flags[idx] != kVoid) {
         double gx, gy;
         grad_rho<PER>(dr, a.flags, x, y, a.nx, a.ny, a.ld, a.px, a.py, gx, gy);
         const double d = dr[idx], rho = 1.0 + d;
@@ -568,20 +683,28 @@ struct slbm_s {
     int64_t step = 0;
     bool local = true;
     int seg = 0;
+    int wide = -1;                   // strip shape: 1 wide, 0 narrow, -1 library default
     std::vector<uint8_t> mask;
 };
 
 namespace {
 
+bool pick_wide(const slbm_s* h)
+{
+    if (h->wide >= 0) return h->wide == 1;
+    return (long long)h->nx * h->ny >= (1LL << 22);   // wide strips pay off on large plates
+}
+
 int pick_seg(const slbm_s* h)
 {
     if (h->seg > 0) return h->seg;
-    // aim for at least ~8 waves per CU on 256 CUs, rows per wave in [4, 64]
-    const int nstrips = (h->nx + kStrip - 1) / kStrip;
-    const long long target = 8LL * 256;
+    // aim for ~16 waves per CU on 256 CUs, rows per wave in [2, 64]
+    const int sw = pick_wide(h) ? 64 : 62;
+    const int nstrips = (h->nx + sw - 1) / sw;
+    const long long target = 16LL * 256;
     long long segs = (target + nstrips - 1) / nstrips;
     int seg = (int)std::max<long long>(1, (h->ny + segs - 1) / segs);
-    return std::min(64, std::max(4, seg));
+    return std::min(64, std::max(2, seg));
 }
 
 template <typename real>
@@ -600,7 +723,8 @@ StepArgs<real> make_args(const slbm_s* h, int src)
     a.t_prev = h->step - 1;
     a.nx = h->nx; a.ny = h->ny; a.ld = h->ld;
     a.seg = pick_seg(h);
-    a.nstrips = (h->nx + kStrip - 1) / kStrip;
+    const int sw = pick_wide(h) ? 64 : 62;
+    a.nstrips = (h->nx + sw - 1) / sw;
     a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
     a.px = h->px; a.py = h->py;
     a.local = h->local ? 1 : 0;
@@ -614,14 +738,44 @@ StepArgs<real> make_args(const slbm_s* h, int src)
 }
 
 template <typename real>
+void dispatch_step(const slbm_s* h, const StepArgs<real>& a)
+{
+    const int grid = ((a.ntiles + 7) / 8) * 8;
+    const bool per = h->px || h->py, wide = pick_wide(h);
+    if (per && wide)
+        hipLaunchKernelGGL((k_step<real, true, true>), dim3(grid), dim3(64), 0, h->stream, a);
+    else if (per)
+        hipLaunchKernelGGL((k_step<real, true, false>), dim3(grid), dim3(64), 0, h->stream, a);
+    else if (wide)
+        hipLaunchKernelGGL((k_step<real, false, true>), dim3(grid), dim3(64), 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_step<real, false, false>), dim3(grid), dim3(64), 0, h->stream, a);
+}
+
+// One step from the current state into the other buffer with the given
+// launch shape, without committing it (the caller decides).
+template <typename real>
+int launch_step_raw(slbm_s* h, int seg, int wide)
+{
+    const int keep = h->seg, keepw = h->wide;
+    h->seg = seg;
+    h->wide = wide;
+    StepArgs<real> a = make_args<real>(h, h->cur);
+    h->seg = keep;
+    // always the pull path, whose memory traffic is that of a step (a state
+    // just created or initialised would otherwise be read in place)
+    a.local = 0;
+    dispatch_step<real>(h, a);
+    h->wide = keepw;
+    HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
+template <typename real>
 int launch_step(slbm_s* h)
 {
     StepArgs<real> a = make_args<real>(h, h->cur);
-    const int grid = ((a.ntiles + 7) / 8) * 8;
-    if (h->px || h->py)
-        hipLaunchKernelGGL((k_step<real, true>), dim3(grid), dim3(64), 0, h->stream, a);
-    else
-        hipLaunchKernelGGL((k_step<real, false>), dim3(grid), dim3(64), 0, h->stream, a);
+    dispatch_step<real>(h, a);
     HIP_TRY(hipGetLastError());
     h->cur ^= 1;
     h->local = false;
@@ -831,8 +985,8 @@ int create_impl(const slbm_params* p, slbm_handle* out)
     if (!h) return fail(SLBM_E_NOMEM, "out of host memory");
     h->device = p->device;
     h->nx = nx; h->ny = ny;
-    h->ld = (nx + 63) / 64 * 64;
-    h->plane = (long long)h->ld * ny;
+    h->ld = (kPadL + nx + 1 + 63) / 64 * 64;
+    h->plane = (long long)h->ld * (ny + 2);
     h->precision = p->precision;
     h->px = p->periodic_x ? 1 : 0;
     h->py = p->periodic_y ? 1 : 0;
@@ -889,12 +1043,12 @@ int create_impl(const slbm_params* p, slbm_handle* out)
         std::vector<int32_t> bi((size_t)h->plane, -1);
         for (int s = 0; s < n; ++s) {
             if (!mat[s]) continue;
-            const size_t d = (size_t)(s / nx) * h->ld + (s % nx);
+            const size_t d = (size_t)sidx(s % nx, s / nx, h->ld);
             fl[d] = cut[s];
         }
         for (size_t i = 0; i < L.size(); ++i) {
             const int s = L[i].site;
-            const size_t d = (size_t)(s / nx) * h->ld + (s % nx);
+            const size_t d = (size_t)sidx(s % nx, s / nx, h->ld);
             if (bi[d] < 0) bi[d] = (int32_t)i;
         }
         TRY_OR_BAIL(hipMemcpy(h->flags, fl.data(), fl.size(), hipMemcpyHostToDevice));
@@ -930,7 +1084,7 @@ int create_impl(const slbm_params* p, slbm_handle* out)
 int copy_out(slbm_s* h, int comp, double scale, double offset, double* dst)
 {
     // lattice field comp of scratch (after outputs()) -> unpadded host array
-    const double* src = h->scratch + (size_t)(1 + comp) * h->plane;
+    const double* src = h->scratch + (size_t)(1 + comp) * h->plane + sidx(0, 0, h->ld);
     HIP_TRY(hipMemcpy2DAsync(dst, (size_t)h->nx * sizeof(double), src, (size_t)h->ld * sizeof(double),
                              (size_t)h->nx * sizeof(double), h->ny, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1043,7 +1197,7 @@ int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const 
     const double lm = h->lamL - h->muL;
     for (int s = 0; s < n; ++s) {
         if (!h->mask[s]) continue;
-        const size_t d = (size_t)(s / nx) * h->ld + (s % nx);
+        const size_t d = (size_t)sidx(s % nx, s / nx, h->ld);
         const double rL = rho ? rho[s] / h->rho_user : 1.0;
         if (!(rL > 0) || !std::isfinite(rL)) return fail(SLBM_E_INVAL, "density must be positive");
         const double vx = vel ? vel[s] / h->s_v : 0.0, vy = vel ? vel[n + s] / h->s_v : 0.0;
@@ -1092,11 +1246,69 @@ int slbm_time(slbm_handle h, int64_t* step, double* t_user)
     return SLBM_OK;
 }
 
-int slbm_set_launch(slbm_handle h, int32_t seg_rows)
+int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
 {
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
+    if (strip != 0 && strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 0, 62 or 64");
     h->seg = seg_rows;
+    h->wide = strip == 0 ? -1 : (strip == 64 ? 1 : 0);
+    return SLBM_OK;
+}
+
+int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* us_out)
+{
+    if (!h) return fail(SLBM_E_INVAL, "null handle");
+    DeviceGuard dg(h->device);
+    int rc = ensure_scratch(h);
+    if (rc) return rc;
+    // the trial steps write the other population buffer (free) and update U
+    // in place: keep U and the divergence flag aside and restore them after
+    // every trial, so the state is left exactly as it was
+    const size_t ub = (size_t)2 * h->plane * sizeof(double);
+    double* saved = h->scratch;
+    unsigned int* flag_saved = (unsigned int*)(h->scratch + 2 * h->plane);
+    HIP_TRY(hipMemcpyAsync(saved, h->U, ub, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(flag_saved, h->diverged, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+    int best = 0, best_w = 1;
+    double best_us = 1e30;
+    for (int wv = 0; wv < 2; ++wv)
+    for (int c : cand) {
+        if (c > std::max(2, h->ny)) break;
+        // bursts of back-to-back launches, as steps run; each launch rereads
+        // the same state, U is put back after the burst
+        constexpr int kBurst = 6;
+        std::vector<float> t;
+        for (int r = 0; r < 3; ++r) {
+            HIP_TRY(hipEventRecord(e0, h->stream));
+            for (int q = 0; q < kBurst; ++q) {
+                rc = h->precision == SLBM_FP32 ? launch_step_raw<float>(h, c, wv) : launch_step_raw<double>(h, c, wv);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipEventRecord(e1, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) t.push_back(ms / kBurst);
+        }
+        std::sort(t.begin(), t.end());
+        const double us = 1e3 * t[0];
+        if (us < best_us) { best_us = us; best = c; best_w = wv; }
+    }
+    HIP_TRY(hipMemcpyAsync(h->diverged, flag_saved, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->seg = best;
+    h->wide = best_w;
+    if (seg_out) *seg_out = best;
+    if (strip_out) *strip_out = best_w ? 64 : 62;
+    if (us_out) *us_out = best_us;
     return SLBM_OK;
 }
 

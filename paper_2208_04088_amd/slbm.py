@@ -22,7 +22,7 @@ PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
 
 EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
-    "slbm_displacement", "slbm_displacement_device", "slbm_time", "slbm_set_launch",
+    "slbm_displacement", "slbm_displacement_device", "slbm_time", "slbm_set_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_last_error",
 ]
 
@@ -74,7 +74,8 @@ def lib():
         "slbm_displacement": [vp, dp],
         "slbm_displacement_device": [vp, vp],
         "slbm_time": [vp, C.POINTER(i64), C.POINTER(C.c_double)],
-        "slbm_set_launch": [vp, i32],
+        "slbm_set_launch": [vp, i32, i32],
+        "slbm_autotune": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)],
         "slbm_save": [vp, vp, C.POINTER(C.c_size_t)],
         "slbm_load": [vp, vp, C.c_size_t],
         "slbm_device_bytes": [vp, C.POINTER(i64)],
@@ -185,8 +186,17 @@ class Solver:
         _check(lib().slbm_time(self.h, C.byref(st), C.byref(t)))
         return st.value, t.value
 
-    def set_launch(self, seg_rows):
-        _check(lib().slbm_set_launch(self.h, int(seg_rows)))
+    def set_launch(self, seg_rows, strip=0):
+        _check(lib().slbm_set_launch(self.h, int(seg_rows), int(strip)))
+
+    def autotune(self):
+        """Picks the fastest launch shape for this plate; returns
+        (rows per wave, strip width, us per step)."""
+        seg = C.c_int32()
+        strip = C.c_int32()
+        us = C.c_double()
+        _check(lib().slbm_autotune(self.h, C.byref(seg), C.byref(strip), C.byref(us)))
+        return seg.value, strip.value, us.value
 
     def save(self):
         n = C.c_size_t(0)

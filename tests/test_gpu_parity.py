@@ -164,9 +164,9 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
     waves, so any rows-per-wave gives bit-identical state."""
     p = mixed_plate(150, 97, seed=5, order=1)
     out = []
-    for seg in (1, 3, 8, 64, 200):
+    for seg, strip in ((1, 62), (3, 64), (8, 62), (64, 64), (200, 62), (2, 64)):
         s = slbm.Solver(p, prec)
-        s.set_launch(seg)
+        s.set_launch(seg, strip)
         s.step(37)
         out.append((s.displacement(), s.moments()[2]))
     for u, P in out[1:]:
@@ -235,12 +235,14 @@ def test_divergence_is_reported(slbm):
 def test_displacement_to_device_memory(slbm):
     import torch
     p = mixed_plate(70, 40, seed=13)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
+    assert stream.cuda_stream != 0
     s = slbm.Solver(p, "fp32", stream=stream.cuda_stream)
     s.step(30)
-    t = torch.empty((2, p.ny, p.nx), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        t = torch.empty((2, p.ny, p.nx), dtype=torch.float64, device="cuda")
     s.displacement_device(t.data_ptr())
-    torch.cuda.synchronize()
+    stream.synchronize()
     assert np.array_equal(t.cpu().numpy(), s.displacement())
 
 
@@ -328,3 +330,20 @@ def test_crack_tip_sif_fp32_follows_freund_k0(slbm):
     assert abs(ratio - 1) < 0.05
     assert 0 <= lag <= 40
     assert abs(ratio - r_ref) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_leaves_the_state_untouched(slbm, prec):
+    """slbm_autotune times trial steps on the live plate; the state, the step
+    count and the results must be exactly as without it."""
+    p = mixed_plate(200, 90, seed=17, order=1)
+    a = slbm.Solver(p, prec)
+    a.step(25)
+    seg, strip, us = a.autotune()
+    assert seg >= 2 and strip in (62, 64) and us > 0
+    assert a.time()[0] == 25
+    a.step(25)
+    b = slbm.Solver(p, prec)
+    b.step(50)
+    assert np.array_equal(a.displacement(), b.displacement())
+    assert np.array_equal(a.moments()[2], b.moments()[2])
