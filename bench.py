@@ -47,6 +47,32 @@ def bytes_per_site(prec):
     return 9 * 2 * (4 if prec == "fp32" else 8) + 2 * 2 * 8
 
 
+def kernel_fingerprint():
+    """SHA-256 of the step kernel's source and the build flags: counter
+    readings are only valid for the kernel they were taken on."""
+    import hashlib
+    from paper_2208_04088_amd import build
+    h = hashlib.sha256()
+    h.update(open(os.path.join(os.path.dirname(build.__file__), "csrc", "step_kernel.h"), "rb").read())
+    h.update(" ".join(build.HIPCC_FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(plate, prec, tuned):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary (profiles/traffic_<workload>.json), or None when there is none
+    for this workload and launch shape or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{plate.name}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_fingerprint") != kernel_fingerprint():
+        return None
+    if [d.get("rows_per_wave"), d.get("strip_width")] != [tuned[0], tuned[1]]:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(plate, budget_s=12.0):
     """The plain CPU reference (fp64) on a bounded number of steps of the
     same plate, all host threads it is allowed."""
@@ -180,6 +206,21 @@ def main():
             "strip_width": tuned[1],
         },
     }
+    # streaming reference: a plain copy of a 2 GiB buffer, timed the same way
+    src_t = torch.empty(1 << 29, dtype=torch.float32, device=dev)
+    dst_t = torch.empty_like(src_t)
+    nbytes = src_t.numel() * 4
+    for _ in range(3):
+        slbm.copy(dst_t.data_ptr(), src_t.data_ptr(), nbytes, 0, stream.cuda_stream)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        slbm.copy(dst_t.data_ptr(), src_t.data_ptr(), nbytes, 0, stream.cuda_stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    result["roofline"]["copy_kernel_gbs"] = round(2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
+    del src_t, dst_t
+    result["roofline"]["traffic"] = measured_traffic(plate, prec, tuned)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(plate)
     print(json.dumps(result), flush=True)

@@ -176,6 +176,12 @@ int slbm_device_bytes(slbm_handle h, int64_t* bytes);
 
 int slbm_destroy(slbm_handle h);
 
+/* Plain device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned
+ * pointers) queued on `stream` (NULL: the null stream) of `device`.  The
+ * streaming reference the fused step's bandwidth is quoted against; not part
+ * of the method. */
+int slbm_copy(void* dst, const void* src, size_t bytes, int32_t device, void* stream);
+
 const char* slbm_last_error(void);
 
 #ifdef __cplusplus

@@ -76,452 +76,13 @@ int fail(int code, const char* fmt, ...)
             return fail(SLBM_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// ----------------------------------------------------------------- lattice
+}  // namespace
 
-// D2Q9 velocities, paper section 3 (numbering as in include/slbm.h).
-__host__ __device__ constexpr int CX(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0); }
-__host__ __device__ constexpr int CY(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
-__host__ __device__ constexpr int OPP(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5); }
-__host__ __device__ constexpr double WD(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+#include "step_kernel.h"
 
-constexpr int kPadL = 64;      // padding columns left of the grid: keeps wide strips 256-byte aligned
+namespace {
 
-// Two strip shapes for the fused step (the autotuner picks per plate):
-//   wide   64 output columns per wave, 256-byte aligned; the two density-halo
-//          sites are fetched by the half-waves;
-//   narrow 62 output columns per wave (lanes 1..62); lanes 0 and 63 sit on
-//          the halo columns and only supply density.  Fewer registers, more
-//          waves in flight, unaligned rows: faster on small plates.
-template <bool WIDE> constexpr int strip_width() { return WIDE ? 64 : 62; }
-constexpr unsigned kVoid = 0xFFu;
-
-struct GroupDev {
-    int32_t profile;           // SLBM_PROFILE_*
-    int32_t pad;
-    double ramp_steps;         // ramp length in steps
-};
-
-// Coefficients of the boundary rule of one cut link (x, k); see build_links.
-template <typename real>
-struct LinkDev {
-    real kappa;                // (l - 2s)/(l + 2s), 0 with no site behind x
-    real wx, wy;               // weights of rho and sigma_tt at x and x - c_k
-    real D;                    // Dirichlet: -beta (2/c_s^2) w_k c_k.v
-    real be[4];                // Neumann: beta d(E_k - 2 r_k)/d(drho_bd, Pxx*, Pyy*, Pxy*)
-    real K1[3], K2[3], E3[3];  // Neumann: known boundary stress per unit profile; e_t e_t
-    int32_t g1, g2;            // groups whose profiles scale D or K1, K2
-    int32_t kind;              // SLBM_DIRICHLET | SLBM_NEUMANN
-    int32_t behind;            // 1: x - c_k is a material site reached by an uncut link
-    int32_t k, dx, dy, pad;
-};
-
-template <typename real>
-struct StepArgs {
-    const real* src;
-    real* dst;
-    double* U;
-    const uint8_t* flags;
-    const int32_t* bidx;
-    const LinkDev<real>* links;
-    const GroupDev* groups;
-    unsigned int* diverged;
-    long long plane;           // ny * ld
-    long long t_prev;          // step whose post-collision state src holds
-    int nx, ny, ld;
-    int seg, nstrips, ntiles;
-    int px, py;
-    int local;                 // src holds the populations themselves
-    real omega, cpsi;          // 1/tau, 1 - 1/(2 tau)
-    real lm, ml;               // lambda - mu, mu - lambda (lattice units)
-    real Fx, Fy;
-};
-
-template <typename real>
-__device__ __forceinline__ real profile_at(const GroupDev* g, int gi, long long t)
-{
-    const GroupDev G = g[gi];
-    if (G.profile == SLBM_PROFILE_RAMP) {
-        real r = real((double)t / G.ramp_steps);
-        return r < real(1) ? r : real(1);
-    }
-    return real(1);
-}
-
-// Shifted equilibrium g_eq,i = f_eq,i - r_i of eq:fieq, drho = rho - 1:
-// w_i [drho (2 - 3|c|^2/2) + 3 c.j + 9/2 (Pxx (cx^2 - 1/3) + Pyy (cy^2 - 1/3) + 2 Pxy cx cy)]
-template <int i, typename real>
-__device__ __forceinline__ real geq(real dr, real jx, real jy, real pxx, real pyy, real pxy)
-{
-    constexpr int cx = CX(i), cy = CY(i);
-    constexpr double w = WD(i);
-    constexpr double a0 = w * (2.0 - 1.5 * (cx * cx + cy * cy));
-    constexpr double ax = 3.0 * w * cx, ay = 3.0 * w * cy;
-    constexpr double axx = 4.5 * w * (cx * cx - 1.0 / 3.0);
-    constexpr double ayy = 4.5 * w * (cy * cy - 1.0 / 3.0);
-    constexpr double axy = 9.0 * w * cx * cy;
-    real v = real(a0) * dr;
-    if (cx != 0) v += real(ax) * jx;
-    if (cy != 0) v += real(ay) * jy;
-    v += real(axx) * pxx + real(ayy) * pyy;
-    if (cx * cy != 0) v += real(axy) * pxy;
-    return v;
-}
-
-template <typename real>
-__device__ __forceinline__ void moments9(const real g[9], real& dr, real& jx, real& jy,
-                                         real& pxx, real& pyy, real& pxy)
-{
-    // eq:moments on shifted populations (the rest state has rho = 1, j = 0, P = 0)
-    const real d57 = g[5] + g[7], d68 = g[6] + g[8];
-    dr = g[0] + g[1] + g[2] + g[3] + g[4] + d57 + d68;
-    jx = g[1] - g[3] + g[5] - g[6] - g[7] + g[8];
-    jy = g[2] - g[4] + g[5] + g[6] - g[7] - g[8];
-    pxx = g[1] + g[3] + d57 + d68;
-    pyy = g[2] + g[4] + d57 + d68;
-    pxy = d57 - d68;
-}
-
-// Offset of site (x, y) in a padded plane.
-__host__ __device__ __forceinline__ int sidx(int x, int y, int ld) { return (y + 1) * ld + (x + kPadL); }
-
-// Offset of the site at (x + dx, y + dy), wrapped on periodic axes.
-template <bool PER>
-__device__ __forceinline__ int wrap_off(int x, int y, int dx, int dy, int nx, int ny, int ld, int px, int py)
-{
-    int xx = x + dx, yy = y + dy;
-    if (PER) {
-        if (px) xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-        if (py) yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
-    }
-    return sidx(xx, yy, ld);
-}
-
-// Moments of the post-collision populations stored at site offset s.
-template <typename real>
-__device__ __forceinline__ void stored_moments(const StepArgs<real>& a, int s, real& dr,
-                                               real& pxx, real& pyy, real& pxy)
-{
-    real h[9];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) h[j] = a.src[j * a.plane + s];
-    real jx, jy;
-    moments9(h, dr, jx, jy, pxx, pyy, pxy);
-}
-
-// The boundary rule of section 4 for the cut link (x, k): the population
-// arriving at x in direction kbar at the current step, from the post-collision
-// state of the previous step (time t_prev).
-template <typename real, bool PER>
-__device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, int x, int y, int s,
-                               real drx, real pxxx, real pyyx, real pxyx)
-{
-    const int k = L.k, kb = OPP(k);
-    const real gk = a.src[k * a.plane + s];
-    const real gkb = a.src[kb * a.plane + s];
-    int sb = 0;
-    real gky = real(0);
-    if (L.behind) {
-        sb = wrap_off<PER>(x, y, -L.dx, -L.dy, a.nx, a.ny, a.ld, a.px, a.py);
-        gky = a.src[k * a.plane + sb];
-    }
-    if (L.kind == SLBM_DIRICHLET) {
-        // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
-        const real p = profile_at<real>(a.groups, L.g1, a.t_prev);
-        return gk + L.kappa * (gky - gkb) + L.D * (real(1) + drx) * p;
-    }
-    // eq:abbcon / eq:abbnoncon.  Cauchy stress from the Poisson stress with the
-    // divergence approximation (eq:poissonstress, eq:approxdiv):
-    // sigma = -P - (lambda - mu) drho I.
-    real drbd = L.wx * drx;
-    real stt = L.wx * (L.E3[0] * (-pxxx - a.lm * drx) + L.E3[1] * (-pyyx - a.lm * drx)
-                       - real(2) * L.E3[2] * pxyx);
-    if (L.wy != real(0)) {
-        real dry, pxxy, pyyy, pxyy;
-        stored_moments(a, sb, dry, pxxy, pyyy, pxyy);
-        drbd += L.wy * dry;
-        stt += L.wy * (L.E3[0] * (-pxxy - a.lm * dry) + L.E3[1] * (-pyyy - a.lm * dry)
-                       - real(2) * L.E3[2] * pxyy);
-    }
-    const real p1 = profile_at<real>(a.groups, L.g1, a.t_prev);
-    const real p2 = L.g2 >= 0 ? profile_at<real>(a.groups, L.g2, a.t_prev) : real(0);
-    // boundary Cauchy stress (eq:trafocauchy) and Poisson stress (eq:bcchainneum)
-    const real sxx = p1 * L.K1[0] + p2 * L.K2[0] + stt * L.E3[0];
-    const real syy = p1 * L.K1[1] + p2 * L.K2[1] + stt * L.E3[1];
-    const real sxy = p1 * L.K1[2] + p2 * L.K2[2] + stt * L.E3[2];
-    const real Pxx = -sxx - a.lm * drbd;
-    const real Pyy = -syy - a.lm * drbd;
-    const real Pxy = -sxy;
-    return -gk - L.kappa * (gky + gkb) + L.be[0] * drbd + L.be[1] * Pxx + L.be[2] * Pyy + L.be[3] * Pxy;
-}
-
-// Replaces the populations of cut links of a boundary site by the section 4
-// rules.  g already holds the pulls along uncut links.
-template <typename real, bool PER>
-__device__ void boundary_fixup(const StepArgs<real>& a, int x, int y, int s, unsigned fl, real g[9])
-{
-    real drx, pxxx, pyyx, pxyx;
-    stored_moments(a, s, drx, pxxx, pyyx, pxyx);
-    int li = a.bidx[s];
-    unsigned m = fl;
-    while (m) {
-        const int k = __builtin_ctz(m) + 1;
-        m &= m - 1;
-        const LinkDev<real> L = a.links[li++];
-        const real v = boundary_value<real, PER>(a, L, x, y, s, drx, pxxx, pyyx, pxyx);
-        const int i = OPP(k);
-#pragma unroll
-        for (int j = 1; j < 9; ++j)
-            if (j == i) g[j] = v;
-    }
-}
-
-// Populations at site (x, y) for the current step (x, y in the grid, wrapped
-// by the caller on periodic axes).  Returns false for sites without state.
-template <typename real, bool PER>
-__device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y, real g[9], unsigned& flo)
-{
-    const int s = sidx(x, y, a.ld);
-    const unsigned fl = a.flags[s];
-    flo = fl;
-    if (fl == kVoid) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = real(0);
-        return false;
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        g[i] = a.local ? a.src[i * a.plane + s]
-                       : a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
-    if (!a.local && fl != 0) boundary_fixup<real, PER>(a, x, y, s, fl, g);
-    return true;
-}
-
-// One row of the sliding window: loads in flight, then completed.  Besides
-// its own site, every lane fetches one density-halo site of its wave's strip:
-// lanes 0-31 the site left of the strip, lanes 32-63 the one right of it
-// (lane 0 and lane 63 use them).
-template <typename real, bool WIDE>
-struct Row {
-    real g[9];                 // own site
-    real h[WIDE ? 9 : 1];      // halo site (wide strips)
-    double ux, uy;
-    unsigned fl, flh;
-    int y, yh;
-    bool in, inh;
-};
-
-// Loads of one site, unconditional: a site outside the grid loads from a
-// clamped in-grid site and is masked when completed (a conditional load
-// would make the compiler wait for earlier loads before initialising its
-// target registers).  The padding ring keeps the pull addresses of any
-// in-grid site inside the allocation.
-template <typename real, bool PER>
-__device__ __forceinline__ void site_issue(const StepArgs<real>& a, int x, int y, real g[9], unsigned& fl,
-                                           int& ys, bool& in, int& s_out)
-{
-    in = true;
-    if (x < 0 || x >= a.nx) {
-        if (PER && a.px) x = x < 0 ? x + a.nx : x - a.nx;
-        if (x < 0 || x >= a.nx) {
-            in = false;
-            x = x < 0 ? 0 : a.nx - 1;
-        }
-    }
-    if (y < 0 || y >= a.ny) {
-        if (PER && a.py) {
-            y = y < 0 ? y + a.ny : y - a.ny;
-        } else {
-            in = false;
-            y = y < 0 ? 0 : a.ny - 1;
-        }
-    }
-    ys = y;
-    const int s = sidx(x, y, a.ld);
-    s_out = s;
-    fl = a.flags[s];
-    if (a.local) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = a.src[i * a.plane + s];
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            g[i] = a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
-    }
-}
-
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ void row_issue(const StepArgs<real>& a, int x, int xh, int y, Row<real, WIDE>& r)
-{
-    int s, sh;
-    site_issue<real, PER>(a, x, y, r.g, r.fl, r.y, r.in, s);
-    if constexpr (WIDE) site_issue<real, PER>(a, xh, y, r.h, r.flh, r.yh, r.inh, sh);
-    r.ux = a.U[s];
-    r.uy = a.U[a.plane + s];
-}
-
-// Completes one site: boundary rules on cut links, nothing for void sites.
-// Returns delta-rho (0 without state).
-template <typename real, bool PER>
-__device__ __forceinline__ real site_finish(const StepArgs<real>& a, int x, int y, bool in, bool want,
-                                            unsigned& fl, real g[9])
-{
-    if (!in) fl = kVoid;
-    const bool live = fl != kVoid;
-    if (want && live && !a.local && fl != 0) {
-        int xx = x;
-        if (PER && a.px) xx = xx < 0 ? xx + a.nx : (xx >= a.nx ? xx - a.nx : xx);
-        boundary_fixup<real, PER>(a, xx, y, sidx(xx, y, a.ld), fl, g);
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = live ? g[i] : real(0);
-    return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
-}
-
-// Density window of the gradient stencil: delta-rho of rows y-1, y at this
-// lane and its two neighbours.
-template <typename real>
-struct Window {
-    real m, m_l, m_r;
-    real c, c_l, c_r;
-};
-
-// Collision, source term and displacement update of one site (row B), given
-// the density window and the next row's densities.
-template <typename real, bool WIDE>
-__device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const Row<real, WIDE>& B,
-                                             const Window<real>& w, real rp, real rp_l, real rp_r)
-{
-    const unsigned fl = B.fl;
-    const real* g = B.g;
-    real dr, jx, jy, pxx, pyy, pxy;
-    moments9(g, dr, jx, jy, pxx, pyy, pxy);
-    // eq:sourceterm: isotropic D2Q9 gradient of rho; across a cut link the
-    // neighbour is extrapolated from the opposite side
-    real nb[9];
-    nb[1] = w.c_r; nb[2] = rp; nb[3] = w.c_l; nb[4] = w.m;
-    nb[5] = rp_r; nb[6] = rp_l; nb[7] = w.m_l; nb[8] = w.m_r;
-    real rt[9];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const bool ci = (fl >> (i - 1)) & 1u;
-        const bool co = (fl >> (OPP(i) - 1)) & 1u;
-        rt[i] = ci ? (co ? dr : real(2) * dr - nb[OPP(i)]) : nb[i];
-    }
-    const real gx = real(1.0 / 3.0) * (rt[1] - rt[3]) + real(1.0 / 12.0) * (rt[5] - rt[6] - rt[7] + rt[8]);
-    const real gy = real(1.0 / 3.0) * (rt[2] - rt[4]) + real(1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
-    const real rho = real(1) + dr;
-    const real c = a.ml / rho;
-    const real Sx = a.Fx + c * gx, Sy = a.Fy + c * gy;
-    jx += real(0.5) * Sx;
-    jy += real(0.5) * Sy;
-    // eq:coll with eq:fieq and psi_i = w_i c_i.S / c_s^2
-    real e[9];
-    e[0] = geq<0>(dr, jx, jy, pxx, pyy, pxy);
-    e[1] = geq<1>(dr, jx, jy, pxx, pyy, pxy);
-    e[2] = geq<2>(dr, jx, jy, pxx, pyy, pxy);
-    e[3] = geq<3>(dr, jx, jy, pxx, pyy, pxy);
-    e[4] = geq<4>(dr, jx, jy, pxx, pyy, pxy);
-    e[5] = geq<5>(dr, jx, jy, pxx, pyy, pxy);
-    e[6] = geq<6>(dr, jx, jy, pxx, pyy, pxy);
-    e[7] = geq<7>(dr, jx, jy, pxx, pyy, pxy);
-    e[8] = geq<8>(dr, jx, jy, pxx, pyy, pxy);
-    const real px1 = a.cpsi * real(1.0 / 3.0) * Sx, py1 = a.cpsi * real(1.0 / 3.0) * Sy;
-    const real pd = a.cpsi * real(1.0 / 12.0);
-    real psi[9];
-    psi[0] = real(0);
-    psi[1] = px1; psi[3] = -px1; psi[2] = py1; psi[4] = -py1;
-    psi[5] = pd * (Sx + Sy); psi[7] = -psi[5];
-    psi[6] = pd * (Sy - Sx); psi[8] = -psi[6];
-    const int s = sidx(x, y, a.ld);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        a.dst[i * a.plane + s] = g[i] + a.omega * (e[i] - g[i]) + psi[i];
-    // displacement: U += j/rho (fp64 accumulation)
-    const double ir = 1.0 / (double)rho;
-    a.U[s] = B.ux + (double)jx * ir;
-    a.U[a.plane + s] = B.uy + (double)jy * ir;
-    return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
-}
-
-// Densities of a completed row as seen by this lane: own site, and the sites
-// left and right of it (from the neighbouring lanes, or the halo site at the
-// ends of the strip).
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ void row_density(const StepArgs<real>& a, int lane, int x, int xh, Row<real, WIDE>& r,
-                                            real& d, real& d_l, real& d_r)
-{
-    d = site_finish<real, PER>(a, x, r.y, r.in, true, r.fl, r.g);
-    const real up = __shfl_up(d, 1), dn = __shfl_down(d, 1);
-    if constexpr (WIDE) {
-        const real dh = site_finish<real, PER>(a, xh, r.yh, r.inh, lane == 0 || lane == 63, r.flh, r.h);
-        d_l = lane == 0 ? dh : up;
-        d_r = lane == 63 ? dh : dn;
-    } else {
-        d_l = up;
-        d_r = dn;
-    }
-}
-
-// One row of the march: issue row y+2 into D, complete row y+1 (C), compute
-// row y (B).  Called with the three rows in rotating roles so that no row's
-// registers are ever copied while its loads are in flight.
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ bool march_row(const StepArgs<real>& a, int lane, int x, int xh, bool out, int y,
-                                          Row<real, WIDE>& B, Row<real, WIDE>& C, Row<real, WIDE>& D,
-                                          Window<real>& w)
-{
-    row_issue<real, PER, WIDE>(a, x, xh, y + 2, D);
-    real rp, rp_l, rp_r;
-    row_density<real, PER, WIDE>(a, lane, x, xh, C, rp, rp_l, rp_r);
-    bool bad = false;
-    if (out && B.fl != kVoid) bad = collide_site<real, WIDE>(a, x, y, B, w, rp, rp_l, rp_r);
-    w.m = w.c; w.m_l = w.c_l; w.m_r = w.c_r;
-    w.c = rp; w.c_l = rp_l; w.c_r = rp_r;
-    return bad;
-}
-
-// One time step of the whole lattice (section 3 and section 4).  One wave per
-// workgroup; a wave owns a strip of columns (wide or narrow, see
-// strip_width) and marches up `seg` rows with a three-row density window in
-// registers.  The loads of row y+2 are issued before row y is computed, so a
-// row's memory latency overlaps the previous row's arithmetic.
-template <typename real, bool PER, bool WIDE>
-__global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
-{
-    const int lane = threadIdx.x;
-    const int B = gridDim.x;                  // a multiple of 8
-    const int b = blockIdx.x;
-    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous band of tiles so that shared halo rows and columns stay in
-    // one L2
-    const int tile = (b & 7) * (B >> 3) + (b >> 3);
-    if (tile >= a.ntiles) return;
-    const int strip = tile % a.nstrips;
-    const int segm = tile / a.nstrips;
-    constexpr int W = strip_width<WIDE>();
-    const int x = WIDE ? strip * W + lane : strip * W - 1 + lane;
-    const int xh = lane < 32 ? strip * W - 1 : strip * W + W;
-    const bool out = x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
-    const int y0 = segm * a.seg;
-    const int y1 = min(y0 + a.seg, a.ny);
-
-    Row<real, WIDE> R0, R1, R2;
-    Window<real> w;
-    row_issue<real, PER, WIDE>(a, x, xh, y0 - 1, R2);
-    row_issue<real, PER, WIDE>(a, x, xh, y0, R0);
-    row_issue<real, PER, WIDE>(a, x, xh, y0 + 1, R1);
-    row_density<real, PER, WIDE>(a, lane, x, xh, R2, w.m, w.m_l, w.m_r);
-    row_density<real, PER, WIDE>(a, lane, x, xh, R0, w.c, w.c_l, w.c_r);
-    bool bad = false;
-    for (int y = y0; y < y1; y += 3) {
-        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y, R0, R1, R2, w);
-        if (y + 1 >= y1) break;
-        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y + 1, R1, R2, R0, w);
-        if (y + 2 >= y1) break;
-        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y + 2, R2, R0, R1, w);
-    }
-    if (bad) atomicOr(a.diverged, 1u);
-}
+using namespace slbm_dev;
 
 // ------------------------------------------------------ output kernels
 
@@ -653,6 +214,15 @@ __global__ __launch_bounds__(256) void k_init(StepArgs<real> a, const double* dr
     for (int i = 0; i < 9; ++i) g_out[i * P + idx] = (real)gi[i];
     a.U[idx] = ux;
     a.U[P + idx] = uy;
+}
+
+// Plain streaming copy (one 16-byte access per thread): the bandwidth
+// reference the step is compared with, and the known-size kernel that
+// calibrates the memory counters.
+__global__ __launch_bounds__(256) void k_copy16(const float4* __restrict__ src, float4* __restrict__ dst, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 }  // namespace
@@ -1372,6 +942,22 @@ int slbm_load(slbm_handle h, const void* buf, size_t bytes)
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->step = hd.step;
     h->local = hd.local != 0;
+    return SLBM_OK;
+}
+
+int slbm_copy(void* dst, const void* src, size_t bytes, int32_t device, void* stream)
+{
+    if (!dst || !src) return fail(SLBM_E_INVAL, "null pointer");
+    if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
+        return fail(SLBM_E_INVAL, "bytes and both pointers must be multiples of 16");
+    DeviceGuard dg(device);
+    const long long n = (long long)(bytes / 16);
+    if (n > (1LL << 31) * 256) return fail(SLBM_E_UNSUPPORTED, "copy larger than 2^39 x 16 bytes");
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (n > 0)
+        hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                           (const float4*)src, (float4*)dst, n);
+    HIP_TRY(hipGetLastError());
     return SLBM_OK;
 }
 

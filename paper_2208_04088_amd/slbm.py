@@ -23,7 +23,7 @@ PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
 EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
     "slbm_displacement", "slbm_displacement_device", "slbm_time", "slbm_set_launch", "slbm_autotune",
-    "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_last_error",
+    "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
 ]
 
 LINK_DTYPE = np.dtype([("site", "<i4"), ("dir", "<i4"), ("q", "<f8"), ("group", "<i4"),
@@ -80,6 +80,7 @@ def lib():
         "slbm_load": [vp, vp, C.c_size_t],
         "slbm_device_bytes": [vp, C.POINTER(i64)],
         "slbm_destroy": [vp],
+        "slbm_copy": [vp, vp, C.c_size_t, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -119,6 +120,12 @@ def marshal(plate, precision=FP32, device=0, stream=None):
                  n_groups=len(plate.groups), groups=groups.ctypes.data,
                  device=int(device), stream=stream)
     return prm, (mask, links, groups)
+
+
+def copy(dst_ptr, src_ptr, nbytes, device=0, stream=None):
+    """slbm_copy: plain device copy (the streaming reference)."""
+    _check(lib().slbm_copy(C.c_void_p(int(dst_ptr)), C.c_void_p(int(src_ptr)), int(nbytes), int(device),
+                           None if stream is None else C.c_void_p(int(stream))))
 
 
 class Solver:
