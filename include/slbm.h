@@ -176,6 +176,49 @@ int slbm_device_bytes(slbm_handle h, int64_t* bytes);
 
 int slbm_destroy(slbm_handle h);
 
+/* ---------------------------------------------------------------- batches
+ *
+ * Many plates of uneven size and geometry advanced together: every step of
+ * every active plate is one kernel launch, steps are queued as replays of a
+ * captured HIP graph, and each plate keeps its own step count.  Plates join
+ * and leave between calls (continuous batching).  Every plate of a batch has
+ * the batch's precision and no periodic axis.  A plate's results are those
+ * it would have alone (the arithmetic of each site does not depend on the
+ * batch).  Not thread-safe.
+ */
+typedef struct slbm_batch_s* slbm_batch;
+
+/* hbm_budget_bytes bounds the device memory of the batch's plates; stream
+ * as in slbm_params (NULL: the batch's own). */
+int slbm_batch_create(int64_t hbm_budget_bytes, int32_t device, void* stream, slbm_batch* out);
+
+/* Creates the plate (as slbm_create, on the batch's device and stream) with
+ * nsteps steps to take, and returns its slot.  SLBM_E_BUDGET when it would
+ * exceed the budget (nothing is allocated then). */
+int slbm_batch_add(slbm_batch b, const slbm_params* params, int64_t nsteps, int32_t* slot);
+
+/* Queues k steps: every plate advances by min(k, its remaining steps). */
+int slbm_batch_step(slbm_batch b, int64_t k);
+
+/* Slots whose steps are all taken (up to capacity written; *n_done = all). */
+int slbm_batch_poll(slbm_batch b, int32_t* done_slots, int32_t capacity, int32_t* n_done);
+
+/* The plate's handle, owned by the batch, for slbm_displacement,
+ * slbm_moments, slbm_sync and slbm_time; valid until the plate is removed. */
+int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h);
+int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps);
+
+/* Frees the plate (its slot and budget are reused). */
+int slbm_batch_remove(slbm_batch b, int32_t slot);
+
+/* Launch shape of the batched step: rows each wave marches and strip width
+ * (62 or 64), for every plate. */
+int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
+
+int slbm_batch_sync(slbm_batch b);
+int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget);
+int slbm_batch_destroy(slbm_batch b);
+
 /* Plain device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned
  * pointers) queued on `stream` (NULL: the null stream) of `device`.  The
  * streaming reference the fused step's bandwidth is quoted against; not part

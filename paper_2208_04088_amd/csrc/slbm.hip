@@ -134,7 +134,7 @@ __device__ void grad_rho(const double* dr, const uint8_t* flags, int x, int y, i
 // Lattice-unit moments and displacement, padded planes out[11] =
 // rho, jx, jy, Pxx, Pyy, Pxy, sxx, syy, sxy, ux, uy.
 template <typename real, bool PER>
-__global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double* dr, double* out)
+__global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double* dr, double* out, int ncomp)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const long long P = a.plane;
@@ -162,7 +162,12 @@ __global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double*
         o[9] = a.U[idx] + 0.5 * jx / rho;
         o[10] = a.U[P + idx] + 0.5 * jy / rho;
     }
-    for (int c = 0; c < 11; ++c) out[c * P + idx] = o[c];
+    if (ncomp == 11) {
+        for (int c = 0; c < 11; ++c) out[c * P + idx] = o[c];
+    } else {
+        out[idx] = o[9];
+        out[P + idx] = o[10];
+    }
 }
 
 // Displacement into a caller's unpadded [2][ny][nx] device array.
@@ -172,8 +177,8 @@ __global__ __launch_bounds__(256) void k_unpad_u(const double* out, int nx, int 
     if (idx >= nx * ny) return;
     const int y = idx / nx, x = idx - y * nx;
     const long long P = (long long)(ny + 2) * ld;
-    u[idx] = out[9 * P + sidx(x, y, ld)];
-    u[(long long)nx * ny + idx] = out[10 * P + sidx(x, y, ld)];
+    u[idx] = out[sidx(x, y, ld)];
+    u[(long long)nx * ny + idx] = out[P + sidx(x, y, ld)];
 }
 
 // ------------------------------------------------------- initial state
@@ -249,6 +254,8 @@ struct slbm_s {
     GroupDev* groups = nullptr;
     unsigned int* diverged = nullptr;
     double* scratch = nullptr;       // outputs and initial fields, allocated on demand
+    int scratch_planes = 0;
+    bool transient_scratch = false;  // free it after every readout (batch plates)
     int n_links = 0;
     int64_t step = 0;
     bool local = true;
@@ -353,38 +360,55 @@ int launch_step(slbm_s* h)
     return SLBM_OK;
 }
 
-int ensure_scratch(slbm_s* h)
+int ensure_scratch(slbm_s* h, int planes)
 {
-    if (h->scratch) return SLBM_OK;
-    HIP_TRY(hipMalloc((void**)&h->scratch, (size_t)12 * h->plane * sizeof(double)));
+    if (h->scratch && h->scratch_planes >= planes) return SLBM_OK;
+    if (h->scratch) (void)hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_planes = 0;
+    HIP_TRY(hipMalloc((void**)&h->scratch, (size_t)planes * h->plane * sizeof(double)));
+    h->scratch_planes = planes;
     return SLBM_OK;
+}
+
+// Plates owned by a batch give their readout scratch back after each use.
+void release_transient_scratch(slbm_s* h)
+{
+    if (!h->transient_scratch || !h->scratch) return;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_planes = 0;
 }
 
 // outputs in lattice units into scratch[1..11]; scratch[0] holds delta-rho
 template <typename real>
-int launch_outputs(slbm_s* h)
+int launch_outputs(slbm_s* h, bool full)
 {
-    int rc = ensure_scratch(h);
+    int rc = ensure_scratch(h, full ? 12 : 3);
     if (rc) return rc;
     StepArgs<real> a = make_args<real>(h, h->cur);
     const int n = (int)h->plane;
     const int grid = (n + 255) / 256;
     double* dr = h->scratch;
     double* out = h->scratch + h->plane;
+    const int ncomp = full ? 11 : 2;
     if (h->px || h->py) {
         hipLaunchKernelGGL((k_density<real, true>), dim3(grid), dim3(256), 0, h->stream, a, dr);
-        hipLaunchKernelGGL((k_outputs<real, true>), dim3(grid), dim3(256), 0, h->stream, a, dr, out);
+        hipLaunchKernelGGL((k_outputs<real, true>), dim3(grid), dim3(256), 0, h->stream, a, dr, out, ncomp);
     } else {
         hipLaunchKernelGGL((k_density<real, false>), dim3(grid), dim3(256), 0, h->stream, a, dr);
-        hipLaunchKernelGGL((k_outputs<real, false>), dim3(grid), dim3(256), 0, h->stream, a, dr, out);
+        hipLaunchKernelGGL((k_outputs<real, false>), dim3(grid), dim3(256), 0, h->stream, a, dr, out, ncomp);
     }
     HIP_TRY(hipGetLastError());
     return SLBM_OK;
 }
 
-int outputs(slbm_s* h)
+// Readout kernels: full = all moments (11 planes), else the displacement only
+// (2 planes, components 9 and 10 of the full set come first).
+int outputs(slbm_s* h, bool full)
 {
-    return h->precision == SLBM_FP32 ? launch_outputs<float>(h) : launch_outputs<double>(h);
+    return h->precision == SLBM_FP32 ? launch_outputs<float>(h, full) : launch_outputs<double>(h, full);
 }
 
 struct DeviceGuard {
@@ -715,7 +739,7 @@ int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma
 {
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     DeviceGuard dg(h->device);
-    int rc = outputs(h);
+    int rc = outputs(h, true);
     if (rc) return rc;
     const size_t n = (size_t)h->nx * h->ny;
     const double sj = h->rho_user * h->s_v;
@@ -727,6 +751,7 @@ int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma
     if (sigma && ((rc = copy_out(h, 6, h->s_sigma, 0.0, sigma)) || (rc = copy_out(h, 7, h->s_sigma, 0.0, sigma + n)) ||
                   (rc = copy_out(h, 8, h->s_sigma, 0.0, sigma + 2 * n))))
         return rc;
+    release_transient_scratch(h);
     return SLBM_OK;
 }
 
@@ -734,10 +759,11 @@ int slbm_displacement(slbm_handle h, double* u)
 {
     if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
     DeviceGuard dg(h->device);
-    int rc = outputs(h);
+    int rc = outputs(h, false);
     if (rc) return rc;
     const size_t n = (size_t)h->nx * h->ny;
-    if ((rc = copy_out(h, 9, 1.0, 0.0, u)) || (rc = copy_out(h, 10, 1.0, 0.0, u + n))) return rc;
+    if ((rc = copy_out(h, 0, 1.0, 0.0, u)) || (rc = copy_out(h, 1, 1.0, 0.0, u + n))) return rc;
+    release_transient_scratch(h);
     return SLBM_OK;
 }
 
@@ -745,12 +771,13 @@ int slbm_displacement_device(slbm_handle h, void* u_dev)
 {
     if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
     DeviceGuard dg(h->device);
-    int rc = outputs(h);
+    int rc = outputs(h, false);
     if (rc) return rc;
     const int n = h->nx * h->ny;
     hipLaunchKernelGGL(k_unpad_u, dim3((n + 255) / 256), dim3(256), 0, h->stream,
                        (const double*)(h->scratch + h->plane), h->nx, h->ny, h->ld, (double*)u_dev);
     HIP_TRY(hipGetLastError());
+    release_transient_scratch(h);
     return SLBM_OK;
 }
 
@@ -758,7 +785,7 @@ int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const 
 {
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     DeviceGuard dg(h->device);
-    int rc = ensure_scratch(h);
+    int rc = ensure_scratch(h, 8);
     if (rc) return rc;
     const int nx = h->nx, ny = h->ny, n = nx * ny;
     const size_t P = (size_t)h->plane;
@@ -783,7 +810,7 @@ int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const 
         f[6 * P + d] = u ? u[s] : 0.0;
         f[7 * P + d] = u ? u[n + s] : 0.0;
     }
-    double* dev = h->scratch;   // 12 planes: fields use 8
+    double* dev = h->scratch;   // 8 planes
     HIP_TRY(hipMemcpyAsync(dev, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     h->cur = 0;
     h->local = true;
@@ -805,6 +832,7 @@ int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const 
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    release_transient_scratch(h);
     return SLBM_OK;
 }
 
@@ -830,7 +858,7 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
 {
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     DeviceGuard dg(h->device);
-    int rc = ensure_scratch(h);
+    int rc = ensure_scratch(h, 3);
     if (rc) return rc;
     // the trial steps write the other population buffer (free) and update U
     // in place: keep U and the divergence flag aside and restore them after
@@ -874,6 +902,7 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
     HIP_TRY(hipStreamSynchronize(h->stream));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    release_transient_scratch(h);
     h->seg = best;
     h->wide = best_w;
     if (seg_out) *seg_out = best;
@@ -887,7 +916,7 @@ int slbm_device_bytes(slbm_handle h, int64_t* bytes)
     if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
     int64_t b = 2 * (int64_t)9 * h->plane * (int64_t)h->esize + 2 * h->plane * 8 + h->plane * 5;
     b += (int64_t)h->n_links * (h->esize == 4 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>));
-    if (h->scratch) b += 12 * h->plane * 8;
+    if (h->scratch) b += (int64_t)h->scratch_planes * h->plane * 8;
     *bytes = b;
     return SLBM_OK;
 }
@@ -958,6 +987,324 @@ int slbm_copy(void* dst, const void* src, size_t bytes, int32_t device, void* st
         hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, (hipStream_t)stream,
                            (const float4*)src, (float4*)dst, n);
     HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
+// ================================================================ batches
+
+}  // extern "C"
+
+struct slbm_batch_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t budget = 0, used = 0;
+    int precision = -1;
+    std::vector<slbm_s*> slot;       // nullptr: free
+    std::vector<int64_t> remaining;  // host mirror of the device countdown
+    std::vector<int64_t> bytes;
+    int wide = 0;                    // strip shape of the batched launch
+    int rows = 8;                    // rows per wave for every plate
+    // device tables (rebuilt when the set of plates or the launch shape changes)
+    void* d_plates = nullptr;
+    int* d_tile_plate = nullptr;
+    int* d_tile_start = nullptr;
+    std::vector<int> live;           // slot of each device plate entry
+    int ntiles = 0;
+    bool dirty = true;
+    hipGraphExec_t graph = nullptr;  // kChunk steps, replayed
+    bool graph_ok = false;
+};
+
+namespace {
+
+constexpr int kChunk = 32;           // steps per captured graph
+
+int64_t estimate_bytes(const slbm_params* p)
+{
+    const int64_t ld = (kPadL + p->nx + 1 + 63) / 64 * 64;
+    const int64_t plane = ld * (p->ny + 2);
+    const int64_t es = p->precision == SLBM_FP32 ? 4 : 8;
+    const int64_t link = p->precision == SLBM_FP32 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>);
+    return 2 * 9 * plane * es + 2 * plane * 8 + plane * 5 + (int64_t)p->n_links * link + 64;
+}
+
+void batch_free_tables(slbm_batch_s* b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_ok = false;
+    if (b->d_plates) (void)hipFree(b->d_plates);
+    if (b->d_tile_plate) (void)hipFree(b->d_tile_plate);
+    if (b->d_tile_start) (void)hipFree(b->d_tile_start);
+    b->d_plates = nullptr;
+    b->d_tile_plate = b->d_tile_start = nullptr;
+    b->ntiles = 0;
+}
+
+template <typename real>
+int batch_build(slbm_batch_s* b)
+{
+    batch_free_tables(b);
+    b->live.clear();
+    std::vector<BatchPlate<real>> bp;
+    std::vector<int> tile_plate, tile_start;
+    for (size_t k = 0; k < b->slot.size(); ++k) {
+        slbm_s* h = b->slot[k];
+        if (!h) continue;
+        const int keep_seg = h->seg, keep_w = h->wide;
+        h->seg = b->rows;
+        h->wide = b->wide;
+        BatchPlate<real> e{};
+        e.args = make_args<real>(h, h->cur);
+        h->seg = keep_seg;
+        h->wide = keep_w;
+        e.remaining = b->remaining[k];
+        e.active = b->remaining[k] > 0 ? 1 : 0;
+        const int p = (int)bp.size();
+        tile_start.push_back((int)tile_plate.size());
+        for (int t = 0; t < e.args.ntiles; ++t) tile_plate.push_back(p);
+        bp.push_back(e);
+        b->live.push_back((int)k);
+    }
+    b->ntiles = (int)tile_plate.size();
+    b->dirty = false;
+    if (bp.empty()) return SLBM_OK;
+    HIP_TRY(hipMalloc(&b->d_plates, bp.size() * sizeof(BatchPlate<real>)));
+    HIP_TRY(hipMalloc((void**)&b->d_tile_plate, tile_plate.size() * sizeof(int)));
+    HIP_TRY(hipMalloc((void**)&b->d_tile_start, tile_start.size() * sizeof(int)));
+    HIP_TRY(hipMemcpyAsync(b->d_plates, bp.data(), bp.size() * sizeof(BatchPlate<real>), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_tile_plate, tile_plate.data(), tile_plate.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_tile_start, tile_start.data(), tile_start.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SLBM_OK;
+}
+
+int batch_grid(const slbm_batch_s* b)
+{
+    // enough waves to fill the machine several times over, tiles walked in
+    // strides of the grid beyond that
+    const int g = std::min(b->ntiles, 256 * 32);
+    return (g + 7) / 8 * 8;
+}
+
+// Queues one batched step (and, with advance, its bookkeeping) on the stream.
+template <typename real>
+void batch_launch(slbm_batch_s* b, bool advance)
+{
+    const int grid = batch_grid(b);
+    if (b->wide)
+        hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), dim3(64), 0, b->stream,
+                           (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+    else
+        hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), dim3(64), 0, b->stream,
+                           (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+    if (advance) {
+        const int n = (int)b->live.size();
+        hipLaunchKernelGGL((k_batch_advance<real>), dim3((n + 63) / 64), dim3(64), 0, b->stream,
+                           (BatchPlate<real>*)b->d_plates, n);
+    }
+}
+
+template <typename real>
+int batch_run(slbm_batch_s* b, int64_t k)
+{
+    if (b->dirty) {
+        int rc = batch_build<real>(b);
+        if (rc) return rc;
+    }
+    if (b->ntiles == 0 || k <= 0) return SLBM_OK;
+    int64_t left = k;
+    if (left >= kChunk) {
+        if (!b->graph_ok) {
+            // kChunk steps captured once and replayed: no memset nodes, only
+            // the step and bookkeeping kernels
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < kChunk; ++i) batch_launch<real>(b, true);
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess) return fail(SLBM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(SLBM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+            b->graph_ok = true;
+        }
+        while (left >= kChunk) {
+            HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+            left -= kChunk;
+        }
+    }
+    for (int64_t i = 0; i < left; ++i) batch_launch<real>(b, true);
+    HIP_TRY(hipGetLastError());
+    // host mirror of the device bookkeeping
+    for (size_t k2 = 0; k2 < b->slot.size(); ++k2) {
+        slbm_s* h = b->slot[k2];
+        if (!h) continue;
+        const int64_t n = std::min(k, b->remaining[k2]);
+        if (n <= 0) continue;
+        h->cur ^= (int)(n & 1);
+        h->step += n;
+        h->local = false;
+        b->remaining[k2] -= n;
+    }
+    return SLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slbm_batch_create(int64_t hbm_budget_bytes, int32_t device, void* stream, slbm_batch* out)
+{
+    if (!out) return fail(SLBM_E_INVAL, "null argument");
+    *out = nullptr;
+    if (hbm_budget_bytes <= 0) return fail(SLBM_E_INVAL, "budget must be positive");
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(SLBM_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= n) return fail(SLBM_E_INVAL, "device %d out of range", device);
+    slbm_batch_s* b = new (std::nothrow) slbm_batch_s();
+    if (!b) return fail(SLBM_E_NOMEM, "out of host memory");
+    b->device = device;
+    b->budget = hbm_budget_bytes;
+    DeviceGuard dg(device);
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete b; return fail(SLBM_E_DEVICE, "stream: %s", hipGetErrorString(e)); }
+        b->own_stream = true;
+    }
+    *out = b;
+    return SLBM_OK;
+}
+
+int slbm_batch_add(slbm_batch b, const slbm_params* params, int64_t nsteps, int32_t* slot)
+{
+    if (!b || !params || !slot) return fail(SLBM_E_INVAL, "null argument");
+    if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
+    if (params->periodic_x || params->periodic_y) return fail(SLBM_E_UNSUPPORTED, "periodic plates are not batched");
+    if (b->precision >= 0 && params->precision != b->precision)
+        return fail(SLBM_E_INVAL, "every plate of a batch has the batch's precision");
+    const int64_t need = estimate_bytes(params);
+    if (b->used + need > b->budget)
+        return fail(SLBM_E_BUDGET, "plate needs %lld bytes, %lld of %lld in use", (long long)need,
+                    (long long)b->used, (long long)b->budget);
+    slbm_params p = *params;
+    p.device = b->device;
+    p.stream = b->stream;
+    slbm_handle h = nullptr;
+    int rc = slbm_create(&p, &h);
+    if (rc) return rc;
+    b->precision = params->precision;
+    int k = -1;
+    for (size_t i = 0; i < b->slot.size(); ++i)
+        if (!b->slot[i]) { k = (int)i; break; }
+    if (k < 0) {
+        k = (int)b->slot.size();
+        b->slot.push_back(nullptr);
+        b->remaining.push_back(0);
+        b->bytes.push_back(0);
+    }
+    h->transient_scratch = true;
+    b->slot[k] = h;
+    b->remaining[k] = nsteps;
+    b->bytes[k] = need;
+    b->used += need;
+    b->dirty = true;
+    *slot = k;
+    return SLBM_OK;
+}
+
+int slbm_batch_step(slbm_batch b, int64_t k)
+{
+    if (!b) return fail(SLBM_E_INVAL, "null batch");
+    if (k < 0) return fail(SLBM_E_INVAL, "negative step count");
+    if (b->precision < 0) return SLBM_OK;
+    DeviceGuard dg(b->device);
+    return b->precision == SLBM_FP32 ? batch_run<float>(b, k) : batch_run<double>(b, k);
+}
+
+int slbm_batch_poll(slbm_batch b, int32_t* done_slots, int32_t capacity, int32_t* n_done)
+{
+    if (!b || !n_done) return fail(SLBM_E_INVAL, "null argument");
+    int n = 0;
+    for (size_t k = 0; k < b->slot.size(); ++k) {
+        if (!b->slot[k] || b->remaining[k] > 0) continue;
+        if (done_slots && n < capacity) done_slots[n] = (int32_t)k;
+        ++n;
+    }
+    *n_done = n;
+    return SLBM_OK;
+}
+
+int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h)
+{
+    if (!b || !h) return fail(SLBM_E_INVAL, "null argument");
+    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+    *h = b->slot[slot];
+    return SLBM_OK;
+}
+
+int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps)
+{
+    if (!b || !steps) return fail(SLBM_E_INVAL, "null argument");
+    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+    *steps = b->remaining[slot];
+    return SLBM_OK;
+}
+
+int slbm_batch_remove(slbm_batch b, int32_t slot)
+{
+    if (!b) return fail(SLBM_E_INVAL, "null batch");
+    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+    DeviceGuard dg(b->device);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    slbm_destroy(b->slot[slot]);
+    b->slot[slot] = nullptr;
+    b->remaining[slot] = 0;
+    b->used -= b->bytes[slot];
+    b->bytes[slot] = 0;
+    b->dirty = true;
+    return SLBM_OK;
+}
+
+int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
+{
+    if (!b) return fail(SLBM_E_INVAL, "null batch");
+    if (rows < 1) return fail(SLBM_E_INVAL, "rows must be >= 1");
+    if (strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 62 or 64");
+    b->rows = rows;
+    b->wide = strip == 64 ? 1 : 0;
+    b->dirty = true;
+    return SLBM_OK;
+}
+
+int slbm_batch_sync(slbm_batch b)
+{
+    if (!b) return fail(SLBM_E_INVAL, "null batch");
+    DeviceGuard dg(b->device);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return SLBM_OK;
+}
+
+int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget)
+{
+    if (!b) return fail(SLBM_E_INVAL, "null batch");
+    if (used) *used = b->used;
+    if (budget) *budget = b->budget;
+    return SLBM_OK;
+}
+
+int slbm_batch_destroy(slbm_batch b)
+{
+    if (!b) return SLBM_OK;
+    DeviceGuard dg(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (slbm_s* h : b->slot)
+        if (h) slbm_destroy(h);
+    batch_free_tables(b);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
     return SLBM_OK;
 }
 

@@ -418,22 +418,15 @@ __device__ __forceinline__ bool march_row(const StepArgs<real>& a, int lane, int
     return bad;
 }
 
-// One time step of the whole lattice (section 3 and section 4).  One wave per
-// workgroup; a wave owns a strip of columns (wide or narrow, see
-// strip_width) and marches up `seg` rows with a three-row density window in
-// registers.  The loads of row y+2 are issued before row y is computed, so a
-// row's memory latency overlaps the previous row's arithmetic.
+// One tile of one time step (section 3 and section 4): a strip of columns
+// (wide or narrow, see strip_width) marched up `seg` rows by one wave, with a
+// three-row density window in registers.  The loads of row y+2 are issued
+// before row y is computed, so a row's memory latency overlaps the previous
+// row's arithmetic.
 template <typename real, bool PER, bool WIDE>
-__global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
+__device__ __forceinline__ void step_tile(const StepArgs<real>& a, int tile)
 {
     const int lane = threadIdx.x;
-    const int B = gridDim.x;                  // a multiple of 8
-    const int b = blockIdx.x;
-    // workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous band of tiles so that shared halo rows and columns stay in
-    // one L2
-    const int tile = (b & 7) * (B >> 3) + (b >> 3);
-    if (tile >= a.ntiles) return;
     const int strip = tile % a.nstrips;
     const int segm = tile / a.nstrips;
     constexpr int W = strip_width<WIDE>();
@@ -461,5 +454,63 @@ __global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
     if (bad) atomicOr(a.diverged, 1u);
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs; this gives each XCD a
+// contiguous band of tile numbers so that the halo rows and columns tiles
+// share stay in one L2.  nb (the grid size) is a multiple of 8.
+__device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+
+// One time step of one plate: one wave per tile.
+template <typename real, bool PER, bool WIDE>
+__global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
+{
+    const int tile = xcd_banded(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    step_tile<real, PER, WIDE>(a, tile);
+}
+
+// Per-plate state of the batched step, in device memory so that a captured
+// graph of steps stays valid from one replay to the next.
+template <typename real>
+struct BatchPlate {
+    StepArgs<real> args;       // src/dst and t_prev as of the next step
+    long long remaining;       // steps still to take; 0: idle
+    int active;                // 1 while remaining > 0
+    int pad;
+};
+
+// One time step of every active plate of a batch in one launch.  The tiles of
+// all plates are numbered consecutively (tile_start[p] is plate p's first);
+// workgroups beyond the tiles of a plate that is done return at once.  Each
+// workgroup walks tiles with a stride of the grid size, so the grid can be
+// sized to the machine rather than to the batch.
+template <typename real, bool WIDE>
+__global__ __launch_bounds__(64) void k_step_batch(const BatchPlate<real>* plates, const int* tile_plate,
+                                                   const int* tile_start, int ntiles)
+{
+    for (int t = xcd_banded(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
+        const int p = tile_plate[t];
+        if (!plates[p].active) continue;
+        const StepArgs<real> a = plates[p].args;   // uniform: held in scalar registers
+        step_tile<real, false, WIDE>(a, t - tile_start[p]);
+    }
+}
+
+// After a batched step: swap each active plate's buffers, advance its clock
+// and count down its remaining steps.
+template <typename real>
+__global__ __launch_bounds__(64) void k_batch_advance(BatchPlate<real>* plates, int nplates)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nplates) return;
+    BatchPlate<real>& B = plates[p];
+    if (!B.active) return;
+    real* t = const_cast<real*>(B.args.src);
+    B.args.src = B.args.dst;
+    B.args.dst = t;
+    B.args.t_prev += 1;
+    B.args.local = 0;
+    B.remaining -= 1;
+    if (B.remaining <= 0) B.active = 0;
+}
 
 }  // namespace slbm_dev

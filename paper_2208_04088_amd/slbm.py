@@ -24,6 +24,9 @@ EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
     "slbm_displacement", "slbm_displacement_device", "slbm_time", "slbm_set_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
+    "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
+    "slbm_batch_remaining", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_sync",
+    "slbm_batch_bytes", "slbm_batch_destroy",
 ]
 
 LINK_DTYPE = np.dtype([("site", "<i4"), ("dir", "<i4"), ("q", "<f8"), ("group", "<i4"),
@@ -81,6 +84,17 @@ def lib():
         "slbm_device_bytes": [vp, C.POINTER(i64)],
         "slbm_destroy": [vp],
         "slbm_copy": [vp, vp, C.c_size_t, i32, vp],
+        "slbm_batch_create": [i64, i32, vp, C.POINTER(vp)],
+        "slbm_batch_add": [vp, C.POINTER(Params), i64, C.POINTER(i32)],
+        "slbm_batch_step": [vp, i64],
+        "slbm_batch_poll": [vp, C.POINTER(i32), i32, C.POINTER(i32)],
+        "slbm_batch_handle": [vp, i32, C.POINTER(vp)],
+        "slbm_batch_remaining": [vp, i32, C.POINTER(i64)],
+        "slbm_batch_remove": [vp, i32],
+        "slbm_batch_set_launch": [vp, i32, i32],
+        "slbm_batch_sync": [vp],
+        "slbm_batch_bytes": [vp, C.POINTER(i64), C.POINTER(i64)],
+        "slbm_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -220,3 +234,78 @@ class Solver:
         b = C.c_int64()
         _check(lib().slbm_device_bytes(self.h, C.byref(b)))
         return b.value
+
+
+class _BorrowedSolver(Solver):
+    """A plate owned by a batch: the single-plate readout calls on its handle."""
+
+    def __init__(self, plate, handle):
+        self.plate = plate
+        self.h = handle
+        self.n = plate.nx * plate.ny
+
+    def close(self):
+        self.h = None        # the batch frees it
+
+
+class Batch:
+    """Plates advanced together (slbm_batch_*)."""
+
+    def __init__(self, budget_bytes, device=0, stream=None):
+        b = C.c_void_p()
+        _check(lib().slbm_batch_create(int(budget_bytes), int(device), stream, C.byref(b)))
+        self.b = b
+        self.plates = {}
+
+    def add(self, plate, nsteps, precision="fp32"):
+        prm, keep = marshal(plate, precision)
+        slot = C.c_int32()
+        _check(lib().slbm_batch_add(self.b, C.byref(prm), int(nsteps), C.byref(slot)))
+        self.plates[slot.value] = plate
+        return slot.value
+
+    def step(self, k):
+        _check(lib().slbm_batch_step(self.b, int(k)))
+
+    def poll(self):
+        n = C.c_int32()
+        _check(lib().slbm_batch_poll(self.b, None, 0, C.byref(n)))
+        buf = (C.c_int32 * max(n.value, 1))()
+        _check(lib().slbm_batch_poll(self.b, buf, n.value, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def solver(self, slot):
+        h = C.c_void_p()
+        _check(lib().slbm_batch_handle(self.b, int(slot), C.byref(h)))
+        return _BorrowedSolver(self.plates[slot], h)
+
+    def remaining(self, slot):
+        r = C.c_int64()
+        _check(lib().slbm_batch_remaining(self.b, int(slot), C.byref(r)))
+        return r.value
+
+    def remove(self, slot):
+        _check(lib().slbm_batch_remove(self.b, int(slot)))
+        self.plates.pop(slot, None)
+
+    def set_launch(self, rows, strip):
+        _check(lib().slbm_batch_set_launch(self.b, int(rows), int(strip)))
+
+    def sync(self):
+        _check(lib().slbm_batch_sync(self.b))
+
+    def bytes(self):
+        u, t = C.c_int64(), C.c_int64()
+        _check(lib().slbm_batch_bytes(self.b, C.byref(u), C.byref(t)))
+        return u.value, t.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().slbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,138 @@
+"""Batched path (slbm_batch_*): many plates in one launch per step, steps
+replayed from a captured graph.  Every plate's result must be bit-identical
+to the same plate run alone (the per-site arithmetic does not depend on the
+batch), which in turn is checked against the CPU reference elsewhere."""
+import numpy as np
+import pytest
+
+from slbm_workloads import configs
+from slbm_workloads import geometry as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slbm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2208_04088_amd import slbm as S
+    S.lib()
+    return S
+
+
+def small_plates(seed, count):
+    """Uneven plates from the batched-workload generator, shrunk to test size."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        out.append(configs._random_plate(rng, area_lo=24 ** 2, area_hi=180 ** 2, load=1e-3, steps=0,
+                                         name=f"small{seed}-{i}"))
+    return out
+
+
+def alone(slbm, plate, steps, prec):
+    s = slbm.Solver(plate, prec)
+    s.step(steps)
+    return s.displacement(), s.moments()[3]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_plates_match_their_solo_runs(slbm, prec):
+    plates = small_plates(3, 7)
+    steps = [0, 1, 31, 32, 33, 70, 101]
+    b = slbm.Batch(8 << 30)
+    slots = [b.add(p, n, prec) for p, n in zip(plates, steps)]
+    for k in (5, 32, 1, 40, 64):        # chunks below, at and above the graph size
+        b.step(k)
+    b.sync()
+    assert sorted(b.poll()) == sorted(slots)
+    for p, n, sl in zip(plates, steps, slots):
+        s = b.solver(sl)
+        assert s.time()[0] == n
+        s.sync()
+        u_ref, sig_ref = alone(slbm, p, n, prec)
+        assert np.array_equal(s.displacement(), u_ref), p.name
+        assert np.array_equal(s.moments()[3], sig_ref), p.name
+    b.close()
+
+
+def test_continuous_batching_joins_and_leaves(slbm):
+    """Plates arrive while others are running and leave when done; each
+    result is the same alone and in the mix."""
+    plates = small_plates(5, 6)
+    want = [45, 80, 33, 64, 100, 20]
+    b = slbm.Batch(8 << 30)
+    live = {}
+    arrivals = {0: [0, 1], 1: [2], 2: [3, 4], 4: [5]}
+    finished = {}
+    for tick in range(12):
+        for i in arrivals.get(tick, []):
+            live[b.add(plates[i], want[i], "fp32")] = i
+        b.step(16)
+        for sl in b.poll():
+            i = live.pop(sl)
+            s = b.solver(sl)
+            finished[i] = (s.time()[0], s.displacement())
+            b.remove(sl)
+    assert sorted(finished) == list(range(6))
+    for i, (n, u) in finished.items():
+        assert n == want[i]
+        u_ref, _ = alone(slbm, plates[i], want[i], "fp32")
+        assert np.array_equal(u, u_ref), plates[i].name
+    assert b.bytes()[0] == 0
+    b.close()
+
+
+def test_batch_launch_shape_does_not_change_results(slbm):
+    plates = small_plates(9, 4)
+    ref = None
+    for rows, strip in ((2, 62), (8, 64), (5, 62), (32, 64)):
+        b = slbm.Batch(8 << 30)
+        slots = [b.add(p, 50, "fp64") for p in plates]
+        b.set_launch(rows, strip)
+        b.step(50)
+        us = [b.solver(sl).displacement() for sl in slots]
+        if ref is None:
+            ref = us
+        else:
+            for a, r in zip(us, ref):
+                assert np.array_equal(a, r)
+        b.close()
+
+
+def test_budget_is_enforced(slbm):
+    plates = small_plates(11, 3)
+    b = slbm.Batch(1 << 20)      # 1 MiB: the first small plate fits, not all three
+    ok, rejected = 0, 0
+    for p in plates:
+        try:
+            b.add(p, 10, "fp32")
+            ok += 1
+        except slbm.SlbmError as e:
+            assert e.code == -6
+            rejected += 1
+    assert rejected >= 1
+    used, budget = b.bytes()
+    assert used <= budget
+    b.close()
+
+
+def test_batch_divergence_is_per_plate(slbm):
+    """One plate that blows up (lambda/mu = 2, traction-free, the paper's
+    extrapolation) flags itself and leaves its neighbours' results intact."""
+    n = 40
+    bad = G.build_plate(n, n, lam=0.1, mu=0.05, tau=0.6, walls=G.edge_walls(n, n, 0, 0, 1, 1),
+                        groups=[G.BCGroup(G.NEUMANN, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (0.0, 1e-4))],
+                        neumann_order=1, name="unstable")
+    good = small_plates(13, 1)[0]
+    b = slbm.Batch(8 << 30)
+    sb = b.add(bad, 2000, "fp32")
+    sg = b.add(good, 2000, "fp32")
+    b.step(2000)
+    with pytest.raises(slbm.SlbmError) as e:
+        b.solver(sb).sync()
+    assert e.value.code == -4
+    b.solver(sg).sync()
+    u_ref, _ = alone(slbm, good, 2000, "fp32")
+    assert np.array_equal(b.solver(sg).displacement(), u_ref)
+    b.close()
