@@ -306,7 +306,6 @@ StepArgs<real> make_args(const slbm_s* h, int src)
     a.px = h->px; a.py = h->py;
     a.local = h->local ? 1 : 0;
     a.omega = (real)(1.0 / h->tau);
-    a.cpsi = (real)(1.0 - 0.5 / h->tau);
     a.lm = (real)(h->lamL - h->muL);
     a.ml = (real)(h->muL - h->lamL);
     a.Fx = (real)h->FL[0];

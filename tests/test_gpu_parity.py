@@ -270,12 +270,10 @@ def rigid_part(d, mask):
 @pytest.mark.slow
 def test_crack_config_fp32_full_length(slbm):
     """1024 x 512 edge-crack plate, fp32 populations, fp64 displacement, 10k
-    steps, against the fp64 reference.  The plate is free-floating: its
-    rigid-body motion is a zero mode whose amplitude integrates the round-off
-    in the net momentum (a 1e-7 perturbation of the start state grows to
-    ~1e-5 in u after 10k steps, almost all of it rigid).  The deformation --
-    displacement minus the rigid-body part of the difference -- and the stress
-    field must agree to 1e-4; the raw displacement difference is printed."""
+    steps, against the fp64 reference: relative L2 of the displacement and of
+    the stress within 1e-4.  The plate is undamped and free-floating, so a
+    per-step bias of the conserved moments (rounded equilibrium weights) would
+    compound over the run; the kernel's collision keeps them exact."""
     p = configs.edge_crack_plate()
     s = slbm.Solver(p, "fp32")
     s.step(p.steps)
@@ -292,7 +290,7 @@ def test_crack_config_fp32_full_length(slbm):
     es = rel_l2(sig, sig_ref)
     print(f"crack1024x512 fp32 {p.steps} steps: rel L2 u = {raw:.3e}, without rigid-body part "
           f"{deform:.3e}, stress {es:.3e}")
-    assert deform <= FP32_TOL
+    assert raw <= FP32_TOL
     assert es <= FP32_TOL
 
 
