@@ -68,7 +68,7 @@ def measured_traffic(plate, prec, tuned):
     d = json.load(open(path))
     if d.get("kernel_fingerprint") != kernel_fingerprint():
         return None
-    if [d.get("rows_per_wave"), d.get("strip_width")] != [tuned[0], tuned[1]]:
+    if [d.get("rows_per_tile"), d.get("strip_width")] != [tuned[0], tuned[1]]:
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="crack1024x512")
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--seg", type=int, default=0, help="rows per wave (0: autotuned)")
+    ap.add_argument("--seg", type=int, default=0, help="rows per tile (0: autotuned)")
     ap.add_argument("--strip", type=int, default=0, help="strip width 62 or 64 (0: autotuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -126,7 +126,7 @@ def main():
         s.set_launch(args.seg, args.strip)
         tuned = (args.seg, args.strip, None)
     else:
-        tuned = s.autotune()          # rows per wave, measured on this plate
+        tuned = s.autotune()          # rows per tile and strip width, measured on this plate
 
     torch.cuda.synchronize()
 
@@ -202,7 +202,7 @@ def main():
             "bytes_per_site": bps,
             "avg_launch_us": round(t_step * 1e6, 3),
             "single_launch_median_us": round(launch_med_ms * 1e3, 3),
-            "rows_per_wave": tuned[0],
+            "rows_per_tile": tuned[0],
             "strip_width": tuned[1],
         },
     }

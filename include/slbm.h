@@ -153,14 +153,16 @@ int slbm_displacement_device(slbm_handle h, void* u_dev);
 /* Step count and physical time of the current state. */
 int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 
-/* Launch shape of the fused step: rows each wave marches (seg_rows >= 1)
- * and strip width (64: aligned columns, one per lane; 62: unaligned, two
- * halo lanes per wave).  0 keeps the library's choice for either.  Results
- * do not depend on the shape. */
+/* Launch shape of the fused step.  A workgroup advances a tile of seg_rows
+ * rows (one wave per row, plus two waves for the density-halo rows) of one
+ * strip of columns; strip is the strip width (62: two halo lanes per wave;
+ * 64: aligned columns, one more wave for the halo columns).  seg_rows is at
+ * most 14 (62) or 13 (64); 0 keeps the library's choice for either.
+ * SLBM_E_INVAL beyond the limits.  Results do not depend on the shape. */
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
 
 /* Times the fused step on this plate for each strip width and a range of
- * rows per wave (short bursts of launches, the state restored after each)
+ * rows per tile (short bursts of launches, the state restored after each)
  * and keeps the fastest; reports it and its time per step in microseconds
  * (any pointer may be NULL).  Synchronises.  The state and step count are
  * unchanged. */
@@ -211,8 +213,9 @@ int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps);
 /* Frees the plate (its slot and budget are reused). */
 int slbm_batch_remove(slbm_batch b, int32_t slot);
 
-/* Launch shape of the batched step: rows each wave marches and strip width
- * (62 or 64), for every plate. */
+/* Launch shape of the batched step, for every plate: rows per tile (1..14
+ * with strip 62, 1..13 with strip 64) as in slbm_set_launch.  SLBM_E_INVAL
+ * beyond the limits. */
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
 
 int slbm_batch_sync(slbm_batch b);

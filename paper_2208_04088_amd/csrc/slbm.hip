@@ -268,20 +268,19 @@ namespace {
 
 bool pick_wide(const slbm_s* h)
 {
-    if (h->wide >= 0) return h->wide == 1;
-    return (long long)h->nx * h->ny >= (1LL << 22);   // wide strips pay off on large plates
+    return h->wide == 1;             // narrow strips unless asked: measured faster on every plate tried
 }
 
+// Rows per tile: short tiles give small plates enough workgroups to fill the
+// machine, tall ones cut the halo-row overhead (2 rows per tile) on large
+// plates; the autotuner refines this per plate.
 int pick_seg(const slbm_s* h)
 {
-    if (h->seg > 0) return h->seg;
-    // aim for ~16 waves per CU on 256 CUs, rows per wave in [2, 64]
-    const int sw = pick_wide(h) ? 64 : 62;
-    const int nstrips = (h->nx + sw - 1) / sw;
-    const long long target = 16LL * 256;
-    long long segs = (target + nstrips - 1) / nstrips;
-    int seg = (int)std::max<long long>(1, (h->ny + segs - 1) / segs);
-    return std::min(64, std::max(2, seg));
+    const int mx = pick_wide(h) ? max_tile_rows<true>() : max_tile_rows<false>();
+    if (h->seg > 0) return std::min(h->seg, mx);
+    const long long n = (long long)h->nx * h->ny;
+    const int r = n >= (1LL << 22) ? 14 : (n >= (1LL << 16) ? 6 : 2);
+    return std::min(r, mx);
 }
 
 template <typename real>
@@ -318,14 +317,15 @@ void dispatch_step(const slbm_s* h, const StepArgs<real>& a)
 {
     const int grid = ((a.ntiles + 7) / 8) * 8;
     const bool per = h->px || h->py, wide = pick_wide(h);
+    const dim3 blk(64 * (wide ? tile_waves<true>(a.seg) : tile_waves<false>(a.seg)));
     if (per && wide)
-        hipLaunchKernelGGL((k_step<real, true, true>), dim3(grid), dim3(64), 0, h->stream, a);
+        hipLaunchKernelGGL((k_step<real, true, true>), dim3(grid), blk, 0, h->stream, a);
     else if (per)
-        hipLaunchKernelGGL((k_step<real, true, false>), dim3(grid), dim3(64), 0, h->stream, a);
+        hipLaunchKernelGGL((k_step<real, true, false>), dim3(grid), blk, 0, h->stream, a);
     else if (wide)
-        hipLaunchKernelGGL((k_step<real, false, true>), dim3(grid), dim3(64), 0, h->stream, a);
+        hipLaunchKernelGGL((k_step<real, false, true>), dim3(grid), blk, 0, h->stream, a);
     else
-        hipLaunchKernelGGL((k_step<real, false, false>), dim3(grid), dim3(64), 0, h->stream, a);
+        hipLaunchKernelGGL((k_step<real, false, false>), dim3(grid), blk, 0, h->stream, a);
 }
 
 // One step from the current state into the other buffer with the given
@@ -580,6 +580,10 @@ int create_impl(const slbm_params* p, slbm_handle* out)
     h->nx = nx; h->ny = ny;
     h->ld = (kPadL + nx + 1 + 63) / 64 * 64;
     h->plane = (long long)h->ld * (ny + 2);
+    if (h->plane * (long long)sizeof(double) >= (1LL << 32)) {
+        delete h;
+        return fail(SLBM_E_UNSUPPORTED, "padded plane exceeds 4 GiB (kernels address planes with 32-bit offsets)");
+    }
     h->precision = p->precision;
     h->px = p->periodic_x ? 1 : 0;
     h->py = p->periodic_y ? 1 : 0;
@@ -848,6 +852,8 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
     if (strip != 0 && strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 0, 62 or 64");
+    if (seg_rows > (strip == 64 ? max_tile_rows<true>() : max_tile_rows<false>()))
+        return fail(SLBM_E_INVAL, "rows per tile above the maximum (14 narrow, 13 wide)");
     h->seg = seg_rows;
     h->wide = strip == 0 ? -1 : (strip == 64 ? 1 : 0);
     return SLBM_OK;
@@ -870,11 +876,12 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cand[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
-    int best = 0, best_w = 1;
+    const int cand[] = {2, 3, 4, 6, 8, 10, 12, 14};
+    int best = 0, best_w = 0;
     double best_us = 1e30;
     for (int wv = 0; wv < 2; ++wv)
     for (int c : cand) {
+        if (c > (wv ? max_tile_rows<true>() : max_tile_rows<false>())) break;
         if (c > std::max(2, h->ny)) break;
         // bursts of back-to-back launches, as steps run; each launch rereads
         // the same state, U is put back after the burst
@@ -1003,7 +1010,7 @@ struct slbm_batch_s {
     std::vector<int64_t> remaining;  // host mirror of the device countdown
     std::vector<int64_t> bytes;
     int wide = 0;                    // strip shape of the batched launch
-    int rows = 8;                    // rows per wave for every plate
+    int rows = 6;                    // rows per tile for every plate
     // device tables (rebuilt when the set of plates or the launch shape changes)
     void* d_plates = nullptr;
     int* d_tile_plate = nullptr;
@@ -1081,9 +1088,9 @@ int batch_build(slbm_batch_s* b)
 
 int batch_grid(const slbm_batch_s* b)
 {
-    // enough waves to fill the machine several times over, tiles walked in
-    // strides of the grid beyond that
-    const int g = std::min(b->ntiles, 256 * 32);
+    // enough workgroups to fill the machine several times over, tiles walked
+    // in strides of the grid beyond that
+    const int g = std::min(b->ntiles, 256 * 8);
     return (g + 7) / 8 * 8;
 }
 
@@ -1092,11 +1099,12 @@ template <typename real>
 void batch_launch(slbm_batch_s* b, bool advance)
 {
     const int grid = batch_grid(b);
+    const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
     if (b->wide)
-        hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), dim3(64), 0, b->stream,
+        hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
                            (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
     else
-        hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), dim3(64), 0, b->stream,
+        hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
                            (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
     if (advance) {
         const int n = (int)b->live.size();
@@ -1270,8 +1278,9 @@ int slbm_batch_remove(slbm_batch b, int32_t slot)
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
 {
     if (!b) return fail(SLBM_E_INVAL, "null batch");
-    if (rows < 1) return fail(SLBM_E_INVAL, "rows must be >= 1");
     if (strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 62 or 64");
+    if (rows < 1 || rows > (strip == 64 ? max_tile_rows<true>() : max_tile_rows<false>()))
+        return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] (narrow) or [1, 13] (wide)");
     b->rows = rows;
     b->wide = strip == 64 ? 1 : 0;
     b->dirty = true;

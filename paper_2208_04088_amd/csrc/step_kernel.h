@@ -1,6 +1,6 @@
 // step_kernel.h -- device code of the fused solid-LBM time step (gfx950).
 //
-// Included by slbm.hip (single-plate path) and batch.hip (batched path).
+// Included by slbm.hip (single-plate and batched paths).
 // Method: Faust, Schlueter, H. Mueller, R. Mueller, "Dirichlet and Neumann
 // boundary conditions in a Lattice Boltzmann Method for Elastodynamics"
 // (2022), sections 3 and 4.  The data layout is described in slbm.hip.
@@ -25,11 +25,10 @@ __host__ __device__ constexpr double WD(int i) { return i == 0 ? 4.0 / 9.0 : (i 
 constexpr int kPadL = 64;      // padding columns left of the grid: keeps wide strips 256-byte aligned
 
 // Two strip shapes for the fused step (the autotuner picks per plate):
-//   wide   64 output columns per wave, 256-byte aligned; the two density-halo
-//          sites are fetched by the half-waves;
+//   wide   64 output columns per wave, 256-byte aligned; one extra wave of the
+//          workgroup supplies the densities of the two halo columns;
 //   narrow 62 output columns per wave (lanes 1..62); lanes 0 and 63 sit on
-//          the halo columns and only supply density.  Fewer registers, more
-//          waves in flight, unaligned rows: faster on small plates.
+//          the halo columns and only supply density.
 template <bool WIDE> constexpr int strip_width() { return WIDE ? 64 : 62; }
 constexpr unsigned kVoid = 0xFFu;
 
@@ -119,6 +118,38 @@ __device__ __forceinline__ void moments9(const real g[9], real& dr, real& jx, re
     pxy = d57 - d68;
 }
 
+// Element e of a plane: a uniform base pointer plus a 32-bit byte offset, so
+// that loads and stores address through a scalar base register and one
+// vector register (a plane holds far fewer than 2^32 bytes; checked at
+// creation).
+// The empty asm pins the base in scalar registers and keeps the compiler
+// from folding the plane offset into per-lane 64-bit address arithmetic.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> sbase(T* p)
+{
+    gptr<T> q = (gptr<T>)p;
+    asm("" : "+s"(q));
+    return q;
+}
+template <typename T>
+__device__ __forceinline__ T ldu(const T* base, unsigned e)       // base uniform over the wave
+{
+    return *(gptr<const T>)((gptr<const char>)sbase(base) + e * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stu(T* base, unsigned e, T v)     // base uniform over the wave
+{
+    *(gptr<T>)((gptr<char>)sbase(base) + e * (unsigned)sizeof(T)) = v;
+}
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned e)       // any base
+{
+    return *(const T*)((const char*)base + e * (unsigned)sizeof(T));
+}
+
 // Offset of site (x, y) in a padded plane.
 __host__ __device__ __forceinline__ int sidx(int x, int y, int ld) { return (y + 1) * ld + (x + kPadL); }
 
@@ -141,7 +172,7 @@ __device__ __forceinline__ void stored_moments(const StepArgs<real>& a, int s, r
 {
     real h[9];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) h[j] = a.src[j * a.plane + s];
+    for (int j = 0; j < 9; ++j) h[j] = ldu(a.src + j * a.plane, s);
     real jx, jy;
     moments9(h, dr, jx, jy, pxx, pyy, pxy);
 }
@@ -154,13 +185,13 @@ __device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, 
                                real drx, real pxxx, real pyyx, real pxyx)
 {
     const int k = L.k, kb = OPP(k);
-    const real gk = a.src[k * a.plane + s];
-    const real gkb = a.src[kb * a.plane + s];
+    const real gk = ldg(a.src + k * a.plane, s);
+    const real gkb = ldg(a.src + kb * a.plane, s);
     int sb = 0;
     real gky = real(0);
     if (L.behind) {
         sb = wrap_off<PER>(x, y, -L.dx, -L.dy, a.nx, a.ny, a.ld, a.px, a.py);
-        gky = a.src[k * a.plane + sb];
+        gky = ldg(a.src + k * a.plane, sb);
     }
     if (L.kind == SLBM_DIRICHLET) {
         // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
@@ -199,7 +230,7 @@ __device__ void boundary_fixup(const StepArgs<real>& a, int x, int y, int s, uns
 {
     real drx, pxxx, pyyx, pxyx;
     stored_moments(a, s, drx, pxxx, pyyx, pxyx);
-    int li = a.bidx[s];
+    int li = ldu(a.bidx, s);
     unsigned m = fl;
     while (m) {
         const int k = __builtin_ctz(m) + 1;
@@ -219,7 +250,7 @@ template <typename real, bool PER>
 __device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y, real g[9], unsigned& flo)
 {
     const int s = sidx(x, y, a.ld);
-    const unsigned fl = a.flags[s];
+    const unsigned fl = ldu(a.flags, s);
     flo = fl;
     if (fl == kVoid) {
 #pragma unroll
@@ -228,25 +259,11 @@ __device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        g[i] = a.local ? a.src[i * a.plane + s]
-                       : a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
+        g[i] = a.local ? ldu(a.src + i * a.plane, s)
+                       : ldu(a.src + i * a.plane, wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py));
     if (!a.local && fl != 0) boundary_fixup<real, PER>(a, x, y, s, fl, g);
     return true;
 }
-
-// One row of the sliding window: loads in flight, then completed.  Besides
-// its own site, every lane fetches one density-halo site of its wave's strip:
-// lanes 0-31 the site left of the strip, lanes 32-63 the one right of it
-// (lane 0 and lane 63 use them).
-template <typename real, bool WIDE>
-struct Row {
-    real g[9];                 // own site
-    real h[WIDE ? 9 : 1];      // halo site (wide strips)
-    double ux, uy;
-    unsigned fl, flh;
-    int y, yh;
-    bool in, inh;
-};
 
 // Loads of one site, unconditional: a site outside the grid loads from a
 // clamped in-grid site and is masked when completed (a conditional load
@@ -276,25 +293,15 @@ __device__ __forceinline__ void site_issue(const StepArgs<real>& a, int x, int y
     ys = y;
     const int s = sidx(x, y, a.ld);
     s_out = s;
-    fl = a.flags[s];
+    fl = ldu(a.flags, s);
     if (a.local) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = a.src[i * a.plane + s];
+        for (int i = 0; i < 9; ++i) g[i] = ldu(a.src + i * a.plane, s);
     } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            g[i] = a.src[i * a.plane + wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py)];
+            g[i] = ldu(a.src + i * a.plane, wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py));
     }
-}
-
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ void row_issue(const StepArgs<real>& a, int x, int xh, int y, Row<real, WIDE>& r)
-{
-    int s, sh;
-    site_issue<real, PER>(a, x, y, r.g, r.fl, r.y, r.in, s);
-    if constexpr (WIDE) site_issue<real, PER>(a, xh, y, r.h, r.flh, r.yh, r.inh, sh);
-    r.ux = a.U[s];
-    r.uy = a.U[a.plane + s];
 }
 
 // Completes one site: boundary rules on cut links, nothing for void sites.
@@ -315,16 +322,16 @@ __device__ __forceinline__ real site_finish(const StepArgs<real>& a, int x, int 
     return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
 }
 
-// Density window of the gradient stencil: delta-rho of rows y-1, y at this
-// lane and its two neighbours.
+// Density stencil of the source term below and at a site: delta-rho of row
+// y-1 (m) and row y (c) at the site's column and its two neighbours.
 template <typename real>
 struct Window {
     real m, m_l, m_r;
     real c, c_l, c_r;
 };
 
-// Collision, source term and displacement update of one site (row B), given
-// the density window and the next row's densities.
+// Collision, source term and displacement update of one site, given the
+// densities of its eight neighbours (w and the row above, rp).
 //
 // eq:coll with eq:fieq, in the closure where the equilibrium's second moment
 // is the populations' own: collision leaves rho and P unchanged, adds S to j
@@ -338,12 +345,11 @@ struct Window {
 // a_e below).  Rounded equilibrium weights would instead scale the conserved
 // moments by (1 + omega eps) each step, a drift of ~5e-4 after 10^4 steps in
 // single precision.
-template <typename real, bool WIDE>
-__device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const Row<real, WIDE>& B,
-                                             const Window<real>& w, real rp, real rp_l, real rp_r)
+template <typename real>
+__device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const real g[9], unsigned fl,
+                                             double ux, double uy, const Window<real>& w, real rp, real rp_l,
+                                             real rp_r)
 {
-    const unsigned fl = B.fl;
-    const real* g = B.g;
     const real A4 = g[1] + g[2] + g[3] + g[4];
     const real B4 = g[5] + g[6] + g[7] + g[8];
     const real Dx = g[5] - g[6] - g[7] + g[8];
@@ -388,99 +394,78 @@ __device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int
     o[8] = g[8] + ((ax - ay) + ae);
     const int s = sidx(x, y, a.ld);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a.dst[i * a.plane + s] = o[i];
+    for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
     // displacement: U += j/rho (fp64 accumulation)
     const double ir = 1.0 / (double)rho;
-    a.U[s] = B.ux + (double)jx * ir;
-    a.U[a.plane + s] = B.uy + (double)jy * ir;
+    stu(a.U, s, ux + (double)jx * ir);
+    stu(a.U + a.plane, s, uy + (double)jy * ir);
     return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
 }
 
-// Densities of a completed row as seen by this lane: own site, and the sites
-// left and right of it (from the neighbouring lanes, or the halo site at the
-// ends of the strip).
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ void row_density(const StepArgs<real>& a, int lane, int x, int xh, Row<real, WIDE>& r,
-                                            real& d, real& d_l, real& d_r)
-{
-    d = site_finish<real, PER>(a, x, r.y, r.in, true, r.fl, r.g);
-    const real up = __shfl_up(d, 1), dn = __shfl_down(d, 1);
-    if constexpr (WIDE) {
-        const real dh = site_finish<real, PER>(a, xh, r.yh, r.inh, lane == 0 || lane == 63, r.flh, r.h);
-        d_l = lane == 0 ? dh : up;
-        d_r = lane == 63 ? dh : dn;
-    } else {
-        d_l = up;
-        d_r = dn;
-    }
-}
+// ------------------------------------------------------------------ tiles
+//
+// A workgroup advances a tile of R rows (R <= kMaxTileRows) of one strip: one
+// wave per output row plus two waves for the density-halo rows below and
+// above the tile (and, for wide strips, one wave for the halo columns).
+// Every wave issues all loads of its row at once, completes the pulls with
+// the boundary rules and puts the density in LDS; after a barrier the output
+// waves read the 3x3 density stencil of the source term from LDS and collide.
+constexpr int kMaxTileRows = 14;
 
-// One row of the march: issue row y+2 into D, complete row y+1 (C), compute
-// row y (B).  Called with the three rows in rotating roles so that no row's
-// registers are ever copied while its loads are in flight.
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ bool march_row(const StepArgs<real>& a, int lane, int x, int xh, bool out, int y,
-                                          Row<real, WIDE>& B, Row<real, WIDE>& C, Row<real, WIDE>& D,
-                                          Window<real>& w)
-{
-    row_issue<real, PER, WIDE>(a, x, xh, y + 2, D);
-    real rp, rp_l, rp_r;
-    row_density<real, PER, WIDE>(a, lane, x, xh, C, rp, rp_l, rp_r);
-    bool bad = false;
-    if (out && B.fl != kVoid) bad = collide_site<real, WIDE>(a, x, y, B, w, rp, rp_l, rp_r);
-    w.m = w.c; w.m_l = w.c_l; w.m_r = w.c_r;
-    w.c = rp; w.c_l = rp_l; w.c_r = rp_r;
-    return bad;
-}
-
-// One tile of one time step (section 3 and section 4): a strip of columns
-// (wide or narrow, see strip_width) marched up `seg` rows by one wave, with a
-// three-row density window in registers.  The loads of row y+2 are issued
-// before row y is computed, so a row's memory latency overlaps the previous
-// row's arithmetic.
-template <typename real, bool PER, bool WIDE>
-__device__ __forceinline__ void step_tile(const StepArgs<real>& a, int tile)
-{
-    const int lane = threadIdx.x;
-    const int strip = tile % a.nstrips;
-    const int segm = tile / a.nstrips;
-    constexpr int W = strip_width<WIDE>();
-    const int x = WIDE ? strip * W + lane : strip * W - 1 + lane;
-    const int xh = lane < 32 ? strip * W - 1 : strip * W + W;
-    const bool out = x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
-    const int y0 = segm * a.seg;
-    const int y1 = min(y0 + a.seg, a.ny);
-
-    Row<real, WIDE> R0, R1, R2;
-    Window<real> w;
-    row_issue<real, PER, WIDE>(a, x, xh, y0 - 1, R2);
-    row_issue<real, PER, WIDE>(a, x, xh, y0, R0);
-    row_issue<real, PER, WIDE>(a, x, xh, y0 + 1, R1);
-    row_density<real, PER, WIDE>(a, lane, x, xh, R2, w.m, w.m_l, w.m_r);
-    row_density<real, PER, WIDE>(a, lane, x, xh, R0, w.c, w.c_l, w.c_r);
-    bool bad = false;
-    for (int y = y0; y < y1; y += 3) {
-        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y, R0, R1, R2, w);
-        if (y + 1 >= y1) break;
-        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y + 1, R1, R2, R0, w);
-        if (y + 2 >= y1) break;
-        bad |= march_row<real, PER, WIDE>(a, lane, x, xh, out, y + 2, R2, R0, R1, w);
-    }
-    if (bad) atomicOr(a.diverged, 1u);
-}
+template <bool WIDE> constexpr int tile_waves(int rows) { return rows + 2 + (WIDE ? 1 : 0); }
+template <bool WIDE> constexpr int max_tile_rows() { return WIDE ? kMaxTileRows - 1 : kMaxTileRows; }
 
 // Workgroups are dealt round-robin to the 8 XCDs; this gives each XCD a
 // contiguous band of tile numbers so that the halo rows and columns tiles
 // share stay in one L2.  nb (the grid size) is a multiple of 8.
 __device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
-// One time step of one plate: one wave per tile.
+
 template <typename real, bool PER, bool WIDE>
-__global__ __launch_bounds__(64) void k_step(StepArgs<real> a)
+__device__ __forceinline__ bool step_tile(const StepArgs<real>& a, int tile, real (*dens)[66])
 {
+    constexpr int W = strip_width<WIDE>();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int R = a.seg;
+    const int strip = tile % a.nstrips;
+    const int y0 = (tile / a.nstrips) * R;
+    const int xs = strip * W;                      // first output column of the strip
+    // row waves: row y0 - 1 + wave, narrow strips with the halo columns on
+    // lanes 0 and 63; the halo-column wave of a wide strip: lane 2r + side is
+    // the site left (side 0) or right (side 1) of the strip in row y0 - 1 + r
+    const bool roww = !WIDE || wave < R + 2;
+    const int hr = lane >> 1, side = lane & 1;
+    const bool hcol = !roww && hr < R + 2;
+    const int x = roww ? (WIDE ? xs + lane : xs - 1 + lane) : (side ? xs + W : xs - 1);
+    const int y = y0 - 1 + (roww ? wave : (hcol ? hr : 0));
+    real g[9];
+    unsigned fl;
+    bool in;
+    int ys, s;
+    site_issue<real, PER>(a, x, y, g, fl, ys, in, s);
+    const double ux = ldu(a.U, s), uy = ldu(a.U + a.plane, s);
+    const real d = site_finish<real, PER>(a, x, ys, in, true, fl, g);
+    const int c = WIDE ? lane + 1 : lane;
+    if (roww) dens[wave][c] = d;
+    else if (hcol) dens[hr][side ? W + 1 : 0] = d;
+    __syncthreads();
+    const bool out = roww && wave >= 1 && wave <= R && y < a.ny && x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
+    if (!out || fl == kVoid) return false;
+    Window<real> w;
+    w.m = dens[wave - 1][c]; w.m_l = dens[wave - 1][c - 1]; w.m_r = dens[wave - 1][c + 1];
+    w.c_l = dens[wave][c - 1]; w.c_r = dens[wave][c + 1];
+    return collide_site<real>(a, x, y, g, fl, ux, uy, w, dens[wave + 1][c], dens[wave + 1][c - 1],
+                              dens[wave + 1][c + 1]);
+}
+
+// One time step of one plate: one workgroup of tile_waves(seg) waves per tile.
+template <typename real, bool PER, bool WIDE>
+__global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
+{
+    __shared__ real dens[kMaxTileRows + 2][66];
     const int tile = xcd_banded(blockIdx.x, gridDim.x);
-    if (tile >= a.ntiles) return;
-    step_tile<real, PER, WIDE>(a, tile);
+    if (tile >= a.ntiles) return;                 // uniform over the workgroup
+    if (step_tile<real, PER, WIDE>(a, tile, dens)) atomicOr(a.diverged, 1u);
 }
 
 // Per-plate state of the batched step, in device memory so that a captured
@@ -494,19 +479,22 @@ struct BatchPlate {
 };
 
 // One time step of every active plate of a batch in one launch.  The tiles of
-// all plates are numbered consecutively (tile_start[p] is plate p's first);
-// workgroups beyond the tiles of a plate that is done return at once.  Each
-// workgroup walks tiles with a stride of the grid size, so the grid can be
-// sized to the machine rather than to the batch.
+// all plates (of one height, the launch's) are numbered consecutively
+// (tile_start[p] is plate p's first); tiles of a plate that is done are
+// skipped.  Each workgroup walks tiles with a stride of the grid size, so the
+// grid can be sized to the machine rather than to the batch.
 template <typename real, bool WIDE>
-__global__ __launch_bounds__(64) void k_step_batch(const BatchPlate<real>* plates, const int* tile_plate,
-                                                   const int* tile_start, int ntiles)
+__global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __restrict__ plates,
+                                                     const int* __restrict__ tile_plate,
+                                                     const int* __restrict__ tile_start, int ntiles)
 {
+    __shared__ real dens[kMaxTileRows + 2][66];
     for (int t = xcd_banded(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
         const int p = tile_plate[t];
-        if (!plates[p].active) continue;
-        const StepArgs<real> a = plates[p].args;   // uniform: held in scalar registers
-        step_tile<real, false, WIDE>(a, t - tile_start[p]);
+        if (!plates[p].active) continue;         // uniform over the workgroup
+        const StepArgs<real> a = plates[p].args;
+        if (step_tile<real, false, WIDE>(a, t - tile_start[p], dens)) atomicOr(a.diverged, 1u);
+        __syncthreads();                          // dens is reused by the next tile
     }
 }
 

@@ -212,7 +212,7 @@ class Solver:
 
     def autotune(self):
         """Picks the fastest launch shape for this plate; returns
-        (rows per wave, strip width, us per step)."""
+        (rows per tile, strip width, us per step)."""
         seg = C.c_int32()
         strip = C.c_int32()
         us = C.c_double()

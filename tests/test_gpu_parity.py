@@ -160,11 +160,12 @@ def test_square_config_fp32_10k_steps(slbm):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_result_does_not_depend_on_launch_shape(slbm, prec):
-    """Every site's arithmetic is independent of how rows are split between
-    waves, so any rows-per-wave gives bit-identical state."""
+    """Every site's arithmetic is independent of how rows and columns are
+    split into tiles, so any launch shape gives bit-identical state; shapes
+    beyond the tile limits are refused."""
     p = mixed_plate(150, 97, seed=5, order=1)
     out = []
-    for seg, strip in ((1, 62), (3, 64), (8, 62), (64, 64), (200, 62), (2, 64)):
+    for seg, strip in ((1, 62), (3, 64), (8, 62), (13, 64), (14, 62), (2, 64), (0, 0)):
         s = slbm.Solver(p, prec)
         s.set_launch(seg, strip)
         s.step(37)
@@ -172,6 +173,11 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
     for u, P in out[1:]:
         assert np.array_equal(u, out[0][0])
         assert np.array_equal(P, out[0][1])
+    s = slbm.Solver(p, prec)
+    for seg, strip in ((15, 62), (14, 64), (-1, 62), (4, 63)):
+        with pytest.raises(slbm.SlbmError) as e:
+            s.set_launch(seg, strip)
+        assert e.value.code == -1
 
 
 @pytest.mark.parametrize("shape", [(1, 7), (2, 2), (3, 5), (61, 9), (62, 3), (63, 4), (64, 65), (124, 2), (125, 33)])
