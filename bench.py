@@ -47,49 +47,53 @@ def bytes_per_site(prec):
     return 9 * 2 * (4 if prec == "fp32" else 8) + 2 * 2 * 8
 
 
-def kernel_fingerprint():
-    """SHA-256 of the step kernel's source and the build flags: counter
-    readings are only valid for the kernel they were taken on."""
-    import hashlib
-    from paper_2208_04088_amd import build
-    h = hashlib.sha256()
-    h.update(open(os.path.join(os.path.dirname(build.__file__), "csrc", "step_kernel.h"), "rb").read())
-    h.update(" ".join(build.HIPCC_FLAGS).encode())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(plate, prec, tuned):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary (profiles/traffic_<workload>.json), or None when there is none
-    for this workload and launch shape or the kernel changed since."""
+    summary (profiles/traffic_<workload>_<precision>.json), or None when there
+    is none for this workload and launch shape or the kernel changed since."""
+    from paper_2208_04088_amd.build import kernel_fingerprint
     path = os.path.join(ROOT, "profiles", f"traffic_{plate.name}_{prec}.json")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path))
+    with open(path) as fh:
+        d = json.load(fh)
     if d.get("kernel_fingerprint") != kernel_fingerprint():
         return None
-    if [d.get("rows_per_tile"), d.get("strip_width")] != [tuned[0], tuned[1]]:
-        return None
-    return d.get("traffic_bytes_per_launch")
+    shape = d.get("shapes", {}).get(f"{tuned[0]}x{tuned[1]}")
+    return shape["traffic_bytes_per_launch"] if shape else None
 
 
-def cpu_baseline(plate, budget_s=12.0):
+def cpu_baseline(plate, budget_s=15.0, one_core_s=8.0):
     """The plain CPU reference (fp64) on a bounded number of steps of the
-    same plate, all host threads it is allowed."""
+    same plate, timed with every host thread it is allowed and with one."""
+    import oracle
     from oracle import Oracle
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
-    os.environ["OMP_NUM_THREADS"] = str(cores)
+    cores = oracle.set_threads(0)
     o = Oracle(plate)
-    t = time.perf_counter()
-    o.step(2)
-    per = (time.perf_counter() - t) / 2
-    n = max(2, int(budget_s / max(per, 1e-9)))
-    t = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t
-    return {"value": round(plate.n_material * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle", "sample": f"{n} steps of {plate.name} ({plate.n_material} material sites) "
-                                        f"from rest, fp64, {dt:.1f} s"}
+    o.step(1)
+
+    def rate(seconds):
+        # steps in growing batches until the time budget is spent
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+            k = 1 if n == 0 else max(1, min(int((seconds - el) / (el / n)) + 1, 2 * n))
+            o.step(k)
+            n += k
+        dt = time.perf_counter() - t0
+        return plate.n_material * n / dt / 1e6, n, dt
+
+    v, n, dt = rate(budget_s)
+    oracle.set_threads(1)
+    v1, n1, dt1 = rate(one_core_s)
+    oracle.set_threads(cores)
+    return {"value": round(v, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n} steps of {plate.name} ({plate.n_material} material sites), fp64, "
+                      f"{dt:.1f} s on {cores} threads; then {n1} steps on 1 thread, {dt1:.1f} s",
+            "value_one_core": round(v1, 3)}
 
 
 def main():
@@ -120,12 +124,14 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     assert stream.cuda_stream != 0
     s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
-    s.step(args.warmup)
-    s.sync()
     if args.seg:
         s.set_launch(args.seg, args.strip)
-        tuned = (args.seg, args.strip, None)
+        s.step(args.warmup)
+        s.sync()
+        tuned = (args.seg, args.strip or 62, None)
     else:
+        s.step(args.warmup)
+        s.sync()
         tuned = s.autotune()          # rows per tile and strip width, measured on this plate
 
     torch.cuda.synchronize()

@@ -67,6 +67,8 @@ def _lib(extended: bool):
     L.oracle_set_populations.argtypes = [C.c_void_p, _D]
     L.oracle_lattice_params.argtypes = [C.c_void_p, _D]
     L.oracle_equilibrium.argtypes = [C.c_double, _D, _D, _D]
+    L.oracle_set_threads.argtypes = [C.c_int]
+    L.oracle_set_threads.restype = C.c_int
     _libs[name] = L
     return L
 
@@ -176,3 +178,9 @@ def equilibrium(rho, j, P, extended=False):
     out = np.empty(9)
     L.oracle_equilibrium(float(rho), _ptr(j, _D), _ptr(P, _D), _ptr(out, _D))
     return out
+
+
+def set_threads(n, extended=False):
+    """OpenMP threads of later reference calls (0: the runtime default);
+    returns the number in effect."""
+    return _lib(extended).oracle_set_threads(int(n))

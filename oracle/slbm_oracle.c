@@ -10,6 +10,9 @@
  * or long double with -DORACLE_EXTENDED (used where the comparison needs the
  * small deviation from the rest state resolved to better than fp64 allows).
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "slbm_oracle.h"
 
 #include <math.h>
@@ -554,4 +557,15 @@ void oracle_lattice_params(const oracle_t* o, double* out6)
     out6[3] = o->dt_user;
     out6[4] = o->s_sigma;
     out6[5] = o->s_v;
+}
+
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

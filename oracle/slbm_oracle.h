@@ -87,6 +87,10 @@ void oracle_lattice_params(const oracle_t* o, double* out6);
 /* The equilibrium of eq:fieq in lattice units, P = {xx, yy, xy}. */
 void oracle_equilibrium(double rho, const double* j, const double* P, double* feq9);
 
+/* Number of OpenMP threads later calls may use (0 or less: the runtime's
+ * default).  Returns the number in effect.  Results do not depend on it. */
+int oracle_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,10 +17,22 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # no fused multiply-add contraction: every launch shape and code path
     # rounds the same expressions the same way, so results are bit-identical
-    # whatever the strip width or rows per wave
+    # whatever the strip width or rows per tile
     "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
+
+
+def kernel_fingerprint():
+    """SHA-256 (16 hex digits) of the step kernel's source and the build
+    flags: hardware-counter readings are only valid for the kernel they were
+    taken on (its launch shape is recorded beside them)."""
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(HERE, "csrc", "step_kernel.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()[:16]
 
 
 def build(verbose=False, extra=()):
