@@ -291,6 +291,78 @@ def test_reference_agrees_with_moment_space_formulation(seed):
 
 # ------------------------------------------------- 1-D step traction --
 
+OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+
+
+@pytest.mark.parametrize("kind", ["neumann", "dirichlet"])
+@pytest.mark.parametrize("q_bottom,q_top", [(0.5, 0.5), (0.3, 0.8), (0.9, 0.15)])
+def test_boundary_rules_are_exact_for_linear_fields(kind, q_bottom, q_top):
+    """Section 4.2: the interpolated rules are built so that, for an
+    equilibrium field varying linearly across the wall, the population a cut
+    link returns equals the one the lattice would have streamed in from the
+    virtual site x + c_k had the field continued -- for every q.  For the
+    Neumann rule (j = 0) this needs the linear extrapolation of rho_bd and
+    sigma_tt along the link (neumann_order 1); for the Dirichlet rule, a
+    linear velocity field with the wall velocity at the wall point.  Walls are
+    horizontal lines at y = -q_bottom and y = ny - 1 + q_top."""
+    nx, ny = 6, 5
+    lam = mu = 0.05
+    if kind == "neumann":
+        def fields(y):      # lattice units: rho, j, P (xx, yy, xy)
+            return 1 + 1e-3 + 2e-4 * y, (0.0, 0.0), (3e-4 - 1e-4 * y, 2e-4 + 5e-5 * y, 1e-4 + 3e-5 * y)
+        g_bot = G.BCGroup(G.NEUMANN, (0.0, 0.0))
+        g_top = G.BCGroup(G.NEUMANN, (0.0, 0.0))
+    else:
+        def fields(y):
+            return 1.0, (2e-4 + 1e-4 * y, -3e-4 + 4e-5 * y), (0.0, 0.0, 0.0)
+        g_bot = G.BCGroup(G.DIRICHLET, (0.0, 0.0))
+        g_top = G.BCGroup(G.DIRICHLET, (0.0, 0.0))
+    walls = [G.HLine(-q_bottom, 0), G.HLine(ny - 1 + q_top, 1)]
+    plate0 = G.build_plate(nx, ny, lam=lam, mu=mu, tau=0.55, walls=walls, groups=[g_bot, g_top],
+                           periodic_x=True, neumann_order=1)
+    par = Oracle(plate0).lattice_params()
+    # boundary data of the linear field at the wall points, in user units
+    yb, yt = -q_bottom, ny - 1 + q_top
+    if kind == "neumann":
+        # sigma = -P at lambda = mu; t = sigma.n with n = (0, -1) below, (0, 1) above
+        _, _, Pb = fields(yb)
+        _, _, Pt = fields(yt)
+        g_bot.value = (Pb[2] * par["s_sigma"], Pb[1] * par["s_sigma"])
+        g_top.value = (-Pt[2] * par["s_sigma"], -Pt[1] * par["s_sigma"])
+    else:
+        g_bot.value = tuple(v * par["s_v"] for v in fields(yb)[1])
+        g_top.value = tuple(v * par["s_v"] for v in fields(yt)[1])
+    plate = G.build_plate(nx, ny, lam=lam, mu=mu, tau=0.55, walls=walls, groups=[g_bot, g_top],
+                          periodic_x=True, neumann_order=1)
+    assert sorted(set(plate.links["q"].round(12))) == sorted({round(q_bottom, 12), round(q_top, 12)})
+    o = Oracle(plate)
+    f0 = np.zeros((9, ny, nx))
+    for y in range(ny):
+        r, j, P = fields(y)
+        f0[:, y, :] = equilibrium(r, j, P)[:, None]
+    o.set_populations(f0)
+    o.step(1)
+    f1 = o.populations()
+    scale = np.abs(f0).max()
+    checked = 0
+    for L in plate.links:
+        x, y = int(L["site"]) % nx, int(L["site"]) // nx
+        k = int(L["dir"])
+        r, j, P = fields(y + CY[k])                 # the virtual site x + c_k
+        want = equilibrium(r, j, P)[OPP[k]]
+        assert abs(f1[OPP[k], y, x] - want) <= 1e-13 * scale, (x, y, k)
+        checked += 1
+    assert checked == 2 * 3 * nx
+    if kind == "neumann":
+        # the boundary-site values of rho_bd and sigma_tt (order 0) are not exact
+        plate.neumann_order = 0
+        o0 = Oracle(plate)
+        o0.set_populations(f0)
+        o0.step(1)
+        d = np.abs(o0.populations() - f1).max()
+        assert d > 1e-7 * scale
+
+
 def test_step_traction_launches_the_dilatational_wave():
     """A strip pulled at one end by a step traction sigma0 carries a
     dilatational wave with particle velocity sigma0/(rho c_d) behind the
