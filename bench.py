@@ -7,6 +7,7 @@ the fused kernel.  The default workload is the 1024 x 512 edge-crack plate
 (fp32 populations, fp64 displacement), run for its 10k steps.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
+    python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
 
 Prints one JSON line.  `value` is material-site updates per second (MLUPS)
 with the state resident in HBM; the roofline object relates the fused
@@ -96,10 +97,135 @@ def cpu_baseline(plate, budget_s=15.0, one_core_s=8.0):
             "value_one_core": round(v1, 3)}
 
 
+def copy_ceiling(slbm, torch, dev, stream):
+    """GB/s of the plain copy kernel over a 2 GiB buffer, timed like the step."""
+    src_t = torch.empty(1 << 29, dtype=torch.float32, device=dev)
+    dst_t = torch.empty_like(src_t)
+    nbytes = src_t.numel() * 4
+    for _ in range(3):
+        slbm.copy(dst_t.data_ptr(), src_t.data_ptr(), nbytes, 0, stream.cuda_stream)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        slbm.copy(dst_t.data_ptr(), src_t.data_ptr(), nbytes, 0, stream.cuda_stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    return round(2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
+
+
+def run_batch(args, slbm, torch, dev, stream):
+    """64 independent plates of uneven size and geometry (seed 0), every one
+    advanced `steps` steps: once as one batch (one launch per step for all
+    plates, steps replayed from captured graphs), once one plate at a time
+    with plain launches in each plate's autotuned shape.  Same plates, same
+    arithmetic: the displacements must agree bit for bit."""
+    import numpy as np
+    from slbm_workloads import configs
+    steps = args.steps if args.steps_given else 5000
+    plates = configs.batch_plates(seed=0, count=64, steps=steps)
+    sites = sum(p.n_material for p in plates)
+    tune_shapes = [(2, 62), (4, 62), (6, 62), (10, 62), (14, 62)]
+    chunk = 64
+    warm = chunk * (len(tune_shapes) + 2)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # batched: warm-up steps pick the launch shape, then the timed steps
+    b = slbm.Batch(200 << 30, device=0, stream=stream.cuda_stream)
+    slots = [b.add(p, warm + steps, "fp32") for p in plates]
+    b.step(chunk)
+    best = None
+    for sh in tune_shapes:
+        b.set_launch(*sh)
+        b.step(chunk // 2)                       # tables and graph rebuilt
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        b.step(chunk // 2)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / (chunk // 2)
+        if best is None or t < best[0]:
+            best = (t, sh)
+    b.set_launch(*best[1])
+    b.step(chunk)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - w0
+    t_batch = e0.elapsed_time(e1) / 1e3
+    u_batch, div_batch = [], 0
+    for sl in slots:
+        sv = b.solver(sl)
+        try:
+            sv.sync()
+        except slbm.SlbmError as e:
+            if e.code != -4:
+                raise
+            div_batch += 1
+        u_batch.append(sv.displacement())
+    b.close()
+
+    # one plate at a time: the same warm-up and step counts, plain launches
+    t_seq, div_seq, equal = 0.0, 0, 0
+    for p, ub in zip(plates, u_batch):
+        s = slbm.Solver(p, "fp32", device=0, stream=stream.cuda_stream)
+        s.step(warm)
+        torch.cuda.synchronize()
+        s.autotune()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_seq += e0.elapsed_time(e1) / 1e3
+        try:
+            s.sync()
+        except slbm.SlbmError as e:
+            if e.code != -4:
+                raise
+            div_seq += 1
+        equal += bool(np.array_equal(s.displacement(), ub, equal_nan=True))
+        s.close()
+    mlups = sites * steps / t_batch / 1e6
+    achieved = sites * bytes_per_site("fp32") * steps / t_batch / 1e9
+    result = {
+        "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": round(t_batch / steps * 1e3, 6), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": "batch64-seed0", "plates": len(plates), "material_sites": sites,
+            "precision": "fp32 populations and arithmetic, fp64 displacement",
+            "bench_step": "one lattice-Boltzmann time step of all 64 plates (one batched launch)",
+            "batched_launch_shape": list(best[1]),
+            "sequential_mlups": round(sites * steps / t_seq / 1e6, 1),
+            "speedup_vs_sequential": round(t_seq / t_batch, 3),
+            "plates_bitwise_equal_to_sequential": equal,
+            "diverged_plates": [div_batch, div_seq],
+            "wall_s": round(wall_b, 4),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_step_batch",
+            "bytes_per_site": bytes_per_site("fp32"),
+            "avg_launch_us": round(t_batch / steps * 1e6, 3),
+            "copy_kernel_gbs": copy_ceiling(slbm, torch, dev, stream),
+        },
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(plates[0])
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="crack1024x512")
     ap.add_argument("--precision", default=None)
@@ -112,17 +238,25 @@ def main():
               "decomposition is a design, not a build", file=sys.stderr)
         sys.exit(2)
 
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 10000
+
     import torch
     from paper_2208_04088_amd import slbm
 
-    plate, prec = workload(args.workload)
-    prec = args.precision or prec
     torch.cuda.init()
     dev = torch.device("cuda:0")
     # a stream of torch's (default priority) that the library queues on, so
     # that torch's events time the library's kernels
     stream = torch.cuda.Stream(device=dev)
     assert stream.cuda_stream != 0
+    if args.workload == "batch64":
+        run_batch(args, slbm, torch, dev, stream)
+        return
+
+    plate, prec = workload(args.workload)
+    prec = args.precision or prec
     s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
     if args.seg:
         s.set_launch(args.seg, args.strip)
@@ -213,19 +347,7 @@ def main():
         },
     }
     # streaming reference: a plain copy of a 2 GiB buffer, timed the same way
-    src_t = torch.empty(1 << 29, dtype=torch.float32, device=dev)
-    dst_t = torch.empty_like(src_t)
-    nbytes = src_t.numel() * 4
-    for _ in range(3):
-        slbm.copy(dst_t.data_ptr(), src_t.data_ptr(), nbytes, 0, stream.cuda_stream)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(10):
-        slbm.copy(dst_t.data_ptr(), src_t.data_ptr(), nbytes, 0, stream.cuda_stream)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    result["roofline"]["copy_kernel_gbs"] = round(2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
-    del src_t, dst_t
+    result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
     result["roofline"]["traffic"] = measured_traffic(plate, prec, tuned)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(plate)

@@ -1088,9 +1088,9 @@ int batch_build(slbm_batch_s* b)
 
 int batch_grid(const slbm_batch_s* b)
 {
-    // enough workgroups to fill the machine several times over, tiles walked
-    // in strides of the grid beyond that
-    const int g = std::min(b->ntiles, 256 * 8);
+    // one workgroup per tile (the kernel also walks tiles in strides of the
+    // grid, so a smaller grid stays correct)
+    const int g = b->ntiles;
     return (g + 7) / 8 * 8;
 }
 

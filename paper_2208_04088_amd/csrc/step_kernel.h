@@ -458,6 +458,15 @@ __device__ __forceinline__ bool step_tile(const StepArgs<real>& a, int tile, rea
                               dens[wave + 1][c + 1]);
 }
 
+// Sets the plate's divergence word when any lane of the wave saw a
+// non-finite value: one atomic per wave, none once the word is set (a plate
+// that has blown up would otherwise send an atomic from every site, every
+// step, to one address).
+__device__ __forceinline__ void flag_divergence(unsigned int* word, bool bad)
+{
+    if (__any(bad) && (threadIdx.x & 63) == 0 && *(volatile unsigned int*)word == 0u) atomicOr(word, 1u);
+}
+
 // One time step of one plate: one workgroup of tile_waves(seg) waves per tile.
 template <typename real, bool PER, bool WIDE>
 __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
@@ -465,7 +474,7 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
     __shared__ real dens[kMaxTileRows + 2][66];
     const int tile = xcd_banded(blockIdx.x, gridDim.x);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
-    if (step_tile<real, PER, WIDE>(a, tile, dens)) atomicOr(a.diverged, 1u);
+    flag_divergence(a.diverged, step_tile<real, PER, WIDE>(a, tile, dens));
 }
 
 // Per-plate state of the batched step, in device memory so that a captured
@@ -493,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __r
         const int p = tile_plate[t];
         if (!plates[p].active) continue;         // uniform over the workgroup
         const StepArgs<real> a = plates[p].args;
-        if (step_tile<real, false, WIDE>(a, t - tile_start[p], dens)) atomicOr(a.diverged, 1u);
+        flag_divergence(a.diverged, step_tile<real, false, WIDE>(a, t - tile_start[p], dens));
         __syncthreads();                          // dens is reused by the next tile
     }
 }
