@@ -263,28 +263,33 @@ def build_plate(nx, ny, *, lam, mu, rho=1.0, tau, walls: Sequence, groups: Seque
     return plate
 
 
+def _shifted(m: np.ndarray, dx: int, dy: int, px: bool, py: bool) -> np.ndarray:
+    """out[y, x] = m[y + dy, x + dx], wrapped on periodic axes, False outside."""
+    if px:
+        m = np.roll(m, -dx, axis=1)
+    if py:
+        m = np.roll(m, -dy, axis=0)
+    out = np.zeros_like(m)
+    ny, nx = m.shape
+    ddx = 0 if px else dx
+    ddy = 0 if py else dy
+    ys, yd = (slice(max(ddy, 0), ny + min(ddy, 0)), slice(max(-ddy, 0), ny - max(ddy, 0)))
+    xs, xd = (slice(max(ddx, 0), nx + min(ddx, 0)), slice(max(-ddx, 0), nx - max(ddx, 0)))
+    out[yd, xd] = m[ys, xs]
+    return out
+
+
 def check_plate(p: Plate) -> None:
     """Every uncut link of a material site must end on a material site."""
-    cut = np.zeros((9, p.ny * p.nx), dtype=bool)
-    cut[p.links["dir"], p.links["site"]] = True
-    m = p.mask.ravel().astype(bool)
-    sites = np.flatnonzero(m)
-    x, y = sites % p.nx, sites // p.nx
+    m = p.mask.astype(bool)
+    cut = np.zeros((9, p.ny, p.nx), dtype=bool)
+    cut[p.links["dir"], p.links["site"] // p.nx, p.links["site"] % p.nx] = True
     for k in range(1, 9):
-        tx, ty = x + CX[k], y + CY[k]
-        if p.periodic_x:
-            tx %= p.nx
-        if p.periodic_y:
-            ty %= p.ny
-        inside = (tx >= 0) & (tx < p.nx) & (ty >= 0) & (ty < p.ny)
-        tgt_mat = np.zeros_like(inside)
-        tgt_mat[inside] = m[(ty * p.nx + tx)[inside]]
-        bad = ~cut[k, sites] & ~tgt_mat
+        bad = m & ~cut[k] & ~_shifted(m, CX[k], CY[k], p.periodic_x, p.periodic_y)
         if bad.any():
             raise ValueError(f"{p.name}: {int(bad.sum())} uncut links in direction {k} leave the material")
     # an isolated site (all eight links cut) is not a solid
-    ncut = cut[1:, :].sum(axis=0)
-    if (ncut[sites] == 8).any():
+    if (m & cut[1:].all(axis=0)).any():
         raise ValueError(f"{p.name}: material site with every link cut")
 
 
