@@ -8,6 +8,7 @@ the fused kernel.  The default workload is the 1024 x 512 edge-crack plate
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
     python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
+    python bench.py --workload serve       # served requests: continuous batching vs one at a time
 
 Prints one JSON line.  `value` is material-site updates per second (MLUPS)
 with the state resident in HBM; the roofline object relates the fused
@@ -222,6 +223,52 @@ def run_batch(args, slbm, torch, dev, stream):
     print(json.dumps(result), flush=True)
 
 
+def run_serve(args, slbm, torch, dev, stream):
+    """The first `--requests` requests of the served trace (seed 1, Poisson
+    arrivals at 50/s, plates 256^2-4096^2, 1e3-2e4 steps) under a 200 GB
+    budget: continuous batching (paper_2208_04088_amd.serve.Server) against
+    the same requests one plate at a time.  Latency runs from a request's
+    arrival to its displacement being back on the host."""
+    from paper_2208_04088_amd import serve
+    from slbm_workloads import configs
+    t = time.perf_counter()
+    trace = configs.served_trace(seed=1, count=args.requests)
+    t_build = time.perf_counter() - t
+    work = sum(r.plate.n_material * r.steps for r in trace)
+    srv = serve.Server(200 << 30, chunk=64, stream=stream.cuda_stream, launch=(10, 62))
+    res = srv.run(trace)
+    srv.close()
+    torch.cuda.synchronize()
+    st = serve.summary(res)
+    seq = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False))
+    span = st["makespan_s"]
+    achieved = work * bytes_per_site("fp32") / span / 1e9
+    result = {
+        "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
+        "value": st["aggregate_mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": int(sum(r.steps for r in trace)),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": f"served-trace-seed1-first{args.requests}", "requests": args.requests,
+            "arrival_rate_per_s": 50, "hbm_budget_gb": 200,
+            "precision": "fp32 populations and arithmetic, fp64 displacement",
+            "bench_step": "serve every request of the trace (each plate its own step count)",
+            "served": st, "one_at_a_time": seq,
+            "speedup_vs_one_at_a_time": round(seq["makespan_s"] / span, 3),
+            "peak_resident_plates": srv.peak_resident, "peak_device_gb": round(srv.peak_bytes / 1e9, 2),
+            "trace_build_s": round(t_build, 1),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_step_batch",
+            "bytes_per_site": bytes_per_site("fp32"),
+        },
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(trace[0].plate)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +279,7 @@ def main():
     ap.add_argument("--seg", type=int, default=0, help="rows per tile (0: autotuned)")
     ap.add_argument("--strip", type=int, default=0, help="strip width 62 or 64 (0: autotuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=40, help="served workload: requests of the trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -253,6 +301,9 @@ def main():
     assert stream.cuda_stream != 0
     if args.workload == "batch64":
         run_batch(args, slbm, torch, dev, stream)
+        return
+    if args.workload == "serve":
+        run_serve(args, slbm, torch, dev, stream)
         return
 
     plate, prec = workload(args.workload)

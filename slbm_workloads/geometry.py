@@ -204,9 +204,12 @@ def build_plate(nx, ny, *, lam, mu, rho=1.0, tau, walls: Sequence, groups: Seque
     near = np.zeros((ny, nx), dtype=bool)
     for w in walls:
         if isinstance(w, Circle):
+            # links are at most sqrt(2) long: only sites within 2 cells of the circle
             y0, y1 = max(int(np.floor(w.cy - w.R)) - 2, 0), min(int(np.ceil(w.cy + w.R)) + 3, ny)
             x0, x1 = max(int(np.floor(w.cx - w.R)) - 2, 0), min(int(np.ceil(w.cx + w.R)) + 3, nx)
-            near[y0:y1, x0:x1] = True
+            yy, xx = np.mgrid[y0:y1, x0:x1]
+            d = np.sqrt((xx - w.cx) ** 2 + (yy - w.cy) ** 2)
+            near[y0:y1, x0:x1] |= np.abs(d - w.R) <= 2.0
         elif isinstance(w, HLine):
             y0, y1 = max(int(np.floor(w.y0)) - 1, 0), min(int(np.ceil(w.y0)) + 2, ny)
             x0 = max(int(np.floor(max(w.x_lo, -1e9))) - 2, 0)

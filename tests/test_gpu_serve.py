@@ -1,0 +1,81 @@
+"""Serving loop (continuous batching under an HBM budget): every result is
+the same alone and in the mix, the budget holds, and requests that arrive
+while others run are admitted as memory frees up."""
+import numpy as np
+import pytest
+
+from slbm_workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2208_04088_amd import serve, slbm
+    slbm.lib()
+    return serve, slbm
+
+
+def small_trace(seed, count, rate):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        steps = int(rng.integers(20, 160))
+        p = configs._random_plate(rng, area_lo=24 ** 2, area_hi=140 ** 2, load=rng.uniform(1e-4, 1e-3),
+                                  steps=steps, name=f"serve{seed}-{i}")
+        out.append(configs.Request(t, p, steps))
+    return out
+
+
+def test_results_are_the_same_alone_and_in_the_mix(mods):
+    serve, slbm = mods
+    trace = small_trace(2, 14, rate=400.0)
+    sizes = []
+    for r in trace:
+        s = slbm.Solver(r.plate, "fp32")
+        sizes.append(s.device_bytes())
+        s.close()
+    budget = int(3.5 * max(sizes))             # a few plates at a time: the rest queue
+    srv = serve.Server(budget, chunk=16)
+    res = srv.run(trace, keep_results=True)
+    srv.close()
+    assert all(r is not None and not r.rejected for r in res)
+    assert srv.peak_bytes <= budget
+    assert srv.peak_resident >= 2
+    assert max(r.wait for r in res) > 0        # some requests queued behind others
+    for r, q in zip(res, trace):
+        assert r.admitted >= r.arrival - 1e-9 and r.finished >= r.admitted
+        s = slbm.Solver(q.plate, "fp32")
+        s.step(q.steps)
+        try:
+            s.sync()
+        except slbm.SlbmError:
+            pass
+        assert np.array_equal(r.u, s.displacement(), equal_nan=True), q.plate.name
+        s.close()
+    st = serve.summary(res)
+    assert st["requests"] == len(trace) and st["p99_latency_s"] >= st["p50_latency_s"] > 0
+
+
+def test_one_at_a_time_gives_the_same_results(mods):
+    serve, slbm = mods
+    trace = small_trace(4, 5, rate=1000.0)
+    a = serve.run_one_at_a_time(trace, keep_results=True)
+    srv = serve.Server(1 << 30, chunk=32)
+    b = srv.run(trace, keep_results=True)
+    srv.close()
+    for x, y in zip(a, b):
+        assert np.array_equal(x.u, y.u, equal_nan=True)
+
+
+def test_request_larger_than_the_budget_is_rejected(mods):
+    serve, slbm = mods
+    trace = small_trace(6, 3, rate=1000.0)
+    srv = serve.Server(1 << 16, chunk=16)     # 64 KiB: nothing fits
+    res = srv.run(trace)
+    srv.close()
+    assert all(r.rejected for r in res)
