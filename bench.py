@@ -227,7 +227,8 @@ def run_serve(args, slbm, torch, dev, stream):
     """The first `--requests` requests of the served trace (seed 1, Poisson
     arrivals at 50/s, plates 256^2-4096^2, 1e3-2e4 steps) under a 200 GB
     budget: continuous batching (paper_2208_04088_amd.serve.Server) against
-    the same requests one plate at a time.  Latency runs from a request's
+    the same requests one plate at a time (oldest first, and least work
+    first).  Latency runs from a request's
     arrival to its displacement being back on the host."""
     from paper_2208_04088_amd import serve
     from slbm_workloads import configs
@@ -235,12 +236,15 @@ def run_serve(args, slbm, torch, dev, stream):
     trace = configs.served_trace(seed=1, count=args.requests)
     t_build = time.perf_counter() - t
     work = sum(r.plate.n_material * r.steps for r in trace)
-    srv = serve.Server(200 << 30, chunk=64, stream=stream.cuda_stream, launch=(10, 62))
+    srv = serve.Server(200 << 30, chunk=64, stream=stream.cuda_stream, launch=(10, 62),
+                       max_resident_sites=2_000_000, policy="swf")
     res = srv.run(trace)
     srv.close()
     torch.cuda.synchronize()
     st = serve.summary(res)
     seq = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False))
+    seq_swf = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False,
+                                                    policy="swf"))
     span = st["makespan_s"]
     achieved = work * bytes_per_site("fp32") / span / 1e9
     result = {
@@ -253,7 +257,8 @@ def run_serve(args, slbm, torch, dev, stream):
             "arrival_rate_per_s": 50, "hbm_budget_gb": 200,
             "precision": "fp32 populations and arithmetic, fp64 displacement",
             "bench_step": "serve every request of the trace (each plate its own step count)",
-            "served": st, "one_at_a_time": seq,
+            "policy": "least work first, at most 2M material sites resident (more when one plate is larger)",
+            "served": st, "one_at_a_time": seq, "one_at_a_time_least_work_first": seq_swf,
             "speedup_vs_one_at_a_time": round(seq["makespan_s"] / span, 3),
             "peak_resident_plates": srv.peak_resident, "peak_device_gb": round(srv.peak_bytes / 1e9, 2),
             "trace_build_s": round(t_build, 1),

@@ -170,6 +170,15 @@ __global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double*
     }
 }
 
+// One padded plane into an unpadded, contiguous [ny][nx] array.
+__global__ __launch_bounds__(256) void k_unpad(const double* plane, int nx, int ny, int ld, double* dst)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nx * ny) return;
+    const int y = idx / nx, x = idx - y * nx;
+    dst[idx] = plane[sidx(x, y, ld)];
+}
+
 // Displacement into a caller's unpadded [2][ny][nx] device array.
 __global__ __launch_bounds__(256) void k_unpad_u(const double* out, int nx, int ny, int ld, double* u)
 {
@@ -680,12 +689,16 @@ int create_impl(const slbm_params* p, slbm_handle* out)
 
 int copy_out(slbm_s* h, int comp, double scale, double offset, double* dst)
 {
-    // lattice field comp of scratch (after outputs()) -> unpadded host array
-    const double* src = h->scratch + (size_t)(1 + comp) * h->plane + sidx(0, 0, h->ld);
-    HIP_TRY(hipMemcpy2DAsync(dst, (size_t)h->nx * sizeof(double), src, (size_t)h->ld * sizeof(double),
-                             (size_t)h->nx * sizeof(double), h->ny, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    // lattice field comp of scratch (after outputs()) -> unpadded host array:
+    // unpadded on the device into scratch plane 0 (the density, no longer
+    // needed once the output kernels ran), then one contiguous copy
     const int n = h->nx * h->ny;
+    hipLaunchKernelGGL(k_unpad, dim3((n + 255) / 256), dim3(256), 0, h->stream,
+                       (const double*)(h->scratch + (size_t)(1 + comp) * h->plane), h->nx, h->ny, h->ld,
+                       h->scratch);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(dst, h->scratch, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     for (int s = 0; s < n; ++s) dst[s] = h->mask[s] ? dst[s] * scale + offset : 0.0;
     return SLBM_OK;
 }

@@ -164,6 +164,8 @@ def _random_plate(rng: np.random.Generator, *, area_lo: float, area_hi: float,
     while len(holes) < n_holes and tries < 200:
         tries += 1
         R = rng.uniform(0.05, 0.2) * nx
+        if nx - 1 - R - 3 <= R + 3 or ny - 1 - R - 3 <= R + 3:
+            continue                   # no room for this radius (small plates)
         cx = rng.uniform(R + 3, nx - 1 - R - 3)
         cy = rng.uniform(R + 3, ny - 1 - R - 3)
         if cx - R < 3 or cy - R < 3 or cy + R > ny - 4 or cx + R > nx - 4:

@@ -61,15 +61,22 @@ def test_results_are_the_same_alone_and_in_the_mix(mods):
     assert st["requests"] == len(trace) and st["p99_latency_s"] >= st["p50_latency_s"] > 0
 
 
-def test_one_at_a_time_gives_the_same_results(mods):
+@pytest.mark.parametrize("policy", ["fcfs", "swf"])
+def test_policies_give_the_same_results(mods, policy):
     serve, slbm = mods
-    trace = small_trace(4, 5, rate=1000.0)
-    a = serve.run_one_at_a_time(trace, keep_results=True)
-    srv = serve.Server(1 << 30, chunk=32)
+    trace = small_trace(4, 6, rate=1000.0)
+    a = serve.run_one_at_a_time(trace, keep_results=True, policy=policy)
+    cap = max(r.plate.n_material for r in trace) * 2
+    srv = serve.Server(1 << 30, chunk=32, max_resident_sites=cap, policy=policy)
     b = srv.run(trace, keep_results=True)
     srv.close()
     for x, y in zip(a, b):
         assert np.array_equal(x.u, y.u, equal_nan=True)
+    if policy == "swf":
+        # with every request waiting at once, the least work is served first
+        work = [r.plate.n_material * r.steps for r in trace]
+        first = min(range(len(trace)), key=lambda i: a[i].admitted)
+        assert work[first] == min(work[i] for i in range(len(trace)) if trace[i].arrival <= a[first].admitted)
 
 
 def test_request_larger_than_the_budget_is_rejected(mods):
