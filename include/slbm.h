@@ -156,9 +156,9 @@ int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 /* Launch shape of the fused step.  A workgroup advances a tile of seg_rows
  * rows (one wave per row, plus two waves for the density-halo rows) of one
  * strip of columns; strip is the strip width (62: two halo lanes per wave;
- * 64: aligned columns, one more wave for the halo columns).  seg_rows is at
- * most 14 (62) or 13 (64); 0 keeps the library's choice for either.
- * SLBM_E_INVAL beyond the limits.  Results do not depend on the shape. */
+ * 64: aligned columns, the halo columns gathered by each wave).  seg_rows is
+ * at most 14; 0 keeps the library's choice for either.  SLBM_E_INVAL beyond
+ * the limits.  Results do not depend on the shape. */
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
 
 /* Times the fused step on this plate for each strip width and a range of
@@ -213,9 +213,9 @@ int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps);
 /* Frees the plate (its slot and budget are reused). */
 int slbm_batch_remove(slbm_batch b, int32_t slot);
 
-/* Launch shape of the batched step, for every plate: rows per tile (1..14
- * with strip 62, 1..13 with strip 64) as in slbm_set_launch.  SLBM_E_INVAL
- * beyond the limits. */
+/* Launch shape of the batched step, for every plate: rows per tile (1..14)
+ * and strip width (62 or 64) as in slbm_set_launch.  SLBM_E_INVAL beyond the
+ * limits. */
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
 
 int slbm_batch_sync(slbm_batch b);

@@ -866,7 +866,7 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
     if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
     if (strip != 0 && strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 0, 62 or 64");
     if (seg_rows > (strip == 64 ? max_tile_rows<true>() : max_tile_rows<false>()))
-        return fail(SLBM_E_INVAL, "rows per tile above the maximum (14 narrow, 13 wide)");
+        return fail(SLBM_E_INVAL, "rows per tile above the maximum (14)");
     h->seg = seg_rows;
     h->wide = strip == 0 ? -1 : (strip == 64 ? 1 : 0);
     return SLBM_OK;
@@ -1293,7 +1293,7 @@ int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
     if (!b) return fail(SLBM_E_INVAL, "null batch");
     if (strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 62 or 64");
     if (rows < 1 || rows > (strip == 64 ? max_tile_rows<true>() : max_tile_rows<false>()))
-        return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] (narrow) or [1, 13] (wide)");
+        return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14]");
     b->rows = rows;
     b->wide = strip == 64 ? 1 : 0;
     b->dirty = true;

@@ -25,8 +25,8 @@ __host__ __device__ constexpr double WD(int i) { return i == 0 ? 4.0 / 9.0 : (i 
 constexpr int kPadL = 64;      // padding columns left of the grid: keeps wide strips 256-byte aligned
 
 // Two strip shapes for the fused step (the autotuner picks per plate):
-//   wide   64 output columns per wave, 256-byte aligned; one extra wave of the
-//          workgroup supplies the densities of the two halo columns;
+//   wide   64 output columns per wave, 256-byte aligned; each wave also
+//          gathers the densities of the two halo columns (HaloGather);
 //   narrow 62 output columns per wave (lanes 1..62); lanes 0 and 63 sit on
 //          the halo columns and only supply density.
 template <bool WIDE> constexpr int strip_width() { return WIDE ? 64 : 62; }
@@ -406,20 +406,98 @@ __device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int
 //
 // A workgroup advances a tile of R rows (R <= kMaxTileRows) of one strip: one
 // wave per output row plus two waves for the density-halo rows below and
-// above the tile (and, for wide strips, one wave for the halo columns).
+// above the tile.
 // Every wave issues all loads of its row at once, completes the pulls with
 // the boundary rules and puts the density in LDS; after a barrier the output
 // waves read the 3x3 density stencil of the source term from LDS and collide.
 constexpr int kMaxTileRows = 14;
 
-template <bool WIDE> constexpr int tile_waves(int rows) { return rows + 2 + (WIDE ? 1 : 0); }
-template <bool WIDE> constexpr int max_tile_rows() { return WIDE ? kMaxTileRows - 1 : kMaxTileRows; }
+template <bool WIDE> constexpr int tile_waves(int rows) { return rows + 2; }
+template <bool WIDE> constexpr int max_tile_rows() { return kMaxTileRows; }
 
 // Workgroups are dealt round-robin to the 8 XCDs; this gives each XCD a
 // contiguous band of tile numbers so that the halo rows and columns tiles
 // share stay in one L2.  nb (the grid size) is a multiple of 8.
 __device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
+// Site coordinates of a halo or row site: wrapped on periodic axes, clamped
+// into the grid (so that every pull address stays in the allocation) and
+// marked outside otherwise.
+template <bool PER>
+__device__ __forceinline__ void place(int nx, int ny, int px, int py, int& x, int& y, bool& in)
+{
+    in = true;
+    if (x < 0 || x >= nx) {
+        if (PER && px) x = x < 0 ? x + nx : x - nx;
+        if (x < 0 || x >= nx) {
+            in = false;
+            x = x < 0 ? 0 : nx - 1;
+        }
+    }
+    if (y < 0 || y >= ny) {
+        if (PER && py) {
+            y = y < 0 ? y + ny : y - ny;
+        } else {
+            in = false;
+            y = y < 0 ? 0 : ny - 1;
+        }
+    }
+}
+
+// Densities of the two halo columns of a wide strip in row y (left: column
+// xs - 1, right: xs + 64).  Lanes 0-8 pull the nine populations of the left
+// site, lanes 32-40 those of the right one (one load each), and the sums are
+// formed in the order site_finish uses, so they equal what the wave owning
+// the site computes.  A halo site with cut links takes the full site path
+// (boundary rules), all lanes of a half-wave on its side.
+template <typename real, bool PER>
+struct HaloGather {
+    real v;
+    unsigned fl;
+    int x, y;
+    bool in;
+
+    __device__ __forceinline__ void issue(const StepArgs<real>& a, int lane, int xs, int yrow)
+    {
+        const int side = lane >> 5, i = lane & 31;
+        const int d = i < 9 ? i : 0;
+        x = side ? xs + 64 : xs - 1;
+        y = yrow;
+        place<PER>(a.nx, a.ny, a.px, a.py, x, y, in);
+        const int hs = sidx(x, y, a.ld);
+        fl = ldu(a.flags, hs);
+        const int off = a.local ? hs : wrap_off<PER>(x, y, -CX(d), -CY(d), a.nx, a.ny, a.ld, a.px, a.py);
+        v = ldg(a.src + d * a.plane, off);
+    }
+
+    __device__ __forceinline__ void finish(const StepArgs<real>& a, int lane, int xs, int yrow, real& dl, real& dr)
+    {
+        const unsigned fl_l = __shfl(fl, 0), fl_r = __shfl(fl, 32);
+        const bool live_l = __shfl((int)in, 0) && fl_l != kVoid;
+        const bool live_r = __shfl((int)in, 32) && fl_r != kVoid;
+        real sl = __shfl(v, 0), sr = __shfl(v, 32);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            sl += __shfl(v, i);
+            sr += __shfl(v, 32 + i);
+        }
+        dl = live_l ? sl : real(0);
+        dr = live_r ? sr : real(0);
+        const bool slow_l = live_l && fl_l != 0 && !a.local, slow_r = live_r && fl_r != 0 && !a.local;
+        if (slow_l || slow_r) {
+            real g[9];
+            unsigned f;
+            bool in2;
+            int ys2, s2;
+            const int hx = (lane >> 5) ? xs + 64 : xs - 1;
+            site_issue<real, PER>(a, hx, yrow, g, f, ys2, in2, s2);
+            const real d = site_finish<real, PER>(a, hx, ys2, in2, true, f, g);
+            const real d_l = __shfl(d, 0), d_r = __shfl(d, 32);
+            if (slow_l) dl = d_l;
+            if (slow_r) dr = d_r;
+        }
+    }
+};
 
 template <typename real, bool PER, bool WIDE>
 __device__ __forceinline__ bool step_tile(const StepArgs<real>& a, int tile, real (*dens)[66])
@@ -427,29 +505,31 @@ __device__ __forceinline__ bool step_tile(const StepArgs<real>& a, int tile, rea
     constexpr int W = strip_width<WIDE>();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int R = a.seg;
-    const int strip = tile % a.nstrips;
+    const int strip = tile % a.nstrips;            // strip fastest: rows stream through memory in order
     const int y0 = (tile / a.nstrips) * R;
     const int xs = strip * W;                      // first output column of the strip
-    // row waves: row y0 - 1 + wave, narrow strips with the halo columns on
-    // lanes 0 and 63; the halo-column wave of a wide strip: lane 2r + side is
-    // the site left (side 0) or right (side 1) of the strip in row y0 - 1 + r
-    const bool roww = !WIDE || wave < R + 2;
-    const int hr = lane >> 1, side = lane & 1;
-    const bool hcol = !roww && hr < R + 2;
-    const int x = roww ? (WIDE ? xs + lane : xs - 1 + lane) : (side ? xs + W : xs - 1);
-    const int y = y0 - 1 + (roww ? wave : (hcol ? hr : 0));
+    // wave w holds row y0 - 1 + w; narrow strips put the halo columns on
+    // lanes 0 and 63, wide ones gather them (HaloGather)
+    const int x = WIDE ? xs + lane : xs - 1 + lane;
+    const int y = y0 - 1 + wave;
     real g[9];
     unsigned fl;
     bool in;
     int ys, s;
     site_issue<real, PER>(a, x, y, g, fl, ys, in, s);
+    HaloGather<real, PER> hg;
+    if constexpr (WIDE) hg.issue(a, lane, xs, y);
     const double ux = ldu(a.U, s), uy = ldu(a.U + a.plane, s);
-    const real d = site_finish<real, PER>(a, x, ys, in, true, fl, g);
     const int c = WIDE ? lane + 1 : lane;
-    if (roww) dens[wave][c] = d;
-    else if (hcol) dens[hr][side ? W + 1 : 0] = d;
+    dens[wave][c] = site_finish<real, PER>(a, x, ys, in, true, fl, g);
+    if constexpr (WIDE) {
+        real dl, dr;
+        hg.finish(a, lane, xs, y, dl, dr);
+        if (lane == 0) dens[wave][0] = dl;
+        if (lane == 63) dens[wave][W + 1] = dr;
+    }
     __syncthreads();
-    const bool out = roww && wave >= 1 && wave <= R && y < a.ny && x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
+    const bool out = wave >= 1 && wave <= R && y < a.ny && x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
     if (!out || fl == kVoid) return false;
     Window<real> w;
     w.m = dens[wave - 1][c]; w.m_l = dens[wave - 1][c - 1]; w.m_r = dens[wave - 1][c + 1];
