@@ -156,13 +156,17 @@ int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 /* Launch shape of the fused step.  A workgroup advances a tile of seg_rows
  * rows (one wave per row, plus two waves for the density-halo rows) of one
  * strip of columns; strip is the strip width (62: two halo lanes per wave;
- * 64: aligned columns, the halo columns gathered by each wave).  seg_rows is
- * at most 14; 0 keeps the library's choice for either.  SLBM_E_INVAL beyond
- * the limits.  Results do not depend on the shape. */
+ * 64: aligned columns, the halo columns gathered by each wave).  strip 58
+ * takes two time steps per launch: the tile's first step is kept in LDS and
+ * the state is read and written once per two steps (seg_rows + 6 waves per
+ * tile, 58 output columns; an odd step count ends with one single step).
+ * seg_rows is at most 14 (10 with strip 58); 0 keeps the library's choice.
+ * SLBM_E_INVAL beyond the limits.  Results do not depend on the shape. */
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
 
-/* Times the fused step on this plate for each strip width and a range of
- * rows per tile (short bursts of launches, the state restored after each)
+/* Times the fused step on this plate for each strip width (62, 64 and the
+ * two-steps-per-launch 58) and a range of rows per tile (short bursts of
+ * launches, the state restored after each)
  * and keeps the fastest; reports it and its time per step in microseconds
  * (any pointer may be NULL).  Synchronises.  The state and step count are
  * unchanged. */

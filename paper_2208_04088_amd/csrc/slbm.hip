@@ -270,6 +270,7 @@ struct slbm_s {
     bool local = true;
     int seg = 0;
     int wide = -1;                   // strip shape: 1 wide, 0 narrow, -1 library default
+    int two = 0;                     // 1: two steps per launch (58-column strips, seg rows <= 10)
     std::vector<uint8_t> mask;
 };
 
@@ -353,6 +354,52 @@ int launch_step_raw(slbm_s* h, int seg, int wide)
     dispatch_step<real>(h, a);
     h->wide = keepw;
     HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
+// Arguments of the two-steps-per-launch kernel: 58-column strips, at most
+// kMaxTileRows2 rows per tile.
+template <typename real>
+StepArgs<real> make_args2(const slbm_s* h, int src, int seg)
+{
+    StepArgs<real> a = make_args<real>(h, src);
+    a.seg = std::max(1, std::min(seg > 0 ? seg : 6, kMaxTileRows2));
+    a.nstrips = (h->nx + kStrip2 - 1) / kStrip2;
+    a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
+    return a;
+}
+
+template <typename real>
+void dispatch_step2(const slbm_s* h, const StepArgs<real>& a)
+{
+    const int grid = ((a.ntiles + 7) / 8) * 8;
+    const dim3 blk(64 * (a.seg + 6));
+    if (h->px || h->py)
+        hipLaunchKernelGGL((k_step2<real, true>), dim3(grid), blk, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_step2<real, false>), dim3(grid), blk, 0, h->stream, a);
+}
+
+// Two steps in one launch, not committed (autotuner trials; see launch_step_raw).
+template <typename real>
+int launch_step2_raw(slbm_s* h, int seg)
+{
+    StepArgs<real> a = make_args2<real>(h, h->cur, seg);
+    a.local = 0;
+    dispatch_step2<real>(h, a);
+    HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
+template <typename real>
+int launch_step2(slbm_s* h)
+{
+    StepArgs<real> a = make_args2<real>(h, h->cur, h->seg);
+    dispatch_step2<real>(h, a);
+    HIP_TRY(hipGetLastError());
+    h->cur ^= 1;
+    h->local = false;
+    h->step += 2;
     return SLBM_OK;
 }
 
@@ -733,7 +780,14 @@ int slbm_step(slbm_handle h, int64_t nsteps)
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
     DeviceGuard dg(h->device);
-    for (int64_t i = 0; i < nsteps; ++i) {
+    int64_t i = 0;
+    if (h->two) {
+        for (; i + 2 <= nsteps; i += 2) {
+            int rc = h->precision == SLBM_FP32 ? launch_step2<float>(h) : launch_step2<double>(h);
+            if (rc) return rc;
+        }
+    }
+    for (; i < nsteps; ++i) {
         int rc = h->precision == SLBM_FP32 ? launch_step<float>(h) : launch_step<double>(h);
         if (rc) return rc;
     }
@@ -864,11 +918,13 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
 {
     if (!h) return fail(SLBM_E_INVAL, "null handle");
     if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
-    if (strip != 0 && strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 0, 62 or 64");
-    if (seg_rows > (strip == 64 ? max_tile_rows<true>() : max_tile_rows<false>()))
-        return fail(SLBM_E_INVAL, "rows per tile above the maximum (14)");
+    if (strip != 0 && strip != 62 && strip != 64 && strip != kStrip2)
+        return fail(SLBM_E_INVAL, "strip must be 0, 58, 62 or 64");
+    if (seg_rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
+        return fail(SLBM_E_INVAL, "rows per tile above the maximum (14; 10 with two steps per launch)");
     h->seg = seg_rows;
-    h->wide = strip == 0 ? -1 : (strip == 64 ? 1 : 0);
+    h->two = strip == kStrip2 ? 1 : 0;
+    h->wide = (strip == 0 || strip == kStrip2) ? -1 : (strip == 64 ? 1 : 0);
     return SLBM_OK;
 }
 
@@ -917,15 +973,39 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
         const double us = 1e3 * t[0];
         if (us < best_us) { best_us = us; best = c; best_w = wv; }
     }
+    // two steps per launch: bursts of three launches, time per step
+    const int cand2[] = {2, 4, 6, 8, 10};
+    for (int c : cand2) {
+        if (c > std::max(2, h->ny)) break;
+        constexpr int kBurst2 = 3;
+        std::vector<float> t;
+        for (int r = 0; r < 3; ++r) {
+            HIP_TRY(hipEventRecord(e0, h->stream));
+            for (int q = 0; q < kBurst2; ++q) {
+                rc = h->precision == SLBM_FP32 ? launch_step2_raw<float>(h, c) : launch_step2_raw<double>(h, c);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipEventRecord(e1, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) t.push_back(ms / (2 * kBurst2));
+        }
+        std::sort(t.begin(), t.end());
+        const double us = 1e3 * t[0];
+        if (us < best_us) { best_us = us; best = c; best_w = 2; }
+    }
     HIP_TRY(hipMemcpyAsync(h->diverged, flag_saved, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release_transient_scratch(h);
     h->seg = best;
-    h->wide = best_w;
+    h->two = best_w == 2 ? 1 : 0;
+    h->wide = best_w == 2 ? -1 : best_w;
     if (seg_out) *seg_out = best;
-    if (strip_out) *strip_out = best_w ? 64 : 62;
+    if (strip_out) *strip_out = best_w == 2 ? kStrip2 : (best_w ? 64 : 62);
     if (us_out) *us_out = best_us;
     return SLBM_OK;
 }

@@ -165,14 +165,47 @@ __device__ __forceinline__ int wrap_off(int x, int y, int dx, int dy, int nx, in
     return sidx(xx, yy, ld);
 }
 
-// Moments of the post-collision populations stored at site offset s.
+// The previous step's post-collision populations around a site, read as
+// prev(i, dx, dy) = population i at (x + dx, y + dy): from the state buffer in
+// global memory (wrapped on periodic axes) ...
+template <typename real, bool PER>
+struct GlobalPrev {
+    const real* src;
+    long long plane;
+    int x, y, nx, ny, ld, px, py;
+    __device__ __forceinline__ real operator()(int i, int dx, int dy) const
+    {
+        return ldg(src + i * plane, wrap_off<PER>(x, y, dx, dy, nx, ny, ld, px, py));
+    }
+    // all nine populations at one site (plane bases uniform over the wave)
+    __device__ __forceinline__ void all(int dx, int dy, real h[9]) const
+    {
+        const int off = wrap_off<PER>(x, y, dx, dy, nx, ny, ld, px, py);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) h[j] = ldu(src + j * plane, off);
+    }
+};
+
+// ... or from a tile of them in LDS, post[row][i][lane] (two-step kernel).
 template <typename real>
-__device__ __forceinline__ void stored_moments(const StepArgs<real>& a, int s, real& dr,
-                                               real& pxx, real& pyy, real& pxy)
+struct LdsPrev {
+    const real (*post)[9][64];
+    int r, l;
+    __device__ __forceinline__ real operator()(int i, int dx, int dy) const { return post[r + dy][i][l + dx]; }
+    __device__ __forceinline__ void all(int dx, int dy, real h[9]) const
+    {
+#pragma unroll
+        for (int j = 0; j < 9; ++j) h[j] = post[r + dy][j][l + dx];
+    }
+};
+
+// Moments of the post-collision populations at (x + dx, y + dy).
+template <typename real, class Prev>
+__device__ __forceinline__ void stored_moments(const Prev& prev, int dx, int dy, real& dr, real& pxx, real& pyy,
+                                               real& pxy)
 {
     real h[9];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) h[j] = ldu(a.src + j * a.plane, s);
+    prev.all(dx, dy, h);
     real jx, jy;
     moments9(h, dr, jx, jy, pxx, pyy, pxy);
 }
@@ -180,22 +213,18 @@ __device__ __forceinline__ void stored_moments(const StepArgs<real>& a, int s, r
 // The boundary rule of section 4 for the cut link (x, k): the population
 // arriving at x in direction kbar at the current step, from the post-collision
 // state of the previous step (time t_prev).
-template <typename real, bool PER>
-__device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, int x, int y, int s,
+template <typename real, class Prev>
+__device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, const Prev& prev, long long t_prev,
                                real drx, real pxxx, real pyyx, real pxyx)
 {
     const int k = L.k, kb = OPP(k);
-    const real gk = ldg(a.src + k * a.plane, s);
-    const real gkb = ldg(a.src + kb * a.plane, s);
-    int sb = 0;
+    const real gk = prev(k, 0, 0);
+    const real gkb = prev(kb, 0, 0);
     real gky = real(0);
-    if (L.behind) {
-        sb = wrap_off<PER>(x, y, -L.dx, -L.dy, a.nx, a.ny, a.ld, a.px, a.py);
-        gky = ldg(a.src + k * a.plane, sb);
-    }
+    if (L.behind) gky = prev(k, -L.dx, -L.dy);
     if (L.kind == SLBM_DIRICHLET) {
         // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
-        const real p = profile_at<real>(a.groups, L.g1, a.t_prev);
+        const real p = profile_at<real>(a.groups, L.g1, t_prev);
         return gk + L.kappa * (gky - gkb) + L.D * (real(1) + drx) * p;
     }
     // eq:abbcon / eq:abbnoncon.  Cauchy stress from the Poisson stress with the
@@ -206,13 +235,13 @@ __device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, 
                        - real(2) * L.E3[2] * pxyx);
     if (L.wy != real(0)) {
         real dry, pxxy, pyyy, pxyy;
-        stored_moments(a, sb, dry, pxxy, pyyy, pxyy);
+        stored_moments<real>(prev, -L.dx, -L.dy, dry, pxxy, pyyy, pxyy);
         drbd += L.wy * dry;
         stt += L.wy * (L.E3[0] * (-pxxy - a.lm * dry) + L.E3[1] * (-pyyy - a.lm * dry)
                        - real(2) * L.E3[2] * pxyy);
     }
-    const real p1 = profile_at<real>(a.groups, L.g1, a.t_prev);
-    const real p2 = L.g2 >= 0 ? profile_at<real>(a.groups, L.g2, a.t_prev) : real(0);
+    const real p1 = profile_at<real>(a.groups, L.g1, t_prev);
+    const real p2 = L.g2 >= 0 ? profile_at<real>(a.groups, L.g2, t_prev) : real(0);
     // boundary Cauchy stress (eq:trafocauchy) and Poisson stress (eq:bcchainneum)
     const real sxx = p1 * L.K1[0] + p2 * L.K2[0] + stt * L.E3[0];
     const real syy = p1 * L.K1[1] + p2 * L.K2[1] + stt * L.E3[1];
@@ -223,25 +252,32 @@ __device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, 
     return -gk - L.kappa * (gky + gkb) + L.be[0] * drbd + L.be[1] * Pxx + L.be[2] * Pyy + L.be[3] * Pxy;
 }
 
-// Replaces the populations of cut links of a boundary site by the section 4
-// rules.  g already holds the pulls along uncut links.
-template <typename real, bool PER>
-__device__ void boundary_fixup(const StepArgs<real>& a, int x, int y, int s, unsigned fl, real g[9])
+// Replaces the populations of cut links of a boundary site (grid offset s) by
+// the section 4 rules.  g already holds the pulls along uncut links.
+template <typename real, class Prev>
+__device__ void boundary_fixup(const StepArgs<real>& a, const Prev& prev, int s, unsigned fl, long long t_prev,
+                               real g[9])
 {
     real drx, pxxx, pyyx, pxyx;
-    stored_moments(a, s, drx, pxxx, pyyx, pxyx);
+    stored_moments<real>(prev, 0, 0, drx, pxxx, pyyx, pxyx);
     int li = ldu(a.bidx, s);
     unsigned m = fl;
     while (m) {
         const int k = __builtin_ctz(m) + 1;
         m &= m - 1;
         const LinkDev<real> L = a.links[li++];
-        const real v = boundary_value<real, PER>(a, L, x, y, s, drx, pxxx, pyyx, pxyx);
+        const real v = boundary_value<real>(a, L, prev, t_prev, drx, pxxx, pyyx, pxyx);
         const int i = OPP(k);
 #pragma unroll
         for (int j = 1; j < 9; ++j)
             if (j == i) g[j] = v;
     }
+}
+
+template <typename real, bool PER>
+__device__ __forceinline__ GlobalPrev<real, PER> global_prev(const StepArgs<real>& a, int x, int y)
+{
+    return GlobalPrev<real, PER>{a.src, a.plane, x, y, a.nx, a.ny, a.ld, a.px, a.py};
 }
 
 // Populations at site (x, y) for the current step (x, y in the grid, wrapped
@@ -261,8 +297,36 @@ __device__ __forceinline__ bool fetch_site(const StepArgs<real>& a, int x, int y
     for (int i = 0; i < 9; ++i)
         g[i] = a.local ? ldu(a.src + i * a.plane, s)
                        : ldu(a.src + i * a.plane, wrap_off<PER>(x, y, -CX(i), -CY(i), a.nx, a.ny, a.ld, a.px, a.py));
-    if (!a.local && fl != 0) boundary_fixup<real, PER>(a, x, y, s, fl, g);
+    if (!a.local && fl != 0) boundary_fixup<real>(a, global_prev<real, PER>(a, x, y), s, fl, a.t_prev, g);
     return true;
+}
+
+// Site coordinates of a row or halo site: wrapped on periodic axes (any
+// distance: tiles reach up to three sites past a plate narrower than that),
+// clamped into the grid otherwise -- so that every pull address stays in the
+// allocation -- and then marked outside.
+template <bool PER>
+__device__ __forceinline__ void place(int nx, int ny, int px, int py, int& x, int& y, bool& in)
+{
+    in = true;
+    if (x < 0 || x >= nx) {
+        if (PER && px) {
+            x %= nx;
+            if (x < 0) x += nx;
+        } else {
+            in = false;
+            x = x < 0 ? 0 : nx - 1;
+        }
+    }
+    if (y < 0 || y >= ny) {
+        if (PER && py) {
+            y %= ny;
+            if (y < 0) y += ny;
+        } else {
+            in = false;
+            y = y < 0 ? 0 : ny - 1;
+        }
+    }
 }
 
 // Loads of one site, unconditional: a site outside the grid loads from a
@@ -274,22 +338,7 @@ template <typename real, bool PER>
 __device__ __forceinline__ void site_issue(const StepArgs<real>& a, int x, int y, real g[9], unsigned& fl,
                                            int& ys, bool& in, int& s_out)
 {
-    in = true;
-    if (x < 0 || x >= a.nx) {
-        if (PER && a.px) x = x < 0 ? x + a.nx : x - a.nx;
-        if (x < 0 || x >= a.nx) {
-            in = false;
-            x = x < 0 ? 0 : a.nx - 1;
-        }
-    }
-    if (y < 0 || y >= a.ny) {
-        if (PER && a.py) {
-            y = y < 0 ? y + a.ny : y - a.ny;
-        } else {
-            in = false;
-            y = y < 0 ? 0 : a.ny - 1;
-        }
-    }
+    place<PER>(a.nx, a.ny, a.px, a.py, x, y, in);
     ys = y;
     const int s = sidx(x, y, a.ld);
     s_out = s;
@@ -313,9 +362,10 @@ __device__ __forceinline__ real site_finish(const StepArgs<real>& a, int x, int 
     if (!in) fl = kVoid;
     const bool live = fl != kVoid;
     if (want && live && !a.local && fl != 0) {
-        int xx = x;
-        if (PER && a.px) xx = xx < 0 ? xx + a.nx : (xx >= a.nx ? xx - a.nx : xx);
-        boundary_fixup<real, PER>(a, xx, y, sidx(xx, y, a.ld), fl, g);
+        int xx = x, yy = y;
+        bool in2;
+        place<PER>(a.nx, a.ny, a.px, a.py, xx, yy, in2);
+        boundary_fixup<real>(a, global_prev<real, PER>(a, xx, yy), sidx(xx, yy, a.ld), fl, a.t_prev, g);
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) g[i] = live ? g[i] : real(0);
@@ -330,8 +380,9 @@ struct Window {
     real c, c_l, c_r;
 };
 
-// Collision, source term and displacement update of one site, given the
-// densities of its eight neighbours (w and the row above, rp).
+// Collision and source term of one site, given the densities of its eight
+// neighbours (w and the row above, rp): the post-collision populations o and
+// the site's j (with S/2) and rho.
 //
 // eq:coll with eq:fieq, in the closure where the equilibrium's second moment
 // is the populations' own: collision leaves rho and P unchanged, adds S to j
@@ -346,9 +397,9 @@ struct Window {
 // moments by (1 + omega eps) each step, a drift of ~5e-4 after 10^4 steps in
 // single precision.
 template <typename real>
-__device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const real g[9], unsigned fl,
-                                             double ux, double uy, const Window<real>& w, real rp, real rp_l,
-                                             real rp_r)
+__device__ __forceinline__ bool collide_core(const StepArgs<real>& a, const real g[9], unsigned fl,
+                                             const Window<real>& w, real rp, real rp_l, real rp_r, real o[9],
+                                             real& jx_out, real& jy_out, real& rho_out)
 {
     const real A4 = g[1] + g[2] + g[3] + g[4];
     const real B4 = g[5] + g[6] + g[7] + g[8];
@@ -382,7 +433,6 @@ __device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int
     const real ae = a.omega * (real(2) * A4 - real(4) * B4 - g[0]) * real(1.0 / 36.0);
     const real ae2 = real(2) * ae;
     const real ax2 = real(2) * ax, ay2 = real(2) * ay;
-    real o[9];
     o[0] = g[0] + real(4) * ae;
     o[1] = g[1] + ((hx - ax2) - ae2);
     o[3] = g[3] + ((ax2 - hx) - ae2);
@@ -392,14 +442,36 @@ __device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int
     o[6] = g[6] + ((ay - ax) + ae);
     o[7] = g[7] + (ae - (ax + ay));
     o[8] = g[8] + ((ax - ay) + ae);
+    jx_out = jx;
+    jy_out = jy;
+    rho_out = rho;
+    return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
+}
+
+// displacement: U += j/rho (fp64 accumulation)
+template <typename real>
+__device__ __forceinline__ void advance_u(double& ux, double& uy, real jx, real jy, real rho)
+{
+    const double ir = 1.0 / (double)rho;
+    ux = ux + (double)jx * ir;
+    uy = uy + (double)jy * ir;
+}
+
+// collide_core, then the populations and the displacement stored at (x, y).
+template <typename real>
+__device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const real g[9], unsigned fl,
+                                             double ux, double uy, const Window<real>& w, real rp, real rp_l,
+                                             real rp_r)
+{
+    real o[9], jx, jy, rho;
+    const bool bad = collide_core<real>(a, g, fl, w, rp, rp_l, rp_r, o, jx, jy, rho);
     const int s = sidx(x, y, a.ld);
 #pragma unroll
     for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
-    // displacement: U += j/rho (fp64 accumulation)
-    const double ir = 1.0 / (double)rho;
-    stu(a.U, s, ux + (double)jx * ir);
-    stu(a.U + a.plane, s, uy + (double)jy * ir);
-    return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
+    advance_u(ux, uy, jx, jy, rho);
+    stu(a.U, s, ux);
+    stu(a.U + a.plane, s, uy);
+    return bad;
 }
 
 // ------------------------------------------------------------------ tiles
@@ -419,30 +491,6 @@ template <bool WIDE> constexpr int max_tile_rows() { return kMaxTileRows; }
 // contiguous band of tile numbers so that the halo rows and columns tiles
 // share stay in one L2.  nb (the grid size) is a multiple of 8.
 __device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
-
-// Site coordinates of a halo or row site: wrapped on periodic axes, clamped
-// into the grid (so that every pull address stays in the allocation) and
-// marked outside otherwise.
-template <bool PER>
-__device__ __forceinline__ void place(int nx, int ny, int px, int py, int& x, int& y, bool& in)
-{
-    in = true;
-    if (x < 0 || x >= nx) {
-        if (PER && px) x = x < 0 ? x + nx : x - nx;
-        if (x < 0 || x >= nx) {
-            in = false;
-            x = x < 0 ? 0 : nx - 1;
-        }
-    }
-    if (y < 0 || y >= ny) {
-        if (PER && py) {
-            y = y < 0 ? y + ny : y - ny;
-        } else {
-            in = false;
-            y = y < 0 ? 0 : ny - 1;
-        }
-    }
-}
 
 // Densities of the two halo columns of a wide strip in row y (left: column
 // xs - 1, right: xs + 64).  Lanes 0-8 pull the nine populations of the left
@@ -555,6 +603,101 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
     const int tile = xcd_banded(blockIdx.x, gridDim.x);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
     flag_divergence(a.diverged, step_tile<real, PER, WIDE>(a, tile, dens));
+}
+
+// ---------------------------------------------------- two steps per launch
+//
+// A workgroup of R + 6 waves (R <= kMaxTileRows2) advances a tile of R rows
+// of a 58-column strip by two time steps, reading the state once and writing
+// it once.  A step at a site depends on the previous state within two sites
+// (the pulls one, the density stencil one more), so the first step is taken
+// on the tile widened by two rows and two columns on each side -- wave w
+// holds row y0 - 3 + w, lane l column xs - 3 + l -- and its post-collision
+// populations stay in LDS, from where the second step pulls.  Every site's
+// arithmetic is that of two single steps, so the state is bit-identical to
+// theirs.
+constexpr int kMaxTileRows2 = 10;
+constexpr int kStrip2 = 58;
+
+template <typename real, bool PER>
+__device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, real (*post)[9][64],
+                                           real (*dens)[66])
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int R = a.seg;
+    const int strip = tile % a.nstrips;
+    const int y0 = (tile / a.nstrips) * R;
+    const int x = strip * kStrip2 - 3 + lane, y = y0 - 3 + wave;
+    // first step, from the state buffer
+    real g[9];
+    unsigned fl;
+    bool in;
+    int ys, s;
+    site_issue<real, PER>(a, x, y, g, fl, ys, in, s);
+    double ux = ldu(a.U, s), uy = ldu(a.U + a.plane, s);
+    dens[wave][lane] = site_finish<real, PER>(a, x, ys, in, true, fl, g);
+    __syncthreads();
+    const bool out = wave >= 3 && wave <= R + 2 && lane >= 3 && lane <= 60 && y < a.ny && x < a.nx && fl != kVoid;
+    bool bad = false;
+    if (wave >= 1 && wave <= R + 4) {
+        real o[9];
+        if (lane >= 1 && lane <= 62 && fl != kVoid) {
+            Window<real> w;
+            w.m = dens[wave - 1][lane]; w.m_l = dens[wave - 1][lane - 1]; w.m_r = dens[wave - 1][lane + 1];
+            w.c_l = dens[wave][lane - 1]; w.c_r = dens[wave][lane + 1];
+            real jx, jy, rho;
+            const bool b = collide_core<real>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
+                                              dens[wave + 1][lane + 1], o, jx, jy, rho);
+            if (out) {
+                bad = b;
+                advance_u(ux, uy, jx, jy, rho);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) o[i] = real(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) post[wave - 1][i][lane] = o[i];
+    }
+    __syncthreads();
+    // second step, from the first step's post-collision populations
+    if (wave >= 2 && wave <= R + 3) {
+        const int r = wave - 1;
+        const int lc = lane < 2 ? 2 : (lane > 61 ? 61 : lane);   // lanes 0, 1, 62, 63: no second-step site
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = post[r - CY(i)][i][lc - CX(i)];
+        const bool live = fl != kVoid;
+        if (live && fl != 0) boundary_fixup<real>(a, LdsPrev<real>{post, r, lc}, s, fl, a.t_prev + 1, g);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = live ? g[i] : real(0);
+        dens[wave][lane] = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+    }
+    __syncthreads();
+    if (out) {
+        Window<real> w;
+        w.m = dens[wave - 1][lane]; w.m_l = dens[wave - 1][lane - 1]; w.m_r = dens[wave - 1][lane + 1];
+        w.c_l = dens[wave][lane - 1]; w.c_r = dens[wave][lane + 1];
+        real o[9], jx, jy, rho;
+        bad |= collide_core<real>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
+                                  dens[wave + 1][lane + 1], o, jx, jy, rho);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
+        advance_u(ux, uy, jx, jy, rho);
+        stu(a.U, s, ux);
+        stu(a.U + a.plane, s, uy);
+    }
+    return bad;
+}
+
+// Two time steps of one plate: one workgroup of seg + 6 waves per tile.
+template <typename real, bool PER>
+__global__ __launch_bounds__(1024) void k_step2(StepArgs<real> a)
+{
+    __shared__ real post[kMaxTileRows2 + 4][9][64];
+    __shared__ real dens[kMaxTileRows2 + 6][66];
+    const int tile = xcd_banded(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;                 // uniform over the workgroup
+    flag_divergence(a.diverged, step_tile2<real, PER>(a, tile, post, dens));
 }
 
 // Per-plate state of the batched step, in device memory so that a captured

@@ -113,9 +113,10 @@ def main():
     if d.get("kernel_fingerprint") != kernel_fingerprint():
         d = {}
     d.update({"kernel_fingerprint": kernel_fingerprint(), "workload": a.workload, "precision": a.precision,
-              "kernel": a.kernel, "copy_kernel": a.copy_kernel, "copy_bytes": a.copy_bytes})
-    d.setdefault("shapes", {})[f"{a.rows}x{a.strip}"] = traffic(a.fetch, a.write, a.kernel, a.copy_kernel,
-                                                                a.copy_bytes)
+              "copy_kernel": a.copy_kernel, "copy_bytes": a.copy_bytes})
+    t = traffic(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes)
+    t["kernel"] = a.kernel
+    d.setdefault("shapes", {})[f"{a.rows}x{a.strip}"] = t
     with open(a.out, "w") as fh:
         json.dump(d, fh, indent=1)
     print(json.dumps(d["shapes"][f"{a.rows}x{a.strip}"]))

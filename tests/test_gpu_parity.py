@@ -204,7 +204,8 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
     beyond the tile limits are refused."""
     p = mixed_plate(150, 97, seed=5, order=1)
     out = []
-    for seg, strip in ((1, 62), (3, 64), (8, 62), (14, 64), (14, 62), (2, 64), (0, 0)):
+    for seg, strip in ((1, 62), (3, 64), (8, 62), (14, 64), (14, 62), (2, 64), (0, 0), (1, 58), (6, 58),
+                       (10, 58)):
         s = slbm.Solver(p, prec)
         s.set_launch(seg, strip)
         s.step(37)
@@ -213,10 +214,39 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
         assert np.array_equal(u, out[0][0])
         assert np.array_equal(P, out[0][1])
     s = slbm.Solver(p, prec)
-    for seg, strip in ((15, 62), (15, 64), (-1, 62), (4, 63)):
+    for seg, strip in ((15, 62), (15, 64), (11, 58), (-1, 62), (4, 63)):
         with pytest.raises(slbm.SlbmError) as e:
             s.set_launch(seg, strip)
         assert e.value.code == -1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["periodic", "init_fields", "odd_steps"])
+def test_two_steps_per_launch_match_single_steps(slbm, prec, case):
+    """The two-steps-per-launch kernel keeps the first step's populations in
+    LDS and takes the second from there: the state must be bit-identical to
+    single steps -- periodic plates, a start from slbm_init_fields (the first
+    step reads in place), and an odd step count (the last step single)."""
+    if case == "periodic":
+        p, n = mixed_plate(64, 40, seed=1, periodic=True), 40
+    else:
+        p, n = mixed_plate(130, 67, seed=2, order=1), (41 if case == "odd_steps" else 30)
+    out = []
+    for shape in ((6, 62), (6, 58), (2, 58), (10, 58)):
+        s = slbm.Solver(p, prec)
+        if case == "init_fields":
+            yy, xx = np.mgrid[0:p.ny, 0:p.nx]
+            vel = 1e-4 * np.stack([np.sin(yy / 5.0), np.cos(xx / 7.0)]) * p.mask
+            s.init_fields(vel=vel)
+        s.set_launch(*shape)
+        s.step(n)
+        s.sync()
+        assert s.time()[0] == n
+        out.append((s.displacement(), s.moments()))
+    for u, m in out[1:]:
+        assert np.array_equal(u, out[0][0])
+        for a, b in zip(m, out[0][1]):
+            assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("shape", [(1, 7), (2, 2), (3, 5), (61, 9), (62, 3), (63, 4), (64, 65), (124, 2), (125, 33)])
@@ -232,6 +262,10 @@ def test_small_and_ragged_grids(slbm, shape):
     s = slbm.Solver(p, "fp64")
     s.step(40)
     compare(s, ref, "fp64")
+    s2 = slbm.Solver(p, "fp64")
+    s2.set_launch(3, 58)                 # two steps per launch
+    s2.step(40)
+    compare(s2, ref, "fp64")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -383,7 +417,7 @@ def test_autotune_leaves_the_state_untouched(slbm, prec):
     a = slbm.Solver(p, prec)
     a.step(25)
     seg, strip, us = a.autotune()
-    assert seg >= 2 and strip in (62, 64) and us > 0
+    assert seg >= 2 and strip in (58, 62, 64) and us > 0
     assert a.time()[0] == 25
     a.step(25)
     b = slbm.Solver(p, prec)
