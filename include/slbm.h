@@ -217,9 +217,10 @@ int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps);
 /* Frees the plate (its slot and budget are reused). */
 int slbm_batch_remove(slbm_batch b, int32_t slot);
 
-/* Launch shape of the batched step, for every plate: rows per tile (1..14)
- * and strip width (62 or 64) as in slbm_set_launch.  SLBM_E_INVAL beyond the
- * limits. */
+/* Launch shape of the batched step, for every plate: rows per tile (1..14,
+ * 1..10 with strip 58) and strip width (62, 64, or 58: two steps per launch,
+ * a plate with one step left taking one) as in slbm_set_launch.
+ * SLBM_E_INVAL beyond the limits. */
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
 
 int slbm_batch_sync(slbm_batch b);

@@ -1104,6 +1104,7 @@ struct slbm_batch_s {
     std::vector<int64_t> bytes;
     int wide = 0;                    // strip shape of the batched launch
     int rows = 6;                    // rows per tile for every plate
+    int two = 0;                     // 1: two steps per launch (58-column strips)
     // device tables (rebuilt when the set of plates or the launch shape changes)
     void* d_plates = nullptr;
     int* d_tile_plate = nullptr;
@@ -1155,7 +1156,7 @@ int batch_build(slbm_batch_s* b)
         h->seg = b->rows;
         h->wide = b->wide;
         BatchPlate<real> e{};
-        e.args = make_args<real>(h, h->cur);
+        e.args = b->two ? make_args2<real>(h, h->cur, b->rows) : make_args<real>(h, h->cur);
         h->seg = keep_seg;
         h->wide = keep_w;
         e.remaining = b->remaining[k];
@@ -1187,11 +1188,16 @@ int batch_grid(const slbm_batch_s* b)
     return (g + 7) / 8 * 8;
 }
 
-// Queues one batched step (and, with advance, its bookkeeping) on the stream.
+// Queues one batched launch of up to maxk steps (2 only in two-step mode)
+// and, with advance, its bookkeeping on the stream.
 template <typename real>
-void batch_launch(slbm_batch_s* b, bool advance)
+void batch_launch(slbm_batch_s* b, bool advance, int maxk = 1)
 {
     const int grid = batch_grid(b);
+    if (b->two) {
+        hipLaunchKernelGGL((k_step2_batch<real>), dim3(grid), dim3(64 * (b->rows + 6)), 0, b->stream,
+                           (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk);
+    } else {
     const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
     if (b->wide)
         hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
@@ -1199,10 +1205,11 @@ void batch_launch(slbm_batch_s* b, bool advance)
     else
         hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
                            (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+    }
     if (advance) {
         const int n = (int)b->live.size();
         hipLaunchKernelGGL((k_batch_advance<real>), dim3((n + 63) / 64), dim3(64), 0, b->stream,
-                           (BatchPlate<real>*)b->d_plates, n);
+                           (BatchPlate<real>*)b->d_plates, n, b->two ? maxk : 1);
     }
 }
 
@@ -1214,14 +1221,18 @@ int batch_run(slbm_batch_s* b, int64_t k)
         if (rc) return rc;
     }
     if (b->ntiles == 0 || k <= 0) return SLBM_OK;
-    int64_t left = k;
-    if (left >= kChunk) {
+    // launches of up to `per` steps; in two-step mode an odd step count ends
+    // with a launch of one step
+    const int per = b->two ? 2 : 1;
+    int64_t left = k / per;                       // launches of `per` steps
+    const int64_t chunk = kChunk / per;           // launches per captured graph
+    if (left >= chunk) {
         if (!b->graph_ok) {
             // kChunk steps captured once and replayed: no memset nodes, only
             // the step and bookkeeping kernels
             hipGraph_t g = nullptr;
             HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < kChunk; ++i) batch_launch<real>(b, true);
+            for (int64_t i = 0; i < chunk; ++i) batch_launch<real>(b, true, per);
             hipError_t e = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess) return fail(SLBM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
             e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
@@ -1229,23 +1240,33 @@ int batch_run(slbm_batch_s* b, int64_t k)
             if (e != hipSuccess) return fail(SLBM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
             b->graph_ok = true;
         }
-        while (left >= kChunk) {
+        while (left >= chunk) {
             HIP_TRY(hipGraphLaunch(b->graph, b->stream));
-            left -= kChunk;
+            left -= chunk;
         }
     }
-    for (int64_t i = 0; i < left; ++i) batch_launch<real>(b, true);
+    for (int64_t i = 0; i < left; ++i) batch_launch<real>(b, true, per);
+    const bool odd = b->two && (k & 1);
+    if (odd) batch_launch<real>(b, true, 1);
     HIP_TRY(hipGetLastError());
-    // host mirror of the device bookkeeping
+    // host mirror of the device bookkeeping: each launch in which a plate is
+    // active swaps its buffers once and takes min(steps of the launch, remaining)
+    const int64_t full = k / per;
     for (size_t k2 = 0; k2 < b->slot.size(); ++k2) {
         slbm_s* h = b->slot[k2];
         if (!h) continue;
-        const int64_t n = std::min(k, b->remaining[k2]);
-        if (n <= 0) continue;
-        h->cur ^= (int)(n & 1);
-        h->step += n;
+        const int64_t rem = b->remaining[k2];
+        if (rem <= 0) continue;
+        int64_t launches = std::min(full, (rem + per - 1) / per);
+        int64_t done = std::min(rem, full * per);
+        if (odd && done < rem) {
+            launches += 1;
+            done += 1;
+        }
+        h->cur ^= (int)(launches & 1);
+        h->step += done;
         h->local = false;
-        b->remaining[k2] -= n;
+        b->remaining[k2] -= done;
     }
     return SLBM_OK;
 }
@@ -1371,11 +1392,12 @@ int slbm_batch_remove(slbm_batch b, int32_t slot)
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
 {
     if (!b) return fail(SLBM_E_INVAL, "null batch");
-    if (strip != 62 && strip != 64) return fail(SLBM_E_INVAL, "strip must be 62 or 64");
-    if (rows < 1 || rows > (strip == 64 ? max_tile_rows<true>() : max_tile_rows<false>()))
-        return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14]");
+    if (strip != 62 && strip != 64 && strip != kStrip2) return fail(SLBM_E_INVAL, "strip must be 58, 62 or 64");
+    if (rows < 1 || rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
+        return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] ([1, 10] with strip 58)");
     b->rows = rows;
     b->wide = strip == 64 ? 1 : 0;
+    b->two = strip == kStrip2 ? 1 : 0;
     b->dirty = true;
     return SLBM_OK;
 }

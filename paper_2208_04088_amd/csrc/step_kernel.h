@@ -619,9 +619,11 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
 constexpr int kMaxTileRows2 = 10;
 constexpr int kStrip2 = 58;
 
+// two = false: only the first step, stored like a single step (a plate in a
+// batch with one step left); uniform over the workgroup.
 template <typename real, bool PER>
 __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, real (*post)[9][64],
-                                           real (*dens)[66])
+                                           real (*dens)[66], bool two = true)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int R = a.seg;
@@ -656,9 +658,19 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
 #pragma unroll
             for (int i = 0; i < 9; ++i) o[i] = real(0);
         }
+        if (!two) {
+            if (out) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
+                stu(a.U, s, ux);
+                stu(a.U + a.plane, s, uy);
+            }
+            return bad;
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) post[wave - 1][i][lane] = o[i];
     }
+    if (!two) return bad;
     __syncthreads();
     // second step, from the first step's post-collision populations
     if (wave >= 2 && wave <= R + 3) {
@@ -690,8 +702,11 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
 }
 
 // Two time steps of one plate: one workgroup of seg + 6 waves per tile.
+#ifndef SLBM_K2_MINW
+#define SLBM_K2_MINW 1
+#endif
 template <typename real, bool PER>
-__global__ __launch_bounds__(1024) void k_step2(StepArgs<real> a)
+__global__ __launch_bounds__(1024, SLBM_K2_MINW) void k_step2(StepArgs<real> a)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
@@ -730,21 +745,42 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __r
     }
 }
 
-// After a batched step: swap each active plate's buffers, advance its clock
-// and count down its remaining steps.
+// Up to two time steps of every active plate of a batch in one launch (the
+// tiles of the two-step kernel): each plate takes min(maxk, remaining).
 template <typename real>
-__global__ __launch_bounds__(64) void k_batch_advance(BatchPlate<real>* plates, int nplates)
+__global__ __launch_bounds__(1024) void k_step2_batch(const BatchPlate<real>* __restrict__ plates,
+                                                      const int* __restrict__ tile_plate,
+                                                      const int* __restrict__ tile_start, int ntiles, int maxk)
+{
+    __shared__ real post[kMaxTileRows2 + 4][9][64];
+    __shared__ real dens[kMaxTileRows2 + 6][66];
+    for (int t = xcd_banded(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
+        const int p = tile_plate[t];
+        if (!plates[p].active) continue;         // uniform over the workgroup
+        const StepArgs<real> a = plates[p].args;
+        const bool two = maxk >= 2 && plates[p].remaining >= 2;
+        flag_divergence(a.diverged, step_tile2<real, false>(a, t - tile_start[p], post, dens, two));
+        __syncthreads();                          // post and dens are reused by the next tile
+    }
+}
+
+// After a batched launch of up to maxk steps: swap each active plate's
+// buffers (a launch reads one and writes the other), advance its clock and
+// count down its remaining steps.
+template <typename real>
+__global__ __launch_bounds__(64) void k_batch_advance(BatchPlate<real>* plates, int nplates, int maxk)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nplates) return;
     BatchPlate<real>& B = plates[p];
     if (!B.active) return;
+    const long long k = B.remaining < maxk ? B.remaining : maxk;
     real* t = const_cast<real*>(B.args.src);
     B.args.src = B.args.dst;
     B.args.dst = t;
-    B.args.t_prev += 1;
+    B.args.t_prev += k;
     B.args.local = 0;
-    B.remaining -= 1;
+    B.remaining -= k;
     if (B.remaining <= 0) B.active = 0;
 }
 

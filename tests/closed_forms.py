@@ -41,3 +41,49 @@ def plane_strain_modulus(lam, mu):
     """Uniaxial-stress stiffness of a strip in plane strain with free lateral
     faces: E' = 4 mu (lambda + mu)/(lambda + 2 mu)."""
     return 4.0 * mu * (lam + mu) / (lam + 2.0 * mu)
+
+
+def freund_k1(t_star, nu, cd, cs, lc, t, f_plus0=0.8774):
+    """Mode-I stress intensity factor at one tip of a crack of length lc whose
+    faces are suddenly loaded by t_star, from t = lc/c_d (when the waves
+    scattered by the other tip arrive) to 2 lc/c_d: K^0 plus Freund's
+    correction (the paper's eq:ki1), with slownesses a = 1/c_d, b = 1/c_s and
+    c_r = 1/c_R.  Both integrals are Cauchy principal values: the inner one
+    at xi = eta, the outer one at eta = c_r; each is written as
+    p.v. int f(x)/(x - c) dx and evaluated by quadrature with that weight."""
+    import numpy as np
+    from scipy.integrate import quad
+
+    k0 = freund_k0(t_star, nu, cd, t)
+    a, b = 1.0 / cd, 1.0 / cs
+    cr = 1.0 / rayleigh_speed(cs, cd)
+    T = t / lc
+    if T <= a:
+        return k0
+
+    def g(xi):
+        num = 4.0 * xi * xi * math.sqrt(max((xi * xi - a * a) * (b * b - xi * xi), 0.0))
+        den = (b * b - 2.0 * xi * xi) ** 2
+        return math.atan2(num, den)
+
+    def inner(eta):
+        # (1/pi) p.v. int_a^b g(xi) 2 eta / (xi^2 - eta^2) dxi
+        f = lambda xi: g(xi) * 2.0 * eta / (xi + eta)
+        if a < eta < b:
+            v = quad(f, a, b, weight="cauchy", wvar=eta, limit=400)[0]
+        else:
+            v = quad(lambda xi: f(xi) / (xi - eta), a, b, limit=400)[0]
+        return v / math.pi
+
+    def h(eta):
+        # Im of the outer integrand times (c_r - eta): sqrt((a - eta)/(a + eta))
+        # is i sqrt((eta - a)/(eta + a)) for eta > a, everything else is real
+        return (math.sqrt(max(T - eta, 0.0)) * math.sqrt(max(eta - a, 0.0) / (eta + a)) * (cr + eta) / eta
+                * math.exp(inner(eta)))
+
+    if T > cr:
+        # int h/(c_r - eta) = -p.v. int h/(eta - c_r)
+        integral = -quad(h, a, T, weight="cauchy", wvar=cr, limit=400)[0]
+    else:
+        integral = quad(lambda e: h(e) / (cr - e), a, T, limit=400)[0]
+    return k0 + 2.0 * t_star * f_plus0 / math.pi * math.sqrt(2.0 * lc / math.pi) * integral

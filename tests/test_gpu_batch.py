@@ -36,11 +36,16 @@ def alone(slbm, plate, steps, prec):
     return s.displacement(), s.moments()[3]
 
 
+@pytest.mark.parametrize("launch", [None, (6, 58)])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_batched_plates_match_their_solo_runs(slbm, prec):
+def test_batched_plates_match_their_solo_runs(slbm, prec, launch):
+    """Step counts on both sides of the captured chunk and odd ones, in both
+    launch modes (one step, or two steps per launch with single-step ends)."""
     plates = small_plates(3, 7)
     steps = [0, 1, 31, 32, 33, 70, 101]
     b = slbm.Batch(8 << 30)
+    if launch:
+        b.set_launch(*launch)
     slots = [b.add(p, n, prec) for p, n in zip(plates, steps)]
     for k in (5, 32, 1, 40, 64):        # chunks below, at and above the graph size
         b.step(k)
@@ -56,12 +61,15 @@ def test_batched_plates_match_their_solo_runs(slbm, prec):
     b.close()
 
 
-def test_continuous_batching_joins_and_leaves(slbm):
+@pytest.mark.parametrize("launch", [None, (4, 58)])
+def test_continuous_batching_joins_and_leaves(slbm, launch):
     """Plates arrive while others are running and leave when done; each
     result is the same alone and in the mix."""
     plates = small_plates(5, 6)
     want = [45, 80, 33, 64, 100, 20]
     b = slbm.Batch(8 << 30)
+    if launch:
+        b.set_launch(*launch)
     live = {}
     arrivals = {0: [0, 1], 1: [2], 2: [3, 4], 4: [5]}
     finished = {}
@@ -86,7 +94,7 @@ def test_continuous_batching_joins_and_leaves(slbm):
 def test_batch_launch_shape_does_not_change_results(slbm):
     plates = small_plates(9, 4)
     ref = None
-    for rows, strip in ((2, 62), (8, 64), (5, 62), (14, 64), (14, 62)):
+    for rows, strip in ((2, 62), (8, 64), (5, 62), (14, 64), (14, 62), (1, 58), (6, 58), (10, 58)):
         b = slbm.Batch(8 << 30)
         slots = [b.add(p, 50, "fp64") for p in plates]
         b.set_launch(rows, strip)

@@ -432,3 +432,58 @@ def test_crack_tip_sif_follows_freund_k0():
     ratio, lag = sif_series(o.step, lambda: o.moments()[3][1], p, 1e-3 * p.mu, t1)
     assert abs(ratio - 1) < 0.05, ratio
     assert 0 <= lag <= 40, lag
+
+
+def test_paper_crack_follows_freund_k0():
+    """Section 5.2 at the paper's own size: 400 x 400, a centred crack of
+    100 cells whose faces are suddenly pushed apart (lambda/mu = 0.769).  The
+    stress intensity factor at P_1, two cells ahead of a tip,
+    K = sigma_xx sqrt(2 pi r), follows Freund's K^0 until the waves from the
+    other tip arrive (t = l_c/c_d): fitted as c K^0(t - d) over
+    [0.3, 1] l_c/c_d, c within 5 % of 1 and a delay of at most 30 steps."""
+    p = configs.paper_center_crack()
+    o = Oracle(p)
+    par = o.lattice_params()
+    cd = math.sqrt((p.lam + 2 * p.mu) / p.rho)
+    cs = math.sqrt(p.mu / p.rho)
+    nu = CF.nu_from_speed_ratio(cd * cd / (cs * cs))
+    lc, ts = 100.0, 0.009615 * p.mu
+    n_end = int(1.0 * lc / cd / par["dt_user"])
+    T, K = [], []
+    for n in range(0, n_end + 1, 4):
+        if n:
+            o.step(4)
+        # P_1 lies on the crack line (between columns 199 and 200), 2 cells
+        # beyond the tip at y = 249.5 (between rows 251 and 252)
+        T.append(n * par["dt_user"])
+        K.append(o.moments()[3][0][251:253, 199:201].mean() * math.sqrt(2 * math.pi * 2.0))
+    T, K = np.array(T), np.array(K)
+    sel = T >= 0.3 * lc / cd
+    best = None
+    for d in np.arange(0.0, 40.0, 0.5) * par["dt_user"]:
+        r = np.array([CF.freund_k0(ts, nu, cd, max(t - d, 0.0)) for t in T[sel]])
+        c = (K[sel] @ r) / (r @ r)
+        e = np.linalg.norm(K[sel] - c * r) / np.linalg.norm(K[sel])
+        if best is None or e < best[0]:
+            best = (e, c, d / par["dt_user"])
+    e, c, lag = best
+    assert abs(c - 1) < 0.05, (c, lag, e)
+    assert 0 <= lag <= 30 and e < 0.02, (c, lag, e)
+
+
+def test_freund_k1_structure():
+    """The evaluator of Freund's K^1 (eq:ki1) for the paper's solid: equal to
+    K^0 until t = l_c/c_d, above it afterwards (the waves scattered by the
+    other tip add to the opening), and rising fastest near the arrival of the
+    Rayleigh waves from the other tip (t = c_r l_c = 1.82 l_c/c_d)."""
+    cd, cs, lc, ts = 1.0, math.sqrt(0.3611), 1.0, 1.0
+    nu = CF.nu_from_speed_ratio(1 / 0.3611)
+    k0 = lambda t: CF.freund_k0(ts, nu, cd, t)
+    k1 = lambda t: CF.freund_k1(ts, nu, cd, cs, lc, t)
+    assert k1(0.9) == k0(0.9)
+    assert abs(k1(1.0 + 1e-6) - k0(1.0 + 1e-6)) < 1e-4 * k0(1.0)
+    v = [k1(t) - k0(t) for t in (1.2, 1.5, 1.7, 1.8)]
+    assert all(x > 0 for x in v) and v == sorted(v)
+    slope_early = (v[1] - v[0]) / 0.3
+    slope_late = (v[3] - v[2]) / 0.1
+    assert slope_late > slope_early
