@@ -125,7 +125,7 @@ def run_batch(args, slbm, torch, dev, stream):
     steps = args.steps if args.steps_given else 5000
     plates = configs.batch_plates(seed=0, count=64, steps=steps)
     sites = sum(p.n_material for p in plates)
-    tune_shapes = [(4, 62), (6, 62), (10, 62), (14, 62), (4, 58), (6, 58), (10, 58)]
+    tune_shapes = [(4, 62), (6, 62), (10, 62), (14, 62), (4, 58), (6, 58), (8, 58), (10, 58)]
     chunk = 64
     warm = chunk * (len(tune_shapes) + 2)
 

@@ -374,10 +374,19 @@ void dispatch_step2(const slbm_s* h, const StepArgs<real>& a)
 {
     const int grid = ((a.ntiles + 7) / 8) * 8;
     const dim3 blk(64 * (a.seg + 6));
-    if (h->px || h->py)
-        hipLaunchKernelGGL((k_step2<real, true>), dim3(grid), blk, 0, h->stream, a);
-    else
-        hipLaunchKernelGGL((k_step2<real, false>), dim3(grid), blk, 0, h->stream, a);
+    constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
+    const bool per = h->px || h->py;
+    if (k2_waves<real>(a.seg) == hi) {
+        if (per)
+            hipLaunchKernelGGL((k_step2<real, true, hi>), dim3(grid), blk, 0, h->stream, a);
+        else
+            hipLaunchKernelGGL((k_step2<real, false, hi>), dim3(grid), blk, 0, h->stream, a);
+    } else {
+        if (per)
+            hipLaunchKernelGGL((k_step2<real, true, lo>), dim3(grid), blk, 0, h->stream, a);
+        else
+            hipLaunchKernelGGL((k_step2<real, false, lo>), dim3(grid), blk, 0, h->stream, a);
+    }
 }
 
 // Two steps in one launch, not committed (autotuner trials; see launch_step_raw).
@@ -974,7 +983,7 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
         if (us < best_us) { best_us = us; best = c; best_w = wv; }
     }
     // two steps per launch: bursts of three launches, time per step
-    const int cand2[] = {2, 4, 6, 8, 10};
+    const int cand2[] = {2, 3, 4, 5, 6, 7, 8, 9, 10};
     for (int c : cand2) {
         if (c > std::max(2, h->ny)) break;
         constexpr int kBurst2 = 3;
@@ -1182,8 +1191,8 @@ int batch_build(slbm_batch_s* b)
 
 int batch_grid(const slbm_batch_s* b)
 {
-    // one workgroup per tile (the kernel also walks tiles in strides of the
-    // grid, so a smaller grid stays correct)
+    // one workgroup per tile: the batched kernels assume at least ntiles
+    // workgroups (a multiple of 8 for the XCD banding)
     const int g = b->ntiles;
     return (g + 7) / 8 * 8;
 }
@@ -1194,17 +1203,24 @@ template <typename real>
 void batch_launch(slbm_batch_s* b, bool advance, int maxk = 1)
 {
     const int grid = batch_grid(b);
+    const BatchPlate<real>* plates = (const BatchPlate<real>*)b->d_plates;
     if (b->two) {
-        hipLaunchKernelGGL((k_step2_batch<real>), dim3(grid), dim3(64 * (b->rows + 6)), 0, b->stream,
-                           (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk);
+        const dim3 blk(64 * (b->rows + 6));
+        constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
+        if (k2_waves<real>(b->rows) == hi)
+            hipLaunchKernelGGL((k_step2_batch<real, hi>), dim3(grid), blk, 0, b->stream,
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk);
+        else
+            hipLaunchKernelGGL((k_step2_batch<real, lo>), dim3(grid), blk, 0, b->stream,
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk);
     } else {
-    const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
-    if (b->wide)
-        hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
-                           (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
-    else
-        hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
-                           (const BatchPlate<real>*)b->d_plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+        const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
+        if (b->wide)
+            hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+        else
+            hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
     }
     if (advance) {
         const int n = (int)b->live.size();

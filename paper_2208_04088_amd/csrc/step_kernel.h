@@ -372,6 +372,15 @@ __device__ __forceinline__ real site_finish(const StepArgs<real>& a, int x, int 
     return g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
 }
 
+// 1/x: the hardware reciprocal in single precision (within one ulp), a
+// correctly rounded division in double precision.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Whether any site of the wave has a cut link (void sites carry kVoid);
+// called where the whole wave is active.
+__device__ __forceinline__ bool wave_has_cuts(unsigned fl) { return __any(fl != 0u && fl != kVoid); }
+
 // Density stencil of the source term below and at a site: delta-rho of row
 // y-1 (m) and row y (c) at the site's column and its two neighbours.
 template <typename real>
@@ -396,10 +405,13 @@ struct Window {
 // a_e below).  Rounded equilibrium weights would instead scale the conserved
 // moments by (1 + omega eps) each step, a drift of ~5e-4 after 10^4 steps in
 // single precision.
-template <typename real>
+//
+// CUTS = false: no site of the wave has a cut link (a wave-uniform fast path;
+// the substitution below is then the identity).
+template <typename real, bool CUTS>
 __device__ __forceinline__ bool collide_core(const StepArgs<real>& a, const real g[9], unsigned fl,
                                              const Window<real>& w, real rp, real rp_l, real rp_r, real o[9],
-                                             real& jx_out, real& jy_out, real& rho_out)
+                                             real& jx_out, real& jy_out, real& ir_out)
 {
     const real A4 = g[1] + g[2] + g[3] + g[4];
     const real B4 = g[5] + g[6] + g[7] + g[8];
@@ -415,14 +427,19 @@ __device__ __forceinline__ bool collide_core(const StepArgs<real>& a, const real
     real rt[9];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-        const bool ci = (fl >> (i - 1)) & 1u;
-        const bool co = (fl >> (OPP(i) - 1)) & 1u;
-        rt[i] = ci ? (co ? dr : real(2) * dr - nb[OPP(i)]) : nb[i];
+        if constexpr (CUTS) {
+            const bool ci = (fl >> (i - 1)) & 1u;
+            const bool co = (fl >> (OPP(i) - 1)) & 1u;
+            rt[i] = ci ? (co ? dr : real(2) * dr - nb[OPP(i)]) : nb[i];
+        } else {
+            rt[i] = nb[i];
+        }
     }
     const real gx = real(1.0 / 3.0) * (rt[1] - rt[3]) + real(1.0 / 12.0) * (rt[5] - rt[6] - rt[7] + rt[8]);
     const real gy = real(1.0 / 3.0) * (rt[2] - rt[4]) + real(1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
     const real rho = real(1) + dr;
-    const real c = a.ml / rho;
+    const real ir = recip(rho);
+    const real c = a.ml * ir;
     const real Sx = a.Fx + c * gx, Sy = a.Fy + c * gy;
     const real hx = real(0.5) * Sx, hy = real(0.5) * Sy;
     // j of eq:moments with the half-step source
@@ -444,31 +461,31 @@ __device__ __forceinline__ bool collide_core(const StepArgs<real>& a, const real
     o[8] = g[8] + ((ax - ay) + ae);
     jx_out = jx;
     jy_out = jy;
-    rho_out = rho;
+    ir_out = ir;
     return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
 }
 
-// displacement: U += j/rho (fp64 accumulation)
+// displacement: U += j/rho, the increment in the populations' precision
+// (ir = 1/rho), the sum in fp64
 template <typename real>
-__device__ __forceinline__ void advance_u(double& ux, double& uy, real jx, real jy, real rho)
+__device__ __forceinline__ void advance_u(double& ux, double& uy, real jx, real jy, real ir)
 {
-    const double ir = 1.0 / (double)rho;
-    ux = ux + (double)jx * ir;
-    uy = uy + (double)jy * ir;
+    ux = ux + (double)(jx * ir);
+    uy = uy + (double)(jy * ir);
 }
 
 // collide_core, then the populations and the displacement stored at (x, y).
-template <typename real>
+template <typename real, bool CUTS>
 __device__ __forceinline__ bool collide_site(const StepArgs<real>& a, int x, int y, const real g[9], unsigned fl,
                                              double ux, double uy, const Window<real>& w, real rp, real rp_l,
                                              real rp_r)
 {
-    real o[9], jx, jy, rho;
-    const bool bad = collide_core<real>(a, g, fl, w, rp, rp_l, rp_r, o, jx, jy, rho);
+    real o[9], jx, jy, ir;
+    const bool bad = collide_core<real, CUTS>(a, g, fl, w, rp, rp_l, rp_r, o, jx, jy, ir);
     const int s = sidx(x, y, a.ld);
 #pragma unroll
     for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
-    advance_u(ux, uy, jx, jy, rho);
+    advance_u(ux, uy, jx, jy, ir);
     stu(a.U, s, ux);
     stu(a.U + a.plane, s, uy);
     return bad;
@@ -577,13 +594,16 @@ __device__ __forceinline__ bool step_tile(const StepArgs<real>& a, int tile, rea
         if (lane == 63) dens[wave][W + 1] = dr;
     }
     __syncthreads();
+    const bool cuts = wave_has_cuts(fl);
     const bool out = wave >= 1 && wave <= R && y < a.ny && x < a.nx && (WIDE || (lane >= 1 && lane <= 62));
     if (!out || fl == kVoid) return false;
     Window<real> w;
     w.m = dens[wave - 1][c]; w.m_l = dens[wave - 1][c - 1]; w.m_r = dens[wave - 1][c + 1];
     w.c_l = dens[wave][c - 1]; w.c_r = dens[wave][c + 1];
-    return collide_site<real>(a, x, y, g, fl, ux, uy, w, dens[wave + 1][c], dens[wave + 1][c - 1],
-                              dens[wave + 1][c + 1]);
+    return cuts ? collide_site<real, true>(a, x, y, g, fl, ux, uy, w, dens[wave + 1][c], dens[wave + 1][c - 1],
+                                           dens[wave + 1][c + 1])
+                : collide_site<real, false>(a, x, y, g, fl, ux, uy, w, dens[wave + 1][c], dens[wave + 1][c - 1],
+                                            dens[wave + 1][c + 1]);
 }
 
 // Sets the plate's divergence word when any lane of the wave saw a
@@ -619,11 +639,11 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
 constexpr int kMaxTileRows2 = 10;
 constexpr int kStrip2 = 58;
 
-// two = false: only the first step, stored like a single step (a plate in a
-// batch with one step left); uniform over the workgroup.
-template <typename real, bool PER>
+// TWO = false: only the first step, stored like a single step (a plate in a
+// batch with one step left).
+template <typename real, bool PER, bool TWO = true>
 __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, real (*post)[9][64],
-                                           real (*dens)[66], bool two = true)
+                                           real (*dens)[66])
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int R = a.seg;
@@ -636,10 +656,16 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
     bool in;
     int ys, s;
     site_issue<real, PER>(a, x, y, g, fl, ys, in, s);
-    double ux = ldu(a.U, s), uy = ldu(a.U + a.plane, s);
+    const bool out_row = wave >= 3 && wave <= R + 2;        // uniform over the wave
+    double ux = 0.0, uy = 0.0;
+    if (out_row) {
+        ux = ldu(a.U, s);
+        uy = ldu(a.U + a.plane, s);
+    }
     dens[wave][lane] = site_finish<real, PER>(a, x, ys, in, true, fl, g);
     __syncthreads();
-    const bool out = wave >= 3 && wave <= R + 2 && lane >= 3 && lane <= 60 && y < a.ny && x < a.nx && fl != kVoid;
+    const bool cuts = wave_has_cuts(fl);
+    const bool out = out_row && lane >= 3 && lane <= 60 && y < a.ny && x < a.nx && fl != kVoid;
     bool bad = false;
     if (wave >= 1 && wave <= R + 4) {
         real o[9];
@@ -647,18 +673,20 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
             Window<real> w;
             w.m = dens[wave - 1][lane]; w.m_l = dens[wave - 1][lane - 1]; w.m_r = dens[wave - 1][lane + 1];
             w.c_l = dens[wave][lane - 1]; w.c_r = dens[wave][lane + 1];
-            real jx, jy, rho;
-            const bool b = collide_core<real>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
-                                              dens[wave + 1][lane + 1], o, jx, jy, rho);
+            real jx, jy, ir;
+            const bool b = cuts ? collide_core<real, true>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
+                                                           dens[wave + 1][lane + 1], o, jx, jy, ir)
+                                : collide_core<real, false>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
+                                                            dens[wave + 1][lane + 1], o, jx, jy, ir);
             if (out) {
                 bad = b;
-                advance_u(ux, uy, jx, jy, rho);
+                advance_u(ux, uy, jx, jy, ir);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) o[i] = real(0);
         }
-        if (!two) {
+        if constexpr (!TWO) {
             if (out) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
@@ -670,7 +698,7 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
 #pragma unroll
         for (int i = 0; i < 9; ++i) post[wave - 1][i][lane] = o[i];
     }
-    if (!two) return bad;
+    if constexpr (!TWO) return bad;
     __syncthreads();
     // second step, from the first step's post-collision populations
     if (wave >= 2 && wave <= R + 3) {
@@ -689,24 +717,31 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
         Window<real> w;
         w.m = dens[wave - 1][lane]; w.m_l = dens[wave - 1][lane - 1]; w.m_r = dens[wave - 1][lane + 1];
         w.c_l = dens[wave][lane - 1]; w.c_r = dens[wave][lane + 1];
-        real o[9], jx, jy, rho;
-        bad |= collide_core<real>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
-                                  dens[wave + 1][lane + 1], o, jx, jy, rho);
+        real o[9], jx, jy, ir;
+        bad |= cuts ? collide_core<real, true>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
+                                               dens[wave + 1][lane + 1], o, jx, jy, ir)
+                    : collide_core<real, false>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
+                                                dens[wave + 1][lane + 1], o, jx, jy, ir);
 #pragma unroll
         for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
-        advance_u(ux, uy, jx, jy, rho);
+        advance_u(ux, uy, jx, jy, ir);
         stu(a.U, s, ux);
         stu(a.U + a.plane, s, uy);
     }
     return bad;
 }
 
-// Two time steps of one plate: one workgroup of seg + 6 waves per tile.
-#ifndef SLBM_K2_MINW
-#define SLBM_K2_MINW 1
-#endif
-template <typename real, bool PER>
-__global__ __launch_bounds__(1024, SLBM_K2_MINW) void k_step2(StepArgs<real> a)
+// Waves per SIMD the two-step kernels are compiled for: in single precision
+// enough for two workgroups of rows + 6 waves on a compute unit (7: at most 72
+// VGPRs, up to 8 rows; 8: at most 64 VGPRs, 9 or 10 rows); in double
+// precision no bound (one workgroup).
+template <typename real>
+constexpr int k2_waves(int rows) { return sizeof(real) == 4 ? (rows > 8 ? 8 : 7) : 1; }
+
+// Two time steps of one plate: one workgroup of seg + 6 waves per tile
+// (W = k2_waves(seg)).
+template <typename real, bool PER, int W>
+__global__ __launch_bounds__(1024, W) void k_step2(StepArgs<real> a)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
@@ -727,41 +762,40 @@ struct BatchPlate {
 
 // One time step of every active plate of a batch in one launch.  The tiles of
 // all plates (of one height, the launch's) are numbered consecutively
-// (tile_start[p] is plate p's first); tiles of a plate that is done are
-// skipped.  Each workgroup walks tiles with a stride of the grid size, so the
-// grid can be sized to the machine rather than to the batch.
+// (tile_start[p] is plate p's first); one workgroup per tile (the grid holds
+// at least ntiles workgroups), tiles of a plate that is done return at once.
 template <typename real, bool WIDE>
 __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __restrict__ plates,
                                                      const int* __restrict__ tile_plate,
                                                      const int* __restrict__ tile_start, int ntiles)
 {
     __shared__ real dens[kMaxTileRows + 2][66];
-    for (int t = xcd_banded(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
-        const int p = tile_plate[t];
-        if (!plates[p].active) continue;         // uniform over the workgroup
-        const StepArgs<real> a = plates[p].args;
-        flag_divergence(a.diverged, step_tile<real, false, WIDE>(a, t - tile_start[p], dens));
-        __syncthreads();                          // dens is reused by the next tile
-    }
+    const int t = xcd_banded(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;                      // uniform over the workgroup
+    const int p = tile_plate[t];
+    if (!plates[p].active) return;
+    const StepArgs<real> a = plates[p].args;
+    flag_divergence(a.diverged, step_tile<real, false, WIDE>(a, t - tile_start[p], dens));
 }
 
 // Up to two time steps of every active plate of a batch in one launch (the
 // tiles of the two-step kernel): each plate takes min(maxk, remaining).
-template <typename real>
-__global__ __launch_bounds__(1024) void k_step2_batch(const BatchPlate<real>* __restrict__ plates,
+template <typename real, int W>
+__global__ __launch_bounds__(1024, W) void k_step2_batch(const BatchPlate<real>* __restrict__ plates,
                                                       const int* __restrict__ tile_plate,
                                                       const int* __restrict__ tile_start, int ntiles, int maxk)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
-    for (int t = xcd_banded(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x) {
-        const int p = tile_plate[t];
-        if (!plates[p].active) continue;         // uniform over the workgroup
-        const StepArgs<real> a = plates[p].args;
-        const bool two = maxk >= 2 && plates[p].remaining >= 2;
-        flag_divergence(a.diverged, step_tile2<real, false>(a, t - tile_start[p], post, dens, two));
-        __syncthreads();                          // post and dens are reused by the next tile
-    }
+    const int t = xcd_banded(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;                      // uniform over the workgroup
+    const int p = tile_plate[t];
+    if (!plates[p].active) return;
+    const StepArgs<real> a = plates[p].args;
+    if (maxk >= 2 && plates[p].remaining >= 2)
+        flag_divergence(a.diverged, step_tile2<real, false, true>(a, t - tile_start[p], post, dens));
+    else
+        flag_divergence(a.diverged, step_tile2<real, false, false>(a, t - tile_start[p], post, dens));
 }
 
 // After a batched launch of up to maxk steps: swap each active plate's
