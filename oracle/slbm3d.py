@@ -1,0 +1,266 @@
+"""Plain CPU reference of a three-dimensional (D3Q19) form of the solid
+lattice-Boltzmann step (TEST INFRASTRUCTURE).
+
+Only the test suite and the benchmark's CPU-baseline leg use this module.  It
+shares no code with the HIP library and is never a fallback for it.
+
+The paper (Faust, Schlueter, H. Mueller, R. Mueller, 2022) treats plane
+strain on D2Q9 and notes that its boundary rules generalise to three
+dimensions (section 1).  This module takes every step of the two-dimensional
+method in the paper's order, on the D3Q19 lattice (same c_s^2 = 1/3, weights
+1/3, 1/18, 1/36, fourth-order isotropic like D2Q9), in float64 numpy:
+
+  moments (eq:moments) -> source term S = F + (mu - lambda)/rho grad(rho)
+  (eq:sourceterm) -> equilibrium with the populations' own second moment
+  (eq:fieq) -> BGK collision with forcing (eq:coll) -> displacement
+  integration U += j/rho -> streaming along uncut links (eq:stream) ->
+  boundary rules on the links cut by the walls (eq:bbcon for Dirichlet,
+  eq:abbcon for Neumann).
+
+Readings beyond the paper (the three-dimensional extension):
+
+* Walls are lattice-conforming planes at x = -1/2 and x = nx - 1/2 (q = 1/2
+  on every cut link, so the rules' interpolation terms vanish); y and z are
+  periodic.
+* The Neumann rule's boundary Cauchy stress is
+      sigma* = Pi sigma(x) Pi + n (x) t* + t* (x) n - (t*.n) n (x) n,
+  Pi = I - n n: its normal part is fixed by the traction t* (sigma*.n = t*),
+  its tangential block taken at the boundary site (the rule with the
+  boundary-site values, the stable one of the two the workloads use).  In two
+  dimensions this is the paper's eq:trafocauchy with sigma_tt at the site.
+* The density gradient uses the isotropic D3Q19 stencil,
+  grad(rho) = 3 sum_i w_i c_i rho(x + c_i), with the neighbour across a cut
+  link extrapolated as 2 rho(x) - rho(x - c_i) (rho(x) if that link is cut
+  too), as in two dimensions.
+
+Units: user units in and out, dx = 1 cell; lattice units inside with
+dx = dt = 1, rho0 = 1, c_s^2 = 1/3, so dt_user = sqrt(rho/(3 mu)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DIRICHLET = 1
+NEUMANN = 2
+
+# D3Q19: rest, the six axis links, the twelve face diagonals
+C = np.array([[0, 0, 0],
+              [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+              [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0],
+              [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1],
+              [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=np.int64)
+Q = len(C)
+W = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
+OPP = np.array([int(np.flatnonzero((C == -c).all(1))[0]) for c in C])
+CS2 = 1.0 / 3.0
+# symmetric-tensor components in the order xx, yy, zz, xy, xz, yz
+SYM = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+
+
+def sym_to_full(p6):
+    """[6, ...] -> [3, 3, ...]"""
+    m = np.empty((3, 3) + p6.shape[1:])
+    for k, (a, b) in enumerate(SYM):
+        m[a, b] = p6[k]
+        m[b, a] = p6[k]
+    return m
+
+
+def full_to_sym(m):
+    return np.stack([m[a, b] for a, b in SYM])
+
+
+def equilibrium(rho, j, P):
+    """eq:fieq on D3Q19: f_eq,i = w_i [rho + c_i.j / c_s^2
+    + (P - c_s^2 rho I):(c_i c_i - c_s^2 I) / (2 c_s^4)].
+    rho [...], j [3, ...], P [3, 3, ...] -> [19, ...]."""
+    out = np.empty((Q,) + np.shape(rho))
+    for i in range(Q):
+        c = C[i]
+        cj = c[0] * j[0] + c[1] * j[1] + c[2] * j[2]
+        pc = 0.0
+        for a in range(3):
+            for b in range(3):
+                pc = pc + (P[a, b] - CS2 * rho * (a == b)) * (c[a] * c[b] - CS2 * (a == b))
+        out[i] = W[i] * (rho + cj / CS2 + pc / (2.0 * CS2 * CS2))
+    return out
+
+
+class Oracle3D:
+    """One box advanced by the reference.  ``box`` is a
+    :class:`slbm_workloads.box3d.Box3`."""
+
+    def __init__(self, box):
+        b = box
+        if not (b.mu > 0 and b.rho > 0):
+            raise ValueError("mu and rho must be positive")
+        if not b.tau > 0.5:
+            raise ValueError("tau must exceed 1/2")
+        self.box = b
+        self.shape = (b.nz, b.ny, b.nx)
+        # unit mapping (section 5.1): c_s = sqrt(mu/rho) = dx/(sqrt(3) dt)
+        self.dt_user = np.sqrt(b.rho / (3.0 * b.mu))
+        self.s_sigma = 3.0 * b.mu
+        self.s_v = 1.0 / self.dt_user
+        self.mu = b.mu / self.s_sigma
+        self.lam = b.lam / self.s_sigma
+        self.tau = float(b.tau)
+        self.F = np.array(b.force, dtype=np.float64) / self.s_sigma
+        self.walls = None
+        if b.x_walls is not None:
+            self.walls = []
+            for wall in b.x_walls:
+                if wall.kind not in (DIRICHLET, NEUMANN):
+                    raise ValueError("wall kind must be Dirichlet or Neumann")
+                scale = self.s_v if wall.kind == DIRICHLET else self.s_sigma
+                self.walls.append((wall.kind, np.array(wall.value, dtype=np.float64) / scale))
+        # cut[i] marks the sites whose link i leaves the material through a wall
+        self.cut = np.zeros((Q,) + self.shape, dtype=bool)
+        if self.walls is not None:
+            for i in range(Q):
+                if C[i, 0] < 0:
+                    self.cut[i, :, :, 0] = True
+                elif C[i, 0] > 0:
+                    self.cut[i, :, :, -1] = True
+        self.f = np.repeat(equilibrium(np.ones(1), np.zeros((3, 1)), np.zeros((3, 3, 1))), b.n_sites, 1)
+        self.f = self.f.reshape((Q,) + self.shape)
+        self.U = np.zeros((3,) + self.shape)
+        self.n = 0
+
+    # -------------------------------------------------------------- steps
+    def _moments(self, f):
+        rho = f.sum(0)
+        j = np.einsum("ia,i...->a...", C.astype(np.float64), f)
+        P = np.einsum("ia,ib,i...->ab...", C.astype(np.float64), C.astype(np.float64), f)
+        return rho, j, P
+
+    def _neighbour(self, a, i, sign):
+        """a(x + sign c_i) with wrap on the periodic axes (x only if periodic;
+        callers do not read across a wall)."""
+        c = C[i] * sign
+        return np.roll(a, (-c[2], -c[1], -c[0]), axis=(0, 1, 2))
+
+    def _source(self, rho):
+        """eq:sourceterm, S = F + ((mu - lambda)/rho) grad(rho), isotropic
+        stencil; across a cut link the neighbour is 2 rho(x) - rho(x - c_i),
+        or rho(x) if the opposite link is cut too."""
+        grad = np.zeros((3,) + self.shape)
+        for i in range(1, Q):
+            r = self._neighbour(rho, i, +1)
+            if self.walls is not None:
+                ext = np.where(self.cut[OPP[i]], rho, 2.0 * rho - self._neighbour(rho, i, -1))
+                r = np.where(self.cut[i], ext, r)
+            for a in range(3):
+                if C[i, a]:
+                    grad[a] += W[i] * C[i, a] * r
+        grad /= CS2
+        S = self.F[:, None, None, None] + ((self.mu - self.lam) / rho) * grad
+        return S
+
+    def _cauchy(self, rho, P):
+        """sigma = -P + (lambda - mu)(1 - rho) I (eq:poissonstress with
+        eq:approxdiv), lattice units, [3, 3, ...]."""
+        s = -P.copy()
+        for a in range(3):
+            s[a, a] += (self.lam - self.mu) * (1.0 - rho)
+        return s
+
+    def step(self, nsteps=1):
+        for _ in range(int(nsteps)):
+            f = self.f
+            rho, j, P = self._moments(f)
+            S = self._source(rho)
+            j = j + 0.5 * S
+            feq = equilibrium(rho, j, P)
+            psi = np.empty_like(f)
+            for i in range(Q):
+                psi[i] = W[i] * (C[i, 0] * S[0] + C[i, 1] * S[1] + C[i, 2] * S[2]) / CS2
+            fcol = f - (f - feq) / self.tau + (1.0 - 1.0 / (2.0 * self.tau)) * psi
+            self.U += j / rho
+            # eq:stream: f_i(x + c_i) = f_col,i(x)
+            fnew = np.empty_like(f)
+            for i in range(Q):
+                fnew[i] = self._neighbour(fcol[i], i, -1)
+            if self.walls is not None:
+                self._walls(fcol, fnew)
+            self.f = fnew
+            self.n += 1
+
+    def _walls(self, fcol, fnew):
+        """Cut links (x, i) at the walls: the population returning to x in
+        direction ibar (q = 1/2).  rho and P at x are the step's moments,
+        equal to those of f_col (collision conserves both in this closure)."""
+        rho, _, P = self._moments(fcol)
+        for side, (kind, value) in enumerate(self.walls):
+            xs = 0 if side == 0 else -1
+            normal = np.array([-1.0, 0.0, 0.0]) if side == 0 else np.array([1.0, 0.0, 0.0])
+            r = rho[:, :, xs]
+            Px = P[:, :, :, :, xs]
+            for i in range(1, Q):
+                if not self.cut[i, 0, 0, xs]:
+                    continue
+                ib = OPP[i]
+                fi = fcol[i, :, :, xs]
+                c = C[i]
+                if kind == DIRICHLET:
+                    # eq:bbcon with j* = rho(x) v*
+                    jstar = r[None] * value[:, None, None]
+                    fnew[ib, :, :, xs] = fi - 2.0 * W[i] * (c[0] * jstar[0] + c[1] * jstar[1] + c[2] * jstar[2]) / CS2
+                else:
+                    # eq:abbcon with the boundary Poisson stress of the traction
+                    sig = self._cauchy(r, Px)
+                    Pi = np.eye(3) - np.outer(normal, normal)
+                    st = np.einsum("ab,bc...,cd->ad...", Pi, sig, Pi)
+                    tn = float(value @ normal)
+                    for a in range(3):
+                        for b_ in range(3):
+                            st[a, b_] = st[a, b_] + normal[a] * value[b_] + value[a] * normal[b_] - tn * normal[a] * normal[b_]
+                    Pstar = -st
+                    for a in range(3):
+                        Pstar[a, a] = Pstar[a, a] + (self.lam - self.mu) * (1.0 - r)
+                    E = 2.0 * equilibrium(r, np.zeros((3,) + r.shape), Pstar)[i]
+                    fnew[ib, :, :, xs] = -fi + E
+
+    # ------------------------------------------------------------ fields
+    def init_fields(self, rho=None, vel=None, sigma=None, u=None):
+        """f = f_eq(rho, rho v - S/2, P(sigma, rho)), U = u - (j/rho)/2, in
+        user units; arrays [nz, ny, nx], vel and u [3, ...], sigma [6, ...]
+        (xx, yy, zz, xy, xz, yz)."""
+        r = np.ones(self.shape) if rho is None else np.asarray(rho, dtype=np.float64) / self.box.rho
+        if not (r > 0).all():
+            raise ValueError("density must be positive")
+        S = self._source(r)
+        j = np.zeros((3,) + self.shape) if vel is None else r * np.asarray(vel, dtype=np.float64) / self.s_v
+        sg = np.zeros((3, 3) + self.shape) if sigma is None else sym_to_full(np.asarray(sigma, dtype=np.float64) / self.s_sigma)
+        P = -sg
+        for a in range(3):
+            P[a, a] = P[a, a] + (self.lam - self.mu) * (1.0 - r)
+        self.f = equilibrium(r, j - 0.5 * S, P)
+        u0 = np.zeros((3,) + self.shape) if u is None else np.asarray(u, dtype=np.float64)
+        self.U = u0 - 0.5 * j / r
+        self.n = 0
+
+    def moments(self):
+        """(rho [nz,ny,nx], j [3,...], P [6,...], sigma [6,...]) in user units;
+        j includes S/2 (eq:moments)."""
+        rho, j, P = self._moments(self.f)
+        S = self._source(rho)
+        j = j + 0.5 * S
+        sig = self._cauchy(rho, P)
+        sv = self.box.rho * self.s_v
+        return (rho * self.box.rho, j * sv, full_to_sym(P) * self.s_sigma, full_to_sym(sig) * self.s_sigma)
+
+    def displacement(self):
+        """u^n = U^n + (j^n/rho^n)/2: the trapezoid rule for the integral of
+        j/rho (U holds u0 - v0/2 plus the left sum), in cells."""
+        rho, j, _ = self._moments(self.f)
+        j = j + 0.5 * self._source(rho)
+        return self.U + 0.5 * j / rho
+
+    def populations(self):
+        return self.f.copy()
+
+    def set_populations(self, f):
+        f = np.asarray(f, dtype=np.float64)
+        assert f.shape == (Q,) + self.shape
+        self.f = f.copy()

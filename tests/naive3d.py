@@ -1,0 +1,119 @@
+"""Brute-force loop form of one D3Q19 step of the solid lattice-Boltzmann
+method (test helper): explicit per-site loops and neighbour indices, written
+from the definitions (eq:moments, eq:sourceterm, eq:fieq, eq:coll,
+eq:stream, eq:bbcon, eq:abbcon at q = 1/2) without sharing code with the
+reference it checks.  Lattice units inside; the box in user units."""
+import itertools
+import math
+
+import numpy as np
+
+DIRICHLET, NEUMANN = 1, 2
+
+
+def _w(c):
+    return {0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0}[sum(a * a for a in c)]
+
+
+def _feq(c, rho, j, P):
+    cs2 = 1.0 / 3.0
+    v = rho + sum(c[a] * j[a] for a in range(3)) / cs2
+    v += sum((P[a][b] - cs2 * rho * (a == b)) * (c[a] * c[b] - cs2 * (a == b))
+             for a in range(3) for b in range(3)) / (2 * cs2 * cs2)
+    return _w(c) * v
+
+
+def naive_step(box, f, U, order):
+    """f [19, nz, ny, nx] in the direction order `order` (tuples), U [3, ...]:
+    returns (f, U) after one step."""
+    nz, ny, nx = f.shape[1:]
+    vel = list(itertools.product((-1, 0, 1), repeat=3))
+    vel = [c for c in vel if sum(a * a for a in c) <= 2]
+    assert sorted(vel) == sorted(order)
+    idx = {c: k for k, c in enumerate(order)}
+    s_sigma = 3 * box.mu
+    s_v = math.sqrt(3 * box.mu / box.rho)
+    lamL, muL = box.lam / s_sigma, box.mu / s_sigma
+    F = [a / s_sigma for a in box.force]
+    walls = box.x_walls
+    tau = box.tau
+
+    def inside_x(x):
+        return walls is None or 0 <= x < nx
+
+    def wrap(x, y, z):
+        return (x % nx, y % ny, z % nz)
+
+    rho = np.zeros((nz, ny, nx))
+    J = np.zeros((3, nz, ny, nx))
+    PP = np.zeros((3, 3, nz, ny, nx))
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        for c in vel:
+            v = f[idx[c], z, y, x]
+            rho[z, y, x] += v
+            for a in range(3):
+                J[a, z, y, x] += v * c[a]
+                for b in range(3):
+                    PP[a, b, z, y, x] += v * c[a] * c[b]
+
+    fcol = np.zeros_like(f)
+    Un = U.copy()
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        r = rho[z, y, x]
+        grad = [0.0, 0.0, 0.0]
+        for c in vel:
+            if c == (0, 0, 0):
+                continue
+            if inside_x(x + c[0]):
+                xx, yy, zz = wrap(x + c[0], y + c[1], z + c[2])
+                rn = rho[zz, yy, xx]
+            elif inside_x(x - c[0]):
+                xx, yy, zz = wrap(x - c[0], y - c[1], z - c[2])
+                rn = 2 * r - rho[zz, yy, xx]
+            else:
+                rn = r
+            for a in range(3):
+                grad[a] += 3 * _w(c) * c[a] * rn
+        S = [F[a] + (muL - lamL) / r * grad[a] for a in range(3)]
+        j = [J[a, z, y, x] + S[a] / 2 for a in range(3)]
+        P = [[PP[a, b, z, y, x] for b in range(3)] for a in range(3)]
+        for c in vel:
+            fi = f[idx[c], z, y, x]
+            psi = 3 * _w(c) * sum(c[a] * S[a] for a in range(3))
+            fcol[idx[c], z, y, x] = fi - (fi - _feq(c, r, j, P)) / tau + (1 - 1 / (2 * tau)) * psi
+        for a in range(3):
+            Un[a, z, y, x] += j[a] / r
+
+    fnew = np.zeros_like(f)
+    for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        for c in vel:
+            if inside_x(x + c[0]):
+                xx, yy, zz = wrap(x + c[0], y + c[1], z + c[2])
+                fnew[idx[c], zz, yy, xx] = fcol[idx[c], z, y, x]
+                continue
+            # the link leaves through a wall: the population returns to x
+            side = 0 if x + c[0] < 0 else 1
+            kind, value = walls[side].kind, walls[side].value
+            cb = tuple(-a for a in c)
+            fc = fcol[idx[c], z, y, x]
+            r = sum(fcol[idx[d], z, y, x] for d in vel)
+            Pm = [[sum(fcol[idx[d], z, y, x] * d[a] * d[b] for d in vel) for b in range(3)] for a in range(3)]
+            if kind == DIRICHLET:
+                vL = [v / s_v for v in value]
+                fnew[idx[cb], z, y, x] = fc - 6 * _w(c) * sum(c[a] * r * vL[a] for a in range(3))
+            else:
+                t = [v / s_sigma for v in value]
+                n = [-1.0 if side == 0 else 1.0, 0.0, 0.0]
+                sig = [[-Pm[a][b] + (lamL - muL) * (1 - r) * (a == b) for b in range(3)] for a in range(3)]
+                # boundary stress: normal part from the traction, tangential
+                # block (rows and columns y, z) from the site
+                st = [[0.0] * 3 for _ in range(3)]
+                for a in (1, 2):
+                    for b in (1, 2):
+                        st[a][b] = sig[a][b]
+                for a in range(3):
+                    st[a][0] = t[a] * n[0]
+                    st[0][a] = t[a] * n[0]
+                Ps = [[-st[a][b] + (lamL - muL) * (1 - r) * (a == b) for b in range(3)] for a in range(3)]
+                fnew[idx[cb], z, y, x] = -fc + 2 * _feq(c, r, [0.0, 0.0, 0.0], Ps)
+    return fnew, Un

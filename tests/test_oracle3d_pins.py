@@ -1,0 +1,234 @@
+"""Pins of the three-dimensional (D3Q19) CPU reference against what the
+mathematics fixes: lattice isotropy, the equilibrium's moments, conservation,
+exact patch tests of both wall rules, axis symmetry, the wave speeds of
+isotropic elasticity (sections 2-3, eq:navier), the one-dimensional step-load
+amplitude, and a brute-force loop implementation on a tiny box."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle.slbm3d import C, OPP, Q, W, Oracle3D, equilibrium, sym_to_full
+from slbm_workloads import box3d as B
+from tests.naive3d import naive_step
+
+
+def test_lattice_isotropy():
+    """D3Q19: weights sum to 1, odd moments vanish, second moment c_s^2 I,
+    fourth moment c_s^4 (delta delta + delta delta + delta delta)."""
+    d = np.eye(3)
+    assert W.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(np.einsum("i,ia->a", W, C), 0)
+    assert np.allclose(np.einsum("i,ia,ib->ab", W, C, C), d / 3)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", W, C, C, C), 0)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", W, C, C, C, C)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.allclose(m4, iso, atol=1e-15)
+    assert (C[OPP] == -C).all() and Q == 19
+
+
+def test_equilibrium_has_the_given_moments():
+    """eq:fieq: sum f_eq = rho, sum f_eq c = j, sum f_eq c c = P."""
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rho = rng.uniform(0.8, 1.2)
+        j = rng.normal(size=3) * 0.1
+        A = rng.normal(size=(3, 3)) * 0.1
+        P = A + A.T
+        f = equilibrium(np.array([rho]), j[:, None], P[:, :, None])[:, 0]
+        assert f.sum() == pytest.approx(rho, abs=1e-14)
+        assert np.allclose(C.T @ f, j, atol=1e-14)
+        assert np.allclose(np.einsum("i,ia,ib->ab", f, C, C), P, atol=1e-14)
+
+
+def test_rest_state_stays_at_rest_with_both_walls():
+    b = B.slab3(7, 3, 4, B.Wall3(B.DIRICHLET), B.Wall3(B.NEUMANN), lam=0.1, mu=0.05, tau=0.6)
+    o = Oracle3D(b)
+    f0 = o.populations()
+    o.step(6)
+    assert np.abs(o.populations() - f0).max() < 1e-14
+    assert np.abs(o.displacement()).max() < 1e-14
+
+
+def test_mass_conserved_and_momentum_gains_the_body_force():
+    """Periodic box: total mass is constant; with lambda = mu the density
+    gradient term vanishes and total momentum grows by the body force per
+    site per step (in user units, j gains rho F dt)."""
+    b = B.periodic_box3(9, 7, 6, lam=0.05, mu=0.05, tau=0.55, force=(2e-5, -1e-5, 3e-5))
+    o = Oracle3D(b)
+    o.init_fields(vel=B.random_velocity(b, 11, 1e-3))
+    r0, j0 = o.moments()[0].sum(), o.moments()[1].sum(axis=(1, 2, 3))
+    steps = 12
+    o.step(steps)
+    r1, j1 = o.moments()[0].sum(), o.moments()[1].sum(axis=(1, 2, 3))
+    assert abs(r1 - r0) < 1e-12 * r0
+    dt = o.dt_user
+    assert np.allclose(j1 - j0, np.array(b.force) * b.n_sites * steps * dt, rtol=1e-9, atol=1e-15)
+
+
+def test_momentum_not_conserved_when_lambda_differs_from_mu():
+    """The (mu - lambda)/rho grad(rho) source divides by the local density, so
+    momentum is conserved exactly only at lambda = mu: the check above would
+    not catch a dropped source term, this one does."""
+    b = B.periodic_box3(9, 7, 6, lam=0.1, mu=0.05, tau=0.6)
+    o = Oracle3D(b)
+    o.init_fields(vel=B.random_velocity(b, 12, 1e-2))
+    j0 = o.moments()[1].sum(axis=(1, 2, 3))
+    o.step(8)
+    j1 = o.moments()[1].sum(axis=(1, 2, 3))
+    assert np.abs(j1 - j0).max() > 1e-12
+
+
+def test_axis_permutation_symmetry():
+    """Cyclic relabelling x -> y -> z -> x of the initial field relabels the
+    solution the same way (the lattice is invariant under it)."""
+    b = B.periodic_box3(6, 6, 6, lam=0.08, mu=0.05, tau=0.6)
+    v = B.random_velocity(b, 5, 1e-3)
+    o1 = Oracle3D(b)
+    o1.init_fields(vel=v)
+    o1.step(5)
+    u1 = o1.displacement()
+    # array axes are (z, y, x); the map (x, y, z) -> (y, z, x) sends component x to y
+    vp = np.empty_like(v)
+    vp[1], vp[2], vp[0] = (np.moveaxis(v[k], (0, 1, 2), (2, 0, 1)) for k in range(3))
+    o2 = Oracle3D(b)
+    o2.init_fields(vel=vp)
+    o2.step(5)
+    u2 = o2.displacement()
+    for k, kp in ((0, 1), (1, 2), (2, 0)):
+        assert np.allclose(np.moveaxis(u1[k], (0, 1, 2), (2, 0, 1)), u2[kp], atol=1e-16, rtol=1e-11)
+
+
+def _mode_frequency(o, kvec, comp, steps):
+    """Angular frequency (per step) of the standing mode sum_x j(x) sin(k.x)
+    along `comp`: the slope of its zero-crossing times, each located by
+    linear interpolation between steps (damping does not move them)."""
+    nz, ny, nx = o.shape
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    s = np.sin(kvec[0] * xx + kvec[1] * yy + kvec[2] * zz)
+    a = []
+    for _ in range(steps):
+        o.step(1)
+        j = o.moments()[1]
+        a.append(float((np.tensordot(comp, j, 1) * s).sum()))
+    a = np.array(a)
+    t = np.arange(1, steps + 1)
+    zc = np.flatnonzero(np.sign(a[1:]) != np.sign(a[:-1]))
+    tc = np.array([t[i] + a[i] / (a[i] - a[i + 1]) for i in zc])
+    half = np.polyfit(np.arange(len(tc)), tc, 1)[0]
+    return np.pi / half
+
+
+@pytest.mark.parametrize("lam_over_mu", [1.0, 0.769, 2.0])
+def test_wave_speeds_along_an_axis(lam_over_mu):
+    """Shear waves travel at c_s = sqrt(mu/rho), pressure waves at
+    c_d = sqrt((lambda + 2 mu)/rho) (eq:navier), here in lattice units
+    (c_s^2 = 1/3, c_d^2 = lambda_L + 2/3), k = 2 pi/64."""
+    n = 64
+    tau = 0.6 if lam_over_mu > 1.5 else 0.55
+    k = 2 * np.pi / n
+    for comp, target in (((0.0, 1.0, 0.0), np.sqrt(1 / 3)), ((1.0, 0.0, 0.0), np.sqrt(lam_over_mu / 3 + 2 / 3))):
+        b = B.periodic_box3(n, 1, 1, lam=0.05 * lam_over_mu, mu=0.05, tau=tau)
+        o = Oracle3D(b)
+        x = np.arange(n)
+        v = np.zeros((3, 1, 1, n))
+        v[int(np.argmax(comp))] = 1e-4 * np.sin(k * x)
+        o.init_fields(vel=v)
+        w = _mode_frequency(o, (k, 0, 0), np.array(comp), 300)
+        assert w / k == pytest.approx(target, rel=3e-3), (comp, w / k, target)
+
+
+def test_wave_speeds_along_a_face_diagonal():
+    """The same speeds for k along (1, 1, 0): exercises the diagonal links
+    and their weights."""
+    n = 32
+    kk = 2 * np.pi / n
+    kvec = (kk, kk, 0.0)
+    kn = np.sqrt(2) * kk
+    b = B.periodic_box3(n, n, 1, lam=0.05, mu=0.05, tau=0.55)
+    zz, yy, xx = np.meshgrid(np.arange(1), np.arange(n), np.arange(n), indexing="ij")
+    s = np.sin(kk * xx + kk * yy)
+    for comp, target in (((1 / np.sqrt(2), -1 / np.sqrt(2), 0.0), np.sqrt(1 / 3)),
+                         ((1 / np.sqrt(2), 1 / np.sqrt(2), 0.0), np.sqrt(1.0))):
+        o = Oracle3D(b)
+        v = np.array(comp)[:, None, None, None] * 1e-4 * s[None]
+        o.init_fields(vel=v)
+        w = _mode_frequency(o, kvec, np.array(comp), 160)
+        assert w / kn == pytest.approx(target, rel=5e-3), (comp, w / kn, target)
+
+
+def test_neumann_walls_hold_a_uniform_stress():
+    """Patch test of eq:abbcon: a uniform stress with the matching tractions
+    on both walls (t* = sigma.n, n = -x and +x) is an exact steady state, for
+    every component: a wrong sign or projection in the boundary stress, or a
+    dropped tangential block, breaks it."""
+    s0 = np.array([2e-4, -1e-4, 3e-4, 1.5e-4, -2.5e-4, 0.5e-4])   # xx yy zz xy xz yz
+    S = sym_to_full(s0[:, None])[:, :, 0]
+    left = B.Wall3(B.NEUMANN, tuple(-S[:, 0]))
+    right = B.Wall3(B.NEUMANN, tuple(S[:, 0]))
+    b = B.slab3(6, 3, 2, left, right, lam=0.1, mu=0.05, tau=0.6)
+    o = Oracle3D(b)
+    sig = np.broadcast_to(s0[:, None, None, None], (6,) + o.shape)
+    o.init_fields(sigma=sig)
+    m0 = o.moments()
+    o.step(7)
+    m1 = o.moments()
+    # rounding leaves ~1e-15; a wrong rule errs by the order of the load (1e-4)
+    assert np.abs(m1[3] - sig).max() < 1e-13
+    assert np.abs(m1[1]).max() < 1e-13
+    assert np.abs(m1[0] - m0[0]).max() < 1e-13
+
+
+def test_dirichlet_walls_carry_a_uniform_translation():
+    """Patch test of eq:bbcon: walls moving with the material's uniform
+    velocity keep it in rigid translation; the displacement grows as v t."""
+    v0 = np.array([3e-4, -2e-4, 1e-4])
+    b = B.slab3(5, 2, 3, B.Wall3(B.DIRICHLET, tuple(v0)), B.Wall3(B.DIRICHLET, tuple(v0)),
+                lam=0.1, mu=0.05, tau=0.6)
+    o = Oracle3D(b)
+    o.init_fields(vel=np.broadcast_to(v0[:, None, None, None], (3,) + o.shape))
+    o.step(9)
+    rho, j, P, sig = o.moments()
+    # rounding leaves ~1e-16; a wrong rule errs by the order of v0 (1e-4)
+    assert np.abs(j - v0[:, None, None, None]).max() < 1e-13
+    assert np.abs(sig).max() < 1e-13
+    u = o.displacement()
+    assert np.abs(u - (v0 * 9 * o.dt_user)[:, None, None, None]).max() < 1e-13
+
+
+def test_step_traction_launches_the_one_dimensional_wave():
+    """A step tension sigma_xx = s0 on the face x = -1/2 of a long slab sends a
+    plane pressure wave in at c_d; behind its front the material moves with
+    v = -s0/(rho c_d) (momentum balance across the front), until the
+    reflection from the free far face returns."""
+    nx, s0 = 240, 1e-4
+    mu, lam = 0.05, 0.05
+    b = B.slab3(nx, 1, 1, B.Wall3(B.NEUMANN, (-s0, 0.0, 0.0)), B.Wall3(B.NEUMANN), lam=lam, mu=mu, tau=0.55)
+    o = Oracle3D(b)
+    cd_lat = np.sqrt(lam / mu / 3 + 2 / 3)
+    steps = int(0.75 * nx / cd_lat)
+    o.step(steps)
+    rho, j, P, sig = o.moments()
+    v = j[0, 0, 0] / rho[0, 0, 0]
+    cd_user = np.sqrt((lam + 2 * mu) / b.rho)
+    behind = v[20:int(0.5 * nx)]
+    assert np.mean(behind) == pytest.approx(-s0 / (b.rho * cd_user), rel=0.02)
+    assert np.abs(v[int(0.9 * nx):]).max() < 1e-3 * s0 / (b.rho * cd_user)
+
+
+def test_brute_force_loops_on_a_tiny_box():
+    """One step of the reference against an explicit per-site loop
+    implementation of the same definitions (tests/naive3d.py), on a 3 x 4 x 2
+    box with walls and random populations."""
+    rng = np.random.default_rng(8)
+    for walls in (None, (B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3)), B.Wall3(B.NEUMANN, (2e-4, -1e-4, 3e-4)))):
+        b = B.Box3(3, 4, 2, lam=0.09, mu=0.05, tau=0.6, force=(1e-5, 0.0, -2e-5), x_walls=walls)
+        o = Oracle3D(b)
+        f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
+        o.set_populations(f)
+        U0 = rng.normal(size=(3,) + o.shape)
+        o.U = U0.copy()
+        o.step(1)
+        fn, Un = naive_step(b, f, U0, [tuple(int(a) for a in c) for c in C])
+        assert np.abs(o.populations() - fn).max() < 1e-14
+        assert np.abs(o.U - Un).max() < 1e-14
