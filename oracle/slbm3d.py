@@ -35,6 +35,12 @@ Readings beyond the paper (the three-dimensional extension):
 
 Units: user units in and out, dx = 1 cell; lattice units inside with
 dx = dt = 1, rho0 = 1, c_s^2 = 1/3, so dt_user = sqrt(rho/(3 mu)).
+
+Precision: float64, or with ``extended=True`` the x87 80-bit long double
+(numpy.longdouble) for every array and constant.  The reference works on the
+unshifted populations, of order one, so in float64 the small deviations it
+computes (momentum, stress, displacement) carry relative rounding near 1e-12;
+the extended form is the reference for float64 parity at that level.
 """
 from __future__ import annotations
 
@@ -53,6 +59,13 @@ Q = len(C)
 W = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
 OPP = np.array([int(np.flatnonzero((C == -c).all(1))[0]) for c in C])
 CS2 = 1.0 / 3.0
+
+
+def _lattice_constants(dtype):
+    """Weights and c_s^2 formed in `dtype`."""
+    one = dtype(1)
+    w = np.array([one / 3] + [one / 18] * 6 + [one / 36] * 12, dtype=dtype)
+    return w, one / 3
 # symmetric-tensor components in the order xx, yy, zz, xy, xz, yz
 SYM = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
 
@@ -73,8 +86,10 @@ def full_to_sym(m):
 def equilibrium(rho, j, P):
     """eq:fieq on D3Q19: f_eq,i = w_i [rho + c_i.j / c_s^2
     + (P - c_s^2 rho I):(c_i c_i - c_s^2 I) / (2 c_s^4)].
-    rho [...], j [3, ...], P [3, 3, ...] -> [19, ...]."""
-    out = np.empty((Q,) + np.shape(rho))
+    rho [...], j [3, ...], P [3, 3, ...] -> [19, ...], in rho's precision."""
+    rho = np.asarray(rho)
+    W, CS2 = _lattice_constants(rho.dtype.type if rho.dtype == np.longdouble else np.float64)
+    out = np.empty((Q,) + np.shape(rho), dtype=rho.dtype if rho.dtype == np.longdouble else np.float64)
     for i in range(Q):
         c = C[i]
         cj = c[0] * j[0] + c[1] * j[1] + c[2] * j[2]
@@ -90,8 +105,10 @@ class Oracle3D:
     """One box advanced by the reference.  ``box`` is a
     :class:`slbm_workloads.box3d.Box3`."""
 
-    def __init__(self, box):
+    def __init__(self, box, extended: bool = False):
         b = box
+        self.dt = np.longdouble if extended else np.float64
+        self.W, self.cs2 = _lattice_constants(self.dt)
         if not (b.mu > 0 and b.rho > 0):
             raise ValueError("mu and rho must be positive")
         if not b.tau > 0.5:
@@ -102,10 +119,10 @@ class Oracle3D:
         self.dt_user = np.sqrt(b.rho / (3.0 * b.mu))
         self.s_sigma = 3.0 * b.mu
         self.s_v = 1.0 / self.dt_user
-        self.mu = b.mu / self.s_sigma
-        self.lam = b.lam / self.s_sigma
-        self.tau = float(b.tau)
-        self.F = np.array(b.force, dtype=np.float64) / self.s_sigma
+        self.mu = self.dt(b.mu) / self.dt(self.s_sigma)
+        self.lam = self.dt(b.lam) / self.dt(self.s_sigma)
+        self.tau = self.dt(b.tau)
+        self.F = np.array(b.force, dtype=self.dt) / self.dt(self.s_sigma)
         self.walls = None
         if b.x_walls is not None:
             self.walls = []
@@ -113,7 +130,7 @@ class Oracle3D:
                 if wall.kind not in (DIRICHLET, NEUMANN):
                     raise ValueError("wall kind must be Dirichlet or Neumann")
                 scale = self.s_v if wall.kind == DIRICHLET else self.s_sigma
-                self.walls.append((wall.kind, np.array(wall.value, dtype=np.float64) / scale))
+                self.walls.append((wall.kind, np.array(wall.value, dtype=self.dt) / self.dt(scale)))
         # cut[i] marks the sites whose link i leaves the material through a wall
         self.cut = np.zeros((Q,) + self.shape, dtype=bool)
         if self.walls is not None:
@@ -122,16 +139,18 @@ class Oracle3D:
                     self.cut[i, :, :, 0] = True
                 elif C[i, 0] > 0:
                     self.cut[i, :, :, -1] = True
-        self.f = np.repeat(equilibrium(np.ones(1), np.zeros((3, 1)), np.zeros((3, 3, 1))), b.n_sites, 1)
+        self.f = np.repeat(equilibrium(np.ones(1, dtype=self.dt), np.zeros((3, 1), dtype=self.dt),
+                                       np.zeros((3, 3, 1), dtype=self.dt)), b.n_sites, 1)
         self.f = self.f.reshape((Q,) + self.shape)
-        self.U = np.zeros((3,) + self.shape)
+        self.U = np.zeros((3,) + self.shape, dtype=self.dt)
         self.n = 0
 
     # -------------------------------------------------------------- steps
     def _moments(self, f):
+        c = C.astype(self.dt)
         rho = f.sum(0)
-        j = np.einsum("ia,i...->a...", C.astype(np.float64), f)
-        P = np.einsum("ia,ib,i...->ab...", C.astype(np.float64), C.astype(np.float64), f)
+        j = np.einsum("ia,i...->a...", c, f)
+        P = np.einsum("ia,ib,i...->ab...", c, c, f)
         return rho, j, P
 
     def _neighbour(self, a, i, sign):
@@ -144,7 +163,7 @@ class Oracle3D:
         """eq:sourceterm, S = F + ((mu - lambda)/rho) grad(rho), isotropic
         stencil; across a cut link the neighbour is 2 rho(x) - rho(x - c_i),
         or rho(x) if the opposite link is cut too."""
-        grad = np.zeros((3,) + self.shape)
+        grad = np.zeros((3,) + self.shape, dtype=self.dt)
         for i in range(1, Q):
             r = self._neighbour(rho, i, +1)
             if self.walls is not None:
@@ -152,8 +171,8 @@ class Oracle3D:
                 r = np.where(self.cut[i], ext, r)
             for a in range(3):
                 if C[i, a]:
-                    grad[a] += W[i] * C[i, a] * r
-        grad /= CS2
+                    grad[a] += self.W[i] * C[i, a] * r
+        grad /= self.cs2
         S = self.F[:, None, None, None] + ((self.mu - self.lam) / rho) * grad
         return S
 
@@ -174,8 +193,8 @@ class Oracle3D:
             feq = equilibrium(rho, j, P)
             psi = np.empty_like(f)
             for i in range(Q):
-                psi[i] = W[i] * (C[i, 0] * S[0] + C[i, 1] * S[1] + C[i, 2] * S[2]) / CS2
-            fcol = f - (f - feq) / self.tau + (1.0 - 1.0 / (2.0 * self.tau)) * psi
+                psi[i] = self.W[i] * (C[i, 0] * S[0] + C[i, 1] * S[1] + C[i, 2] * S[2]) / self.cs2
+            fcol = f - (f - feq) / self.tau + (1 - 1 / (2 * self.tau)) * psi
             self.U += j / rho
             # eq:stream: f_i(x + c_i) = f_col,i(x)
             fnew = np.empty_like(f)
@@ -197,7 +216,9 @@ class Oracle3D:
             r = rho[:, :, xs]
             Px = P[:, :, :, :, xs]
             for i in range(1, Q):
-                if not self.cut[i, 0, 0, xs]:
+                # the links this wall cuts: those that leave the material
+                # through it (with nx = 1 both walls act on the same sites)
+                if C[i, 0] != (-1 if side == 0 else 1):
                     continue
                 ib = OPP[i]
                 fi = fcol[i, :, :, xs]
@@ -205,20 +226,20 @@ class Oracle3D:
                 if kind == DIRICHLET:
                     # eq:bbcon with j* = rho(x) v*
                     jstar = r[None] * value[:, None, None]
-                    fnew[ib, :, :, xs] = fi - 2.0 * W[i] * (c[0] * jstar[0] + c[1] * jstar[1] + c[2] * jstar[2]) / CS2
+                    fnew[ib, :, :, xs] = fi - 2 * self.W[i] * (c[0] * jstar[0] + c[1] * jstar[1] + c[2] * jstar[2]) / self.cs2
                 else:
                     # eq:abbcon with the boundary Poisson stress of the traction
                     sig = self._cauchy(r, Px)
-                    Pi = np.eye(3) - np.outer(normal, normal)
+                    Pi = (np.eye(3) - np.outer(normal, normal)).astype(self.dt)
                     st = np.einsum("ab,bc...,cd->ad...", Pi, sig, Pi)
-                    tn = float(value @ normal)
+                    tn = value @ normal
                     for a in range(3):
                         for b_ in range(3):
                             st[a, b_] = st[a, b_] + normal[a] * value[b_] + value[a] * normal[b_] - tn * normal[a] * normal[b_]
                     Pstar = -st
                     for a in range(3):
                         Pstar[a, a] = Pstar[a, a] + (self.lam - self.mu) * (1.0 - r)
-                    E = 2.0 * equilibrium(r, np.zeros((3,) + r.shape), Pstar)[i]
+                    E = 2 * equilibrium(r, np.zeros((3,) + r.shape, dtype=self.dt), Pstar)[i]
                     fnew[ib, :, :, xs] = -fi + E
 
     # ------------------------------------------------------------ fields
@@ -226,17 +247,19 @@ class Oracle3D:
         """f = f_eq(rho, rho v - S/2, P(sigma, rho)), U = u - (j/rho)/2, in
         user units; arrays [nz, ny, nx], vel and u [3, ...], sigma [6, ...]
         (xx, yy, zz, xy, xz, yz)."""
-        r = np.ones(self.shape) if rho is None else np.asarray(rho, dtype=np.float64) / self.box.rho
+        r = np.ones(self.shape, dtype=self.dt) if rho is None else np.asarray(rho, dtype=self.dt) / self.dt(self.box.rho)
         if not (r > 0).all():
             raise ValueError("density must be positive")
         S = self._source(r)
-        j = np.zeros((3,) + self.shape) if vel is None else r * np.asarray(vel, dtype=np.float64) / self.s_v
-        sg = np.zeros((3, 3) + self.shape) if sigma is None else sym_to_full(np.asarray(sigma, dtype=np.float64) / self.s_sigma)
+        j = np.zeros((3,) + self.shape, dtype=self.dt) if vel is None else \
+            r * np.asarray(vel, dtype=self.dt) / self.dt(self.s_v)
+        sg = np.zeros((3, 3) + self.shape, dtype=self.dt) if sigma is None else \
+            sym_to_full(np.asarray(sigma, dtype=self.dt) / self.dt(self.s_sigma))
         P = -sg
         for a in range(3):
             P[a, a] = P[a, a] + (self.lam - self.mu) * (1.0 - r)
         self.f = equilibrium(r, j - 0.5 * S, P)
-        u0 = np.zeros((3,) + self.shape) if u is None else np.asarray(u, dtype=np.float64)
+        u0 = np.zeros((3,) + self.shape, dtype=self.dt) if u is None else np.asarray(u, dtype=self.dt)
         self.U = u0 - 0.5 * j / r
         self.n = 0
 
@@ -248,19 +271,20 @@ class Oracle3D:
         j = j + 0.5 * S
         sig = self._cauchy(rho, P)
         sv = self.box.rho * self.s_v
-        return (rho * self.box.rho, j * sv, full_to_sym(P) * self.s_sigma, full_to_sym(sig) * self.s_sigma)
+        out = (rho * self.box.rho, j * sv, full_to_sym(P) * self.s_sigma, full_to_sym(sig) * self.s_sigma)
+        return tuple(np.asarray(a, dtype=np.float64) for a in out)
 
     def displacement(self):
         """u^n = U^n + (j^n/rho^n)/2: the trapezoid rule for the integral of
         j/rho (U holds u0 - v0/2 plus the left sum), in cells."""
         rho, j, _ = self._moments(self.f)
-        j = j + 0.5 * self._source(rho)
-        return self.U + 0.5 * j / rho
+        j = j + self._source(rho) / 2
+        return np.asarray(self.U + j / rho / 2, dtype=np.float64)
 
     def populations(self):
-        return self.f.copy()
+        return np.asarray(self.f, dtype=np.float64)
 
     def set_populations(self, f):
-        f = np.asarray(f, dtype=np.float64)
+        f = np.asarray(f, dtype=self.dt)
         assert f.shape == (Q,) + self.shape
         self.f = f.copy()

@@ -218,11 +218,13 @@ def test_step_traction_launches_the_one_dimensional_wave():
 
 def test_brute_force_loops_on_a_tiny_box():
     """One step of the reference against an explicit per-site loop
-    implementation of the same definitions (tests/naive3d.py), on a 3 x 4 x 2
-    box with walls and random populations."""
+    implementation of the same definitions (tests/naive3d.py), on 3 x 4 x 2
+    boxes with and without walls and on 1 x 4 x 2 slabs (both walls on the
+    same sites), with random populations."""
     rng = np.random.default_rng(8)
-    for walls in (None, (B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3)), B.Wall3(B.NEUMANN, (2e-4, -1e-4, 3e-4)))):
-        b = B.Box3(3, 4, 2, lam=0.09, mu=0.05, tau=0.6, force=(1e-5, 0.0, -2e-5), x_walls=walls)
+    walls2 = (B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3)), B.Wall3(B.NEUMANN, (2e-4, -1e-4, 3e-4)))
+    for nx, walls in ((3, None), (3, walls2), (1, walls2), (1, walls2[::-1])):
+        b = B.Box3(nx, 4, 2, lam=0.09, mu=0.05, tau=0.6, force=(1e-5, 0.0, -2e-5), x_walls=walls)
         o = Oracle3D(b)
         f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
         o.set_populations(f)
