@@ -9,6 +9,7 @@ the fused kernel.  The default workload is the 1024 x 512 edge-crack plate
     python bench.py [--steps K] [--warmup W] [--workload NAME]
     python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
     python bench.py --workload serve       # served requests: continuous batching vs one at a time
+    python bench.py --workload cube256     # the three-dimensional (D3Q19) step on a 256^3 slab
 
 Prints one JSON line.  `value` is material-site updates per second (MLUPS)
 with the state resident in HBM; the roofline object relates the fused
@@ -112,6 +113,106 @@ def copy_ceiling(slbm, torch, dev, stream):
     c1.record(stream)
     torch.cuda.synchronize()
     return round(2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
+
+
+def bytes_per_site3(prec):
+    # D3Q19 populations read once and written once, displacement (3 x fp64) read and written once
+    return 19 * 2 * (4 if prec == "fp32" else 8) + 3 * 2 * 8
+
+
+def measured_traffic3(box, prec):
+    """Calibrated counter bytes per step of the two 3-D kernels
+    (profiles/traffic_<box>_<precision>.json), or None when there is none or
+    the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{box.name}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2208_04088_amd.build import kernel_fingerprint
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_fingerprint") != kernel_fingerprint("step3_kernel.h"):
+        return None
+    shapes = d.get("shapes", {})
+    parts = [shapes.get(k) for k in ("k3_density", "k3_step")]
+    return None if None in parts else sum(p["traffic_bytes_per_launch"] for p in parts)
+
+
+def cpu_baseline3(box, budget_s=15.0):
+    """The CPU reference (numpy, fp64) on a bounded sample: a 64^3 box of the
+    same configuration, stepped for about `budget_s` seconds."""
+    import numpy as np
+    from oracle.slbm3d import Oracle3D
+    from slbm_workloads import box3d as B
+    n = min(64, box.nx)
+    sample = B.Box3(n, min(64, box.ny), min(64, box.nz), lam=box.lam, mu=box.mu, tau=box.tau, rho=box.rho,
+                    force=box.force, x_walls=box.x_walls, name=f"{box.name}-sample{n}")
+    o = Oracle3D(sample)
+    o.step(1)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        k += 1
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS", "")
+    return {"value": round(sample.n_sites * k / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": int(threads) if threads.isdigit() else 1, "kind": "oracle",
+            "sample": f"{k} steps of a {sample.nx}x{sample.ny}x{sample.nz} box of the same configuration "
+                      f"({sample.n_sites} sites), numpy fp64, {dt:.1f} s"}
+
+
+def run_3d(args, torch, dev, stream, n):
+    """The three-dimensional (D3Q19) step on an n^3 slab: face x = -1/2
+    clamped, face x = n - 1/2 pulled by a step traction, periodic in y and z;
+    fp32 populations, fp64 displacement, from rest.  One bench step is one
+    time step of the whole box (two launches: density pass, step)."""
+    import numpy as np
+    from paper_2208_04088_amd import slbm3
+    from slbm_workloads import box3d as B
+    steps = args.steps if args.steps_given else 1000
+    box = B.cube_pulled(n, steps=steps)
+    prec = args.precision or "fp32"
+    s = slbm3.Solver3(box, prec, device=0, stream=stream.cuda_stream)
+    warm = min(args.warmup, 100)
+    s.step(warm)
+    s.sync()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(steps)
+    ev1.record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    t_step = ev0.elapsed_time(ev1) / 1e3 / steps
+    assert np.isfinite(s.displacement()).all()
+    sites = box.n_sites
+    bps = bytes_per_site3(prec)
+    achieved = sites * bps / t_step / 1e9
+    from paper_2208_04088_amd import slbm
+    result = {
+        "metric": "MLUPS (site updates per second) of the D3Q19 solid-LBM step",
+        "value": round(sites / t_step / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": round(t_step * 1e3, 6), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "sites": sites,
+                   "precision": "fp32 populations and arithmetic, fp64 displacement" if prec == "fp32" else "fp64",
+                   "lambda_over_mu": box.lam / box.mu, "tau": box.tau,
+                   "bench_step": "one D3Q19 time step of the whole box (density pass and step kernel)",
+                   "wall_s": round(wall, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic3(box, prec),
+                     "kernel": "k3_density + k3_step", "bytes_per_site": bps, "launches_per_step": 2,
+                     "avg_step_us": round(t_step * 1e6, 3),
+                     "note": "achieved counts the step's algorithmic bytes over the time of both launches; "
+                             "the density pass re-reads the pulled populations (traffic: measured bytes per step)"},
+    }
+    result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
+    s.close()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline3(box)
+    print(json.dumps(result), flush=True)
 
 
 def run_batch(args, slbm, torch, dev, stream):
@@ -315,6 +416,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args, slbm, torch, dev, stream)
+        return
+    if args.workload.startswith("cube"):
+        run_3d(args, torch, dev, stream, int(args.workload[4:] or 256))
         return
 
     plate, prec = workload(args.workload)

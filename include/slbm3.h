@@ -1,0 +1,115 @@
+/*
+ * slbm3.h -- C ABI of the three-dimensional (D3Q19) solid lattice-Boltzmann
+ * step in libslbm.so.
+ *
+ * The paper (Faust, Schlueter, H. Mueller, R. Mueller, 2022) states its
+ * method in two dimensions and notes that its local boundary rules carry
+ * over to three (section 1).  This is that three-dimensional form: the same
+ * moments (eq:moments), source term with the density gradient
+ * (eq:sourceterm), equilibrium with the populations' own second moment
+ * (eq:fieq), BGK collision with forcing (eq:coll), streaming (eq:stream) and
+ * displacement integration, on the D3Q19 lattice (c_s^2 = 1/3, weights 1/3,
+ * 1/18, 1/36).
+ *
+ * Geometry
+ *   A box of nx x ny x nz sites at integer coordinates, periodic in y and z.
+ *   In x it is either periodic or closed by two lattice-conforming walls at
+ *   x = -1/2 and x = nx - 1/2 (every cut link has q = 1/2).  A Dirichlet wall
+ *   carries a wall velocity, with the rule of eq:bbcon.  A Neumann wall
+ *   carries a traction t* (the stress times the outward normal of the
+ *   material: -x at the first wall, +x at the second), with the rule of
+ *   eq:abbcon.  That rule's boundary Cauchy stress is
+ *   sigma* = Pi sigma(x) Pi + n t* + t* n - (t*.n) n n, with Pi = I - n n and
+ *   sigma(x) the stress at the boundary site.  Both walls apply from the
+ *   first step.
+ *
+ * Host arrays
+ *   Arrays are [component][nz][ny][nx] of doubles, x fastest.  The site index
+ *   is (iz*ny + iy)*nx + ix.  Vectors have three components (x, y, z).
+ *   Symmetric tensors have six, in the order xx, yy, zz, xy, xz, yz.
+ *
+ * Units, ownership, threading and errors
+ *   As in slbm.h: user units with dx = 1 and dt = sqrt(rho/(3 mu)); every
+ *   input is copied and the library owns its device memory.  A handle is not
+ *   shared between threads.  Work is queued on the handle's stream, and calls
+ *   that return host data synchronise it.  The status codes and
+ *   slbm_last_error() are those of slbm.h.
+ */
+#ifndef SLBM3_H
+#define SLBM3_H
+
+#include <stdint.h>
+
+#include "slbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slbm3_s* slbm3_handle;
+
+typedef struct {
+    int32_t kind;                /* SLBM_DIRICHLET (value: wall velocity) or SLBM_NEUMANN (value: traction) */
+    double value[3];             /* user units */
+} slbm3_wall;
+
+typedef struct {
+    int32_t nx, ny, nz;          /* sites, each >= 1; at most 2^29 in total */
+    double lambda, mu, rho;      /* user units; mu > 0, rho > 0, lambda > -mu */
+    double tau_bar;              /* relaxation time in units of dt, > 1/2 */
+    double body_force[3];        /* per volume, user units */
+    int32_t periodic_x;          /* 1: periodic in x; 0: the two walls below */
+    slbm3_wall walls[2];         /* at x = -1/2 and at x = nx - 1/2 (ignored when periodic_x) */
+    int32_t precision;           /* SLBM_FP64, or SLBM_FP32 (fp32 populations and arithmetic, fp64 U) */
+    int32_t device;              /* HIP device ordinal */
+    void* stream;                /* hipStream_t to queue work on; NULL: a stream owned by the handle */
+} slbm3_params;
+
+/* Creates a box at rest (f = f_eq(rho, 0, 0), U = 0, step 0).  SLBM_E_INVAL
+ * for invalid parameters, SLBM_E_UNSUPPORTED above 2^29 sites, SLBM_E_NOMEM
+ * or SLBM_E_DEVICE if allocation fails; *out is NULL on failure. */
+int slbm3_create(const slbm3_params* params, slbm3_handle* out);
+
+/* Sets the state from fields (any pointer may be NULL: density rho, velocity
+ * 0, stress 0, displacement 0):
+ *   f = f_eq(rho, rho v - S/2, P), with P = -sigma + (lambda - mu)(1 - rho/rho0) I;
+ *   U = u - (j/rho)/2.
+ * The step count is reset to 0.  Arrays: rho [n], vel [3][n], sigma [6][n],
+ * u [3][n].  SLBM_E_INVAL for a non-positive density.  Synchronises. */
+int slbm3_init_fields(slbm3_handle h, const double* rho, const double* vel, const double* sigma,
+                      const double* u);
+
+/* Queues nsteps time steps (two launches each). */
+int slbm3_step(slbm3_handle h, int64_t nsteps);
+
+/* Waits for queued work.  SLBM_E_DIVERGED if a step produced a non-finite
+ * value since creation or the last slbm3_init_fields. */
+int slbm3_sync(slbm3_handle h);
+
+/* Moments of the current state, in user units.  These are the density rho
+ * [n], the momentum j [3][n] (with the half source term, eq:moments), the
+ * second moment P [6][n] and the Cauchy stress sigma [6][n]
+ * (eq:poissonstress with eq:approxdiv).  Any output pointer may be NULL.
+ * Synchronises. */
+int slbm3_moments(slbm3_handle h, double* rho, double* j, double* P, double* sigma);
+
+/* Displacement u [3][n] in cells: U + (j/rho)/2, the trapezoid rule for the
+ * integral of j/rho.  Synchronises. */
+int slbm3_displacement(slbm3_handle h, double* u);
+
+/* Steps taken since creation or the last slbm3_init_fields, and that time in
+ * user units. */
+int slbm3_time(slbm3_handle h, int64_t* step, double* t_user);
+
+/* Device memory held by the handle, in bytes. */
+int slbm3_device_bytes(slbm3_handle h, int64_t* bytes);
+
+/* Frees the handle and its device memory after the queued work; NULL is a
+ * no-op. */
+int slbm3_destroy(slbm3_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

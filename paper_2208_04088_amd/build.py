@@ -23,13 +23,14 @@ HIPCC_FLAGS = [
 ]
 
 
-def kernel_fingerprint():
-    """SHA-256 (16 hex digits) of the step kernel's source and the build
-    flags: hardware-counter readings are only valid for the kernel they were
-    taken on (its launch shape is recorded beside them)."""
+def kernel_fingerprint(source="step_kernel.h"):
+    """SHA-256 (16 hex digits) of a kernel source (the two-dimensional step
+    kernels by default, step3_kernel.h for the three-dimensional ones) and the
+    build flags: hardware-counter readings are only valid for the kernel they
+    were taken on (its launch shape is recorded beside them)."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(HERE, "csrc", "step_kernel.h"), "rb") as fh:
+    with open(os.path.join(HERE, "csrc", source), "rb") as fh:
         h.update(fh.read())
     h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]

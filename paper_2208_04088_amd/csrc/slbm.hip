@@ -1450,3 +1450,7 @@ int slbm_batch_destroy(slbm_batch b)
 const char* slbm_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ------------------------------------------------ three-dimensional step
+
+#include "slbm3_api.h"

@@ -99,6 +99,8 @@ def main():
     q.add_argument("--rows", type=int, required=True)
     q.add_argument("--strip", type=int, required=True)
     q.add_argument("--out", required=True)
+    q.add_argument("--source", default="step_kernel.h", help="kernel source the fingerprint covers")
+    q.add_argument("--key", default=None, help="entry name (default: <rows>x<strip>)")
     a = ap.parse_args()
     if a.cmd == "trace":
         print(f"{'kernel':<58} {'calls':>6} {'avg us':>9} {'median':>9} {'min':>9} {'max':>9}")
@@ -110,16 +112,18 @@ def main():
     if os.path.exists(a.out):
         with open(a.out) as fh:
             d = json.load(fh)
-    if d.get("kernel_fingerprint") != kernel_fingerprint():
+    fp = kernel_fingerprint(a.source)
+    if d.get("kernel_fingerprint") != fp:
         d = {}
-    d.update({"kernel_fingerprint": kernel_fingerprint(), "workload": a.workload, "precision": a.precision,
+    d.update({"kernel_fingerprint": fp, "workload": a.workload, "precision": a.precision,
               "copy_kernel": a.copy_kernel, "copy_bytes": a.copy_bytes})
     t = traffic(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes)
     t["kernel"] = a.kernel
-    d.setdefault("shapes", {})[f"{a.rows}x{a.strip}"] = t
+    key = a.key or f"{a.rows}x{a.strip}"
+    d.setdefault("shapes", {})[key] = t
     with open(a.out, "w") as fh:
         json.dump(d, fh, indent=1)
-    print(json.dumps(d["shapes"][f"{a.rows}x{a.strip}"]))
+    print(json.dumps(d["shapes"][key]))
 
 
 if __name__ == "__main__":

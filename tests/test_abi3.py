@@ -1,0 +1,95 @@
+"""The three-dimensional C ABI without a GPU: libslbm.so exports every
+function include/slbm3.h declares, slbm3_params has the header's layout,
+invalid boxes are rejected on the host, and a valid one fails loudly when no
+device is present."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2208_04088_amd import slbm as S
+from paper_2208_04088_amd import slbm3 as S3
+from slbm_workloads import box3d as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slbm3.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slbm3_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = S3.lib()
+    names = declared_functions()
+    assert len(names) == 9
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(S3.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout3.c"
+    cname = {"lam": "lambda", "tau": "tau_bar"}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "slbm3.h"', "int main(void){",
+             'printf("slbm3_params %zu\\n", sizeof(slbm3_params));',
+             'printf("slbm3_wall %zu\\n", sizeof(slbm3_wall));',
+             'printf("slbm3_wall.value %zu\\n", offsetof(slbm3_wall, value));']
+    for f, _ in S3.Params3._fields_:
+        lines.append(f'printf("slbm3_params.{f} %zu\\n", offsetof(slbm3_params, {cname.get(f, f)}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout3"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.split("\n") if l)
+    assert int(out["slbm3_params"]) == C.sizeof(S3.Params3)
+    assert int(out["slbm3_wall"]) == C.sizeof(S3.Wall)
+    assert int(out["slbm3_wall.value"]) == S3.Wall.value.offset
+    for f, _ in S3.Params3._fields_:
+        assert int(out[f"slbm3_params.{f}"]) == getattr(S3.Params3, f).offset, f
+
+
+def _create(box, **over):
+    prm = S3.marshal(box, "fp32")
+    for k, v in over.items():
+        setattr(prm, k, v)
+    h = C.c_void_p()
+    L = S3.lib()
+    rc = L.slbm3_create(C.byref(prm), C.byref(h))
+    if rc == 0:
+        L.slbm3_destroy(h)
+    return rc, L.slbm_last_error().decode()
+
+
+def _slab():
+    return B.slab3(8, 4, 3, B.Wall3(B.DIRICHLET), B.Wall3(B.NEUMANN, (1e-5, 0.0, 0.0)))
+
+
+@pytest.mark.parametrize("case", ["nx", "nz", "tau", "mu", "rho", "lambda", "precision", "wall_kind"])
+def test_invalid_boxes_are_rejected_on_the_host(case):
+    over = {"nx": dict(nx=0), "nz": dict(nz=-2), "tau": dict(tau=0.5), "mu": dict(mu=0.0),
+            "rho": dict(rho=-1.0), "lambda": dict(lam=-0.06), "precision": dict(precision=5)}.get(case, {})
+    box = _slab()
+    if case == "wall_kind":
+        box.x_walls = (B.Wall3(3), box.x_walls[1])
+    rc, msg = _create(box, **over)
+    assert rc == -1, (rc, msg)
+    assert msg
+
+
+def test_too_large_a_box_is_unsupported():
+    rc, msg = _create(B.periodic_box3(1024, 1024, 512))
+    assert rc == -5, (rc, msg)
+
+
+def test_valid_box_without_a_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, msg = _create(_slab())
+    assert rc == -3, (rc, msg)

@@ -1,0 +1,147 @@
+"""Parity of the three-dimensional HIP step (include/slbm3.h) with the CPU
+reference (oracle/slbm3d.py), element by element on the same seeded inputs:
+fp64 within 1e-12 relative L2 (against the reference's extended-precision
+form), fp32 (fp64 displacement) within 1e-4.  Boxes are ragged against the
+kernels' 64-site row chunks."""
+import numpy as np
+import pytest
+
+from oracle.slbm3d import Oracle3D
+from slbm_workloads import box3d as B
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def S3():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_04088_amd import slbm3
+    slbm3.lib()
+    return slbm3
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def err(a, b, unit):
+    """(relative L2 error, whether it is within the rounding floor): the
+    floor, 1e-15 sqrt(N) lattice units of the quantity (`unit` converts one
+    lattice unit to user units), covers fields that are zero in exact
+    arithmetic, such as the displacement before the first step."""
+    d = float(np.linalg.norm(a - b))
+    return d / max(float(np.linalg.norm(b)), 1e-300), d <= 1e-15 * np.sqrt(a.size) * unit
+
+
+def units(box):
+    """User units of one lattice unit: velocity, stress."""
+    return np.sqrt(3 * box.mu / box.rho), 3 * box.mu
+
+
+def run_both(S3, box, prec, steps, fields=None):
+    s = S3.Solver3(box, prec)
+    # fp64 parity at 1e-12 needs the reference's extended form: in float64 it
+    # rounds its unshifted populations at about that level itself
+    o = Oracle3D(box, extended=(prec == "fp64"))
+    if fields is not None:
+        s.init_fields(**fields)
+        o.init_fields(**fields)
+    s.step(steps)
+    o.step(steps)
+    s.sync()
+    out = (s.displacement(), s.moments())
+    ref = (o.displacement(), o.moments())
+    st, t = s.time()
+    assert st == steps
+    s.close()
+    return out, ref
+
+
+def check(out, ref, tol, what, box):
+    """Relative L2 of the displacement (cells), rho, j, P and sigma, each
+    with its rounding floor."""
+    (u, (rho, j, P, sig)), (ur, (rr, jr, Pr, sr)) = out, ref
+    sv, ss = units(box)
+    errs = {"u": err(u, ur, 1.0), "rho": err(rho, rr, box.rho),
+            "j": err(j, jr, box.rho * sv), "P": err(P, Pr, ss), "sigma": err(sig, sr, ss)}
+    print(what, {k: f"{v[0]:.2e}" + (" (floor)" if v[1] else "") for k, v in errs.items()})
+    for k, (v, small) in errs.items():
+        assert v <= tol or small, (what, k, v)
+
+
+@pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 30), ("fp32", FP32_TOL, 200)])
+def test_periodic_box(S3, prec, tol, steps):
+    box = B.periodic_box3(40, 12, 10, lam=0.08, mu=0.05, tau=0.6, force=(1e-6, -2e-6, 0.5e-6))
+    fields = dict(vel=B.random_velocity(box, 21, 1e-3))
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"periodic {prec}", box)
+
+
+@pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 40), ("fp32", FP32_TOL, 300)])
+def test_slab_with_both_wall_kinds(S3, prec, tol, steps):
+    box = B.slab3(70, 6, 5, B.Wall3(B.DIRICHLET, (2e-4, -1e-4, 3e-4)), B.Wall3(B.NEUMANN, (1e-4, 2e-5, -3e-5)),
+                  lam=0.05, mu=0.05, tau=0.55)
+    fields = dict(vel=B.random_velocity(box, 22, 5e-4))
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"slab {prec}", box)
+
+
+@pytest.mark.parametrize("kinds", [(B.NEUMANN, B.NEUMANN), (B.DIRICHLET, B.DIRICHLET), (B.NEUMANN, B.DIRICHLET)])
+def test_single_site_thick_slab(S3, kinds):
+    """nx = 1: both walls act on the same sites."""
+    box = B.slab3(1, 7, 9, B.Wall3(kinds[0], (1e-4, 0.0, 2e-5)), B.Wall3(kinds[1], (-2e-4, 1e-5, 0.0)),
+                  lam=0.05, mu=0.05, tau=0.6)
+    fields = dict(vel=B.random_velocity(box, 23, 1e-4))
+    out, ref = run_both(S3, box, "fp64", 25, fields)
+    check(out, ref, FP64_TOL, f"nx=1 {kinds}", box)
+
+
+def test_initial_fields_all_given(S3):
+    box = B.slab3(66, 5, 4, B.Wall3(B.NEUMANN), B.Wall3(B.DIRICHLET), lam=0.1, mu=0.05, tau=0.6)
+    rng = np.random.default_rng(24)
+    shape = (box.nz, box.ny, box.nx)
+    fields = dict(rho=1.0 + 1e-4 * rng.standard_normal(shape), vel=B.random_velocity(box, 25, 2e-4),
+                  sigma=1e-5 * rng.standard_normal((6,) + shape), u=1e-3 * rng.standard_normal((3,) + shape))
+    for steps in (0, 7):
+        out, ref = run_both(S3, box, "fp64", steps, fields)
+        check(out, ref, FP64_TOL, f"init fields, {steps} steps", box)
+
+
+def test_rest_stays_at_rest(S3):
+    box = B.slab3(9, 3, 3, B.Wall3(B.DIRICHLET), B.Wall3(B.NEUMANN))
+    for prec in ("fp32", "fp64"):
+        s = S3.Solver3(box, prec)
+        s.step(10)
+        s.sync()
+        assert np.abs(s.displacement()).max() == 0.0
+        assert np.abs(s.moments()[1]).max() == 0.0
+        s.close()
+
+
+def test_non_finite_state_is_reported(S3):
+    from paper_2208_04088_amd import slbm
+    box = B.periodic_box3(8, 4, 4)
+    s = S3.Solver3(box, "fp32")
+    v = np.zeros((3,) + (box.nz, box.ny, box.nx))
+    v[0, 1, 2, 3] = np.inf
+    s.init_fields(vel=v)
+    s.step(3)
+    with pytest.raises(slbm.SlbmError) as e:
+        s.sync()
+    assert e.value.code == -4
+    s.close()
+
+
+@pytest.mark.slow
+def test_cube128_fp32_against_the_reference(S3):
+    """The benchmark's kind of box at 128^3: pulled slab, fp32, 20 steps from
+    a random velocity field, every site against the reference."""
+    box = B.cube_pulled(128, steps=20)
+    fields = dict(vel=B.random_velocity(box, 26, 1e-4, smooth=3))
+    out, ref = run_both(S3, box, "fp32", 20, fields)
+    check(out, ref, FP32_TOL, "cube128 fp32", box)
