@@ -74,6 +74,170 @@ __device__ __forceinline__ real geq3(real dr, const real j[3], const real P[6])
     return v;
 }
 
+// ------------------------------------------------------ ghost moments
+//
+// The collision of eq:coll leaves rho and P unchanged and adds S to j (the
+// equilibrium carries the populations' own second moment).  It is applied as
+//   g_i <- g_i + T_i(S) + sum_k a_k n_k,i
+// with T(S) = (S_a/2)(e_{+a} - e_{-a}) on the axis links, whose zeroth,
+// first and second moments are exactly 0, S and 0 in floating point, and nine
+// integer ghost vectors n_k orthogonal to 1, c and c c (an orthogonal D3Q19
+// moment basis: epsilon, q_x, q_y, q_z, 3 pi_xx, pi_ww, m_x, m_y, m_z).  The
+// coefficients a_k are the projections of the BGK change onto the n_k:
+//   a_k = [omega (E_k - m_k) + (1 - omega/2) Psi_k - tau_k] / N_k,
+// m_k = n_k.g, E_k = n_k.g_eq, Psi_k = n_k.psi, tau_k = n_k.T, N_k = n_k.n_k.
+// In exact arithmetic this is the BGK update; in floating point the conserved
+// moments change only by unbiased rounding, whereas rounded equilibrium
+// weights would scale them by (1 + omega eps) every step.
+__host__ __device__ constexpr int ghost3(int k, int i)
+{
+    const int cx = kCX[i], cy = kCY[i], cz = kCZ[i];
+    const int c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return (21 * c2 * c2 - 53 * c2 + 24) / 2;             // epsilon
+    case 1: return (5 * c2 - 9) * cx;                             // q_x
+    case 2: return (5 * c2 - 9) * cy;                             // q_y
+    case 3: return (5 * c2 - 9) * cz;                             // q_z
+    case 4: return (3 * c2 - 5) * (3 * cx * cx - c2);             // 3 pi_xx
+    case 5: return (3 * c2 - 5) * (cy * cy - cz * cz);            // pi_ww
+    case 6: return cx * (cy * cy - cz * cz);                      // m_x
+    case 7: return cy * (cz * cz - cx * cx);                      // m_y
+    default: return cz * (cx * cx - cy * cy);                     // m_z
+    }
+}
+constexpr int kGhosts3 = 9;
+
+// sum_i n_k,i f(i) for the lattice tables, at compile time
+__host__ __device__ constexpr int ghost_dot_poly(int k, int px, int py, int pz)
+{
+    int s = 0;
+    for (int i = 0; i < kQ; ++i) {
+        int m = 1;
+        for (int e = 0; e < px; ++e) m *= kCX[i];
+        for (int e = 0; e < py; ++e) m *= kCY[i];
+        for (int e = 0; e < pz; ++e) m *= kCZ[i];
+        s += ghost3(k, i) * m;
+    }
+    return s;
+}
+__host__ __device__ constexpr bool ghosts_orthogonal()
+{
+    for (int k = 0; k < kGhosts3; ++k)
+        for (int px = 0; px <= 2; ++px)
+            for (int py = 0; py <= 2 - px; ++py)
+                for (int pz = 0; pz <= 2 - px - py; ++pz)
+                    if (ghost_dot_poly(k, px, py, pz) != 0) return false;
+    for (int k = 0; k < kGhosts3; ++k)
+        for (int l = 0; l < k; ++l) {
+            int s = 0;
+            for (int i = 0; i < kQ; ++i) s += ghost3(k, i) * ghost3(l, i);
+            if (s != 0) return false;
+        }
+    return true;
+}
+static_assert(ghosts_orthogonal(), "ghost vectors must be orthogonal to 1, c, c c and to each other");
+
+__host__ __device__ constexpr double ghost_norm(int k)
+{
+    double s = 0;
+    for (int i = 0; i < kQ; ++i) s += double(ghost3(k, i)) * ghost3(k, i);
+    return s;
+}
+// E_k = n_k.g_eq = er(k) drho + sum_a ej(k, a) j_a + sum_c ep(k, c) P_c (c: xx yy zz xy xz yz)
+__host__ __device__ constexpr double ghost_er(int k)
+{
+    double s = 0;
+    for (int i = 0; i < kQ; ++i) s += ghost3(k, i) * w3(i) * (2.5 - 1.5 * c2_3(i));
+    return s;
+}
+__host__ __device__ constexpr double ghost_ej(int k, int a)      // also Psi_k per S_a
+{
+    double s = 0;
+    for (int i = 0; i < kQ; ++i) s += ghost3(k, i) * 3.0 * w3(i) * (a == 0 ? kCX[i] : (a == 1 ? kCY[i] : kCZ[i]));
+    return s;
+}
+__host__ __device__ constexpr double ghost_ep(int k, int c)
+{
+    double s = 0;
+    for (int i = 0; i < kQ; ++i) {
+        const int cx = kCX[i], cy = kCY[i], cz = kCZ[i];
+        double t = 0;
+        switch (c) {
+        case 0: t = cx * cx - 1.0 / 3.0; break;
+        case 1: t = cy * cy - 1.0 / 3.0; break;
+        case 2: t = cz * cz - 1.0 / 3.0; break;
+        case 3: t = 2.0 * cx * cy; break;
+        case 4: t = 2.0 * cx * cz; break;
+        default: t = 2.0 * cy * cz; break;
+        }
+        s += ghost3(k, i) * 4.5 * w3(i) * t;
+    }
+    return s;
+}
+// tau_k per S_a: T puts +S_a/2 on link +a (1, 3, 5) and -S_a/2 on -a (2, 4, 6)
+__host__ __device__ constexpr double ghost_et(int k, int a) { return 0.5 * (ghost3(k, 1 + 2 * a) - ghost3(k, 2 + 2 * a)); }
+
+// Coefficient of one ghost from the site's moments (drho, j with S/2, P),
+// its populations and S.
+template <int k, typename real>
+__device__ __forceinline__ real ghost_coef3(const real g[kQ], real dr, const real j[3], const real P[6],
+                                            const real S[3], real omega, real omega_h)
+{
+    real m = real(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int n = ghost3(k, i);
+        if (n == 1) m += g[i];
+        else if (n == -1) m -= g[i];
+        else if (n != 0) m += real(n) * g[i];
+    }
+    real e = real(ghost_er(k)) * dr;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (ghost_ej(k, a) != 0.0) e += real(ghost_ej(k, a)) * j[a];
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (ghost_ep(k, c) != 0.0) e += real(ghost_ep(k, c)) * P[c];
+    real src = real(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (ghost_ej(k, a) != 0.0) src += omega_h * (real(ghost_ej(k, a)) * S[a]);
+        if (ghost_et(k, a) != 0.0) src -= real(ghost_et(k, a)) * S[a];
+    }
+    return (omega * (e - m) + src) * real(1.0 / ghost_norm(k));
+}
+
+// Post-collision populations o from g, the moments (j with S/2) and S.
+template <typename real>
+__device__ __forceinline__ void collide_ghost3(const real g[kQ], real dr, const real j[3], const real P[6],
+                                               const real S[3], real omega, real omega_h, real o[kQ])
+{
+    real ak[kGhosts3];
+    ak[0] = ghost_coef3<0>(g, dr, j, P, S, omega, omega_h);
+    ak[1] = ghost_coef3<1>(g, dr, j, P, S, omega, omega_h);
+    ak[2] = ghost_coef3<2>(g, dr, j, P, S, omega, omega_h);
+    ak[3] = ghost_coef3<3>(g, dr, j, P, S, omega, omega_h);
+    ak[4] = ghost_coef3<4>(g, dr, j, P, S, omega, omega_h);
+    ak[5] = ghost_coef3<5>(g, dr, j, P, S, omega, omega_h);
+    ak[6] = ghost_coef3<6>(g, dr, j, P, S, omega, omega_h);
+    ak[7] = ghost_coef3<7>(g, dr, j, P, S, omega, omega_h);
+    ak[8] = ghost_coef3<8>(g, dr, j, P, S, omega, omega_h);
+    const real h[3] = {real(0.5) * S[0], real(0.5) * S[1], real(0.5) * S[2]};
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        real d = real(0);
+#pragma unroll
+        for (int k = 0; k < kGhosts3; ++k) {
+            const int n = ghost3(k, i);
+            if (n == 1) d += ak[k];
+            else if (n == -1) d -= ak[k];
+            else if (n != 0) d += real(n) * ak[k];
+        }
+        if (i >= 1 && i <= 6) d += (i & 1) ? h[(i - 1) >> 1] : -h[(i - 1) >> 1];
+        o[i] = g[i] + d;
+    }
+}
+
 // delta-rho, j and P (xx yy zz xy xz yz) of shifted populations.
 template <typename real>
 __device__ __forceinline__ void moments3(const real g[kQ], real& dr, real j[3], real P[6])
@@ -296,16 +460,9 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
         j[k] = j[k] + real(0.5) * S[k];
     }
     const unsigned s = sidx3(st.x, st.y, st.z, a.nx, a.ny);
+    // eq:coll in ghost-moment form (exact conserved moments)
     real o[kQ];
-#define SLBM3_COLL(k)                                                                             \
-    {                                                                                             \
-        const real psi = real(3.0 * w3(k)) * (real(kCX[k]) * S[0] + real(kCY[k]) * S[1] + real(kCZ[k]) * S[2]); \
-        o[k] = g[k] - a.omega * (g[k] - geq3<k, real>(dr, j, P)) + a.omega_h * psi;              \
-    }
-    SLBM3_COLL(0) SLBM3_COLL(1) SLBM3_COLL(2) SLBM3_COLL(3) SLBM3_COLL(4) SLBM3_COLL(5) SLBM3_COLL(6)
-    SLBM3_COLL(7) SLBM3_COLL(8) SLBM3_COLL(9) SLBM3_COLL(10) SLBM3_COLL(11) SLBM3_COLL(12)
-    SLBM3_COLL(13) SLBM3_COLL(14) SLBM3_COLL(15) SLBM3_COLL(16) SLBM3_COLL(17) SLBM3_COLL(18)
-#undef SLBM3_COLL
+    collide_ghost3(g, dr, j, P, S, a.omega, a.omega_h, o);
     const bool bad = !(fabs(dr) + fabs(j[0]) + fabs(j[1]) + fabs(j[2]) < real(1e30));
     if (st.in) {
 #pragma unroll
