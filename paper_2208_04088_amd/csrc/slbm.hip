@@ -69,6 +69,20 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
+// Runs the body of a C entry point: no exception crosses the ABI (host
+// allocation failure is SLBM_E_NOMEM).
+template <class F>
+int guarded(F&& body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail(SLBM_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(SLBM_E_DEVICE, "unexpected host error");
+    }
+}
+
 #define HIP_TRY(expr)                                                              \
     do {                                                                           \
         hipError_t e_ = (expr);                                                    \
@@ -776,257 +790,279 @@ int slbm_create(const slbm_params* params, slbm_handle* out)
 
 int slbm_destroy(slbm_handle h)
 {
-    if (!h) return SLBM_OK;
-    DeviceGuard dg(h->device);
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    free_all(h);
-    delete h;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return SLBM_OK;
+        DeviceGuard dg(h->device);
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        free_all(h);
+        delete h;
+        return SLBM_OK;
+    });
 }
 
 int slbm_step(slbm_handle h, int64_t nsteps)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
-    DeviceGuard dg(h->device);
-    int64_t i = 0;
-    if (h->two) {
-        for (; i + 2 <= nsteps; i += 2) {
-            int rc = h->precision == SLBM_FP32 ? launch_step2<float>(h) : launch_step2<double>(h);
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
+        DeviceGuard dg(h->device);
+        int64_t i = 0;
+        if (h->two) {
+            for (; i + 2 <= nsteps; i += 2) {
+                int rc = h->precision == SLBM_FP32 ? launch_step2<float>(h) : launch_step2<double>(h);
+                if (rc) return rc;
+            }
+        }
+        for (; i < nsteps; ++i) {
+            int rc = h->precision == SLBM_FP32 ? launch_step<float>(h) : launch_step<double>(h);
             if (rc) return rc;
         }
-    }
-    for (; i < nsteps; ++i) {
-        int rc = h->precision == SLBM_FP32 ? launch_step<float>(h) : launch_step<double>(h);
-        if (rc) return rc;
-    }
-    return SLBM_OK;
+        return SLBM_OK;
+    });
 }
 
 int slbm_sync(slbm_handle h)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    DeviceGuard dg(h->device);
-    unsigned int flag = 0;
-    HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    if (flag) return fail(SLBM_E_DIVERGED, "a non-finite value appeared by step %lld", (long long)h->step);
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        DeviceGuard dg(h->device);
+        unsigned int flag = 0;
+        HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (flag) return fail(SLBM_E_DIVERGED, "a non-finite value appeared by step %lld", (long long)h->step);
+        return SLBM_OK;
+    });
 }
 
 int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    DeviceGuard dg(h->device);
-    int rc = outputs(h, true);
-    if (rc) return rc;
-    const size_t n = (size_t)h->nx * h->ny;
-    const double sj = h->rho_user * h->s_v;
-    if (rho && (rc = copy_out(h, 0, h->rho_user, 0.0, rho))) return rc;
-    if (j && ((rc = copy_out(h, 1, sj, 0.0, j)) || (rc = copy_out(h, 2, sj, 0.0, j + n)))) return rc;
-    if (P && ((rc = copy_out(h, 3, h->s_sigma, 0.0, P)) || (rc = copy_out(h, 4, h->s_sigma, 0.0, P + n)) ||
-              (rc = copy_out(h, 5, h->s_sigma, 0.0, P + 2 * n))))
-        return rc;
-    if (sigma && ((rc = copy_out(h, 6, h->s_sigma, 0.0, sigma)) || (rc = copy_out(h, 7, h->s_sigma, 0.0, sigma + n)) ||
-                  (rc = copy_out(h, 8, h->s_sigma, 0.0, sigma + 2 * n))))
-        return rc;
-    release_transient_scratch(h);
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        DeviceGuard dg(h->device);
+        int rc = outputs(h, true);
+        if (rc) return rc;
+        const size_t n = (size_t)h->nx * h->ny;
+        const double sj = h->rho_user * h->s_v;
+        if (rho && (rc = copy_out(h, 0, h->rho_user, 0.0, rho))) return rc;
+        if (j && ((rc = copy_out(h, 1, sj, 0.0, j)) || (rc = copy_out(h, 2, sj, 0.0, j + n)))) return rc;
+        if (P && ((rc = copy_out(h, 3, h->s_sigma, 0.0, P)) || (rc = copy_out(h, 4, h->s_sigma, 0.0, P + n)) ||
+                  (rc = copy_out(h, 5, h->s_sigma, 0.0, P + 2 * n))))
+            return rc;
+        if (sigma && ((rc = copy_out(h, 6, h->s_sigma, 0.0, sigma)) || (rc = copy_out(h, 7, h->s_sigma, 0.0, sigma + n)) ||
+                      (rc = copy_out(h, 8, h->s_sigma, 0.0, sigma + 2 * n))))
+            return rc;
+        release_transient_scratch(h);
+        return SLBM_OK;
+    });
 }
 
 int slbm_displacement(slbm_handle h, double* u)
 {
-    if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
-    DeviceGuard dg(h->device);
-    int rc = outputs(h, false);
-    if (rc) return rc;
-    const size_t n = (size_t)h->nx * h->ny;
-    if ((rc = copy_out(h, 0, 1.0, 0.0, u)) || (rc = copy_out(h, 1, 1.0, 0.0, u + n))) return rc;
-    release_transient_scratch(h);
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
+        DeviceGuard dg(h->device);
+        int rc = outputs(h, false);
+        if (rc) return rc;
+        const size_t n = (size_t)h->nx * h->ny;
+        if ((rc = copy_out(h, 0, 1.0, 0.0, u)) || (rc = copy_out(h, 1, 1.0, 0.0, u + n))) return rc;
+        release_transient_scratch(h);
+        return SLBM_OK;
+    });
 }
 
 int slbm_displacement_device(slbm_handle h, void* u_dev)
 {
-    if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
-    DeviceGuard dg(h->device);
-    int rc = outputs(h, false);
-    if (rc) return rc;
-    const int n = h->nx * h->ny;
-    hipLaunchKernelGGL(k_unpad_u, dim3((n + 255) / 256), dim3(256), 0, h->stream,
-                       (const double*)(h->scratch + h->plane), h->nx, h->ny, h->ld, (double*)u_dev);
-    HIP_TRY(hipGetLastError());
-    release_transient_scratch(h);
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
+        DeviceGuard dg(h->device);
+        int rc = outputs(h, false);
+        if (rc) return rc;
+        const int n = h->nx * h->ny;
+        hipLaunchKernelGGL(k_unpad_u, dim3((n + 255) / 256), dim3(256), 0, h->stream,
+                           (const double*)(h->scratch + h->plane), h->nx, h->ny, h->ld, (double*)u_dev);
+        HIP_TRY(hipGetLastError());
+        release_transient_scratch(h);
+        return SLBM_OK;
+    });
 }
 
 int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const double* sigma, const double* u)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    DeviceGuard dg(h->device);
-    int rc = ensure_scratch(h, 8);
-    if (rc) return rc;
-    const int nx = h->nx, ny = h->ny, n = nx * ny;
-    const size_t P = (size_t)h->plane;
-    // lattice-unit fields on the host, padded layout: dr, jx, jy, pxx, pyy, pxy, ux, uy
-    std::vector<double> f((size_t)8 * P, 0.0);
-    const double lm = h->lamL - h->muL;
-    for (int s = 0; s < n; ++s) {
-        if (!h->mask[s]) continue;
-        const size_t d = (size_t)sidx(s % nx, s / nx, h->ld);
-        const double rL = rho ? rho[s] / h->rho_user : 1.0;
-        if (!(rL > 0) || !std::isfinite(rL)) return fail(SLBM_E_INVAL, "density must be positive");
-        const double vx = vel ? vel[s] / h->s_v : 0.0, vy = vel ? vel[n + s] / h->s_v : 0.0;
-        const double sxx = sigma ? sigma[s] / h->s_sigma : 0.0, syy = sigma ? sigma[n + s] / h->s_sigma : 0.0;
-        const double sxy = sigma ? sigma[2 * n + s] / h->s_sigma : 0.0;
-        const double div = 1.0 - rL;   // eq:approxdiv
-        f[d] = rL - 1.0;
-        f[P + d] = rL * vx;
-        f[2 * P + d] = rL * vy;
-        f[3 * P + d] = -sxx + lm * div;   // eq:poissonstress
-        f[4 * P + d] = -syy + lm * div;
-        f[5 * P + d] = -sxy;
-        f[6 * P + d] = u ? u[s] : 0.0;
-        f[7 * P + d] = u ? u[n + s] : 0.0;
-    }
-    double* dev = h->scratch;   // 8 planes
-    HIP_TRY(hipMemcpyAsync(dev, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    h->cur = 0;
-    h->local = true;
-    h->step = 0;
-    const int grid = (int)((P + 255) / 256);
-    if (h->precision == SLBM_FP32) {
-        StepArgs<float> a = make_args<float>(h, 0);
-        if (h->px || h->py)
-            hipLaunchKernelGGL((k_init<float, true>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (float*)h->buf[0]);
-        else
-            hipLaunchKernelGGL((k_init<float, false>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (float*)h->buf[0]);
-    } else {
-        StepArgs<double> a = make_args<double>(h, 0);
-        if (h->px || h->py)
-            hipLaunchKernelGGL((k_init<double, true>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (double*)h->buf[0]);
-        else
-            hipLaunchKernelGGL((k_init<double, false>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (double*)h->buf[0]);
-    }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    release_transient_scratch(h);
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        DeviceGuard dg(h->device);
+        int rc = ensure_scratch(h, 8);
+        if (rc) return rc;
+        const int nx = h->nx, ny = h->ny, n = nx * ny;
+        const size_t P = (size_t)h->plane;
+        // lattice-unit fields on the host, padded layout: dr, jx, jy, pxx, pyy, pxy, ux, uy
+        std::vector<double> f((size_t)8 * P, 0.0);
+        const double lm = h->lamL - h->muL;
+        for (int s = 0; s < n; ++s) {
+            if (!h->mask[s]) continue;
+            const size_t d = (size_t)sidx(s % nx, s / nx, h->ld);
+            const double rL = rho ? rho[s] / h->rho_user : 1.0;
+            if (!(rL > 0) || !std::isfinite(rL)) return fail(SLBM_E_INVAL, "density must be positive");
+            const double vx = vel ? vel[s] / h->s_v : 0.0, vy = vel ? vel[n + s] / h->s_v : 0.0;
+            const double sxx = sigma ? sigma[s] / h->s_sigma : 0.0, syy = sigma ? sigma[n + s] / h->s_sigma : 0.0;
+            const double sxy = sigma ? sigma[2 * n + s] / h->s_sigma : 0.0;
+            const double div = 1.0 - rL;   // eq:approxdiv
+            f[d] = rL - 1.0;
+            f[P + d] = rL * vx;
+            f[2 * P + d] = rL * vy;
+            f[3 * P + d] = -sxx + lm * div;   // eq:poissonstress
+            f[4 * P + d] = -syy + lm * div;
+            f[5 * P + d] = -sxy;
+            f[6 * P + d] = u ? u[s] : 0.0;
+            f[7 * P + d] = u ? u[n + s] : 0.0;
+        }
+        double* dev = h->scratch;   // 8 planes
+        HIP_TRY(hipMemcpyAsync(dev, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        h->cur = 0;
+        h->local = true;
+        h->step = 0;
+        const int grid = (int)((P + 255) / 256);
+        if (h->precision == SLBM_FP32) {
+            StepArgs<float> a = make_args<float>(h, 0);
+            if (h->px || h->py)
+                hipLaunchKernelGGL((k_init<float, true>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (float*)h->buf[0]);
+            else
+                hipLaunchKernelGGL((k_init<float, false>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (float*)h->buf[0]);
+        } else {
+            StepArgs<double> a = make_args<double>(h, 0);
+            if (h->px || h->py)
+                hipLaunchKernelGGL((k_init<double, true>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (double*)h->buf[0]);
+            else
+                hipLaunchKernelGGL((k_init<double, false>), dim3(grid), dim3(256), 0, h->stream, a, dev, dev + P, dev + 3 * P, dev + 6 * P, (double*)h->buf[0]);
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        release_transient_scratch(h);
+        return SLBM_OK;
+    });
 }
 
 int slbm_time(slbm_handle h, int64_t* step, double* t_user)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    if (step) *step = h->step;
-    if (t_user) *t_user = (double)h->step * h->dt_user;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (step) *step = h->step;
+        if (t_user) *t_user = (double)h->step * h->dt_user;
+        return SLBM_OK;
+    });
 }
 
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
-    if (strip != 0 && strip != 62 && strip != 64 && strip != kStrip2)
-        return fail(SLBM_E_INVAL, "strip must be 0, 58, 62 or 64");
-    if (seg_rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
-        return fail(SLBM_E_INVAL, "rows per tile above the maximum (14; 10 with two steps per launch)");
-    h->seg = seg_rows;
-    h->two = strip == kStrip2 ? 1 : 0;
-    h->wide = (strip == 0 || strip == kStrip2) ? -1 : (strip == 64 ? 1 : 0);
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
+        if (strip != 0 && strip != 62 && strip != 64 && strip != kStrip2)
+            return fail(SLBM_E_INVAL, "strip must be 0, 58, 62 or 64");
+        if (seg_rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
+            return fail(SLBM_E_INVAL, "rows per tile above the maximum (14; 10 with two steps per launch)");
+        h->seg = seg_rows;
+        h->two = strip == kStrip2 ? 1 : 0;
+        h->wide = (strip == 0 || strip == kStrip2) ? -1 : (strip == 64 ? 1 : 0);
+        return SLBM_OK;
+    });
 }
 
 int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* us_out)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    DeviceGuard dg(h->device);
-    int rc = ensure_scratch(h, 3);
-    if (rc) return rc;
-    // the trial steps write the other population buffer (free) and update U
-    // in place: keep U and the divergence flag aside and restore them after
-    // every trial, so the state is left exactly as it was
-    const size_t ub = (size_t)2 * h->plane * sizeof(double);
-    double* saved = h->scratch;
-    unsigned int* flag_saved = (unsigned int*)(h->scratch + 2 * h->plane);
-    HIP_TRY(hipMemcpyAsync(saved, h->U, ub, hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(flag_saved, h->diverged, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    const int cand[] = {2, 3, 4, 6, 8, 10, 12, 14};
-    int best = 0, best_w = 0;
-    double best_us = 1e30;
-    for (int wv = 0; wv < 2; ++wv)
-    for (int c : cand) {
-        if (c > (wv ? max_tile_rows<true>() : max_tile_rows<false>())) break;
-        if (c > std::max(2, h->ny)) break;
-        // bursts of back-to-back launches, as steps run; each launch rereads
-        // the same state, U is put back after the burst
-        constexpr int kBurst = 6;
-        std::vector<float> t;
-        for (int r = 0; r < 3; ++r) {
-            HIP_TRY(hipEventRecord(e0, h->stream));
-            for (int q = 0; q < kBurst; ++q) {
-                rc = h->precision == SLBM_FP32 ? launch_step_raw<float>(h, c, wv) : launch_step_raw<double>(h, c, wv);
-                if (rc) return rc;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        DeviceGuard dg(h->device);
+        int rc = ensure_scratch(h, 3);
+        if (rc) return rc;
+        // the trial steps write the other population buffer (free) and update U
+        // in place: keep U and the divergence flag aside and restore them after
+        // every trial, so the state is left exactly as it was
+        const size_t ub = (size_t)2 * h->plane * sizeof(double);
+        double* saved = h->scratch;
+        unsigned int* flag_saved = (unsigned int*)(h->scratch + 2 * h->plane);
+        HIP_TRY(hipMemcpyAsync(saved, h->U, ub, hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(flag_saved, h->diverged, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        const int cand[] = {2, 3, 4, 6, 8, 10, 12, 14};
+        int best = 0, best_w = 0;
+        double best_us = 1e30;
+        for (int wv = 0; wv < 2; ++wv)
+        for (int c : cand) {
+            if (c > (wv ? max_tile_rows<true>() : max_tile_rows<false>())) break;
+            if (c > std::max(2, h->ny)) break;
+            // bursts of back-to-back launches, as steps run; each launch rereads
+            // the same state, U is put back after the burst
+            constexpr int kBurst = 6;
+            std::vector<float> t;
+            for (int r = 0; r < 3; ++r) {
+                HIP_TRY(hipEventRecord(e0, h->stream));
+                for (int q = 0; q < kBurst; ++q) {
+                    rc = h->precision == SLBM_FP32 ? launch_step_raw<float>(h, c, wv) : launch_step_raw<double>(h, c, wv);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipEventRecord(e1, h->stream));
+                HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0) t.push_back(ms / kBurst);
             }
-            HIP_TRY(hipEventRecord(e1, h->stream));
-            HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (r > 0) t.push_back(ms / kBurst);
+            std::sort(t.begin(), t.end());
+            const double us = 1e3 * t[0];
+            if (us < best_us) { best_us = us; best = c; best_w = wv; }
         }
-        std::sort(t.begin(), t.end());
-        const double us = 1e3 * t[0];
-        if (us < best_us) { best_us = us; best = c; best_w = wv; }
-    }
-    // two steps per launch: bursts of three launches, time per step
-    const int cand2[] = {2, 3, 4, 5, 6, 7, 8, 9, 10};
-    for (int c : cand2) {
-        if (c > std::max(2, h->ny)) break;
-        constexpr int kBurst2 = 3;
-        std::vector<float> t;
-        for (int r = 0; r < 3; ++r) {
-            HIP_TRY(hipEventRecord(e0, h->stream));
-            for (int q = 0; q < kBurst2; ++q) {
-                rc = h->precision == SLBM_FP32 ? launch_step2_raw<float>(h, c) : launch_step2_raw<double>(h, c);
-                if (rc) return rc;
+        // two steps per launch: bursts of three launches, time per step
+        const int cand2[] = {2, 3, 4, 5, 6, 7, 8, 9, 10};
+        for (int c : cand2) {
+            if (c > std::max(2, h->ny)) break;
+            constexpr int kBurst2 = 3;
+            std::vector<float> t;
+            for (int r = 0; r < 3; ++r) {
+                HIP_TRY(hipEventRecord(e0, h->stream));
+                for (int q = 0; q < kBurst2; ++q) {
+                    rc = h->precision == SLBM_FP32 ? launch_step2_raw<float>(h, c) : launch_step2_raw<double>(h, c);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipEventRecord(e1, h->stream));
+                HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0) t.push_back(ms / (2 * kBurst2));
             }
-            HIP_TRY(hipEventRecord(e1, h->stream));
-            HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (r > 0) t.push_back(ms / (2 * kBurst2));
+            std::sort(t.begin(), t.end());
+            const double us = 1e3 * t[0];
+            if (us < best_us) { best_us = us; best = c; best_w = 2; }
         }
-        std::sort(t.begin(), t.end());
-        const double us = 1e3 * t[0];
-        if (us < best_us) { best_us = us; best = c; best_w = 2; }
-    }
-    HIP_TRY(hipMemcpyAsync(h->diverged, flag_saved, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    release_transient_scratch(h);
-    h->seg = best;
-    h->two = best_w == 2 ? 1 : 0;
-    h->wide = best_w == 2 ? -1 : best_w;
-    if (seg_out) *seg_out = best;
-    if (strip_out) *strip_out = best_w == 2 ? kStrip2 : (best_w ? 64 : 62);
-    if (us_out) *us_out = best_us;
-    return SLBM_OK;
+        HIP_TRY(hipMemcpyAsync(h->diverged, flag_saved, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        release_transient_scratch(h);
+        h->seg = best;
+        h->two = best_w == 2 ? 1 : 0;
+        h->wide = best_w == 2 ? -1 : best_w;
+        if (seg_out) *seg_out = best;
+        if (strip_out) *strip_out = best_w == 2 ? kStrip2 : (best_w ? 64 : 62);
+        if (us_out) *us_out = best_us;
+        return SLBM_OK;
+    });
 }
 
 int slbm_device_bytes(slbm_handle h, int64_t* bytes)
 {
-    if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
-    int64_t b = 2 * (int64_t)9 * h->plane * (int64_t)h->esize + 2 * h->plane * 8 + h->plane * 5;
-    b += (int64_t)h->n_links * (h->esize == 4 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>));
-    if (h->scratch) b += (int64_t)h->scratch_planes * h->plane * 8;
-    *bytes = b;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
+        int64_t b = 2 * (int64_t)9 * h->plane * (int64_t)h->esize + 2 * h->plane * 8 + h->plane * 5;
+        b += (int64_t)h->n_links * (h->esize == 4 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>));
+        if (h->scratch) b += (int64_t)h->scratch_planes * h->plane * 8;
+        *bytes = b;
+        return SLBM_OK;
+    });
 }
 
 namespace {
@@ -1041,61 +1077,67 @@ constexpr uint64_t kMagic = 0x31304d424c53ULL;  // "SLBM01"
 
 int slbm_save(slbm_handle h, void* buf, size_t* bytes)
 {
-    if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
-    const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
-    const size_t need = sizeof(SaveHeader) + pop + ub;
-    if (!buf) { *bytes = need; return SLBM_OK; }
-    if (*bytes < need) return fail(SLBM_E_INVAL, "buffer too small: %zu < %zu", *bytes, need);
-    DeviceGuard dg(h->device);
-    SaveHeader hd{kMagic, h->nx, h->ny, h->ld, h->precision, h->step, h->local ? 1 : 0, 0};
-    unsigned int flag = 0;
-    char* p = (char*)buf;
-    HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(p + sizeof hd, h->buf[h->cur], pop, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(p + sizeof hd + pop, h->U, ub, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    hd.diverged = (int32_t)flag;
-    std::memcpy(p, &hd, sizeof hd);
-    *bytes = need;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
+        const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
+        const size_t need = sizeof(SaveHeader) + pop + ub;
+        if (!buf) { *bytes = need; return SLBM_OK; }
+        if (*bytes < need) return fail(SLBM_E_INVAL, "buffer too small: %zu < %zu", *bytes, need);
+        DeviceGuard dg(h->device);
+        SaveHeader hd{kMagic, h->nx, h->ny, h->ld, h->precision, h->step, h->local ? 1 : 0, 0};
+        unsigned int flag = 0;
+        char* p = (char*)buf;
+        HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(p + sizeof hd, h->buf[h->cur], pop, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(p + sizeof hd + pop, h->U, ub, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        hd.diverged = (int32_t)flag;
+        std::memcpy(p, &hd, sizeof hd);
+        *bytes = need;
+        return SLBM_OK;
+    });
 }
 
 int slbm_load(slbm_handle h, const void* buf, size_t bytes)
 {
-    if (!h || !buf) return fail(SLBM_E_INVAL, "null argument");
-    const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
-    SaveHeader hd;
-    if (bytes < sizeof hd + pop + ub) return fail(SLBM_E_INVAL, "checkpoint too short");
-    std::memcpy(&hd, buf, sizeof hd);
-    if (hd.magic != kMagic || hd.nx != h->nx || hd.ny != h->ny || hd.ld != h->ld || hd.precision != h->precision)
-        return fail(SLBM_E_INVAL, "checkpoint does not match this plate");
-    DeviceGuard dg(h->device);
-    const char* p = (const char*)buf;
-    h->cur = 0;
-    HIP_TRY(hipMemcpyAsync(h->buf[0], p + sizeof hd, pop, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->U, p + sizeof hd + pop, ub, hipMemcpyHostToDevice, h->stream));
-    unsigned int flag = (unsigned int)hd.diverged;
-    HIP_TRY(hipMemcpyAsync(h->diverged, &flag, sizeof flag, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->step = hd.step;
-    h->local = hd.local != 0;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !buf) return fail(SLBM_E_INVAL, "null argument");
+        const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
+        SaveHeader hd;
+        if (bytes < sizeof hd + pop + ub) return fail(SLBM_E_INVAL, "checkpoint too short");
+        std::memcpy(&hd, buf, sizeof hd);
+        if (hd.magic != kMagic || hd.nx != h->nx || hd.ny != h->ny || hd.ld != h->ld || hd.precision != h->precision)
+            return fail(SLBM_E_INVAL, "checkpoint does not match this plate");
+        DeviceGuard dg(h->device);
+        const char* p = (const char*)buf;
+        h->cur = 0;
+        HIP_TRY(hipMemcpyAsync(h->buf[0], p + sizeof hd, pop, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->U, p + sizeof hd + pop, ub, hipMemcpyHostToDevice, h->stream));
+        unsigned int flag = (unsigned int)hd.diverged;
+        HIP_TRY(hipMemcpyAsync(h->diverged, &flag, sizeof flag, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->step = hd.step;
+        h->local = hd.local != 0;
+        return SLBM_OK;
+    });
 }
 
 int slbm_copy(void* dst, const void* src, size_t bytes, int32_t device, void* stream)
 {
-    if (!dst || !src) return fail(SLBM_E_INVAL, "null pointer");
-    if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
-        return fail(SLBM_E_INVAL, "bytes and both pointers must be multiples of 16");
-    DeviceGuard dg(device);
-    const long long n = (long long)(bytes / 16);
-    if (n > (1LL << 31) * 256) return fail(SLBM_E_UNSUPPORTED, "copy larger than 2^39 x 16 bytes");
-    const unsigned grid = (unsigned)((n + 255) / 256);
-    if (n > 0)
-        hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, (hipStream_t)stream,
-                           (const float4*)src, (float4*)dst, n);
-    HIP_TRY(hipGetLastError());
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!dst || !src) return fail(SLBM_E_INVAL, "null pointer");
+        if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
+            return fail(SLBM_E_INVAL, "bytes and both pointers must be multiples of 16");
+        DeviceGuard dg(device);
+        const long long n = (long long)(bytes / 16);
+        if (n > (1LL << 31) * 256) return fail(SLBM_E_UNSUPPORTED, "copy larger than 2^39 x 16 bytes");
+        const unsigned grid = (unsigned)((n + 255) / 256);
+        if (n > 0)
+            hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                               (const float4*)src, (float4*)dst, n);
+        HIP_TRY(hipGetLastError());
+        return SLBM_OK;
+    });
 }
 
 // ================================================================ batches
@@ -1293,158 +1335,180 @@ extern "C" {
 
 int slbm_batch_create(int64_t hbm_budget_bytes, int32_t device, void* stream, slbm_batch* out)
 {
-    if (!out) return fail(SLBM_E_INVAL, "null argument");
-    *out = nullptr;
-    if (hbm_budget_bytes <= 0) return fail(SLBM_E_INVAL, "budget must be positive");
-    int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(SLBM_E_DEVICE, "no HIP device");
-    if (device < 0 || device >= n) return fail(SLBM_E_INVAL, "device %d out of range", device);
-    slbm_batch_s* b = new (std::nothrow) slbm_batch_s();
-    if (!b) return fail(SLBM_E_NOMEM, "out of host memory");
-    b->device = device;
-    b->budget = hbm_budget_bytes;
-    DeviceGuard dg(device);
-    if (stream) {
-        b->stream = (hipStream_t)stream;
-    } else {
-        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-        if (e != hipSuccess) { delete b; return fail(SLBM_E_DEVICE, "stream: %s", hipGetErrorString(e)); }
-        b->own_stream = true;
-    }
-    *out = b;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!out) return fail(SLBM_E_INVAL, "null argument");
+        *out = nullptr;
+        if (hbm_budget_bytes <= 0) return fail(SLBM_E_INVAL, "budget must be positive");
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(SLBM_E_DEVICE, "no HIP device");
+        if (device < 0 || device >= n) return fail(SLBM_E_INVAL, "device %d out of range", device);
+        slbm_batch_s* b = new (std::nothrow) slbm_batch_s();
+        if (!b) return fail(SLBM_E_NOMEM, "out of host memory");
+        b->device = device;
+        b->budget = hbm_budget_bytes;
+        DeviceGuard dg(device);
+        if (stream) {
+            b->stream = (hipStream_t)stream;
+        } else {
+            hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) { delete b; return fail(SLBM_E_DEVICE, "stream: %s", hipGetErrorString(e)); }
+            b->own_stream = true;
+        }
+        *out = b;
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_add(slbm_batch b, const slbm_params* params, int64_t nsteps, int32_t* slot)
 {
-    if (!b || !params || !slot) return fail(SLBM_E_INVAL, "null argument");
-    if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
-    if (params->periodic_x || params->periodic_y) return fail(SLBM_E_UNSUPPORTED, "periodic plates are not batched");
-    if (b->precision >= 0 && params->precision != b->precision)
-        return fail(SLBM_E_INVAL, "every plate of a batch has the batch's precision");
-    const int64_t need = estimate_bytes(params);
-    if (b->used + need > b->budget)
-        return fail(SLBM_E_BUDGET, "plate needs %lld bytes, %lld of %lld in use", (long long)need,
-                    (long long)b->used, (long long)b->budget);
-    slbm_params p = *params;
-    p.device = b->device;
-    p.stream = b->stream;
-    slbm_handle h = nullptr;
-    int rc = slbm_create(&p, &h);
-    if (rc) return rc;
-    b->precision = params->precision;
-    int k = -1;
-    for (size_t i = 0; i < b->slot.size(); ++i)
-        if (!b->slot[i]) { k = (int)i; break; }
-    if (k < 0) {
-        k = (int)b->slot.size();
-        b->slot.push_back(nullptr);
-        b->remaining.push_back(0);
-        b->bytes.push_back(0);
-    }
-    h->transient_scratch = true;
-    b->slot[k] = h;
-    b->remaining[k] = nsteps;
-    b->bytes[k] = need;
-    b->used += need;
-    b->dirty = true;
-    *slot = k;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b || !params || !slot) return fail(SLBM_E_INVAL, "null argument");
+        if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
+        if (params->periodic_x || params->periodic_y) return fail(SLBM_E_UNSUPPORTED, "periodic plates are not batched");
+        if (b->precision >= 0 && params->precision != b->precision)
+            return fail(SLBM_E_INVAL, "every plate of a batch has the batch's precision");
+        const int64_t need = estimate_bytes(params);
+        if (b->used + need > b->budget)
+            return fail(SLBM_E_BUDGET, "plate needs %lld bytes, %lld of %lld in use", (long long)need,
+                        (long long)b->used, (long long)b->budget);
+        slbm_params p = *params;
+        p.device = b->device;
+        p.stream = b->stream;
+        slbm_handle h = nullptr;
+        int rc = slbm_create(&p, &h);
+        if (rc) return rc;
+        b->precision = params->precision;
+        int k = -1;
+        for (size_t i = 0; i < b->slot.size(); ++i)
+            if (!b->slot[i]) { k = (int)i; break; }
+        if (k < 0) {
+            k = (int)b->slot.size();
+            b->slot.push_back(nullptr);
+            b->remaining.push_back(0);
+            b->bytes.push_back(0);
+        }
+        h->transient_scratch = true;
+        b->slot[k] = h;
+        b->remaining[k] = nsteps;
+        b->bytes[k] = need;
+        b->used += need;
+        b->dirty = true;
+        *slot = k;
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_step(slbm_batch b, int64_t k)
 {
-    if (!b) return fail(SLBM_E_INVAL, "null batch");
-    if (k < 0) return fail(SLBM_E_INVAL, "negative step count");
-    if (b->precision < 0) return SLBM_OK;
-    DeviceGuard dg(b->device);
-    return b->precision == SLBM_FP32 ? batch_run<float>(b, k) : batch_run<double>(b, k);
+    return guarded([&]() -> int {
+        if (!b) return fail(SLBM_E_INVAL, "null batch");
+        if (k < 0) return fail(SLBM_E_INVAL, "negative step count");
+        if (b->precision < 0) return SLBM_OK;
+        DeviceGuard dg(b->device);
+        return b->precision == SLBM_FP32 ? batch_run<float>(b, k) : batch_run<double>(b, k);
+    });
 }
 
 int slbm_batch_poll(slbm_batch b, int32_t* done_slots, int32_t capacity, int32_t* n_done)
 {
-    if (!b || !n_done) return fail(SLBM_E_INVAL, "null argument");
-    int n = 0;
-    for (size_t k = 0; k < b->slot.size(); ++k) {
-        if (!b->slot[k] || b->remaining[k] > 0) continue;
-        if (done_slots && n < capacity) done_slots[n] = (int32_t)k;
-        ++n;
-    }
-    *n_done = n;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b || !n_done) return fail(SLBM_E_INVAL, "null argument");
+        int n = 0;
+        for (size_t k = 0; k < b->slot.size(); ++k) {
+            if (!b->slot[k] || b->remaining[k] > 0) continue;
+            if (done_slots && n < capacity) done_slots[n] = (int32_t)k;
+            ++n;
+        }
+        *n_done = n;
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h)
 {
-    if (!b || !h) return fail(SLBM_E_INVAL, "null argument");
-    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-    *h = b->slot[slot];
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b || !h) return fail(SLBM_E_INVAL, "null argument");
+        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+        *h = b->slot[slot];
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps)
 {
-    if (!b || !steps) return fail(SLBM_E_INVAL, "null argument");
-    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-    *steps = b->remaining[slot];
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b || !steps) return fail(SLBM_E_INVAL, "null argument");
+        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+        *steps = b->remaining[slot];
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_remove(slbm_batch b, int32_t slot)
 {
-    if (!b) return fail(SLBM_E_INVAL, "null batch");
-    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-    DeviceGuard dg(b->device);
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    slbm_destroy(b->slot[slot]);
-    b->slot[slot] = nullptr;
-    b->remaining[slot] = 0;
-    b->used -= b->bytes[slot];
-    b->bytes[slot] = 0;
-    b->dirty = true;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b) return fail(SLBM_E_INVAL, "null batch");
+        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+        DeviceGuard dg(b->device);
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        slbm_destroy(b->slot[slot]);
+        b->slot[slot] = nullptr;
+        b->remaining[slot] = 0;
+        b->used -= b->bytes[slot];
+        b->bytes[slot] = 0;
+        b->dirty = true;
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
 {
-    if (!b) return fail(SLBM_E_INVAL, "null batch");
-    if (strip != 62 && strip != 64 && strip != kStrip2) return fail(SLBM_E_INVAL, "strip must be 58, 62 or 64");
-    if (rows < 1 || rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
-        return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] ([1, 10] with strip 58)");
-    b->rows = rows;
-    b->wide = strip == 64 ? 1 : 0;
-    b->two = strip == kStrip2 ? 1 : 0;
-    b->dirty = true;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b) return fail(SLBM_E_INVAL, "null batch");
+        if (strip != 62 && strip != 64 && strip != kStrip2) return fail(SLBM_E_INVAL, "strip must be 58, 62 or 64");
+        if (rows < 1 || rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
+            return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] ([1, 10] with strip 58)");
+        b->rows = rows;
+        b->wide = strip == 64 ? 1 : 0;
+        b->two = strip == kStrip2 ? 1 : 0;
+        b->dirty = true;
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_sync(slbm_batch b)
 {
-    if (!b) return fail(SLBM_E_INVAL, "null batch");
-    DeviceGuard dg(b->device);
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b) return fail(SLBM_E_INVAL, "null batch");
+        DeviceGuard dg(b->device);
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget)
 {
-    if (!b) return fail(SLBM_E_INVAL, "null batch");
-    if (used) *used = b->used;
-    if (budget) *budget = b->budget;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b) return fail(SLBM_E_INVAL, "null batch");
+        if (used) *used = b->used;
+        if (budget) *budget = b->budget;
+        return SLBM_OK;
+    });
 }
 
 int slbm_batch_destroy(slbm_batch b)
 {
-    if (!b) return SLBM_OK;
-    DeviceGuard dg(b->device);
-    (void)hipStreamSynchronize(b->stream);
-    for (slbm_s* h : b->slot)
-        if (h) slbm_destroy(h);
-    batch_free_tables(b);
-    if (b->own_stream) (void)hipStreamDestroy(b->stream);
-    delete b;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!b) return SLBM_OK;
+        DeviceGuard dg(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        for (slbm_s* h : b->slot)
+            if (h) slbm_destroy(h);
+        batch_free_tables(b);
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return SLBM_OK;
+    });
 }
 
 const char* slbm_last_error(void) { return g_err.c_str(); }

@@ -114,140 +114,150 @@ extern "C" {
 
 int slbm3_create(const slbm3_params* p, slbm3_handle* out)
 {
-    if (!p || !out) return fail(SLBM_E_INVAL, "null argument");
-    *out = nullptr;
-    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(SLBM_E_INVAL, "box sizes must be positive");
-    if (!(p->mu > 0) || !(p->rho > 0)) return fail(SLBM_E_INVAL, "mu and rho must be positive");
-    if (!(p->tau_bar > 0.5)) return fail(SLBM_E_INVAL, "tau_bar must exceed 1/2");
-    if (!(p->lambda > -p->mu)) return fail(SLBM_E_INVAL, "lambda must exceed -mu");
-    if (p->precision != SLBM_FP32 && p->precision != SLBM_FP64) return fail(SLBM_E_INVAL, "bad precision");
-    const long long plane = (long long)p->nx * p->ny * p->nz;
-    if (plane * (long long)sizeof(double) >= (1LL << 32))
-        return fail(SLBM_E_UNSUPPORTED, "box exceeds 2^29 sites (kernels address planes with 32-bit offsets)");
-    if (!p->periodic_x) {
-        for (int s = 0; s < 2; ++s)
-            if (p->walls[s].kind != SLBM_DIRICHLET && p->walls[s].kind != SLBM_NEUMANN)
-                return fail(SLBM_E_INVAL, "wall %d: kind must be SLBM_DIRICHLET or SLBM_NEUMANN", s);
-    }
-    slbm3_s* h = new (std::nothrow) slbm3_s();
-    if (!h) return fail(SLBM_E_NOMEM, "out of host memory");
-    h->device = p->device;
-    h->nx = p->nx; h->ny = p->ny; h->nz = p->nz;
-    h->plane = plane;
-    h->precision = p->precision;
-    h->esize = p->precision == SLBM_FP32 ? 4 : 8;
-    h->px = p->periodic_x ? 1 : 0;
-    // units (section 5.1): c_s = sqrt(mu/rho) = dx/(sqrt 3 dt)
-    h->rho_user = p->rho;
-    h->dt_user = std::sqrt(p->rho / (3.0 * p->mu));
-    h->s_sigma = 3.0 * p->mu;
-    h->s_v = 1.0 / h->dt_user;
-    h->lamL = p->lambda / h->s_sigma;
-    h->muL = p->mu / h->s_sigma;
-    h->tau = p->tau_bar;
-    for (int k = 0; k < 3; ++k) h->FL[k] = p->body_force[k] / h->s_sigma;
-    if (!h->px) {
-        for (int s = 0; s < 2; ++s) {
-            h->wkind[s] = p->walls[s].kind;
-            const double scale = p->walls[s].kind == SLBM_DIRICHLET ? h->s_v : h->s_sigma;
-            for (int k = 0; k < 3; ++k) h->wval[s][k] = p->walls[s].value[k] / scale;
+    return guarded([&]() -> int {
+        if (!p || !out) return fail(SLBM_E_INVAL, "null argument");
+        *out = nullptr;
+        if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(SLBM_E_INVAL, "box sizes must be positive");
+        if (!(p->mu > 0) || !(p->rho > 0)) return fail(SLBM_E_INVAL, "mu and rho must be positive");
+        if (!(p->tau_bar > 0.5)) return fail(SLBM_E_INVAL, "tau_bar must exceed 1/2");
+        if (!(p->lambda > -p->mu)) return fail(SLBM_E_INVAL, "lambda must exceed -mu");
+        if (p->precision != SLBM_FP32 && p->precision != SLBM_FP64) return fail(SLBM_E_INVAL, "bad precision");
+        const long long plane = (long long)p->nx * p->ny * p->nz;
+        if (plane * (long long)sizeof(double) >= (1LL << 32))
+            return fail(SLBM_E_UNSUPPORTED, "box exceeds 2^29 sites (kernels address planes with 32-bit offsets)");
+        if (!p->periodic_x) {
+            for (int s = 0; s < 2; ++s)
+                if (p->walls[s].kind != SLBM_DIRICHLET && p->walls[s].kind != SLBM_NEUMANN)
+                    return fail(SLBM_E_INVAL, "wall %d: kind must be SLBM_DIRICHLET or SLBM_NEUMANN", s);
         }
-    }
-    DeviceGuard dg(h->device);
-#define TRY_OR_BAIL(expr)                                \
-    do {                                                 \
-        int rc_ = [&]() -> int { HIP_TRY(expr); return SLBM_OK; }(); \
-        if (rc_) { free3(h); delete h; return rc_; }     \
-    } while (0)
-    if (p->stream) {
-        h->stream = (hipStream_t)p->stream;
-    } else {
-        TRY_OR_BAIL(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-        h->own_stream = true;
-    }
-    const size_t pop = (size_t)19 * plane * h->esize;
-    TRY_OR_BAIL(hipMalloc(&h->buf[0], pop));
-    TRY_OR_BAIL(hipMalloc(&h->buf[1], pop));
-    TRY_OR_BAIL(hipMalloc((void**)&h->U, (size_t)3 * plane * sizeof(double)));
-    TRY_OR_BAIL(hipMalloc(&h->dens, (size_t)plane * h->esize));
-    TRY_OR_BAIL(hipMalloc((void**)&h->diverged, sizeof(unsigned int)));
-    // rest state: g = 0 (f = r), U = 0
-    TRY_OR_BAIL(hipMemsetAsync(h->buf[0], 0, pop, h->stream));
-    TRY_OR_BAIL(hipMemsetAsync(h->buf[1], 0, pop, h->stream));
-    TRY_OR_BAIL(hipMemsetAsync(h->U, 0, (size_t)3 * plane * sizeof(double), h->stream));
-    TRY_OR_BAIL(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
-    TRY_OR_BAIL(hipStreamSynchronize(h->stream));
-#undef TRY_OR_BAIL
-    *out = h;
-    return SLBM_OK;
+        slbm3_s* h = new (std::nothrow) slbm3_s();
+        if (!h) return fail(SLBM_E_NOMEM, "out of host memory");
+        h->device = p->device;
+        h->nx = p->nx; h->ny = p->ny; h->nz = p->nz;
+        h->plane = plane;
+        h->precision = p->precision;
+        h->esize = p->precision == SLBM_FP32 ? 4 : 8;
+        h->px = p->periodic_x ? 1 : 0;
+        // units (section 5.1): c_s = sqrt(mu/rho) = dx/(sqrt 3 dt)
+        h->rho_user = p->rho;
+        h->dt_user = std::sqrt(p->rho / (3.0 * p->mu));
+        h->s_sigma = 3.0 * p->mu;
+        h->s_v = 1.0 / h->dt_user;
+        h->lamL = p->lambda / h->s_sigma;
+        h->muL = p->mu / h->s_sigma;
+        h->tau = p->tau_bar;
+        for (int k = 0; k < 3; ++k) h->FL[k] = p->body_force[k] / h->s_sigma;
+        if (!h->px) {
+            for (int s = 0; s < 2; ++s) {
+                h->wkind[s] = p->walls[s].kind;
+                const double scale = p->walls[s].kind == SLBM_DIRICHLET ? h->s_v : h->s_sigma;
+                for (int k = 0; k < 3; ++k) h->wval[s][k] = p->walls[s].value[k] / scale;
+            }
+        }
+        DeviceGuard dg(h->device);
+    #define TRY_OR_BAIL(expr)                                \
+        do {                                                 \
+            int rc_ = [&]() -> int { HIP_TRY(expr); return SLBM_OK; }(); \
+            if (rc_) { free3(h); delete h; return rc_; }     \
+        } while (0)
+        if (p->stream) {
+            h->stream = (hipStream_t)p->stream;
+        } else {
+            TRY_OR_BAIL(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            h->own_stream = true;
+        }
+        const size_t pop = (size_t)19 * plane * h->esize;
+        TRY_OR_BAIL(hipMalloc(&h->buf[0], pop));
+        TRY_OR_BAIL(hipMalloc(&h->buf[1], pop));
+        TRY_OR_BAIL(hipMalloc((void**)&h->U, (size_t)3 * plane * sizeof(double)));
+        TRY_OR_BAIL(hipMalloc(&h->dens, (size_t)plane * h->esize));
+        TRY_OR_BAIL(hipMalloc((void**)&h->diverged, sizeof(unsigned int)));
+        // rest state: g = 0 (f = r), U = 0
+        TRY_OR_BAIL(hipMemsetAsync(h->buf[0], 0, pop, h->stream));
+        TRY_OR_BAIL(hipMemsetAsync(h->buf[1], 0, pop, h->stream));
+        TRY_OR_BAIL(hipMemsetAsync(h->U, 0, (size_t)3 * plane * sizeof(double), h->stream));
+        TRY_OR_BAIL(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
+        TRY_OR_BAIL(hipStreamSynchronize(h->stream));
+    #undef TRY_OR_BAIL
+        *out = h;
+        return SLBM_OK;
+    });
 }
 
 int slbm3_destroy(slbm3_handle h)
 {
-    if (!h) return SLBM_OK;
-    DeviceGuard dg(h->device);
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    free3(h);
-    delete h;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return SLBM_OK;
+        DeviceGuard dg(h->device);
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        free3(h);
+        delete h;
+        return SLBM_OK;
+    });
 }
 
 int slbm3_init_fields(slbm3_handle h, const double* rho, const double* vel, const double* sigma, const double* u)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    DeviceGuard dg(h->device);
-    int rc = ensure_scratch3(h);
-    if (rc) return rc;
-    const long long n = h->plane;
-    // lattice units on the host: delta-rho, j = rho v, P = -sigma - (lambda - mu) drho I, u0
-    std::vector<double> in((size_t)13 * n, 0.0);
-    for (long long s = 0; s < n; ++s) {
-        const double r = rho ? rho[s] / h->rho_user : 1.0;
-        if (!(r > 0)) return fail(SLBM_E_INVAL, "density must be positive");
-        in[s] = r - 1.0;
-        for (int k = 0; k < 3; ++k) {
-            in[(1 + k) * n + s] = vel ? r * vel[k * n + s] / h->s_v : 0.0;
-            in[(10 + k) * n + s] = u ? u[k * n + s] : 0.0;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        DeviceGuard dg(h->device);
+        int rc = ensure_scratch3(h);
+        if (rc) return rc;
+        const long long n = h->plane;
+        // lattice units on the host: delta-rho, j = rho v, P = -sigma - (lambda - mu) drho I, u0
+        std::vector<double> in((size_t)13 * n, 0.0);
+        for (long long s = 0; s < n; ++s) {
+            const double r = rho ? rho[s] / h->rho_user : 1.0;
+            if (!(r > 0)) return fail(SLBM_E_INVAL, "density must be positive");
+            in[s] = r - 1.0;
+            for (int k = 0; k < 3; ++k) {
+                in[(1 + k) * n + s] = vel ? r * vel[k * n + s] / h->s_v : 0.0;
+                in[(10 + k) * n + s] = u ? u[k * n + s] : 0.0;
+            }
+            for (int k = 0; k < 6; ++k) {
+                const double sg = sigma ? sigma[k * n + s] / h->s_sigma : 0.0;
+                in[(4 + k) * n + s] = -sg - (k < 3 ? (h->lamL - h->muL) * (r - 1.0) : 0.0);
+            }
         }
-        for (int k = 0; k < 6; ++k) {
-            const double sg = sigma ? sigma[k * n + s] / h->s_sigma : 0.0;
-            in[(4 + k) * n + s] = -sg - (k < 3 ? (h->lamL - h->muL) * (r - 1.0) : 0.0);
-        }
-    }
-    HIP_TRY(hipMemcpyAsync(h->scratch, in.data(), in.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    rc = launch3_any(h, 2);
-    if (rc) return rc;
-    HIP_TRY(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->local = true;
-    h->step = 0;
-    return SLBM_OK;
+        HIP_TRY(hipMemcpyAsync(h->scratch, in.data(), in.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        rc = launch3_any(h, 2);
+        if (rc) return rc;
+        HIP_TRY(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->local = true;
+        h->step = 0;
+        return SLBM_OK;
+    });
 }
 
 int slbm3_step(slbm3_handle h, int64_t nsteps)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
-    DeviceGuard dg(h->device);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        int rc = launch3_any(h, 0);
-        if (rc) return rc;
-        h->cur ^= 1;
-        h->local = false;
-        h->step += 1;
-    }
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
+        DeviceGuard dg(h->device);
+        for (int64_t k = 0; k < nsteps; ++k) {
+            int rc = launch3_any(h, 0);
+            if (rc) return rc;
+            h->cur ^= 1;
+            h->local = false;
+            h->step += 1;
+        }
+        return SLBM_OK;
+    });
 }
 
 int slbm3_sync(slbm3_handle h)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    DeviceGuard dg(h->device);
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    unsigned int flag = 0;
-    HIP_TRY(hipMemcpy(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost));
-    if (flag) return fail(SLBM_E_DIVERGED, "non-finite state (diverged)");
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        DeviceGuard dg(h->device);
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        unsigned int flag = 0;
+        HIP_TRY(hipMemcpy(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost));
+        if (flag) return fail(SLBM_E_DIVERGED, "non-finite state (diverged)");
+        return SLBM_OK;
+    });
 }
 
 // Outputs of the current state in user units (host arrays, x fastest).
@@ -266,49 +276,57 @@ static int outputs3(slbm3_handle h, std::vector<double>& o)
 
 int slbm3_moments(slbm3_handle h, double* rho, double* j, double* P, double* sigma)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    std::vector<double> o;
-    int rc = outputs3(h, o);
-    if (rc) return rc;
-    const long long n = h->plane;
-    const double sv = h->rho_user * h->s_v;
-    for (long long s = 0; s < n; ++s) {
-        if (rho) rho[s] = (1.0 + o[s]) * h->rho_user;
-        for (int k = 0; k < 3; ++k)
-            if (j) j[k * n + s] = o[(1 + k) * n + s] * sv;
-        for (int k = 0; k < 6; ++k) {
-            if (P) P[k * n + s] = o[(4 + k) * n + s] * h->s_sigma;
-            if (sigma) sigma[k * n + s] = o[(10 + k) * n + s] * h->s_sigma;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        std::vector<double> o;
+        int rc = outputs3(h, o);
+        if (rc) return rc;
+        const long long n = h->plane;
+        const double sv = h->rho_user * h->s_v;
+        for (long long s = 0; s < n; ++s) {
+            if (rho) rho[s] = (1.0 + o[s]) * h->rho_user;
+            for (int k = 0; k < 3; ++k)
+                if (j) j[k * n + s] = o[(1 + k) * n + s] * sv;
+            for (int k = 0; k < 6; ++k) {
+                if (P) P[k * n + s] = o[(4 + k) * n + s] * h->s_sigma;
+                if (sigma) sigma[k * n + s] = o[(10 + k) * n + s] * h->s_sigma;
+            }
         }
-    }
-    return SLBM_OK;
+        return SLBM_OK;
+    });
 }
 
 int slbm3_displacement(slbm3_handle h, double* u)
 {
-    if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
-    std::vector<double> o;
-    int rc = outputs3(h, o);
-    if (rc) return rc;
-    std::memcpy(u, o.data() + 16 * h->plane, (size_t)3 * h->plane * sizeof(double));
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
+        std::vector<double> o;
+        int rc = outputs3(h, o);
+        if (rc) return rc;
+        std::memcpy(u, o.data() + 16 * h->plane, (size_t)3 * h->plane * sizeof(double));
+        return SLBM_OK;
+    });
 }
 
 int slbm3_time(slbm3_handle h, int64_t* step, double* t_user)
 {
-    if (!h) return fail(SLBM_E_INVAL, "null handle");
-    if (step) *step = h->step;
-    if (t_user) *t_user = (double)h->step * h->dt_user;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (step) *step = h->step;
+        if (t_user) *t_user = (double)h->step * h->dt_user;
+        return SLBM_OK;
+    });
 }
 
 int slbm3_device_bytes(slbm3_handle h, int64_t* bytes)
 {
-    if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
-    int64_t b = 2 * (int64_t)19 * h->plane * (int64_t)h->esize + 3 * h->plane * 8 + h->plane * (int64_t)h->esize;
-    if (h->scratch) b += (int64_t)19 * h->plane * 8;
-    *bytes = b;
-    return SLBM_OK;
+    return guarded([&]() -> int {
+        if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
+        int64_t b = 2 * (int64_t)19 * h->plane * (int64_t)h->esize + 3 * h->plane * 8 + h->plane * (int64_t)h->esize;
+        if (h->scratch) b += (int64_t)19 * h->plane * 8;
+        *bytes = b;
+        return SLBM_OK;
+    });
 }
 
 }  // extern "C"
