@@ -43,47 +43,91 @@ def plane_strain_modulus(lam, mu):
     return 4.0 * mu * (lam + mu) / (lam + 2.0 * mu)
 
 
+def _freund_g(xi, a, b):
+    """Phase of the Rayleigh function on the branch cut a < xi < b:
+    tan g = 4 xi^2 sqrt((xi^2 - a^2)(b^2 - xi^2)) / (b^2 - 2 xi^2)^2, with
+    g in [0, pi/2] (the arctan in the inner integral of eq:ki1)."""
+    num = 4.0 * xi * xi * math.sqrt(max((xi * xi - a * a) * (b * b - xi * xi), 0.0))
+    return math.atan2(num, (b * b - 2.0 * xi * xi) ** 2)
+
+
+def _freund_inner(eta, a, b):
+    """Real part of the inner integral of eq:ki1 divided by pi:
+    (1/pi) p.v. int_a^b g(xi) 2 eta/(xi^2 - eta^2) dxi, written as the
+    principal value of [g(xi) 2 eta/(xi + eta)]/(xi - eta)."""
+    from scipy.integrate import quad
+    f = lambda xi: _freund_g(xi, a, b) * 2.0 * eta / (xi + eta)
+    if a < eta < b:
+        v = quad(f, a, b, weight="cauchy", wvar=eta, limit=400)[0]
+    else:
+        v = quad(lambda xi: f(xi) / (xi - eta), a, b, limit=400)[0]
+    return v / math.pi
+
+
+def _freund_outer(T, a, b, cr, inner):
+    """int_a^T Im(...) d eta of eq:ki1 (slownesses, l_c = 1 in T = t/l_c).
+
+    The inner path passes xi = eta (for a < eta < b) on a small semicircle
+    above the real axis, which adds -i pi times the residue g(eta) to the
+    principal value; after the 1/pi the exponential carries the phase
+    e^{-i g(eta)}.  sqrt((a - eta)/(a + eta)) = i sqrt((eta - a)/(eta + a))
+    for eta > a (principal branch).  Every other factor is real, so
+    Im(i e^{-i g} X) = X cos g.  The pole of (c_r + eta)/(c_r - eta) at
+    eta = c_r is taken as a principal value."""
+    from scipy.integrate import quad
+
+    def h(eta):
+        ph = math.cos(_freund_g(eta, a, b)) if a < eta < b else 1.0
+        return (math.sqrt(max(T - eta, 0.0)) * math.sqrt(max(eta - a, 0.0) / (eta + a)) * (cr + eta) / eta
+                * math.exp(inner(eta)) * ph)
+
+    if T > cr:
+        # int h/(c_r - eta) = -p.v. int h/(eta - c_r)
+        return -quad(h, a, T, weight="cauchy", wvar=cr, limit=400)[0]
+    return quad(lambda e: h(e) / (cr - e), a, T, limit=400)[0]
+
+
 def freund_k1(t_star, nu, cd, cs, lc, t, f_plus0=0.8774):
     """Mode-I stress intensity factor at one tip of a crack of length lc whose
     faces are suddenly loaded by t_star, from t = lc/c_d (when the waves
     scattered by the other tip arrive) to 2 lc/c_d: K^0 plus Freund's
-    correction (the paper's eq:ki1), with slownesses a = 1/c_d, b = 1/c_s and
-    c_r = 1/c_R.  Both integrals are Cauchy principal values: the inner one
-    at xi = eta, the outer one at eta = c_r; each is written as
-    p.v. int f(x)/(x - c) dx and evaluated by quadrature with that weight."""
-    import numpy as np
-    from scipy.integrate import quad
-
+    correction (the paper's eq:ki1, section 5.2), with slownesses a = 1/c_d,
+    b = 1/c_s and c_r = 1/c_R, and F_+(0) as the paper gives it.  The
+    contour and branch choices are those of :func:`_freund_outer`."""
     k0 = freund_k0(t_star, nu, cd, t)
     a, b = 1.0 / cd, 1.0 / cs
     cr = 1.0 / rayleigh_speed(cs, cd)
     T = t / lc
     if T <= a:
         return k0
+    I = _freund_outer(T, a, b, cr, lambda eta: _freund_inner(eta, a, b))
+    return k0 + 2.0 * t_star * f_plus0 / math.pi * math.sqrt(2.0 * lc / math.pi) * I
 
-    def g(xi):
-        num = 4.0 * xi * xi * math.sqrt(max((xi * xi - a * a) * (b * b - xi * xi), 0.0))
-        den = (b * b - 2.0 * xi * xi) ** 2
-        return math.atan2(num, den)
 
-    def inner(eta):
-        # (1/pi) p.v. int_a^b g(xi) 2 eta / (xi^2 - eta^2) dxi
-        f = lambda xi: g(xi) * 2.0 * eta / (xi + eta)
-        if a < eta < b:
-            v = quad(f, a, b, weight="cauchy", wvar=eta, limit=400)[0]
-        else:
-            v = quad(lambda xi: f(xi) / (xi - eta), a, b, limit=400)[0]
-        return v / math.pi
+def freund_k1_curve(t_star, nu, cd, cs, lc, times, f_plus0=0.8774, nodes=2400):
+    """freund_k1 at many times: the inner integral (a smooth function of eta
+    on [a, 2.5 a] apart from square-root behaviour at b) is tabulated once on
+    `nodes` points that include b and interpolated by cubic splines on each
+    side of b.  Valid for t <= 2.5 lc/c_d."""
+    import numpy as np
+    from scipy.interpolate import CubicSpline
 
-    def h(eta):
-        # Im of the outer integrand times (c_r - eta): sqrt((a - eta)/(a + eta))
-        # is i sqrt((eta - a)/(eta + a)) for eta > a, everything else is real
-        return (math.sqrt(max(T - eta, 0.0)) * math.sqrt(max(eta - a, 0.0) / (eta + a)) * (cr + eta) / eta
-                * math.exp(inner(eta)))
-
-    if T > cr:
-        # int h/(c_r - eta) = -p.v. int h/(eta - c_r)
-        integral = -quad(h, a, T, weight="cauchy", wvar=cr, limit=400)[0]
-    else:
-        integral = quad(lambda e: h(e) / (cr - e), a, T, limit=400)[0]
-    return k0 + 2.0 * t_star * f_plus0 / math.pi * math.sqrt(2.0 * lc / math.pi) * integral
+    a, b = 1.0 / cd, 1.0 / cs
+    cr = 1.0 / rayleigh_speed(cs, cd)
+    lo = np.linspace(a, b, nodes // 2)
+    hi = np.linspace(b, 2.5 * a, nodes // 2)
+    s_lo = CubicSpline(lo, [_freund_inner(e, a, b) for e in lo])
+    s_hi = CubicSpline(hi, [_freund_inner(e, a, b) for e in hi])
+    inner = lambda eta: float(s_lo(eta) if eta <= b else s_hi(eta))
+    out = []
+    for t in times:
+        k0 = freund_k0(t_star, nu, cd, max(t, 0.0))
+        T = t / lc
+        if T <= a:
+            out.append(k0)
+            continue
+        if T > 2.5 * a:
+            raise ValueError("freund_k1_curve is tabulated up to t = 2.5 lc/c_d")
+        I = _freund_outer(T, a, b, cr, inner)
+        out.append(k0 + 2.0 * t_star * f_plus0 / math.pi * math.sqrt(2.0 * lc / math.pi) * I)
+    return np.array(out)

@@ -474,8 +474,9 @@ def test_paper_crack_follows_freund_k0():
 def test_freund_k1_structure():
     """The evaluator of Freund's K^1 (eq:ki1) for the paper's solid: equal to
     K^0 until t = l_c/c_d, above it afterwards (the waves scattered by the
-    other tip add to the opening), and rising fastest near the arrival of the
-    Rayleigh waves from the other tip (t = c_r l_c = 1.82 l_c/c_d)."""
+    other tip add to the opening), rising fastest at the arrival of the
+    Rayleigh waves from the other tip (t = c_r l_c = 1.82 l_c/c_d) and
+    levelling off after it (section 5.2)."""
     cd, cs, lc, ts = 1.0, math.sqrt(0.3611), 1.0, 1.0
     nu = CF.nu_from_speed_ratio(1 / 0.3611)
     k0 = lambda t: CF.freund_k0(ts, nu, cd, t)
@@ -484,6 +485,88 @@ def test_freund_k1_structure():
     assert abs(k1(1.0 + 1e-6) - k0(1.0 + 1e-6)) < 1e-4 * k0(1.0)
     v = [k1(t) - k0(t) for t in (1.2, 1.5, 1.7, 1.8)]
     assert all(x > 0 for x in v) and v == sorted(v)
-    slope_early = (v[1] - v[0]) / 0.3
-    slope_late = (v[3] - v[2]) / 0.1
-    assert slope_late > slope_early
+    slope_early = (k1(1.5) - k1(1.2)) / 0.3
+    slope_arrival = (k1(1.85) - k1(1.75)) / 0.1
+    slope_after = (k1(2.0) - k1(1.9)) / 0.1
+    assert slope_arrival > 2 * slope_early
+    assert slope_after < 0.5 * slope_early
+
+
+def test_rayleigh_function_factors_at_zero():
+    """The arctan phase g that the inner integral of eq:ki1 integrates is the
+    phase of the Rayleigh function R(z) = (b^2 - 2z^2)^2 + 4 z^2 sqrt(a^2 - z^2)
+    sqrt(b^2 - z^2) on its branch cut.  Its factors
+    S(z) = exp(-(1/pi) int_a^b g(xi) dxi/(xi + z)) satisfy
+    R = 2 (b^2 - a^2)(c_r^2 - z^2) S(z) S(-z); at z = 0 this reads
+    S(0)^2 = b^4 / (2 (b^2 - a^2) c_r^2), with c_r from the Rayleigh root."""
+    from scipy.integrate import quad
+    for cs2 in (0.3611, 1.0 / 3.0, 0.45):
+        cs = math.sqrt(cs2)
+        a, b, cr = 1.0, 1.0 / cs, 1.0 / CF.rayleigh_speed(cs, 1.0)
+        s0 = math.exp(-quad(lambda x: CF._freund_g(x, a, b) / x, a, b, limit=400)[0] / math.pi)
+        assert abs(s0 * s0 - b ** 4 / (2 * (b * b - a * a) * cr * cr)) < 1e-9, cs2
+
+
+def _k1_integral_by_contour(T, a, b, cr, eps=2e-5, delta=1e-4):
+    """The integral of eq:ki1 evaluated as printed, in complex arithmetic:
+    principal square roots, the arctan continued off the real axis as
+    (log(D + iN) - log(D - iN))/2i, the inner pole at xi = eta passed on a
+    semicircle of radius eps above the real axis (quadrature in the angle),
+    and the outer pole at eta = c_r excluded symmetrically (principal
+    value).  Shares nothing with closed_forms but the Rayleigh root."""
+    from scipy.integrate import quad
+
+    def gc(xi):
+        N = 4 * xi * xi * np.sqrt((xi * xi - a * a) * (b * b - xi * xi) + 0j)
+        D = (b * b - 2 * xi * xi) ** 2 + 0j
+        return (np.log(D + 1j * N) - np.log(D - 1j * N)) / 2j
+
+    def inner(eta):
+        f = lambda xi: (gc(xi) * 2 * eta / (xi * xi - eta * eta)).real
+        if not a < eta < b:
+            return quad(f, a, b, limit=400)[0] + 0j
+        s = quad(f, a, eta - eps, limit=400)[0] + quad(f, eta + eps, b, limit=400)[0]
+        z = lambda th: eta + eps * np.exp(1j * th)
+        arc = lambda th: gc(z(th)) * 2 * eta / (z(th) ** 2 - eta * eta) * 1j * eps * np.exp(1j * th)
+        # the semicircle runs from theta = pi down to 0
+        return s - (quad(lambda th: arc(th).real, 0, math.pi)[0] + 1j * quad(lambda th: arc(th).imag, 0, math.pi)[0])
+
+    def h(eta):
+        return (np.sqrt(T - eta + 0j) * np.sqrt((a - eta) / (a + eta) + 0j) * (cr + eta) / (cr - eta) / eta
+                * np.exp(inner(eta) / math.pi)).imag
+
+    if T <= cr:
+        return quad(h, a, T, limit=200)[0]
+    return quad(h, a, cr - delta, limit=200)[0] + quad(h, cr + delta, T, limit=200)[0]
+
+
+def test_freund_k1_matches_contour_evaluation():
+    """The real form the K^1 evaluator integrates (principal values plus the
+    phase that the semicircle around the inner pole contributes) equals
+    eq:ki1 evaluated literally along the contour the paper describes, before
+    and after the Rayleigh pole.  Dropping the semicircle's contribution
+    makes the first value 8 times larger."""
+    cs = math.sqrt(0.3611)
+    a, b, cr = 1.0, 1.0 / cs, 1.0 / CF.rayleigh_speed(cs, 1.0)
+    for T, tol in ((1.5, 1e-6), (1.95, 1e-3)):
+        lit = _k1_integral_by_contour(T, a, b, cr)
+        red = CF._freund_outer(T, a, b, cr, lambda e: CF._freund_inner(e, a, b))
+        assert abs(lit - red) <= tol * abs(red), (T, lit, red)
+    curve = CF.freund_k1_curve(1.0, CF.nu_from_speed_ratio(1 / 0.3611), 1.0, cs, 1.0, [1.3, 1.9])
+    for t, v in zip((1.3, 1.9), curve):
+        assert abs(v - CF.freund_k1(1.0, CF.nu_from_speed_ratio(1 / 0.3611), 1.0, cs, 1.0, t)) < 1e-5 * v
+
+
+def test_paper_crack_follows_freund_k1():
+    """Section 5.2 past the first scattered waves: on the paper's 400 x 400
+    crack, from t = l_c/c_d (when the waves scattered by the other tip
+    arrive) to 1.75 l_c/c_d, the stress intensity factor at P_1 keeps the
+    ratio to Freund's K^1 that it has at l_c/c_d, within 2 % (the K^0
+    continuation drifts by 5 %); its steepest rise comes with the Rayleigh
+    waves from the other tip, at c_r l_c within 0.05 l_c/c_d."""
+    from crack_sif import paper_crack_k1_window
+    p = configs.paper_center_crack()
+    o = Oracle(p)
+    _, _, drift, t_steep, t_rayleigh = paper_crack_k1_window(o.step, lambda: o.moments()[3][0], p)
+    assert drift < 0.02, drift
+    assert abs(t_steep - t_rayleigh) < 0.05, (t_steep, t_rayleigh)
