@@ -260,17 +260,25 @@ int slbm3_sync(slbm3_handle h)
     });
 }
 
-// Outputs of the current state in user units (host arrays, x fastest).
-static int outputs3(slbm3_handle h, std::vector<double>& o)
+// Outputs of the current state (lattice units) into the device scratch
+// planes, laid out as k3_outputs writes them.
+static int outputs3(slbm3_handle h)
 {
-    DeviceGuard dg(h->device);
     int rc = ensure_scratch3(h);
     if (rc) return rc;
-    rc = launch3_any(h, 1);
-    if (rc) return rc;
-    o.resize((size_t)19 * h->plane);
-    HIP_TRY(hipMemcpyAsync(o.data(), h->scratch, o.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return launch3_any(h, 1);
+}
+
+// Planes [first, first + count) of the output scratch into a host array (x
+// fastest), then x -> (x + add) * scale (lattice to user units).
+static int copy_planes3(slbm3_handle h, int first, int count, double add, double scale, double* dst)
+{
+    const size_t n = (size_t)count * (size_t)h->plane;
+    HIP_TRY(hipMemcpyAsync(dst, h->scratch + (size_t)first * (size_t)h->plane, n * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    if (add != 0.0 || scale != 1.0)
+        for (size_t s = 0; s < n; ++s) dst[s] = (dst[s] + add) * scale;
     return SLBM_OK;
 }
 
@@ -278,20 +286,13 @@ int slbm3_moments(slbm3_handle h, double* rho, double* j, double* P, double* sig
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
-        std::vector<double> o;
-        int rc = outputs3(h, o);
+        DeviceGuard dg(h->device);
+        int rc = outputs3(h);
         if (rc) return rc;
-        const long long n = h->plane;
-        const double sv = h->rho_user * h->s_v;
-        for (long long s = 0; s < n; ++s) {
-            if (rho) rho[s] = (1.0 + o[s]) * h->rho_user;
-            for (int k = 0; k < 3; ++k)
-                if (j) j[k * n + s] = o[(1 + k) * n + s] * sv;
-            for (int k = 0; k < 6; ++k) {
-                if (P) P[k * n + s] = o[(4 + k) * n + s] * h->s_sigma;
-                if (sigma) sigma[k * n + s] = o[(10 + k) * n + s] * h->s_sigma;
-            }
-        }
+        if (rho && (rc = copy_planes3(h, 0, 1, 1.0, h->rho_user, rho))) return rc;
+        if (j && (rc = copy_planes3(h, 1, 3, 0.0, h->rho_user * h->s_v, j))) return rc;
+        if (P && (rc = copy_planes3(h, 4, 6, 0.0, h->s_sigma, P))) return rc;
+        if (sigma && (rc = copy_planes3(h, 10, 6, 0.0, h->s_sigma, sigma))) return rc;
         return SLBM_OK;
     });
 }
@@ -300,11 +301,10 @@ int slbm3_displacement(slbm3_handle h, double* u)
 {
     return guarded([&]() -> int {
         if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
-        std::vector<double> o;
-        int rc = outputs3(h, o);
+        DeviceGuard dg(h->device);
+        int rc = outputs3(h);
         if (rc) return rc;
-        std::memcpy(u, o.data() + 16 * h->plane, (size_t)3 * h->plane * sizeof(double));
-        return SLBM_OK;
+        return copy_planes3(h, 16, 3, 0.0, 1.0, u);
     });
 }
 
