@@ -150,6 +150,14 @@ int slbm_displacement(slbm_handle h, double* u);
  * the handle's stream, without synchronising. */
 int slbm_displacement_device(slbm_handle h, void* u_dev);
 
+/* Same as slbm_moments into device memory on the handle's stream, without
+ * synchronising: rho_dev [n], j_dev [2][n], P_dev [3][n], sigma_dev [3][n]
+ * (any pointer may be NULL), each an array of doubles (dtype SLBM_FP64) or
+ * floats (SLBM_FP32, the double values rounded to nearest).  The arrays
+ * belong to the caller and must be device memory on the handle's device,
+ * valid until the queued work has run.  SLBM_E_INVAL for another dtype. */
+int slbm_moments_device(slbm_handle h, void* rho_dev, void* j_dev, void* P_dev, void* sigma_dev, int dtype);
+
 /* Step count and physical time of the current state. */
 int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 

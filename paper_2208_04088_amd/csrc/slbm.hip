@@ -204,6 +204,18 @@ __global__ __launch_bounds__(256) void k_unpad_u(const double* out, int nx, int 
     u[(long long)nx * ny + idx] = out[P + sidx(x, y, ld)];
 }
 
+// One padded lattice-unit plane, times a unit scale, into a caller's
+// unpadded [ny][nx] device array of doubles or floats.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpad_scaled(const double* plane, int nx, int ny, int ld, double scale,
+                                                      T* dst)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nx * ny) return;
+    const int y = idx / nx, x = idx - y * nx;
+    dst[idx] = (T)(plane[sidx(x, y, ld)] * scale);
+}
+
 // ------------------------------------------------------- initial state
 
 // Equilibrium of given lattice-unit fields (drho, j, P) with j the physical
@@ -880,6 +892,37 @@ int slbm_displacement_device(slbm_handle h, void* u_dev)
         const int n = h->nx * h->ny;
         hipLaunchKernelGGL(k_unpad_u, dim3((n + 255) / 256), dim3(256), 0, h->stream,
                            (const double*)(h->scratch + h->plane), h->nx, h->ny, h->ld, (double*)u_dev);
+        HIP_TRY(hipGetLastError());
+        release_transient_scratch(h);
+        return SLBM_OK;
+    });
+}
+
+int slbm_moments_device(slbm_handle h, void* rho, void* j, void* P, void* sigma, int dtype)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (dtype != SLBM_FP64 && dtype != SLBM_FP32) return fail(SLBM_E_INVAL, "dtype must be SLBM_FP64 or SLBM_FP32");
+        DeviceGuard dg(h->device);
+        int rc = outputs(h, true);
+        if (rc) return rc;
+        const int n = h->nx * h->ny;
+        const double sj = h->rho_user * h->s_v;
+        // output components (as in slbm_moments): 0 rho, 1-2 j, 3-5 P, 6-8 sigma
+        const struct { void* dst; int first, count; double scale; } part[4] = {
+            {rho, 0, 1, h->rho_user}, {j, 1, 2, sj}, {P, 3, 3, h->s_sigma}, {sigma, 6, 3, h->s_sigma}};
+        for (const auto& pt : part) {
+            if (!pt.dst) continue;
+            for (int c = 0; c < pt.count; ++c) {
+                const double* src = h->scratch + (size_t)(1 + pt.first + c) * h->plane;
+                if (dtype == SLBM_FP64)
+                    hipLaunchKernelGGL(k_unpad_scaled<double>, dim3((n + 255) / 256), dim3(256), 0, h->stream, src,
+                                       h->nx, h->ny, h->ld, pt.scale, (double*)pt.dst + (size_t)c * n);
+                else
+                    hipLaunchKernelGGL(k_unpad_scaled<float>, dim3((n + 255) / 256), dim3(256), 0, h->stream, src,
+                                       h->nx, h->ny, h->ld, pt.scale, (float*)pt.dst + (size_t)c * n);
+            }
+        }
         HIP_TRY(hipGetLastError());
         release_transient_scratch(h);
         return SLBM_OK;

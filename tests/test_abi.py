@@ -138,3 +138,10 @@ def test_valid_problem_without_a_gpu_fails_loudly():
         pytest.skip("a GPU is present")
     rc, msg = _create(_plate())
     assert rc == -3, (rc, msg)
+
+
+def test_device_moments_reject_a_null_handle():
+    """slbm_moments_device checks its arguments before any device call."""
+    L = S.lib()
+    assert L.slbm_moments_device(None, None, None, None, None, S.FP64) == -1
+    assert "handle" in L.slbm_last_error().decode()

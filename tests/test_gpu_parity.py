@@ -325,6 +325,34 @@ def test_displacement_to_device_memory(slbm):
     assert np.array_equal(t.cpu().numpy(), s.displacement())
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_moments_to_device_memory(slbm, prec):
+    """slbm_moments_device writes what slbm_moments returns: the same doubles
+    (dtype fp64), or those doubles rounded to float (dtype fp32), on the
+    handle's stream; NULL pointers skip their fields."""
+    import torch
+    p = mixed_plate(70, 40, seed=13)
+    stream = torch.cuda.Stream()
+    s = slbm.Solver(p, prec, stream=stream.cuda_stream)
+    s.step(30)
+    ref = s.moments()
+    for dt, tdt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        with torch.cuda.stream(stream):
+            t = [torch.full(sh, 7.0, dtype=tdt, device="cuda")
+                 for sh in ((p.ny, p.nx), (2, p.ny, p.nx), (3, p.ny, p.nx), (3, p.ny, p.nx))]
+        s.moments_device(*[x.data_ptr() for x in t], dtype=dt)
+        stream.synchronize()
+        for got, want in zip(t, ref):
+            w = want.astype(np.float32) if dt == "fp32" else want
+            assert np.array_equal(got.cpu().numpy(), w)
+        with torch.cuda.stream(stream):
+            only_j = torch.full((2, p.ny, p.nx), 7.0, dtype=tdt, device="cuda")
+        s.moments_device(0, only_j.data_ptr(), 0, 0, dtype=dt)
+        stream.synchronize()
+        w = ref[1].astype(np.float32) if dt == "fp32" else ref[1]
+        assert np.array_equal(only_j.cpu().numpy(), w)
+
+
 # ------------------------------------------------------- full sizes --
 
 def rigid_part(d, mask):
