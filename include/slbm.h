@@ -222,6 +222,10 @@ int slbm_batch_poll(slbm_batch b, int32_t* done_slots, int32_t capacity, int32_t
 int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h);
 int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps);
 
+/* The plate's displacement [2][n] in cells, into a host array (slbm_displacement
+ * of the slot's handle).  SLBM_E_INVAL for an empty slot.  Synchronises. */
+int slbm_batch_displacement(slbm_batch b, int32_t slot, double* u);
+
 /* Frees the plate (its slot and budget are reused). */
 int slbm_batch_remove(slbm_batch b, int32_t slot);
 

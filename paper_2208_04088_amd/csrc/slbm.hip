@@ -1477,6 +1477,15 @@ int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h)
     });
 }
 
+int slbm_batch_displacement(slbm_batch b, int32_t slot, double* u)
+{
+    return guarded([&]() -> int {
+        if (!b || !u) return fail(SLBM_E_INVAL, "null argument");
+        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
+        return slbm_displacement(b->slot[slot], u);
+    });
+}
+
 int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps)
 {
     return guarded([&]() -> int {

@@ -25,7 +25,7 @@ EXPORTS = [
     "slbm_displacement", "slbm_displacement_device", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
-    "slbm_batch_remaining", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_sync",
+    "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_sync",
     "slbm_batch_bytes", "slbm_batch_destroy",
 ]
 
@@ -90,6 +90,7 @@ def lib():
         "slbm_batch_step": [vp, i64],
         "slbm_batch_poll": [vp, C.POINTER(i32), i32, C.POINTER(i32)],
         "slbm_batch_handle": [vp, i32, C.POINTER(vp)],
+        "slbm_batch_displacement": [vp, i32, vp],
         "slbm_batch_remaining": [vp, i32, C.POINTER(i64)],
         "slbm_batch_remove": [vp, i32],
         "slbm_batch_set_launch": [vp, i32, i32],
@@ -287,6 +288,13 @@ class Batch:
         h = C.c_void_p()
         _check(lib().slbm_batch_handle(self.b, int(slot), C.byref(h)))
         return _BorrowedSolver(self.plates[slot], h)
+
+    def displacement(self, slot):
+        """The plate's displacement [2, ny, nx] in cells."""
+        p = self.plates[slot]
+        u = np.empty((2, p.ny, p.nx))
+        _check(lib().slbm_batch_displacement(self.b, int(slot), u.ctypes.data_as(C.c_void_p)))
+        return u
 
     def remaining(self, slot):
         r = C.c_int64()

@@ -145,3 +145,8 @@ def test_device_moments_reject_a_null_handle():
     L = S.lib()
     assert L.slbm_moments_device(None, None, None, None, None, S.FP64) == -1
     assert "handle" in L.slbm_last_error().decode()
+
+
+def test_batch_displacement_rejects_a_null_batch():
+    L = S.lib()
+    assert L.slbm_batch_displacement(None, 0, None) == -1

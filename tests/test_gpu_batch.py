@@ -57,6 +57,7 @@ def test_batched_plates_match_their_solo_runs(slbm, prec, launch):
         s.sync()
         u_ref, sig_ref = alone(slbm, p, n, prec)
         assert np.array_equal(s.displacement(), u_ref), p.name
+        assert np.array_equal(b.displacement(sl), u_ref), p.name
         assert np.array_equal(s.moments()[3], sig_ref), p.name
     b.close()
 
@@ -80,7 +81,7 @@ def test_continuous_batching_joins_and_leaves(slbm, launch):
         for sl in b.poll():
             i = live.pop(sl)
             s = b.solver(sl)
-            finished[i] = (s.time()[0], s.displacement())
+            finished[i] = (s.time()[0], b.displacement(sl))
             b.remove(sl)
     assert sorted(finished) == list(range(6))
     for i, (n, u) in finished.items():
