@@ -327,7 +327,8 @@ def run_batch(args, slbm, torch, dev, stream):
 
 def run_serve(args, slbm, torch, dev, stream):
     """The first `--requests` requests of the served trace (seed 1, Poisson
-    arrivals at 50/s, plates 256^2-4096^2, 1e3-2e4 steps) under a 200 GB
+    arrivals at `--rate` per second, 50 by default, plates 256^2-4096^2,
+    1e3-2e4 steps; the rate only stretches the arrival times) under a 200 GB
     budget: continuous batching (paper_2208_04088_amd.serve.Server) against
     the same requests one plate at a time (oldest first, and least work
     first).  Latency runs from a request's
@@ -335,7 +336,7 @@ def run_serve(args, slbm, torch, dev, stream):
     from paper_2208_04088_amd import serve
     from slbm_workloads import configs
     t = time.perf_counter()
-    trace = configs.served_trace(seed=1, count=args.requests)
+    trace = configs.served_trace(seed=1, count=args.requests, rate=args.rate)
     t_build = time.perf_counter() - t
     work = sum(r.plate.n_material * r.steps for r in trace)
     launch = (6, 58)                     # two steps per launch, 6 rows per tile
@@ -356,8 +357,8 @@ def run_serve(args, slbm, torch, dev, stream):
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {
-            "workload": f"served-trace-seed1-first{args.requests}", "requests": args.requests,
-            "arrival_rate_per_s": 50, "hbm_budget_gb": 200,
+            "workload": f"served-trace-seed1-first{args.requests}" + ("" if args.rate == 50 else f"-rate{args.rate:g}"),
+            "requests": args.requests, "arrival_rate_per_s": args.rate, "hbm_budget_gb": 200,
             "precision": "fp32 populations and arithmetic, fp64 displacement",
             "bench_step": "serve every request of the trace (each plate its own step count)",
             "policy": "least work first, at most 2M material sites resident (more when one plate is larger)",
@@ -385,6 +386,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="crack1024x512")
+    ap.add_argument("--rate", type=float, default=50.0, help="arrival rate of the served trace (requests/s)")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--seg", type=int, default=0, help="rows per tile (0: autotuned)")
     ap.add_argument("--strip", type=int, default=0,
