@@ -420,6 +420,57 @@ def test_hole_config_full_size(slbm, lam, tau, steps):
 
 
 @pytest.mark.slow
+def test_square4096_full_size_in_the_bench_launch_shape(slbm):
+    """The 4096 x 4096 clamped/pulled plate the benchmark times, at full size
+    in the shape the autotuner picks for it (two steps per launch, 10 rows),
+    fp32, 120 steps: displacement and moments against the reference."""
+    p = configs.square_clamped_pulled(4096, steps=120)
+    s = slbm.Solver(p, "fp32")
+    s.set_launch(10, 58)
+    s.step(p.steps)
+    s.sync()
+    ref = Oracle(p)
+    ref.step(p.steps)
+    e = compare(s, ref, "fp32")
+    print(f"square4096 fp32 {p.steps} steps (10 x 58): rel L2 u = {e:.3e}")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_largest_grid(slbm, prec):
+    """The largest grid the library accepts, 16384 x 16384 = 2^28 sites, in
+    the two-steps-per-launch shape: left edge clamped, right edge pulled by a
+    step traction, 10 steps.  A site's state after k steps depends only on
+    sites within 2k columns (one for the pull, one for the density stencil,
+    per step), so the right-most columns must equal those of a 64-column
+    plate with the same edges run by the reference, and every site farther
+    than 2k columns from the pulled edge must still be exactly at rest."""
+    n, k, w = 16384, 10, 64
+    full = configs.square_clamped_pulled(n, steps=k)
+    assert full.nx * full.ny == 1 << 28
+    s = slbm.Solver(full, prec)
+    s.set_launch(10, 58)
+    s.step(k)
+    s.sync()
+    u = s.displacement()
+    s.close()
+    print(f"largest grid {prec}: {k} steps on {n} x {n} done", flush=True)
+    crop = G.build_plate(w, n, lam=full.lam, mu=full.mu, tau=full.tau,
+                         walls=G.edge_walls(w, n, left=0, right=1, bottom=2, top=2), groups=full.groups,
+                         neumann_order=full.neumann_order, name="crop")
+    ref = Oracle(crop, extended=(prec == "fp64"))
+    ref.step(k)
+    u_ref = ref.displacement()
+    m = w - 2 * k - 2                              # columns beyond the cropped plate's own left edge's reach
+    a, b = u[:, :, n - m:], u_ref[:, :, w - m:]
+    e = rel_l2(a, b)
+    print(f"largest grid {prec}: right-most {m} columns vs reference rel L2 {e:.3e}", flush=True)
+    assert np.abs(b).max() > 0
+    assert e <= (FP64_TOL if prec == "fp64" else FP32_TOL), e
+    assert not np.any(u[:, :, : n - 2 * k - 1])
+
+
+@pytest.mark.slow
 def test_crack_tip_sif_fp32_follows_freund_k0(slbm):
     """The fp32 HIP path reproduces Freund's K^0 growth on the 1024 x 512
     edge crack (within 5 %) and the reference's own fit (within 1e-3)."""

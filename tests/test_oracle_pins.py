@@ -417,6 +417,39 @@ def test_rayleigh_root_closed_form():
     assert abs(CF.rayleigh_speed(cs, cd) / cs - 0.91940) < 1e-5
 
 
+def test_domain_of_dependence_is_two_columns_per_step():
+    """A step reads neighbours one site away (the pull) and the density of
+    the pulled state one site further (the source term's gradient), so after
+    k steps a site depends only on sites within 2k columns.  A 256-wide plate
+    pulled on its right edge and a 64-wide plate with the same edges then
+    agree exactly in their right-most 64 - 2k - 2 columns, and sites farther
+    than 2k columns from the pulled edge are exactly as in the same plate
+    without the load (at rest up to the rounding of the unshifted rest
+    populations, which both share)."""
+    n, k, w = 256, 10, 64
+    full = configs.square_clamped_pulled(n, steps=k)
+    crop = G.build_plate(w, n, lam=full.lam, mu=full.mu, tau=full.tau,
+                         walls=G.edge_walls(w, n, left=0, right=1, bottom=2, top=2), groups=full.groups,
+                         neumann_order=full.neumann_order, name="crop")
+    a, b = Oracle(full), Oracle(crop)
+    a.step(k)
+    b.step(k)
+    ua, ub = a.displacement(), b.displacement()
+    m = w - 2 * k - 2
+    assert np.abs(ub[:, :, w - m:]).max() > 0
+    assert np.array_equal(ua[:, :, n - m:], ub[:, :, w - m:])
+    rest = G.build_plate(n, n, lam=full.lam, mu=full.mu, tau=full.tau,
+                         walls=G.edge_walls(n, n, left=0, right=1, bottom=2, top=2),
+                         groups=[full.groups[0], G.BCGroup(G.NEUMANN, (0.0, 0.0)), full.groups[2]],
+                         neumann_order=full.neumann_order, name="rest")
+    r = Oracle(rest)
+    r.step(k)
+    u0 = r.displacement()
+    far = n - 2 * k - 1
+    assert np.array_equal(ua[:, :, :far], u0[:, :, :far])
+    assert not np.array_equal(ua[:, :, far:], u0[:, :, far:])
+
+
 # ------------------------------------------------ Freund's K^0 (crack) --
 
 def test_crack_tip_sif_follows_freund_k0():
