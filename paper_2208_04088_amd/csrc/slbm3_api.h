@@ -123,8 +123,8 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
         if (!(p->lambda > -p->mu)) return fail(SLBM_E_INVAL, "lambda must exceed -mu");
         if (p->precision != SLBM_FP32 && p->precision != SLBM_FP64) return fail(SLBM_E_INVAL, "bad precision");
         const long long plane = (long long)p->nx * p->ny * p->nz;
-        if (plane * (long long)sizeof(double) >= (1LL << 32))
-            return fail(SLBM_E_UNSUPPORTED, "box exceeds 2^29 sites (kernels address planes with 32-bit offsets)");
+        if (plane > (1LL << 29))
+            return fail(SLBM_E_UNSUPPORTED, "box exceeds 2^29 sites (kernels index a plane's sites with 32-bit offsets)");
         if (!p->periodic_x) {
             for (int s = 0; s < 2; ++s)
                 if (p->walls[s].kind != SLBM_DIRICHLET && p->walls[s].kind != SLBM_NEUMANN)

@@ -157,3 +157,32 @@ def test_fp32_long_run(S3):
     fields = dict(vel=B.random_velocity(box, 40, 1e-3))
     out, ref = run_both(S3, box, "fp32", 5000, fields)
     check(out, ref, FP32_TOL, "periodic fp32 5000 steps", box)
+
+
+@pytest.mark.slow
+def test_largest_box(S3):
+    """The largest box the library accepts, 1024 x 1024 x 512 = 2^29 sites,
+    fp32: clamped at x = -1/2, pulled at x = nx - 1/2 by a step traction,
+    periodic in y and z.  The solution depends on x alone, so after 10 steps
+    sampled (y, z) columns equal the first one bit for bit, and that column
+    matches the reference run on a 1024 x 2 x 2 slab of the same walls."""
+    nx, ny, nz, k = 1024, 1024, 512, 10
+    walls = (B.Wall3(B.DIRICHLET), B.Wall3(B.NEUMANN, (5e-5, 0.0, 0.0)))
+    box = B.slab3(nx, ny, nz, *walls)
+    assert box.nx * box.ny * box.nz == 1 << 29
+    s = S3.Solver3(box, "fp32")
+    s.step(k)
+    s.sync()
+    u = s.displacement().reshape(3, ny * nz, nx)
+    s.close()
+    print(f"largest box: {k} steps on {nx} x {ny} x {nz} done", flush=True)
+    cols = np.random.default_rng(5).integers(0, ny * nz, 4096)
+    assert np.array_equal(u[:, cols, :], np.broadcast_to(u[:, :1, :], (3, cols.size, nx)))
+    assert np.array_equal(u[:, -1, :], u[:, 0, :])
+    o = Oracle3D(B.slab3(nx, 2, 2, *walls))
+    o.step(k)
+    u_ref = o.displacement()[:, 0, 0, :]
+    e = rel_l2(u[:, 0, :], u_ref)
+    print(f"largest box: x-profile vs reference rel L2 {e:.3e}", flush=True)
+    assert np.abs(u_ref).max() > 0
+    assert e <= FP32_TOL, e
