@@ -95,7 +95,7 @@ typedef struct {
 } slbm_link;
 
 typedef struct {
-    int32_t nx, ny;
+    int32_t nx, ny;          /* sites, each >= 1; at most 2^28 in total */
     double lambda, mu, rho;  /* user units, dx = 1 cell */
     double tau;              /* BGK relaxation time in units of dt, > 1/2 */
     double body_force[2];    /* uniform body force per volume, user units */
@@ -119,7 +119,8 @@ typedef struct slbm_s* slbm_handle;
  * (zero displacement and velocity, unstressed).  SLBM_E_INVAL when a cut link
  * names a void site, an uncut link leaves the material, q is outside (0, 1],
  * a normal is not a unit vector, a group index is out of range, tau <= 1/2,
- * or mu, rho <= 0. */
+ * or mu, rho <= 0.  SLBM_E_UNSUPPORTED above 2^28 sites; SLBM_E_NOMEM or
+ * SLBM_E_DEVICE if allocation fails. */
 int slbm_create(const slbm_params* params, slbm_handle* out);
 
 /* Replaces the state by the equilibrium of given fields (section 2: P from

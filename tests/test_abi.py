@@ -150,3 +150,11 @@ def test_device_moments_reject_a_null_handle():
 def test_batch_displacement_rejects_a_null_batch():
     L = S.lib()
     assert L.slbm_batch_displacement(None, 0, None) == -1
+
+
+def test_too_large_a_grid_is_unsupported():
+    """At most 2^28 sites: one more row of 16384 is refused on the host,
+    before the mask is read (a grid of exactly 2^28 sites is run by the GPU
+    tests)."""
+    rc, msg = _create(_plate(), nx=16384, ny=16385)
+    assert rc == -5, (rc, msg)
