@@ -40,7 +40,7 @@ def workload(name):
         "square4096": (lambda: configs.square_clamped_pulled(4096, steps=2000), "fp32"),
     }
     if name not in table:
-        raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}")
+        raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}, batch64, serve or cube<N>")
     f, prec = table[name]
     return f(), prec
 
@@ -402,6 +402,12 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 10000
+    special = args.workload in ("batch64", "serve") or (
+        args.workload.startswith("cube") and args.workload[4:].isdigit() and int(args.workload[4:]) > 0)
+    if not special:
+        workload(args.workload)          # exits with the list of workloads for an unknown name
+    if args.precision not in (None, "fp32", "fp64"):
+        raise SystemExit(f"unknown precision {args.precision}; choose fp32 or fp64")
 
     import torch
     from paper_2208_04088_amd import slbm
@@ -419,7 +425,7 @@ def main():
         run_serve(args, slbm, torch, dev, stream)
         return
     if args.workload.startswith("cube"):
-        run_3d(args, torch, dev, stream, int(args.workload[4:] or 256))
+        run_3d(args, torch, dev, stream, int(args.workload[4:]))
         return
 
     plate, prec = workload(args.workload)
