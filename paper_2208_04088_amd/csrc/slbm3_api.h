@@ -10,6 +10,7 @@ struct slbm3_s {
     bool own_stream = false;
     int nx = 0, ny = 0, nz = 0;
     long long plane = 0;             // sites
+    long long stride = 0;            // elements between planes of the population and U buffers
     int precision = SLBM_FP64;
     size_t esize = 8;
     int px = 1;
@@ -41,6 +42,7 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     a.dens = (real*)h->dens;
     a.diverged = h->diverged;
     a.plane = h->plane;
+    a.stride = h->stride;
     a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
     a.px = h->px;
     a.local = h->local ? 1 : 0;
@@ -55,6 +57,16 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     a.lm = (real)(h->lamL - h->muL);
     for (int k = 0; k < 3; ++k) a.F[k] = (real)h->FL[k];
     return a;
+}
+
+// Elements from one plane of a population or displacement buffer to the
+// next: the plane rounded up to 4096 sites, then to an odd multiple of 4096,
+// so that a power-of-two box does not start all its planes on one channel.
+long long plane_stride(long long plane)
+{
+    long long q = (plane + 4095) / 4096;
+    if ((q & 1) == 0) q += 1;
+    return q * 4096;
 }
 
 int grid3(const slbm3_s* h)
@@ -135,6 +147,7 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
         h->device = p->device;
         h->nx = p->nx; h->ny = p->ny; h->nz = p->nz;
         h->plane = plane;
+        h->stride = plane_stride(plane);
         h->precision = p->precision;
         h->esize = p->precision == SLBM_FP32 ? 4 : 8;
         h->px = p->periodic_x ? 1 : 0;
@@ -166,16 +179,16 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
             TRY_OR_BAIL(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
             h->own_stream = true;
         }
-        const size_t pop = (size_t)19 * plane * h->esize;
+        const size_t pop = (size_t)19 * h->stride * h->esize;
         TRY_OR_BAIL(hipMalloc(&h->buf[0], pop));
         TRY_OR_BAIL(hipMalloc(&h->buf[1], pop));
-        TRY_OR_BAIL(hipMalloc((void**)&h->U, (size_t)3 * plane * sizeof(double)));
+        TRY_OR_BAIL(hipMalloc((void**)&h->U, (size_t)3 * h->stride * sizeof(double)));
         TRY_OR_BAIL(hipMalloc(&h->dens, (size_t)plane * h->esize));
         TRY_OR_BAIL(hipMalloc((void**)&h->diverged, sizeof(unsigned int)));
         // rest state: g = 0 (f = r), U = 0
         TRY_OR_BAIL(hipMemsetAsync(h->buf[0], 0, pop, h->stream));
         TRY_OR_BAIL(hipMemsetAsync(h->buf[1], 0, pop, h->stream));
-        TRY_OR_BAIL(hipMemsetAsync(h->U, 0, (size_t)3 * plane * sizeof(double), h->stream));
+        TRY_OR_BAIL(hipMemsetAsync(h->U, 0, (size_t)3 * h->stride * sizeof(double), h->stream));
         TRY_OR_BAIL(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
         TRY_OR_BAIL(hipStreamSynchronize(h->stream));
     #undef TRY_OR_BAIL
@@ -322,7 +335,7 @@ int slbm3_device_bytes(slbm3_handle h, int64_t* bytes)
 {
     return guarded([&]() -> int {
         if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
-        int64_t b = 2 * (int64_t)19 * h->plane * (int64_t)h->esize + 3 * h->plane * 8 + h->plane * (int64_t)h->esize;
+        int64_t b = 2 * (int64_t)19 * h->stride * (int64_t)h->esize + 3 * h->stride * 8 + h->plane * (int64_t)h->esize;
         if (h->scratch) b += (int64_t)19 * h->plane * 8;
         *bytes = b;
         return SLBM_OK;

@@ -10,7 +10,9 @@
 // sigma* = Pi sigma(x) Pi + n t* + t* n - (t*.n) n n (Pi = I - n n).
 //
 // State: shifted post-collision populations g = f - r (r the rest state),
-// SoA planes g[i][z][y][x], site offset (z ny + y) nx + x.  One step is two
+// SoA planes g[i][z][y][x], site offset (z ny + y) nx + x; consecutive planes
+// are `stride` elements apart, a little more than a plane, so that the 19
+// streams of a pull do not all start on the same HBM channel.  One step is two
 // launches: k3_density (delta-rho of the pulled state, needed by the
 // gradient stencil of every neighbour) and k3_step (pull with the wall
 // rules, moments, source term, collision, U, store).
@@ -42,6 +44,7 @@ struct Step3Args {
     real* dens;                // delta-rho of the pulled state (written by k3_density)
     unsigned int* diverged;
     long long plane;           // sites per plane
+    long long stride;          // elements from one plane of src, dst or U to the next (>= plane)
     int nx, ny, nz;
     int px;                    // periodic in x (else walls)
     int local;                 // src holds the populations at the sites themselves
@@ -299,7 +302,7 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
     const unsigned s = sidx3(st.x, st.y, st.z, nx, ny);
     if (a.local) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) g[i] = a.src[i * a.plane + s];
+        for (int i = 0; i < kQ; ++i) g[i] = a.src[i * a.stride + s];
         return;
     }
     const int ym = wrap(st.y - 1, ny), yp = wrap(st.y + 1, ny);
@@ -317,12 +320,12 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
         const int xx = kCX[i] > 0 ? xm : (kCX[i] < 0 ? xp : st.x);
         const int yy = kCY[i] > 0 ? ym : (kCY[i] < 0 ? yp : st.y);
         const int zz = kCZ[i] > 0 ? zm : (kCZ[i] < 0 ? zp : st.z);
-        g[i] = a.src[i * a.plane + sidx3(xx, yy, zz, nx, ny)];
+        g[i] = a.src[i * a.stride + sidx3(xx, yy, zz, nx, ny)];
     }
     if (!PX && (st.x == 0 || st.x == nx - 1)) {
         real h[kQ];
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) h[i] = a.src[i * a.plane + s];
+        for (int i = 0; i < kQ; ++i) h[i] = a.src[i * a.stride + s];
         real dr, j[3], P[6];
         moments3(h, dr, j, P);
         // both walls when nx == 1
@@ -466,9 +469,9 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
     const bool bad = !(fabs(dr) + fabs(j[0]) + fabs(j[1]) + fabs(j[2]) < real(1e30));
     if (st.in) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) a.dst[i * a.plane + s] = o[i];
+        for (int i = 0; i < kQ; ++i) a.dst[i * a.stride + s] = o[i];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a.U[k * a.plane + s] = a.U[k * a.plane + s] + (double)(j[k] * ir);
+        for (int k = 0; k < 3; ++k) a.U[k * a.stride + s] = a.U[k * a.stride + s] + (double)(j[k] * ir);
     }
     if (__any(bad && st.in) && (threadIdx.x & 63) == 0 && *(volatile unsigned int*)a.diverged == 0u)
         atomicOr(a.diverged, 1u);
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(256) void k3_outputs(Step3Args<real> a, double* out
     for (int k = 0; k < 3; ++k) {
         const double jk = (double)j[k] + 0.5 * ((double)a.F[k] + (double)c * (double)grad[k]);
         out[(1 + k) * n + s] = jk;
-        out[(16 + k) * n + s] = a.U[k * n + s] + 0.5 * jk / (double)rho;
+        out[(16 + k) * n + s] = a.U[k * a.stride + s] + 0.5 * jk / (double)rho;
     }
     for (int k = 0; k < 6; ++k) {
         out[(4 + k) * n + s] = (double)P[k];
@@ -537,12 +540,12 @@ __global__ __launch_bounds__(256) void k3_init(Step3Args<real> a, const double* 
     for (int k = 0; k < 6; ++k) P[k] = (real)in[(4 + k) * n + s];
     if (!st.in) return;
     real* d = a.dst;
-#define SLBM3_INIT(k) d[k * n + s] = geq3<k, real>(dr, j, P);
+#define SLBM3_INIT(k) d[k * a.stride + s] = geq3<k, real>(dr, j, P);
     SLBM3_INIT(0) SLBM3_INIT(1) SLBM3_INIT(2) SLBM3_INIT(3) SLBM3_INIT(4) SLBM3_INIT(5) SLBM3_INIT(6)
     SLBM3_INIT(7) SLBM3_INIT(8) SLBM3_INIT(9) SLBM3_INIT(10) SLBM3_INIT(11) SLBM3_INIT(12)
     SLBM3_INIT(13) SLBM3_INIT(14) SLBM3_INIT(15) SLBM3_INIT(16) SLBM3_INIT(17) SLBM3_INIT(18)
 #undef SLBM3_INIT
-    for (int k = 0; k < 3; ++k) a.U[k * n + s] = in[(10 + k) * n + s] - 0.5 * in[(1 + k) * n + s] / rho;
+    for (int k = 0; k < 3; ++k) a.U[k * a.stride + s] = in[(10 + k) * n + s] - 0.5 * in[(1 + k) * n + s] / rho;
 }
 
 }  // namespace slbm3_dev
