@@ -73,7 +73,8 @@ int grid3(const slbm3_s* h)
 {
     const long long tiles = (long long)((h->nx + 63) / 64) * h->ny * h->nz;
     const long long wg = (tiles + 3) / 4;
-    return (int)((wg + 7) / 8 * 8);
+    const long long unit = 8LL * kXcdGroup;           // xcd_group3 permutes whole units
+    return (int)((wg + unit - 1) / unit * unit);
 }
 
 // Density pass then `what` (0 step, 1 outputs into scratch, 2 init from scratch).

@@ -416,15 +416,24 @@ __device__ __forceinline__ void grad3(const Step3Args<real>& a, const Site3& st,
               real(1.0 / 12.0) * ((nb[11] - nb[12]) - (nb[13] - nb[14]) + (nb[15] - nb[16]) - (nb[17] - nb[18]));
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs; each XCD gets a contiguous
-// band of tiles (nb, the grid size, is a multiple of 8).
-__device__ __forceinline__ int xcd_band3(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+// Workgroups are dealt round-robin to the 8 XCDs.  Each XCD takes groups of
+// kXcdGroup consecutive workgroups, and the groups of the 8 XCDs interleave:
+// the chip streams through one region of the box at a time (one set of 19
+// plane streams rather than one per XCD), while rows that share neighbours
+// stay in one L2.  The grid size is a multiple of 8 kXcdGroup, which makes
+// the map a permutation of the workgroup indices.
+constexpr int kXcdGroup = 16;
+__device__ __forceinline__ int xcd_group3(int b)
+{
+    const int x = b & 7, l = b >> 3;
+    return ((l / kXcdGroup) * 8 + x) * kXcdGroup + l % kXcdGroup;
+}
 
 // delta-rho of the pulled state at every site.
 template <typename real, bool PX>
 __global__ __launch_bounds__(256) void k3_density(Step3Args<real> a)
 {
-    const int tile = xcd_band3(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
@@ -444,7 +453,7 @@ __device__ __forceinline__ double recip3(double x) { return 1.0 / x; }
 template <typename real, bool PX>
 __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 {
-    const int tile = xcd_band3(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
@@ -484,7 +493,7 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 template <typename real, bool PX>
 __global__ __launch_bounds__(256) void k3_outputs(Step3Args<real> a, double* out)
 {
-    const int tile = xcd_band3(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
@@ -525,7 +534,7 @@ __global__ __launch_bounds__(256) void k3_set_dens(Step3Args<real> a, const doub
 template <typename real, bool PX>
 __global__ __launch_bounds__(256) void k3_init(Step3Args<real> a, const double* in)
 {
-    const int tile = xcd_band3(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     const unsigned s = sidx3(st.x, st.y, st.z, a.nx, a.ny);
