@@ -50,7 +50,7 @@ def bytes_per_site(prec):
     return 9 * 2 * (4 if prec == "fp32" else 8) + 2 * 2 * 8
 
 
-def measured_traffic(plate, prec, tuned):
+def measured_traffic(plate, prec, tuned, group=0):
     """HBM bytes per launch of the step kernel from the committed counter
     summary (profiles/traffic_<workload>_<precision>.json), or None when there
     is none for this workload and launch shape or the kernel changed since."""
@@ -62,7 +62,8 @@ def measured_traffic(plate, prec, tuned):
         d = json.load(fh)
     if d.get("kernel_fingerprint") != kernel_fingerprint():
         return None
-    shape = d.get("shapes", {}).get(f"{tuned[0]}x{tuned[1]}")
+    key = f"{tuned[0]}x{tuned[1]}" + (f"-g{group}" if group else "")
+    shape = d.get("shapes", {}).get(key)
     return shape["traffic_bytes_per_launch"] if shape else None
 
 
@@ -391,6 +392,8 @@ def main():
     ap.add_argument("--seg", type=int, default=0, help="rows per tile (0: autotuned)")
     ap.add_argument("--strip", type=int, default=0,
                     help="strip width 62 or 64, or 58 for two steps per launch (0: autotuned)")
+    ap.add_argument("--xcd-group", type=int, default=0,
+                    help="with --seg: workgroups to XCDs, 0 contiguous bands, g interleaved groups of g")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=40, help="served workload: requests of the trace")
     args = ap.parse_args()
@@ -433,13 +436,15 @@ def main():
     s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
     if args.seg:
         s.set_launch(args.seg, args.strip)
+        s.set_xcd_group(args.xcd_group)
         s.step(args.warmup)
         s.sync()
         tuned = (args.seg, args.strip or 62, None)
     else:
         s.step(args.warmup)
         s.sync()
-        tuned = s.autotune()          # rows per tile and strip width, measured on this plate
+        tuned = s.autotune()          # rows per tile, strip width and XCD map, measured on this plate
+    group = s.launch()[2]
 
     torch.cuda.synchronize()
 
@@ -520,11 +525,12 @@ def main():
             "single_launch_median_us": round(launch_med_ms * 1e3, 3),
             "rows_per_tile": tuned[0],
             "strip_width": tuned[1],
+            "xcd_group": group,
         },
     }
     # streaming reference: a plain copy of a 2 GiB buffer, timed the same way
     result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
-    result["roofline"]["traffic"] = measured_traffic(plate, prec, tuned)
+    result["roofline"]["traffic"] = measured_traffic(plate, prec, tuned, group)
     if spl == 2:
         result["roofline"]["note"] = (
             "achieved counts bytes_per_site per site update (the single-step minimum); this kernel takes two "

@@ -173,12 +173,26 @@ int slbm_time(slbm_handle h, int64_t* step, double* t_user);
  * SLBM_E_INVAL beyond the limits.  Results do not depend on the shape. */
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
 
+/* How the step's workgroups are dealt to the GPU's 8 XCDs: 0 (the default)
+ * gives each XCD one contiguous band of tiles; group g in 1..64 gives each
+ * XCD groups of g consecutive workgroups, the groups of the XCDs interleaved.
+ * Bands keep the rows neighbouring tiles share in one L2; interleaved groups
+ * spread clusters of expensive boundary tiles (a hole, a crack) over all
+ * XCDs.  Results do not depend on it.  SLBM_E_INVAL outside 0..64. */
+int slbm_set_xcd_group(slbm_handle h, int32_t group);
+
+/* The launch configuration in use: rows per tile (0: the library's choice),
+ * strip (0 default, 58, 62 or 64, as in slbm_set_launch) and XCD group (as in
+ * slbm_set_xcd_group); any pointer may be NULL. */
+int slbm_get_launch(slbm_handle h, int32_t* seg_rows, int32_t* strip, int32_t* xcd_group);
+
 /* Times the fused step on this plate for each strip width (62, 64 and the
  * two-steps-per-launch 58) and a range of rows per tile (short bursts of
- * launches, the state restored after each)
- * and keeps the fastest; reports it and its time per step in microseconds
- * (any pointer may be NULL).  Synchronises.  The state and step count are
- * unchanged. */
+ * launches, the state restored after each) and keeps the fastest; then times
+ * that shape with interleaved XCD groups of 8 and keeps them if they are at
+ * least 1 % faster (else bands).  Reports the shape and its time per step in
+ * microseconds (any pointer may be NULL); slbm_get_launch gives the XCD
+ * group.  Synchronises.  The state and step count are unchanged. */
 int slbm_autotune(slbm_handle h, int32_t* seg_rows, int32_t* strip, double* us_per_step);
 
 /* Checkpoint: the full state in an opaque buffer.  With buf = NULL,

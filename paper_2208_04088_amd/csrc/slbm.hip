@@ -297,6 +297,7 @@ struct slbm_s {
     int seg = 0;
     int wide = -1;                   // strip shape: 1 wide, 0 narrow, -1 library default
     int two = 0;                     // 1: two steps per launch (58-column strips, seg rows <= 10)
+    int group = 0;                   // workgroups to XCDs: 0 contiguous bands, g > 0 interleaved groups of g
     std::vector<uint8_t> mask;
 };
 
@@ -340,6 +341,7 @@ StepArgs<real> make_args(const slbm_s* h, int src)
     a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
     a.px = h->px; a.py = h->py;
     a.local = h->local ? 1 : 0;
+    a.group = h->group;
     a.omega = (real)(1.0 / h->tau);
     a.lm = (real)(h->lamL - h->muL);
     a.ml = (real)(h->muL - h->lamL);
@@ -348,10 +350,19 @@ StepArgs<real> make_args(const slbm_s* h, int src)
     return a;
 }
 
+// Workgroups of a single-plate launch: the tiles, rounded up to a whole
+// number of XCD rounds (8 workgroups, or 8 groups with interleaved groups).
+template <typename real>
+int grid_for(const StepArgs<real>& a)
+{
+    const int unit = 8 * std::max(1, a.group);
+    return (a.ntiles + unit - 1) / unit * unit;
+}
+
 template <typename real>
 void dispatch_step(const slbm_s* h, const StepArgs<real>& a)
 {
-    const int grid = ((a.ntiles + 7) / 8) * 8;
+    const int grid = grid_for(a);
     const bool per = h->px || h->py, wide = pick_wide(h);
     const dim3 blk(64 * (wide ? tile_waves<true>(a.seg) : tile_waves<false>(a.seg)));
     if (per && wide)
@@ -398,7 +409,7 @@ StepArgs<real> make_args2(const slbm_s* h, int src, int seg)
 template <typename real>
 void dispatch_step2(const slbm_s* h, const StepArgs<real>& a)
 {
-    const int grid = ((a.ntiles + 7) / 8) * 8;
+    const int grid = grid_for(a);
     const dim3 blk(64 * (a.seg + 6));
     constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
     const bool per = h->px || h->py;
@@ -1012,6 +1023,27 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
     });
 }
 
+int slbm_set_xcd_group(slbm_handle h, int32_t group)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (group < 0 || group > 64) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or 1..64");
+        h->group = group;
+        return SLBM_OK;
+    });
+}
+
+int slbm_get_launch(slbm_handle h, int32_t* seg_rows, int32_t* strip, int32_t* xcd_group)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (seg_rows) *seg_rows = h->seg;
+        if (strip) *strip = h->two ? kStrip2 : (h->wide < 0 ? 0 : (h->wide ? 64 : 62));
+        if (xcd_group) *xcd_group = h->group;
+        return SLBM_OK;
+    });
+}
+
 int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* us_out)
 {
     return guarded([&]() -> int {
@@ -1030,57 +1062,58 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
+        // time per step of a shape (wv: 0 narrow, 1 wide, 2 two steps per
+        // launch) with the current XCD map: the best of two bursts of
+        // back-to-back launches after a warm one, as steps run; each launch
+        // rereads the same state, and U is put back after every burst
+        auto time_shape = [&](int c, int wv, double& us) -> int {
+            const int burst = wv == 2 ? 3 : 6;
+            std::vector<float> t;
+            for (int r = 0; r < 3; ++r) {
+                HIP_TRY(hipEventRecord(e0, h->stream));
+                for (int q = 0; q < burst; ++q) {
+                    const int rc2 = wv == 2
+                        ? (h->precision == SLBM_FP32 ? launch_step2_raw<float>(h, c) : launch_step2_raw<double>(h, c))
+                        : (h->precision == SLBM_FP32 ? launch_step_raw<float>(h, c, wv) : launch_step_raw<double>(h, c, wv));
+                    if (rc2) return rc2;
+                }
+                HIP_TRY(hipEventRecord(e1, h->stream));
+                HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0) t.push_back(ms / (wv == 2 ? 2 * burst : burst));
+            }
+            us = 1e3 * *std::min_element(t.begin(), t.end());
+            return SLBM_OK;
+        };
+        const int keep_group = h->group;
+        h->group = 0;
         const int cand[] = {2, 3, 4, 6, 8, 10, 12, 14};
         int best = 0, best_w = 0;
-        double best_us = 1e30;
+        double best_us = 1e30, us = 0;
         for (int wv = 0; wv < 2; ++wv)
         for (int c : cand) {
             if (c > (wv ? max_tile_rows<true>() : max_tile_rows<false>())) break;
             if (c > std::max(2, h->ny)) break;
-            // bursts of back-to-back launches, as steps run; each launch rereads
-            // the same state, U is put back after the burst
-            constexpr int kBurst = 6;
-            std::vector<float> t;
-            for (int r = 0; r < 3; ++r) {
-                HIP_TRY(hipEventRecord(e0, h->stream));
-                for (int q = 0; q < kBurst; ++q) {
-                    rc = h->precision == SLBM_FP32 ? launch_step_raw<float>(h, c, wv) : launch_step_raw<double>(h, c, wv);
-                    if (rc) return rc;
-                }
-                HIP_TRY(hipEventRecord(e1, h->stream));
-                HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (r > 0) t.push_back(ms / kBurst);
-            }
-            std::sort(t.begin(), t.end());
-            const double us = 1e3 * t[0];
+            if ((rc = time_shape(c, wv, us))) { h->group = keep_group; return rc; }
             if (us < best_us) { best_us = us; best = c; best_w = wv; }
         }
-        // two steps per launch: bursts of three launches, time per step
+        // two steps per launch
         const int cand2[] = {2, 3, 4, 5, 6, 7, 8, 9, 10};
         for (int c : cand2) {
             if (c > std::max(2, h->ny)) break;
-            constexpr int kBurst2 = 3;
-            std::vector<float> t;
-            for (int r = 0; r < 3; ++r) {
-                HIP_TRY(hipEventRecord(e0, h->stream));
-                for (int q = 0; q < kBurst2; ++q) {
-                    rc = h->precision == SLBM_FP32 ? launch_step2_raw<float>(h, c) : launch_step2_raw<double>(h, c);
-                    if (rc) return rc;
-                }
-                HIP_TRY(hipEventRecord(e1, h->stream));
-                HIP_TRY(hipMemcpyAsync(h->U, saved, ub, hipMemcpyDeviceToDevice, h->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (r > 0) t.push_back(ms / (2 * kBurst2));
-            }
-            std::sort(t.begin(), t.end());
-            const double us = 1e3 * t[0];
+            if ((rc = time_shape(c, 2, us))) { h->group = keep_group; return rc; }
             if (us < best_us) { best_us = us; best = c; best_w = 2; }
         }
+        // the best shape with interleaved XCD groups of 8, kept when at least
+        // 1 % faster (plates whose boundary tiles cluster)
+        h->group = 8;
+        if ((rc = time_shape(best, best_w, us))) { h->group = keep_group; return rc; }
+        if (us < 0.99 * best_us)
+            best_us = us;
+        else
+            h->group = 0;
         HIP_TRY(hipMemcpyAsync(h->diverged, flag_saved, sizeof(unsigned int), hipMemcpyDeviceToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
         (void)hipEventDestroy(e0);

@@ -68,6 +68,7 @@ struct StepArgs {
     int seg, nstrips, ntiles;
     int px, py;
     int local;                 // src holds the populations themselves
+    int group;                 // workgroups to XCDs: 0 contiguous bands, g > 0 interleaved groups of g
     real omega;                // 1/tau
     real lm, ml;               // lambda - mu, mu - lambda (lattice units)
     real Fx, Fy;
@@ -509,6 +510,19 @@ template <bool WIDE> constexpr int max_tile_rows() { return kMaxTileRows; }
 // share stay in one L2.  nb (the grid size) is a multiple of 8.
 __device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
+// The single-plate kernels can instead give each XCD groups of g consecutive
+// workgroups, the groups of the 8 XCDs interleaved (the grid is then a
+// multiple of 8 g).  Tiles with boundary work cluster (a hole, a crack); bands
+// hand such a cluster to one XCD, which finishes last, while interleaved
+// groups spread it.  Which is faster depends on the plate, so the autotuner
+// measures both.
+__device__ __forceinline__ int xcd_map(int b, int nb, int g)
+{
+    if (g <= 0) return xcd_banded(b, nb);
+    const int x = b & 7, l = b >> 3;
+    return ((l / g) * 8 + x) * g + l % g;
+}
+
 // Densities of the two halo columns of a wide strip in row y (left: column
 // xs - 1, right: xs + 64).  Lanes 0-8 pull the nine populations of the left
 // site, lanes 32-40 those of the right one (one load each), and the sums are
@@ -620,7 +634,7 @@ template <typename real, bool PER, bool WIDE>
 __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
 {
     __shared__ real dens[kMaxTileRows + 2][66];
-    const int tile = xcd_banded(blockIdx.x, gridDim.x);
+    const int tile = xcd_map(blockIdx.x, gridDim.x, a.group);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
     flag_divergence(a.diverged, step_tile<real, PER, WIDE>(a, tile, dens));
 }
@@ -745,7 +759,7 @@ __global__ __launch_bounds__(1024, W) void k_step2(StepArgs<real> a)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
-    const int tile = xcd_banded(blockIdx.x, gridDim.x);
+    const int tile = xcd_map(blockIdx.x, gridDim.x, a.group);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
     flag_divergence(a.diverged, step_tile2<real, PER>(a, tile, post, dens));
 }

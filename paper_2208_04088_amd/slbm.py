@@ -22,7 +22,7 @@ PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
 
 EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
-    "slbm_displacement", "slbm_displacement_device", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_autotune",
+    "slbm_displacement", "slbm_displacement_device", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
     "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_sync",
@@ -79,6 +79,8 @@ def lib():
         "slbm_moments_device": [vp, vp, vp, vp, vp, i32],
         "slbm_time": [vp, C.POINTER(i64), C.POINTER(C.c_double)],
         "slbm_set_launch": [vp, i32, i32],
+        "slbm_set_xcd_group": [vp, i32],
+        "slbm_get_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "slbm_autotune": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)],
         "slbm_save": [vp, vp, C.POINTER(C.c_size_t)],
         "slbm_load": [vp, vp, C.c_size_t],
@@ -219,6 +221,16 @@ class Solver:
 
     def set_launch(self, seg_rows, strip=0):
         _check(lib().slbm_set_launch(self.h, int(seg_rows), int(strip)))
+
+    def set_xcd_group(self, group):
+        """0: contiguous bands of tiles per XCD; g > 0: interleaved groups of g."""
+        _check(lib().slbm_set_xcd_group(self.h, int(group)))
+
+    def launch(self):
+        """(rows per tile, strip, XCD group) in use."""
+        r, st, g = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().slbm_get_launch(self.h, C.byref(r), C.byref(st), C.byref(g)))
+        return r.value, st.value, g.value
 
     def autotune(self):
         """Picks the fastest launch shape for this plate; returns

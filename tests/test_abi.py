@@ -158,3 +158,9 @@ def test_too_large_a_grid_is_unsupported():
     tests)."""
     rc, msg = _create(_plate(), nx=16384, ny=16385)
     assert rc == -5, (rc, msg)
+
+
+def test_launch_configuration_calls_reject_a_null_handle():
+    L = S.lib()
+    assert L.slbm_set_xcd_group(None, 8) == -1
+    assert L.slbm_get_launch(None, None, None, None) == -1

@@ -200,14 +200,18 @@ def test_square_config_fp32_10k_steps(slbm):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_result_does_not_depend_on_launch_shape(slbm, prec):
     """Every site's arithmetic is independent of how rows and columns are
-    split into tiles, so any launch shape gives bit-identical state; shapes
-    beyond the tile limits are refused."""
+    split into tiles and how tiles are dealt to the XCDs, so any launch shape
+    and XCD map give bit-identical state; shapes and groups beyond the limits
+    are refused."""
     p = mixed_plate(150, 97, seed=5, order=1)
     out = []
-    for seg, strip in ((1, 62), (3, 64), (8, 62), (14, 64), (14, 62), (2, 64), (0, 0), (1, 58), (6, 58),
-                       (10, 58)):
+    for seg, strip, group in ((1, 62, 0), (3, 64, 0), (8, 62, 0), (14, 64, 0), (14, 62, 0), (2, 64, 0),
+                              (0, 0, 0), (1, 58, 0), (6, 58, 0), (10, 58, 0), (3, 62, 8), (1, 58, 1),
+                              (6, 58, 8), (10, 58, 64), (2, 64, 5)):
         s = slbm.Solver(p, prec)
         s.set_launch(seg, strip)
+        s.set_xcd_group(group)
+        assert s.launch() == (seg, strip, group)
         s.step(37)
         out.append((s.displacement(), s.moments()[2]))
     for u, P in out[1:]:
@@ -217,6 +221,10 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
     for seg, strip in ((15, 62), (15, 64), (11, 58), (-1, 62), (4, 63)):
         with pytest.raises(slbm.SlbmError) as e:
             s.set_launch(seg, strip)
+        assert e.value.code == -1
+    for group in (-1, 65):
+        with pytest.raises(slbm.SlbmError) as e:
+            s.set_xcd_group(group)
         assert e.value.code == -1
 
 
@@ -519,6 +527,7 @@ def test_autotune_leaves_the_state_untouched(slbm, prec):
     a.step(25)
     seg, strip, us = a.autotune()
     assert seg >= 2 and strip in (58, 62, 64) and us > 0
+    assert a.launch() == (seg, strip, a.launch()[2]) and a.launch()[2] in (0, 8)
     assert a.time()[0] == 25
     a.step(25)
     b = slbm.Solver(p, prec)
