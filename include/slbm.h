@@ -250,6 +250,12 @@ int slbm_batch_remove(slbm_batch b, int32_t slot);
  * SLBM_E_INVAL beyond the limits. */
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
 
+/* How the batched launch deals its workgroups to the XCDs, as
+ * slbm_set_xcd_group for one plate: 0 (the default) contiguous bands, g in
+ * 1..64 interleaved groups of g.  Results do not depend on it.  SLBM_E_INVAL
+ * outside 0..64. */
+int slbm_batch_set_xcd_group(slbm_batch b, int32_t group);
+
 int slbm_batch_sync(slbm_batch b);
 int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget);
 int slbm_batch_destroy(slbm_batch b);

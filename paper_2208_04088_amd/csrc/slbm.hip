@@ -1232,6 +1232,7 @@ struct slbm_batch_s {
     int wide = 0;                    // strip shape of the batched launch
     int rows = 6;                    // rows per tile for every plate
     int two = 0;                     // 1: two steps per launch (58-column strips)
+    int group = 0;                   // workgroups to XCDs: 0 contiguous bands, g > 0 interleaved groups of g
     // device tables (rebuilt when the set of plates or the launch shape changes)
     void* d_plates = nullptr;
     int* d_tile_plate = nullptr;
@@ -1310,9 +1311,9 @@ int batch_build(slbm_batch_s* b)
 int batch_grid(const slbm_batch_s* b)
 {
     // one workgroup per tile: the batched kernels assume at least ntiles
-    // workgroups (a multiple of 8 for the XCD banding)
-    const int g = b->ntiles;
-    return (g + 7) / 8 * 8;
+    // workgroups, a whole number of XCD rounds (8 workgroups, or 8 groups)
+    const int unit = 8 * std::max(1, b->group);
+    return (b->ntiles + unit - 1) / unit * unit;
 }
 
 // Queues one batched launch of up to maxk steps (2 only in two-step mode)
@@ -1327,18 +1328,18 @@ void batch_launch(slbm_batch_s* b, bool advance, int maxk = 1)
         constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
         if (k2_waves<real>(b->rows) == hi)
             hipLaunchKernelGGL((k_step2_batch<real, hi>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, b->group);
         else
             hipLaunchKernelGGL((k_step2_batch<real, lo>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, b->group);
     } else {
         const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
         if (b->wide)
             hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, b->group);
         else
             hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, b->group);
     }
     if (advance) {
         const int n = (int)b->live.size();
@@ -1556,6 +1557,17 @@ int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
         b->rows = rows;
         b->wide = strip == 64 ? 1 : 0;
         b->two = strip == kStrip2 ? 1 : 0;
+        b->dirty = true;
+        return SLBM_OK;
+    });
+}
+
+int slbm_batch_set_xcd_group(slbm_batch b, int32_t group)
+{
+    return guarded([&]() -> int {
+        if (!b) return fail(SLBM_E_INVAL, "null batch");
+        if (group < 0 || group > 64) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or 1..64");
+        b->group = group;
         b->dirty = true;
         return SLBM_OK;
     });

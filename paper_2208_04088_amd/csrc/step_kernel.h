@@ -510,7 +510,7 @@ template <bool WIDE> constexpr int max_tile_rows() { return kMaxTileRows; }
 // share stay in one L2.  nb (the grid size) is a multiple of 8.
 __device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
-// The single-plate kernels can instead give each XCD groups of g consecutive
+// The step kernels can instead give each XCD groups of g consecutive
 // workgroups, the groups of the 8 XCDs interleaved (the grid is then a
 // multiple of 8 g).  Tiles with boundary work cluster (a hole, a crack); bands
 // hand such a cluster to one XCD, which finishes last, while interleaved
@@ -781,10 +781,10 @@ struct BatchPlate {
 template <typename real, bool WIDE>
 __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __restrict__ plates,
                                                      const int* __restrict__ tile_plate,
-                                                     const int* __restrict__ tile_start, int ntiles)
+                                                     const int* __restrict__ tile_start, int ntiles, int group)
 {
     __shared__ real dens[kMaxTileRows + 2][66];
-    const int t = xcd_banded(blockIdx.x, gridDim.x);
+    const int t = xcd_map(blockIdx.x, gridDim.x, group);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
     if (!plates[p].active) return;
@@ -797,11 +797,12 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __r
 template <typename real, int W>
 __global__ __launch_bounds__(1024, W) void k_step2_batch(const BatchPlate<real>* __restrict__ plates,
                                                       const int* __restrict__ tile_plate,
-                                                      const int* __restrict__ tile_start, int ntiles, int maxk)
+                                                      const int* __restrict__ tile_start, int ntiles, int maxk,
+                                                      int group)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
-    const int t = xcd_banded(blockIdx.x, gridDim.x);
+    const int t = xcd_map(blockIdx.x, gridDim.x, group);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
     if (!plates[p].active) return;

@@ -72,7 +72,8 @@ class Server:
     """Continuous batching under an HBM budget (bytes)."""
 
     def __init__(self, budget_bytes: int, precision: str = "fp32", chunk: int = 64, device: int = 0,
-                 stream=None, launch=None, max_resident_sites: Optional[int] = None, policy: str = "fcfs"):
+                 stream=None, launch=None, max_resident_sites: Optional[int] = None, policy: str = "fcfs",
+                 xcd_group: int = 0):
         self.batch = slbm.Batch(budget_bytes, device=device, stream=stream)
         self.precision = precision
         self.chunk = int(chunk)
@@ -84,6 +85,7 @@ class Server:
         self.peak_resident = 0
         if launch is not None:
             self.batch.set_launch(*launch)
+        self.batch.set_xcd_group(xcd_group)
 
     def close(self):
         self.batch.close()

@@ -25,7 +25,7 @@ EXPORTS = [
     "slbm_displacement", "slbm_displacement_device", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
-    "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_sync",
+    "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_set_xcd_group", "slbm_batch_sync",
     "slbm_batch_bytes", "slbm_batch_destroy",
 ]
 
@@ -96,6 +96,7 @@ def lib():
         "slbm_batch_remaining": [vp, i32, C.POINTER(i64)],
         "slbm_batch_remove": [vp, i32],
         "slbm_batch_set_launch": [vp, i32, i32],
+        "slbm_batch_set_xcd_group": [vp, i32],
         "slbm_batch_sync": [vp],
         "slbm_batch_bytes": [vp, C.POINTER(i64), C.POINTER(i64)],
         "slbm_batch_destroy": [vp],
@@ -319,6 +320,10 @@ class Batch:
 
     def set_launch(self, rows, strip):
         _check(lib().slbm_batch_set_launch(self.b, int(rows), int(strip)))
+
+    def set_xcd_group(self, group):
+        """0: contiguous bands of tiles per XCD; g > 0: interleaved groups of g."""
+        _check(lib().slbm_batch_set_xcd_group(self.b, int(group)))
 
     def sync(self):
         _check(lib().slbm_batch_sync(self.b))

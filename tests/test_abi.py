@@ -164,3 +164,4 @@ def test_launch_configuration_calls_reject_a_null_handle():
     L = S.lib()
     assert L.slbm_set_xcd_group(None, 8) == -1
     assert L.slbm_get_launch(None, None, None, None) == -1
+    assert L.slbm_batch_set_xcd_group(None, 8) == -1

@@ -68,6 +68,9 @@ class FakeBatch:
     def set_launch(self, *a):
         pass
 
+    def set_xcd_group(self, g):
+        self.xcd_group = g
+
     def close(self):
         pass
 
