@@ -174,11 +174,12 @@ int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
 
 /* How the step's workgroups are dealt to the GPU's 8 XCDs: 0 (the default)
- * gives each XCD one contiguous band of tiles; group g in 1..64 gives each
- * XCD groups of g consecutive workgroups, the groups of the XCDs interleaved.
+ * gives each XCD one contiguous band of tiles; group g, a power of two up to
+ * 64, gives each XCD groups of g consecutive workgroups, the groups of the
+ * XCDs interleaved.
  * Bands keep the rows neighbouring tiles share in one L2; interleaved groups
  * spread clusters of expensive boundary tiles (a hole, a crack) over all
- * XCDs.  Results do not depend on it.  SLBM_E_INVAL outside 0..64. */
+ * XCDs.  Results do not depend on it.  SLBM_E_INVAL for other values. */
 int slbm_set_xcd_group(slbm_handle h, int32_t group);
 
 /* The launch configuration in use: rows per tile (0: the library's choice),
@@ -251,9 +252,9 @@ int slbm_batch_remove(slbm_batch b, int32_t slot);
 int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
 
 /* How the batched launch deals its workgroups to the XCDs, as
- * slbm_set_xcd_group for one plate: 0 (the default) contiguous bands, g in
- * 1..64 interleaved groups of g.  Results do not depend on it.  SLBM_E_INVAL
- * outside 0..64. */
+ * slbm_set_xcd_group for one plate: 0 (the default) contiguous bands, g a
+ * power of two up to 64 interleaved groups of g.  Results do not depend on
+ * it.  SLBM_E_INVAL for other values. */
 int slbm_batch_set_xcd_group(slbm_batch b, int32_t group);
 
 int slbm_batch_sync(slbm_batch b);

@@ -303,6 +303,11 @@ struct slbm_s {
 
 namespace {
 
+// XCD groups: 0 (contiguous bands) or a power of two up to 64; the kernels
+// take log2 of the group, -1 for bands.
+bool valid_group(int g) { return g == 0 || (g > 0 && g <= 64 && (g & (g - 1)) == 0); }
+int group_shift(int g) { return g > 0 ? __builtin_ctz((unsigned)g) : -1; }
+
 bool pick_wide(const slbm_s* h)
 {
     return h->wide == 1;             // narrow strips unless asked: measured faster on every plate tried
@@ -341,7 +346,7 @@ StepArgs<real> make_args(const slbm_s* h, int src)
     a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
     a.px = h->px; a.py = h->py;
     a.local = h->local ? 1 : 0;
-    a.group = h->group;
+    a.group_shift = group_shift(h->group);
     a.omega = (real)(1.0 / h->tau);
     a.lm = (real)(h->lamL - h->muL);
     a.ml = (real)(h->muL - h->lamL);
@@ -355,7 +360,7 @@ StepArgs<real> make_args(const slbm_s* h, int src)
 template <typename real>
 int grid_for(const StepArgs<real>& a)
 {
-    const int unit = 8 * std::max(1, a.group);
+    const int unit = 8 << std::max(0, a.group_shift);
     return (a.ntiles + unit - 1) / unit * unit;
 }
 
@@ -1027,7 +1032,7 @@ int slbm_set_xcd_group(slbm_handle h, int32_t group)
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
-        if (group < 0 || group > 64) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or 1..64");
+        if (!valid_group(group)) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or a power of two up to 64");
         h->group = group;
         return SLBM_OK;
     });
@@ -1312,7 +1317,7 @@ int batch_grid(const slbm_batch_s* b)
 {
     // one workgroup per tile: the batched kernels assume at least ntiles
     // workgroups, a whole number of XCD rounds (8 workgroups, or 8 groups)
-    const int unit = 8 * std::max(1, b->group);
+    const int unit = 8 << std::max(0, group_shift(b->group));
     return (b->ntiles + unit - 1) / unit * unit;
 }
 
@@ -1328,18 +1333,18 @@ void batch_launch(slbm_batch_s* b, bool advance, int maxk = 1)
         constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
         if (k2_waves<real>(b->rows) == hi)
             hipLaunchKernelGGL((k_step2_batch<real, hi>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, b->group);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, group_shift(b->group));
         else
             hipLaunchKernelGGL((k_step2_batch<real, lo>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, b->group);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, group_shift(b->group));
     } else {
         const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
         if (b->wide)
             hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, b->group);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, group_shift(b->group));
         else
             hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, b->group);
+                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, group_shift(b->group));
     }
     if (advance) {
         const int n = (int)b->live.size();
@@ -1566,7 +1571,7 @@ int slbm_batch_set_xcd_group(slbm_batch b, int32_t group)
 {
     return guarded([&]() -> int {
         if (!b) return fail(SLBM_E_INVAL, "null batch");
-        if (group < 0 || group > 64) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or 1..64");
+        if (!valid_group(group)) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or a power of two up to 64");
         b->group = group;
         b->dirty = true;
         return SLBM_OK;

@@ -68,7 +68,7 @@ struct StepArgs {
     int seg, nstrips, ntiles;
     int px, py;
     int local;                 // src holds the populations themselves
-    int group;                 // workgroups to XCDs: 0 contiguous bands, g > 0 interleaved groups of g
+    int group_shift;           // workgroups to XCDs: -1 contiguous bands, s >= 0 interleaved groups of 2^s
     real omega;                // 1/tau
     real lm, ml;               // lambda - mu, mu - lambda (lattice units)
     real Fx, Fy;
@@ -510,17 +510,20 @@ template <bool WIDE> constexpr int max_tile_rows() { return kMaxTileRows; }
 // share stay in one L2.  nb (the grid size) is a multiple of 8.
 __device__ __forceinline__ int xcd_banded(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
-// The step kernels can instead give each XCD groups of g consecutive
+// The step kernels can instead give each XCD groups of 2^s consecutive
 // workgroups, the groups of the 8 XCDs interleaved (the grid is then a
-// multiple of 8 g).  Tiles with boundary work cluster (a hole, a crack); bands
-// hand such a cluster to one XCD, which finishes last, while interleaved
-// groups spread it.  Which is faster depends on the plate, so the autotuner
-// measures both.
-__device__ __forceinline__ int xcd_map(int b, int nb, int g)
+// multiple of 8 2^s).  Tiles with boundary work cluster (a hole, a crack);
+// bands hand such a cluster to one XCD, which finishes last, while
+// interleaved groups spread it.  Which is faster depends on the plate, so the
+// autotuner measures both.  Both maps are formed without a branch, so a wave
+// needs its arguments only once before its first loads.
+__device__ __forceinline__ int xcd_map(int b, int nb, int shift)
 {
-    if (g <= 0) return xcd_banded(b, nb);
     const int x = b & 7, l = b >> 3;
-    return ((l / g) * 8 + x) * g + l % g;
+    const int band = x * (nb >> 3) + l;
+    const int s = shift < 0 ? 0 : shift;
+    const int grouped = ((((l >> s) << 3) + x) << s) + (l & ((1 << s) - 1));
+    return shift < 0 ? band : grouped;
 }
 
 // Densities of the two halo columns of a wide strip in row y (left: column
@@ -634,7 +637,7 @@ template <typename real, bool PER, bool WIDE>
 __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
 {
     __shared__ real dens[kMaxTileRows + 2][66];
-    const int tile = xcd_map(blockIdx.x, gridDim.x, a.group);
+    const int tile = xcd_map(blockIdx.x, gridDim.x, a.group_shift);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
     flag_divergence(a.diverged, step_tile<real, PER, WIDE>(a, tile, dens));
 }
@@ -759,7 +762,7 @@ __global__ __launch_bounds__(1024, W) void k_step2(StepArgs<real> a)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
-    const int tile = xcd_map(blockIdx.x, gridDim.x, a.group);
+    const int tile = xcd_map(blockIdx.x, gridDim.x, a.group_shift);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
     flag_divergence(a.diverged, step_tile2<real, PER>(a, tile, post, dens));
 }
@@ -781,10 +784,10 @@ struct BatchPlate {
 template <typename real, bool WIDE>
 __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __restrict__ plates,
                                                      const int* __restrict__ tile_plate,
-                                                     const int* __restrict__ tile_start, int ntiles, int group)
+                                                     const int* __restrict__ tile_start, int ntiles, int group_shift)
 {
     __shared__ real dens[kMaxTileRows + 2][66];
-    const int t = xcd_map(blockIdx.x, gridDim.x, group);
+    const int t = xcd_map(blockIdx.x, gridDim.x, group_shift);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
     if (!plates[p].active) return;
@@ -798,11 +801,11 @@ template <typename real, int W>
 __global__ __launch_bounds__(1024, W) void k_step2_batch(const BatchPlate<real>* __restrict__ plates,
                                                       const int* __restrict__ tile_plate,
                                                       const int* __restrict__ tile_start, int ntiles, int maxk,
-                                                      int group)
+                                                      int group_shift)
 {
     __shared__ real post[kMaxTileRows2 + 4][9][64];
     __shared__ real dens[kMaxTileRows2 + 6][66];
-    const int t = xcd_map(blockIdx.x, gridDim.x, group);
+    const int t = xcd_map(blockIdx.x, gridDim.x, group_shift);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
     if (!plates[p].active) return;

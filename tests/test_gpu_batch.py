@@ -96,7 +96,7 @@ def test_batch_launch_shape_does_not_change_results(slbm):
     plates = small_plates(9, 4)
     ref = None
     for rows, strip, group in ((2, 62, 0), (8, 64, 0), (5, 62, 0), (14, 64, 0), (14, 62, 0), (1, 58, 0),
-                               (6, 58, 0), (10, 58, 0), (5, 62, 8), (6, 58, 8), (10, 58, 64), (3, 64, 3)):
+                               (6, 58, 0), (10, 58, 0), (5, 62, 8), (6, 58, 8), (10, 58, 64), (3, 64, 2)):
         b = slbm.Batch(8 << 30)
         slots = [b.add(p, 50, "fp64") for p in plates]
         b.set_launch(rows, strip)

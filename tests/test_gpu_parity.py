@@ -207,7 +207,7 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
     out = []
     for seg, strip, group in ((1, 62, 0), (3, 64, 0), (8, 62, 0), (14, 64, 0), (14, 62, 0), (2, 64, 0),
                               (0, 0, 0), (1, 58, 0), (6, 58, 0), (10, 58, 0), (3, 62, 8), (1, 58, 1),
-                              (6, 58, 8), (10, 58, 64), (2, 64, 5)):
+                              (6, 58, 8), (10, 58, 64), (2, 64, 4)):
         s = slbm.Solver(p, prec)
         s.set_launch(seg, strip)
         s.set_xcd_group(group)
@@ -222,7 +222,7 @@ def test_result_does_not_depend_on_launch_shape(slbm, prec):
         with pytest.raises(slbm.SlbmError) as e:
             s.set_launch(seg, strip)
         assert e.value.code == -1
-    for group in (-1, 65):
+    for group in (-1, 3, 65, 128):
         with pytest.raises(slbm.SlbmError) as e:
             s.set_xcd_group(group)
         assert e.value.code == -1
