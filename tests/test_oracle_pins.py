@@ -540,6 +540,18 @@ def test_rayleigh_function_factors_at_zero():
         assert abs(s0 * s0 - b ** 4 / (2 * (b * b - a * a) * cr * cr)) < 1e-9, cs2
 
 
+def test_freund_constants_are_the_papers():
+    """The K^1 evaluator's F_+(0) and the sampling point P_1 used by the crack
+    checks are the values section 5.2 prints."""
+    import inspect
+    g = json.load(open(os.path.join(HERE, "golden", "paper_numbers.json")))
+    assert inspect.signature(CF.freund_k1).parameters["f_plus0"].default == g["freund_F_plus_0"]["value"]
+    assert inspect.signature(CF.freund_k1_curve).parameters["f_plus0"].default == g["freund_F_plus_0"]["value"]
+    # P_1 two cells ahead of the upper tip: 0.52 l_c from the centre, the tip at 0.5 l_c, dx = l_c/100
+    p1 = g["crack_point_P1"]
+    assert abs((p1["y_over_lc"] - 0.5) * p1["crack_length_cells"] - 2.0) < 1e-12 and p1["x_over_lc"] == 0.0
+
+
 def _k1_integral_by_contour(T, a, b, cr, eps=2e-5, delta=1e-4):
     """The integral of eq:ki1 evaluated as printed, in complex arithmetic:
     principal square roots, the arctan continued off the real axis as
