@@ -391,6 +391,7 @@ def test_crack_config_fp32_full_length(slbm):
     compound over the run; the kernel's collision keeps them exact."""
     p = configs.edge_crack_plate()
     s = slbm.Solver(p, "fp32")
+    s.set_launch(6, 58)                   # the configuration the benchmark times
     s.step(p.steps)
     s.sync()
     u = s.displacement()
@@ -412,12 +413,15 @@ def test_crack_config_fp32_full_length(slbm):
 @pytest.mark.slow
 @pytest.mark.parametrize("lam,tau,steps", [(0.1, 0.6, 50), (0.05, 0.55, 300)])
 def test_hole_config_full_size(slbm, lam, tau, steps):
-    """2048 x 2048 plate with the curved hole at full size in the launch shape
-    the bench uses.  lambda/mu = 2 (the workload's value) grows a boundary mode
+    """2048 x 2048 plate with the curved hole at full size in the
+    configuration the benchmark's autotuner picks (two steps per launch, 10
+    rows, XCD groups of 8).  lambda/mu = 2 (the workload's value) grows a boundary mode
     that swamps the solution within ~150 steps, so it is compared over the
     first 50; lambda/mu = 1 over 300."""
     p = configs.hole_plate(lam=lam, tau=tau)
     s = slbm.Solver(p, "fp32")
+    s.set_launch(10, 58)
+    s.set_xcd_group(8)
     s.step(steps)
     s.sync()
     ref = Oracle(p)
@@ -430,11 +434,13 @@ def test_hole_config_full_size(slbm, lam, tau, steps):
 @pytest.mark.slow
 def test_square4096_full_size_in_the_bench_launch_shape(slbm):
     """The 4096 x 4096 clamped/pulled plate the benchmark times, at full size
-    in the shape the autotuner picks for it (two steps per launch, 10 rows),
-    fp32, 120 steps: displacement and moments against the reference."""
+    in the configuration the autotuner picks for it (two steps per launch,
+    10 rows, XCD groups of 8), fp32, 120 steps: displacement and moments
+    against the reference."""
     p = configs.square_clamped_pulled(4096, steps=120)
     s = slbm.Solver(p, "fp32")
     s.set_launch(10, 58)
+    s.set_xcd_group(8)
     s.step(p.steps)
     s.sync()
     ref = Oracle(p)
