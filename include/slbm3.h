@@ -97,6 +97,17 @@ int slbm3_moments(slbm3_handle h, double* rho, double* j, double* P, double* sig
  * integral of j/rho.  Synchronises. */
 int slbm3_displacement(slbm3_handle h, double* u);
 
+/* Same as slbm3_displacement into device memory u_dev ([3][n] doubles) on
+ * the handle's stream, without synchronising; u_dev belongs to the caller and
+ * must stay valid until the queued work has run. */
+int slbm3_displacement_device(slbm3_handle h, void* u_dev);
+
+/* Same as slbm3_moments into device memory on the handle's stream, without
+ * synchronising: rho [n], j [3][n], P [6][n], sigma [6][n] (any pointer may be
+ * NULL), each an array of doubles (dtype SLBM_FP64) or floats (SLBM_FP32, the
+ * double values rounded to nearest).  SLBM_E_INVAL for another dtype. */
+int slbm3_moments_device(slbm3_handle h, void* rho_dev, void* j_dev, void* P_dev, void* sigma_dev, int dtype);
+
 /* Steps taken since creation or the last slbm3_init_fields, and that time in
  * user units. */
 int slbm3_time(slbm3_handle h, int64_t* step, double* t_user);

@@ -121,6 +121,29 @@ void free3(slbm3_s* h)
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
+// count consecutive output planes, x -> (x + add) * scale (lattice to user
+// units, as copy_planes3), into caller device memory of doubles or floats
+// (the planes are contiguous in both).
+template <typename T>
+__global__ __launch_bounds__(256) void k3_scale_out(const double* src, long long n, double add, double scale, T* dst)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (T)((src[i] + add) * scale);
+}
+
+int device_planes3(slbm3_handle h, int first, int count, double add, double scale, void* dst, int dtype)
+{
+    const long long n = (long long)count * h->plane;
+    const double* src = h->scratch + (size_t)first * (size_t)h->plane;
+    const dim3 grid((unsigned)((n + 255) / 256)), blk(256);
+    if (dtype == SLBM_FP64)
+        hipLaunchKernelGGL(k3_scale_out<double>, grid, blk, 0, h->stream, src, n, add, scale, (double*)dst);
+    else
+        hipLaunchKernelGGL(k3_scale_out<float>, grid, blk, 0, h->stream, src, n, add, scale, (float*)dst);
+    HIP_TRY(hipGetLastError());
+    return SLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -319,6 +342,33 @@ int slbm3_displacement(slbm3_handle h, double* u)
         int rc = outputs3(h);
         if (rc) return rc;
         return copy_planes3(h, 16, 3, 0.0, 1.0, u);
+    });
+}
+
+int slbm3_displacement_device(slbm3_handle h, void* u_dev)
+{
+    return guarded([&]() -> int {
+        if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
+        DeviceGuard dg(h->device);
+        int rc = outputs3(h);
+        if (rc) return rc;
+        return device_planes3(h, 16, 3, 0.0, 1.0, u_dev, SLBM_FP64);
+    });
+}
+
+int slbm3_moments_device(slbm3_handle h, void* rho, void* j, void* P, void* sigma, int dtype)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (dtype != SLBM_FP64 && dtype != SLBM_FP32) return fail(SLBM_E_INVAL, "dtype must be SLBM_FP64 or SLBM_FP32");
+        DeviceGuard dg(h->device);
+        int rc = outputs3(h);
+        if (rc) return rc;
+        if (rho && (rc = device_planes3(h, 0, 1, 1.0, h->rho_user, rho, dtype))) return rc;
+        if (j && (rc = device_planes3(h, 1, 3, 0.0, h->rho_user * h->s_v, j, dtype))) return rc;
+        if (P && (rc = device_planes3(h, 4, 6, 0.0, h->s_sigma, P, dtype))) return rc;
+        if (sigma && (rc = device_planes3(h, 10, 6, 0.0, h->s_sigma, sigma, dtype))) return rc;
+        return SLBM_OK;
     });
 }
 

@@ -11,7 +11,8 @@ import numpy as np
 from . import slbm as S
 
 EXPORTS = ["slbm3_create", "slbm3_init_fields", "slbm3_step", "slbm3_sync", "slbm3_moments",
-           "slbm3_displacement", "slbm3_time", "slbm3_device_bytes", "slbm3_destroy"]
+           "slbm3_displacement", "slbm3_displacement_device", "slbm3_moments_device", "slbm3_time",
+           "slbm3_device_bytes", "slbm3_destroy"]
 
 
 class Wall(C.Structure):
@@ -46,6 +47,8 @@ def lib():
         "slbm3_sync": [vp],
         "slbm3_moments": [vp, dp, dp, dp, dp],
         "slbm3_displacement": [vp, dp],
+        "slbm3_displacement_device": [vp, vp],
+        "slbm3_moments_device": [vp, vp, vp, vp, vp, C.c_int32],
         "slbm3_time": [vp, C.POINTER(i64), C.POINTER(C.c_double)],
         "slbm3_device_bytes": [vp, C.POINTER(i64)],
         "slbm3_destroy": [vp],
@@ -129,6 +132,17 @@ class Solver3:
         u = np.empty(3 * self.n)
         S._check(lib().slbm3_displacement(self.h, S._p(u)))
         return u.reshape((3,) + self.shape)
+
+    def displacement_device(self, ptr):
+        """Writes [3][nz][ny][nx] doubles to device pointer ``ptr`` (e.g. a torch
+        tensor's data_ptr()) on the handle's stream."""
+        S._check(lib().slbm3_displacement_device(self.h, C.c_void_p(int(ptr))))
+
+    def moments_device(self, rho=0, j=0, P=0, sigma=0, dtype="fp64"):
+        """The moments of :meth:`moments` into device pointers (0 skips one), as
+        doubles ("fp64") or floats ("fp32"), on the handle's stream."""
+        ptrs = [C.c_void_p(int(p)) if p else None for p in (rho, j, P, sigma)]
+        S._check(lib().slbm3_moments_device(self.h, *ptrs, S.PRECISION[dtype]))
 
     def time(self):
         st, t = C.c_int64(), C.c_double()

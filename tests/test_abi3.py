@@ -26,7 +26,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     L = S3.lib()
     names = declared_functions()
-    assert len(names) == 9
+    assert len(names) == 11
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert sorted(S3.EXPORTS) == names
@@ -95,3 +95,9 @@ def test_valid_box_without_a_gpu_fails_loudly():
         pytest.skip("a GPU is present")
     rc, msg = _create(_slab())
     assert rc == -3, (rc, msg)
+
+
+def test_device_outputs_reject_a_null_handle():
+    L = S3.lib()
+    assert L.slbm3_displacement_device(None, None) == -1
+    assert L.slbm3_moments_device(None, None, None, None, None, 0) == -1

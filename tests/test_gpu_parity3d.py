@@ -186,3 +186,30 @@ def test_largest_box(S3):
     print(f"largest box: x-profile vs reference rel L2 {e:.3e}", flush=True)
     assert np.abs(u_ref).max() > 0
     assert e <= FP32_TOL, e
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_device_outputs_match_host_outputs(S3, prec):
+    """slbm3_displacement_device and slbm3_moments_device write what the host
+    readouts return: the same doubles, or those doubles rounded to float."""
+    import torch
+    box = B.slab3(70, 5, 4, B.Wall3(B.DIRICHLET, (1e-4, 0.0, 0.0)), B.Wall3(B.NEUMANN, (5e-5, 1e-5, 0.0)))
+    stream = torch.cuda.Stream()
+    s = S3.Solver3(box, prec, stream=stream.cuda_stream)
+    s.step(25)
+    u_ref = s.displacement()
+    ref = s.moments()
+    with torch.cuda.stream(stream):
+        u = torch.full((3, box.nz, box.ny, box.nx), 7.0, dtype=torch.float64, device="cuda")
+    s.displacement_device(u.data_ptr())
+    stream.synchronize()
+    assert np.array_equal(u.cpu().numpy(), u_ref)
+    for dt, tdt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        with torch.cuda.stream(stream):
+            t = [torch.full(r.shape, 7.0, dtype=tdt, device="cuda") for r in ref]
+        s.moments_device(*[x.data_ptr() for x in t], dtype=dt)
+        stream.synchronize()
+        for got, want in zip(t, ref):
+            w = want.astype(np.float32) if dt == "fp32" else want
+            assert np.array_equal(got.cpu().numpy(), w)
+    s.close()
