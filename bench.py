@@ -67,6 +67,23 @@ def measured_traffic(plate, prec, tuned, group=0):
     return shape["traffic_bytes_per_launch"] if shape else None
 
 
+def measured_traffic_batch(shape, group):
+    """HBM bytes per launch of the batched step kernel on the 64 plates of
+    seed 0, from profiles/traffic_batch64-seed0_fp32.json, or None when there
+    is none for this launch shape or the kernel changed since."""
+    from paper_2208_04088_amd.build import kernel_fingerprint
+    path = os.path.join(ROOT, "profiles", "traffic_batch64-seed0_fp32.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_fingerprint") != kernel_fingerprint():
+        return None
+    key = f"{shape[0]}x{shape[1]}" + (f"-g{group}" if group else "")
+    entry = d.get("shapes", {}).get(key)
+    return entry["traffic_bytes_per_launch"] if entry else None
+
+
 def cpu_baseline(plate, budget_s=15.0, one_core_s=8.0):
     """The plain CPU reference (fp64) on a bounded number of steps of the
     same plate, timed with every host thread it is allowed and with one."""
@@ -228,6 +245,9 @@ def run_batch(args, slbm, torch, dev, stream):
     sites = sum(p.n_material for p in plates)
     tune_shapes = [(4, 62), (6, 62), (10, 62), (14, 62), (4, 58), (6, 58), (8, 58), (10, 58)]
     chunk = 64
+    if args.seg:
+        # a fixed configuration (profiling runs); the warm-up keeps its form
+        tune_shapes = [(args.seg, args.strip or 62)]
     warm = chunk * (len(tune_shapes) + 3)
 
     def ev():
@@ -251,14 +271,17 @@ def run_batch(args, slbm, torch, dev, stream):
             best = (t, sh)
     b.set_launch(*best[1])
     # the best shape with interleaved XCD groups of 8, kept when 1 % faster
-    b.set_xcd_group(8)
+    b.set_xcd_group(args.xcd_group if args.seg else 8)
     b.step(chunk // 2)
     e0, e1 = ev(), ev()
     e0.record(stream)
     b.step(chunk // 2)
     e1.record(stream)
     torch.cuda.synchronize()
-    group = 8 if e0.elapsed_time(e1) / (chunk // 2) < 0.99 * best[0] else 0
+    if args.seg:
+        group = args.xcd_group
+    else:
+        group = 8 if e0.elapsed_time(e1) / (chunk // 2) < 0.99 * best[0] else 0
     b.set_xcd_group(group)
     b.step(chunk)
     torch.cuda.synchronize()
@@ -324,7 +347,7 @@ def run_batch(args, slbm, torch, dev, stream):
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic_batch(best[1], group),
             "kernel": "k_step2_batch" if best[1][1] == 58 else "k_step_batch",
             "bytes_per_site": bytes_per_site("fp32"),
             "steps_per_launch": 2 if best[1][1] == 58 else 1,
