@@ -196,24 +196,32 @@ def test_dirichlet_walls_carry_a_uniform_translation():
     assert np.abs(u - (v0 * 9 * o.dt_user)[:, None, None, None]).max() < 1e-13
 
 
-def test_step_traction_launches_the_one_dimensional_wave():
-    """A step tension sigma_xx = s0 on the face x = -1/2 of a long slab sends a
-    plane pressure wave in at c_d; behind its front the material moves with
-    v = -s0/(rho c_d) (momentum balance across the front), until the
-    reflection from the free far face returns."""
+@pytest.mark.parametrize("mode", ["tension", "shear"])
+def test_step_traction_launches_the_one_dimensional_wave(mode):
+    """A step tension sigma_xx = s0 (or shear sigma_xy = s0) on the face
+    x = -1/2 of a long slab sends a plane pressure (shear) wave in at c_d
+    (c_s); behind its front the material moves with v = -s0/(rho c) along x
+    (y), by momentum balance across the front, until the reflection from the
+    free far face returns.  The shear case pins the tangential part of the
+    Neumann rule's boundary stress."""
     nx, s0 = 240, 1e-4
     mu, lam = 0.05, 0.05
-    b = B.slab3(nx, 1, 1, B.Wall3(B.NEUMANN, (-s0, 0.0, 0.0)), B.Wall3(B.NEUMANN), lam=lam, mu=mu, tau=0.55)
+    k = 0 if mode == "tension" else 1
+    t = [0.0, 0.0, 0.0]
+    t[k] = -s0
+    b = B.slab3(nx, 1, 1, B.Wall3(B.NEUMANN, tuple(t)), B.Wall3(B.NEUMANN), lam=lam, mu=mu, tau=0.55)
     o = Oracle3D(b)
-    cd_lat = np.sqrt(lam / mu / 3 + 2 / 3)
-    steps = int(0.75 * nx / cd_lat)
+    c_lat = np.sqrt(lam / mu / 3 + 2 / 3) if mode == "tension" else np.sqrt(1 / 3)
+    steps = int(0.75 * nx / c_lat)
     o.step(steps)
     rho, j, P, sig = o.moments()
-    v = j[0, 0, 0] / rho[0, 0, 0]
-    cd_user = np.sqrt((lam + 2 * mu) / b.rho)
+    v = j[k, 0, 0] / rho[0, 0, 0]
+    c_user = np.sqrt((lam + 2 * mu) / b.rho) if mode == "tension" else np.sqrt(mu / b.rho)
     behind = v[20:int(0.5 * nx)]
-    assert np.mean(behind) == pytest.approx(-s0 / (b.rho * cd_user), rel=0.02)
-    assert np.abs(v[int(0.9 * nx):]).max() < 1e-3 * s0 / (b.rho * cd_user)
+    assert np.mean(behind) == pytest.approx(-s0 / (b.rho * c_user), rel=0.02)
+    assert np.abs(v[int(0.9 * nx):]).max() < 1e-3 * s0 / (b.rho * c_user)
+    other = j[1 - k, 0, 0] / rho[0, 0, 0]
+    assert np.abs(other).max() < 1e-6 * s0 / (b.rho * c_user)
 
 
 def test_brute_force_loops_on_a_tiny_box():
