@@ -470,15 +470,27 @@ def main():
     plate, prec = workload(args.workload)
     prec = args.precision or prec
     s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
+
+    def diverged_sync():
+        # a plate that overflowed (SLBM_E_DIVERGED) keeps stepping at the same
+        # cost; the line reports the flag
+        try:
+            s.sync()
+            return False
+        except slbm.SlbmError as e:
+            if e.code != -4:
+                raise
+            return True
+
     if args.seg:
         s.set_launch(args.seg, args.strip)
         s.set_xcd_group(args.xcd_group)
         s.step(args.warmup)
-        s.sync()
+        diverged_warm = diverged_sync()
         tuned = (args.seg, args.strip or 62, None)
     else:
         s.step(args.warmup)
-        s.sync()
+        diverged_warm = diverged_sync()
         tuned = s.autotune()          # rows per tile, strip width and XCD map, measured on this plate
     group = s.launch()[2]
 
@@ -492,13 +504,7 @@ def main():
     ev0.record(stream)
     s.step(args.steps)
     ev1.record(stream)
-    diverged = False
-    try:
-        s.sync()
-    except slbm.SlbmError as e:
-        if e.code != -4:
-            raise
-        diverged = True
+    diverged = diverged_sync() or diverged_warm
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     region_ms = ev0.elapsed_time(ev1)
