@@ -3,18 +3,24 @@
 A bench step is one lattice-Boltzmann time step of the whole plate: pull
 streaming with the boundary rules, moments, density-gradient source term,
 equilibrium, collision, displacement update and the non-finite guard, all in
-the fused kernel.  The default workload is the 1024 x 512 edge-crack plate
-(fp32 populations, fp64 displacement), run for its 10k steps.
+the fused kernel.  The default workload is the 2048 x 2048 plate with a
+centred hole of radius 256 (curved traction-free wall, lambda/mu = 2,
+tau_bar = 0.6, fp32 populations, fp64 displacement).  Its line also carries
+the fp64-plain step on the same plate, a 4096^2 plate and the served trace
+(p50/p99 latency) as sub-records.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-extras]
     python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
     python bench.py --workload serve       # served requests: continuous batching vs one at a time
     python bench.py --workload cube256     # the three-dimensional (D3Q19) step on a 256^3 slab
 
 Prints one JSON line.  `value` is material-site updates per second (MLUPS)
-with the state resident in HBM; the roofline object relates the fused
-kernel's algorithmic bytes to the 8 TB/s HBM peak; cpu_baseline times the
-plain CPU reference on a bounded sample of the same plate.
+with the state already in device memory when the timed region starts; the
+roofline object relates the fused kernel's algorithmic bytes to the 8 TB/s
+HBM peak (bound "mall" when the working set fits the 256 MB Infinity Cache,
+which then serves most of it), and reports the measured DRAM-side traffic and
+rate beside it; cpu_baseline times the plain CPU reference on a bounded
+sample of the same plate.
 """
 import argparse
 import json
@@ -32,8 +38,9 @@ def workload(name):
     from slbm_workloads import configs
     table = {
         "crack1024x512": (lambda: configs.edge_crack_plate(), "fp32"),
-        # the specified lambda/mu = 2 grows a boundary mode and overflows within
-        # ~1000 steps; the same geometry at lambda = mu does the same work
+        # as specified (lambda/mu = 2, tau_bar = 0.6): its traction-free walls
+        # grow a surface mode and the state overflows after ~150 steps; the
+        # same geometry at lambda = mu does the same work for longer
         "hole2048": (lambda: configs.hole_plate(), "fp32"),
         "hole2048-lm1": (lambda: configs.hole_plate(lam=0.05, tau=0.55), "fp32"),
         "square128": (lambda: configs.square_clamped_pulled(), "fp64"),
@@ -360,20 +367,19 @@ def run_batch(args, slbm, torch, dev, stream):
     print(json.dumps(result), flush=True)
 
 
-def run_serve(args, slbm, torch, dev, stream):
+def serve_record(args, slbm, torch, stream, both_orders=False):
     """The first `--requests` requests of the served trace (seed 1, Poisson
     arrivals at `--rate` per second, 50 by default, plates 256^2-4096^2,
     1e3-2e4 steps; the rate only stretches the arrival times) under a 200 GB
     budget: continuous batching (paper_2208_04088_amd.serve.Server) against
-    the same requests one plate at a time (oldest first, and least work
-    first).  Latency runs from a request's
-    arrival to its displacement being back on the host."""
+    the same requests one plate at a time (least work first; with
+    both_orders also oldest first).  Latency runs from a request's arrival to
+    its displacement being back on the host."""
     from paper_2208_04088_amd import serve
     from slbm_workloads import configs
     t = time.perf_counter()
     trace = configs.served_trace(seed=1, count=args.requests, rate=args.rate)
     t_build = time.perf_counter() - t
-    work = sum(r.plate.n_material * r.steps for r in trace)
     launch = (6, 58)                     # two steps per launch, 6 rows per tile
     srv = serve.Server(200 << 30, chunk=64, stream=stream.cuda_stream, launch=launch,
                        max_resident_sites=2_000_000, policy="swf", xcd_group=args.xcd_group)
@@ -381,33 +387,43 @@ def run_serve(args, slbm, torch, dev, stream):
     srv.close()
     torch.cuda.synchronize()
     st = serve.summary(res)
-    seq = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False))
     seq_swf = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False,
                                                     policy="swf"))
-    span = st["makespan_s"]
-    achieved = work * bytes_per_site("fp32") / span / 1e9
+    out = {
+        "workload": f"served-trace-seed1-first{args.requests}" + ("" if args.rate == 50 else f"-rate{args.rate:g}"),
+        "requests": args.requests, "arrival_rate_per_s": args.rate, "hbm_budget_gb": 200,
+        "precision": "fp32 populations and arithmetic, fp64 displacement",
+        "policy": "least work first, at most 2M material sites resident (more when one plate is larger)",
+        "launch_shape": list(launch), "xcd_group": args.xcd_group,
+        "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+        "aggregate_mlups": st["aggregate_mlups"],
+        "served": st, "one_at_a_time_least_work_first": seq_swf,
+        "speedup_vs_one_at_a_time": round(seq_swf["makespan_s"] / st["makespan_s"], 3),
+        "peak_resident_plates": srv.peak_resident, "peak_device_gb": round(srv.peak_bytes / 1e9, 2),
+        "trace_build_s": round(t_build, 1),
+    }
+    if both_orders:
+        seq = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False))
+        out["one_at_a_time"] = seq
+        out["speedup_vs_one_at_a_time_oldest_first"] = round(seq["makespan_s"] / st["makespan_s"], 3)
+    return out, trace
+
+
+def run_serve(args, slbm, torch, dev, stream):
+    """The served trace as its own line (see serve_record)."""
+    rec, trace = serve_record(args, slbm, torch, stream, both_orders=True)
+    st = rec["served"]
     result = {
         "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
         "value": st["aggregate_mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": int(sum(r.steps for r in trace)),
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {
-            "workload": f"served-trace-seed1-first{args.requests}" + ("" if args.rate == 50 else f"-rate{args.rate:g}"),
-            "requests": args.requests, "arrival_rate_per_s": args.rate, "hbm_budget_gb": 200,
-            "precision": "fp32 populations and arithmetic, fp64 displacement",
-            "bench_step": "serve every request of the trace (each plate its own step count)",
-            "policy": "least work first, at most 2M material sites resident (more when one plate is larger)",
-            "xcd_group": args.xcd_group,
-            "served": st, "one_at_a_time": seq, "one_at_a_time_least_work_first": seq_swf,
-            "speedup_vs_one_at_a_time": round(seq["makespan_s"] / span, 3),
-            "peak_resident_plates": srv.peak_resident, "peak_device_gb": round(srv.peak_bytes / 1e9, 2),
-            "trace_build_s": round(t_build, 1),
-        },
+        "config": dict(rec, bench_step="serve every request of the trace (each plate its own step count)"),
         "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_step2_batch" if launch[1] == 58 else "k_step_batch",
-            "steps_per_launch": 2 if launch[1] == 58 else 1,
+            "bound": "hbm", "achieved": round(st["aggregate_mlups"] * bytes_per_site("fp32") / 1e3, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(st["aggregate_mlups"] * bytes_per_site("fp32") / 1e3 / HBM_PEAK_GBS, 4),
+            "traffic": None, "kernel": "k_step2_batch", "steps_per_launch": 2,
             "bytes_per_site": bytes_per_site("fp32"),
         },
     }
@@ -416,12 +432,140 @@ def run_serve(args, slbm, torch, dev, stream):
     print(json.dumps(result), flush=True)
 
 
+MALL_BYTES = 256 << 20          # the Infinity Cache (MALL) in front of HBM
+
+
+def working_set_bytes(plate, prec):
+    """Device bytes one step touches: both population buffers, U and the
+    per-site flags, in the library's padded layout (64 columns of left
+    padding, rows rounded to 64, one row of padding above and below)."""
+    ld = (64 + plate.nx + 1 + 63) // 64 * 64
+    plane = ld * (plate.ny + 2)
+    es = 4 if prec == "fp32" else 8
+    return plane * (2 * 9 * es + 2 * 8 + 1)
+
+
+def time_plate(args, slbm, torch, stream, plate, prec, steps, warmup, shape=None):
+    """One plate: warm-up steps, the launch shape (autotuned on this plate, or
+    `shape` = (rows, strip, xcd group)), then `steps` steps timed with events
+    on the library's stream.  Returns the line's fields without cpu_baseline."""
+    s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
+
+    def diverged_sync():
+        # a plate that overflowed (SLBM_E_DIVERGED) keeps stepping at the same
+        # cost; the line reports the flag
+        try:
+            s.sync()
+            return False
+        except slbm.SlbmError as e:
+            if e.code != -4:
+                raise
+            return True
+
+    if shape is not None:
+        s.set_launch(shape[0], shape[1])
+        s.set_xcd_group(shape[2])
+        s.step(warmup)
+        diverged_warm = diverged_sync()
+    else:
+        s.step(warmup)
+        diverged_warm = diverged_sync()
+        s.autotune()                  # rows per tile, strip width and XCD map, measured on this plate
+    rows, strip, group = s.launch()
+    strip = strip or 62
+    torch.cuda.synchronize()
+
+    # timed region: K steps queued back to back on one stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(steps)
+    ev1.record(stream)
+    diverged = diverged_sync() or diverged_warm
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    region_ms = ev0.elapsed_time(ev1)
+
+    # per-launch kernel time: events around single launches (a launch takes
+    # two steps with strip width 58)
+    spl = 2 if strip == 58 else 1
+    n_probe = min(200, max(20, steps // 50))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_probe)]
+    for a, b in evs:
+        a.record(stream)
+        s.step(spl)
+        b.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    launch_med_ms = launch_ms[len(launch_ms) // 2]
+    if not diverged:
+        s.sync()
+        import numpy as np
+        assert np.isfinite(s.displacement()).all()
+    s.close()
+
+    sites = plate.n_material
+    t_step = region_ms / 1e3 / steps
+    bps = bytes_per_site(prec)
+    achieved = sites * bps / t_step / 1e9
+    avg_launch_us = t_step * spl * 1e6
+    ws = working_set_bytes(plate, prec)
+    traffic = measured_traffic(plate, prec, (rows, strip), group)
+    roof = {
+        # a working set inside the Infinity Cache is served from it, not from HBM
+        "bound": "hbm" if ws > MALL_BYTES else "mall",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "achieved_dram_gbs": None if traffic is None else round(traffic / avg_launch_us / 1e3, 1),
+        "kernel": "k_step2" if spl == 2 else "k_step",
+        "bytes_per_site": bps,
+        "steps_per_launch": spl,
+        "avg_launch_us": round(avg_launch_us, 3),
+        "single_launch_median_us": round(launch_med_ms * 1e3, 3),
+        "rows_per_tile": rows,
+        "strip_width": strip,
+        "xcd_group": group,
+        "working_set_bytes": ws,
+    }
+    if spl == 2:
+        roof["note"] = (
+            "achieved counts bytes_per_site per site update (the one-step minimum); this kernel takes two "
+            "steps per launch and reads and writes the state once per launch, so it needs half that from HBM; "
+            "traffic is the measured bytes per launch and achieved_dram_gbs the rate it moves them at")
+    return {
+        "value": round(sites / t_step / 1e6, 1),
+        "ms_per_step": round(t_step * 1e3, 6),
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "config": {
+            "workload": plate.name, "nx": plate.nx, "ny": plate.ny, "material_sites": sites,
+            "precision": "fp32 populations and arithmetic, fp64 displacement" if prec == "fp32" else "fp64",
+            "lambda_over_mu": plate.lam / plate.mu, "tau": plate.tau, "neumann_order": plate.neumann_order,
+            "bench_step": "one lattice-Boltzmann time step of the whole plate",
+            "wall_s": round(wall, 4),
+            "diverged": diverged,
+        },
+        "roofline": roof,
+    }
+
+
+def sub_record(r, steps, warmup):
+    """A timed plate as a sub-record of the line."""
+    out = {"metric": "MLUPS", "value": r["value"], "unit": "MLUPS", "steps": steps, "warmup": warmup,
+           "ms_per_step": r["ms_per_step"], "dtype": r["dtype"]}
+    out.update({"config": r["config"], "roofline": r["roofline"]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", default="crack1024x512")
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="hole2048")
     ap.add_argument("--rate", type=float, default=50.0, help="arrival rate of the served trace (requests/s)")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--seg", type=int, default=0, help="rows per tile (0: autotuned)")
@@ -431,7 +575,9 @@ def main():
                     help="with --seg, and for the served workload: workgroups to XCDs, 0 contiguous bands, "
                          "g interleaved groups of g")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--requests", type=int, default=40, help="served workload: requests of the trace")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the hole plate alone, without the fp64, 4096^2 and served sub-records")
+    ap.add_argument("--requests", type=int, default=256, help="served workload: requests of the trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -439,8 +585,12 @@ def main():
         sys.exit(2)
 
     args.steps_given = args.steps is not None
+    default_line = args.workload == "hole2048" and not args.no_extras and args.precision in (None, "fp32") \
+        and not args.seg
     if args.steps is None:
-        args.steps = 10000
+        args.steps = 20 if args.workload == "hole2048" else 10000
+    if args.warmup is None:
+        args.warmup = 5 if args.workload == "hole2048" else 500
     special = args.workload in ("batch64", "serve") or (
         args.workload.startswith("cube") and args.workload[4:].isdigit() and int(args.workload[4:]) > 0)
     if not special:
@@ -469,115 +619,37 @@ def main():
 
     plate, prec = workload(args.workload)
     prec = args.precision or prec
-    s = slbm.Solver(plate, prec, device=0, stream=stream.cuda_stream)
-
-    def diverged_sync():
-        # a plate that overflowed (SLBM_E_DIVERGED) keeps stepping at the same
-        # cost; the line reports the flag
-        try:
-            s.sync()
-            return False
-        except slbm.SlbmError as e:
-            if e.code != -4:
-                raise
-            return True
-
-    if args.seg:
-        s.set_launch(args.seg, args.strip)
-        s.set_xcd_group(args.xcd_group)
-        s.step(args.warmup)
-        diverged_warm = diverged_sync()
-        tuned = (args.seg, args.strip or 62, None)
-    else:
-        s.step(args.warmup)
-        diverged_warm = diverged_sync()
-        tuned = s.autotune()          # rows per tile, strip width and XCD map, measured on this plate
-    group = s.launch()[2]
-
-    torch.cuda.synchronize()
-
-    # timed region: K steps queued back to back on one stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(args.steps)
-    ev1.record(stream)
-    diverged = diverged_sync() or diverged_warm
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    region_ms = ev0.elapsed_time(ev1)
-
-    # per-launch kernel time: events around single launches (a launch takes
-    # two steps with strip width 58)
-    spl = 2 if tuned[1] == 58 else 1
-    n_probe = min(200, max(20, args.steps // 50))
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_probe)]
-    for a, b in evs:
-        a.record(stream)
-        s.step(spl)
-        b.record(stream)
-    torch.cuda.synchronize()
-    launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
-    launch_med_ms = launch_ms[len(launch_ms) // 2]
-    if not diverged:
-        s.sync()
-        import numpy as np
-        assert np.isfinite(s.displacement()).all()
-
-    sites = plate.n_material
-    t_step = region_ms / 1e3 / args.steps
-    mlups = sites / t_step / 1e6
-    bps = bytes_per_site(prec)
-    traffic_note = None
-    achieved = sites * bps / t_step / 1e9
+    shape = (args.seg, args.strip or 62, args.xcd_group) if args.seg else None
+    r = time_plate(args, slbm, torch, stream, plate, prec, args.steps, args.warmup, shape)
     result = {
         "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
-        "value": round(mlups, 1),
+        "value": r["value"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_step * 1e3, 6),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64",
+        "dtype": r["dtype"],
         "data": "synthetic",
-        "config": {
-            "workload": plate.name, "nx": plate.nx, "ny": plate.ny, "material_sites": sites,
-            "precision": "fp32 populations and arithmetic, fp64 displacement" if prec == "fp32" else "fp64",
-            "lambda_over_mu": plate.lam / plate.mu, "tau": plate.tau, "neumann_order": plate.neumann_order,
-            "bench_step": "one lattice-Boltzmann time step of the whole plate",
-            "wall_s": round(wall, 4),
-            "diverged": diverged,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_note,
-            "kernel": "k_step2" if spl == 2 else "k_step",
-            "bytes_per_site": bps,
-            "steps_per_launch": spl,
-            "avg_launch_us": round(t_step * spl * 1e6, 3),
-            "single_launch_median_us": round(launch_med_ms * 1e3, 3),
-            "rows_per_tile": tuned[0],
-            "strip_width": tuned[1],
-            "xcd_group": group,
-        },
+        "config": r["config"],
+        "roofline": r["roofline"],
     }
     # streaming reference: a plain copy of a 2 GiB buffer, timed the same way
     result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
-    result["roofline"]["traffic"] = measured_traffic(plate, prec, tuned, group)
-    if spl == 2:
-        result["roofline"]["note"] = (
-            "achieved counts bytes_per_site per site update (the single-step minimum); this kernel takes two "
-            "steps per launch and reads and writes the state once, so it moves about half that from HBM "
-            "(traffic: measured bytes per launch)")
+    if default_line:
+        # the metric's other halves on the same line: the fp64-plain step on
+        # the same plate, a 4096^2 plate (1.5 GB, far above the cache) and
+        # the served trace with its latency percentiles
+        r64 = time_plate(args, slbm, torch, stream, plate, "fp64", args.steps, args.warmup)
+        result["fp64"] = sub_record(r64, args.steps, args.warmup)
+        big, _ = workload("square4096")
+        steps_big = max(args.steps, 20)
+        rbig = time_plate(args, slbm, torch, stream, big, "fp32", steps_big, args.warmup)
+        result["square4096"] = sub_record(rbig, steps_big, args.warmup)
+        result["served"], _ = serve_record(args, slbm, torch, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(plate)
     print(json.dumps(result), flush=True)
