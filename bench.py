@@ -241,124 +241,117 @@ def run_3d(args, torch, dev, stream, n):
 
 def run_batch(args, slbm, torch, dev, stream):
     """64 independent plates of uneven size and geometry (seed 0), every one
-    advanced `steps` steps: once as one batch (one launch per step for all
-    plates, steps replayed from captured graphs), once one plate at a time
+    advanced `steps` steps: once as one batch (one launch per step, or two,
+    for all plates, steps replayed from captured graphs, the launch shape
+    picked by slbm_batch_autotune during warm-up), once one plate at a time
     with plain launches in each plate's autotuned shape.  Same plates, same
-    arithmetic: the displacements must agree bit for bit."""
+    arithmetic: the displacements of the plates that stay finite must agree
+    bit for bit.  A plate whose state overflows (lambda/mu > 1 grows a mode
+    at traction-free walls) is retired by the batch and stopped, at the next
+    check, one at a time; throughput counts the plates that completed."""
     import numpy as np
     from slbm_workloads import configs
     steps = args.steps if args.steps_given else 5000
     plates = configs.batch_plates(seed=0, count=64, steps=steps)
-    sites = sum(p.n_material for p in plates)
-    tune_shapes = [(4, 62), (6, 62), (10, 62), (14, 62), (4, 58), (6, 58), (8, 58), (10, 58)]
-    chunk = 64
-    if args.seg:
-        # a fixed configuration (profiling runs); the warm-up keeps its form
-        tune_shapes = [(args.seg, args.strip or 62)]
-    warm = chunk * (len(tune_shapes) + 3)
+    warm = 512
+    check = 1024                          # one-at-a-time divergence check interval (steps)
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    # batched: warm-up steps pick the launch shape, then the timed steps
+    # batched: warm-up steps pick the launch shape (or the one given), then the timed steps
     b = slbm.Batch(200 << 30, device=0, stream=stream.cuda_stream)
     slots = [b.add(p, warm + steps, "fp32") for p in plates]
-    b.step(chunk)
-    best = None
-    for sh in tune_shapes:
-        b.set_launch(*sh)
-        b.step(chunk // 2)                       # tables and graph rebuilt
-        e0, e1 = ev(), ev()
-        e0.record(stream)
-        b.step(chunk // 2)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) / (chunk // 2)
-        if best is None or t < best[0]:
-            best = (t, sh)
-    b.set_launch(*best[1])
-    # the best shape with interleaved XCD groups of 8, kept when 1 % faster
-    b.set_xcd_group(args.xcd_group if args.seg else 8)
-    b.step(chunk // 2)
-    e0, e1 = ev(), ev()
-    e0.record(stream)
-    b.step(chunk // 2)
-    e1.record(stream)
-    torch.cuda.synchronize()
     if args.seg:
-        group = args.xcd_group
+        b.set_launch(args.seg, args.strip or 62)
+        b.set_xcd_group(args.xcd_group)
+        b.step(warm)
     else:
-        group = 8 if e0.elapsed_time(e1) / (chunk // 2) < 0.99 * best[0] else 0
-    b.set_xcd_group(group)
-    b.step(chunk)
-    torch.cuda.synchronize()
+        b.autotune(warm)
+        taken = max(b.solver(sl).time()[0] for sl in slots)   # plates still running took every trial step
+        b.step(warm - taken)
+    shape = b.launch()
+    b.sync()
     e0, e1 = ev(), ev()
     w0 = time.perf_counter()
     e0.record(stream)
     b.step(steps)
     e1.record(stream)
+    b.sync()
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - w0
     t_batch = e0.elapsed_time(e1) / 1e3
-    u_batch, div_batch = [], 0
+    u_batch, ok_batch = [], []
     for sl in slots:
         sv = b.solver(sl)
         try:
             sv.sync()
+            ok_batch.append(True)
         except slbm.SlbmError as e:
             if e.code != -4:
                 raise
-            div_batch += 1
+            ok_batch.append(False)
         u_batch.append(sv.displacement())
     b.close()
 
     # one plate at a time: the same warm-up and step counts, plain launches
-    t_seq, div_seq, equal = 0.0, 0, 0
-    for p, ub in zip(plates, u_batch):
+    t_seq, ok_seq, equal = 0.0, [], 0
+    for p, ub, okb in zip(plates, u_batch, ok_batch):
         s = slbm.Solver(p, "fp32", device=0, stream=stream.cuda_stream)
         s.step(warm)
         torch.cuda.synchronize()
         s.autotune()
         e0, e1 = ev(), ev()
         e0.record(stream)
-        s.step(steps)
+        done, ok = 0, True
+        while done < steps:
+            k = min(check, steps - done)
+            s.step(k)
+            done += k
+            try:
+                s.sync()
+            except slbm.SlbmError as e:
+                if e.code != -4:
+                    raise
+                ok = False
+                break
         e1.record(stream)
         torch.cuda.synchronize()
         t_seq += e0.elapsed_time(e1) / 1e3
-        try:
-            s.sync()
-        except slbm.SlbmError as e:
-            if e.code != -4:
-                raise
-            div_seq += 1
-        equal += bool(np.array_equal(s.displacement(), ub, equal_nan=True))
+        ok_seq.append(ok)
+        if ok and okb:
+            equal += bool(np.array_equal(s.displacement(), ub))
         s.close()
-    mlups = sites * steps / t_batch / 1e6
-    achieved = sites * bytes_per_site("fp32") * steps / t_batch / 1e9
+    done_sites = sum(p.n_material for p, ok in zip(plates, ok_batch) if ok)
+    mlups = done_sites * steps / t_batch / 1e6
+    achieved = done_sites * bytes_per_site("fp32") * steps / t_batch / 1e9
     result = {
         "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": round(t_batch / steps * 1e3, 6), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {
-            "workload": "batch64-seed0", "plates": len(plates), "material_sites": sites,
+            "workload": "batch64-seed0", "plates": len(plates),
+            "material_sites": sum(p.n_material for p in plates), "completed_material_sites": done_sites,
             "precision": "fp32 populations and arithmetic, fp64 displacement",
-            "bench_step": "one lattice-Boltzmann time step of all 64 plates (one batched launch)",
-            "batched_launch_shape": list(best[1]),
-            "batched_xcd_group": group,
-            "sequential_mlups": round(sites * steps / t_seq / 1e6, 1),
+            "bench_step": "one lattice-Boltzmann time step of all 64 plates (one batched launch per one or "
+                          "two steps); throughput counts the plates that stay finite",
+            "batched_launch_shape": list(shape),
+            "sequential_mlups": round(done_sites * steps / t_seq / 1e6, 1),
             "speedup_vs_sequential": round(t_seq / t_batch, 3),
-            "plates_bitwise_equal_to_sequential": equal,
-            "diverged_plates": [div_batch, div_seq],
+            "plates_completed": [sum(ok_batch), sum(ok_seq)],
+            "plates_diverged": [len(plates) - sum(ok_batch), len(plates) - sum(ok_seq)],
+            "completed_plates_bitwise_equal_to_sequential": equal,
             "wall_s": round(wall_b, 4),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic_batch(best[1], group),
-            "kernel": "k_step2_batch" if best[1][1] == 58 else "k_step_batch",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic_batch(shape[:2], shape[2]),
+            "kernel": "k_step2_batch" if shape[1] == 58 else "k_step_batch",
             "bytes_per_site": bytes_per_site("fp32"),
-            "steps_per_launch": 2 if best[1][1] == 58 else 1,
-            "avg_launch_us": round(t_batch / steps * 1e6 * (2 if best[1][1] == 58 else 1), 3),
+            "steps_per_launch": 2 if shape[1] == 58 else 1,
+            "avg_launch_us": round(t_batch / steps * 1e6 * (2 if shape[1] == 58 else 1), 3),
             "copy_kernel_gbs": copy_ceiling(slbm, torch, dev, stream),
         },
     }
@@ -371,10 +364,13 @@ def serve_record(args, slbm, torch, stream, both_orders=False):
     """The first `--requests` requests of the served trace (seed 1, Poisson
     arrivals at `--rate` per second, 50 by default, plates 256^2-4096^2,
     1e3-2e4 steps; the rate only stretches the arrival times) under a 200 GB
-    budget: continuous batching (paper_2208_04088_amd.serve.Server) against
-    the same requests one plate at a time (least work first; with
-    both_orders also oldest first).  Latency runs from a request's arrival to
-    its displacement being back on the host."""
+    budget: continuous batching (paper_2208_04088_amd.serve.Server, rounds
+    of about 20 ms of device work, two rounds in flight) against the same
+    requests one plate at a time (least work first; with both_orders also
+    oldest first).  Latency runs from a request's arrival to its
+    displacement being back on the host; percentiles and throughput are over
+    the requests that completed, and requests whose state overflowed
+    (lambda/mu > 1) are counted apart."""
     from paper_2208_04088_amd import serve
     from slbm_workloads import configs
     t = time.perf_counter()
@@ -382,7 +378,8 @@ def serve_record(args, slbm, torch, stream, both_orders=False):
     t_build = time.perf_counter() - t
     launch = (6, 58)                     # two steps per launch, 6 rows per tile
     srv = serve.Server(200 << 30, chunk=64, stream=stream.cuda_stream, launch=launch,
-                       max_resident_sites=2_000_000, policy="swf", xcd_group=args.xcd_group)
+                       max_resident_sites=2_000_000, policy="swf", xcd_group=args.xcd_group, round_ms=20.0,
+                       timing_stream=stream)
     res = srv.run(trace)
     srv.close()
     torch.cuda.synchronize()
@@ -395,8 +392,11 @@ def serve_record(args, slbm, torch, stream, both_orders=False):
         "precision": "fp32 populations and arithmetic, fp64 displacement",
         "policy": "least work first, at most 2M material sites resident (more when one plate is larger)",
         "launch_shape": list(launch), "xcd_group": args.xcd_group,
-        "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
-        "aggregate_mlups": st["aggregate_mlups"],
+        "p50_latency_s": st.get("p50_latency_s"), "p99_latency_s": st.get("p99_latency_s"),
+        "aggregate_mlups": st.get("aggregate_mlups"),
+        "completed": st["requests"], "diverged": st["diverged"],
+        "gpu_busy_fraction": (round(srv.gpu_busy_s / srv.gpu_span_s, 4) if srv.gpu_span_s else None),
+        "rounds": srv.rounds,
         "served": st, "one_at_a_time_least_work_first": seq_swf,
         "speedup_vs_one_at_a_time": round(seq_swf["makespan_s"] / st["makespan_s"], 3),
         "peak_resident_plates": srv.peak_resident, "peak_device_gb": round(srv.peak_bytes / 1e9, 2),
@@ -413,6 +413,7 @@ def run_serve(args, slbm, torch, dev, stream):
     """The served trace as its own line (see serve_record)."""
     rec, trace = serve_record(args, slbm, torch, stream, both_orders=True)
     st = rec["served"]
+    st.setdefault("aggregate_mlups", 0.0)
     result = {
         "metric": "MLUPS (material-site updates per second) of the fused D2Q9 solid-LBM step",
         "value": st["aggregate_mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": int(sum(r.steps for r in trace)),

@@ -208,41 +208,73 @@ int slbm_destroy(slbm_handle h);
 
 /* ---------------------------------------------------------------- batches
  *
- * Many plates of uneven size and geometry advanced together: every step of
- * every active plate is one kernel launch, steps are queued as replays of a
- * captured HIP graph, and each plate keeps its own step count.  Plates join
- * and leave between calls (continuous batching).  Every plate of a batch has
- * the batch's precision and no periodic axis.  A plate's results are those
- * it would have alone (the arithmetic of each site does not depend on the
- * batch).  Not thread-safe.
+ * Many plates of uneven size and geometry, each the problem of sections 2-4
+ * with its own geometry, material and loads, advanced together: one kernel
+ * launch takes a step (or two, with strip 58) of every plate still running,
+ * launches are queued as replays of a captured HIP graph, and each plate
+ * keeps its own step count.  Plates join and leave between calls
+ * (continuous batching).  Every plate of a batch has the batch's precision
+ * and no periodic axis.  A plate's results are those it would have alone
+ * (the arithmetic of each site does not depend on the batch).
+ *
+ * Device memory: the batch reserves its whole budget at creation and carves
+ * every plate, and one readout scratch the plates share (sized for the
+ * displacement readout of the largest plate; the full moments readout grows
+ * it on demand), out of it, so slbm_batch_add fails rather than exceed the
+ * budget, and no call while steps run allocates or frees device memory (a
+ * removed plate's memory is reused once the work queued before its removal
+ * has run).  Tables of a few bytes per tile and per plate sit outside the
+ * budget.
+ *
+ * Streams: steps go to the batch's stream; plate creation and readouts of
+ * batch plates to a second stream of the batch's, a readout after the
+ * plate's last queued step, so admitting and reading out plates overlaps the
+ * steps of the others.
+ *
+ * Divergence: from the launch after a plate's state turns non-finite, the
+ * kernels skip its arithmetic (its steps are still counted); it is retired
+ * (its remaining steps set to zero, so slbm_batch_poll lists it) at a later
+ * batch call, once the copy of the divergence words queued with each step
+ * call has arrived; slbm_sync on its handle reports SLBM_E_DIVERGED.  Not
+ * thread-safe.
  */
 typedef struct slbm_batch_s* slbm_batch;
 
-/* hbm_budget_bytes bounds the device memory of the batch's plates; stream
- * as in slbm_params (NULL: the batch's own). */
+/* hbm_budget_bytes of device memory, reserved now, hold the batch's plates;
+ * stream as in slbm_params (NULL: the batch's own).  SLBM_E_NOMEM when the
+ * budget cannot be reserved. */
 int slbm_batch_create(int64_t hbm_budget_bytes, int32_t device, void* stream, slbm_batch* out);
 
-/* Creates the plate (as slbm_create, on the batch's device and stream) with
- * nsteps steps to take, and returns its slot.  SLBM_E_BUDGET when it would
- * exceed the budget (nothing is allocated then). */
+/* Creates the plate (as slbm_create, on the batch's device, in its budget)
+ * with nsteps steps to take, and returns its slot.  SLBM_E_BUDGET when the
+ * plate, or the readout scratch its displacement needs, does not fit the
+ * budget (nothing stays allocated then). */
 int slbm_batch_add(slbm_batch b, const slbm_params* params, int64_t nsteps, int32_t* slot);
 
-/* Queues k steps: every plate advances by min(k, its remaining steps). */
+/* Queues k steps: every plate advances by min(k, its remaining steps)
+ * (eq:LBE, sections 3-4).  Does not wait for the device. */
 int slbm_batch_step(slbm_batch b, int64_t k);
 
-/* Slots whose steps are all taken (up to capacity written; *n_done = all). */
+/* Slots whose steps are all queued, or that were retired as diverged (up to
+ * capacity written; *n_done = all).  Does not wait for the device. */
 int slbm_batch_poll(slbm_batch b, int32_t* done_slots, int32_t capacity, int32_t* n_done);
 
-/* The plate's handle, owned by the batch, for slbm_displacement,
- * slbm_moments, slbm_sync and slbm_time; valid until the plate is removed. */
+/* The plate's handle, owned by the batch, for the readouts slbm_displacement,
+ * slbm_displacement_device, slbm_moments, slbm_moments_device, slbm_sync,
+ * slbm_save and slbm_time (queued behind the plate's steps); valid until the
+ * plate is removed.  Calls that step or change the plate (slbm_step,
+ * slbm_init_fields, slbm_load, slbm_autotune, slbm_set_launch,
+ * slbm_set_xcd_group, slbm_destroy) return SLBM_E_INVAL on it. */
 int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h);
 int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps);
 
 /* The plate's displacement [2][n] in cells, into a host array (slbm_displacement
- * of the slot's handle).  SLBM_E_INVAL for an empty slot.  Synchronises. */
+ * of the slot's handle).  SLBM_E_INVAL for an empty slot.  Waits for the
+ * plate's queued steps and its readout only. */
 int slbm_batch_displacement(slbm_batch b, int32_t slot, double* u);
 
-/* Frees the plate (its slot and budget are reused). */
+/* Removes the plate; its slot is reused at once and its memory once the work
+ * queued before the call has run.  Does not wait for the device. */
 int slbm_batch_remove(slbm_batch b, int32_t slot);
 
 /* Launch shape of the batched step, for every plate: rows per tile (1..14,
@@ -257,8 +289,35 @@ int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip);
  * it.  SLBM_E_INVAL for other values. */
 int slbm_batch_set_xcd_group(slbm_batch b, int32_t group);
 
+/* The batched launch shape in use (any pointer may be NULL). */
+int slbm_batch_get_launch(slbm_batch b, int32_t* rows, int32_t* strip, int32_t* xcd_group);
+
+/* Picks the batched launch shape on the plates resident now: times a set of
+ * shapes (two steps per launch at 4, 6, 8 and 10 rows, one step at 6, 10 and
+ * 14 rows), then the best with XCD groups of 8 (kept when 1 % faster), each
+ * over 32 steps after 32 that rebuild its tables and graph, while budget
+ * steps last.  The trial steps are real: every plate advances by them (at
+ * most its remaining steps), exactly as it would in any shape.  Keeps and
+ * reports the fastest shape and its time per step of the whole batch in
+ * microseconds (any pointer may be NULL).  Synchronises. */
+int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows, int32_t* strip, int32_t* xcd_group,
+                        double* us_per_step);
+
+/* Waits for everything queued on the batch's streams. */
 int slbm_batch_sync(slbm_batch b);
+
+/* Waits until at most in_flight of the batch's slbm_batch_step calls are
+ * still queued or running (0: all have run), and retires the plates found
+ * diverged meanwhile.  A loop that queues the next call before it waits
+ * keeps the device busy while bounding how far the host runs ahead.
+ * SLBM_E_INVAL for in_flight < 0. */
+int slbm_batch_wait(slbm_batch b, int32_t in_flight);
+
+/* Device memory in use in the budget (plates and readout scratch, including
+ * blocks of removed plates not yet reusable) and the budget. */
 int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget);
+
+/* Waits for the batch's work, then frees every plate and the budget. */
 int slbm_batch_destroy(slbm_batch b);
 
 /* Plain device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned

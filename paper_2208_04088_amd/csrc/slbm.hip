@@ -46,6 +46,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -269,6 +271,154 @@ __global__ __launch_bounds__(256) void k_copy16(const float4* __restrict__ src, 
 
 // ======================================================= host side (C ABI)
 
+namespace {
+
+// Device memory of a batch: one allocation of the batch's budget, handed out
+// first-fit in 256-byte aligned blocks.  A block released while queued work
+// may still touch it becomes reusable once events recorded after that work
+// have completed, so that nothing the serving loop calls while the GPU runs
+// has to wait for the device (hipFree would).  Allocation fails, rather than
+// exceed the budget, when no free block is large enough.
+struct Arena {
+    static constexpr size_t kAlign = 256;
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;                   // offset -> length, coalesced
+    std::map<size_t, size_t> used;                    // offset -> length
+    size_t deferred_bytes = 0;
+    struct Deferred {
+        std::vector<hipEvent_t> events;               // all must complete
+        std::vector<size_t> offs;
+        std::vector<hipEvent_t> destroy;              // per-plate events retired with the blocks
+    };
+    std::deque<Deferred> deferred;
+
+    hipError_t init(size_t n)
+    {
+        size = (n + kAlign - 1) / kAlign * kAlign;
+        const hipError_t e = hipMalloc((void**)&base, size);
+        if (e == hipSuccess) free_[0] = size;
+        return e;
+    }
+    size_t live() const
+    {
+        size_t s = deferred_bytes;
+        for (const auto& u : used) s += u.second;
+        return s;
+    }
+    void give_back(size_t off)
+    {
+        auto it = used.find(off);
+        if (it == used.end()) return;
+        size_t o = off, len = it->second;
+        used.erase(it);
+        auto nx = free_.lower_bound(o);
+        if (nx != free_.end() && nx->first == o + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == o) {
+                pv->second += len;
+                return;
+            }
+        }
+        free_[o] = len;
+    }
+    bool done(const Deferred& d) const
+    {
+        for (hipEvent_t e : d.events)
+            if (hipEventQuery(e) != hipSuccess) return false;
+        return true;
+    }
+    void retire(Deferred& d)
+    {
+        for (hipEvent_t e : d.events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : d.destroy) (void)hipEventDestroy(e);
+        for (size_t o : d.offs) {
+            deferred_bytes -= used_len(o);
+            give_back(o);
+        }
+    }
+    size_t used_len(size_t o) const
+    {
+        auto it = used.find(o);
+        return it == used.end() ? 0 : it->second;
+    }
+    // Returns blocks whose events have completed to the free list; with wait,
+    // waits for the oldest outstanding release first.
+    void reclaim(bool wait)
+    {
+        if (wait && !deferred.empty())
+            for (hipEvent_t e : deferred.front().events) (void)hipEventSynchronize(e);
+        while (!deferred.empty() && done(deferred.front())) {
+            retire(deferred.front());
+            deferred.pop_front();
+        }
+    }
+    void* try_alloc(size_t n)
+    {
+        n = (n + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t o = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[o + n] = len - n;
+            used[o] = n;
+            return base + o;
+        }
+        return nullptr;
+    }
+    // nullptr when no block fits even after every outstanding release has completed
+    void* alloc(size_t n)
+    {
+        if (n == 0) n = 1;
+        reclaim(false);
+        for (;;) {
+            if (void* p = try_alloc(n)) return p;
+            if (deferred.empty()) return nullptr;
+            reclaim(true);
+        }
+    }
+    void release(void* p)
+    {
+        if (p) give_back((size_t)((char*)p - base));
+    }
+    // Releases blocks once every event of evs (recorded after the last work
+    // that may touch them) has completed; the events are the arena's now.
+    void release_after(std::vector<hipEvent_t> evs, const std::vector<void*>& ptrs,
+                       std::vector<hipEvent_t> destroy = {})
+    {
+        Deferred d;
+        d.events = std::move(evs);
+        d.destroy = std::move(destroy);
+        for (void* p : ptrs) {
+            if (!p) continue;
+            const size_t o = (size_t)((char*)p - base);
+            d.offs.push_back(o);
+            deferred_bytes += used_len(o);
+        }
+        deferred.push_back(std::move(d));
+    }
+    void destroy_all()
+    {
+        for (Deferred& d : deferred) {
+            for (hipEvent_t e : d.events) (void)hipEventSynchronize(e);
+            retire(d);
+        }
+        deferred.clear();
+        if (base) (void)hipFree(base);
+        base = nullptr;
+        used.clear();
+        free_.clear();
+    }
+};
+
+}  // namespace
+
+struct slbm_batch_s;
+
 struct slbm_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -290,7 +440,15 @@ struct slbm_s {
     unsigned int* diverged = nullptr;
     double* scratch = nullptr;       // outputs and initial fields, allocated on demand
     int scratch_planes = 0;
-    bool transient_scratch = false;  // free it after every readout (batch plates)
+    // a plate owned by a batch: device memory from the batch's arena, the
+    // divergence word and the readout scratch the batch's, readouts queued on
+    // the batch's side stream after the event recorded behind the plate's
+    // last batched launch; stepping and state changes go through the batch
+    slbm_batch_s* batch = nullptr;
+    Arena* arena = nullptr;
+    bool ext_flag = false;
+    hipEvent_t ready = nullptr;
+    uint64_t batch_id = 0;
     int n_links = 0;
     int64_t step = 0;
     bool local = true;
@@ -466,8 +624,13 @@ int launch_step(slbm_s* h)
     return SLBM_OK;
 }
 
+// A batch plate's readouts use the batch's shared scratch (defined with the
+// batch code below).
+int batch_scratch(slbm_s* h, int planes);
+
 int ensure_scratch(slbm_s* h, int planes)
 {
+    if (h->batch) return batch_scratch(h, planes);
     if (h->scratch && h->scratch_planes >= planes) return SLBM_OK;
     if (h->scratch) (void)hipFree(h->scratch);
     h->scratch = nullptr;
@@ -477,14 +640,21 @@ int ensure_scratch(slbm_s* h, int planes)
     return SLBM_OK;
 }
 
-// Plates owned by a batch give their readout scratch back after each use.
+// A batch plate forgets the batch's scratch after each readout (the batch
+// may move it to a larger block later).
 void release_transient_scratch(slbm_s* h)
 {
-    if (!h->transient_scratch || !h->scratch) return;
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(h->scratch);
+    if (!h->batch) return;
     h->scratch = nullptr;
     h->scratch_planes = 0;
+}
+
+// Readouts of a batch plate are queued on its side stream behind the plate's
+// last batched launch (queued on the batch's compute stream).
+int wait_ready(slbm_s* h)
+{
+    if (h->ready) HIP_TRY(hipStreamWaitEvent(h->stream, h->ready, 0));
+    return SLBM_OK;
 }
 
 // outputs in lattice units into scratch[1..11]; scratch[0] holds delta-rho
@@ -530,16 +700,39 @@ struct DeviceGuard {
     }
 };
 
+// Device memory of a plate: from the batch's arena for batch plates, else
+// hipMalloc.  An exhausted arena reports out-of-memory.
+hipError_t dev_alloc(slbm_s* h, void** p, size_t n)
+{
+    if (!h->arena) return hipMalloc(p, n);
+    *p = h->arena->alloc(n);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+// The plate's own device blocks (not the batch's divergence word or scratch).
+std::vector<void*> plate_blocks(slbm_s* h)
+{
+    std::vector<void*> v = {h->buf[0], h->buf[1], h->U, h->flags, h->bidx, h->links, h->groups};
+    if (!h->ext_flag) v.push_back(h->diverged);
+    if (!h->batch) v.push_back(h->scratch);
+    return v;
+}
+
+// Frees at once: nothing queued may still use the plate.
 void free_all(slbm_s* h)
 {
-    for (void*& p : h->buf) { if (p) (void)hipFree(p); p = nullptr; }
-    if (h->U) (void)hipFree(h->U);
-    if (h->flags) (void)hipFree(h->flags);
-    if (h->bidx) (void)hipFree(h->bidx);
-    if (h->links) (void)hipFree(h->links);
-    if (h->groups) (void)hipFree(h->groups);
-    if (h->diverged) (void)hipFree(h->diverged);
-    if (h->scratch) (void)hipFree(h->scratch);
+    for (void* p : plate_blocks(h)) {
+        if (!p) continue;
+        if (h->arena)
+            h->arena->release(p);
+        else
+            (void)hipFree(p);
+    }
+    h->buf[0] = h->buf[1] = nullptr;
+    h->U = nullptr;
+    h->scratch = nullptr;
+    if (h->ready) (void)hipEventDestroy(h->ready);
+    h->ready = nullptr;
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
@@ -614,13 +807,19 @@ int upload_links(slbm_s* h, const std::vector<slbm_link>& L, const std::vector<u
     }
     (void)n;
     if (!d.empty()) {
-        HIP_TRY(hipMalloc(&h->links, d.size() * sizeof(LinkDev<real>)));
-        HIP_TRY(hipMemcpy(h->links, d.data(), d.size() * sizeof(LinkDev<real>), hipMemcpyHostToDevice));
+        const hipError_t e = dev_alloc(h, &h->links, d.size() * sizeof(LinkDev<real>));
+        if (e == hipErrorOutOfMemory) return fail(SLBM_E_NOMEM, "no device memory for the link records");
+        HIP_TRY(e);
+        HIP_TRY(hipMemcpyAsync(h->links, d.data(), d.size() * sizeof(LinkDev<real>), hipMemcpyHostToDevice,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
     }
     return SLBM_OK;
 }
 
-int create_impl(const slbm_params* p, slbm_handle* out)
+// A plate from its parameters.  With an arena (batch plates) its device
+// memory comes from there and ext_flag, if given, is its divergence word.
+int create_impl(const slbm_params* p, slbm_handle* out, Arena* arena = nullptr, unsigned int* ext_flag = nullptr)
 {
     if (!p || !out) return fail(SLBM_E_INVAL, "null argument");
     *out = nullptr;
@@ -708,6 +907,7 @@ int create_impl(const slbm_params* p, slbm_handle* out)
     h->esize = p->precision == SLBM_FP32 ? 4 : 8;
     h->n_links = p->n_links;
     h->mask = mat;
+    h->arena = arena;
 
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
@@ -736,12 +936,17 @@ int create_impl(const slbm_params* p, slbm_handle* out)
         h->own_stream = true;
     }
     const size_t pop_bytes = (size_t)9 * h->plane * h->esize;
-    TRY_OR_BAIL(hipMalloc(&h->buf[0], pop_bytes));
-    TRY_OR_BAIL(hipMalloc(&h->buf[1], pop_bytes));
-    TRY_OR_BAIL(hipMalloc((void**)&h->U, (size_t)2 * h->plane * sizeof(double)));
-    TRY_OR_BAIL(hipMalloc((void**)&h->flags, (size_t)h->plane));
-    TRY_OR_BAIL(hipMalloc((void**)&h->bidx, (size_t)h->plane * sizeof(int32_t)));
-    TRY_OR_BAIL(hipMalloc((void**)&h->diverged, sizeof(unsigned int)));
+    TRY_OR_BAIL(dev_alloc(h, &h->buf[0], pop_bytes));
+    TRY_OR_BAIL(dev_alloc(h, &h->buf[1], pop_bytes));
+    TRY_OR_BAIL(dev_alloc(h, (void**)&h->U, (size_t)2 * h->plane * sizeof(double)));
+    TRY_OR_BAIL(dev_alloc(h, (void**)&h->flags, (size_t)h->plane));
+    TRY_OR_BAIL(dev_alloc(h, (void**)&h->bidx, (size_t)h->plane * sizeof(int32_t)));
+    if (ext_flag) {
+        h->diverged = ext_flag;
+        h->ext_flag = true;
+    } else {
+        TRY_OR_BAIL(dev_alloc(h, (void**)&h->diverged, sizeof(unsigned int)));
+    }
     {
         std::vector<uint8_t> fl((size_t)h->plane, (uint8_t)kVoid);
         std::vector<int32_t> bi((size_t)h->plane, -1);
@@ -755,8 +960,12 @@ int create_impl(const slbm_params* p, slbm_handle* out)
             const size_t d = (size_t)sidx(s % nx, s / nx, h->ld);
             if (bi[d] < 0) bi[d] = (int32_t)i;
         }
-        TRY_OR_BAIL(hipMemcpy(h->flags, fl.data(), fl.size(), hipMemcpyHostToDevice));
-        TRY_OR_BAIL(hipMemcpy(h->bidx, bi.data(), bi.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        // queued on the plate's stream (for batch plates the batch's side
+        // stream, so that the upload does not wait for running steps)
+        TRY_OR_BAIL(hipMemcpyAsync(h->flags, fl.data(), fl.size(), hipMemcpyHostToDevice, h->stream));
+        TRY_OR_BAIL(hipMemcpyAsync(h->bidx, bi.data(), bi.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   h->stream));
+        TRY_OR_BAIL(hipStreamSynchronize(h->stream));
     }
     {
         std::vector<GroupDev> gd(std::max(1, p->n_groups));
@@ -764,8 +973,10 @@ int create_impl(const slbm_params* p, slbm_handle* out)
             gd[g].profile = p->groups[g].profile;
             gd[g].ramp_steps = p->groups[g].profile == SLBM_PROFILE_RAMP ? p->groups[g].ramp_time / h->dt_user : 1.0;
         }
-        TRY_OR_BAIL(hipMalloc((void**)&h->groups, gd.size() * sizeof(GroupDev)));
-        TRY_OR_BAIL(hipMemcpy(h->groups, gd.data(), gd.size() * sizeof(GroupDev), hipMemcpyHostToDevice));
+        TRY_OR_BAIL(dev_alloc(h, (void**)&h->groups, gd.size() * sizeof(GroupDev)));
+        TRY_OR_BAIL(hipMemcpyAsync(h->groups, gd.data(), gd.size() * sizeof(GroupDev), hipMemcpyHostToDevice,
+                                   h->stream));
+        TRY_OR_BAIL(hipStreamSynchronize(h->stream));
     }
     {
         int rc = h->precision == SLBM_FP32 ? upload_links<float>(h, L, cut, p) : upload_links<double>(h, L, cut, p);
@@ -820,6 +1031,7 @@ int slbm_destroy(slbm_handle h)
 {
     return guarded([&]() -> int {
         if (!h) return SLBM_OK;
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch: remove it with slbm_batch_remove");
         DeviceGuard dg(h->device);
         if (h->stream) (void)hipStreamSynchronize(h->stream);
         free_all(h);
@@ -832,6 +1044,7 @@ int slbm_step(slbm_handle h, int64_t nsteps)
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
         DeviceGuard dg(h->device);
         int64_t i = 0;
@@ -854,6 +1067,7 @@ int slbm_sync(slbm_handle h)
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
         DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
         unsigned int flag = 0;
         HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -867,6 +1081,7 @@ int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
         DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
         int rc = outputs(h, true);
         if (rc) return rc;
         const size_t n = (size_t)h->nx * h->ny;
@@ -889,6 +1104,7 @@ int slbm_displacement(slbm_handle h, double* u)
     return guarded([&]() -> int {
         if (!h || !u) return fail(SLBM_E_INVAL, "null argument");
         DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
         int rc = outputs(h, false);
         if (rc) return rc;
         const size_t n = (size_t)h->nx * h->ny;
@@ -903,6 +1119,7 @@ int slbm_displacement_device(slbm_handle h, void* u_dev)
     return guarded([&]() -> int {
         if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
         DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
         int rc = outputs(h, false);
         if (rc) return rc;
         const int n = h->nx * h->ny;
@@ -920,6 +1137,7 @@ int slbm_moments_device(slbm_handle h, void* rho, void* j, void* P, void* sigma,
         if (!h) return fail(SLBM_E_INVAL, "null handle");
         if (dtype != SLBM_FP64 && dtype != SLBM_FP32) return fail(SLBM_E_INVAL, "dtype must be SLBM_FP64 or SLBM_FP32");
         DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
         int rc = outputs(h, true);
         if (rc) return rc;
         const int n = h->nx * h->ny;
@@ -949,6 +1167,7 @@ int slbm_init_fields(slbm_handle h, const double* rho, const double* vel, const 
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         DeviceGuard dg(h->device);
         int rc = ensure_scratch(h, 8);
         if (rc) return rc;
@@ -1016,6 +1235,7 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         if (seg_rows < 0) return fail(SLBM_E_INVAL, "seg_rows must be >= 0");
         if (strip != 0 && strip != 62 && strip != 64 && strip != kStrip2)
             return fail(SLBM_E_INVAL, "strip must be 0, 58, 62 or 64");
@@ -1032,6 +1252,7 @@ int slbm_set_xcd_group(slbm_handle h, int32_t group)
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         if (!valid_group(group)) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or a power of two up to 64");
         h->group = group;
         return SLBM_OK;
@@ -1053,6 +1274,7 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
 {
     return guarded([&]() -> int {
         if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         DeviceGuard dg(h->device);
         int rc = ensure_scratch(h, 3);
         if (rc) return rc;
@@ -1165,6 +1387,7 @@ int slbm_save(slbm_handle h, void* buf, size_t* bytes)
         if (!buf) { *bytes = need; return SLBM_OK; }
         if (*bytes < need) return fail(SLBM_E_INVAL, "buffer too small: %zu < %zu", *bytes, need);
         DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
         SaveHeader hd{kMagic, h->nx, h->ny, h->ld, h->precision, h->step, h->local ? 1 : 0, 0};
         unsigned int flag = 0;
         char* p = (char*)buf;
@@ -1183,6 +1406,7 @@ int slbm_load(slbm_handle h, const void* buf, size_t bytes)
 {
     return guarded([&]() -> int {
         if (!h || !buf) return fail(SLBM_E_INVAL, "null argument");
+        if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         const size_t pop = (size_t)9 * h->plane * h->esize, ub = (size_t)2 * h->plane * sizeof(double);
         SaveHeader hd;
         if (bytes < sizeof hd + pop + ub) return fail(SLBM_E_INVAL, "checkpoint too short");
@@ -1225,393 +1449,9 @@ int slbm_copy(void* dst, const void* src, size_t bytes, int32_t device, void* st
 
 }  // extern "C"
 
-struct slbm_batch_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int64_t budget = 0, used = 0;
-    int precision = -1;
-    std::vector<slbm_s*> slot;       // nullptr: free
-    std::vector<int64_t> remaining;  // host mirror of the device countdown
-    std::vector<int64_t> bytes;
-    int wide = 0;                    // strip shape of the batched launch
-    int rows = 6;                    // rows per tile for every plate
-    int two = 0;                     // 1: two steps per launch (58-column strips)
-    int group = 0;                   // workgroups to XCDs: 0 contiguous bands, g > 0 interleaved groups of g
-    // device tables (rebuilt when the set of plates or the launch shape changes)
-    void* d_plates = nullptr;
-    int* d_tile_plate = nullptr;
-    int* d_tile_start = nullptr;
-    std::vector<int> live;           // slot of each device plate entry
-    int ntiles = 0;
-    bool dirty = true;
-    hipGraphExec_t graph = nullptr;  // kChunk steps, replayed
-    bool graph_ok = false;
-};
-
-namespace {
-
-constexpr int kChunk = 32;           // steps per captured graph
-
-int64_t estimate_bytes(const slbm_params* p)
-{
-    const int64_t ld = (kPadL + p->nx + 1 + 63) / 64 * 64;
-    const int64_t plane = ld * (p->ny + 2);
-    const int64_t es = p->precision == SLBM_FP32 ? 4 : 8;
-    const int64_t link = p->precision == SLBM_FP32 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>);
-    return 2 * 9 * plane * es + 2 * plane * 8 + plane * 5 + (int64_t)p->n_links * link + 64;
-}
-
-void batch_free_tables(slbm_batch_s* b)
-{
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-    b->graph_ok = false;
-    if (b->d_plates) (void)hipFree(b->d_plates);
-    if (b->d_tile_plate) (void)hipFree(b->d_tile_plate);
-    if (b->d_tile_start) (void)hipFree(b->d_tile_start);
-    b->d_plates = nullptr;
-    b->d_tile_plate = b->d_tile_start = nullptr;
-    b->ntiles = 0;
-}
-
-template <typename real>
-int batch_build(slbm_batch_s* b)
-{
-    batch_free_tables(b);
-    b->live.clear();
-    std::vector<BatchPlate<real>> bp;
-    std::vector<int> tile_plate, tile_start;
-    for (size_t k = 0; k < b->slot.size(); ++k) {
-        slbm_s* h = b->slot[k];
-        if (!h) continue;
-        const int keep_seg = h->seg, keep_w = h->wide;
-        h->seg = b->rows;
-        h->wide = b->wide;
-        BatchPlate<real> e{};
-        e.args = b->two ? make_args2<real>(h, h->cur, b->rows) : make_args<real>(h, h->cur);
-        h->seg = keep_seg;
-        h->wide = keep_w;
-        e.remaining = b->remaining[k];
-        e.active = b->remaining[k] > 0 ? 1 : 0;
-        const int p = (int)bp.size();
-        tile_start.push_back((int)tile_plate.size());
-        for (int t = 0; t < e.args.ntiles; ++t) tile_plate.push_back(p);
-        bp.push_back(e);
-        b->live.push_back((int)k);
-    }
-    b->ntiles = (int)tile_plate.size();
-    b->dirty = false;
-    if (bp.empty()) return SLBM_OK;
-    HIP_TRY(hipMalloc(&b->d_plates, bp.size() * sizeof(BatchPlate<real>)));
-    HIP_TRY(hipMalloc((void**)&b->d_tile_plate, tile_plate.size() * sizeof(int)));
-    HIP_TRY(hipMalloc((void**)&b->d_tile_start, tile_start.size() * sizeof(int)));
-    HIP_TRY(hipMemcpyAsync(b->d_plates, bp.data(), bp.size() * sizeof(BatchPlate<real>), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->d_tile_plate, tile_plate.data(), tile_plate.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->d_tile_start, tile_start.data(), tile_start.size() * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    return SLBM_OK;
-}
-
-int batch_grid(const slbm_batch_s* b)
-{
-    // one workgroup per tile: the batched kernels assume at least ntiles
-    // workgroups, a whole number of XCD rounds (8 workgroups, or 8 groups)
-    const int unit = 8 << std::max(0, group_shift(b->group));
-    return (b->ntiles + unit - 1) / unit * unit;
-}
-
-// Queues one batched launch of up to maxk steps (2 only in two-step mode)
-// and, with advance, its bookkeeping on the stream.
-template <typename real>
-void batch_launch(slbm_batch_s* b, bool advance, int maxk = 1)
-{
-    const int grid = batch_grid(b);
-    const BatchPlate<real>* plates = (const BatchPlate<real>*)b->d_plates;
-    if (b->two) {
-        const dim3 blk(64 * (b->rows + 6));
-        constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
-        if (k2_waves<real>(b->rows) == hi)
-            hipLaunchKernelGGL((k_step2_batch<real, hi>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, group_shift(b->group));
-        else
-            hipLaunchKernelGGL((k_step2_batch<real, lo>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, group_shift(b->group));
-    } else {
-        const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
-        if (b->wide)
-            hipLaunchKernelGGL((k_step_batch<real, true>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, group_shift(b->group));
-        else
-            hipLaunchKernelGGL((k_step_batch<real, false>), dim3(grid), blk, 0, b->stream,
-                               plates, b->d_tile_plate, b->d_tile_start, b->ntiles, group_shift(b->group));
-    }
-    if (advance) {
-        const int n = (int)b->live.size();
-        hipLaunchKernelGGL((k_batch_advance<real>), dim3((n + 63) / 64), dim3(64), 0, b->stream,
-                           (BatchPlate<real>*)b->d_plates, n, b->two ? maxk : 1);
-    }
-}
-
-template <typename real>
-int batch_run(slbm_batch_s* b, int64_t k)
-{
-    if (b->dirty) {
-        int rc = batch_build<real>(b);
-        if (rc) return rc;
-    }
-    if (b->ntiles == 0 || k <= 0) return SLBM_OK;
-    // launches of up to `per` steps; in two-step mode an odd step count ends
-    // with a launch of one step
-    const int per = b->two ? 2 : 1;
-    int64_t left = k / per;                       // launches of `per` steps
-    const int64_t chunk = kChunk / per;           // launches per captured graph
-    if (left >= chunk) {
-        if (!b->graph_ok) {
-            // kChunk steps captured once and replayed: no memset nodes, only
-            // the step and bookkeeping kernels
-            hipGraph_t g = nullptr;
-            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            for (int64_t i = 0; i < chunk; ++i) batch_launch<real>(b, true, per);
-            hipError_t e = hipStreamEndCapture(b->stream, &g);
-            if (e != hipSuccess) return fail(SLBM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return fail(SLBM_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
-            b->graph_ok = true;
-        }
-        while (left >= chunk) {
-            HIP_TRY(hipGraphLaunch(b->graph, b->stream));
-            left -= chunk;
-        }
-    }
-    for (int64_t i = 0; i < left; ++i) batch_launch<real>(b, true, per);
-    const bool odd = b->two && (k & 1);
-    if (odd) batch_launch<real>(b, true, 1);
-    HIP_TRY(hipGetLastError());
-    // host mirror of the device bookkeeping: each launch in which a plate is
-    // active swaps its buffers once and takes min(steps of the launch, remaining)
-    const int64_t full = k / per;
-    for (size_t k2 = 0; k2 < b->slot.size(); ++k2) {
-        slbm_s* h = b->slot[k2];
-        if (!h) continue;
-        const int64_t rem = b->remaining[k2];
-        if (rem <= 0) continue;
-        int64_t launches = std::min(full, (rem + per - 1) / per);
-        int64_t done = std::min(rem, full * per);
-        if (odd && done < rem) {
-            launches += 1;
-            done += 1;
-        }
-        h->cur ^= (int)(launches & 1);
-        h->step += done;
-        h->local = false;
-        b->remaining[k2] -= done;
-    }
-    return SLBM_OK;
-}
-
-}  // namespace
+#include "batch_api.h"
 
 extern "C" {
-
-int slbm_batch_create(int64_t hbm_budget_bytes, int32_t device, void* stream, slbm_batch* out)
-{
-    return guarded([&]() -> int {
-        if (!out) return fail(SLBM_E_INVAL, "null argument");
-        *out = nullptr;
-        if (hbm_budget_bytes <= 0) return fail(SLBM_E_INVAL, "budget must be positive");
-        int n = 0;
-        if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(SLBM_E_DEVICE, "no HIP device");
-        if (device < 0 || device >= n) return fail(SLBM_E_INVAL, "device %d out of range", device);
-        slbm_batch_s* b = new (std::nothrow) slbm_batch_s();
-        if (!b) return fail(SLBM_E_NOMEM, "out of host memory");
-        b->device = device;
-        b->budget = hbm_budget_bytes;
-        DeviceGuard dg(device);
-        if (stream) {
-            b->stream = (hipStream_t)stream;
-        } else {
-            hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-            if (e != hipSuccess) { delete b; return fail(SLBM_E_DEVICE, "stream: %s", hipGetErrorString(e)); }
-            b->own_stream = true;
-        }
-        *out = b;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_add(slbm_batch b, const slbm_params* params, int64_t nsteps, int32_t* slot)
-{
-    return guarded([&]() -> int {
-        if (!b || !params || !slot) return fail(SLBM_E_INVAL, "null argument");
-        if (nsteps < 0) return fail(SLBM_E_INVAL, "negative step count");
-        if (params->periodic_x || params->periodic_y) return fail(SLBM_E_UNSUPPORTED, "periodic plates are not batched");
-        if (b->precision >= 0 && params->precision != b->precision)
-            return fail(SLBM_E_INVAL, "every plate of a batch has the batch's precision");
-        const int64_t need = estimate_bytes(params);
-        if (b->used + need > b->budget)
-            return fail(SLBM_E_BUDGET, "plate needs %lld bytes, %lld of %lld in use", (long long)need,
-                        (long long)b->used, (long long)b->budget);
-        slbm_params p = *params;
-        p.device = b->device;
-        p.stream = b->stream;
-        slbm_handle h = nullptr;
-        int rc = slbm_create(&p, &h);
-        if (rc) return rc;
-        b->precision = params->precision;
-        int k = -1;
-        for (size_t i = 0; i < b->slot.size(); ++i)
-            if (!b->slot[i]) { k = (int)i; break; }
-        if (k < 0) {
-            k = (int)b->slot.size();
-            b->slot.push_back(nullptr);
-            b->remaining.push_back(0);
-            b->bytes.push_back(0);
-        }
-        h->transient_scratch = true;
-        b->slot[k] = h;
-        b->remaining[k] = nsteps;
-        b->bytes[k] = need;
-        b->used += need;
-        b->dirty = true;
-        *slot = k;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_step(slbm_batch b, int64_t k)
-{
-    return guarded([&]() -> int {
-        if (!b) return fail(SLBM_E_INVAL, "null batch");
-        if (k < 0) return fail(SLBM_E_INVAL, "negative step count");
-        if (b->precision < 0) return SLBM_OK;
-        DeviceGuard dg(b->device);
-        return b->precision == SLBM_FP32 ? batch_run<float>(b, k) : batch_run<double>(b, k);
-    });
-}
-
-int slbm_batch_poll(slbm_batch b, int32_t* done_slots, int32_t capacity, int32_t* n_done)
-{
-    return guarded([&]() -> int {
-        if (!b || !n_done) return fail(SLBM_E_INVAL, "null argument");
-        int n = 0;
-        for (size_t k = 0; k < b->slot.size(); ++k) {
-            if (!b->slot[k] || b->remaining[k] > 0) continue;
-            if (done_slots && n < capacity) done_slots[n] = (int32_t)k;
-            ++n;
-        }
-        *n_done = n;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_handle(slbm_batch b, int32_t slot, slbm_handle* h)
-{
-    return guarded([&]() -> int {
-        if (!b || !h) return fail(SLBM_E_INVAL, "null argument");
-        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-        *h = b->slot[slot];
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_displacement(slbm_batch b, int32_t slot, double* u)
-{
-    return guarded([&]() -> int {
-        if (!b || !u) return fail(SLBM_E_INVAL, "null argument");
-        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-        return slbm_displacement(b->slot[slot], u);
-    });
-}
-
-int slbm_batch_remaining(slbm_batch b, int32_t slot, int64_t* steps)
-{
-    return guarded([&]() -> int {
-        if (!b || !steps) return fail(SLBM_E_INVAL, "null argument");
-        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-        *steps = b->remaining[slot];
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_remove(slbm_batch b, int32_t slot)
-{
-    return guarded([&]() -> int {
-        if (!b) return fail(SLBM_E_INVAL, "null batch");
-        if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return fail(SLBM_E_INVAL, "no plate in slot %d", slot);
-        DeviceGuard dg(b->device);
-        HIP_TRY(hipStreamSynchronize(b->stream));
-        slbm_destroy(b->slot[slot]);
-        b->slot[slot] = nullptr;
-        b->remaining[slot] = 0;
-        b->used -= b->bytes[slot];
-        b->bytes[slot] = 0;
-        b->dirty = true;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
-{
-    return guarded([&]() -> int {
-        if (!b) return fail(SLBM_E_INVAL, "null batch");
-        if (strip != 62 && strip != 64 && strip != kStrip2) return fail(SLBM_E_INVAL, "strip must be 58, 62 or 64");
-        if (rows < 1 || rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
-            return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] ([1, 10] with strip 58)");
-        b->rows = rows;
-        b->wide = strip == 64 ? 1 : 0;
-        b->two = strip == kStrip2 ? 1 : 0;
-        b->dirty = true;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_set_xcd_group(slbm_batch b, int32_t group)
-{
-    return guarded([&]() -> int {
-        if (!b) return fail(SLBM_E_INVAL, "null batch");
-        if (!valid_group(group)) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or a power of two up to 64");
-        b->group = group;
-        b->dirty = true;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_sync(slbm_batch b)
-{
-    return guarded([&]() -> int {
-        if (!b) return fail(SLBM_E_INVAL, "null batch");
-        DeviceGuard dg(b->device);
-        HIP_TRY(hipStreamSynchronize(b->stream));
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget)
-{
-    return guarded([&]() -> int {
-        if (!b) return fail(SLBM_E_INVAL, "null batch");
-        if (used) *used = b->used;
-        if (budget) *budget = b->budget;
-        return SLBM_OK;
-    });
-}
-
-int slbm_batch_destroy(slbm_batch b)
-{
-    return guarded([&]() -> int {
-        if (!b) return SLBM_OK;
-        DeviceGuard dg(b->device);
-        (void)hipStreamSynchronize(b->stream);
-        for (slbm_s* h : b->slot)
-            if (h) slbm_destroy(h);
-        batch_free_tables(b);
-        if (b->own_stream) (void)hipStreamDestroy(b->stream);
-        delete b;
-        return SLBM_OK;
-    });
-}
 
 const char* slbm_last_error(void) { return g_err.c_str(); }
 

@@ -768,21 +768,49 @@ __global__ __launch_bounds__(1024, W) void k_step2(StepArgs<real> a)
 }
 
 // Per-plate state of the batched step, in device memory so that a captured
-// graph of steps stays valid from one replay to the next.
+// graph of steps stays valid from one replay to the next.  The table holds
+// two copies, one per launch parity: a launch reads its plates from copy
+// `parity`, and the workgroup of each plate's first tile writes the plate's
+// state for the next launch into copy parity ^ 1 (its buffers swapped, its
+// clock and countdown advanced), so consecutive launches need no separate
+// bookkeeping kernel.
 template <typename real>
 struct BatchPlate {
-    StepArgs<real> args;       // src/dst and t_prev as of the next step
+    StepArgs<real> args;       // src/dst and t_prev as of this launch
     long long remaining;       // steps still to take; 0: idle
     int active;                // 1 while remaining > 0
-    int pad;
+    int halted;                // 1 once the plate's divergence word was set: its tiles skip the arithmetic
 };
+
+// The plate's state after a launch of up to maxk steps: an active plate
+// takes min(maxk, remaining) steps, reading one buffer and writing the other.
+// A plate whose state overflowed in an earlier launch is halted: its steps
+// are still counted (the host's account of every plate stays exact) but no
+// longer computed, until the host retires it.
+template <typename real>
+__device__ __forceinline__ BatchPlate<real> batch_next(BatchPlate<real> B, int maxk)
+{
+    if (B.active && !B.halted && *(volatile unsigned int*)B.args.diverged) B.halted = 1;
+    if (B.active) {
+        const long long k = B.remaining < maxk ? B.remaining : maxk;
+        real* t = const_cast<real*>(B.args.src);
+        B.args.src = B.args.dst;
+        B.args.dst = t;
+        B.args.t_prev += k;
+        B.args.local = 0;
+        B.remaining -= k;
+        B.active = B.remaining > 0 ? 1 : 0;
+    }
+    return B;
+}
 
 // One time step of every active plate of a batch in one launch.  The tiles of
 // all plates (of one height, the launch's) are numbered consecutively
 // (tile_start[p] is plate p's first); one workgroup per tile (the grid holds
 // at least ntiles workgroups), tiles of a plate that is done return at once.
+// plates points at 2 * cap descriptors (copy `parity` is read).
 template <typename real, bool WIDE>
-__global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __restrict__ plates,
+__global__ __launch_bounds__(1024) void k_step_batch(BatchPlate<real>* __restrict__ plates, int cap, int parity,
                                                      const int* __restrict__ tile_plate,
                                                      const int* __restrict__ tile_start, int ntiles, int group_shift)
 {
@@ -790,15 +818,18 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchPlate<real>* __r
     const int t = xcd_map(blockIdx.x, gridDim.x, group_shift);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
-    if (!plates[p].active) return;
-    const StepArgs<real> a = plates[p].args;
-    flag_divergence(a.diverged, step_tile<real, false, WIDE>(a, t - tile_start[p], dens));
+    const BatchPlate<real> B = plates[parity * cap + p];
+    const int lt = t - tile_start[p];
+    // the plate's first tile hands the next launch its state
+    if (lt == 0 && threadIdx.x == 0) plates[(parity ^ 1) * cap + p] = batch_next(B, 1);
+    if (!B.active || B.halted) return;
+    flag_divergence(B.args.diverged, step_tile<real, false, WIDE>(B.args, lt, dens));
 }
 
 // Up to two time steps of every active plate of a batch in one launch (the
 // tiles of the two-step kernel): each plate takes min(maxk, remaining).
 template <typename real, int W>
-__global__ __launch_bounds__(1024, W) void k_step2_batch(const BatchPlate<real>* __restrict__ plates,
+__global__ __launch_bounds__(1024, W) void k_step2_batch(BatchPlate<real>* __restrict__ plates, int cap, int parity,
                                                       const int* __restrict__ tile_plate,
                                                       const int* __restrict__ tile_start, int ntiles, int maxk,
                                                       int group_shift)
@@ -808,32 +839,15 @@ __global__ __launch_bounds__(1024, W) void k_step2_batch(const BatchPlate<real>*
     const int t = xcd_map(blockIdx.x, gridDim.x, group_shift);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
-    if (!plates[p].active) return;
-    const StepArgs<real> a = plates[p].args;
-    if (maxk >= 2 && plates[p].remaining >= 2)
-        flag_divergence(a.diverged, step_tile2<real, false, true>(a, t - tile_start[p], post, dens));
+    const BatchPlate<real> B = plates[parity * cap + p];
+    const int lt = t - tile_start[p];
+    // the plate's first tile hands the next launch its state
+    if (lt == 0 && threadIdx.x == 0) plates[(parity ^ 1) * cap + p] = batch_next(B, maxk);
+    if (!B.active || B.halted) return;
+    if (maxk >= 2 && B.remaining >= 2)
+        flag_divergence(B.args.diverged, step_tile2<real, false, true>(B.args, lt, post, dens));
     else
-        flag_divergence(a.diverged, step_tile2<real, false, false>(a, t - tile_start[p], post, dens));
-}
-
-// After a batched launch of up to maxk steps: swap each active plate's
-// buffers (a launch reads one and writes the other), advance its clock and
-// count down its remaining steps.
-template <typename real>
-__global__ __launch_bounds__(64) void k_batch_advance(BatchPlate<real>* plates, int nplates, int maxk)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nplates) return;
-    BatchPlate<real>& B = plates[p];
-    if (!B.active) return;
-    const long long k = B.remaining < maxk ? B.remaining : maxk;
-    real* t = const_cast<real*>(B.args.src);
-    B.args.src = B.args.dst;
-    B.args.dst = t;
-    B.args.t_prev += k;
-    B.args.local = 0;
-    B.remaining -= k;
-    if (B.remaining <= 0) B.active = 0;
+        flag_divergence(B.args.diverged, step_tile2<real, false, false>(B.args, lt, post, dens));
 }
 
 }  // namespace slbm_dev

@@ -7,10 +7,15 @@ cap is set -- as long as the material sites resident stay within it (enough
 plates to fill the machine, not so many that every request shares it with
 every other and finishes late).  With policy "swf" the waiting request with
 the least work (sites x steps) goes first instead of the oldest.  Every
-resident plate is advanced together, one launch per step for all of them,
-`chunk` steps per round (each plate by at most its remaining steps).  After
-each round the finished plates are read back, removed (their memory is freed
-at once) and the queue is admitted again.  All state stays on the device
+resident plate is advanced together, one launch per step (or two) for all of
+them, a round of steps at a time (each plate by at most its remaining steps).
+
+The host never waits for the round it has just queued: after queuing round
+r it reads back the plates that finished in round r - 1 (each readout waits
+for that plate's last steps only, on the batch's side stream), removes them
+and admits new requests, so the GPU runs round r meanwhile.  Plates whose
+state overflowed are retired by the batch (SLBM_E_DIVERGED) and reported as
+such, without taking their remaining steps.  All state stays on the device
 between rounds.
 
 `run_one_at_a_time` serves the same requests with one plate on the device at
@@ -26,6 +31,10 @@ from typing import Iterable, List, Optional
 import numpy as np
 
 from . import slbm
+
+# material-site updates per microsecond the batched kernel sustains (sizes a
+# round of steps to a target duration)
+RATE_SITES_PER_US = 40e3
 
 
 @dataclasses.dataclass
@@ -46,6 +55,7 @@ class Result:
     diverged: bool
     rejected: bool = False
     u: Optional[np.ndarray] = None
+    steps_taken: int = 0
 
     @property
     def latency(self) -> float:
@@ -69,26 +79,41 @@ def _readout(solver, keep):
 
 
 class Server:
-    """Continuous batching under an HBM budget (bytes)."""
+    """Continuous batching under an HBM budget (bytes).
+
+    chunk: steps per round (the least, with round_ms); round_ms: target GPU
+    time of a round, from the resident sites; timing_stream: a torch stream
+    (the batch's) on which to time the rounds, for the GPU-busy fraction."""
 
     def __init__(self, budget_bytes: int, precision: str = "fp32", chunk: int = 64, device: int = 0,
                  stream=None, launch=None, max_resident_sites: Optional[int] = None, policy: str = "fcfs",
-                 xcd_group: int = 0):
+                 xcd_group: int = 0, round_ms: Optional[float] = None, timing_stream=None):
         self.batch = slbm.Batch(budget_bytes, device=device, stream=stream)
         self.precision = precision
         self.chunk = int(chunk)
+        self.round_ms = round_ms
         self.max_sites = max_resident_sites
         if policy not in ("fcfs", "swf"):
             raise ValueError("policy must be 'fcfs' or 'swf'")
         self.policy = policy
         self.peak_bytes = 0
         self.peak_resident = 0
+        self.timing_stream = timing_stream
+        self.gpu_busy_s = None
+        self.gpu_span_s = None
+        self.rounds = 0
         if launch is not None:
             self.batch.set_launch(*launch)
         self.batch.set_xcd_group(xcd_group)
 
     def close(self):
         self.batch.close()
+
+    def _round_steps(self, sites: int) -> int:
+        if not self.round_ms:
+            return self.chunk
+        steps = int(self.round_ms * 1e3 * RATE_SITES_PER_US / max(sites, 1))
+        return max(self.chunk, min(4096, steps // 32 * 32))
 
     def run(self, requests: Iterable[Request], keep_results: bool = False,
             clock=time.perf_counter, sleep=time.sleep) -> List[Result]:
@@ -98,11 +123,13 @@ class Server:
         order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
         pending = collections.deque(order)
         waiting = collections.deque()
-        resident = {}                     # slot -> (request index, admitted time)
-        sites = 0                         # material sites resident
+        resident = {}                     # slot -> (request index, admitted time): still stepping
+        finishing = {}                    # slot -> (request index, admitted time): steps all queued
+        sites = 0                         # material sites of the plates still stepping
         results: List[Optional[Result]] = [None] * len(reqs)
+        events = []
         t0 = clock()
-        while pending or waiting or resident:
+        while pending or waiting or resident or finishing:
             now = clock() - t0
             while pending and reqs[pending[0]].arrival <= now:
                 waiting.append(pending.popleft())
@@ -120,7 +147,7 @@ class Server:
                 except slbm.SlbmError as e:
                     if e.code != -6:
                         raise
-                    if not resident:
+                    if not resident and not finishing:
                         # larger than the whole budget: it can never run
                         waiting.popleft()
                         t = clock() - t0
@@ -132,30 +159,54 @@ class Server:
                 sites += nsites[i]
             used = self.batch.bytes()[0]
             self.peak_bytes = max(self.peak_bytes, used)
-            self.peak_resident = max(self.peak_resident, len(resident))
-            if not resident:
-                if pending:
-                    sleep(max(0.0, reqs[pending[0]].arrival - (clock() - t0)))
-                continue
-            self.batch.step(self.chunk)
-            self.batch.sync()
-            for slot in self.batch.poll():
-                i, adm = resident.pop(slot)
+            self.peak_resident = max(self.peak_resident, len(resident) + len(finishing))
+            # queue the next round before touching the plates of the last one
+            if resident:
+                if self.timing_stream is not None:
+                    import torch
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(self.timing_stream)
+                self.batch.step(self._round_steps(sites))
+                if self.timing_stream is not None:
+                    e1.record(self.timing_stream)
+                    events.append((e0, e1))
+                self.rounds += 1
+            # at most two rounds in flight: the device always has the next one
+            # queued, and the host never runs far ahead of what it has seen
+            # (plates found diverged are retired within a few rounds)
+            self.batch.wait(1)
+            # results of the plates whose steps were all queued before this round
+            for slot, (i, adm) in list(finishing.items()):
                 r = reqs[i]
-                sites -= nsites[i]
-                diverged, u = _readout(self.batch.solver(slot), keep_results)
+                sv = self.batch.solver(slot)
+                diverged, u = _readout(sv, keep_results)
+                taken = sv.time()[0]
                 self.batch.remove(slot)
-                results[i] = Result(i, r.arrival, adm, clock() - t0, r.steps, nsites[i], diverged, False, u)
+                del finishing[slot]
+                results[i] = Result(i, r.arrival, adm, clock() - t0, r.steps, nsites[i], diverged, False, u,
+                                    taken)
+            for slot in self.batch.poll():
+                if slot in resident:
+                    finishing[slot] = resident.pop(slot)
+                    sites -= nsites[finishing[slot][0]]
+            if not resident and not finishing and pending and not waiting:
+                sleep(max(0.0, reqs[pending[0]].arrival - (clock() - t0)))
+        if events:
+            import torch
+            torch.cuda.synchronize()
+            self.gpu_busy_s = sum(a.elapsed_time(b) for a, b in events) / 1e3
+            self.gpu_span_s = events[0][0].elapsed_time(events[-1][1]) / 1e3
         return results
 
 
 def run_one_at_a_time(requests: Iterable[Request], precision: str = "fp32", device: int = 0, stream=None,
                       keep_results: bool = False, autotune: bool = True, policy: str = "fcfs",
-                      clock=time.perf_counter, sleep=time.sleep) -> List[Result]:
+                      clock=time.perf_counter, sleep=time.sleep, check_every: int = 1024) -> List[Result]:
     """The same requests served one plate at a time with plain launches
     (each plate in its autotuned launch shape, or the library's default):
     the oldest waiting request first ("fcfs") or the one with the least work
-    ("swf")."""
+    ("swf").  A plate is checked for divergence every `check_every` steps
+    and stopped when its state has overflowed, as the server retires it."""
     if policy not in ("fcfs", "swf"):
         raise ValueError("policy must be 'fcfs' or 'swf'")
     reqs = list(requests)
@@ -178,28 +229,50 @@ def run_one_at_a_time(requests: Iterable[Request], precision: str = "fp32", devi
         s = slbm.Solver(r.plate, precision, device=device, stream=stream)
         if autotune:
             s.autotune()
-        s.step(r.steps)
+        done = 0
+        while done < r.steps:
+            k = min(check_every, r.steps - done)
+            s.step(k)
+            done += k
+            if done < r.steps:
+                try:
+                    s.sync()
+                except slbm.SlbmError as e:
+                    if e.code != -4:
+                        raise
+                    break
         diverged, u = _readout(s, keep_results)
         s.close()
-        results[i] = Result(i, r.arrival, adm, clock() - t0, r.steps, int(r.plate.n_material), diverged, False, u)
+        results[i] = Result(i, r.arrival, adm, clock() - t0, r.steps, int(r.plate.n_material), diverged, False, u,
+                            done)
     return results
 
 
 def summary(results: List[Result]) -> dict:
-    """Latency percentiles (s), queue wait, and aggregate throughput (MLUPS,
-    material-site updates over the time from the start to the last result)."""
-    done = [r for r in results if r is not None and not r.rejected]
-    lat = np.array([r.latency for r in done])
-    wait = np.array([r.wait for r in done])
-    span = max(r.finished for r in done)
-    work = sum(r.sites * r.steps for r in done)
-    return {
+    """Latency percentiles (s), queue wait and aggregate throughput (MLUPS:
+    material-site updates of the requests that completed, over the time from
+    the start to the last result) of the completed requests; requests whose
+    state overflowed are counted apart, with the steps they took."""
+    served = [r for r in results if r is not None and not r.rejected]
+    done = [r for r in served if not r.diverged]
+    bad = [r for r in served if r.diverged]
+    span = max(r.finished for r in served) if served else 0.0
+    out = {
         "requests": len(done),
         "rejected": sum(1 for r in results if r is not None and r.rejected),
-        "diverged": sum(1 for r in done if r.diverged),
-        "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-        "mean_queue_wait_s": round(float(wait.mean()), 4),
+        "diverged": len(bad),
         "makespan_s": round(span, 4),
-        "aggregate_mlups": round(work / span / 1e6, 1),
     }
+    if done:
+        lat = np.array([r.latency for r in done])
+        wait = np.array([r.wait for r in done])
+        out.update({
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_queue_wait_s": round(float(wait.mean()), 4),
+            "aggregate_mlups": round(sum(r.sites * r.steps for r in done) / span / 1e6, 1),
+        })
+    if bad:
+        out["diverged_steps_taken_mean"] = round(float(np.mean([r.steps_taken for r in bad])), 1)
+        out["diverged_detect_latency_p50_s"] = round(float(np.percentile([r.latency for r in bad], 50)), 4)
+    return out

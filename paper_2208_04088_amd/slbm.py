@@ -25,7 +25,9 @@ EXPORTS = [
     "slbm_displacement", "slbm_displacement_device", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
-    "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch", "slbm_batch_set_xcd_group", "slbm_batch_sync",
+    "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch",
+    "slbm_batch_set_xcd_group", "slbm_batch_get_launch", "slbm_batch_autotune", "slbm_batch_sync",
+    "slbm_batch_wait",
     "slbm_batch_bytes", "slbm_batch_destroy",
 ]
 
@@ -97,7 +99,10 @@ def lib():
         "slbm_batch_remove": [vp, i32],
         "slbm_batch_set_launch": [vp, i32, i32],
         "slbm_batch_set_xcd_group": [vp, i32],
+        "slbm_batch_get_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "slbm_batch_autotune": [vp, i64, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)],
         "slbm_batch_sync": [vp],
+        "slbm_batch_wait": [vp, i32],
         "slbm_batch_bytes": [vp, C.POINTER(i64), C.POINTER(i64)],
         "slbm_batch_destroy": [vp],
     }
@@ -260,12 +265,18 @@ class Solver:
 
 
 class _BorrowedSolver(Solver):
-    """A plate owned by a batch: the single-plate readout calls on its handle."""
+    """A plate owned by a batch: the single-plate readout calls on its handle
+    (the library refuses calls that would step or change it)."""
 
     def __init__(self, plate, handle):
         self.plate = plate
         self.h = handle
         self.n = plate.nx * plate.ny
+
+    def _owned(self, *args, **kw):
+        raise SlbmError(-1, "the plate belongs to a batch: step it with Batch.step")
+
+    step = init_fields = load = autotune = set_launch = set_xcd_group = _owned
 
     def close(self):
         self.h = None        # the batch frees it
@@ -325,8 +336,28 @@ class Batch:
         """0: contiguous bands of tiles per XCD; g > 0: interleaved groups of g."""
         _check(lib().slbm_batch_set_xcd_group(self.b, int(group)))
 
+    def launch(self):
+        """(rows per tile, strip, XCD group) of the batched launch."""
+        r, st, g = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().slbm_batch_get_launch(self.b, C.byref(r), C.byref(st), C.byref(g)))
+        return r.value, st.value, g.value
+
+    def autotune(self, max_steps):
+        """slbm_batch_autotune: picks the launch shape on the resident plates
+        with real steps (at most max_steps); returns (rows, strip, XCD group,
+        us per step)."""
+        r, st, g, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().slbm_batch_autotune(self.b, int(max_steps), C.byref(r), C.byref(st), C.byref(g),
+                                         C.byref(us)))
+        return r.value, st.value, g.value, us.value
+
     def sync(self):
         _check(lib().slbm_batch_sync(self.b))
+
+    def wait(self, in_flight):
+        """Blocks until at most `in_flight` step calls are still queued or
+        running (slbm_batch_wait)."""
+        _check(lib().slbm_batch_wait(self.b, int(in_flight)))
 
     def bytes(self):
         u, t = C.c_int64(), C.c_int64()

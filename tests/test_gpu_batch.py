@@ -1,12 +1,16 @@
 """Batched path (slbm_batch_*): many plates in one launch per step, steps
-replayed from a captured graph.  Every plate's result must be bit-identical
-to the same plate run alone (the per-site arithmetic does not depend on the
-batch), which in turn is checked against the CPU reference elsewhere."""
+replayed from a captured graph.  Every plate's result is checked against the
+CPU reference element by element, and must be bit-identical to the same plate
+run alone (the per-site arithmetic does not depend on the batch)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
+from oracle import Oracle
 from slbm_workloads import configs
 from slbm_workloads import geometry as G
+from test_gpu_parity import FP32_TOL, compare, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +31,24 @@ def small_plates(seed, count):
     for i in range(count):
         out.append(configs._random_plate(rng, area_lo=24 ** 2, area_hi=180 ** 2, load=1e-3, steps=0,
                                          name=f"small{seed}-{i}"))
+    return out
+
+
+def oracle_plates(seed, count):
+    """Uneven plates of the batched-workload generator (0-3 holes, an edge
+    crack with probability 1/2, mu ~ U[0.02, 0.08]) at test size, with
+    lambda/mu redrawn in [0.5, 1] and the Neumann extrapolation order
+    alternating between the two rules, and a last plate at lambda/mu = 1.8
+    (tau_bar 0.6), whose traction-free walls grow a surface mode: it is
+    compared over its first 40 steps only."""
+    rng = np.random.default_rng(seed + 1000)
+    out = []
+    for i, p in enumerate(small_plates(seed, count)):
+        last = i == count - 1
+        lm = 1.8 if last else rng.uniform(0.5, 1.0)
+        order = 0 if last else i % 2
+        out.append(dataclasses.replace(p, lam=lm * p.mu, tau=configs.tau_for(lm), neumann_order=order,
+                                       name=f"{p.name}-lm{lm:.2f}-o{order}"))
     return out
 
 
@@ -62,6 +84,73 @@ def test_batched_plates_match_their_solo_runs(slbm, prec, launch):
     b.close()
 
 
+@pytest.mark.parametrize("launch", [(6, 62), (6, 58), (10, 58)])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_plates_match_the_reference(slbm, prec, launch):
+    """Eight uneven random plates (holes, edge crack, both Neumann rules,
+    lambda/mu in [0.5, 1] and one at 1.8) advanced together by uneven step
+    chunks, each to its own step count: every plate's displacement, density,
+    momentum, Poisson stress and Cauchy stress against the CPU reference
+    (fp64 to 1e-12 against the extended-precision build, fp32 to 1e-4)."""
+    plates = oracle_plates(21, 8)
+    steps = [37, 64, 101, 150, 23, 211, 120, 40]
+    b = slbm.Batch(8 << 30)
+    b.set_launch(*launch)
+    slots = [b.add(p, n, prec) for p, n in zip(plates, steps)]
+    for k in (5, 32, 1, 40, 64, 128):        # chunks below, at and above the graph size, odd ones
+        b.step(k)
+    b.sync()
+    assert sorted(b.poll()) == sorted(slots)
+    for p, n, sl in zip(plates, steps, slots):
+        s = b.solver(sl)
+        assert s.time()[0] == n
+        s.sync()
+        ref = Oracle(p, extended=(prec == "fp64"))
+        ref.step(n)
+        e = compare(s, ref, prec)
+        print(f"{p.name} {p.nx}x{p.ny} {n} steps {prec}: rel L2 u = {e:.2e}")
+    b.close()
+
+
+def test_batch_autotune_takes_real_steps(slbm):
+    """slbm_batch_autotune times launch shapes with real steps: the plates
+    advance by them, and their state equals the same number of steps taken
+    alone; the shape it keeps is reported."""
+    plates = oracle_plates(7, 6)[:5]             # lambda/mu <= 1: none diverges and is retired
+    b = slbm.Batch(8 << 30)
+    slots = [b.add(p, 600, "fp32") for p in plates]
+    rows, strip, group, us = b.autotune(600)
+    assert strip in (58, 62) and group in (0, 8) and us > 0
+    assert b.launch() == (rows, strip, group)
+    taken = [b.solver(sl).time()[0] for sl in slots]
+    assert len(set(taken)) == 1 and 0 < taken[0] <= 600
+    b.step(33)
+    for p, sl in zip(plates, slots):
+        u_ref, _ = alone(slbm, p, taken[0] + 33, "fp32")
+        assert np.array_equal(b.solver(sl).displacement(), u_ref, equal_nan=True), p.name
+    b.close()
+
+
+def test_batch_plate_handle_refuses_stepping(slbm):
+    """A batch plate's handle is for readouts: stepping it, or changing its
+    state or launch shape, would desynchronise the batch and is refused."""
+    p = small_plates(8, 1)[0]
+    b = slbm.Batch(8 << 30)
+    sl = b.add(p, 10, "fp32")
+    s = b.solver(sl)
+    for call in (lambda: s.step(1), lambda: s.autotune(), lambda: s.set_launch(6, 58),
+                 lambda: s.init_fields(), lambda: s.set_xcd_group(8)):
+        with pytest.raises(slbm.SlbmError) as e:
+            call()
+        assert e.value.code == -1
+    L = slbm.lib()
+    assert L.slbm_step(s.h, 1) == -1 and L.slbm_destroy(s.h) == -1
+    b.step(10)
+    u_ref, _ = alone(slbm, p, 10, "fp32")
+    assert np.array_equal(b.displacement(sl), u_ref)
+    b.close()
+
+
 @pytest.mark.parametrize("launch", [None, (4, 58)])
 def test_continuous_batching_joins_and_leaves(slbm, launch):
     """Plates arrive while others are running and leave when done; each
@@ -88,6 +177,7 @@ def test_continuous_batching_joins_and_leaves(slbm, launch):
         assert n == want[i]
         u_ref, _ = alone(slbm, plates[i], want[i], "fp32")
         assert np.array_equal(u, u_ref), plates[i].name
+    b.sync()                         # the removed plates' memory is reusable once their work has run
     assert b.bytes()[0] == 0
     b.close()
 
@@ -130,20 +220,28 @@ def test_budget_is_enforced(slbm):
 
 def test_batch_divergence_is_per_plate(slbm):
     """One plate that blows up (lambda/mu = 2, traction-free, the paper's
-    extrapolation) flags itself and leaves its neighbours' results intact."""
+    extrapolation) flags itself, is retired before its step count (its
+    remaining steps set to zero), and leaves its neighbours' results intact."""
     n = 40
     bad = G.build_plate(n, n, lam=0.1, mu=0.05, tau=0.6, walls=G.edge_walls(n, n, 0, 0, 1, 1),
                         groups=[G.BCGroup(G.NEUMANN, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (0.0, 1e-4))],
                         neumann_order=1, name="unstable")
     good = small_plates(13, 1)[0]
     b = slbm.Batch(8 << 30)
-    sb = b.add(bad, 2000, "fp32")
-    sg = b.add(good, 2000, "fp32")
-    b.step(2000)
+    sb = b.add(bad, 20000, "fp32")
+    sg = b.add(good, 4000, "fp32")
+    for _ in range(4000 // 64 + 1):
+        b.step(64)
+    b.sync()
+    assert sorted(b.poll()) == sorted([sb, sg])
+    assert b.remaining(sb) == 0
+    stopped = b.solver(sb).time()[0]
+    assert stopped < 20000
     with pytest.raises(slbm.SlbmError) as e:
         b.solver(sb).sync()
     assert e.value.code == -4
     b.solver(sg).sync()
-    u_ref, _ = alone(slbm, good, 2000, "fp32")
+    u_ref, _ = alone(slbm, good, 4000, "fp32")
     assert np.array_equal(b.solver(sg).displacement(), u_ref)
+    print(f"diverged plate retired after {stopped} of 20000 steps")
     b.close()

@@ -1,10 +1,14 @@
 """Serving loop (continuous batching under an HBM budget): every result is
 the same alone and in the mix, the budget holds, and requests that arrive
 while others run are admitted as memory frees up."""
+import dataclasses
+
 import numpy as np
 import pytest
 
+from oracle import Oracle
 from slbm_workloads import configs
+from slbm_workloads import geometry as G
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +63,63 @@ def test_results_are_the_same_alone_and_in_the_mix(mods):
         s.close()
     st = serve.summary(res)
     assert st["requests"] == len(trace) and st["p99_latency_s"] >= st["p50_latency_s"] > 0
+
+
+def test_served_results_match_the_reference(mods):
+    """Requests of a served trace (uneven random plates arriving while others
+    run), each result against the CPU reference element by element:
+    lambda/mu redrawn in [0.5, 1] so that the plates stay stable over their
+    step counts; fp32 displacement within 1e-4 relative L2."""
+    serve, slbm = mods
+    rng = np.random.default_rng(31)
+    trace = []
+    for r in small_trace(12, 6, rate=300.0):
+        lm = rng.uniform(0.5, 1.0)
+        p = dataclasses.replace(r.plate, lam=lm * r.plate.mu, tau=configs.tau_for(lm))
+        trace.append(configs.Request(r.arrival, p, r.steps))
+    srv = serve.Server(2 << 30, chunk=16, max_resident_sites=3 * max(r.plate.n_material for r in trace))
+    res = srv.run(trace, keep_results=True)
+    srv.close()
+    assert srv.peak_resident >= 2
+    for r, q in zip(res, trace):
+        assert not r.diverged and not r.rejected
+        ref = Oracle(q.plate)
+        ref.step(q.steps)
+        u_ref = ref.displacement()
+        e = float(np.linalg.norm(r.u - u_ref) / np.linalg.norm(u_ref))
+        print(f"{q.plate.name} {q.plate.nx}x{q.plate.ny} {q.steps} steps: rel L2 u = {e:.2e}")
+        assert e <= 1e-4, (q.plate.name, e)
+
+
+def test_diverging_request_is_retired(mods):
+    """A request whose state overflows (lambda/mu = 2, traction-free walls,
+    the paper's extrapolation) is reported as diverged after fewer steps
+    than it asked for, and the requests beside it are unaffected."""
+    serve, slbm = mods
+    n = 40
+    bad = G.build_plate(n, n, lam=0.1, mu=0.05, tau=0.6, walls=G.edge_walls(n, n, 0, 0, 1, 1),
+                        groups=[G.BCGroup(G.NEUMANN, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (0.0, 1e-4))],
+                        neumann_order=1, name="unstable")
+    trace = small_trace(14, 3, rate=500.0)
+    trace.insert(1, configs.Request(trace[0].arrival, bad, 30000))
+    srv = serve.Server(2 << 30, chunk=64)
+    res = srv.run(trace, keep_results=True)
+    srv.close()
+    assert res[1].diverged and res[1].steps_taken < 30000
+    for r, q in zip(res, trace):
+        if q.plate is bad:
+            continue
+        assert not r.diverged
+        s = slbm.Solver(q.plate, "fp32")
+        s.step(q.steps)
+        try:
+            s.sync()
+        except slbm.SlbmError:
+            pass
+        assert np.array_equal(r.u, s.displacement(), equal_nan=True), q.plate.name
+        s.close()
+    st = serve.summary(res)
+    assert st["diverged"] == 1 and st["requests"] == len(trace) - 1
 
 
 @pytest.mark.parametrize("policy", ["fcfs", "swf"])

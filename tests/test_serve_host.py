@@ -31,6 +31,7 @@ class FakeBatch:
         self.used = 0
         self.order = []
         self.max_sites_seen = 0
+        self.steps_called = []
 
     def add(self, plate, steps, prec):
         need = 100 * plate.n_material
@@ -41,7 +42,9 @@ class FakeBatch:
         self.slots[s] = [plate, steps, need]
         self.used += need
         self.order.append(plate.name)
-        self.max_sites_seen = max(self.max_sites_seen, sum(p.n_material for p, _, _ in self.slots.values()))
+        # sites of the plates still stepping (finished ones wait for their readout)
+        self.max_sites_seen = max(self.max_sites_seen,
+                                  sum(p.n_material for p, r, _ in self.slots.values() if r > 0))
         return s
 
     def step(self, k):
@@ -49,15 +52,21 @@ class FakeBatch:
         self.clock.t += 1e-5 * sites * k
         for v in self.slots.values():
             v[1] = max(0, v[1] - k)
+        self.steps_called.append(k)
 
     def sync(self):
+        pass
+
+    def wait(self, n):
         pass
 
     def poll(self):
         return [s for s, v in self.slots.items() if v[1] == 0]
 
     def solver(self, slot):
-        return types.SimpleNamespace(sync=lambda: None, displacement=lambda: np.zeros(1))
+        plate, rem, _ = self.slots[slot]
+        return types.SimpleNamespace(sync=lambda: None, displacement=lambda: np.zeros(1),
+                                     time=lambda: (0, 0.0))
 
     def remove(self, slot):
         self.used -= self.slots.pop(slot)[2]
@@ -139,3 +148,49 @@ def test_summary_percentiles():
     assert st["p50_latency_s"] == pytest.approx(50.5)
     assert st["p99_latency_s"] == pytest.approx(99.01)
     assert st["aggregate_mlups"] == pytest.approx(100 * 10 * 100 / 100 / 1e6, abs=0.1)
+
+
+def test_summary_counts_diverged_requests_apart():
+    """Latency and throughput are over the requests that completed; those
+    whose state overflowed are counted with the steps they took."""
+    rs = [serve.Result(i, 0.0, 0.0, float(i + 1), 10, 100, False) for i in range(4)]
+    rs.append(serve.Result(4, 0.0, 0.0, 9.0, 1000, 10 ** 6, True, steps_taken=64))
+    st = serve.summary(rs)
+    assert st["requests"] == 4 and st["diverged"] == 1
+    assert st["p99_latency_s"] == pytest.approx(3.97)
+    assert st["makespan_s"] == 9.0
+    assert st["aggregate_mlups"] == pytest.approx(4 * 100 * 10 / 9.0 / 1e6, abs=1e-3)
+    assert st["diverged_steps_taken_mean"] == 64
+
+
+def test_next_round_is_queued_before_readout(monkeypatch):
+    """The loop queues round r + 1 before it reads back the plates that
+    finished in round r, so the device is never idle for a readout."""
+    srv, b, clock = server(monkeypatch, budget=10 ** 12)
+    calls = []
+    real_step, real_solver = b.step, b.solver
+
+    def step(k):
+        calls.append(("step", k))
+        real_step(k)
+
+    def solver(slot):
+        calls.append(("readout", slot))
+        return real_solver(slot)
+
+    b.step, b.solver = step, solver
+    spec = [(0.0, 100, 10), (0.0, 100, 40)]
+    srv.run([serve.Request(a, P(f"r{i}", n), s) for i, (a, n, s) in enumerate(spec)], clock=clock,
+            sleep=clock.sleep)
+    # r0 finishes in the first round; its readout comes after the second is queued
+    first_readout = next(i for i, c in enumerate(calls) if c[0] == "readout")
+    assert [c[0] for c in calls[:first_readout]] == ["step", "step"]
+
+
+def test_round_length_follows_the_resident_sites(monkeypatch):
+    srv, b, clock = server(monkeypatch, budget=10 ** 12, round_ms=10.0)
+    spec = [(0.0, 10 ** 6, 2000)]
+    srv.run([serve.Request(a, P(f"r{i}", n), s) for i, (a, n, s) in enumerate(spec)], clock=clock,
+            sleep=clock.sleep)
+    # 10 ms at 40e3 sites per microsecond over 1e6 sites: 400 steps a round
+    assert b.steps_called[0] == 384
