@@ -151,6 +151,20 @@ int slbm_displacement(slbm_handle h, double* u);
  * the handle's stream, without synchronising. */
 int slbm_displacement_device(slbm_handle h, void* u_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * displacement as slbm_displacement_device, into device memory u_dev
+ * ([2][n] doubles, the caller's), queued on the handle's stream, without
+ * synchronising, and with no device allocation or free: its density
+ * scratch is a fixed 144 MiB array in the library's code object, one per
+ * device, so plates whose padded plane ((ny + 2) rows of nx + 65 sites
+ * rounded up to a multiple of 64) exceeds 18874368 sites return
+ * SLBM_E_INVAL (a 4096 x 4096 plate fits).  Every call on a device uses
+ * that device's one array: calls that may overlap on one device (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller.  SLBM_E_INVAL for a null pointer. */
+int slbm_displacement_device_noalloc(slbm_handle h, void* u_dev);
+
 /* Same as slbm_moments into device memory on the handle's stream, without
  * synchronising: rho_dev [n], j_dev [2][n], P_dev [3][n], sigma_dev [3][n]
  * (any pointer may be NULL), each an array of doubles (dtype SLBM_FP64) or

@@ -48,6 +48,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -147,8 +148,37 @@ __device__ void grad_rho(const double* dr, const uint8_t* flags, int x, int y, i
     gy = (1.0 / 3.0) * (rt[2] - rt[4]) + (1.0 / 12.0) * (rt[5] + rt[6] - rt[7] - rt[8]);
 }
 
-// Lattice-unit moments and displacement, padded planes out[11] =
-// rho, jx, jy, Pxx, Pyy, Pxy, sxx, syy, sxy, ux, uy.
+// Lattice-unit moments and displacement of the material site (x, y) (padded
+// offset idx) from the current state and the density field dr: o[11] = rho,
+// jx, jy, Pxx, Pyy, Pxy, sxx, syy, sxy, ux, uy (eq:moments with the half-step
+// source, eq:poissonstress with eq:approxdiv, the trapezoid displacement).
+template <typename real, bool PER>
+__device__ __forceinline__ void site_outputs(const StepArgs<real>& a, const double* dr, int x, int y, int idx,
+                                             double o[11])
+{
+    real g[9];
+    unsigned fl;
+    fetch_site<real, PER>(a, x, y, g, fl);
+    double gd[9];
+    for (int i = 0; i < 9; ++i) gd[i] = (double)g[i];
+    double d, jx, jy, pxx, pyy, pxy;
+    moments9(gd, d, jx, jy, pxx, pyy, pxy);
+    double gx, gy;
+    grad_rho<PER>(dr, a.flags, x, y, a.nx, a.ny, a.ld, a.px, a.py, gx, gy);
+    const double rho = 1.0 + d;
+    const double c = (double)a.ml / rho;
+    jx += 0.5 * ((double)a.Fx + c * gx);
+    jy += 0.5 * ((double)a.Fy + c * gy);
+    const double lm = (double)a.lm;
+    o[0] = rho; o[1] = jx; o[2] = jy; o[3] = pxx; o[4] = pyy; o[5] = pxy;
+    o[6] = -pxx - lm * d; o[7] = -pyy - lm * d; o[8] = -pxy;
+    // trapezoid readout: U holds u0 - v0/2 + sum of earlier j/rho
+    o[9] = a.U[idx] + 0.5 * jx / rho;
+    o[10] = a.U[a.plane + idx] + 0.5 * jy / rho;
+}
+
+// Padded planes out[11] (site_outputs; zero where there is no state), or
+// only ux, uy (ncomp 2).
 template <typename real, bool PER>
 __global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double* dr, double* out, int ncomp)
 {
@@ -157,33 +187,29 @@ __global__ __launch_bounds__(256) void k_outputs(StepArgs<real> a, const double*
     if (idx >= P) return;
     const int y = idx / a.ld - 1, x = idx % a.ld - kPadL;
     double o[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && a.flags[idx] != kVoid) {
-        real g[9];
-        unsigned fl;
-        fetch_site<real, PER>(a, x, y, g, fl);
-        double gd[9];
-        for (int i = 0; i < 9; ++i) gd[i] = (double)g[i];
-        double d, jx, jy, pxx, pyy, pxy;
-        moments9(gd, d, jx, jy, pxx, pyy, pxy);
-        double gx, gy;
-        grad_rho<PER>(dr, a.flags, x, y, a.nx, a.ny, a.ld, a.px, a.py, gx, gy);
-        const double rho = 1.0 + d;
-        const double c = (double)a.ml / rho;
-        jx += 0.5 * ((double)a.Fx + c * gx);
-        jy += 0.5 * ((double)a.Fy + c * gy);
-        const double lm = (double)a.lm;
-        o[0] = rho; o[1] = jx; o[2] = jy; o[3] = pxx; o[4] = pyy; o[5] = pxy;
-        o[6] = -pxx - lm * d; o[7] = -pyy - lm * d; o[8] = -pxy;
-        // trapezoid readout: U holds u0 - v0/2 + sum of earlier j/rho
-        o[9] = a.U[idx] + 0.5 * jx / rho;
-        o[10] = a.U[P + idx] + 0.5 * jy / rho;
-    }
+    if (x >= 0 && x < a.nx && y >= 0 && y < a.ny && a.flags[idx] != kVoid) site_outputs<real, PER>(a, dr, x, y, idx, o);
     if (ncomp == 11) {
         for (int c = 0; c < 11; ++c) out[c * P + idx] = o[c];
     } else {
         out[idx] = o[9];
         out[P + idx] = o[10];
     }
+}
+
+// The displacement straight into an unpadded [2][ny][nx] array (zero where
+// there is no state): the values k_outputs gives, without its padded planes.
+template <typename real, bool PER>
+__global__ __launch_bounds__(256) void k_displacement_out(StepArgs<real> a, const double* dr, double* u)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = a.nx * a.ny;
+    if (idx >= n) return;
+    const int y = idx / a.nx, x = idx - y * a.nx;
+    const int s = sidx(x, y, a.ld);
+    double o[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (a.flags[s] != kVoid) site_outputs<real, PER>(a, dr, x, y, s, o);
+    u[idx] = o[9];
+    u[n + idx] = o[10];
 }
 
 // One padded plane into an unpadded, contiguous [ny][nx] array.
@@ -1014,6 +1040,50 @@ int copy_out(slbm_s* h, int comp, double scale, double offset, double* dst)
 
 }  // namespace
 
+// ------------------------------------------------ readout without allocation
+
+// The density plane slbm_displacement_device_noalloc reads the displacement
+// through: a fixed array in the library's code object, so the call needs no
+// device allocation.  Each device the library runs on holds its own copy
+// (144 MiB) until the process ends; every call on a device shares it.
+constexpr size_t kStaticScratchDoubles = (size_t)18874368;   // 144 MiB of fp64: a 4096 x 4096 plate's padded plane
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (the host-side name
+// is only a stand-in, not a device address), looked up once per device.
+int static_scratch(int device, double** out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(SLBM_E_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SLBM_E_DEVICE, "address of the static readout scratch: %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return SLBM_OK;
+}
+
+template <typename real, bool PER>
+void launch_displacement_noalloc(slbm_s* h, double* dr, double* u)
+{
+    const StepArgs<real> a = make_args<real>(h, h->cur);
+    const int n = h->nx * h->ny;
+    hipLaunchKernelGGL((k_density<real, PER>), dim3((int)((h->plane + 255) / 256)), dim3(256), 0, h->stream, a, dr);
+    hipLaunchKernelGGL((k_displacement_out<real, PER>), dim3((n + 255) / 256), dim3(256), 0, h->stream, a,
+                       (const double*)dr, u);
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ ABI
 
 extern "C" {
@@ -1127,6 +1197,29 @@ int slbm_displacement_device(slbm_handle h, void* u_dev)
                            (const double*)(h->scratch + h->plane), h->nx, h->ny, h->ld, (double*)u_dev);
         HIP_TRY(hipGetLastError());
         release_transient_scratch(h);
+        return SLBM_OK;
+    });
+}
+
+int slbm_displacement_device_noalloc(slbm_handle h, void* u_dev)
+{
+    return guarded([&]() -> int {
+        if (!h || !u_dev) return fail(SLBM_E_INVAL, "null argument");
+        if ((size_t)h->plane > kStaticScratchDoubles)
+            return fail(SLBM_E_INVAL, "padded plane of %lld sites exceeds the static readout scratch of %zu sites",
+                        (long long)h->plane, kStaticScratchDoubles);
+        DeviceGuard dg(h->device);
+        if (int rw = wait_ready(h)) return rw;
+        double* dr = nullptr;
+        if (int rc = static_scratch(h->device, &dr)) return rc;
+        const bool per = h->px || h->py;
+        if (h->precision == SLBM_FP32)
+            per ? launch_displacement_noalloc<float, true>(h, dr, (double*)u_dev)
+                : launch_displacement_noalloc<float, false>(h, dr, (double*)u_dev);
+        else
+            per ? launch_displacement_noalloc<double, true>(h, dr, (double*)u_dev)
+                : launch_displacement_noalloc<double, false>(h, dr, (double*)u_dev);
+        HIP_TRY(hipGetLastError());
         return SLBM_OK;
     });
 }

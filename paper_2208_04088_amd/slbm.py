@@ -22,7 +22,7 @@ PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
 
 EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
-    "slbm_displacement", "slbm_displacement_device", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
+    "slbm_displacement", "slbm_displacement_device", "slbm_displacement_device_noalloc", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
     "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
     "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch",
@@ -78,6 +78,7 @@ def lib():
         "slbm_moments": [vp, dp, dp, dp, dp],
         "slbm_displacement": [vp, dp],
         "slbm_displacement_device": [vp, vp],
+        "slbm_displacement_device_noalloc": [vp, vp],
         "slbm_moments_device": [vp, vp, vp, vp, vp, i32],
         "slbm_time": [vp, C.POINTER(i64), C.POINTER(C.c_double)],
         "slbm_set_launch": [vp, i32, i32],
@@ -210,6 +211,12 @@ class Solver:
         """Writes [2][ny][nx] doubles to device pointer ``ptr`` (e.g. a torch
         tensor's data_ptr()) on the handle's stream."""
         _check(lib().slbm_displacement_device(self.h, C.c_void_p(int(ptr))))
+
+    def displacement_device_noalloc(self, ptr):
+        """As displacement_device, with no device allocation: the density
+        scratch is the library's static per-device array (plates up to
+        4096 x 4096; overlapping calls on one device race)."""
+        _check(lib().slbm_displacement_device_noalloc(self.h, C.c_void_p(int(ptr))))
 
     def moments_device(self, rho=0, j=0, P=0, sigma=0, dtype="fp64"):
         """Writes the moments of :meth:`moments` to device pointers (e.g.
