@@ -6,8 +6,9 @@ equilibrium, collision, displacement update and the non-finite guard, all in
 the fused kernel.  The default workload is the 2048 x 2048 plate with a
 centred hole of radius 256 (curved traction-free wall, lambda/mu = 2,
 tau_bar = 0.6, fp32 populations, fp64 displacement).  Its line also carries
-the fp64-plain step on the same plate, a 4096^2 plate and the served trace
-(p50/p99 latency) as sub-records.
+the fp64-plain step on the same plate, a 4096^2 plate, a 2048^2 plate with a
+moving curved Dirichlet wall and the served trace (p50/p99 latency) as
+sub-records.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-extras]
     python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
@@ -45,6 +46,8 @@ def workload(name):
         "hole2048-lm1": (lambda: configs.hole_plate(lam=0.05, tau=0.55), "fp32"),
         "square128": (lambda: configs.square_clamped_pulled(), "fp64"),
         "square4096": (lambda: configs.square_clamped_pulled(4096, steps=2000), "fp32"),
+        # curved Dirichlet walls, one moving (ramped): periodic, no free wall, stable
+        "movinghole2048": (lambda: configs.moving_hole_plate(), "fp32"),
     }
     if name not in table:
         raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}, batch64, serve or cube<N>")
@@ -500,8 +503,10 @@ def time_plate(args, slbm, torch, stream, plate, prec, steps, warmup, shape=None
     torch.cuda.synchronize()
     launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
     launch_med_ms = launch_ms[len(launch_ms) // 2]
-    if not diverged:
-        s.sync()
+    # the probe launches step on past the timed region: report the state at the end
+    diverged_end = diverged_sync()
+    steps_end = s.time()[0]
+    if not diverged_end:
         import numpy as np
         assert np.isfinite(s.displacement()).all()
     s.close()
@@ -548,6 +553,7 @@ def time_plate(args, slbm, torch, stream, plate, prec, steps, warmup, shape=None
             "bench_step": "one lattice-Boltzmann time step of the whole plate",
             "wall_s": round(wall, 4),
             "diverged": diverged,
+            "diverged_after_probes": diverged_end, "steps_after_probes": steps_end,
         },
         "roofline": roof,
     }
@@ -642,14 +648,18 @@ def main():
     result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
     if default_line:
         # the metric's other halves on the same line: the fp64-plain step on
-        # the same plate, a 4096^2 plate (1.5 GB, far above the cache) and
-        # the served trace with its latency percentiles
+        # the same plate, a 4096^2 plate (1.5 GB, far above the cache), the
+        # moving-wall plate and the served trace with its latency percentiles
         r64 = time_plate(args, slbm, torch, stream, plate, "fp64", args.steps, args.warmup)
         result["fp64"] = sub_record(r64, args.steps, args.warmup)
         big, _ = workload("square4096")
         steps_big = max(args.steps, 20)
         rbig = time_plate(args, slbm, torch, stream, big, "fp32", steps_big, args.warmup)
         result["square4096"] = sub_record(rbig, steps_big, args.warmup)
+        # curved Dirichlet walls, one of them moving (eq:bbnoncon with j* != 0)
+        mov, _ = workload("movinghole2048")
+        rmov = time_plate(args, slbm, torch, stream, mov, "fp32", args.steps, args.warmup)
+        result["movinghole2048"] = sub_record(rmov, args.steps, args.warmup)
         result["served"], _ = serve_record(args, slbm, torch, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(plate)

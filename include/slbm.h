@@ -55,7 +55,7 @@ typedef enum {
     SLBM_E_INVAL = -1,       /* invalid argument or inconsistent geometry */
     SLBM_E_NOMEM = -2,       /* device or host allocation failed */
     SLBM_E_DEVICE = -3,      /* a HIP call failed */
-    SLBM_E_DIVERGED = -4,    /* a non-finite or huge value appeared */
+    SLBM_E_DIVERGED = -4,    /* a non-finite value, or |drho| + |j| >= rho0 (lattice units), appeared */
     SLBM_E_UNSUPPORTED = -5, /* valid request this build does not handle */
     SLBM_E_BUDGET = -6       /* a batch has no room for the plate */
 } slbm_status;
@@ -130,11 +130,23 @@ int slbm_create(const slbm_params* params, slbm_handle* out);
 int slbm_init_fields(slbm_handle h, const double* rho, const double* vel,
                      const double* sigma, const double* u);
 
-/* Queues nsteps time steps on the handle's stream and returns. */
+/* Queues nsteps time steps on the handle's stream and returns.  One step is
+ * the lattice-Boltzmann equation eq:LBE of section 3 -- moments
+ * (eq:moments), source term (eq:sourceterm), equilibrium (eq:fieq), BGK
+ * collision with forcing (eq:coll), streaming (eq:stream) -- with the rules
+ * of section 4 on the cut links and the displacement advanced by j/rho
+ * (section 2, u obtained by integrating j).  SLBM_E_INVAL for nsteps < 0 or
+ * a plate owned by a batch. */
 int slbm_step(slbm_handle h, int64_t nsteps);
 
 /* Waits for queued work; SLBM_E_DIVERGED once any step produced a value
- * that is not finite (checked on every site at every step). */
+ * that is not finite, or a site whose density deviation and momentum reach
+ * the rest density, |drho| + |j| >= rho0 in lattice units -- far outside
+ * linear elasticity (checked on every site at every step).  The method is
+ * explicit and conditionally stable (section 3 sets tau_bar for stability;
+ * the Neumann rule of section 4 can grow a surface mode on traction-free
+ * walls), so a run can overflow; the flag stays set until slbm_init_fields
+ * or slbm_load. */
 int slbm_sync(slbm_handle h);
 
 /* Moments of the current state in user units, host arrays [n] / [2][n] /
@@ -143,8 +155,11 @@ int slbm_sync(slbm_handle h);
  * read zero.  Synchronises. */
 int slbm_moments(slbm_handle h, double* rho, double* j, double* P, double* sigma);
 
-/* Displacement [2][n] in cells: the integral of j/rho with the trapezoid
- * rule.  Synchronises. */
+/* Displacement [2][n] in cells, host array: u is not a variable of the
+ * lattice-Boltzmann state (section 2: it is obtained by integrating
+ * j = rho du/dt), so the library sums j/rho every step and reads out with
+ * the trapezoid rule, u^n = U^n + j^n/(2 rho^n).  Void sites read zero.
+ * Synchronises. */
 int slbm_displacement(slbm_handle h, double* u);
 
 /* Same as slbm_displacement into device memory u_dev ([2][n] doubles) on
@@ -173,7 +188,9 @@ int slbm_displacement_device_noalloc(slbm_handle h, void* u_dev);
  * valid until the queued work has run.  SLBM_E_INVAL for another dtype. */
 int slbm_moments_device(slbm_handle h, void* rho_dev, void* j_dev, void* P_dev, void* sigma_dev, int dtype);
 
-/* Step count and physical time of the current state. */
+/* Step count and physical time of the current state: t = step * dt with
+ * dt = sqrt(rho/(3 mu)) (section 5.1, c_s = dx/(sqrt(3) dt)); either pointer
+ * may be NULL. */
 int slbm_time(slbm_handle h, int64_t* step, double* t_user);
 
 /* Launch shape of the fused step.  A workgroup advances a tile of seg_rows
@@ -210,14 +227,23 @@ int slbm_get_launch(slbm_handle h, int32_t* seg_rows, int32_t* strip, int32_t* x
  * group.  Synchronises.  The state and step count are unchanged. */
 int slbm_autotune(slbm_handle h, int32_t* seg_rows, int32_t* strip, double* us_per_step);
 
-/* Checkpoint: the full state in an opaque buffer.  With buf = NULL,
- * slbm_save only reports the size in *bytes. */
+/* Checkpoint of the full state of the time stepping of section 3 (the
+ * populations, the displacement sum, the step count and the divergence
+ * flag) in an opaque host buffer the caller owns.  With buf = NULL,
+ * slbm_save only reports the size in *bytes; SLBM_E_INVAL when *bytes is
+ * too small.  slbm_load restores it on a plate of the same size and
+ * precision (SLBM_E_INVAL otherwise), so that stepping on gives results
+ * bit-identical to an uninterrupted run.  Both synchronise. */
 int slbm_save(slbm_handle h, void* buf, size_t* bytes);
 int slbm_load(slbm_handle h, const void* buf, size_t bytes);
 
-/* HBM bytes the handle holds on the device. */
+/* HBM bytes the handle holds on the device (populations, displacement,
+ * geometry, link records and any readout scratch). */
 int slbm_device_bytes(slbm_handle h, int64_t* bytes);
 
+/* Waits for the handle's work and frees its device memory and stream (if
+ * the library created it).  NULL is a no-op; SLBM_E_INVAL for a plate owned
+ * by a batch (slbm_batch_remove frees those). */
 int slbm_destroy(slbm_handle h);
 
 /* ---------------------------------------------------------------- batches

@@ -83,7 +83,8 @@ int slbm3_init_fields(slbm3_handle h, const double* rho, const double* vel, cons
 int slbm3_step(slbm3_handle h, int64_t nsteps);
 
 /* Waits for queued work.  SLBM_E_DIVERGED if a step produced a non-finite
- * value since creation or the last slbm3_init_fields. */
+ * value, or a site with |drho| + |j| >= rho0 (lattice units, far outside
+ * linear elasticity), since creation or the last slbm3_init_fields. */
 int slbm3_sync(slbm3_handle h);
 
 /* Moments of the current state, in user units.  These are the density rho

@@ -20,6 +20,7 @@ HIPCC_FLAGS = [
     # whatever the strip width or rows per tile
     "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
+    "-pthread",          # slbm_create checks large geometries on several host threads
 ]
 
 

@@ -51,6 +51,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "slbm.h"
@@ -887,19 +888,47 @@ int create_impl(const slbm_params* p, slbm_handle* out, Arena* arena = nullptr, 
         if (cut[l.site] & bit) return fail(SLBM_E_INVAL, "link %d: duplicate", i);
         cut[l.site] |= bit;
     }
-    for (int s = 0; s < n; ++s) {
-        if (!mat[s]) continue;
-        if (cut[s] == 0xFF) return fail(SLBM_E_INVAL, "site %d: every link is cut", s);
+    // every uncut link of a material site must end at a material site whose
+    // opposite link is uncut too: checked in parallel over contiguous site
+    // ranges (a large plate has hundreds of millions of links); the error
+    // reported is the one at the lowest site, as a sequential scan finds it
+    auto check_site = [&](int s, int& kbad) -> int {
+        kbad = 0;
+        if (!mat[s]) return 0;
+        if (cut[s] == 0xFF) return 1;
         const int x = s % nx, y = s / nx;
         for (int k = 1; k <= 8; ++k) {
             if (cut[s] & (1u << (k - 1))) continue;
             int tx = x + CX(k), ty = y + CY(k);
             if (p->periodic_x) tx = (tx + nx) % nx;
             if (p->periodic_y) ty = (ty + ny) % ny;
-            if (tx < 0 || tx >= nx || ty < 0 || ty >= ny || !mat[ty * nx + tx])
-                return fail(SLBM_E_INVAL, "site (%d,%d): uncut link %d leaves the material", x, y, k);
-            if (cut[ty * nx + tx] & (1u << (OPP(k) - 1)))
-                return fail(SLBM_E_INVAL, "site (%d,%d): link %d is cut from one end only", x, y, k);
+            kbad = k;
+            if (tx < 0 || tx >= nx || ty < 0 || ty >= ny || !mat[ty * nx + tx]) return 2;
+            if (cut[ty * nx + tx] & (1u << (OPP(k) - 1))) return 3;
+        }
+        return 0;
+    };
+    {
+        const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const int parts = n >= (1 << 16) ? nthreads : 1;
+        std::vector<int> first(parts, n);
+        auto scan = [&](int part) {
+            const int s0 = (int)((int64_t)n * part / parts), s1 = (int)((int64_t)n * (part + 1) / parts);
+            int kb;
+            for (int s = s0; s < s1; ++s)
+                if (check_site(s, kb)) { first[part] = s; return; }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < parts; ++t) pool.emplace_back(scan, t);
+        scan(0);
+        for (std::thread& t : pool) t.join();
+        const int s = *std::min_element(first.begin(), first.end());
+        if (s < n) {
+            int k = 0;
+            const int why = check_site(s, k);
+            if (why == 1) return fail(SLBM_E_INVAL, "site %d: every link is cut", s);
+            if (why == 2) return fail(SLBM_E_INVAL, "site (%d,%d): uncut link %d leaves the material", s % nx, s / nx, k);
+            return fail(SLBM_E_INVAL, "site (%d,%d): link %d is cut from one end only", s % nx, s / nx, k);
         }
     }
     std::sort(L.begin(), L.end(), [](const slbm_link& a, const slbm_link& b) {
@@ -1141,7 +1170,9 @@ int slbm_sync(slbm_handle h)
         unsigned int flag = 0;
         HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        if (flag) return fail(SLBM_E_DIVERGED, "a non-finite value appeared by step %lld", (long long)h->step);
+        if (flag)
+            return fail(SLBM_E_DIVERGED, "the state diverged (a value not finite or beyond the rest density) by step %lld",
+                        (long long)h->step);
         return SLBM_OK;
     });
 }

@@ -27,6 +27,11 @@ namespace slbm3_dev {
 // (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1); (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).
 // Opposite directions are adjacent: opp(i) = i + 1 for odd i.
 constexpr int kQ = 19;
+
+// A site update is flagged as diverged when |drho| + |j| (lattice units,
+// rest density 1) reaches this bound -- a density deviation as large as the
+// rest density itself, far outside linear elasticity -- or is not finite.
+constexpr double kDivergeBound = 1.0;
 constexpr int kCX[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int kCY[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int kCZ[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
     // eq:coll in ghost-moment form (exact conserved moments)
     real o[kQ];
     collide_ghost3(g, dr, j, P, S, a.omega, a.omega_h, o);
-    const bool bad = !(fabs(dr) + fabs(j[0]) + fabs(j[1]) + fabs(j[2]) < real(1e30));
+    const bool bad = !(fabs(dr) + fabs(j[0]) + fabs(j[1]) + fabs(j[2]) < real(kDivergeBound));
     if (st.in) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) a.dst[i * a.stride + s] = o[i];

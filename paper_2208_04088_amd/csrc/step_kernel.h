@@ -32,6 +32,12 @@ constexpr int kPadL = 64;      // padding columns left of the grid: keeps wide s
 template <bool WIDE> constexpr int strip_width() { return WIDE ? 64 : 62; }
 constexpr unsigned kVoid = 0xFFu;
 
+// A site update is flagged as diverged when |drho| + |j| (lattice units,
+// rest density 1) reaches this bound -- a density deviation as large as the
+// rest density itself, far outside linear elasticity -- or is not finite.
+// An unstable mode is caught long before it overflows.
+constexpr double kDivergeBound = 1.0;
+
 struct GroupDev {
     int32_t profile;           // SLBM_PROFILE_*
     int32_t pad;
@@ -463,7 +469,7 @@ __device__ __forceinline__ bool collide_core(const StepArgs<real>& a, const real
     jx_out = jx;
     jy_out = jy;
     ir_out = ir;
-    return !(fabs(dr) + fabs(jx) + fabs(jy) < real(1e30));
+    return !(fabs(dr) + fabs(jx) + fabs(jy) < real(kDivergeBound));
 }
 
 // displacement: U += j/rho, the increment in the populations' precision

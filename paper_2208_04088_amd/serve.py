@@ -82,12 +82,13 @@ class Server:
     """Continuous batching under an HBM budget (bytes).
 
     chunk: steps per round (the least, with round_ms); round_ms: target GPU
-    time of a round, from the resident sites; timing_stream: a torch stream
-    (the batch's) on which to time the rounds, for the GPU-busy fraction."""
+    time of a round, from the resident sites; depth: rounds queued on the
+    device at most; timing_stream: a torch stream (the batch's) on which to
+    time the rounds, for the GPU-busy fraction."""
 
     def __init__(self, budget_bytes: int, precision: str = "fp32", chunk: int = 64, device: int = 0,
                  stream=None, launch=None, max_resident_sites: Optional[int] = None, policy: str = "fcfs",
-                 xcd_group: int = 0, round_ms: Optional[float] = None, timing_stream=None):
+                 xcd_group: int = 0, round_ms: Optional[float] = None, timing_stream=None, depth: int = 3):
         self.batch = slbm.Batch(budget_bytes, device=device, stream=stream)
         self.precision = precision
         self.chunk = int(chunk)
@@ -99,6 +100,7 @@ class Server:
         self.peak_bytes = 0
         self.peak_resident = 0
         self.timing_stream = timing_stream
+        self.depth = max(1, int(depth))
         self.gpu_busy_s = None
         self.gpu_span_s = None
         self.rounds = 0
@@ -171,10 +173,11 @@ class Server:
                     e1.record(self.timing_stream)
                     events.append((e0, e1))
                 self.rounds += 1
-            # at most two rounds in flight: the device always has the next one
-            # queued, and the host never runs far ahead of what it has seen
-            # (plates found diverged are retired within a few rounds)
-            self.batch.wait(1)
+            # at most `depth` rounds in flight: the device has the next ones
+            # queued while the host admits and reads out, and the host never
+            # runs far ahead of what it has seen (plates found diverged are
+            # retired within a few rounds)
+            self.batch.wait(self.depth - 1)
             # results of the plates whose steps were all queued before this round
             for slot, (i, adm) in list(finishing.items()):
                 r = reqs[i]

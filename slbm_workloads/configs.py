@@ -83,6 +83,25 @@ def hole_plate(n: int = 2048, R: float = 256.0, *, mu: float = 0.05, lam: float 
                        neumann_order=neumann_order)
 
 
+def moving_hole_plate(n: int = 2048, *, mu: float = 0.05, lam: float = 0.04, tau: float = 0.55,
+                      wall_speed=(1e-4, -2e-4), ramp_steps: int = 2000, force=(1e-6, -2e-6),
+                      steps: int = 20000) -> Plate:
+    """Periodic n x n plate (no edges) with two holes, both curved Dirichlet
+    walls: one held fixed (u* = 0, radius 0.18 n, centred at (0.45 n,
+    0.55 n)) against which a uniform body force presses the material, and a
+    smaller one (radius 0.1 n, at (0.8 n, 0.25 n)) whose wall moves with a
+    velocity ramped from zero over ramp_steps steps and then held, so that
+    its links carry j* = rho du*/dt != 0 (the paper's curved Dirichlet rule,
+    section 4.2).  No wall is traction-free, so the plate stays stable."""
+    dt = math.sqrt(1.0 / (3.0 * mu))
+    groups = [BCGroup(DIRICHLET, (0.0, 0.0)),
+              BCGroup(DIRICHLET, tuple(wall_speed), PROFILE_RAMP, ramp_steps * dt)]
+    walls = [Circle(n * 0.45, n * 0.55, n * 0.18, 0), Circle(n * 0.8, n * 0.25, n * 0.1, 1)]
+    return build_plate(n, n, lam=lam, mu=mu, tau=tau, walls=walls, groups=groups, force=tuple(force),
+                       periodic_x=True, periodic_y=True, name=f"movinghole{n}", steps=steps,
+                       neumann_order=0)
+
+
 # ----------------------------------------------------------- paper scale --
 
 def paper_hole_plate(c2_ratio: float = 3.0, *, n: int = 80, mu: float = 1.0,

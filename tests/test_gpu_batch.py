@@ -58,6 +58,31 @@ def alone(slbm, plate, steps, prec):
     return s.displacement(), s.moments()[3]
 
 
+def diverged(slbm, solver):
+    """Whether the plate's state diverged (SLBM_E_DIVERGED at sync)."""
+    try:
+        solver.sync()
+        return False
+    except slbm.SlbmError as e:
+        assert e.code == -4
+        return True
+
+
+def check_like_alone(slbm, plate, steps, prec, solver, u=None):
+    """A batch plate's result against the same plate stepped alone: bit for
+    bit while it stays finite; a plate whose state diverges (the random
+    plates draw lambda/mu up to 2, whose free walls grow a surface mode) is
+    flagged in both, its arithmetic stopped in the batch."""
+    s = slbm.Solver(plate, prec)
+    s.step(steps)
+    if diverged(slbm, solver):
+        assert diverged(slbm, s), plate.name
+        return False
+    assert not diverged(slbm, s), plate.name
+    assert np.array_equal(solver.displacement() if u is None else u, s.displacement()), plate.name
+    return True
+
+
 @pytest.mark.parametrize("launch", [None, (6, 58)])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_batched_plates_match_their_solo_runs(slbm, prec, launch):
@@ -73,14 +98,16 @@ def test_batched_plates_match_their_solo_runs(slbm, prec, launch):
         b.step(k)
     b.sync()
     assert sorted(b.poll()) == sorted(slots)
+    finite = 0
     for p, n, sl in zip(plates, steps, slots):
         s = b.solver(sl)
-        assert s.time()[0] == n
-        s.sync()
-        u_ref, sig_ref = alone(slbm, p, n, prec)
-        assert np.array_equal(s.displacement(), u_ref), p.name
-        assert np.array_equal(b.displacement(sl), u_ref), p.name
-        assert np.array_equal(s.moments()[3], sig_ref), p.name
+        assert s.time()[0] == n or diverged(slbm, s)
+        if check_like_alone(slbm, p, n, prec, s):
+            finite += 1
+            u_ref, sig_ref = alone(slbm, p, n, prec)
+            assert np.array_equal(b.displacement(sl), u_ref), p.name
+            assert np.array_equal(s.moments()[3], sig_ref), p.name
+    assert finite >= 4
     b.close()
 
 
@@ -116,7 +143,8 @@ def test_batch_autotune_takes_real_steps(slbm):
     """slbm_batch_autotune times launch shapes with real steps: the plates
     advance by them, and their state equals the same number of steps taken
     alone; the shape it keeps is reported."""
-    plates = oracle_plates(7, 6)[:5]             # lambda/mu <= 1: none diverges and is retired
+    # lambda/mu <= 1 and the boundary-site Neumann rule: none diverges and is retired
+    plates = [dataclasses.replace(p, neumann_order=0) for p in oracle_plates(7, 6)[:5]]
     b = slbm.Batch(8 << 30)
     slots = [b.add(p, 600, "fp32") for p in plates]
     rows, strip, group, us = b.autotune(600)
@@ -126,8 +154,7 @@ def test_batch_autotune_takes_real_steps(slbm):
     assert len(set(taken)) == 1 and 0 < taken[0] <= 600
     b.step(33)
     for p, sl in zip(plates, slots):
-        u_ref, _ = alone(slbm, p, taken[0] + 33, "fp32")
-        assert np.array_equal(b.solver(sl).displacement(), u_ref, equal_nan=True), p.name
+        assert check_like_alone(slbm, p, taken[0] + 33, "fp32", b.solver(sl)), p.name
     b.close()
 
 
@@ -170,20 +197,24 @@ def test_continuous_batching_joins_and_leaves(slbm, launch):
         for sl in b.poll():
             i = live.pop(sl)
             s = b.solver(sl)
-            finished[i] = (s.time()[0], b.displacement(sl))
+            finished[i] = (s.time()[0], b.displacement(sl), diverged(slbm, s))
             b.remove(sl)
     assert sorted(finished) == list(range(6))
-    for i, (n, u) in finished.items():
-        assert n == want[i]
-        u_ref, _ = alone(slbm, plates[i], want[i], "fp32")
-        assert np.array_equal(u, u_ref), plates[i].name
+    for i, (n, u, div) in finished.items():
+        s = slbm.Solver(plates[i], "fp32")
+        s.step(want[i])
+        assert div == diverged(slbm, s), plates[i].name
+        if not div:
+            assert n == want[i]
+            assert np.array_equal(u, s.displacement()), plates[i].name
     b.sync()                         # the removed plates' memory is reusable once their work has run
     assert b.bytes()[0] == 0
     b.close()
 
 
 def test_batch_launch_shape_does_not_change_results(slbm):
-    plates = small_plates(9, 4)
+    # lambda/mu <= 1 and the boundary-site Neumann rule: every plate stays finite
+    plates = [dataclasses.replace(p, neumann_order=0) for p in oracle_plates(9, 5)[:4]]
     ref = None
     for rows, strip, group in ((2, 62, 0), (8, 64, 0), (5, 62, 0), (14, 64, 0), (14, 62, 0), (1, 58, 0),
                                (6, 58, 0), (10, 58, 0), (5, 62, 8), (6, 58, 8), (10, 58, 64), (3, 64, 2)):
@@ -226,7 +257,9 @@ def test_batch_divergence_is_per_plate(slbm):
     bad = G.build_plate(n, n, lam=0.1, mu=0.05, tau=0.6, walls=G.edge_walls(n, n, 0, 0, 1, 1),
                         groups=[G.BCGroup(G.NEUMANN, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (0.0, 1e-4))],
                         neumann_order=1, name="unstable")
-    good = small_plates(13, 1)[0]
+    # straight walls only, lambda = mu, boundary-site rule: stays finite over
+    # thousands of steps (curved traction-free walls with small q grow slowly)
+    good = configs.square_clamped_pulled(48)
     b = slbm.Batch(8 << 30)
     sb = b.add(bad, 20000, "fp32")
     sg = b.add(good, 4000, "fp32")

@@ -183,6 +183,20 @@ def test_square_config_fp64_full_length(slbm):
     print(f"square128 fp64 {p.steps} steps: rel L2 u = {e:.3e}")
 
 
+@pytest.mark.slow
+def test_square_config_fp64_10k_steps(slbm):
+    """The fp64 path over 10^4 steps of the 128 x 128 plate: displacement and
+    moments within 1e-12 of the extended-precision reference."""
+    p = configs.square_clamped_pulled(steps=10000)
+    ref = Oracle(p, extended=True)
+    ref.step(p.steps)
+    s = slbm.Solver(p, "fp64")
+    s.step(p.steps)
+    s.sync()
+    e = compare(s, ref, "fp64")
+    print(f"square128 fp64 {p.steps} steps: rel L2 u = {e:.3e}")
+
+
 def test_square_config_fp32_10k_steps(slbm):
     """Same plate in fp32 for 10k steps: displacement within 1e-4 relative L2."""
     p = configs.square_clamped_pulled(steps=10000)
@@ -429,6 +443,25 @@ def test_hole_config_full_size(slbm, lam, tau, steps):
     e = rel_l2(s.displacement(), ref.displacement())
     print(f"hole2048 lam/mu={lam / 0.05:g} fp32 {steps} steps: rel L2 u = {e:.3e}")
     assert e <= FP32_TOL
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_moving_hole_plate_full_size(slbm, prec):
+    """The 2048 x 2048 periodic plate with a fixed and a moving curved
+    Dirichlet hole (the benchmark's workload for eq:bbnoncon with j* != 0),
+    at full size in the two-step shape with XCD groups, 120 steps into the
+    wall's ramp: displacement and moments against the reference."""
+    p = configs.moving_hole_plate(steps=120, ramp_steps=60)
+    s = slbm.Solver(p, prec)
+    s.set_launch(10, 58)
+    s.set_xcd_group(8)
+    s.step(p.steps)
+    s.sync()
+    ref = Oracle(p, extended=(prec == "fp64"))
+    ref.step(p.steps)
+    e = compare(s, ref, prec)
+    print(f"movinghole2048 {prec} {p.steps} steps: rel L2 u = {e:.3e}")
 
 
 @pytest.mark.slow
