@@ -336,10 +336,11 @@ int slbm_batch_get_launch(slbm_batch b, int32_t* rows, int32_t* strip, int32_t* 
  * shapes (two steps per launch at 4, 6, 8 and 10 rows, one step at 6, 10 and
  * 14 rows), then the best with XCD groups of 8 (kept when 1 % faster), each
  * over 32 steps after 32 that rebuild its tables and graph, while budget
- * steps last.  The trial steps are real: every plate advances by them (at
- * most its remaining steps), exactly as it would in any shape.  Keeps and
- * reports the fastest shape and its time per step of the whole batch in
- * microseconds (any pointer may be NULL).  Synchronises. */
+ * steps last, comparing the time per material-site update of the plates
+ * running in the timed steps.  The trial steps are real: every plate advances
+ * by them (at most its remaining steps), exactly as it would in any shape.
+ * Keeps and reports the fastest shape and its time per step of the whole
+ * batch in microseconds (any pointer may be NULL).  Synchronises. */
 int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows, int32_t* strip, int32_t* xcd_group,
                         double* us_per_step);
 

@@ -635,7 +635,10 @@ int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows_out, int3
         int64_t spent = 0;
         Shape best{b->rows, b->two ? kStrip2 : (b->wide ? 64 : 62), b->group};
         double best_us = 0;
-        auto trial = [&](const Shape& s, double& us) -> int {
+        // shapes are compared by time per material-site update of the plates
+        // running in the timed chunk: plates retired during the trials
+        // (diverged, or done) would otherwise favour the later candidates
+        auto trial = [&](const Shape& s, double& us, double& per_site) -> int {
             b->rows = s.rows;
             b->two = s.strip == kStrip2 ? 1 : 0;
             b->wide = s.strip == 64 ? 1 : 0;
@@ -643,6 +646,10 @@ int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows_out, int3
             b->dirty = true;
             int rc = batch_run_any(b, kChunk);
             if (rc) return rc;
+            batch_harvest(b, 0);
+            double sites = 0;
+            for (size_t k = 0; k < b->slot.size(); ++k)
+                if (b->slot[k] && b->remaining[k] >= kChunk) sites += (double)b->slot[k]->n_material;
             HIP_TRY(hipEventRecord(e0, b->stream));
             if ((rc = batch_run_any(b, kChunk))) return rc;
             HIP_TRY(hipEventRecord(e1, b->stream));
@@ -651,6 +658,7 @@ int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows_out, int3
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             spent += per_trial;
             us = 1e3 * ms / kChunk;
+            per_site = sites > 0 ? us / sites : us;
             return SLBM_OK;
         };
         auto running = [&]() {
@@ -660,18 +668,19 @@ int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows_out, int3
         };
         int rc = SLBM_OK;
         bool any = false;
+        double best_site = 0;
         for (const Shape& s : cand) {
             if (spent + per_trial > max_steps || !running()) break;
-            double us = 0;
-            if ((rc = trial(s, us))) break;
-            if (!any || us < best_us) { best = s; best_us = us; any = true; }
+            double us = 0, site = 0;
+            if ((rc = trial(s, us, site))) break;
+            if (!any || site < best_site) { best = s; best_us = us; best_site = site; any = true; }
         }
         // the best shape with interleaved XCD groups of 8, kept when at least 1 % faster
         if (!rc && any && spent + per_trial <= max_steps && running()) {
-            double us = 0;
+            double us = 0, site = 0;
             Shape g = best;
             g.group = 8;
-            if (!(rc = trial(g, us)) && us < 0.99 * best_us) {
+            if (!(rc = trial(g, us, site)) && site < 0.99 * best_site) {
                 best = g;
                 best_us = us;
             }

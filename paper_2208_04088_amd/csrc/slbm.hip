@@ -476,6 +476,7 @@ struct slbm_s {
     bool ext_flag = false;
     hipEvent_t ready = nullptr;
     uint64_t batch_id = 0;
+    int64_t n_material = 0;
     int n_links = 0;
     int64_t step = 0;
     bool local = true;
@@ -963,6 +964,7 @@ int create_impl(const slbm_params* p, slbm_handle* out, Arena* arena = nullptr, 
     h->n_links = p->n_links;
     h->mask = mat;
     h->arena = arena;
+    for (int s = 0; s < n; ++s) h->n_material += mat[s];
 
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
