@@ -201,8 +201,21 @@ int slbm_time(slbm_handle h, int64_t* step, double* t_user);
  * the state is read and written once per two steps (seg_rows + 6 waves per
  * tile, 58 output columns; an odd step count ends with one single step).
  * seg_rows is at most 14 (10 with strip 58); 0 keeps the library's choice.
- * SLBM_E_INVAL beyond the limits.  Results do not depend on the shape. */
+ * With strip 58 the library also lists, per tile, the plate's cut links in
+ * the tile's reach (slbm_boundary_lists), so that the tile evaluates the
+ * section 4 rules of all of them together; it allocates device memory for
+ * the lists (SLBM_E_NOMEM if none is left).  SLBM_E_INVAL beyond the limits.
+ * Results do not depend on the shape. */
 int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
+
+/* The per-tile cut-link lists of the two-steps-per-launch step (strip 58):
+ * the rows per tile they were built for (0: none, and the step evaluates the
+ * boundary rules of section 4 site by site), the records in all lists, and
+ * the most in one tile.  Lists are kept only when every tile's fits the
+ * tile's LDS (384 records) and the plate has at most 64 BC groups; a cut
+ * link appears in every tile whose rows and columns, halo included, reach
+ * its site.  Any pointer may be NULL. */
+int slbm_boundary_lists(slbm_handle h, int32_t* rows, int64_t* records, int32_t* max_per_tile);
 
 /* How the step's workgroups are dealt to the GPU's 8 XCDs: 0 (the default)
  * gives each XCD one contiguous band of tiles; group g, a power of two up to

@@ -485,6 +485,20 @@ struct slbm_s {
     int two = 0;                     // 1: two steps per launch (58-column strips, seg rows <= 10)
     int group = 0;                   // workgroups to XCDs: 0 contiguous bands, g > 0 interleaved groups of g
     std::vector<uint8_t> mask;
+    // per-tile cut-link records of the two-step kernel (build_tile_records):
+    // the link records as uploaded and each link's site, the lists on the
+    // device for tiles of rec_seg rows, rec_fit when every tile's fits the
+    // cooperative kernel
+    std::vector<char> link_host;
+    std::vector<int32_t> link_site;
+    int ngroups = 0;
+    int32_t* rec_start = nullptr;
+    void* recs = nullptr;
+    int rec_seg = 0;
+    bool rec_fit = false;
+    int64_t rec_bytes = 0;
+    int64_t rec_count = 0;
+    int32_t rec_max = 0;
 };
 
 namespace {
@@ -522,6 +536,7 @@ StepArgs<real> make_args(const slbm_s* h, int src)
     a.bidx = h->bidx;
     a.links = (const LinkDev<real>*)h->links;
     a.groups = h->groups;
+    a.ngroups = h->ngroups;
     a.diverged = h->diverged;
     a.plane = h->plane;
     a.t_prev = h->step - 1;
@@ -585,16 +600,137 @@ int launch_step_raw(slbm_s* h, int seg, int wide)
     return SLBM_OK;
 }
 
+// Rows per tile of the two-step kernel for a requested number (0: default).
+int seg2_rows(int seg) { return std::max(1, std::min(seg > 0 ? seg : 6, kMaxTileRows2)); }
+
+void drop_tile_records(slbm_s* h)
+{
+    if (h->rec_start) (void)hipFree(h->rec_start);
+    if (h->recs) (void)hipFree(h->recs);
+    h->rec_start = nullptr;
+    h->recs = nullptr;
+    h->rec_seg = 0;
+    h->rec_fit = false;
+    h->rec_bytes = 0;
+    h->rec_count = 0;
+    h->rec_max = 0;
+}
+
+// Coordinates c + m n (any m on a periodic axis, m = 0 otherwise) in [lo, hi]:
+// where a site of that coordinate sits in the tiles' footprints, which on a
+// periodic axis reach past the grid and wrap.
+template <class F>
+void axis_images(int c, int n, bool per, int lo, int hi, F&& f)
+{
+    if (!per) {
+        if (c >= lo && c <= hi) f(c);
+        return;
+    }
+    long long v = c - (long long)n * ((c - lo + n - 1) / n);   // the smallest image >= lo (c >= 0 > lo - n)
+    if (v < lo) v += n;
+    for (; v <= hi; v += n) f((int)v);
+}
+
+long long floor_div(long long a, long long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// The cut links each tile of the two-step kernel (seg rows, 58-column strips)
+// sees in its footprint -- rows y0 - 3 .. y0 + seg + 2, columns xs - 3 ..
+// xs + 60, wave w and lane l at y0 - 3 + w, xs - 3 + l -- each a copy of the
+// link's record with its position (w << 8 | l).  Tile t's records are
+// recs[rec_start[t] .. rec_start[t + 1]).  When a tile has more than the
+// cooperative kernel takes (or the plate more groups than it tabulates), no
+// lists are kept and the two-step kernel takes the rules site by site.
+template <typename real>
+int build_tile_records(slbm_s* h, int seg)
+{
+    seg = seg2_rows(seg);
+    if (h->rec_seg == seg) return SLBM_OK;
+    drop_tile_records(h);
+    h->rec_seg = seg;
+    if (h->n_links == 0 || h->ngroups > kTileGroupCap) return SLBM_OK;
+    const int R = seg, nx = h->nx, ny = h->ny;
+    const int nstrips = (nx + kStrip2 - 1) / kStrip2, ntr = (ny + R - 1) / R;
+    const long long ntiles = (long long)nstrips * ntr;
+    const LinkDev<real>* L = reinterpret_cast<const LinkDev<real>*>(h->link_host.data());
+    auto each = [&](auto&& f) {
+        for (int i = 0; i < h->n_links; ++i) {
+            const int site = h->link_site[i], x = site % nx, y = site / nx;
+            axis_images(y, ny, h->py != 0, -3, ntr * R + 2, [&](int yh) {
+                const long long tr0 = std::max<long long>(0, -floor_div(-(yh - R - 2), R));
+                const long long tr1 = std::min<long long>(ntr - 1, floor_div(yh + 3, R));
+                for (long long tr = tr0; tr <= tr1; ++tr) {
+                    const int w = yh - (int)(tr * R - 3);
+                    axis_images(x, nx, h->px != 0, -3, nstrips * kStrip2 + 2, [&](int xh) {
+                        const long long s0 = std::max<long long>(0, -floor_div(-(xh - 60), kStrip2));
+                        const long long s1 = std::min<long long>(nstrips - 1, floor_div(xh + 3, kStrip2));
+                        for (long long st = s0; st <= s1; ++st)
+                            f(st + tr * nstrips, w, xh - (int)(st * kStrip2 - 3), i);
+                    });
+                }
+            });
+        }
+    };
+    std::vector<int32_t> start((size_t)ntiles + 1, 0);
+    each([&](long long t, int, int, int) { ++start[(size_t)t + 1]; });
+    int32_t most = 0;
+    for (long long t = 0; t < ntiles; ++t) most = std::max(most, start[(size_t)t + 1]);
+    if (most > kTileRecCap) return SLBM_OK;
+    for (long long t = 0; t < ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
+    const size_t total = (size_t)start[(size_t)ntiles];
+    std::vector<LinkDev<real>> rec(total);
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    each([&](long long t, int w, int l, int i) {
+        LinkDev<real>& r = rec[(size_t)fill[(size_t)t]++];
+        r = L[i];
+        r.pos = (w << 8) | l;
+    });
+    hipError_t e = hipMalloc((void**)&h->rec_start, start.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&h->recs, std::max<size_t>(1, total) * sizeof(LinkDev<real>));
+    if (e != hipSuccess) {
+        drop_tile_records(h);
+        if (e == hipErrorOutOfMemory) return fail(SLBM_E_NOMEM, "no device memory for the tile record lists");
+        HIP_TRY(e);
+    }
+    HIP_TRY(hipMemcpyAsync(h->rec_start, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           h->stream));
+    if (total)
+        HIP_TRY(hipMemcpyAsync(h->recs, rec.data(), total * sizeof(LinkDev<real>), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->rec_fit = true;
+    h->rec_bytes = (int64_t)(start.size() * sizeof(int32_t) + total * sizeof(LinkDev<real>));
+    h->rec_count = (int64_t)total;
+    h->rec_max = most;
+    return SLBM_OK;
+}
+
+int tile_records(slbm_s* h, int seg)
+{
+    return h->precision == SLBM_FP32 ? build_tile_records<float>(h, seg) : build_tile_records<double>(h, seg);
+}
+
 // Arguments of the two-steps-per-launch kernel: 58-column strips, at most
 // kMaxTileRows2 rows per tile.
 template <typename real>
 StepArgs<real> make_args2(const slbm_s* h, int src, int seg)
 {
     StepArgs<real> a = make_args<real>(h, src);
-    a.seg = std::max(1, std::min(seg > 0 ? seg : 6, kMaxTileRows2));
+    a.seg = seg2_rows(seg);
     a.nstrips = (h->nx + kStrip2 - 1) / kStrip2;
     a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
+    if (h->rec_fit && h->rec_seg == a.seg) {
+        a.rec_start = h->rec_start;
+        a.recs = (const LinkDev<real>*)h->recs;
+    }
     return a;
+}
+
+template <typename real, bool PER, int W>
+void dispatch_step2_w(const slbm_s* h, const StepArgs<real>& a, int grid, dim3 blk)
+{
+    if (a.rec_start)
+        hipLaunchKernelGGL((k_step2<real, PER, W, true>), dim3(grid), blk, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((k_step2<real, PER, W, false>), dim3(grid), blk, 0, h->stream, a);
 }
 
 template <typename real>
@@ -606,14 +742,14 @@ void dispatch_step2(const slbm_s* h, const StepArgs<real>& a)
     const bool per = h->px || h->py;
     if (k2_waves<real>(a.seg) == hi) {
         if (per)
-            hipLaunchKernelGGL((k_step2<real, true, hi>), dim3(grid), blk, 0, h->stream, a);
+            dispatch_step2_w<real, true, hi>(h, a, grid, blk);
         else
-            hipLaunchKernelGGL((k_step2<real, false, hi>), dim3(grid), blk, 0, h->stream, a);
+            dispatch_step2_w<real, false, hi>(h, a, grid, blk);
     } else {
         if (per)
-            hipLaunchKernelGGL((k_step2<real, true, lo>), dim3(grid), blk, 0, h->stream, a);
+            dispatch_step2_w<real, true, lo>(h, a, grid, blk);
         else
-            hipLaunchKernelGGL((k_step2<real, false, lo>), dim3(grid), blk, 0, h->stream, a);
+            dispatch_step2_w<real, false, lo>(h, a, grid, blk);
     }
 }
 
@@ -834,6 +970,9 @@ int upload_links(slbm_s* h, const std::vector<slbm_link>& L, const std::vector<u
         fill_link(d[i], l, behind, p, h);
     }
     (void)n;
+    h->link_host.assign(reinterpret_cast<const char*>(d.data()), reinterpret_cast<const char*>(d.data() + d.size()));
+    h->link_site.resize(L.size());
+    for (size_t i = 0; i < L.size(); ++i) h->link_site[i] = L[i].site;
     if (!d.empty()) {
         const hipError_t e = dev_alloc(h, &h->links, d.size() * sizeof(LinkDev<real>));
         if (e == hipErrorOutOfMemory) return fail(SLBM_E_NOMEM, "no device memory for the link records");
@@ -962,6 +1101,7 @@ int create_impl(const slbm_params* p, slbm_handle* out, Arena* arena = nullptr, 
     h->FL[1] = p->body_force[1] / h->s_sigma;
     h->esize = p->precision == SLBM_FP32 ? 4 : 8;
     h->n_links = p->n_links;
+    h->ngroups = p->n_groups;
     h->mask = mat;
     h->arena = arena;
     for (int s = 0; s < n; ++s) h->n_material += mat[s];
@@ -1135,6 +1275,7 @@ int slbm_destroy(slbm_handle h)
         if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch: remove it with slbm_batch_remove");
         DeviceGuard dg(h->device);
         if (h->stream) (void)hipStreamSynchronize(h->stream);
+        drop_tile_records(h);
         free_all(h);
         delete h;
         return SLBM_OK;
@@ -1367,6 +1508,11 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip)
             return fail(SLBM_E_INVAL, "strip must be 0, 58, 62 or 64");
         if (seg_rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
             return fail(SLBM_E_INVAL, "rows per tile above the maximum (14; 10 with two steps per launch)");
+        if (strip == kStrip2) {
+            DeviceGuard dg(h->device);
+            const int rc = tile_records(h, seg_rows);
+            if (rc) return rc;
+        }
         h->seg = seg_rows;
         h->two = strip == kStrip2 ? 1 : 0;
         h->wide = (strip == 0 || strip == kStrip2) ? -1 : (strip == 64 ? 1 : 0);
@@ -1381,6 +1527,17 @@ int slbm_set_xcd_group(slbm_handle h, int32_t group)
         if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         if (!valid_group(group)) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or a power of two up to 64");
         h->group = group;
+        return SLBM_OK;
+    });
+}
+
+int slbm_boundary_lists(slbm_handle h, int32_t* rows, int64_t* records, int32_t* max_per_tile)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(SLBM_E_INVAL, "null handle");
+        if (rows) *rows = h->rec_fit ? h->rec_seg : 0;
+        if (records) *records = h->rec_fit ? h->rec_count : 0;
+        if (max_per_tile) *max_per_tile = h->rec_fit ? h->rec_max : 0;
         return SLBM_OK;
     });
 }
@@ -1421,6 +1578,10 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
         // rereads the same state, and U is put back after every burst
         auto time_shape = [&](int c, int wv, double& us) -> int {
             const int burst = wv == 2 ? 3 : 6;
+            if (wv == 2) {
+                const int rc2 = tile_records(h, c);
+                if (rc2) return rc2;
+            }
             std::vector<float> t;
             for (int r = 0; r < 3; ++r) {
                 HIP_TRY(hipEventRecord(e0, h->stream));
@@ -1472,6 +1633,7 @@ int slbm_autotune(slbm_handle h, int32_t* seg_out, int32_t* strip_out, double* u
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         release_transient_scratch(h);
+        if (best_w == 2 && (rc = tile_records(h, best))) return rc;
         h->seg = best;
         h->two = best_w == 2 ? 1 : 0;
         h->wide = best_w == 2 ? -1 : best_w;
@@ -1488,6 +1650,7 @@ int slbm_device_bytes(slbm_handle h, int64_t* bytes)
         if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
         int64_t b = 2 * (int64_t)9 * h->plane * (int64_t)h->esize + 2 * h->plane * 8 + h->plane * 5;
         b += (int64_t)h->n_links * (h->esize == 4 ? (int64_t)sizeof(LinkDev<float>) : (int64_t)sizeof(LinkDev<double>));
+        b += h->rec_bytes;
         if (h->scratch) b += (int64_t)h->scratch_planes * h->plane * 8;
         *bytes = b;
         return SLBM_OK;

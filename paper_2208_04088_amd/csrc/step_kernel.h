@@ -55,7 +55,8 @@ struct LinkDev {
     int32_t g1, g2;            // groups whose profiles scale D or K1, K2
     int32_t kind;              // SLBM_DIRICHLET | SLBM_NEUMANN
     int32_t behind;            // 1: x - c_k is a material site reached by an uncut link
-    int32_t k, dx, dy, pad;
+    int32_t k, dx, dy;
+    int32_t pos;               // in a tile's record list: the site's wave << 8 | lane in the tile
 };
 
 template <typename real>
@@ -68,11 +69,16 @@ struct StepArgs {
     const LinkDev<real>* links;
     const GroupDev* groups;
     unsigned int* diverged;
+    // cut links per tile of the two-step kernel (null: none built for this
+    // launch shape): tile t's are recs[rec_start[t] .. rec_start[t + 1])
+    const int32_t* rec_start;
+    const LinkDev<real>* recs;
     long long plane;           // ny * ld
     long long t_prev;          // step whose post-collision state src holds
     int nx, ny, ld;
     int seg, nstrips, ntiles;
     int px, py;
+    int ngroups;               // entries of groups
     int local;                 // src holds the populations themselves
     int group_shift;           // workgroups to XCDs: -1 contiguous bands, s >= 0 interleaved groups of 2^s
     real omega;                // 1/tau
@@ -81,14 +87,19 @@ struct StepArgs {
 };
 
 template <typename real>
-__device__ __forceinline__ real profile_at(const GroupDev* g, int gi, long long t)
+__device__ __forceinline__ real profile_of(const GroupDev& G, long long t)
 {
-    const GroupDev G = g[gi];
     if (G.profile == SLBM_PROFILE_RAMP) {
         real r = real((double)t / G.ramp_steps);
         return r < real(1) ? r : real(1);
     }
     return real(1);
+}
+
+template <typename real>
+__device__ __forceinline__ real profile_at(const GroupDev* g, int gi, long long t)
+{
+    return profile_of<real>(g[gi], t);
 }
 
 // Shifted equilibrium g_eq,i = f_eq,i - r_i of eq:fieq, drho = rho - 1:
@@ -218,8 +229,44 @@ __device__ __forceinline__ void stored_moments(const Prev& prev, int dx, int dy,
 }
 
 // The boundary rule of section 4 for the cut link (x, k): the population
-// arriving at x in direction kbar at the current step, from the post-collision
-// state of the previous step (time t_prev).
+// arriving at x in direction kbar at the current step, from the previous
+// post-collision state -- gk, gkb its populations k and kbar at x, gky its
+// population k at x - c_k (0 with no site behind x), (drx, pxxx, pyyx, pxyx)
+// its moments at x and (dry, pxxy, pyyy, pxyy) at x - c_k (read only when the
+// rule extrapolates, L.wy != 0), p1 and p2 the profiles of the link's groups
+// at that step (p2 = 0 without a second group).
+template <typename real>
+__device__ real rule_value(const StepArgs<real>& a, const LinkDev<real>& L, real gk, real gkb, real gky,
+                           real drx, real pxxx, real pyyx, real pxyx, real dry, real pxxy, real pyyy, real pxyy,
+                           real p1, real p2)
+{
+    if (L.kind == SLBM_DIRICHLET) {
+        // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
+        return gk + L.kappa * (gky - gkb) + L.D * (real(1) + drx) * p1;
+    }
+    // eq:abbcon / eq:abbnoncon.  Cauchy stress from the Poisson stress with the
+    // divergence approximation (eq:poissonstress, eq:approxdiv):
+    // sigma = -P - (lambda - mu) drho I.
+    real drbd = L.wx * drx;
+    real stt = L.wx * (L.E3[0] * (-pxxx - a.lm * drx) + L.E3[1] * (-pyyx - a.lm * drx)
+                       - real(2) * L.E3[2] * pxyx);
+    if (L.wy != real(0)) {
+        drbd += L.wy * dry;
+        stt += L.wy * (L.E3[0] * (-pxxy - a.lm * dry) + L.E3[1] * (-pyyy - a.lm * dry)
+                       - real(2) * L.E3[2] * pxyy);
+    }
+    // boundary Cauchy stress (eq:trafocauchy) and Poisson stress (eq:bcchainneum)
+    const real sxx = p1 * L.K1[0] + p2 * L.K2[0] + stt * L.E3[0];
+    const real syy = p1 * L.K1[1] + p2 * L.K2[1] + stt * L.E3[1];
+    const real sxy = p1 * L.K1[2] + p2 * L.K2[2] + stt * L.E3[2];
+    const real Pxx = -sxx - a.lm * drbd;
+    const real Pyy = -syy - a.lm * drbd;
+    const real Pxy = -sxy;
+    return -gk - L.kappa * (gky + gkb) + L.be[0] * drbd + L.be[1] * Pxx + L.be[2] * Pyy + L.be[3] * Pxy;
+}
+
+// rule_value with the state read through prev (time t_prev) and the
+// profiles from the group table.
 template <typename real, class Prev>
 __device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, const Prev& prev, long long t_prev,
                                real drx, real pxxx, real pyyx, real pxyx)
@@ -230,33 +277,15 @@ __device__ real boundary_value(const StepArgs<real>& a, const LinkDev<real>& L, 
     real gky = real(0);
     if (L.behind) gky = prev(k, -L.dx, -L.dy);
     if (L.kind == SLBM_DIRICHLET) {
-        // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
         const real p = profile_at<real>(a.groups, L.g1, t_prev);
-        return gk + L.kappa * (gky - gkb) + L.D * (real(1) + drx) * p;
+        return rule_value<real>(a, L, gk, gkb, gky, drx, pxxx, pyyx, pxyx, real(0), real(0), real(0), real(0), p,
+                                real(0));
     }
-    // eq:abbcon / eq:abbnoncon.  Cauchy stress from the Poisson stress with the
-    // divergence approximation (eq:poissonstress, eq:approxdiv):
-    // sigma = -P - (lambda - mu) drho I.
-    real drbd = L.wx * drx;
-    real stt = L.wx * (L.E3[0] * (-pxxx - a.lm * drx) + L.E3[1] * (-pyyx - a.lm * drx)
-                       - real(2) * L.E3[2] * pxyx);
-    if (L.wy != real(0)) {
-        real dry, pxxy, pyyy, pxyy;
-        stored_moments<real>(prev, -L.dx, -L.dy, dry, pxxy, pyyy, pxyy);
-        drbd += L.wy * dry;
-        stt += L.wy * (L.E3[0] * (-pxxy - a.lm * dry) + L.E3[1] * (-pyyy - a.lm * dry)
-                       - real(2) * L.E3[2] * pxyy);
-    }
+    real dry = real(0), pxxy = real(0), pyyy = real(0), pxyy = real(0);
+    if (L.wy != real(0)) stored_moments<real>(prev, -L.dx, -L.dy, dry, pxxy, pyyy, pxyy);
     const real p1 = profile_at<real>(a.groups, L.g1, t_prev);
     const real p2 = L.g2 >= 0 ? profile_at<real>(a.groups, L.g2, t_prev) : real(0);
-    // boundary Cauchy stress (eq:trafocauchy) and Poisson stress (eq:bcchainneum)
-    const real sxx = p1 * L.K1[0] + p2 * L.K2[0] + stt * L.E3[0];
-    const real syy = p1 * L.K1[1] + p2 * L.K2[1] + stt * L.E3[1];
-    const real sxy = p1 * L.K1[2] + p2 * L.K2[2] + stt * L.E3[2];
-    const real Pxx = -sxx - a.lm * drbd;
-    const real Pyy = -syy - a.lm * drbd;
-    const real Pxy = -sxy;
-    return -gk - L.kappa * (gky + gkb) + L.be[0] * drbd + L.be[1] * Pxx + L.be[2] * Pyy + L.be[3] * Pxy;
+    return rule_value<real>(a, L, gk, gkb, gky, drx, pxxx, pyyx, pxyx, dry, pxxy, pyyy, pxyy, p1, p2);
 }
 
 // Replaces the populations of cut links of a boundary site (grid offset s) by
@@ -662,17 +691,71 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs<real> a)
 constexpr int kMaxTileRows2 = 10;
 constexpr int kStrip2 = 58;
 
+// Cut links whose rules a tile of the two-step kernel evaluates together
+// (below), and the BC groups whose profiles it tabulates: the host uses the
+// cooperative kernel only when every tile's records and the plate's groups
+// fit.
+constexpr int kTileRecCap = 384;
+constexpr int kTileGroupCap = 64;
+
+// LDS of a two-step tile.  post holds the first step's post-collision
+// populations (rows 0..R+3); in the cooperative kernel, before that, rows
+// 0..R+5 (plane k of row w) carry the first step's rule values of the cut
+// links of wave w.
+template <typename real, bool COOP>
+struct TileLds {
+    real post[kMaxTileRows2 + (COOP ? 6 : 4)][9][64];
+    real dens[kMaxTileRows2 + 6][66];
+};
+template <typename real>
+struct TileLds<real, true> {
+    real post[kMaxTileRows2 + 6][9][64];
+    real dens[kMaxTileRows2 + 6][66];
+    LinkDev<real> recs[kTileRecCap];
+    real prof[2][kTileGroupCap];
+};
+
+// Population k of h[0..8] for a k known only at run time, by bit masks (a
+// dynamically indexed register array would go through scratch memory).
+__device__ __forceinline__ float pick9(const float h[9], int k)
+{
+    unsigned v = 0u;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) v |= __float_as_uint(h[j]) & (0u - (unsigned)(k == j));
+    return __uint_as_float(v);
+}
+__device__ __forceinline__ double pick9(const double h[9], int k)
+{
+    unsigned long long v = 0ull;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) v |= (unsigned long long)__double_as_longlong(h[j]) & (0ull - (unsigned long long)(k == j));
+    return __longlong_as_double((long long)v);
+}
+
 // TWO = false: only the first step, stored like a single step (a plate in a
 // batch with one step left).
-template <typename real, bool PER, bool TWO = true>
-__device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, real (*post)[9][64],
-                                           real (*dens)[66])
+//
+// The rules of section 4 at the tile's cut links, two ways.  COOP = false:
+// site by site, each site with cut links pulling, from global memory (first
+// step) or LDS (second), the state its links read and the links'
+// coefficients, one link after the other.  COOP = true (the plate carries
+// per-tile record lists, rec_start, each of at most kTileRecCap records):
+// together -- the workgroup copies the tile's records into LDS with its first
+// loads, one thread per record gathers the state its rule reads (one round of
+// loads for all records), evaluates it and leaves the value in LDS where the
+// site's lane picks it up (first step) or in the LDS slot the site's pull
+// reads (second step).  Both compute every rule value from the same inputs
+// with rule_value, so the state is the same to the bit.
+template <typename real, bool PER, bool TWO, bool COOP>
+__device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, TileLds<real, COOP>& lds)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, nthr = blockDim.x;
     const int R = a.seg;
     const int strip = tile % a.nstrips;
     const int y0 = (tile / a.nstrips) * R;
-    const int x = strip * kStrip2 - 3 + lane, y = y0 - 3 + wave;
+    const int xs = strip * kStrip2 - 3;
+    const int x = xs + lane, y = y0 - 3 + wave;
     // first step, from the state buffer
     real g[9];
     unsigned fl;
@@ -685,7 +768,88 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
         ux = ldu(a.U, s);
         uy = ldu(a.U + a.plane, s);
     }
-    dens[wave][lane] = site_finish<real, PER>(a, x, ys, in, true, fl, g);
+    int r0 = 0, nrec = 0;
+    if constexpr (COOP) {
+        r0 = a.rec_start[tile];
+        nrec = a.rec_start[tile + 1] - r0;                  // uniform over the workgroup
+    }
+    // the tile's records and the groups' profiles into LDS, and the first
+    // step's rules (none when src holds the populations themselves)
+    if constexpr (COOP) if (nrec > 0) {
+        // the record this thread evaluates: where it is and which link
+        int rpos = 0, rk = 1;
+        const bool rec = tid < nrec;
+        if (rec) {
+            rpos = a.recs[r0 + tid].pos;
+            rk = a.recs[r0 + tid].k;
+        }
+        // the tile's records into LDS, 8 words per thread in flight
+        {
+            constexpr int RW = (int)(sizeof(LinkDev<real>) / 4);
+            const uint32_t* gw = reinterpret_cast<const uint32_t*>(a.recs + r0);
+            uint32_t* lw = reinterpret_cast<uint32_t*>(lds.recs);
+            const int n = nrec * RW;
+            for (int base = 0; base < n; base += 8 * nthr) {
+                uint32_t t[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int i = base + tid + j * nthr;
+                    t[j] = gw[i < n ? i : 0];
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int i = base + tid + j * nthr;
+                    if (i < n) lw[i] = t[j];
+                }
+            }
+        }
+        // profiles of the groups at the first and the second step
+        if (tid < a.ngroups) {
+            const GroupDev G = a.groups[tid];
+            lds.prof[0][tid] = profile_of<real>(G, a.t_prev);
+            lds.prof[1][tid] = profile_of<real>(G, a.t_prev + 1);
+        }
+        // the state the record's rule reads: the nine populations at its site
+        // x and at x - c_k
+        real h0[9], hb[9];
+        const bool rule1 = rec && !a.local;
+        if (rule1) {
+            int rx = xs + (rpos & 255), ry = y0 - 3 + (rpos >> 8);
+            bool rin;
+            place<PER>(a.nx, a.ny, a.px, a.py, rx, ry, rin);
+            const int so = sidx(rx, ry, a.ld);
+            const int sb = wrap_off<PER>(rx, ry, -CX(rk), -CY(rk), a.nx, a.ny, a.ld, a.px, a.py);
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                h0[j] = ldu(a.src + j * a.plane, so);
+                hb[j] = ldu(a.src + j * a.plane, sb);
+            }
+        }
+        __syncthreads();
+        if (rule1) {
+            const LinkDev<real>& L = lds.recs[tid];
+            real drx, jx, jy, pxxx, pyyx, pxyx;
+            moments9(h0, drx, jx, jy, pxxx, pyyx, pxyx);
+            real dry = real(0), pxxy = real(0), pyyy = real(0), pxyy = real(0);
+            if (L.kind != SLBM_DIRICHLET && L.wy != real(0)) moments9(hb, dry, jx, jy, pxxy, pyyy, pxyy);
+            const real gk = pick9(h0, rk), gkb = pick9(h0, OPP(rk));
+            const real gky = L.behind ? pick9(hb, rk) : real(0);
+            const real p1 = lds.prof[0][L.g1];
+            const real p2 = (L.kind != SLBM_DIRICHLET && L.g2 >= 0) ? lds.prof[0][L.g2] : real(0);
+            lds.post[rpos >> 8][rk][rpos & 255] =
+                rule_value<real>(a, L, gk, gkb, gky, drx, pxxx, pyyx, pxyx, dry, pxxy, pyyy, pxyy, p1, p2);
+        }
+        if (!a.local) {                                 // uniform over the workgroup
+            __syncthreads();
+            // the site's pulls along its cut links are the rule values
+            if (in && fl != kVoid && fl != 0u) {
+#pragma unroll
+                for (int k = 1; k < 9; ++k)
+                    if ((fl >> (k - 1)) & 1u) g[OPP(k)] = lds.post[wave][k][lane];
+            }
+        }
+    }
+    lds.dens[wave][lane] = site_finish<real, PER>(a, x, ys, in, !COOP, fl, g);
     __syncthreads();
     const bool cuts = wave_has_cuts(fl);
     const bool out = out_row && lane >= 3 && lane <= 60 && y < a.ny && x < a.nx && fl != kVoid;
@@ -694,13 +858,15 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
         real o[9];
         if (lane >= 1 && lane <= 62 && fl != kVoid) {
             Window<real> w;
-            w.m = dens[wave - 1][lane]; w.m_l = dens[wave - 1][lane - 1]; w.m_r = dens[wave - 1][lane + 1];
-            w.c_l = dens[wave][lane - 1]; w.c_r = dens[wave][lane + 1];
+            w.m = lds.dens[wave - 1][lane]; w.m_l = lds.dens[wave - 1][lane - 1]; w.m_r = lds.dens[wave - 1][lane + 1];
+            w.c_l = lds.dens[wave][lane - 1]; w.c_r = lds.dens[wave][lane + 1];
             real jx, jy, ir;
-            const bool b = cuts ? collide_core<real, true>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
-                                                           dens[wave + 1][lane + 1], o, jx, jy, ir)
-                                : collide_core<real, false>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
-                                                            dens[wave + 1][lane + 1], o, jx, jy, ir);
+            const bool b = cuts ? collide_core<real, true>(a, g, fl, w, lds.dens[wave + 1][lane],
+                                                           lds.dens[wave + 1][lane - 1], lds.dens[wave + 1][lane + 1],
+                                                           o, jx, jy, ir)
+                                : collide_core<real, false>(a, g, fl, w, lds.dens[wave + 1][lane],
+                                                            lds.dens[wave + 1][lane - 1], lds.dens[wave + 1][lane + 1],
+                                                            o, jx, jy, ir);
             if (out) {
                 bad = b;
                 advance_u(ux, uy, jx, jy, ir);
@@ -719,32 +885,66 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, re
             return bad;
         }
 #pragma unroll
-        for (int i = 0; i < 9; ++i) post[wave - 1][i][lane] = o[i];
+        for (int i = 0; i < 9; ++i) lds.post[wave - 1][i][lane] = o[i];
     }
     if constexpr (!TWO) return bad;
     __syncthreads();
     // second step, from the first step's post-collision populations
+    if constexpr (COOP) if (nrec > 0) {
+        // every rule value from the unmodified state first, then each into the
+        // slot its site pulls from (a slot another rule reads -- across a
+        // crack -- is overwritten only after all have read it)
+        real v = real(0);
+        int vr = 0, vi = 0, vl = 0;
+        bool put = false;
+        if (tid < nrec) {
+            const LinkDev<real>& L = lds.recs[tid];
+            const int w = L.pos >> 8, l = L.pos & 255;
+            if (w >= 2 && w <= R + 3 && l >= 2 && l <= 61) {
+                const LdsPrev<real> prev{lds.post, w - 1, l};
+                real drx, pxxx, pyyx, pxyx;
+                stored_moments<real>(prev, 0, 0, drx, pxxx, pyyx, pxyx);
+                const int k = L.k, kb = OPP(k);
+                const real gk = prev(k, 0, 0), gkb = prev(kb, 0, 0);
+                const real gky = L.behind ? prev(k, -L.dx, -L.dy) : real(0);
+                real dry = real(0), pxxy = real(0), pyyy = real(0), pxyy = real(0);
+                if (L.kind != SLBM_DIRICHLET && L.wy != real(0))
+                    stored_moments<real>(prev, -L.dx, -L.dy, dry, pxxy, pyyy, pxyy);
+                const real p1 = lds.prof[1][L.g1];
+                const real p2 = (L.kind != SLBM_DIRICHLET && L.g2 >= 0) ? lds.prof[1][L.g2] : real(0);
+                v = rule_value<real>(a, L, gk, gkb, gky, drx, pxxx, pyyx, pxyx, dry, pxxy, pyyy, pxyy, p1, p2);
+                vr = w - 1 + L.dy;
+                vi = kb;
+                vl = l + L.dx;
+                put = true;
+            }
+        }
+        __syncthreads();
+        if (put) lds.post[vr][vi][vl] = v;
+        __syncthreads();
+    }
     if (wave >= 2 && wave <= R + 3) {
         const int r = wave - 1;
         const int lc = lane < 2 ? 2 : (lane > 61 ? 61 : lane);   // lanes 0, 1, 62, 63: no second-step site
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = post[r - CY(i)][i][lc - CX(i)];
+        for (int i = 0; i < 9; ++i) g[i] = lds.post[r - CY(i)][i][lc - CX(i)];
         const bool live = fl != kVoid;
-        if (live && fl != 0) boundary_fixup<real>(a, LdsPrev<real>{post, r, lc}, s, fl, a.t_prev + 1, g);
+        if constexpr (!COOP)
+            if (live && fl != 0) boundary_fixup<real>(a, LdsPrev<real>{lds.post, r, lc}, s, fl, a.t_prev + 1, g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = live ? g[i] : real(0);
-        dens[wave][lane] = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
+        lds.dens[wave][lane] = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
     }
     __syncthreads();
     if (out) {
         Window<real> w;
-        w.m = dens[wave - 1][lane]; w.m_l = dens[wave - 1][lane - 1]; w.m_r = dens[wave - 1][lane + 1];
-        w.c_l = dens[wave][lane - 1]; w.c_r = dens[wave][lane + 1];
+        w.m = lds.dens[wave - 1][lane]; w.m_l = lds.dens[wave - 1][lane - 1]; w.m_r = lds.dens[wave - 1][lane + 1];
+        w.c_l = lds.dens[wave][lane - 1]; w.c_r = lds.dens[wave][lane + 1];
         real o[9], jx, jy, ir;
-        bad |= cuts ? collide_core<real, true>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
-                                               dens[wave + 1][lane + 1], o, jx, jy, ir)
-                    : collide_core<real, false>(a, g, fl, w, dens[wave + 1][lane], dens[wave + 1][lane - 1],
-                                                dens[wave + 1][lane + 1], o, jx, jy, ir);
+        bad |= cuts ? collide_core<real, true>(a, g, fl, w, lds.dens[wave + 1][lane], lds.dens[wave + 1][lane - 1],
+                                               lds.dens[wave + 1][lane + 1], o, jx, jy, ir)
+                    : collide_core<real, false>(a, g, fl, w, lds.dens[wave + 1][lane], lds.dens[wave + 1][lane - 1],
+                                                lds.dens[wave + 1][lane + 1], o, jx, jy, ir);
 #pragma unroll
         for (int i = 0; i < 9; ++i) stu(a.dst + i * a.plane, s, o[i]);
         advance_u(ux, uy, jx, jy, ir);
@@ -762,15 +962,15 @@ template <typename real>
 constexpr int k2_waves(int rows) { return sizeof(real) == 4 ? (rows > 8 ? 8 : 7) : 1; }
 
 // Two time steps of one plate: one workgroup of seg + 6 waves per tile
-// (W = k2_waves(seg)).
-template <typename real, bool PER, int W>
+// (W = k2_waves(seg)); COOP: the boundary rules tile by tile from the
+// plate's tile record lists.
+template <typename real, bool PER, int W, bool COOP>
 __global__ __launch_bounds__(1024, W) void k_step2(StepArgs<real> a)
 {
-    __shared__ real post[kMaxTileRows2 + 4][9][64];
-    __shared__ real dens[kMaxTileRows2 + 6][66];
+    __shared__ TileLds<real, COOP> lds;
     const int tile = xcd_map(blockIdx.x, gridDim.x, a.group_shift);
     if (tile >= a.ntiles) return;                 // uniform over the workgroup
-    flag_divergence(a.diverged, step_tile2<real, PER>(a, tile, post, dens));
+    flag_divergence(a.diverged, step_tile2<real, PER, true, COOP>(a, tile, lds));
 }
 
 // Per-plate state of the batched step, in device memory so that a captured
@@ -840,8 +1040,7 @@ __global__ __launch_bounds__(1024, W) void k_step2_batch(BatchPlate<real>* __res
                                                       const int* __restrict__ tile_start, int ntiles, int maxk,
                                                       int group_shift)
 {
-    __shared__ real post[kMaxTileRows2 + 4][9][64];
-    __shared__ real dens[kMaxTileRows2 + 6][66];
+    __shared__ TileLds<real, false> lds;
     const int t = xcd_map(blockIdx.x, gridDim.x, group_shift);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
@@ -851,9 +1050,9 @@ __global__ __launch_bounds__(1024, W) void k_step2_batch(BatchPlate<real>* __res
     if (lt == 0 && threadIdx.x == 0) plates[(parity ^ 1) * cap + p] = batch_next(B, maxk);
     if (!B.active || B.halted) return;
     if (maxk >= 2 && B.remaining >= 2)
-        flag_divergence(B.args.diverged, step_tile2<real, false, true>(B.args, lt, post, dens));
+        flag_divergence(B.args.diverged, step_tile2<real, false, true, false>(B.args, lt, lds));
     else
-        flag_divergence(B.args.diverged, step_tile2<real, false, false>(B.args, lt, post, dens));
+        flag_divergence(B.args.diverged, step_tile2<real, false, false, false>(B.args, lt, lds));
 }
 
 }  // namespace slbm_dev

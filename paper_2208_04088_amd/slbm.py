@@ -23,7 +23,7 @@ PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
 EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
     "slbm_displacement", "slbm_displacement_device", "slbm_displacement_device_noalloc", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
-    "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
+    "slbm_boundary_lists", "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
     "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch",
     "slbm_batch_set_xcd_group", "slbm_batch_get_launch", "slbm_batch_autotune", "slbm_batch_sync",
@@ -84,6 +84,7 @@ def lib():
         "slbm_set_launch": [vp, i32, i32],
         "slbm_set_xcd_group": [vp, i32],
         "slbm_get_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "slbm_boundary_lists": [vp, C.POINTER(i32), C.POINTER(C.c_int64), C.POINTER(i32)],
         "slbm_autotune": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)],
         "slbm_save": [vp, vp, C.POINTER(C.c_size_t)],
         "slbm_load": [vp, vp, C.c_size_t],
@@ -244,6 +245,14 @@ class Solver:
         r, st, g = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().slbm_get_launch(self.h, C.byref(r), C.byref(st), C.byref(g)))
         return r.value, st.value, g.value
+
+    def boundary_lists(self):
+        """slbm_boundary_lists: (rows per tile the per-tile cut-link lists of
+        the two-step kernel were built for, 0 if none; records; most in one
+        tile)."""
+        r, n, m = C.c_int32(), C.c_int64(), C.c_int32()
+        _check(lib().slbm_boundary_lists(self.h, C.byref(r), C.byref(n), C.byref(m)))
+        return r.value, n.value, m.value
 
     def autotune(self):
         """Picks the fastest launch shape for this plate; returns

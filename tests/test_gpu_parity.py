@@ -271,6 +271,67 @@ def test_two_steps_per_launch_match_single_steps(slbm, prec, case):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["mixed", "mixed_order1", "periodic", "small_periodic"])
+def test_tile_lists_match_site_by_site_rules(slbm, prec, case):
+    """With strip 58 the library lists each tile's cut links and the tile
+    evaluates their rules together (first step from global memory, second
+    from LDS) instead of site by site; the inputs of every rule value are the
+    same, so the state must be bit-identical to single steps (which take the
+    rules site by site) -- edges, corners, a crack, a curved hole, step and
+    ramped Dirichlet and Neumann groups, both extrapolation orders, periodic
+    axes whose tile footprints wrap (a plate narrower than a strip)."""
+    if case == "periodic":
+        p, n = mixed_plate(64, 40, seed=1, periodic=True), 41
+    elif case == "small_periodic":
+        p = G.build_plate(40, 23, lam=0.06, mu=0.05, tau=0.6, periodic_x=True,
+                          walls=[G.HLine(-0.5, 0), G.HLine(22.5, 1), G.Circle(20.0, 11.0, 5.0, 1)],
+                          groups=[G.BCGroup(G.DIRICHLET, (0.0, 0.0)),
+                                  G.BCGroup(G.NEUMANN, (3e-5, 1e-5), G.PROFILE_RAMP, 20.0)],
+                          neumann_order=1)
+        n = 40
+    else:
+        p, n = mixed_plate(150, 97, seed=5, order=1 if case == "mixed_order1" else 0), 41
+    ref = slbm.Solver(p, prec)
+    ref.set_launch(6, 62)
+    ref.step(n)
+    for rows in (1, 4, 10):
+        s = slbm.Solver(p, prec)
+        s.set_launch(rows, 58)
+        built, records, most = s.boundary_lists()
+        assert built == rows and records > 0 and 0 < most <= 384, (built, records, most)
+        s.step(n)
+        s.sync()
+        assert np.array_equal(s.displacement(), ref.displacement())
+        for a, b in zip(s.moments(), ref.moments()):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plate_too_dense_for_tile_lists(slbm, prec):
+    """A plate cut into two-row strips by full-width cracks has more cut links
+    per tile than a tile's LDS takes: no lists are kept, the two-step kernel
+    takes the rules site by site, and the state still matches single steps
+    and the CPU reference."""
+    nx, ny = 70, 24
+    walls = G.edge_walls(nx, ny, left=0, right=1, bottom=1, top=1)
+    walls += [G.HLine(y + 0.5, 1, x_lo=-0.5, x_hi=nx - 0.5) for y in range(1, ny - 2, 2)]
+    p = G.build_plate(nx, ny, lam=0.04, mu=0.05, tau=0.55, walls=walls,
+                      groups=[G.BCGroup(G.DIRICHLET, (0.0, 0.0)), G.BCGroup(G.NEUMANN, (2e-5, 0.0))],
+                      neumann_order=0)
+    s = slbm.Solver(p, prec)
+    s.set_launch(10, 58)
+    assert s.boundary_lists() == (0, 0, 0)
+    s.step(30)
+    one = slbm.Solver(p, prec)
+    one.set_launch(6, 62)
+    one.step(30)
+    assert np.array_equal(s.displacement(), one.displacement())
+    ref = Oracle(p, extended=True)
+    ref.step(30)
+    compare(s, ref, prec)
+
+
 @pytest.mark.parametrize("shape", [(1, 7), (2, 2), (3, 5), (61, 9), (62, 3), (63, 4), (64, 65), (124, 2), (125, 33)])
 def test_small_and_ragged_grids(slbm, shape):
     """Degenerate and ragged sizes around the 62-column strip and the 64-element pitch."""
