@@ -60,7 +60,13 @@ def bytes_per_site(prec):
     return 9 * 2 * (4 if prec == "fp32" else 8) + 2 * 2 * 8
 
 
-def measured_traffic(plate, prec, tuned, group=0):
+def shape_key(rows, strip, group, lists):
+    """Name of a launch shape in the counter summaries: rows x strip, the XCD
+    group, and whether the two-step kernel ran with per-tile cut-link lists."""
+    return f"{rows}x{strip}" + (f"-g{group}" if group else "") + ("-lists" if lists else "")
+
+
+def measured_traffic(plate, prec, tuned, group=0, lists=False):
     """HBM bytes per launch of the step kernel from the committed counter
     summary (profiles/traffic_<workload>_<precision>.json), or None when there
     is none for this workload and launch shape or the kernel changed since."""
@@ -72,12 +78,11 @@ def measured_traffic(plate, prec, tuned, group=0):
         d = json.load(fh)
     if d.get("kernel_fingerprint") != kernel_fingerprint():
         return None
-    key = f"{tuned[0]}x{tuned[1]}" + (f"-g{group}" if group else "")
-    shape = d.get("shapes", {}).get(key)
+    shape = d.get("shapes", {}).get(shape_key(tuned[0], tuned[1], group, lists))
     return shape["traffic_bytes_per_launch"] if shape else None
 
 
-def measured_traffic_batch(shape, group):
+def measured_traffic_batch(shape, group, lists=False):
     """HBM bytes per launch of the batched step kernel on the 64 plates of
     seed 0, from profiles/traffic_batch64-seed0_fp32.json, or None when there
     is none for this launch shape or the kernel changed since."""
@@ -89,8 +94,7 @@ def measured_traffic_batch(shape, group):
         d = json.load(fh)
     if d.get("kernel_fingerprint") != kernel_fingerprint():
         return None
-    key = f"{shape[0]}x{shape[1]}" + (f"-g{group}" if group else "")
-    entry = d.get("shapes", {}).get(key)
+    entry = d.get("shapes", {}).get(shape_key(shape[0], shape[1], group, lists))
     return entry["traffic_bytes_per_launch"] if entry else None
 
 
@@ -274,6 +278,8 @@ def run_batch(args, slbm, torch, dev, stream):
         taken = max(b.solver(sl).time()[0] for sl in slots)   # plates still running took every trial step
         b.step(warm - taken)
     shape = b.launch()
+    # the cooperative batched kernel runs when every plate carries tile lists
+    batch_lists = shape[1] == 58 and all(b.solver(sl).boundary_lists()[0] == shape[0] for sl in slots)
     b.sync()
     e0, e1 = ev(), ev()
     w0 = time.perf_counter()
@@ -350,8 +356,9 @@ def run_batch(args, slbm, torch, dev, stream):
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic_batch(shape[:2], shape[2]),
+            "traffic": measured_traffic_batch(shape[:2], shape[2], batch_lists),
             "kernel": "k_step2_batch" if shape[1] == 58 else "k_step_batch",
+            "tile_lists": batch_lists,
             "bytes_per_site": bytes_per_site("fp32"),
             "steps_per_launch": 2 if shape[1] == 58 else 1,
             "avg_launch_us": round(t_batch / steps * 1e6 * (2 if shape[1] == 58 else 1), 3),
@@ -477,6 +484,7 @@ def time_plate(args, slbm, torch, stream, plate, prec, steps, warmup, shape=None
         s.autotune()                  # rows per tile, strip width and XCD map, measured on this plate
     rows, strip, group = s.launch()
     strip = strip or 62
+    lists = s.boundary_lists()
     torch.cuda.synchronize()
 
     # timed region: K steps queued back to back on one stream
@@ -517,7 +525,7 @@ def time_plate(args, slbm, torch, stream, plate, prec, steps, warmup, shape=None
     achieved = sites * bps / t_step / 1e9
     avg_launch_us = t_step * spl * 1e6
     ws = working_set_bytes(plate, prec)
-    traffic = measured_traffic(plate, prec, (rows, strip), group)
+    traffic = measured_traffic(plate, prec, (rows, strip), group, lists=strip == 58 and lists[0] == rows)
     roof = {
         # a working set inside the Infinity Cache is served from it, not from HBM
         "bound": "hbm" if ws > MALL_BYTES else "mall",
@@ -538,6 +546,8 @@ def time_plate(args, slbm, torch, stream, plate, prec, steps, warmup, shape=None
         "working_set_bytes": ws,
     }
     if spl == 2:
+        # the boundary rules evaluated tile by tile from per-tile cut-link lists
+        roof["tile_lists"] = {"rows": lists[0], "records": lists[1], "max_per_tile": lists[2]}
         roof["note"] = (
             "achieved counts bytes_per_site per site update (the one-step minimum); this kernel takes two "
             "steps per launch and reads and writes the state once per launch, so it needs half that from HBM; "

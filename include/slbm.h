@@ -212,9 +212,10 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
  * the rows per tile they were built for (0: none, and the step evaluates the
  * boundary rules of section 4 site by site), the records in all lists, and
  * the most in one tile.  Lists are kept only when every tile's fits the
- * tile's LDS (384 records) and the plate has at most 64 BC groups; a cut
- * link appears in every tile whose rows and columns, halo included, reach
- * its site.  Any pointer may be NULL. */
+ * tile's LDS and workgroup (576 records, and one per thread: 64 (rows + 6))
+ * and the plate has at most 64 BC groups; a cut link appears in every tile
+ * whose rows and columns, halo included, reach its site.  Any pointer may be
+ * NULL. */
 int slbm_boundary_lists(slbm_handle h, int32_t* rows, int64_t* records, int32_t* max_per_tile);
 
 /* How the step's workgroups are dealt to the GPU's 8 XCDs: 0 (the default)

@@ -63,6 +63,7 @@ struct slbm_batch_s {
     std::vector<void*> retired;      // outgrown tables and flag arrays, freed with the batch
     std::vector<int> live;           // slot of each device plate entry
     int ntiles = 0;
+    bool coop = false;               // every running plate has tile lists for the launch shape
     bool dirty = true;
     int parity = 0;                  // descriptor copy the next launch reads
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // kChunk steps from either parity
@@ -186,6 +187,7 @@ int batch_build(slbm_batch_s* b)
 {
     batch_drop_graphs(b);
     b->live.clear();
+    bool all_lists = b->two != 0;
     std::vector<BatchPlate<real>> bp;
     std::vector<int> tile_plate, tile_start;
     for (size_t k = 0; k < b->slot.size(); ++k) {
@@ -200,6 +202,7 @@ int batch_build(slbm_batch_s* b)
         h->wide = keep_w;
         e.remaining = b->remaining[k];
         e.active = 1;
+        if (!e.args.rec_start) all_lists = false;
         const int p = (int)bp.size();
         tile_start.push_back((int)tile_plate.size());
         for (int t = 0; t < e.args.ntiles; ++t) tile_plate.push_back(p);
@@ -207,6 +210,7 @@ int batch_build(slbm_batch_s* b)
         b->live.push_back((int)k);
     }
     b->ntiles = (int)tile_plate.size();
+    b->coop = all_lists;
     b->dirty = false;
     b->parity = 0;
     if (bp.empty()) return SLBM_OK;
@@ -262,12 +266,22 @@ void batch_launch(slbm_batch_s* b, int parity, int maxk)
     if (b->two) {
         const dim3 blk(64 * (b->rows + 6));
         constexpr int lo = k2_waves<real>(1), hi = k2_waves<real>(kMaxTileRows2);
-        if (k2_waves<real>(b->rows) == hi)
-            hipLaunchKernelGGL((k_step2_batch<real, hi>), dim3(grid), blk, 0, b->stream, plates, cap, parity,
-                               b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, group_shift(b->group));
-        else
-            hipLaunchKernelGGL((k_step2_batch<real, lo>), dim3(grid), blk, 0, b->stream, plates, cap, parity,
-                               b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, group_shift(b->group));
+        const int gs = group_shift(b->group);
+        if (k2_waves<real>(b->rows) == hi) {
+            if (b->coop)
+                hipLaunchKernelGGL((k_step2_batch<real, hi, true>), dim3(grid), blk, 0, b->stream, plates, cap, parity,
+                                   b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, gs);
+            else
+                hipLaunchKernelGGL((k_step2_batch<real, hi, false>), dim3(grid), blk, 0, b->stream, plates, cap,
+                                   parity, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, gs);
+        } else {
+            if (b->coop)
+                hipLaunchKernelGGL((k_step2_batch<real, lo, true>), dim3(grid), blk, 0, b->stream, plates, cap, parity,
+                                   b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, gs);
+            else
+                hipLaunchKernelGGL((k_step2_batch<real, lo, false>), dim3(grid), blk, 0, b->stream, plates, cap,
+                                   parity, b->d_tile_plate, b->d_tile_start, b->ntiles, maxk, gs);
+        }
     } else {
         const dim3 blk(64 * (b->wide ? tile_waves<true>(b->rows) : tile_waves<false>(b->rows)));
         if (b->wide)
@@ -348,6 +362,22 @@ int batch_run_any(slbm_batch_s* b, int64_t k)
 {
     if (b->precision < 0) return SLBM_OK;
     return b->precision == SLBM_FP32 ? batch_run<float>(b, k) : batch_run<double>(b, k);
+}
+
+hipStream_t batch_compute_stream(slbm_batch_s* b) { return b->stream; }
+
+// Tile lists of every plate for the batch's launch shape (two steps per
+// launch only; a plate without room for its lists in the budget goes
+// without, and the batch then takes the boundary rules site by site).
+int batch_lists(slbm_batch_s* b)
+{
+    if (!b->two) return SLBM_OK;
+    for (slbm_s* h : b->slot) {
+        if (!h) continue;
+        const int rc = tile_records(h, b->rows);
+        if (rc) return rc;
+    }
+    return SLBM_OK;
 }
 
 // Bytes of the readout scratch a plate needs (its padded planes, fp64).
@@ -501,6 +531,12 @@ int slbm_batch_add(slbm_batch b, const slbm_params* params, int64_t nsteps, int3
             delete h;
             return fail(SLBM_E_DEVICE, "event: %s", hipGetErrorString(e));
         }
+        if (b->two && (rc = tile_records(h, b->rows))) {
+            h->batch = nullptr;
+            free_all(h);
+            delete h;
+            return rc;
+        }
         b->precision = params->precision;
         if (k == (int)b->slot.size()) {
             b->slot.push_back(nullptr);
@@ -586,11 +622,12 @@ int slbm_batch_set_launch(slbm_batch b, int32_t rows, int32_t strip)
         if (strip != 62 && strip != 64 && strip != kStrip2) return fail(SLBM_E_INVAL, "strip must be 58, 62 or 64");
         if (rows < 1 || rows > (strip == kStrip2 ? kMaxTileRows2 : kMaxTileRows))
             return fail(SLBM_E_INVAL, "rows per tile must be in [1, 14] ([1, 10] with strip 58)");
+        DeviceGuard dg(b->device);
         b->rows = rows;
         b->wide = strip == 64 ? 1 : 0;
         b->two = strip == kStrip2 ? 1 : 0;
         b->dirty = true;
-        return SLBM_OK;
+        return batch_lists(b);
     });
 }
 
@@ -644,8 +681,9 @@ int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows_out, int3
             b->wide = s.strip == 64 ? 1 : 0;
             b->group = s.group;
             b->dirty = true;
-            int rc = batch_run_any(b, kChunk);
+            int rc = batch_lists(b);
             if (rc) return rc;
+            if ((rc = batch_run_any(b, kChunk))) return rc;
             batch_harvest(b, 0);
             double sites = 0;
             for (size_t k = 0; k < b->slot.size(); ++k)
@@ -693,6 +731,7 @@ int slbm_batch_autotune(slbm_batch b, int64_t max_steps, int32_t* rows_out, int3
         b->wide = best.strip == 64 ? 1 : 0;
         b->group = best.group;
         b->dirty = true;
+        if ((rc = batch_lists(b))) return rc;
         if (rows_out) *rows_out = best.rows;
         if (strip_out) *strip_out = best.strip;
         if (group_out) *group_out = best.group;

@@ -600,13 +600,42 @@ int launch_step_raw(slbm_s* h, int seg, int wide)
     return SLBM_OK;
 }
 
+// A batch plate's steps run on the batch's compute stream (defined with the
+// batch code below); device memory of a plate (defined below).
+hipStream_t batch_compute_stream(slbm_batch_s* b);
+hipError_t dev_alloc(slbm_s* h, void** p, size_t n);
+
 // Rows per tile of the two-step kernel for a requested number (0: default).
 int seg2_rows(int seg) { return std::max(1, std::min(seg > 0 ? seg : 6, kMaxTileRows2)); }
 
+// Frees a plate's tile lists: at once for a single plate (hipFree waits for
+// the device), for a batch plate back to the batch's arena once the launches
+// and readouts queued so far have completed.
 void drop_tile_records(slbm_s* h)
 {
-    if (h->rec_start) (void)hipFree(h->rec_start);
-    if (h->recs) (void)hipFree(h->recs);
+    if (h->arena && (h->rec_start || h->recs)) {
+        if (h->batch) {
+            hipEvent_t ec = nullptr, es = nullptr;
+            if (hipEventCreateWithFlags(&ec, hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&es, hipEventDisableTiming) == hipSuccess &&
+                hipEventRecord(ec, batch_compute_stream(h->batch)) == hipSuccess &&
+                hipEventRecord(es, h->stream) == hipSuccess) {
+                h->arena->release_after({ec, es}, {h->rec_start, h->recs});
+            } else {
+                if (ec) (void)hipEventDestroy(ec);
+                if (es) (void)hipEventDestroy(es);
+                (void)hipDeviceSynchronize();
+                h->arena->release(h->rec_start);
+                h->arena->release(h->recs);
+            }
+        } else {
+            h->arena->release(h->rec_start);
+            h->arena->release(h->recs);
+        }
+    } else {
+        if (h->rec_start) (void)hipFree(h->rec_start);
+        if (h->recs) (void)hipFree(h->recs);
+    }
     h->rec_start = nullptr;
     h->recs = nullptr;
     h->rec_seg = 0;
@@ -635,8 +664,8 @@ long long floor_div(long long a, long long b) { return a >= 0 ? a / b : -((-a + 
 
 // The cut links each tile of the two-step kernel (seg rows, 58-column strips)
 // sees in its footprint -- rows y0 - 3 .. y0 + seg + 2, columns xs - 3 ..
-// xs + 60, wave w and lane l at y0 - 3 + w, xs - 3 + l -- each a copy of the
-// link's record with its position (w << 8 | l).  Tile t's records are
+// xs + 60, wave w and lane l at y0 - 3 + w, xs - 3 + l -- each the link's
+// coefficients with its position (w << 8 | l).  Tile t's records are
 // recs[rec_start[t] .. rec_start[t + 1]).  When a tile has more than the
 // cooperative kernel takes (or the plate more groups than it tabulates), no
 // lists are kept and the two-step kernel takes the rules site by site.
@@ -674,30 +703,42 @@ int build_tile_records(slbm_s* h, int seg)
     each([&](long long t, int, int, int) { ++start[(size_t)t + 1]; });
     int32_t most = 0;
     for (long long t = 0; t < ntiles; ++t) most = std::max(most, start[(size_t)t + 1]);
-    if (most > kTileRecCap) return SLBM_OK;
+    // one record per thread of the tile's workgroup, and what its LDS holds
+    if (most > std::min(kTileRecCap, 64 * (R + 6))) return SLBM_OK;
     for (long long t = 0; t < ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
     const size_t total = (size_t)start[(size_t)ntiles];
-    std::vector<LinkDev<real>> rec(total);
+    std::vector<TileRec<real>> rec(total);
     std::vector<int32_t> fill(start.begin(), start.end() - 1);
     each([&](long long t, int w, int l, int i) {
-        LinkDev<real>& r = rec[(size_t)fill[(size_t)t]++];
-        r = L[i];
+        TileRec<real>& r = rec[(size_t)fill[(size_t)t]++];
+        const LinkDev<real>& d = L[i];
+        r.kappa = d.kappa; r.wx = d.wx; r.wy = d.wy; r.D = d.D;
+        for (int j = 0; j < 4; ++j) r.be[j] = d.be[j];
+        for (int j = 0; j < 3; ++j) {
+            r.K1[j] = d.K1[j];
+            r.K2[j] = d.K2[j];
+            r.E3[j] = d.E3[j];
+        }
+        r.meta = d.k | (d.kind << 4) | (d.behind << 6) | ((d.g1 + 1) << 8) | ((d.g2 + 1) << 16);
         r.pos = (w << 8) | l;
     });
-    hipError_t e = hipMalloc((void**)&h->rec_start, start.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&h->recs, std::max<size_t>(1, total) * sizeof(LinkDev<real>));
+    hipError_t e = dev_alloc(h, (void**)&h->rec_start, start.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = dev_alloc(h, &h->recs, std::max<size_t>(1, total) * sizeof(TileRec<real>));
     if (e != hipSuccess) {
         drop_tile_records(h);
+        h->rec_seg = seg;
+        // a batch plate without room in the budget goes without lists
+        if (e == hipErrorOutOfMemory && h->arena) return SLBM_OK;
         if (e == hipErrorOutOfMemory) return fail(SLBM_E_NOMEM, "no device memory for the tile record lists");
         HIP_TRY(e);
     }
     HIP_TRY(hipMemcpyAsync(h->rec_start, start.data(), start.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            h->stream));
     if (total)
-        HIP_TRY(hipMemcpyAsync(h->recs, rec.data(), total * sizeof(LinkDev<real>), hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->recs, rec.data(), total * sizeof(TileRec<real>), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->rec_fit = true;
-    h->rec_bytes = (int64_t)(start.size() * sizeof(int32_t) + total * sizeof(LinkDev<real>));
+    h->rec_bytes = (int64_t)(start.size() * sizeof(int32_t) + total * sizeof(TileRec<real>));
     h->rec_count = (int64_t)total;
     h->rec_max = most;
     return SLBM_OK;
@@ -719,7 +760,7 @@ StepArgs<real> make_args2(const slbm_s* h, int src, int seg)
     a.ntiles = a.nstrips * ((h->ny + a.seg - 1) / a.seg);
     if (h->rec_fit && h->rec_seg == a.seg) {
         a.rec_start = h->rec_start;
-        a.recs = (const LinkDev<real>*)h->recs;
+        a.recs = (const TileRec<real>*)h->recs;
     }
     return a;
 }
@@ -876,7 +917,8 @@ hipError_t dev_alloc(slbm_s* h, void** p, size_t n)
 // The plate's own device blocks (not the batch's divergence word or scratch).
 std::vector<void*> plate_blocks(slbm_s* h)
 {
-    std::vector<void*> v = {h->buf[0], h->buf[1], h->U, h->flags, h->bidx, h->links, h->groups};
+    std::vector<void*> v = {h->buf[0], h->buf[1], h->U, h->flags, h->bidx, h->links, h->groups, h->rec_start,
+                            h->recs};
     if (!h->ext_flag) v.push_back(h->diverged);
     if (!h->batch) v.push_back(h->scratch);
     return v;
@@ -893,6 +935,9 @@ void free_all(slbm_s* h)
             (void)hipFree(p);
     }
     h->buf[0] = h->buf[1] = nullptr;
+    h->rec_start = nullptr;
+    h->recs = nullptr;
+    h->rec_fit = false;
     h->U = nullptr;
     h->scratch = nullptr;
     if (h->ready) (void)hipEventDestroy(h->ready);
@@ -1275,7 +1320,6 @@ int slbm_destroy(slbm_handle h)
         if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch: remove it with slbm_batch_remove");
         DeviceGuard dg(h->device);
         if (h->stream) (void)hipStreamSynchronize(h->stream);
-        drop_tile_records(h);
         free_all(h);
         delete h;
         return SLBM_OK;

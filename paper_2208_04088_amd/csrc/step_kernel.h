@@ -55,9 +55,26 @@ struct LinkDev {
     int32_t g1, g2;            // groups whose profiles scale D or K1, K2
     int32_t kind;              // SLBM_DIRICHLET | SLBM_NEUMANN
     int32_t behind;            // 1: x - c_k is a material site reached by an uncut link
-    int32_t k, dx, dy;
-    int32_t pos;               // in a tile's record list: the site's wave << 8 | lane in the tile
+    int32_t k, dx, dy, pad;
 };
+
+// A cut link in a tile's list (the two-step kernel's cooperative rules): the
+// link record's coefficients, with its direction, kind, the site-behind flag
+// and its groups packed into meta (k | kind << 4 | behind << 6 | (g1 + 1) << 8
+// | (g2 + 1) << 16, groups below 255) and its position in the tile.
+template <typename real>
+struct TileRec {
+    real kappa, wx, wy, D;
+    real be[4];
+    real K1[3], K2[3], E3[3];
+    int32_t meta;
+    int32_t pos;               // the site's wave << 8 | lane in the tile
+};
+
+template <typename real>
+__host__ __device__ inline int link_kind(const LinkDev<real>& L) { return L.kind; }
+template <typename real>
+__host__ __device__ inline int link_kind(const TileRec<real>& R) { return (R.meta >> 4) & 3; }
 
 template <typename real>
 struct StepArgs {
@@ -72,7 +89,7 @@ struct StepArgs {
     // cut links per tile of the two-step kernel (null: none built for this
     // launch shape): tile t's are recs[rec_start[t] .. rec_start[t + 1])
     const int32_t* rec_start;
-    const LinkDev<real>* recs;
+    const TileRec<real>* recs;
     long long plane;           // ny * ld
     long long t_prev;          // step whose post-collision state src holds
     int nx, ny, ld;
@@ -235,12 +252,12 @@ __device__ __forceinline__ void stored_moments(const Prev& prev, int dx, int dy,
 // its moments at x and (dry, pxxy, pyyy, pxyy) at x - c_k (read only when the
 // rule extrapolates, L.wy != 0), p1 and p2 the profiles of the link's groups
 // at that step (p2 = 0 without a second group).
-template <typename real>
-__device__ real rule_value(const StepArgs<real>& a, const LinkDev<real>& L, real gk, real gkb, real gky,
+template <typename real, class Rec>
+__device__ real rule_value(const StepArgs<real>& a, const Rec& L, real gk, real gkb, real gky,
                            real drx, real pxxx, real pyyx, real pxyx, real dry, real pxxy, real pyyy, real pxyy,
                            real p1, real p2)
 {
-    if (L.kind == SLBM_DIRICHLET) {
+    if (link_kind(L) == SLBM_DIRICHLET) {
         // eq:bbcon / eq:bbnoncon, j* = rho(x) d(u*)/dt (eq:bcchaindir)
         return gk + L.kappa * (gky - gkb) + L.D * (real(1) + drx) * p1;
     }
@@ -693,26 +710,33 @@ constexpr int kStrip2 = 58;
 
 // Cut links whose rules a tile of the two-step kernel evaluates together
 // (below), and the BC groups whose profiles it tabulates: the host uses the
-// cooperative kernel only when every tile's records and the plate's groups
-// fit.
-constexpr int kTileRecCap = 384;
+// cooperative kernel only when every tile's records (at most one per thread
+// of the workgroup) and the plate's groups fit.  The records fill what is
+// left of the LDS two single-precision workgroups share on a compute unit.
+constexpr int kTileRecCap = 576;
 constexpr int kTileGroupCap = 64;
 
 // LDS of a two-step tile.  post holds the first step's post-collision
-// populations (rows 0..R+3); in the cooperative kernel, before that, rows
-// 0..R+5 (plane k of row w) carry the first step's rule values of the cut
-// links of wave w.
+// populations (rows 0..R+3).  In the cooperative kernel the same words first
+// carry the first step's rule values, plane k - 1 of row w those of the cut
+// links k of wave w (rows 0..R+5); they are read before the first step's
+// collision writes post.
 template <typename real, bool COOP>
 struct TileLds {
-    real post[kMaxTileRows2 + (COOP ? 6 : 4)][9][64];
+    real post_[kMaxTileRows2 + 4][9][64];
     real dens[kMaxTileRows2 + 6][66];
+    __device__ real (*post())[9][64] { return post_; }
 };
 template <typename real>
 struct TileLds<real, true> {
-    real post[kMaxTileRows2 + 6][9][64];
+    static constexpr int kWords = (kMaxTileRows2 + 6) * 8 * 64 > (kMaxTileRows2 + 4) * 9 * 64
+                                      ? (kMaxTileRows2 + 6) * 8 * 64 : (kMaxTileRows2 + 4) * 9 * 64;
+    real buf[kWords];
     real dens[kMaxTileRows2 + 6][66];
-    LinkDev<real> recs[kTileRecCap];
+    TileRec<real> recs[kTileRecCap];
     real prof[2][kTileGroupCap];
+    __device__ real (*post())[9][64] { return reinterpret_cast<real (*)[9][64]>(buf); }
+    __device__ real (*rule1())[8][64] { return reinterpret_cast<real (*)[8][64]>(buf); }
 };
 
 // Population k of h[0..8] for a k known only at run time, by bit masks (a
@@ -756,6 +780,7 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, Ti
     const int y0 = (tile / a.nstrips) * R;
     const int xs = strip * kStrip2 - 3;
     const int x = xs + lane, y = y0 - 3 + wave;
+    real (*const post)[9][64] = lds.post();
     // first step, from the state buffer
     real g[9];
     unsigned fl;
@@ -781,11 +806,11 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, Ti
         const bool rec = tid < nrec;
         if (rec) {
             rpos = a.recs[r0 + tid].pos;
-            rk = a.recs[r0 + tid].k;
+            rk = a.recs[r0 + tid].meta & 15;
         }
         // the tile's records into LDS, 8 words per thread in flight
         {
-            constexpr int RW = (int)(sizeof(LinkDev<real>) / 4);
+            constexpr int RW = (int)(sizeof(TileRec<real>) / 4);
             const uint32_t* gw = reinterpret_cast<const uint32_t*>(a.recs + r0);
             uint32_t* lw = reinterpret_cast<uint32_t*>(lds.recs);
             const int n = nrec * RW;
@@ -827,16 +852,18 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, Ti
         }
         __syncthreads();
         if (rule1) {
-            const LinkDev<real>& L = lds.recs[tid];
+            const TileRec<real>& L = lds.recs[tid];
+            const int meta = L.meta, kind = link_kind(L);
+            const int g1 = ((meta >> 8) & 255) - 1, g2 = ((meta >> 16) & 255) - 1;
             real drx, jx, jy, pxxx, pyyx, pxyx;
             moments9(h0, drx, jx, jy, pxxx, pyyx, pxyx);
             real dry = real(0), pxxy = real(0), pyyy = real(0), pxyy = real(0);
-            if (L.kind != SLBM_DIRICHLET && L.wy != real(0)) moments9(hb, dry, jx, jy, pxxy, pyyy, pxyy);
+            if (kind != SLBM_DIRICHLET && L.wy != real(0)) moments9(hb, dry, jx, jy, pxxy, pyyy, pxyy);
             const real gk = pick9(h0, rk), gkb = pick9(h0, OPP(rk));
-            const real gky = L.behind ? pick9(hb, rk) : real(0);
-            const real p1 = lds.prof[0][L.g1];
-            const real p2 = (L.kind != SLBM_DIRICHLET && L.g2 >= 0) ? lds.prof[0][L.g2] : real(0);
-            lds.post[rpos >> 8][rk][rpos & 255] =
+            const real gky = ((meta >> 6) & 1) ? pick9(hb, rk) : real(0);
+            const real p1 = lds.prof[0][g1];
+            const real p2 = (kind != SLBM_DIRICHLET && g2 >= 0) ? lds.prof[0][g2] : real(0);
+            lds.rule1()[rpos >> 8][rk - 1][rpos & 255] =
                 rule_value<real>(a, L, gk, gkb, gky, drx, pxxx, pyyx, pxyx, dry, pxxy, pyyy, pxyy, p1, p2);
         }
         if (!a.local) {                                 // uniform over the workgroup
@@ -845,7 +872,7 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, Ti
             if (in && fl != kVoid && fl != 0u) {
 #pragma unroll
                 for (int k = 1; k < 9; ++k)
-                    if ((fl >> (k - 1)) & 1u) g[OPP(k)] = lds.post[wave][k][lane];
+                    if ((fl >> (k - 1)) & 1u) g[OPP(k)] = lds.rule1()[wave][k - 1][lane];
             }
         }
     }
@@ -885,7 +912,7 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, Ti
             return bad;
         }
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds.post[wave - 1][i][lane] = o[i];
+        for (int i = 0; i < 9; ++i) post[wave - 1][i][lane] = o[i];
     }
     if constexpr (!TWO) return bad;
     __syncthreads();
@@ -898,39 +925,40 @@ __device__ __forceinline__ bool step_tile2(const StepArgs<real>& a, int tile, Ti
         int vr = 0, vi = 0, vl = 0;
         bool put = false;
         if (tid < nrec) {
-            const LinkDev<real>& L = lds.recs[tid];
+            const TileRec<real>& L = lds.recs[tid];
             const int w = L.pos >> 8, l = L.pos & 255;
             if (w >= 2 && w <= R + 3 && l >= 2 && l <= 61) {
-                const LdsPrev<real> prev{lds.post, w - 1, l};
+                const int meta = L.meta, kind = link_kind(L);
+                const int g1 = ((meta >> 8) & 255) - 1, g2 = ((meta >> 16) & 255) - 1;
+                const int k = meta & 15, kb = OPP(k), dx = CX(k), dy = CY(k);
+                const LdsPrev<real> prev{post, w - 1, l};
                 real drx, pxxx, pyyx, pxyx;
                 stored_moments<real>(prev, 0, 0, drx, pxxx, pyyx, pxyx);
-                const int k = L.k, kb = OPP(k);
                 const real gk = prev(k, 0, 0), gkb = prev(kb, 0, 0);
-                const real gky = L.behind ? prev(k, -L.dx, -L.dy) : real(0);
+                const real gky = ((meta >> 6) & 1) ? prev(k, -dx, -dy) : real(0);
                 real dry = real(0), pxxy = real(0), pyyy = real(0), pxyy = real(0);
-                if (L.kind != SLBM_DIRICHLET && L.wy != real(0))
-                    stored_moments<real>(prev, -L.dx, -L.dy, dry, pxxy, pyyy, pxyy);
-                const real p1 = lds.prof[1][L.g1];
-                const real p2 = (L.kind != SLBM_DIRICHLET && L.g2 >= 0) ? lds.prof[1][L.g2] : real(0);
+                if (kind != SLBM_DIRICHLET && L.wy != real(0)) stored_moments<real>(prev, -dx, -dy, dry, pxxy, pyyy, pxyy);
+                const real p1 = lds.prof[1][g1];
+                const real p2 = (kind != SLBM_DIRICHLET && g2 >= 0) ? lds.prof[1][g2] : real(0);
                 v = rule_value<real>(a, L, gk, gkb, gky, drx, pxxx, pyyx, pxyx, dry, pxxy, pyyy, pxyy, p1, p2);
-                vr = w - 1 + L.dy;
+                vr = w - 1 + dy;
                 vi = kb;
-                vl = l + L.dx;
+                vl = l + dx;
                 put = true;
             }
         }
         __syncthreads();
-        if (put) lds.post[vr][vi][vl] = v;
+        if (put) post[vr][vi][vl] = v;
         __syncthreads();
     }
     if (wave >= 2 && wave <= R + 3) {
         const int r = wave - 1;
         const int lc = lane < 2 ? 2 : (lane > 61 ? 61 : lane);   // lanes 0, 1, 62, 63: no second-step site
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = lds.post[r - CY(i)][i][lc - CX(i)];
+        for (int i = 0; i < 9; ++i) g[i] = post[r - CY(i)][i][lc - CX(i)];
         const bool live = fl != kVoid;
         if constexpr (!COOP)
-            if (live && fl != 0) boundary_fixup<real>(a, LdsPrev<real>{lds.post, r, lc}, s, fl, a.t_prev + 1, g);
+            if (live && fl != 0) boundary_fixup<real>(a, LdsPrev<real>{post, r, lc}, s, fl, a.t_prev + 1, g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = live ? g[i] : real(0);
         lds.dens[wave][lane] = g[0] + g[1] + g[2] + g[3] + g[4] + g[5] + g[6] + g[7] + g[8];
@@ -1034,13 +1062,14 @@ __global__ __launch_bounds__(1024) void k_step_batch(BatchPlate<real>* __restric
 
 // Up to two time steps of every active plate of a batch in one launch (the
 // tiles of the two-step kernel): each plate takes min(maxk, remaining).
-template <typename real, int W>
+// COOP: every plate carries tile lists (the boundary rules tile by tile).
+template <typename real, int W, bool COOP>
 __global__ __launch_bounds__(1024, W) void k_step2_batch(BatchPlate<real>* __restrict__ plates, int cap, int parity,
                                                       const int* __restrict__ tile_plate,
                                                       const int* __restrict__ tile_start, int ntiles, int maxk,
                                                       int group_shift)
 {
-    __shared__ TileLds<real, false> lds;
+    __shared__ TileLds<real, COOP> lds;
     const int t = xcd_map(blockIdx.x, gridDim.x, group_shift);
     if (t >= ntiles) return;                      // uniform over the workgroup
     const int p = tile_plate[t];
@@ -1050,9 +1079,9 @@ __global__ __launch_bounds__(1024, W) void k_step2_batch(BatchPlate<real>* __res
     if (lt == 0 && threadIdx.x == 0) plates[(parity ^ 1) * cap + p] = batch_next(B, maxk);
     if (!B.active || B.halted) return;
     if (maxk >= 2 && B.remaining >= 2)
-        flag_divergence(B.args.diverged, step_tile2<real, false, true, false>(B.args, lt, lds));
+        flag_divergence(B.args.diverged, step_tile2<real, false, true, COOP>(B.args, lt, lds));
     else
-        flag_divergence(B.args.diverged, step_tile2<real, false, false, false>(B.args, lt, lds));
+        flag_divergence(B.args.diverged, step_tile2<real, false, false, COOP>(B.args, lt, lds));
 }
 
 }  // namespace slbm_dev

@@ -124,6 +124,9 @@ def test_batched_plates_match_the_reference(slbm, prec, launch):
     b = slbm.Batch(8 << 30)
     b.set_launch(*launch)
     slots = [b.add(p, n, prec) for p, n in zip(plates, steps)]
+    for sl in slots:
+        # with two steps per launch every plate carries its tile lists
+        assert b.solver(sl).boundary_lists()[0] == (launch[0] if launch[1] == 58 else 0)
     for k in (5, 32, 1, 40, 64, 128):        # chunks below, at and above the graph size, odd ones
         b.step(k)
     b.sync()
