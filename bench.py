@@ -82,22 +82,6 @@ def measured_traffic(plate, prec, tuned, group=0, lists=False):
     return shape["traffic_bytes_per_launch"] if shape else None
 
 
-def measured_traffic_batch(shape, group, lists=False):
-    """HBM bytes per launch of the batched step kernel on the 64 plates of
-    seed 0, from profiles/traffic_batch64-seed0_fp32.json, or None when there
-    is none for this launch shape or the kernel changed since."""
-    from paper_2208_04088_amd.build import kernel_fingerprint
-    path = os.path.join(ROOT, "profiles", "traffic_batch64-seed0_fp32.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        d = json.load(fh)
-    if d.get("kernel_fingerprint") != kernel_fingerprint():
-        return None
-    entry = d.get("shapes", {}).get(shape_key(shape[0], shape[1], group, lists))
-    return entry["traffic_bytes_per_launch"] if entry else None
-
-
 def cpu_baseline(plate, budget_s=15.0, one_core_s=8.0):
     """The plain CPU reference (fp64) on a bounded number of steps of the
     same plate, timed with every host thread it is allowed and with one."""
@@ -356,7 +340,12 @@ def run_batch(args, slbm, torch, dev, stream):
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic_batch(shape[:2], shape[2], batch_lists),
+            # the plate mix of a batched launch changes as plates finish or are
+            # retired: a profiled run's average bytes per launch (in the batch's
+            # profile) does not describe the timed region's launches
+            "traffic": None,
+            "traffic_note": "per-launch DRAM bytes depend on which plates are still running; the batch's profile "
+                            "gives the average over a profiled run",
             "kernel": "k_step2_batch" if shape[1] == 58 else "k_step_batch",
             "tile_lists": batch_lists,
             "bytes_per_site": bytes_per_site("fp32"),
@@ -386,7 +375,8 @@ def serve_record(args, slbm, torch, stream, both_orders=False):
     t = time.perf_counter()
     trace = configs.served_trace(seed=1, count=args.requests, rate=args.rate)
     t_build = time.perf_counter() - t
-    launch = (6, 58)                     # two steps per launch, 6 rows per tile
+    # two steps per launch; rows per tile and XCD map as given (--seg, --xcd-group), else 10 rows, bands
+    launch = (args.seg, args.strip or 58) if args.seg else (10, 58)
     srv = serve.Server(200 << 30, chunk=64, stream=stream.cuda_stream, launch=launch,
                        max_resident_sites=2_000_000, policy="swf", xcd_group=args.xcd_group, round_ms=20.0,
                        timing_stream=stream)
@@ -394,8 +384,8 @@ def serve_record(args, slbm, torch, stream, both_orders=False):
     srv.close()
     torch.cuda.synchronize()
     st = serve.summary(res)
-    seq_swf = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False,
-                                                    policy="swf"))
+    seq_swf = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, policy="swf",
+                                                    launch=launch, xcd_group=args.xcd_group))
     out = {
         "workload": f"served-trace-seed1-first{args.requests}" + ("" if args.rate == 50 else f"-rate{args.rate:g}"),
         "requests": args.requests, "arrival_rate_per_s": args.rate, "hbm_budget_gb": 200,
@@ -413,7 +403,8 @@ def serve_record(args, slbm, torch, stream, both_orders=False):
         "trace_build_s": round(t_build, 1),
     }
     if both_orders:
-        seq = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, autotune=False))
+        seq = serve.summary(serve.run_one_at_a_time(trace, stream=stream.cuda_stream, launch=launch,
+                                                    xcd_group=args.xcd_group))
         out["one_at_a_time"] = seq
         out["speedup_vs_one_at_a_time_oldest_first"] = round(seq["makespan_s"] / st["makespan_s"], 3)
     return out, trace

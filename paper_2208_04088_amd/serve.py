@@ -204,9 +204,11 @@ class Server:
 
 def run_one_at_a_time(requests: Iterable[Request], precision: str = "fp32", device: int = 0, stream=None,
                       keep_results: bool = False, autotune: bool = True, policy: str = "fcfs",
-                      clock=time.perf_counter, sleep=time.sleep, check_every: int = 1024) -> List[Result]:
+                      clock=time.perf_counter, sleep=time.sleep, check_every: int = 1024,
+                      launch=None, xcd_group: int = 0) -> List[Result]:
     """The same requests served one plate at a time with plain launches
-    (each plate in its autotuned launch shape, or the library's default):
+    (each plate in its autotuned launch shape, in `launch` = (rows, strip)
+    with `xcd_group` when given, or the library's default):
     the oldest waiting request first ("fcfs") or the one with the least work
     ("swf").  A plate is checked for divergence every `check_every` steps
     and stopped when its state has overflowed, as the server retires it."""
@@ -230,7 +232,10 @@ def run_one_at_a_time(requests: Iterable[Request], precision: str = "fp32", devi
         r = reqs[i]
         adm = clock() - t0
         s = slbm.Solver(r.plate, precision, device=device, stream=stream)
-        if autotune:
+        if launch is not None:
+            s.set_launch(*launch)
+            s.set_xcd_group(xcd_group)
+        elif autotune:
             s.autotune()
         done = 0
         while done < r.steps:
