@@ -112,7 +112,25 @@ def cpu_baseline(plate, budget_s=15.0, one_core_s=8.0):
     return {"value": round(v, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{n} steps of {plate.name} ({plate.n_material} material sites), fp64, "
                       f"{dt:.1f} s on {cores} threads; then {n1} steps on 1 thread, {dt1:.1f} s",
-            "value_one_core": round(v1, 3)}
+            "value_one_core": round(v1, 3), **host_cpu()}
+
+
+def host_cpu():
+    """The host CPU model and the hardware threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count()
+    return {"cpu_model": model, "host_threads_available": n}
 
 
 def copy_ceiling(slbm, torch, dev, stream):
@@ -173,7 +191,7 @@ def cpu_baseline3(box, budget_s=15.0):
     # numpy's elementwise loops and einsum (no BLAS path) run on one thread
     return {"value": round(sample.n_sites * k / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{k} steps of a {sample.nx}x{sample.ny}x{sample.nz} box of the same configuration "
-                      f"({sample.n_sites} sites), numpy fp64 on one thread, {dt:.1f} s"}
+                      f"({sample.n_sites} sites), numpy fp64 on one thread, {dt:.1f} s", **host_cpu()}
 
 
 def run_3d(args, torch, dev, stream, n):

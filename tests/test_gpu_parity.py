@@ -272,7 +272,7 @@ def test_two_steps_per_launch_match_single_steps(slbm, prec, case):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["mixed", "mixed_order1", "periodic", "small_periodic"])
+@pytest.mark.parametrize("case", ["mixed", "mixed_order1", "periodic", "small_periodic", "big_hole"])
 def test_tile_lists_match_site_by_site_rules(slbm, prec, case):
     """With strip 58 the library lists each tile's cut links and the tile
     evaluates their rules together (first step from global memory, second
@@ -280,8 +280,11 @@ def test_tile_lists_match_site_by_site_rules(slbm, prec, case):
     same, so the state must be bit-identical to single steps (which take the
     rules site by site) -- edges, corners, a crack, a curved hole, step and
     ramped Dirichlet and Neumann groups, both extrapolation orders, periodic
-    axes whose tile footprints wrap (a plate narrower than a strip)."""
-    if case == "periodic":
+    axes whose tile footprints wrap (a plate narrower than a strip), and a hole
+    wider than a strip, whose tiles without material outputs are skipped."""
+    if case == "big_hole":
+        p, n = configs.hole_plate(200, 80.0, lam=0.05, tau=0.55), 41
+    elif case == "periodic":
         p, n = mixed_plate(64, 40, seed=1, periodic=True), 41
     elif case == "small_periodic":
         p = G.build_plate(40, 23, lam=0.06, mu=0.05, tau=0.6, periodic_x=True,
