@@ -218,6 +218,24 @@ int slbm_set_launch(slbm_handle h, int32_t seg_rows, int32_t strip);
  * NULL. */
 int slbm_boundary_lists(slbm_handle h, int32_t* rows, int64_t* records, int32_t* max_per_tile);
 
+/* Host only (no device call): the layout of those lists for an nx x ny grid
+ * (periodic_x, periodic_y as in slbm_params) and tiles of `rows` rows (1 to
+ * 10) of 58-column strips.  Tile t (strip fastest) reaches rows y0 - 3 ..
+ * y0 + rows + 2 and columns xs - 3 .. xs + 60 (y0 = rows (t / strips),
+ * xs = 58 (t mod strips)), wrapping on periodic axes; wave w and lane l of the
+ * tile hold row y0 - 3 + w and column xs - 3 + l.  Every cut link i (its site
+ * link_sites[i] = y nx + x, as slbm_link.site) appears in each tile whose
+ * reach holds its site, once per image of the site there.  Writes
+ * tile_start[0 .. n_tiles] (tile t's records are tile_start[t] ..
+ * tile_start[t + 1]), and for each record the link index (rec_link) and the
+ * position w << 8 | l (rec_pos), `capacity` entries at most (SLBM_E_INVAL if
+ * there are more; pass NULL arrays to get the counts first).  Any pointer may
+ * be NULL.  SLBM_E_INVAL for a bad grid, rows or site. */
+int slbm_tile_list_layout(int32_t nx, int32_t ny, int32_t periodic_x, int32_t periodic_y, int32_t rows,
+                          int32_t n_links, const int32_t* link_sites, int32_t* tile_start, int32_t* rec_link,
+                          int32_t* rec_pos, int64_t capacity, int64_t* n_tiles, int64_t* n_records,
+                          int32_t* max_per_tile);
+
 /* How the step's workgroups are dealt to the GPU's 8 XCDs: 0 (the default)
  * gives each XCD one contiguous band of tiles; group g, a power of two up to
  * 64, gives each XCD groups of g consecutive workgroups, the groups of the

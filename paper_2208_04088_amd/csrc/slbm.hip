@@ -43,6 +43,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <climits>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -662,34 +663,33 @@ void axis_images(int c, int n, bool per, int lo, int hi, F&& f)
 
 long long floor_div(long long a, long long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-// The cut links each tile of the two-step kernel (seg rows, 58-column strips)
-// sees in its footprint -- rows y0 - 3 .. y0 + seg + 2, columns xs - 3 ..
-// xs + 60, wave w and lane l at y0 - 3 + w, xs - 3 + l -- each the link's
-// coefficients with its position (w << 8 | l).  Tile t's records are
-// recs[rec_start[t] .. rec_start[t + 1]).  When a tile has more than the
-// cooperative kernel takes (or the plate more groups than it tabulates), no
-// lists are kept and the two-step kernel takes the rules site by site.
-template <typename real>
-int build_tile_records(slbm_s* h, int seg)
+// Where the cut links sit in the tiles of the two-step kernel (R rows,
+// 58-column strips): a tile's reach is rows y0 - 3 .. y0 + R + 2 and columns
+// xs - 3 .. xs + 60, wave w and lane l at y0 - 3 + w, xs - 3 + l, wrapping on
+// periodic axes.  Every link (site y nx + x) appears in each tile whose reach
+// holds its site, once per image of the site there.  start[t] .. start[t + 1]
+// index tile t's records, each a link and a position (w << 8 | l); `most` is
+// the largest count in one tile.  Host only.
+struct TileLayout {
+    std::vector<int32_t> start, link, pos;
+    int32_t most = 0;
+    long long ntiles = 0;
+};
+
+TileLayout tile_layout(int nx, int ny, bool px, bool py, int R, const int32_t* site, int n, int64_t cap)
 {
-    seg = seg2_rows(seg);
-    if (h->rec_seg == seg) return SLBM_OK;
-    drop_tile_records(h);
-    h->rec_seg = seg;
-    if (h->n_links == 0 || h->ngroups > kTileGroupCap) return SLBM_OK;
-    const int R = seg, nx = h->nx, ny = h->ny;
+    TileLayout out;
     const int nstrips = (nx + kStrip2 - 1) / kStrip2, ntr = (ny + R - 1) / R;
-    const long long ntiles = (long long)nstrips * ntr;
-    const LinkDev<real>* L = reinterpret_cast<const LinkDev<real>*>(h->link_host.data());
+    out.ntiles = (long long)nstrips * ntr;
     auto each = [&](auto&& f) {
-        for (int i = 0; i < h->n_links; ++i) {
-            const int site = h->link_site[i], x = site % nx, y = site / nx;
-            axis_images(y, ny, h->py != 0, -3, ntr * R + 2, [&](int yh) {
+        for (int i = 0; i < n; ++i) {
+            const int x = site[i] % nx, y = site[i] / nx;
+            axis_images(y, ny, py, -3, ntr * R + 2, [&](int yh) {
                 const long long tr0 = std::max<long long>(0, -floor_div(-(yh - R - 2), R));
                 const long long tr1 = std::min<long long>(ntr - 1, floor_div(yh + 3, R));
                 for (long long tr = tr0; tr <= tr1; ++tr) {
                     const int w = yh - (int)(tr * R - 3);
-                    axis_images(x, nx, h->px != 0, -3, nstrips * kStrip2 + 2, [&](int xh) {
+                    axis_images(x, nx, px, -3, nstrips * kStrip2 + 2, [&](int xh) {
                         const long long s0 = std::max<long long>(0, -floor_div(-(xh - 60), kStrip2));
                         const long long s1 = std::min<long long>(nstrips - 1, floor_div(xh + 3, kStrip2));
                         for (long long st = s0; st <= s1; ++st)
@@ -699,19 +699,55 @@ int build_tile_records(slbm_s* h, int seg)
             });
         }
     };
-    std::vector<int32_t> start((size_t)ntiles + 1, 0);
-    each([&](long long t, int, int, int) { ++start[(size_t)t + 1]; });
-    int32_t most = 0;
-    for (long long t = 0; t < ntiles; ++t) most = std::max(most, start[(size_t)t + 1]);
-    // one record per thread of the tile's workgroup, and what its LDS holds
-    if (most > std::min(kTileRecCap, 64 * (R + 6))) return SLBM_OK;
-    for (long long t = 0; t < ntiles; ++t) start[(size_t)t + 1] += start[(size_t)t];
-    const size_t total = (size_t)start[(size_t)ntiles];
-    std::vector<TileRec<real>> rec(total);
-    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    out.start.assign((size_t)out.ntiles + 1, 0);
+    each([&](long long t, int, int, int) { ++out.start[(size_t)t + 1]; });
+    for (long long t = 0; t < out.ntiles; ++t) out.most = std::max(out.most, out.start[(size_t)t + 1]);
+    int64_t total = 0;
+    for (long long t = 0; t < out.ntiles; ++t) total += out.start[(size_t)t + 1];
+    if (total > INT32_MAX) {                           // offsets are 32-bit: no lists
+        out.most = INT32_MAX;
+        out.start.clear();
+        return out;
+    }
+    for (long long t = 0; t < out.ntiles; ++t) out.start[(size_t)t + 1] += out.start[(size_t)t];
+    if (out.most > cap) return out;                    // counts only
+    out.link.resize((size_t)total);
+    out.pos.resize((size_t)total);
+    std::vector<int32_t> fill(out.start.begin(), out.start.end() - 1);
     each([&](long long t, int w, int l, int i) {
-        TileRec<real>& r = rec[(size_t)fill[(size_t)t]++];
-        const LinkDev<real>& d = L[i];
+        const int32_t k = fill[(size_t)t]++;
+        out.link[(size_t)k] = i;
+        out.pos[(size_t)k] = (w << 8) | l;
+    });
+    return out;
+}
+
+// The plate's tile lists on the device for tiles of seg rows: tile_layout's
+// records, each with its link's coefficients (TileRec).  When a tile has more
+// than the cooperative kernel takes (or the plate more groups than it
+// tabulates), no lists are kept and the two-step kernel takes the rules site
+// by site.
+template <typename real>
+int build_tile_records(slbm_s* h, int seg)
+{
+    seg = seg2_rows(seg);
+    if (h->rec_seg == seg) return SLBM_OK;
+    drop_tile_records(h);
+    h->rec_seg = seg;
+    if (h->n_links == 0 || h->ngroups > kTileGroupCap) return SLBM_OK;
+    const int R = seg;
+    // one record per thread of the tile's workgroup, and what its LDS holds
+    const int cap = std::min(kTileRecCap, 64 * (R + 6));
+    const TileLayout lay = tile_layout(h->nx, h->ny, h->px != 0, h->py != 0, R, h->link_site.data(), h->n_links, cap);
+    if (lay.most > cap) return SLBM_OK;
+    const std::vector<int32_t>& start = lay.start;
+    const int32_t most = lay.most;
+    const size_t total = lay.link.size();
+    const LinkDev<real>* L = reinterpret_cast<const LinkDev<real>*>(h->link_host.data());
+    std::vector<TileRec<real>> rec(total);
+    for (size_t k = 0; k < total; ++k) {
+        TileRec<real>& r = rec[k];
+        const LinkDev<real>& d = L[lay.link[k]];
         r.kappa = d.kappa; r.wx = d.wx; r.wy = d.wy; r.D = d.D;
         for (int j = 0; j < 4; ++j) r.be[j] = d.be[j];
         for (int j = 0; j < 3; ++j) {
@@ -720,8 +756,8 @@ int build_tile_records(slbm_s* h, int seg)
             r.E3[j] = d.E3[j];
         }
         r.meta = d.k | (d.kind << 4) | (d.behind << 6) | ((d.g1 + 1) << 8) | ((d.g2 + 1) << 16);
-        r.pos = (w << 8) | l;
-    });
+        r.pos = lay.pos[k];
+    }
     hipError_t e = dev_alloc(h, (void**)&h->rec_start, start.size() * sizeof(int32_t));
     if (e == hipSuccess) e = dev_alloc(h, &h->recs, std::max<size_t>(1, total) * sizeof(TileRec<real>));
     if (e != hipSuccess) {
@@ -1571,6 +1607,33 @@ int slbm_set_xcd_group(slbm_handle h, int32_t group)
         if (h->batch) return fail(SLBM_E_INVAL, "the plate belongs to a batch (only readouts go through its handle)");
         if (!valid_group(group)) return fail(SLBM_E_INVAL, "xcd group must be 0 (bands) or a power of two up to 64");
         h->group = group;
+        return SLBM_OK;
+    });
+}
+
+int slbm_tile_list_layout(int32_t nx, int32_t ny, int32_t periodic_x, int32_t periodic_y, int32_t rows,
+                          int32_t n_links, const int32_t* link_sites, int32_t* tile_start, int32_t* rec_link,
+                          int32_t* rec_pos, int64_t capacity, int64_t* n_tiles, int64_t* n_records,
+                          int32_t* max_per_tile)
+{
+    return guarded([&]() -> int {
+        if (nx < 1 || ny < 1 || (long long)nx * ny > (1LL << 28)) return fail(SLBM_E_INVAL, "bad grid");
+        if (rows < 1 || rows > kMaxTileRows2) return fail(SLBM_E_INVAL, "rows per tile must be in [1, 10]");
+        if (n_links < 0 || (n_links > 0 && !link_sites)) return fail(SLBM_E_INVAL, "bad link list");
+        for (int i = 0; i < n_links; ++i)
+            if (link_sites[i] < 0 || (long long)link_sites[i] >= (long long)nx * ny)
+                return fail(SLBM_E_INVAL, "link %d: site out of the grid", i);
+        const TileLayout lay = tile_layout(nx, ny, periodic_x != 0, periodic_y != 0, rows, link_sites, n_links,
+                                           INT64_MAX);
+        if (lay.start.empty()) return fail(SLBM_E_UNSUPPORTED, "more than 2^31 - 1 tile records");
+        const int64_t total = lay.start[(size_t)lay.ntiles];
+        if (n_tiles) *n_tiles = lay.ntiles;
+        if (n_records) *n_records = total;
+        if (max_per_tile) *max_per_tile = lay.most;
+        if (tile_start) std::memcpy(tile_start, lay.start.data(), lay.start.size() * sizeof(int32_t));
+        if ((rec_link || rec_pos) && total > capacity) return fail(SLBM_E_INVAL, "capacity below the record count");
+        if (rec_link) std::memcpy(rec_link, lay.link.data(), (size_t)total * sizeof(int32_t));
+        if (rec_pos) std::memcpy(rec_pos, lay.pos.data(), (size_t)total * sizeof(int32_t));
         return SLBM_OK;
     });
 }

@@ -23,7 +23,7 @@ PRECISION = {"fp64": FP64, "f64": FP64, "fp32": FP32, "f32": FP32}
 EXPORTS = [
     "slbm_create", "slbm_init_fields", "slbm_step", "slbm_sync", "slbm_moments",
     "slbm_displacement", "slbm_displacement_device", "slbm_displacement_device_noalloc", "slbm_moments_device", "slbm_time", "slbm_set_launch", "slbm_set_xcd_group", "slbm_get_launch", "slbm_autotune",
-    "slbm_boundary_lists", "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
+    "slbm_boundary_lists", "slbm_tile_list_layout", "slbm_save", "slbm_load", "slbm_device_bytes", "slbm_destroy", "slbm_copy", "slbm_last_error",
     "slbm_batch_create", "slbm_batch_add", "slbm_batch_step", "slbm_batch_poll", "slbm_batch_handle",
     "slbm_batch_remaining", "slbm_batch_displacement", "slbm_batch_remove", "slbm_batch_set_launch",
     "slbm_batch_set_xcd_group", "slbm_batch_get_launch", "slbm_batch_autotune", "slbm_batch_sync",
@@ -85,6 +85,8 @@ def lib():
         "slbm_set_xcd_group": [vp, i32],
         "slbm_get_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "slbm_boundary_lists": [vp, C.POINTER(i32), C.POINTER(C.c_int64), C.POINTER(i32)],
+        "slbm_tile_list_layout": [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, C.c_int64,
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(i32)],
         "slbm_autotune": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)],
         "slbm_save": [vp, vp, C.POINTER(C.c_size_t)],
         "slbm_load": [vp, vp, C.c_size_t],
@@ -152,6 +154,22 @@ def copy(dst_ptr, src_ptr, nbytes, device=0, stream=None):
     """slbm_copy: plain device copy (the streaming reference)."""
     _check(lib().slbm_copy(C.c_void_p(int(dst_ptr)), C.c_void_p(int(src_ptr)), int(nbytes), int(device),
                            None if stream is None else C.c_void_p(int(stream))))
+
+
+def tile_list_layout(nx, ny, link_sites, rows, periodic_x=False, periodic_y=False):
+    """slbm_tile_list_layout (host only): (tile_start, rec_link, rec_pos,
+    most) of the two-step kernel's per-tile cut-link lists."""
+    sites = np.ascontiguousarray(link_sites, dtype=np.int32)
+    nt, nr, most = C.c_int64(), C.c_int64(), C.c_int32()
+    args = (int(nx), int(ny), int(bool(periodic_x)), int(bool(periodic_y)), int(rows), len(sites),
+            sites.ctypes.data if len(sites) else None)
+    _check(lib().slbm_tile_list_layout(*args, None, None, None, 0, C.byref(nt), C.byref(nr), C.byref(most)))
+    start = np.empty(nt.value + 1, dtype=np.int32)
+    link = np.empty(max(nr.value, 1), dtype=np.int32)
+    pos = np.empty(max(nr.value, 1), dtype=np.int32)
+    _check(lib().slbm_tile_list_layout(*args, start.ctypes.data, link.ctypes.data, pos.ctypes.data, nr.value,
+                                       C.byref(nt), C.byref(nr), C.byref(most)))
+    return start, link[:nr.value], pos[:nr.value], most.value
 
 
 class Solver:
