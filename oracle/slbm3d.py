@@ -124,13 +124,19 @@ class Oracle3D:
         self.tau = self.dt(b.tau)
         self.F = np.array(b.force, dtype=self.dt) / self.dt(self.s_sigma)
         self.walls = None
+        if b.neumann_order not in (0, 1):
+            raise ValueError("neumann_order must be 0 or 1")
+        self.norder = b.neumann_order
         if b.x_walls is not None:
             self.walls = []
             for wall in b.x_walls:
                 if wall.kind not in (DIRICHLET, NEUMANN):
                     raise ValueError("wall kind must be Dirichlet or Neumann")
+                if not 0.0 < wall.q <= 1.0:
+                    raise ValueError("wall q must be in (0, 1]")
                 scale = self.s_v if wall.kind == DIRICHLET else self.s_sigma
-                self.walls.append((wall.kind, np.array(wall.value, dtype=self.dt) / self.dt(scale)))
+                self.walls.append((wall.kind, np.array(wall.value, dtype=self.dt) / self.dt(scale),
+                                   self.dt(wall.q)))
         # cut[i] marks the sites whose link i leaves the material through a wall
         self.cut = np.zeros((Q,) + self.shape, dtype=bool)
         if self.walls is not None:
@@ -207,12 +213,21 @@ class Oracle3D:
 
     def _walls(self, fcol, fnew):
         """Cut links (x, i) at the walls: the population returning to x in
-        direction ibar (q = 1/2).  rho and P at x are the step's moments,
-        equal to those of f_col (collision conserves both in this closure)."""
+        direction ibar, from the post-collision populations (section 4: eq:bbcon
+        and eq:abbcon at q = 1/2, eq:bbnoncon and eq:abbnoncon otherwise).  rho
+        and P at x are the step's moments, equal to those of f_col (collision
+        conserves both in this closure).  The site behind x along the link,
+        x - c_i, is the next site inward (x = 1 or nx - 2); a one-site-wide
+        slab has none, and its links lose the terms that need it (q taken as
+        1/2), as where two walls cut opposite links in two dimensions."""
         rho, _, P = self._moments(fcol)
-        for side, (kind, value) in enumerate(self.walls):
+        nx = self.shape[2]
+        behind = nx >= 2
+        for side, (kind, value, q) in enumerate(self.walls):
             xs = 0 if side == 0 else -1
             normal = np.array([-1.0, 0.0, 0.0]) if side == 0 else np.array([1.0, 0.0, 0.0])
+            kappa = (1 - 2 * q) / (1 + 2 * q) if behind else self.dt(0)
+            beta = 2 / (1 + 2 * q) if behind else self.dt(1)
             r = rho[:, :, xs]
             Px = P[:, :, :, :, xs]
             for i in range(1, Q):
@@ -222,25 +237,40 @@ class Oracle3D:
                     continue
                 ib = OPP[i]
                 fi = fcol[i, :, :, xs]
+                fib = fcol[ib, :, :, xs]
+                # f_i at the site behind, x - c_i (wrapped in y and z)
+                fi_y = self._neighbour(fcol[i], i, -1)[:, :, xs] if behind else 0
                 c = C[i]
                 if kind == DIRICHLET:
-                    # eq:bbcon with j* = rho(x) v*
+                    # eq:bbcon / eq:bbnoncon with j* = rho(x) v*
                     jstar = r[None] * value[:, None, None]
-                    fnew[ib, :, :, xs] = fi - 2 * self.W[i] * (c[0] * jstar[0] + c[1] * jstar[1] + c[2] * jstar[2]) / self.cs2
+                    cj = c[0] * jstar[0] + c[1] * jstar[1] + c[2] * jstar[2]
+                    fnew[ib, :, :, xs] = fi + kappa * (fi_y - fib) - beta * 2 * self.W[i] * cj / self.cs2
                 else:
-                    # eq:abbcon with the boundary Poisson stress of the traction
+                    # eq:abbcon / eq:abbnoncon: rho_bd and the tangential block of the
+                    # boundary Cauchy stress at the site, or extrapolated along the
+                    # link, (1 + q) X(x) - q X(x - c_i); the normal part from the
+                    # traction: sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n
                     sig = self._cauchy(r, Px)
+                    rbd = r
+                    if behind and self.norder == 1:
+                        r_y = self._neighbour(rho, i, -1)[:, :, xs]
+                        P_y = np.stack([np.stack([self._neighbour(P[a, b_], i, -1)[:, :, xs]
+                                                  for b_ in range(3)]) for a in range(3)])
+                        sig = (1 + q) * sig - q * self._cauchy(r_y, P_y)
+                        rbd = (1 + q) * r - q * r_y
                     Pi = (np.eye(3) - np.outer(normal, normal)).astype(self.dt)
                     st = np.einsum("ab,bc...,cd->ad...", Pi, sig, Pi)
                     tn = value @ normal
                     for a in range(3):
                         for b_ in range(3):
                             st[a, b_] = st[a, b_] + normal[a] * value[b_] + value[a] * normal[b_] - tn * normal[a] * normal[b_]
+                    # eq:bcchainneum with eq:approxdiv at rho_bd
                     Pstar = -st
                     for a in range(3):
-                        Pstar[a, a] = Pstar[a, a] + (self.lam - self.mu) * (1.0 - r)
-                    E = 2 * equilibrium(r, np.zeros((3,) + r.shape, dtype=self.dt), Pstar)[i]
-                    fnew[ib, :, :, xs] = -fi + E
+                        Pstar[a, a] = Pstar[a, a] + (self.lam - self.mu) * (1.0 - rbd)
+                    E = 2 * equilibrium(rbd, np.zeros((3,) + rbd.shape, dtype=self.dt), Pstar)[i]
+                    fnew[ib, :, :, xs] = -fi - kappa * (fi_y + fib) + beta * E
 
     # ------------------------------------------------------------ fields
     def init_fields(self, rho=None, vel=None, sigma=None, u=None):

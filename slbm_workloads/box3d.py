@@ -1,6 +1,8 @@
 """Three-dimensional inputs: a box of sites, periodic in y and z, either
-periodic in x or closed by two lattice-conforming walls at x = -1/2 and
-x = nx - 1/2.  Each wall carries a Dirichlet wall velocity or a Neumann
+periodic in x or closed by two walls, planes normal to x that cross the links
+leaving the material at a fraction q of their length (q = 1/2: the
+lattice-conforming planes x = -1/2 and x = nx - 1/2; in general x = -q and
+x = nx - 1 + q).  Each wall carries a Dirichlet wall velocity or a Neumann
 traction (user units), applied from the first step.
 
 Description only: no arithmetic of the method.  Seeded initial fields for
@@ -23,6 +25,7 @@ Vec3 = Tuple[float, float, float]
 class Wall3:
     kind: int                      # DIRICHLET (value: wall velocity) or NEUMANN (value: traction)
     value: Vec3 = (0.0, 0.0, 0.0)
+    q: float = 0.5                 # fraction of a cut link inside the material, (0, 1]
 
 
 @dataclass
@@ -35,10 +38,13 @@ class Box3:
     tau: float
     rho: float = 1.0
     force: Vec3 = (0.0, 0.0, 0.0)
-    # None: periodic in x; else the walls at x = -1/2 and x = nx - 1/2
+    # None: periodic in x; else the walls at x = -q and x = nx - 1 + q
     x_walls: Optional[Tuple[Wall3, Wall3]] = None
     name: str = ""
     steps: int = 0
+    # Neumann walls: rho_bd and the tangential stress taken at the boundary
+    # site (0) or extrapolated along the link from the site behind it (1)
+    neumann_order: int = 0
 
     @property
     def n_sites(self) -> int:
@@ -56,9 +62,10 @@ def periodic_box3(nx, ny, nz, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0, force=(0.
 
 
 def slab3(nx, ny, nz, left: Wall3, right: Wall3, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0,
-          force=(0.0, 0.0, 0.0), name="", steps=0) -> Box3:
+          force=(0.0, 0.0, 0.0), name="", steps=0, neumann_order=0) -> Box3:
     return Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, rho=rho, force=tuple(force),
-                x_walls=(left, right), name=name or f"slab{nx}x{ny}x{nz}", steps=steps)
+                x_walls=(left, right), name=name or f"slab{nx}x{ny}x{nz}", steps=steps,
+                neumann_order=neumann_order)
 
 
 def cube_pulled(n=256, *, mu=0.05, lam=0.05, load=1e-3, tau=0.55, steps=2000) -> Box3:

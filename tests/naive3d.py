@@ -1,8 +1,10 @@
 """Brute-force loop form of one D3Q19 step of the solid lattice-Boltzmann
 method (test helper): explicit per-site loops and neighbour indices, written
 from the definitions (eq:moments, eq:sourceterm, eq:fieq, eq:coll,
-eq:stream, eq:bbcon, eq:abbcon at q = 1/2) without sharing code with the
-reference it checks.  Lattice units inside; the box in user units."""
+eq:stream, eq:bbcon and eq:abbcon, or eq:bbnoncon and eq:abbnoncon for walls
+at q != 1/2, with rho_bd and the tangential stress at the site or
+extrapolated along the link) without sharing code with the reference it
+checks.  Lattice units inside; the box in user units."""
 import itertools
 import math
 
@@ -93,20 +95,41 @@ def naive_step(box, f, U, order):
                 continue
             # the link leaves through a wall: the population returns to x
             side = 0 if x + c[0] < 0 else 1
-            kind, value = walls[side].kind, walls[side].value
+            kind, value, q = walls[side].kind, walls[side].value, walls[side].q
             cb = tuple(-a for a in c)
             fc = fcol[idx[c], z, y, x]
+            fcb = fcol[idx[cb], z, y, x]
             r = sum(fcol[idx[d], z, y, x] for d in vel)
             Pm = [[sum(fcol[idx[d], z, y, x] * d[a] * d[b] for d in vel) for b in range(3)] for a in range(3)]
+            # the site behind x along the link, x - c (inside when nx > 1)
+            has_b = nx > 1
+            if has_b:
+                bx, by, bz = wrap(x - c[0], y - c[1], z - c[2])
+                fb = fcol[idx[c], bz, by, bx]
+                rb = sum(fcol[idx[d], bz, by, bx] for d in vel)
+                Pb = [[sum(fcol[idx[d], bz, by, bx] * d[a] * d[b] for d in vel) for b in range(3)] for a in range(3)]
+                kap, bet = (1 - 2 * q) / (1 + 2 * q), 2 / (1 + 2 * q)
+            else:
+                fb, kap, bet = 0.0, 0.0, 1.0
             if kind == DIRICHLET:
                 vL = [v / s_v for v in value]
-                fnew[idx[cb], z, y, x] = fc - 6 * _w(c) * sum(c[a] * r * vL[a] for a in range(3))
+                fnew[idx[cb], z, y, x] = (fc + kap * (fb - fcb)
+                                          - bet * 6 * _w(c) * sum(c[a] * r * vL[a] for a in range(3)))
             else:
                 t = [v / s_sigma for v in value]
                 n = [-1.0 if side == 0 else 1.0, 0.0, 0.0]
-                sig = [[-Pm[a][b] + (lamL - muL) * (1 - r) * (a == b) for b in range(3)] for a in range(3)]
+
+                def cauchy(rr, PP_):
+                    return [[-PP_[a][b] + (lamL - muL) * (1 - rr) * (a == b) for b in range(3)] for a in range(3)]
+
+                sig = cauchy(r, Pm)
+                rbd = r
+                if has_b and box.neumann_order == 1:
+                    sb = cauchy(rb, Pb)
+                    sig = [[(1 + q) * sig[a][b] - q * sb[a][b] for b in range(3)] for a in range(3)]
+                    rbd = (1 + q) * r - q * rb
                 # boundary stress: normal part from the traction, tangential
-                # block (rows and columns y, z) from the site
+                # block (rows and columns y, z) from the site or extrapolated
                 st = [[0.0] * 3 for _ in range(3)]
                 for a in (1, 2):
                     for b in (1, 2):
@@ -114,6 +137,6 @@ def naive_step(box, f, U, order):
                 for a in range(3):
                     st[a][0] = t[a] * n[0]
                     st[0][a] = t[a] * n[0]
-                Ps = [[-st[a][b] + (lamL - muL) * (1 - r) * (a == b) for b in range(3)] for a in range(3)]
-                fnew[idx[cb], z, y, x] = -fc + 2 * _feq(c, r, [0.0, 0.0, 0.0], Ps)
+                Ps = [[-st[a][b] + (lamL - muL) * (1 - rbd) * (a == b) for b in range(3)] for a in range(3)]
+                fnew[idx[cb], z, y, x] = -fc - kap * (fb + fcb) + bet * 2 * _feq(c, rbd, [0.0, 0.0, 0.0], Ps)
     return fnew, Un

@@ -157,16 +157,19 @@ def test_wave_speeds_along_a_face_diagonal():
         assert w / kn == pytest.approx(target, rel=5e-3), (comp, w / kn, target)
 
 
-def test_neumann_walls_hold_a_uniform_stress():
-    """Patch test of eq:abbcon: a uniform stress with the matching tractions
-    on both walls (t* = sigma.n, n = -x and +x) is an exact steady state, for
-    every component: a wrong sign or projection in the boundary stress, or a
-    dropped tangential block, breaks it."""
+@pytest.mark.parametrize("q,order", [(0.5, 0), (0.2, 0), (0.8, 0), (0.5, 1), (0.3, 1), (1.0, 1)])
+def test_neumann_walls_hold_a_uniform_stress(q, order):
+    """Patch test of eq:abbcon (q = 1/2) and eq:abbnoncon: a uniform stress
+    with the matching tractions on both walls (t* = sigma.n, n = -x and +x)
+    is an exact steady state, for every component, at any q and with rho_bd
+    and the tangential stress at the site or extrapolated: a wrong sign or
+    projection in the boundary stress, a dropped tangential block, or kappa
+    and beta that do not satisfy 1 + 2 kappa = 2 beta break it."""
     s0 = np.array([2e-4, -1e-4, 3e-4, 1.5e-4, -2.5e-4, 0.5e-4])   # xx yy zz xy xz yz
     S = sym_to_full(s0[:, None])[:, :, 0]
-    left = B.Wall3(B.NEUMANN, tuple(-S[:, 0]))
-    right = B.Wall3(B.NEUMANN, tuple(S[:, 0]))
-    b = B.slab3(6, 3, 2, left, right, lam=0.1, mu=0.05, tau=0.6)
+    left = B.Wall3(B.NEUMANN, tuple(-S[:, 0]), q=q)
+    right = B.Wall3(B.NEUMANN, tuple(S[:, 0]), q=1.0 - q / 2)
+    b = B.slab3(6, 3, 2, left, right, lam=0.1, mu=0.05, tau=0.6, neumann_order=order)
     o = Oracle3D(b)
     sig = np.broadcast_to(s0[:, None, None, None], (6,) + o.shape)
     o.init_fields(sigma=sig)
@@ -179,11 +182,14 @@ def test_neumann_walls_hold_a_uniform_stress():
     assert np.abs(m1[0] - m0[0]).max() < 1e-13
 
 
-def test_dirichlet_walls_carry_a_uniform_translation():
-    """Patch test of eq:bbcon: walls moving with the material's uniform
-    velocity keep it in rigid translation; the displacement grows as v t."""
+@pytest.mark.parametrize("q", [0.5, 0.2, 0.8, 1.0])
+def test_dirichlet_walls_carry_a_uniform_translation(q):
+    """Patch test of eq:bbcon (q = 1/2) and eq:bbnoncon: walls moving with the
+    material's uniform velocity keep it in rigid translation at any q (the
+    interpolation weights satisfy beta - kappa = 1); the displacement grows
+    as v t."""
     v0 = np.array([3e-4, -2e-4, 1e-4])
-    b = B.slab3(5, 2, 3, B.Wall3(B.DIRICHLET, tuple(v0)), B.Wall3(B.DIRICHLET, tuple(v0)),
+    b = B.slab3(5, 2, 3, B.Wall3(B.DIRICHLET, tuple(v0), q=q), B.Wall3(B.DIRICHLET, tuple(v0), q=q),
                 lam=0.1, mu=0.05, tau=0.6)
     o = Oracle3D(b)
     o.init_fields(vel=np.broadcast_to(v0[:, None, None, None], (3,) + o.shape))
@@ -196,20 +202,23 @@ def test_dirichlet_walls_carry_a_uniform_translation():
     assert np.abs(u - (v0 * 9 * o.dt_user)[:, None, None, None]).max() < 1e-13
 
 
-@pytest.mark.parametrize("mode", ["tension", "shear"])
-def test_step_traction_launches_the_one_dimensional_wave(mode):
-    """A step tension sigma_xx = s0 (or shear sigma_xy = s0) on the face
-    x = -1/2 of a long slab sends a plane pressure (shear) wave in at c_d
-    (c_s); behind its front the material moves with v = -s0/(rho c) along x
-    (y), by momentum balance across the front, until the reflection from the
-    free far face returns.  The shear case pins the tangential part of the
-    Neumann rule's boundary stress."""
+@pytest.mark.parametrize("mode,q,order", [("tension", 0.5, 0), ("shear", 0.5, 0), ("tension", 0.2, 0),
+                                          ("shear", 0.8, 0), ("tension", 0.3, 1), ("shear", 0.5, 1)])
+def test_step_traction_launches_the_one_dimensional_wave(mode, q, order):
+    """A step tension sigma_xx = s0 (or shear sigma_xy = s0) on the face of a
+    long slab (the wall crossing the boundary links at q) sends a plane
+    pressure (shear) wave in at c_d (c_s); behind its front the material moves
+    with v = -s0/(rho c) along x (y), by momentum balance across the front,
+    until the reflection from the free far face returns.  The shear case pins
+    the tangential part of the Neumann rule's boundary stress; q != 1/2 and
+    the extrapolated rule pin eq:abbnoncon's kappa, beta and rho_bd."""
     nx, s0 = 240, 1e-4
     mu, lam = 0.05, 0.05
     k = 0 if mode == "tension" else 1
     t = [0.0, 0.0, 0.0]
     t[k] = -s0
-    b = B.slab3(nx, 1, 1, B.Wall3(B.NEUMANN, tuple(t)), B.Wall3(B.NEUMANN), lam=lam, mu=mu, tau=0.55)
+    b = B.slab3(nx, 1, 1, B.Wall3(B.NEUMANN, tuple(t), q=q), B.Wall3(B.NEUMANN, q=q), lam=lam, mu=mu,
+                tau=0.55, neumann_order=order)
     o = Oracle3D(b)
     c_lat = np.sqrt(lam / mu / 3 + 2 / 3) if mode == "tension" else np.sqrt(1 / 3)
     steps = int(0.75 * nx / c_lat)
@@ -224,15 +233,98 @@ def test_step_traction_launches_the_one_dimensional_wave(mode):
     assert np.abs(other).max() < 1e-6 * s0 / (b.rho * c_user)
 
 
+@pytest.mark.parametrize("kind", ["neumann", "dirichlet"])
+@pytest.mark.parametrize("q_left,q_right", [(0.5, 0.5), (0.3, 0.8), (0.9, 0.15)])
+def test_wall_rules_are_exact_for_linear_fields(kind, q_left, q_right):
+    """Section 4.2 in three dimensions: for an equilibrium field varying
+    linearly across the wall, a cut link returns the population the lattice
+    would have streamed in from the virtual site x + c_i had the field
+    continued -- for every q.  The Neumann rule (j = 0) needs rho_bd and the
+    tangential block of the stress extrapolated along the link (order 1) and
+    the traction of the field at the wall plane; the Dirichlet rule, a linear
+    velocity field with the wall velocity at the wall plane.  Walls at
+    x = -q_left and x = nx - 1 + q_right; lambda = mu, so the source term
+    vanishes and the collision leaves the field as it is."""
+    nx, ny, nz = 5, 3, 2
+    mu = lam = 0.05
+
+    def fields(x):          # lattice units: rho, j, P (full 3 x 3)
+        if kind == "neumann":
+            P6 = np.array([3e-4 - 1e-4 * x, 2e-4 + 5e-5 * x, -1e-4 + 2e-5 * x,
+                           1e-4 + 3e-5 * x, -2e-4 + 1e-5 * x, 5e-5 - 4e-5 * x])
+            return 1 + 1e-3 + 2e-4 * x, np.zeros(3), sym_to_full(P6[:, None])[:, :, 0]
+        return 1.0, np.array([2e-4 + 1e-4 * x, -3e-4 + 4e-5 * x, 1e-4 - 2e-5 * x]), np.zeros((3, 3))
+
+    def box(order, wl, wr):
+        return B.slab3(nx, ny, nz, wl, wr, lam=lam, mu=mu, tau=0.55, neumann_order=order)
+
+    probe = Oracle3D(box(1, B.Wall3(B.NEUMANN), B.Wall3(B.NEUMANN)))
+    xl, xr = -q_left, nx - 1 + q_right
+    if kind == "neumann":
+        # sigma = -P at lambda = mu; t* = sigma.n, n = -x at the first wall, +x at the second
+        wl = B.Wall3(B.NEUMANN, tuple(fields(xl)[2][:, 0] * probe.s_sigma), q=q_left)
+        wr = B.Wall3(B.NEUMANN, tuple(-fields(xr)[2][:, 0] * probe.s_sigma), q=q_right)
+    else:
+        wl = B.Wall3(B.DIRICHLET, tuple(fields(xl)[1] * probe.s_v), q=q_left)
+        wr = B.Wall3(B.DIRICHLET, tuple(fields(xr)[1] * probe.s_v), q=q_right)
+    o = Oracle3D(box(1, wl, wr))
+    f0 = np.zeros((Q, nz, ny, nx))
+    for x in range(nx):
+        r, j, P = fields(x)
+        f0[:, :, :, x] = equilibrium(np.array([r]), j[:, None], P[:, :, None])[:, 0, None, None]
+    o.set_populations(f0)
+    o.step(1)
+    f1 = o.populations()
+    scale = np.abs(f0).max()
+    checked = 0
+    for i in range(1, Q):
+        if C[i, 0] == 0:
+            continue
+        x = 0 if C[i, 0] < 0 else nx - 1
+        r, j, P = fields(x + C[i, 0])                # the virtual site x + c_i
+        want = equilibrium(np.array([r]), j[:, None], P[:, :, None])[OPP[i], 0]
+        assert np.abs(f1[OPP[i], :, :, x] - want).max() <= 1e-13 * scale, (i, x)
+        checked += 1
+    assert checked == 10
+    if kind == "neumann":
+        # rho_bd and the tangential stress at the boundary site (order 0) are not exact
+        o0 = Oracle3D(box(0, wl, wr))
+        o0.set_populations(f0)
+        o0.step(1)
+        assert np.abs(o0.populations() - f1).max() > 1e-7 * scale
+
+
+@pytest.mark.parametrize("q", [0.2, 0.8])
+def test_moving_wall_drags_the_material_at_its_velocity(q):
+    """A wall crossing the boundary links at q, set moving along y at v_w
+    (eq:bbnoncon with j* = rho v_w), launches a shear wave; behind its front
+    the material moves with the wall, v = v_w, whatever q (a wrong kappa or
+    beta imposes another velocity)."""
+    nx, vw = 200, 2e-4
+    b = B.slab3(nx, 1, 1, B.Wall3(B.DIRICHLET, (0.0, vw, 0.0), q=q), B.Wall3(B.NEUMANN), lam=0.05, mu=0.05,
+                tau=0.55)
+    o = Oracle3D(b)
+    o.step(int(0.6 * nx * np.sqrt(3)))
+    rho, j, P, sig = o.moments()
+    v = j[1, 0, 0] / rho[0, 0, 0]
+    assert np.mean(v[10:int(0.4 * nx)]) == pytest.approx(vw, rel=0.01)
+    assert np.abs(v[int(0.8 * nx):]).max() < 1e-3 * vw
+
+
 def test_brute_force_loops_on_a_tiny_box():
     """One step of the reference against an explicit per-site loop
     implementation of the same definitions (tests/naive3d.py), on 3 x 4 x 2
-    boxes with and without walls and on 1 x 4 x 2 slabs (both walls on the
-    same sites), with random populations."""
+    boxes with and without walls, walls at q = 1/2 and elsewhere, rho_bd and
+    the tangential stress at the site and extrapolated, and on 1 x 4 x 2
+    slabs (both walls on the same sites, no site behind), with random
+    populations."""
     rng = np.random.default_rng(8)
     walls2 = (B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3)), B.Wall3(B.NEUMANN, (2e-4, -1e-4, 3e-4)))
-    for nx, walls in ((3, None), (3, walls2), (1, walls2), (1, walls2[::-1])):
-        b = B.Box3(nx, 4, 2, lam=0.09, mu=0.05, tau=0.6, force=(1e-5, 0.0, -2e-5), x_walls=walls)
+    wallsq = (B.Wall3(B.NEUMANN, (-1e-4, 3e-4, 2e-4), q=0.3), B.Wall3(B.DIRICHLET, (2e-3, -1e-3, 1e-3), q=0.75))
+    for nx, walls, order in ((3, None, 0), (3, walls2, 0), (1, walls2, 0), (1, walls2[::-1], 0),
+                             (3, wallsq, 0), (3, wallsq, 1), (3, wallsq[::-1], 1), (1, wallsq, 1)):
+        b = B.Box3(nx, 4, 2, lam=0.09, mu=0.05, tau=0.6, force=(1e-5, 0.0, -2e-5), x_walls=walls,
+                   neumann_order=order)
         o = Oracle3D(b)
         f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
         o.set_populations(f)
