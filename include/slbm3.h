@@ -13,15 +13,22 @@
  *
  * Geometry
  *   A box of nx x ny x nz sites at integer coordinates, periodic in y and z.
- *   In x it is either periodic or closed by two lattice-conforming walls at
- *   x = -1/2 and x = nx - 1/2 (every cut link has q = 1/2).  A Dirichlet wall
- *   carries a wall velocity, with the rule of eq:bbcon.  A Neumann wall
- *   carries a traction t* (the stress times the outward normal of the
+ *   In x it is either periodic or closed by two walls, planes normal to x
+ *   that cross every link leaving the material at the fraction q of its
+ *   length (section 4: q = 1/2 gives the lattice-conforming planes
+ *   x = -1/2 and x = nx - 1/2; in general the planes are x = -q and
+ *   x = nx - 1 + q).  A Dirichlet wall carries a wall velocity, with the
+ *   rule of eq:bbcon (q = 1/2) or eq:bbnoncon (j* = rho(x) v*).  A Neumann
+ *   wall carries a traction t* (the stress times the outward normal of the
  *   material: -x at the first wall, +x at the second), with the rule of
- *   eq:abbcon.  That rule's boundary Cauchy stress is
- *   sigma* = Pi sigma(x) Pi + n t* + t* n - (t*.n) n n, with Pi = I - n n and
- *   sigma(x) the stress at the boundary site.  Both walls apply from the
- *   first step.
+ *   eq:abbcon or eq:abbnoncon.  That rule's boundary Cauchy stress is
+ *   sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n, with Pi = I - n n; its
+ *   tangential block sigma_b, and rho_bd, are those at the boundary site
+ *   (neumann_order 0) or extrapolated along the link from the site behind,
+ *   (1 + q) X(x) - q X(x - c_i) (neumann_order 1, the paper's form).  The
+ *   rules at q != 1/2 read the population at x - c_i, the next site inward;
+ *   a one-site-wide slab has none and takes kappa = 0, beta = 1.  Both
+ *   walls apply from the first step.
  *
  * Host arrays
  *   Arrays are [component][nz][ny][nx] of doubles, x fastest.  The site index
@@ -51,6 +58,7 @@ typedef struct slbm3_s* slbm3_handle;
 typedef struct {
     int32_t kind;                /* SLBM_DIRICHLET (value: wall velocity) or SLBM_NEUMANN (value: traction) */
     double value[3];             /* user units */
+    double q;                    /* fraction of a cut link inside the material, (0, 1]; 1/2: lattice-conforming */
 } slbm3_wall;
 
 typedef struct {
@@ -59,7 +67,8 @@ typedef struct {
     double tau_bar;              /* relaxation time in units of dt, > 1/2 */
     double body_force[3];        /* per volume, user units */
     int32_t periodic_x;          /* 1: periodic in x; 0: the two walls below */
-    slbm3_wall walls[2];         /* at x = -1/2 and at x = nx - 1/2 (ignored when periodic_x) */
+    slbm3_wall walls[2];         /* crossing the links of the first and the last sites in x (ignored when periodic_x) */
+    int32_t neumann_order;       /* 0: rho_bd and the tangential stress at the boundary site; 1: extrapolated */
     int32_t precision;           /* SLBM_FP64, or SLBM_FP32 (fp32 populations and arithmetic, fp64 U) */
     int32_t device;              /* HIP device ordinal */
     void* stream;                /* hipStream_t to queue work on; NULL: a stream owned by the handle */

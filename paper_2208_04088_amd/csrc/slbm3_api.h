@@ -16,6 +16,8 @@ struct slbm3_s {
     int px = 1;
     int wkind[2] = {0, 0};
     double wval[2][3] = {{0, 0, 0}, {0, 0, 0}};   // lattice units
+    double wq[2] = {0.5, 0.5};
+    int norder = 0;
     double lamL = 0, muL = 1.0 / 3.0, tau = 0.55, FL[3] = {0, 0, 0};
     double dt_user = 1, s_sigma = 1, s_v = 1, rho_user = 1;
     void* buf[2] = {nullptr, nullptr};
@@ -50,6 +52,14 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     for (int s = 0; s < 2; ++s) {
         a.wkind[s] = h->wkind[s];
         for (int k = 0; k < 3; ++k) a.wval[s][k] = (real)h->wval[s][k];
+        // section 4.2: a site behind x along the cut link exists unless nx = 1
+        const bool behind = h->nx >= 2;
+        const double q = h->wq[s];
+        a.wkap[s] = (real)(behind ? (1.0 - 2.0 * q) / (1.0 + 2.0 * q) : 0.0);
+        a.wbeta[s] = (real)(behind ? 2.0 / (1.0 + 2.0 * q) : 1.0);
+        a.wq1[s] = (real)(1.0 + q);
+        a.wq[s] = (real)q;
+        a.wext[s] = behind && h->norder == 1 && h->wkind[s] == SLBM_NEUMANN ? 1 : 0;
     }
     a.omega = (real)(1.0 / h->tau);
     a.omega_h = (real)(1.0 - 0.5 / h->tau);
@@ -161,10 +171,14 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
         const long long plane = (long long)p->nx * p->ny * p->nz;
         if (plane > (1LL << 29))
             return fail(SLBM_E_UNSUPPORTED, "box exceeds 2^29 sites (kernels index a plane's sites with 32-bit offsets)");
+        if (p->neumann_order != 0 && p->neumann_order != 1) return fail(SLBM_E_INVAL, "neumann_order must be 0 or 1");
         if (!p->periodic_x) {
-            for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < 2; ++s) {
                 if (p->walls[s].kind != SLBM_DIRICHLET && p->walls[s].kind != SLBM_NEUMANN)
                     return fail(SLBM_E_INVAL, "wall %d: kind must be SLBM_DIRICHLET or SLBM_NEUMANN", s);
+                if (!(p->walls[s].q > 0.0 && p->walls[s].q <= 1.0))
+                    return fail(SLBM_E_INVAL, "wall %d: q must be in (0, 1]", s);
+            }
         }
         slbm3_s* h = new (std::nothrow) slbm3_s();
         if (!h) return fail(SLBM_E_NOMEM, "out of host memory");
@@ -189,8 +203,10 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
                 h->wkind[s] = p->walls[s].kind;
                 const double scale = p->walls[s].kind == SLBM_DIRICHLET ? h->s_v : h->s_sigma;
                 for (int k = 0; k < 3; ++k) h->wval[s][k] = p->walls[s].value[k] / scale;
+                h->wq[s] = p->walls[s].q;
             }
         }
+        h->norder = p->neumann_order;
         DeviceGuard dg(h->device);
     #define TRY_OR_BAIL(expr)                                \
         do {                                                 \

@@ -54,8 +54,13 @@ struct Step3Args {
     int px;                    // periodic in x (else walls)
     int local;                 // src holds the populations at the sites themselves
     int ntiles;                // 64-site row chunks
-    int wkind[2];              // walls at x = -1/2, x = nx - 1/2
+    int wkind[2];              // walls crossing the first and the last site's x links
     real wval[2][3];           // lattice units: wall velocity (Dirichlet) or traction (Neumann)
+    // per wall, from its q: kappa = (1 - 2q)/(1 + 2q), beta = 2/(1 + 2q)
+    // (0 and 1 with no site behind, nx = 1); wext: Neumann with rho_bd and
+    // the tangential stress extrapolated along the link, weights 1 + q, -q
+    real wkap[2], wbeta[2], wq1[2], wq[2];
+    int wext[2];
     real omega, omega_h;       // 1/tau, 1 - 1/(2 tau)
     real ml, lm;               // mu - lambda, lambda - mu (lattice units)
     real F[3];
@@ -340,39 +345,61 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
             const int kind = a.wkind[side];
             const real n = side == 0 ? real(-1) : real(1);
             const real* v = a.wval[side];
-            // Neumann: boundary Poisson stress P* = -sigma* - (lambda - mu) drho I
-            // with sigma = -P - (lambda - mu) drho I at the site
-            real Ps[6];
-            Ps[0] = -(n * v[0]) - a.lm * dr;                  // sigma*_xx = n t_x
-            Ps[1] = P[1];                                     // tangential block: sigma*_tt = sigma_tt
-            Ps[2] = P[2];
-            Ps[3] = -(n * v[1]);                              // sigma*_xy = n t_y
-            Ps[4] = -(n * v[2]);                              // sigma*_xz = n t_z
-            Ps[5] = P[5];
+            const real kap = a.wkap[side], bet = a.wbeta[side];
+            // the site behind x along a cut link, x - c_i, is the next site
+            // inward (none in a one-site-wide slab, where kappa = 0)
+            const int bx = nx == 1 ? st.x : (side == 0 ? st.x + 1 : st.x - 1);
             const real rho = real(1) + dr;
             const real jz[3] = {real(0), real(0), real(0)};
 #pragma unroll
             for (int i = 1; i < kQ; ++i) {
                 // link i leaves through this wall; its opposite returns
                 if (kCX[i] != (side == 0 ? -1 : 1)) continue;
+                const unsigned sb = sidx3(bx, wrap(st.y - kCY[i], ny), wrap(st.z - kCZ[i], nz), nx, ny);
+                const real hy = a.src[i * a.stride + sb];    // f_i at x - c_i
                 real val;
                 if (kind == kWallDirichlet) {
-                    // eq:bbcon, q = 1/2: f_ib = f_i - 6 w_i c_i.j*, j* = rho v*
+                    // eq:bbcon / eq:bbnoncon: f_ib = f_i + kappa (f_i(x - c_i) - f_ib)
+                    // - beta 6 w_i c_i.j*, j* = rho(x) v*
                     const real cv = real(kCX[i]) * v[0] + real(kCY[i]) * v[1] + real(kCZ[i]) * v[2];
-                    val = h[i] - real(6.0 * w3(i)) * rho * cv;
+                    val = h[i] + kap * (hy - h[opp3(i)]) - bet * (real(6.0 * w3(i)) * rho * cv);
                 } else {
-                    // eq:abbcon, q = 1/2: f_ib = -f_i + 2 f_eq,i(rho, 0, P*);
-                    // shifted: g_ib = -g_i + 2 g_eq,i
+                    // eq:abbcon / eq:abbnoncon: f_ib = -f_i - kappa (f_i(x - c_i) + f_ib)
+                    // + beta 2 f_eq,i(rho_bd, 0, P*); shifted: g_eq in place of f_eq.
+                    // Boundary Poisson stress P* = -sigma* - (lambda - mu) drho_bd I with
+                    // sigma = -P - (lambda - mu) drho I: its normal row from the traction,
+                    // its tangential block that of P at the site, or extrapolated along
+                    // the link, (1 + q) X(x) - q X(x - c_i)
+                    real drb = dr, Pb1 = P[1], Pb2 = P[2], Pb5 = P[5];
+                    if (a.wext[side]) {
+                        real hb[kQ];
+#pragma unroll
+                        for (int k = 0; k < kQ; ++k) hb[k] = a.src[k * a.stride + sb];
+                        real dry, jy[3], Py[6];
+                        moments3(hb, dry, jy, Py);
+                        const real w1 = a.wq1[side], w2 = a.wq[side];
+                        drb = w1 * dr - w2 * dry;
+                        Pb1 = w1 * P[1] - w2 * Py[1];
+                        Pb2 = w1 * P[2] - w2 * Py[2];
+                        Pb5 = w1 * P[5] - w2 * Py[5];
+                    }
+                    real Ps[6];
+                    Ps[0] = -(n * v[0]) - a.lm * drb;             // sigma*_xx = n t_x
+                    Ps[1] = Pb1;                                  // tangential block
+                    Ps[2] = Pb2;
+                    Ps[3] = -(n * v[1]);                          // sigma*_xy = n t_y
+                    Ps[4] = -(n * v[2]);                          // sigma*_xz = n t_z
+                    Ps[5] = Pb5;
                     real e;
                     switch (i) {
-#define SLBM3_GEQ(k) case k: e = geq3<k, real>(dr, jz, Ps); break;
+#define SLBM3_GEQ(k) case k: e = geq3<k, real>(drb, jz, Ps); break;
                         SLBM3_GEQ(1) SLBM3_GEQ(2) SLBM3_GEQ(3) SLBM3_GEQ(4) SLBM3_GEQ(5) SLBM3_GEQ(6)
                         SLBM3_GEQ(7) SLBM3_GEQ(8) SLBM3_GEQ(9) SLBM3_GEQ(10) SLBM3_GEQ(11) SLBM3_GEQ(12)
                         SLBM3_GEQ(13) SLBM3_GEQ(14) SLBM3_GEQ(15) SLBM3_GEQ(16) SLBM3_GEQ(17) SLBM3_GEQ(18)
 #undef SLBM3_GEQ
                         default: e = real(0);
                     }
-                    val = -h[i] + real(2) * e;
+                    val = -h[i] - kap * (hy + h[opp3(i)]) + bet * (real(2) * e);
                 }
                 g[opp3(i)] = val;
             }

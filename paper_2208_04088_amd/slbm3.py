@@ -16,7 +16,7 @@ EXPORTS = ["slbm3_create", "slbm3_init_fields", "slbm3_step", "slbm3_sync", "slb
 
 
 class Wall(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3)]
+    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("q", C.c_double)]
 
 
 class Params3(C.Structure):
@@ -26,6 +26,7 @@ class Params3(C.Structure):
         ("body_force", C.c_double * 3),
         ("periodic_x", C.c_int32),
         ("walls", Wall * 2),
+        ("neumann_order", C.c_int32),
         ("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -66,12 +67,15 @@ def marshal(box, precision=S.FP32, device=0, stream=None):
     if isinstance(precision, str):
         precision = S.PRECISION[precision]
     walls = (Wall * 2)()
+    for k in range(2):
+        walls[k] = Wall(0, (C.c_double * 3)(0.0, 0.0, 0.0), 0.5)
     if box.x_walls is not None:
         for k, w in enumerate(box.x_walls):
-            walls[k] = Wall(int(w.kind), (C.c_double * 3)(*w.value))
+            walls[k] = Wall(int(w.kind), (C.c_double * 3)(*w.value), float(w.q))
     return Params3(nx=box.nx, ny=box.ny, nz=box.nz, lam=box.lam, mu=box.mu, rho=box.rho, tau=box.tau,
                    body_force=(C.c_double * 3)(*box.force), periodic_x=int(box.x_walls is None),
-                   walls=walls, precision=int(precision), device=int(device), stream=stream)
+                   walls=walls, neumann_order=int(box.neumann_order), precision=int(precision),
+                   device=int(device), stream=stream)
 
 
 class Solver3:

@@ -91,6 +91,33 @@ def test_slab_with_both_wall_kinds(S3, prec, tol, steps):
     check(out, ref, tol, f"slab {prec}", box)
 
 
+@pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 40), ("fp32", FP32_TOL, 300)])
+@pytest.mark.parametrize("qs,order", [((0.2, 0.8), 0), ((0.8, 0.3), 1), ((1.0, 0.15), 1)])
+def test_slab_with_walls_off_the_lattice(S3, prec, tol, steps, qs, order):
+    """Walls crossing the cut links at q != 1/2 (eq:bbnoncon, eq:abbnoncon),
+    with rho_bd and the tangential stress at the boundary site or
+    extrapolated along the link, both wall kinds on either side."""
+    left, right = (B.Wall3(B.DIRICHLET, (2e-4, -1e-4, 3e-4), q=qs[0]),
+                   B.Wall3(B.NEUMANN, (1e-4, 2e-5, -3e-5), q=qs[1]))
+    if order == 1 and qs[0] > 0.9:
+        left, right = (B.Wall3(B.NEUMANN, (-1e-4, 3e-5, 1e-5), q=qs[0]),
+                       B.Wall3(B.DIRICHLET, (-1e-4, 2e-4, 0.0), q=qs[1]))
+    box = B.slab3(70, 6, 5, left, right, lam=0.05, mu=0.05, tau=0.55, neumann_order=order)
+    fields = dict(vel=B.random_velocity(box, 24, 5e-4))
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"slab q={qs} order {order} {prec}", box)
+
+
+def test_single_site_thick_slab_off_the_lattice(S3):
+    """nx = 1 with walls at q != 1/2: no site behind, so the rules take
+    kappa = 0 and beta = 1 (and no extrapolation) as in the reference."""
+    box = B.slab3(1, 7, 9, B.Wall3(B.NEUMANN, (1e-4, 0.0, 2e-5), q=0.3), B.Wall3(B.DIRICHLET, (-2e-4, 1e-5, 0.0), q=0.9),
+                  lam=0.05, mu=0.05, tau=0.6, neumann_order=1)
+    fields = dict(vel=B.random_velocity(box, 25, 1e-4))
+    out, ref = run_both(S3, box, "fp64", 25, fields)
+    check(out, ref, FP64_TOL, "nx=1 off the lattice", box)
+
+
 @pytest.mark.parametrize("kinds", [(B.NEUMANN, B.NEUMANN), (B.DIRICHLET, B.DIRICHLET), (B.NEUMANN, B.DIRICHLET)])
 def test_single_site_thick_slab(S3, kinds):
     """nx = 1: both walls act on the same sites."""
