@@ -145,11 +145,57 @@ class Oracle3D:
                     self.cut[i, :, :, 0] = True
                 elif C[i, 0] > 0:
                     self.cut[i, :, :, -1] = True
+        self.mask = None
+        if b.mask is not None:
+            self._general(b)
         self.f = np.repeat(equilibrium(np.ones(1, dtype=self.dt), np.zeros((3, 1), dtype=self.dt),
                                        np.zeros((3, 3, 1), dtype=self.dt)), b.n_sites, 1)
         self.f = self.f.reshape((Q,) + self.shape)
+        self.rest = self.f[:, :1, :1, :1].copy()
         self.U = np.zeros((3,) + self.shape, dtype=self.dt)
         self.n = 0
+
+    def _general(self, b):
+        """A box with cut links (periodic on every axis): the material mask,
+        the links, their groups in lattice units."""
+        if b.x_walls is not None:
+            raise ValueError("a box with a material mask is periodic on every axis")
+        mask = np.asarray(b.mask).astype(bool)
+        if mask.shape != self.shape:
+            raise ValueError("mask shape must be (nz, ny, nx)")
+        self.mask = mask
+        L = b.links
+        site = L["site"].astype(np.int64)
+        z, rem = np.divmod(site, b.ny * b.nx)
+        y, x = np.divmod(rem, b.nx)
+        k = L["dir"].astype(np.int64)
+        if not mask[z, y, x].all():
+            raise ValueError("a cut link starts at a void site")
+        fz, fy, fx = (z + C[k, 2]) % b.nz, (y + C[k, 1]) % b.ny, (x + C[k, 0]) % b.nx
+        if mask[fz, fy, fx].any():
+            raise ValueError("a cut link ends at a material site")
+        q = L["q"]
+        if not ((q > 0) & (q <= 1)).all():
+            raise ValueError("q must be in (0, 1]")
+        n = np.asarray(L["normal"], dtype=float)
+        if np.abs(np.linalg.norm(n, axis=1) - 1).max() > 1e-9:
+            raise ValueError("normals must be unit vectors")
+        self.cut[k, z, y, x] = True
+        # every link from the material into the void must be listed
+        for i in range(1, Q):
+            far_void = ~np.roll(mask, (-C[i, 2], -C[i, 1], -C[i, 0]), axis=(0, 1, 2))
+            if (far_void & mask & ~self.cut[i]).any():
+                raise ValueError("a link from the material into the void is not listed")
+        self.links = dict(z=z, y=y, x=x, k=k, q=q.astype(self.dt), g=L["group"].astype(np.int64),
+                          n=n.astype(self.dt))
+        self.gkind = np.array([g.kind for g in b.groups])
+        self.gval = []
+        for g in b.groups:
+            if g.kind not in (DIRICHLET, NEUMANN):
+                raise ValueError("group kind must be Dirichlet or Neumann")
+            scale = self.s_v if g.kind == DIRICHLET else self.s_sigma
+            self.gval.append((np.array(g.value, dtype=self.dt) / self.dt(scale),
+                              self.dt(getattr(g, "pressure", 0.0)) / self.dt(self.s_sigma)))
 
     # -------------------------------------------------------------- steps
     def _moments(self, f):
@@ -172,7 +218,7 @@ class Oracle3D:
         grad = np.zeros((3,) + self.shape, dtype=self.dt)
         for i in range(1, Q):
             r = self._neighbour(rho, i, +1)
-            if self.walls is not None:
+            if self.walls is not None or self.mask is not None:
                 ext = np.where(self.cut[OPP[i]], rho, 2.0 * rho - self._neighbour(rho, i, -1))
                 r = np.where(self.cut[i], ext, r)
             for a in range(3):
@@ -208,6 +254,11 @@ class Oracle3D:
                 fnew[i] = self._neighbour(fcol[i], i, -1)
             if self.walls is not None:
                 self._walls(fcol, fnew)
+            if self.mask is not None:
+                self._links(fcol, fnew)
+                # void sites hold the rest state (nothing reads them)
+                fnew[:, ~self.mask] = self.rest[:, 0, 0]
+                self.U[:, ~self.mask] = 0
             self.f = fnew
             self.n += 1
 
@@ -272,6 +323,65 @@ class Oracle3D:
                     E = 2 * equilibrium(rbd, np.zeros((3,) + rbd.shape, dtype=self.dt), Pstar)[i]
                     fnew[ib, :, :, xs] = -fi - kappa * (fi_y + fib) + beta * E
 
+    def _links(self, fcol, fnew):
+        """The cut links of a general geometry, each with its own q, outward
+        normal and group (section 4.2, as `_walls` for planes): the population
+        returning to x in direction ibar.  A link whose opposite link at x is
+        cut too has no site behind x (kappa = 0, beta = 1, no extrapolation)."""
+        rho, _, P = self._moments(fcol)
+        L = self.links
+        z, y, x, k, q = L["z"], L["y"], L["x"], L["k"], L["q"]
+        nz, ny, nx = self.shape
+        kb = OPP[k]
+        thin = self.cut[kb, z, y, x]
+        bz, by, bx = (z - C[k, 2]) % nz, (y - C[k, 1]) % ny, (x - C[k, 0]) % nx
+        kappa = np.where(thin, 0, (1 - 2 * q) / (1 + 2 * q))
+        beta = np.where(thin, 1, 2 / (1 + 2 * q))
+        fk = fcol[k, z, y, x]
+        fkb = fcol[kb, z, y, x]
+        fky = np.where(thin, 0, fcol[k, bz, by, bx])
+        r = rho[z, y, x]
+        c = C[k].astype(self.dt)                                   # [m, 3]
+        out = np.empty_like(fk)
+        for gi, (val, pres) in enumerate(self.gval):
+            sel = L["g"] == gi
+            if not sel.any():
+                continue
+            if self.gkind[gi] == DIRICHLET:
+                # eq:bbcon / eq:bbnoncon with j* = rho(x) v*
+                cj = (c[sel] @ val) * r[sel]
+                out[sel] = (fk[sel] + kappa[sel] * (fky[sel] - fkb[sel])
+                            - beta[sel] * 2 * self.W[k[sel]] * cj / self.cs2)
+                continue
+            # eq:abbcon / eq:abbnoncon: t* = value - pressure n; sigma* =
+            # Pi sigma_b Pi + n t* + t* n - (t*.n) n n, sigma_b and rho_bd at
+            # the site or extrapolated along the link (order 1, not thin)
+            sz, sy, sx, sq, sn = z[sel], y[sel], x[sel], q[sel], L["n"][sel]
+            Ps = P[:, :, sz, sy, sx]                              # [3, 3, m]
+            rs = rho[sz, sy, sx]
+            sig = self._cauchy(rs, Ps)
+            rbd = rs
+            if self.norder == 1:
+                ext = ~thin[sel]
+                ry = rho[bz[sel], by[sel], bx[sel]]
+                Py = P[:, :, bz[sel], by[sel], bx[sel]]
+                sig_y = self._cauchy(ry, Py)
+                sig = np.where(ext[None, None], (1 + sq) * sig - sq * sig_y, sig)
+                rbd = np.where(ext, (1 + sq) * rs - sq * ry, rs)
+            t = val[None, :] - pres * sn                           # [m, 3]
+            Pi = np.eye(3, dtype=self.dt)[:, :, None] - np.einsum("ma,mb->abm", sn, sn)
+            st = np.einsum("abm,bcm,cdm->adm", Pi, sig, Pi)
+            tn = np.einsum("ma,ma->m", t, sn)
+            st = st + np.einsum("ma,mb->abm", sn, t) + np.einsum("ma,mb->abm", t, sn) \
+                - tn[None, None] * np.einsum("ma,mb->abm", sn, sn)
+            Pstar = -st
+            for a in range(3):
+                Pstar[a, a] = Pstar[a, a] + (self.lam - self.mu) * (1.0 - rbd)
+            feq = equilibrium(rbd, np.zeros((3,) + rbd.shape, dtype=self.dt), Pstar)   # [Q, m]
+            E = 2 * feq[k[sel], np.arange(len(rbd))]
+            out[sel] = -fk[sel] - kappa[sel] * (fky[sel] + fkb[sel]) + beta[sel] * E
+        fnew[kb, z, y, x] = out
+
     # ------------------------------------------------------------ fields
     def init_fields(self, rho=None, vel=None, sigma=None, u=None):
         """f = f_eq(rho, rho v - S/2, P(sigma, rho)), U = u - (j/rho)/2, in
@@ -291,6 +401,10 @@ class Oracle3D:
         self.f = equilibrium(r, j - 0.5 * S, P)
         u0 = np.zeros((3,) + self.shape, dtype=self.dt) if u is None else np.asarray(u, dtype=self.dt)
         self.U = u0 - 0.5 * j / r
+        if self.mask is not None:
+            # void sites: the rest state, no displacement (fields there are ignored)
+            self.f[:, ~self.mask] = self.rest[:, 0, 0]
+            self.U[:, ~self.mask] = 0
         self.n = 0
 
     def moments(self):
@@ -302,14 +416,21 @@ class Oracle3D:
         sig = self._cauchy(rho, P)
         sv = self.box.rho * self.s_v
         out = (rho * self.box.rho, j * sv, full_to_sym(P) * self.s_sigma, full_to_sym(sig) * self.s_sigma)
-        return tuple(np.asarray(a, dtype=np.float64) for a in out)
+        out = tuple(np.asarray(a, dtype=np.float64) for a in out)
+        if self.mask is not None:
+            for a in out:
+                a[..., ~self.mask] = 0.0            # void sites report zeros
+        return out
 
     def displacement(self):
         """u^n = U^n + (j^n/rho^n)/2: the trapezoid rule for the integral of
         j/rho (U holds u0 - v0/2 plus the left sum), in cells."""
         rho, j, _ = self._moments(self.f)
         j = j + self._source(rho) / 2
-        return np.asarray(self.U + j / rho / 2, dtype=np.float64)
+        u = np.asarray(self.U + j / rho / 2, dtype=np.float64)
+        if self.mask is not None:
+            u[:, ~self.mask] = 0.0
+        return u
 
     def populations(self):
         return np.asarray(self.f, dtype=np.float64)

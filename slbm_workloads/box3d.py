@@ -45,14 +45,94 @@ class Box3:
     # Neumann walls: rho_bd and the tangential stress taken at the boundary
     # site (0) or extrapolated along the link from the site behind it (1)
     neumann_order: int = 0
+    # general geometry (periodic on every axis, no x_walls): the material
+    # mask [nz, ny, nx] (1 = material), one record per cut link (LINK3_DTYPE:
+    # a link from a material site whose far end is void) and the groups
+    mask: Optional[np.ndarray] = None
+    links: Optional[np.ndarray] = None
+    groups: Optional[list] = None
 
     @property
     def n_sites(self) -> int:
         return self.nx * self.ny * self.nz
 
     @property
+    def n_material(self) -> int:
+        return self.n_sites if self.mask is None else int(self.mask.sum())
+
+    @property
     def periodic_x(self) -> bool:
         return self.x_walls is None
+
+
+@dataclass
+class BCGroup3:
+    """Boundary data of cut links: a wall velocity (DIRICHLET), or a traction
+    t* = value - pressure n, n the link's outward normal of the material
+    (NEUMANN; a pressure loads a curved cavity uniformly)."""
+    kind: int
+    value: Vec3 = (0.0, 0.0, 0.0)
+    pressure: float = 0.0
+
+
+@dataclass
+class Sphere3:
+    """Spherical cavity: sites with |x - c|^2 < R^2 are void."""
+    cx: float
+    cy: float
+    cz: float
+    R: float
+    group: int
+
+
+# D3Q19 directions in the order of the kernels and the reference
+C3 = np.array([[0, 0, 0],
+               [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+               [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0],
+               [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1],
+               [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=np.int64)
+
+LINK3_DTYPE = np.dtype([("site", "<i4"), ("dir", "<i4"), ("q", "<f8"), ("group", "<i4"),
+                        ("normal", "<f8", (3,))], align=True)
+
+
+def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0,
+                force=(0.0, 0.0, 0.0), neumann_order=0, name="", steps=0) -> Box3:
+    """A box periodic on every axis with spherical cavities (each inside the
+    box, away from its faces).  A link from a material site x whose far end
+    x + c_i lies in a cavity is cut where it first enters it: q = that
+    fraction of the link, normal = the material's outward normal there
+    (towards the centre)."""
+    zz, yy, xx = np.mgrid[0:nz, 0:ny, 0:nx]
+    mask = np.ones((nz, ny, nx), dtype=np.uint8)
+    for sp in spheres:
+        if not (sp.R < sp.cx < nx - 1 - sp.R and sp.R < sp.cy < ny - 1 - sp.R and sp.R < sp.cz < nz - 1 - sp.R):
+            raise ValueError("a cavity must lie inside the box")
+        inside = (xx - sp.cx) ** 2 + (yy - sp.cy) ** 2 + (zz - sp.cz) ** 2 < sp.R ** 2
+        mask[inside] = 0
+    recs = []
+    mat = np.argwhere(mask == 1)
+    for i in range(1, len(C3)):
+        c = C3[i]
+        fz, fy, fx = (mat[:, 0] + c[2]) % nz, (mat[:, 1] + c[1]) % ny, (mat[:, 2] + c[0]) % nx
+        cut = mask[fz, fy, fx] == 0
+        for z, y, x in mat[cut]:
+            far = np.array([x + c[0], y + c[1], z + c[2]], dtype=float)
+            for sp in spheres:
+                d = far - (sp.cx, sp.cy, sp.cz)
+                if d @ d < sp.R ** 2:
+                    break
+            p0 = np.array([x, y, z], dtype=float) - (sp.cx, sp.cy, sp.cz)
+            a, b, cc = float(c @ c), float(p0 @ c), float(p0 @ p0) - sp.R ** 2
+            t = (-b - np.sqrt(max(b * b - a * cc, 0.0))) / a
+            t = min(max(t, 1e-9), 1.0)
+            w = np.array([x, y, z], dtype=float) + t * c
+            n = (np.array([sp.cx, sp.cy, sp.cz]) - w) / sp.R
+            recs.append(((z * ny + y) * nx + x, i, t, sp.group, tuple(n / np.linalg.norm(n))))
+    links = np.array(sorted(recs, key=lambda r: (r[0], r[1])), dtype=LINK3_DTYPE)
+    return Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, rho=rho, force=tuple(force), name=name or
+                f"spheres{nx}x{ny}x{nz}", steps=steps, neumann_order=neumann_order, mask=mask, links=links,
+                groups=list(groups))
 
 
 def periodic_box3(nx, ny, nz, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0, force=(0.0, 0.0, 0.0),

@@ -39,9 +39,23 @@ def naive_step(box, f, U, order):
     F = [a / s_sigma for a in box.force]
     walls = box.x_walls
     tau = box.tau
+    mask = box.mask
+    links = {}
+    if mask is not None:
+        for L in box.links:
+            s_ = int(L["site"])
+            links[(s_ % (ny * nx) % nx, s_ % (ny * nx) // nx, s_ // (ny * nx), order[int(L["dir"])])] = L
 
     def inside_x(x):
         return walls is None or 0 <= x < nx
+
+    def material(x, y, z):
+        if not inside_x(x):
+            return False
+        if mask is None:
+            return True
+        xx, yy, zz = wrap(x, y, z)
+        return bool(mask[zz, yy, xx])
 
     def wrap(x, y, z):
         return (x % nx, y % ny, z % nz)
@@ -61,15 +75,17 @@ def naive_step(box, f, U, order):
     fcol = np.zeros_like(f)
     Un = U.copy()
     for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        if not material(x, y, z):
+            continue
         r = rho[z, y, x]
         grad = [0.0, 0.0, 0.0]
         for c in vel:
             if c == (0, 0, 0):
                 continue
-            if inside_x(x + c[0]):
+            if material(x + c[0], y + c[1], z + c[2]):
                 xx, yy, zz = wrap(x + c[0], y + c[1], z + c[2])
                 rn = rho[zz, yy, xx]
-            elif inside_x(x - c[0]):
+            elif material(x - c[0], y - c[1], z - c[2]):
                 xx, yy, zz = wrap(x - c[0], y - c[1], z - c[2])
                 rn = 2 * r - rho[zz, yy, xx]
             else:
@@ -87,11 +103,24 @@ def naive_step(box, f, U, order):
             Un[a, z, y, x] += j[a] / r
 
     fnew = np.zeros_like(f)
+    if mask is not None:
+        rest = [_feq(c, 1.0, [0.0, 0.0, 0.0], [[0.0] * 3 for _ in range(3)]) for c in order]
+        for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+            if not mask[z, y, x]:
+                fnew[:, z, y, x] = rest
+                Un[:, z, y, x] = 0.0
     for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+        if not material(x, y, z):
+            continue
         for c in vel:
-            if inside_x(x + c[0]):
+            if material(x + c[0], y + c[1], z + c[2]):
                 xx, yy, zz = wrap(x + c[0], y + c[1], z + c[2])
                 fnew[idx[c], zz, yy, xx] = fcol[idx[c], z, y, x]
+                continue
+            if mask is not None:
+                fnew[idx[tuple(-a for a in c)], z, y, x] = _cut_link(box, fcol, idx, vel, links[(x, y, z, c)],
+                                                                     x, y, z, c, material, wrap, lamL, muL,
+                                                                     s_v, s_sigma)
                 continue
             # the link leaves through a wall: the population returns to x
             side = 0 if x + c[0] < 0 else 1
@@ -140,3 +169,50 @@ def naive_step(box, f, U, order):
                 Ps = [[-st[a][b] + (lamL - muL) * (1 - rbd) * (a == b) for b in range(3)] for a in range(3)]
                 fnew[idx[cb], z, y, x] = -fc - kap * (fb + fcb) + bet * 2 * _feq(c, rbd, [0.0, 0.0, 0.0], Ps)
     return fnew, Un
+
+
+def _cut_link(box, fcol, idx, vel, L, x, y, z, c, material, wrap, lamL, muL, s_v, s_sigma):
+    """The population returning to material site (x, y, z) along the cut link
+    in direction c, with the link's own q, outward normal and group."""
+    q = float(L["q"])
+    n = [float(v) for v in L["normal"]]
+    G = box.groups[int(L["group"])]
+    cb = tuple(-a for a in c)
+    fc = fcol[idx[c], z, y, x]
+    fcb = fcol[idx[cb], z, y, x]
+
+    def mom(xx, yy, zz):
+        r = sum(fcol[idx[d], zz, yy, xx] for d in vel)
+        Pm = [[sum(fcol[idx[d], zz, yy, xx] * d[a] * d[b] for d in vel) for b in range(3)] for a in range(3)]
+        return r, Pm
+
+    r, Pm = mom(x, y, z)
+    # no site behind x when the opposite link is cut as well
+    has_b = material(x - c[0], y - c[1], z - c[2])
+    if has_b:
+        bx, by, bz = wrap(x - c[0], y - c[1], z - c[2])
+        fb = fcol[idx[c], bz, by, bx]
+        kap, bet = (1 - 2 * q) / (1 + 2 * q), 2 / (1 + 2 * q)
+    else:
+        fb, kap, bet = 0.0, 0.0, 1.0
+    if G.kind == DIRICHLET:
+        vL = [v / s_v for v in G.value]
+        return fc + kap * (fb - fcb) - bet * 6 * _w(c) * sum(c[a] * r * vL[a] for a in range(3))
+
+    def cauchy(rr, PP_):
+        return [[-PP_[a][b] + (lamL - muL) * (1 - rr) * (a == b) for b in range(3)] for a in range(3)]
+
+    sig = cauchy(r, Pm)
+    rbd = r
+    if has_b and box.neumann_order == 1:
+        rb, Pb = mom(bx, by, bz)
+        sb = cauchy(rb, Pb)
+        sig = [[(1 + q) * sig[a][b] - q * sb[a][b] for b in range(3)] for a in range(3)]
+        rbd = (1 + q) * r - q * rb
+    t = [G.value[a] / s_sigma - G.pressure / s_sigma * n[a] for a in range(3)]
+    tn = sum(t[a] * n[a] for a in range(3))
+    Pi = [[(a == b) - n[a] * n[b] for b in range(3)] for a in range(3)]
+    st = [[sum(Pi[a][e] * sig[e][f] * Pi[f][b] for e in range(3) for f in range(3))
+           + n[a] * t[b] + t[a] * n[b] - tn * n[a] * n[b] for b in range(3)] for a in range(3)]
+    Ps = [[-st[a][b] + (lamL - muL) * (1 - rbd) * (a == b) for b in range(3)] for a in range(3)]
+    return -fc - kap * (fb + fcb) + bet * 2 * _feq(c, rbd, [0.0, 0.0, 0.0], Ps)

@@ -334,3 +334,127 @@ def test_brute_force_loops_on_a_tiny_box():
         fn, Un = naive_step(b, f, U0, [tuple(int(a) for a in c) for c in C])
         assert np.abs(o.populations() - fn).max() < 1e-14
         assert np.abs(o.U - Un).max() < 1e-14
+
+
+# ------------------------------------------------ general cut-link geometry --
+
+def _planes_as_links(nx, ny, nz, walls, order, lam=0.09, mu=0.05, tau=0.6):
+    """The slab of `walls` (at q_left, q_right) written as a general geometry:
+    material columns 1..nx between void columns 0 and nx + 1, periodic in x,
+    the links into the void cut at the walls' q with normals -x and +x."""
+    NX = nx + 2
+    mask = np.zeros((nz, ny, NX), dtype=np.uint8)
+    mask[:, :, 1:nx + 1] = 1
+    recs = []
+    for z in range(nz):
+        for y in range(ny):
+            for side, x in ((0, 1), (1, nx)):
+                for i in range(1, Q):
+                    if C[i, 0] == (-1 if side == 0 else 1):
+                        recs.append(((z * ny + y) * NX + x, i, walls[side].q, side,
+                                     (-1.0 if side == 0 else 1.0, 0.0, 0.0)))
+    links = np.array(sorted(recs, key=lambda r: (r[0], r[1])), dtype=B.LINK3_DTYPE)
+    groups = [B.BCGroup3(w.kind, w.value) for w in walls]
+    return B.Box3(NX, ny, nz, lam=lam, mu=mu, tau=tau, mask=mask, links=links, groups=groups,
+                  neumann_order=order)
+
+
+@pytest.mark.parametrize("nx,qs,order", [(5, (0.5, 0.5), 0), (5, (0.3, 0.8), 1), (4, (0.9, 0.15), 0),
+                                         (1, (0.3, 0.7), 1)])
+def test_cut_links_reproduce_the_wall_planes(nx, qs, order):
+    """The general geometry (a material mask, per-link q, normal and group)
+    reduces to the pinned wall planes: planes written as cut links into void
+    columns give the same state (the one-site-wide slab has links with no
+    site behind, cut on both sides)."""
+    walls = (B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3), q=qs[0]), B.Wall3(B.NEUMANN, (2e-4, -1e-4, 3e-4), q=qs[1]))
+    plane = B.slab3(nx, 4, 3, *walls, lam=0.09, mu=0.05, tau=0.6, neumann_order=order)
+    gen = _planes_as_links(nx, 4, 3, walls, order)
+    o1, o2 = Oracle3D(plane), Oracle3D(gen)
+    rng = np.random.default_rng(11)
+    v = 1e-3 * rng.normal(size=(3,) + o1.shape)
+    o1.init_fields(vel=v)
+    v2 = np.zeros((3,) + o2.shape)
+    v2[:, :, :, 1:nx + 1] = v
+    o2.init_fields(vel=v2)
+    o1.step(9)
+    o2.step(9)
+    f1, f2 = o1.populations(), o2.populations()[:, :, :, 1:nx + 1]
+    assert np.abs(f1 - f2).max() < 1e-14
+    assert np.abs(o1.displacement() - o2.displacement()[:, :, :, 1:nx + 1]).max() < 1e-13
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_pressurised_cavity_holds_a_hydrostatic_state(order):
+    """Patch test of eq:abbnoncon on a curved wall: a spherical cavity under
+    pressure p (t* = -p n on every link, each with its own normal) in a
+    material under the uniform stress -p I is an exact steady state, at the
+    q of every cut link and with the tangential stress at the site or
+    extrapolated."""
+    p = 2e-4
+    b = B.sphere_box3(16, 15, 14, [B.Sphere3(7.3, 6.8, 6.6, 3.7, 0)], [B.BCGroup3(B.NEUMANN, pressure=p)],
+                      lam=0.1, mu=0.05, tau=0.6, neumann_order=order)
+    assert len(set(np.round(b.links["q"], 6))) > 20
+    o = Oracle3D(b)
+    sig = np.zeros((6,) + o.shape)
+    sig[:3] = -p
+    o.init_fields(sigma=sig)
+    o.step(6)
+    m = o.moments()
+    mk = b.mask.astype(bool)
+    # rounding leaves ~1e-15; a wrong normal projection errs by the order of p
+    assert np.abs(m[3][:, mk] - sig[:, mk]).max() < 1e-13
+    assert np.abs(m[1][:, mk]).max() < 1e-13
+
+
+def test_moving_cavity_carries_a_uniform_translation():
+    """Patch test of eq:bbnoncon on a curved wall: a spherical cavity whose
+    wall moves with the material's uniform velocity keeps it translating."""
+    v0 = np.array([3e-4, -2e-4, 1e-4])
+    b = B.sphere_box3(16, 15, 14, [B.Sphere3(7.3, 6.8, 6.6, 3.7, 0)], [B.BCGroup3(B.DIRICHLET, tuple(v0))],
+                      lam=0.1, mu=0.05, tau=0.6)
+    o = Oracle3D(b)
+    o.init_fields(vel=np.broadcast_to(v0[:, None, None, None], (3,) + o.shape))
+    o.step(7)
+    rho, j, P, sig = o.moments()
+    mk = b.mask.astype(bool)
+    assert np.abs(j[:, mk] - v0[:, None]).max() < 1e-13
+    assert np.abs(sig[:, mk]).max() < 1e-13
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_brute_force_loops_with_a_cavity(order):
+    """One step of the general geometry against the per-site loop form on a
+    6 x 6 x 5 box with a small cavity (links of many q and normals, thin
+    links where the cavity is one site across), random populations."""
+    b = B.sphere_box3(6, 6, 5, [B.Sphere3(2.6, 2.4, 2.1, 1.3, 0)],
+                      [B.BCGroup3(B.NEUMANN, (1e-4, -2e-4, 5e-5), pressure=3e-4)], lam=0.09, mu=0.05, tau=0.6,
+                      force=(1e-5, 0.0, -2e-5), neumann_order=order)
+    b2 = B.sphere_box3(6, 6, 5, [B.Sphere3(2.6, 2.4, 2.1, 1.3, 0)], [B.BCGroup3(B.DIRICHLET, (1e-3, 2e-3, -1e-3))],
+                       lam=0.09, mu=0.05, tau=0.6, neumann_order=order)
+    rng = np.random.default_rng(9)
+    for box in (b, b2):
+        o = Oracle3D(box)
+        f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
+        f[:, ~box.mask.astype(bool)] = o.populations()[:, ~box.mask.astype(bool)]
+        o.set_populations(f)
+        U0 = rng.normal(size=(3,) + o.shape) * box.mask
+        o.U = U0.copy()
+        o.step(1)
+        fn, Un = naive_step(box, f, U0, [tuple(int(a) for a in c) for c in C])
+        assert np.abs(o.populations() - fn).max() < 1e-14
+        assert np.abs(o.U - Un).max() < 1e-14
+
+
+def test_inconsistent_cut_links_are_refused():
+    b = B.sphere_box3(10, 9, 8, [B.Sphere3(4.4, 4.2, 3.9, 2.2, 0)], [B.BCGroup3(B.NEUMANN)])
+    for bad in ("missing", "material_far_end", "q"):
+        links = b.links.copy()
+        if bad == "missing":
+            links = links[1:]
+        elif bad == "material_far_end":
+            links["dir"][0] = B.C3.tolist().index([-c for c in B.C3[links["dir"][0]].tolist()])
+        else:
+            links["q"][0] = 1.5
+        with pytest.raises(ValueError):
+            Oracle3D(B.Box3(b.nx, b.ny, b.nz, lam=b.lam, mu=b.mu, tau=b.tau, mask=b.mask, links=links,
+                            groups=b.groups))
