@@ -30,6 +30,22 @@
  *   a one-site-wide slab has none and takes kappa = 0, beta = 1.  Both
  *   walls apply from the first step.
  *
+ *   Directions c_i (D3Q19): 0 rest; 1-6 +x -x +y -y +z -z; 7-10 (1,1,0)
+ *   (-1,-1,0) (1,-1,0) (-1,1,0); 11-14 (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1);
+ *   15-18 (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).
+ *
+ *   General geometry: a box periodic on every axis with a material mask;
+ *   void sites (cavities, cracks) hold no material.  Each link from a
+ *   material site into the void is cut where it leaves the material, at its
+ *   own fraction q, with its own outward normal and boundary group, and takes
+ *   the rule of its group as above (Dirichlet: eq:bbcon / eq:bbnoncon;
+ *   Neumann: eq:abbcon / eq:abbnoncon with the traction t* = value -
+ *   pressure n).  Where the opposite link at the same site is cut too there
+ *   is no site behind: kappa = 0, beta = 1 and no extrapolation.  The density
+ *   gradient takes 2 rho(x) - rho(x - c_i) across a cut link (rho(x) if both
+ *   are cut).  Void sites report zero density, momentum, stress and
+ *   displacement.
+ *
  * Host arrays
  *   Arrays are [component][nz][ny][nx] of doubles, x fastest.  The site index
  *   is (iz*ny + iy)*nx + ix.  Vectors have three components (x, y, z).
@@ -61,6 +77,24 @@ typedef struct {
     double q;                    /* fraction of a cut link inside the material, (0, 1]; 1/2: lattice-conforming */
 } slbm3_wall;
 
+/* One cut link of a general geometry (48 bytes): the link from the material
+ * site x to x + c_dir, whose far end is void, crossing the boundary at the
+ * fraction q of its length. */
+typedef struct {
+    int32_t site;                /* (iz*ny + iy)*nx + ix of x, a material site */
+    int32_t dir;                 /* direction i of the link, 1..18 (order above) */
+    double q;                    /* (0, 1] */
+    int32_t group;               /* index into slbm3_params.groups */
+    double normal[3];            /* outward unit normal of the material where the link crosses */
+} slbm3_link;
+
+/* Boundary data shared by a group of cut links, user units. */
+typedef struct {
+    int32_t kind;                /* SLBM_DIRICHLET (value: wall velocity) or SLBM_NEUMANN */
+    double value[3];             /* Dirichlet: wall velocity; Neumann: traction, t* = value - pressure n */
+    double pressure;             /* Neumann: uniform pressure on the boundary (0: none); ignored for Dirichlet */
+} slbm3_bc_group;
+
 typedef struct {
     int32_t nx, ny, nz;          /* sites, each >= 1; at most 2^29 in total */
     double lambda, mu, rho;      /* user units; mu > 0, rho > 0, lambda > -mu */
@@ -69,6 +103,12 @@ typedef struct {
     int32_t periodic_x;          /* 1: periodic in x; 0: the two walls below */
     slbm3_wall walls[2];         /* crossing the links of the first and the last sites in x (ignored when periodic_x) */
     int32_t neumann_order;       /* 0: rho_bd and the tangential stress at the boundary site; 1: extrapolated */
+    /* General geometry (needs periodic_x = 1; NULL mask: none): */
+    const uint8_t* mask;         /* [nz][ny][nx], nonzero: material, 0: void */
+    int64_t n_links;             /* every link from a material site into the void, once */
+    const slbm3_link* links;     /* any order */
+    int32_t n_groups;
+    const slbm3_bc_group* groups;
     int32_t precision;           /* SLBM_FP64, or SLBM_FP32 (fp32 populations and arithmetic, fp64 U) */
     int32_t device;              /* HIP device ordinal */
     void* stream;                /* hipStream_t to queue work on; NULL: a stream owned by the handle */
@@ -76,7 +116,12 @@ typedef struct {
 
 /* Creates a box at rest (f = f_eq(rho, 0, 0), U = 0, step 0).  SLBM_E_INVAL
  * for invalid parameters, SLBM_E_UNSUPPORTED above 2^29 sites, SLBM_E_NOMEM
- * or SLBM_E_DEVICE if allocation fails; *out is NULL on failure. */
+ * or SLBM_E_DEVICE if allocation fails; *out is NULL on failure.  With a mask
+ * SLBM_E_INVAL also names the first invalid link: a site out of range or
+ * void, a direction out of 1..18, a far end that is material, q outside
+ * (0, 1], a group out of range, a normal that is not a unit vector (to
+ * 1e-9), a link listed twice, or a link from the material into the void
+ * that is not listed; and an invalid group kind.  The arrays are copied. */
 int slbm3_create(const slbm3_params* params, slbm3_handle* out);
 
 /* Sets the state from fields (any pointer may be NULL: density rho, velocity

@@ -28,6 +28,13 @@ struct slbm3_s {
     unsigned int* diverged = nullptr;
     double* scratch = nullptr;       // 19 planes of doubles, on demand (outputs, initial fields)
     int64_t step = 0;
+    // general geometry: site flags, first link record of each site, records
+    bool geo = false;
+    uint32_t* flags = nullptr;
+    int32_t* bidx = nullptr;
+    void* links = nullptr;
+    int64_t n_links = 0;
+    size_t link_bytes = 0;
 };
 
 namespace {
@@ -66,7 +73,119 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     a.ml = (real)(h->muL - h->lamL);
     a.lm = (real)(h->lamL - h->muL);
     for (int k = 0; k < 3; ++k) a.F[k] = (real)h->FL[k];
+    a.flags = h->flags;
+    a.bidx = h->bidx;
+    a.links = (const Link3<real>*)h->links;
     return a;
+}
+
+// The cut links of a general geometry as the kernels read them: per-site
+// flags (bit i - 1: link i cut; kVoid3: void), each cut site's first record,
+// and the records sorted by site and direction, in lattice units.  Validates
+// what slbm3_create documents; the host arrays are the caller's.
+struct Geo3 {
+    std::vector<uint32_t> flags;
+    std::vector<int32_t> bidx;
+    std::vector<Link3<double>> recs;
+};
+
+int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
+{
+    const long long n = h->plane;
+    const int nx = h->nx, ny = h->ny, nz = h->nz;
+    if (p->n_links < 0 || (p->n_links > 0 && !p->links)) return fail(SLBM_E_INVAL, "links: null array");
+    if (p->n_groups < 0 || (p->n_groups > 0 && !p->groups)) return fail(SLBM_E_INVAL, "groups: null array");
+    if (p->n_links > 18LL * n) return fail(SLBM_E_INVAL, "more links than a box has");
+    for (int k = 0; k < p->n_groups; ++k) {
+        const slbm3_bc_group& gr = p->groups[k];
+        if (gr.kind != SLBM_DIRICHLET && gr.kind != SLBM_NEUMANN)
+            return fail(SLBM_E_INVAL, "group %d: kind must be SLBM_DIRICHLET or SLBM_NEUMANN", k);
+        if (!std::isfinite(gr.value[0]) || !std::isfinite(gr.value[1]) || !std::isfinite(gr.value[2]) ||
+            !std::isfinite(gr.pressure))
+            return fail(SLBM_E_INVAL, "group %d: values must be finite", k);
+    }
+    g.flags.assign((size_t)n, 0u);
+    for (long long s = 0; s < n; ++s)
+        if (!p->mask[s]) g.flags[s] = kVoid3;
+    auto far_site = [&](long long s, int i) {
+        const long long x = s % nx, y = (s / nx) % ny, z = s / ((long long)nx * ny);
+        const long long fx = (x + kCX[i] + nx) % nx, fy = (y + kCY[i] + ny) % ny, fz = (z + kCZ[i] + nz) % nz;
+        return (fz * ny + fy) * nx + fx;
+    };
+    for (int64_t l = 0; l < p->n_links; ++l) {
+        const slbm3_link& L = p->links[l];
+        if (L.site < 0 || (long long)L.site >= n) return fail(SLBM_E_INVAL, "link %lld: site out of range", (long long)l);
+        if (L.dir < 1 || L.dir > 18) return fail(SLBM_E_INVAL, "link %lld: direction must be in 1..18", (long long)l);
+        if (!p->mask[L.site]) return fail(SLBM_E_INVAL, "link %lld: starts at a void site", (long long)l);
+        if (p->mask[far_site(L.site, L.dir)]) return fail(SLBM_E_INVAL, "link %lld: ends at a material site", (long long)l);
+        if (!(L.q > 0.0 && L.q <= 1.0)) return fail(SLBM_E_INVAL, "link %lld: q must be in (0, 1]", (long long)l);
+        if (L.group < 0 || L.group >= p->n_groups) return fail(SLBM_E_INVAL, "link %lld: group out of range", (long long)l);
+        const double nn = std::sqrt(L.normal[0] * L.normal[0] + L.normal[1] * L.normal[1] + L.normal[2] * L.normal[2]);
+        if (!(std::fabs(nn - 1.0) <= 1e-9)) return fail(SLBM_E_INVAL, "link %lld: normal is not a unit vector", (long long)l);
+        const uint32_t bit = 1u << (L.dir - 1);
+        if (g.flags[L.site] & bit) return fail(SLBM_E_INVAL, "link %lld: listed twice", (long long)l);
+        g.flags[L.site] |= bit;
+    }
+    // every link from the material into the void is listed
+    for (long long s = 0; s < n; ++s) {
+        if (!p->mask[s]) continue;
+        for (int i = 1; i < kQ; ++i)
+            if (!p->mask[far_site(s, i)] && !(g.flags[s] & (1u << (i - 1))))
+                return fail(SLBM_E_INVAL, "site %lld: link %d into the void is not listed", s, i);
+    }
+    // records sorted by site, then direction (the kernel walks a site's cut
+    // bits upwards from its first record)
+    std::vector<int64_t> order((size_t)p->n_links);
+    for (int64_t l = 0; l < p->n_links; ++l) order[(size_t)l] = l;
+    std::sort(order.begin(), order.end(), [&](int64_t u, int64_t v) {
+        const slbm3_link &A = p->links[u], &B = p->links[v];
+        return A.site != B.site ? A.site < B.site : A.dir < B.dir;
+    });
+    g.bidx.assign((size_t)n, 0);
+    g.recs.resize(order.size());
+    for (size_t r = 0; r < order.size(); ++r) {
+        const slbm3_link& L = p->links[order[r]];
+        if (r == 0 || p->links[order[r - 1]].site != L.site) g.bidx[L.site] = (int32_t)r;
+        const slbm3_bc_group& gr = p->groups[L.group];
+        const int i = L.dir, ib = opp3(i);
+        // section 4.2: no site behind x when the opposite link is cut too
+        const bool thin = (g.flags[L.site] >> (ib - 1)) & 1u;
+        const double q = L.q;
+        Link3<double>& R = g.recs[r];
+        R.kap = thin ? 0.0 : (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
+        R.bet = thin ? 1.0 : 2.0 / (1.0 + 2.0 * q);
+        R.q1 = 1.0 + q;
+        R.q = q;
+        R.w = w3(i);
+        for (int c = 0; c < 3; ++c) {
+            R.n[c] = L.normal[c];
+            R.a[c] = gr.kind == SLBM_DIRICHLET ? gr.value[c] / h->s_v
+                                               : (gr.value[c] - gr.pressure * R.n[c]) / h->s_sigma;
+        }
+        R.k = i;
+        R.kb = ib;
+        R.kind = gr.kind;
+        R.ext = gr.kind == SLBM_NEUMANN && h->norder == 1 && !thin ? 1 : 0;
+        R.cx = kCX[i]; R.cy = kCY[i]; R.cz = kCZ[i];
+        R.pad = 0;
+    }
+    return SLBM_OK;
+}
+
+// The records in the handle's precision.
+template <typename real>
+std::vector<Link3<real>> cast_links3(const std::vector<Link3<double>>& in)
+{
+    std::vector<Link3<real>> out(in.size());
+    for (size_t r = 0; r < in.size(); ++r) {
+        const Link3<double>& A = in[r];
+        Link3<real>& B = out[r];
+        B.kap = (real)A.kap; B.bet = (real)A.bet; B.q1 = (real)A.q1; B.q = (real)A.q; B.w = (real)A.w;
+        for (int c = 0; c < 3; ++c) { B.a[c] = (real)A.a[c]; B.n[c] = (real)A.n[c]; }
+        B.k = A.k; B.kb = A.kb; B.kind = A.kind; B.ext = A.ext;
+        B.cx = A.cx; B.cy = A.cy; B.cz = A.cz; B.pad = 0;
+    }
+    return out;
 }
 
 // Elements from one plane of a population or displacement buffer to the
@@ -88,7 +207,8 @@ int grid3(const slbm3_s* h)
 }
 
 // Density pass then `what` (0 step, 1 outputs into scratch, 2 init from scratch).
-template <typename real, bool PX>
+// GEO (general geometry) implies PX.
+template <typename real, bool PX, bool GEO>
 int launch3(slbm3_s* h, int what)
 {
     Step3Args<real> a = make_args3<real>(h, h->cur);
@@ -97,24 +217,27 @@ int launch3(slbm3_s* h, int what)
         a.dst = (real*)h->buf[h->cur];
         hipLaunchKernelGGL((k3_set_dens<real>), dim3((unsigned)((h->plane + 255) / 256)), blk, 0, h->stream, a,
                            (const double*)h->scratch);
-        hipLaunchKernelGGL((k3_init<real, PX>), grid, blk, 0, h->stream, a, (const double*)h->scratch);
+        hipLaunchKernelGGL((k3_init<real, PX, GEO>), grid, blk, 0, h->stream, a, (const double*)h->scratch);
         HIP_TRY(hipGetLastError());
         return SLBM_OK;
     }
-    hipLaunchKernelGGL((k3_density<real, PX>), grid, blk, 0, h->stream, a);
+    hipLaunchKernelGGL((k3_density<real, PX, GEO>), grid, blk, 0, h->stream, a);
     if (what == 0)
-        hipLaunchKernelGGL((k3_step<real, PX>), grid, blk, 0, h->stream, a);
+        hipLaunchKernelGGL((k3_step<real, PX, GEO>), grid, blk, 0, h->stream, a);
     else
-        hipLaunchKernelGGL((k3_outputs<real, PX>), grid, blk, 0, h->stream, a, h->scratch);
+        hipLaunchKernelGGL((k3_outputs<real, PX, GEO>), grid, blk, 0, h->stream, a, h->scratch);
     HIP_TRY(hipGetLastError());
     return SLBM_OK;
 }
 
 int launch3_any(slbm3_s* h, int what)
 {
-    if (h->precision == SLBM_FP32)
-        return h->px ? launch3<float, true>(h, what) : launch3<float, false>(h, what);
-    return h->px ? launch3<double, true>(h, what) : launch3<double, false>(h, what);
+    if (h->precision == SLBM_FP32) {
+        if (h->geo) return launch3<float, true, true>(h, what);
+        return h->px ? launch3<float, true, false>(h, what) : launch3<float, false, false>(h, what);
+    }
+    if (h->geo) return launch3<double, true, true>(h, what);
+    return h->px ? launch3<double, true, false>(h, what) : launch3<double, false, false>(h, what);
 }
 
 int ensure_scratch3(slbm3_s* h)
@@ -126,7 +249,8 @@ int ensure_scratch3(slbm3_s* h)
 
 void free3(slbm3_s* h)
 {
-    for (void* p : {h->buf[0], h->buf[1], (void*)h->U, h->dens, (void*)h->diverged, (void*)h->scratch})
+    for (void* p : {h->buf[0], h->buf[1], (void*)h->U, h->dens, (void*)h->diverged, (void*)h->scratch,
+                    (void*)h->flags, (void*)h->bidx, h->links})
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -172,6 +296,10 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
         if (plane > (1LL << 29))
             return fail(SLBM_E_UNSUPPORTED, "box exceeds 2^29 sites (kernels index a plane's sites with 32-bit offsets)");
         if (p->neumann_order != 0 && p->neumann_order != 1) return fail(SLBM_E_INVAL, "neumann_order must be 0 or 1");
+        if (p->mask && !p->periodic_x)
+            return fail(SLBM_E_INVAL, "a box with a material mask is periodic on every axis (periodic_x = 1)");
+        if (!p->mask && (p->n_links != 0 || p->n_groups != 0))
+            return fail(SLBM_E_INVAL, "links and groups need a material mask");
         if (!p->periodic_x) {
             for (int s = 0; s < 2; ++s) {
                 if (p->walls[s].kind != SLBM_DIRICHLET && p->walls[s].kind != SLBM_NEUMANN)
@@ -207,6 +335,13 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
             }
         }
         h->norder = p->neumann_order;
+        Geo3 geo;
+        if (p->mask) {
+            const int rc = build_geo3(p, h, geo);
+            if (rc) { delete h; return rc; }
+            h->geo = true;
+            h->n_links = (int64_t)geo.recs.size();
+        }
         DeviceGuard dg(h->device);
     #define TRY_OR_BAIL(expr)                                \
         do {                                                 \
@@ -230,6 +365,28 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
         TRY_OR_BAIL(hipMemsetAsync(h->buf[1], 0, pop, h->stream));
         TRY_OR_BAIL(hipMemsetAsync(h->U, 0, (size_t)3 * h->stride * sizeof(double), h->stream));
         TRY_OR_BAIL(hipMemsetAsync(h->diverged, 0, sizeof(unsigned int), h->stream));
+        if (h->geo) {
+            TRY_OR_BAIL(hipMalloc((void**)&h->flags, (size_t)plane * sizeof(uint32_t)));
+            TRY_OR_BAIL(hipMalloc((void**)&h->bidx, (size_t)plane * sizeof(int32_t)));
+            TRY_OR_BAIL(hipMemcpyAsync(h->flags, geo.flags.data(), (size_t)plane * sizeof(uint32_t),
+                                       hipMemcpyHostToDevice, h->stream));
+            TRY_OR_BAIL(hipMemcpyAsync(h->bidx, geo.bidx.data(), (size_t)plane * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, h->stream));
+            if (!geo.recs.empty()) {
+                if (h->precision == SLBM_FP32) {
+                    const std::vector<Link3<float>> r = cast_links3<float>(geo.recs);
+                    h->link_bytes = r.size() * sizeof(Link3<float>);
+                    TRY_OR_BAIL(hipMalloc(&h->links, h->link_bytes));
+                    TRY_OR_BAIL(hipMemcpyAsync(h->links, r.data(), h->link_bytes, hipMemcpyHostToDevice, h->stream));
+                    TRY_OR_BAIL(hipStreamSynchronize(h->stream));
+                } else {
+                    h->link_bytes = geo.recs.size() * sizeof(Link3<double>);
+                    TRY_OR_BAIL(hipMalloc(&h->links, h->link_bytes));
+                    TRY_OR_BAIL(hipMemcpyAsync(h->links, geo.recs.data(), h->link_bytes, hipMemcpyHostToDevice,
+                                               h->stream));
+                }
+            }
+        }
         TRY_OR_BAIL(hipStreamSynchronize(h->stream));
     #undef TRY_OR_BAIL
         *out = h;
@@ -404,6 +561,7 @@ int slbm3_device_bytes(slbm3_handle h, int64_t* bytes)
         if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
         int64_t b = 2 * (int64_t)19 * h->stride * (int64_t)h->esize + 3 * h->stride * 8 + h->plane * (int64_t)h->esize;
         if (h->scratch) b += (int64_t)19 * h->plane * 8;
+        if (h->geo) b += h->plane * 8 + (int64_t)h->link_bytes;
         *bytes = b;
         return SLBM_OK;
     });

@@ -41,6 +41,25 @@ __host__ __device__ constexpr int c2_3(int i) { return kCX[i] * kCX[i] + kCY[i] 
 
 enum { kWallNone = 0, kWallDirichlet = 1, kWallNeumann = 2 };
 
+// Site flags of a box with cut links (general geometry): bit i - 1 set when
+// link i of the site is cut, kVoid3 for a void site.
+constexpr uint32_t kVoid3 = 0x80000000u;
+constexpr uint32_t kCutMask3 = 0x3FFFFu;
+
+// One cut link (x, i) of a general geometry, in lattice units: the rule's
+// kappa and beta (0 and 1 when the opposite link is cut too, no site behind),
+// the extrapolation weights 1 + q and q, w_i, the wall velocity (Dirichlet)
+// or traction t* = value - pressure n (Neumann), the outward normal n, and
+// the link's direction.
+template <typename real>
+struct Link3 {
+    real kap, bet, q1, q, w;
+    real a[3];
+    real n[3];
+    int32_t k, kb, kind, ext;  // ext: Neumann with rho_bd and sigma_b extrapolated
+    int32_t cx, cy, cz, pad;
+};
+
 template <typename real>
 struct Step3Args {
     const real* src;           // post-collision state (pulled), or the populations themselves (local)
@@ -61,6 +80,11 @@ struct Step3Args {
     // the tangential stress extrapolated along the link, weights 1 + q, -q
     real wkap[2], wbeta[2], wq1[2], wq[2];
     int wext[2];
+    // general geometry (periodic on every axis): site flags, each cut site's
+    // first link record, the records (sorted by site and direction)
+    const uint32_t* flags;
+    const int32_t* bidx;
+    const Link3<real>* links;
     real omega, omega_h;       // 1/tau, 1 - 1/(2 tau)
     real ml, lm;               // mu - lambda, lambda - mu (lattice units)
     real F[3];
@@ -305,11 +329,119 @@ __device__ __forceinline__ unsigned sidx3(int x, int y, int z, int nx, int ny)
 // returning population comes from the wall rule, from the site's own
 // post-collision populations (rho and P are those of the previous step,
 // conserved by the collision).
-template <typename real, bool PX>
-__device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st, real g[kQ])
+// h[k] = x for a k known only at run time, by bit masks (a dynamically
+// indexed register array would go through scratch memory or LDS).
+__device__ __forceinline__ unsigned bits19(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ unsigned long long bits19(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ __forceinline__ float unbits19(unsigned v, float) { return __uint_as_float(v); }
+__device__ __forceinline__ double unbits19(unsigned long long v, double) { return __longlong_as_double((long long)v); }
+
+template <typename real>
+__device__ __forceinline__ void put19(real h[kQ], int k, real x)
+{
+    using B = decltype(bits19(real(0)));
+    const B b = bits19(x);
+#pragma unroll
+    for (int j = 0; j < kQ; ++j) {
+        const B m = (B)(0 - (B)(k == j));
+        h[j] = unbits19((bits19(h[j]) & ~m) | (b & m), real(0));
+    }
+}
+
+// The rules of section 4 at the cut links of a general geometry's site: each
+// link's own q, normal and group (eq:bbcon / eq:bbnoncon, eq:abbcon /
+// eq:abbnoncon with sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n).
+template <typename real>
+__device__ __forceinline__ void cut_links3(const Step3Args<real>& a, const Site3& st, unsigned s, uint32_t fl, real g[kQ])
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    real dr, j[3], P[6];
+    {
+        real h[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) h[i] = a.src[i * a.stride + s];
+        moments3(h, dr, j, P);
+    }
+    const real rho = real(1) + dr;
+    int li = a.bidx[s];
+    uint32_t m = fl & kCutMask3;
+    while (m) {
+        m &= m - 1;
+        const Link3<real> L = a.links[li++];
+        const int i = L.k, ib = L.kb;
+        // the site behind x along the link, x - c_i (periodic axes)
+        const unsigned sb = sidx3(wrap(st.x - L.cx, nx), wrap(st.y - L.cy, ny), wrap(st.z - L.cz, nz), nx, ny);
+        const real hi = a.src[i * a.stride + s], hib = a.src[ib * a.stride + s];
+        const real hy = L.kap != real(0) ? a.src[i * a.stride + sb] : real(0);
+        real val;
+        if (L.kind == kWallDirichlet) {
+            const real cv = real(L.cx) * L.a[0] + real(L.cy) * L.a[1] + real(L.cz) * L.a[2];
+            val = hi + L.kap * (hy - hib) - L.bet * (real(6) * L.w * rho * cv);
+        } else {
+            // sigma_b = -P_b - (lambda - mu) drho_b I at the site, or
+            // extrapolated along the link; rho_bd likewise
+            real drb = dr, Pb[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) Pb[c] = P[c];
+            if (L.ext) {
+                real hb[kQ];
+#pragma unroll
+                for (int k = 0; k < kQ; ++k) hb[k] = a.src[k * a.stride + sb];
+                real dry, jy[3], Py[6];
+                moments3(hb, dry, jy, Py);
+                drb = L.q1 * dr - L.q * dry;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) Pb[c] = L.q1 * P[c] - L.q * Py[c];
+            }
+            // full 3 x 3 of sigma_b (xx yy zz xy xz yz)
+            real sb3[3][3];
+            sb3[0][0] = -Pb[0] - a.lm * drb; sb3[1][1] = -Pb[1] - a.lm * drb; sb3[2][2] = -Pb[2] - a.lm * drb;
+            sb3[0][1] = sb3[1][0] = -Pb[3];
+            sb3[0][2] = sb3[2][0] = -Pb[4];
+            sb3[1][2] = sb3[2][1] = -Pb[5];
+            const real n[3] = {L.n[0], L.n[1], L.n[2]};
+            real Pi[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Pi[r][c] = (r == c ? real(1) : real(0)) - n[r] * n[c];
+            real tmp[3][3], st3[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) tmp[r][c] = Pi[r][0] * sb3[0][c] + Pi[r][1] * sb3[1][c] + Pi[r][2] * sb3[2][c];
+            const real tn = L.a[0] * n[0] + L.a[1] * n[1] + L.a[2] * n[2];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    st3[r][c] = (tmp[r][0] * Pi[0][c] + tmp[r][1] * Pi[1][c] + tmp[r][2] * Pi[2][c])
+                                + n[r] * L.a[c] + L.a[r] * n[c] - tn * n[r] * n[c];
+            // P* = -sigma* - (lambda - mu) drho_bd I; g_eq,i(drho_bd, 0, P*)
+            const real cx = real(L.cx), cy = real(L.cy), cz = real(L.cz);
+            const real c2 = cx * cx + cy * cy + cz * cz;
+            const real third = real(1.0 / 3.0);
+            const real pxx = -st3[0][0] - a.lm * drb, pyy = -st3[1][1] - a.lm * drb, pzz = -st3[2][2] - a.lm * drb;
+            const real quad = pxx * (cx * cx - third) + pyy * (cy * cy - third) + pzz * (cz * cz - third)
+                              + real(2) * (-st3[0][1] * cx * cy - st3[0][2] * cx * cz - st3[1][2] * cy * cz);
+            const real e = L.w * (drb * (real(2.5) - real(1.5) * c2) + real(4.5) * quad);
+            val = -hi - L.kap * (hy + hib) + L.bet * (real(2) * e);
+        }
+        put19(g, ib, val);
+    }
+}
+
+template <typename real, bool PX, bool GEO = false>
+__device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st, real g[kQ], uint32_t& fl)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned s = sidx3(st.x, st.y, st.z, nx, ny);
+    fl = GEO ? a.flags[s] : 0u;
+    if (GEO && (fl & kVoid3)) {                 // void: nothing to pull
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) g[i] = real(0);
+        return;
+    }
     if (a.local) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = a.src[i * a.stride + s];
@@ -331,6 +463,10 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
         const int yy = kCY[i] > 0 ? ym : (kCY[i] < 0 ? yp : st.y);
         const int zz = kCZ[i] > 0 ? zm : (kCZ[i] < 0 ? zp : st.z);
         g[i] = a.src[i * a.stride + sidx3(xx, yy, zz, nx, ny)];
+    }
+    if constexpr (GEO) {
+        if ((fl & kCutMask3) != 0u) cut_links3<real>(a, st, s, fl, g);
+        return;
     }
     if (!PX && (st.x == 0 || st.x == nx - 1)) {
         real h[kQ];
@@ -410,8 +546,9 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
 // Density gradient of eq:sourceterm, isotropic D3Q19 stencil
 // grad = 3 sum_i w_i c_i rho(x + c_i), from the delta-rho buffer; across a
 // cut link the neighbour is 2 rho(x) - rho(x - c_i) (rho(x) if that is cut too).
-template <typename real, bool PX>
-__device__ __forceinline__ void grad3(const Step3Args<real>& a, const Site3& st, real dr, real grad[3])
+template <typename real, bool PX, bool GEO = false>
+__device__ __forceinline__ void grad3(const Step3Args<real>& a, const Site3& st, real dr, real grad[3],
+                                      uint32_t fl = 0u)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const real* d = a.dens;
@@ -434,6 +571,16 @@ __device__ __forceinline__ void grad3(const Step3Args<real>& a, const Site3& st,
         for (int i = 1; i < kQ; ++i) {
             const bool ci = (kCX[i] < 0 && cutm) || (kCX[i] > 0 && cutp);
             const bool co = (kCX[i] > 0 && cutm) || (kCX[i] < 0 && cutp);
+            sub[i] = ci ? (co ? dr : real(2) * dr - nb[opp3(i)]) : nb[i];
+        }
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) nb[i] = sub[i];
+    }
+    if (GEO && (fl & kCutMask3) != 0u) {
+        real sub[kQ];
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+            const bool ci = (fl >> (i - 1)) & 1u, co = (fl >> (opp3(i) - 1)) & 1u;
             sub[i] = ci ? (co ? dr : real(2) * dr - nb[opp3(i)]) : nb[i];
         }
 #pragma unroll
@@ -462,17 +609,19 @@ __device__ __forceinline__ int xcd_group3(int b)
 }
 
 // delta-rho of the pulled state at every site.
-template <typename real, bool PX>
+template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_density(Step3Args<real> a)
 {
     const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
-    pull3<real, PX>(a, st, g);
+    uint32_t fl;
+    pull3<real, PX, GEO>(a, st, g, fl);
     real dr = real(0);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) dr += g[i];
+    if (GEO && (fl & kVoid3)) dr = real(0);               // void: never read
     if (st.in) a.dens[sidx3(st.x, st.y, st.z, a.nx, a.ny)] = dr;
 }
 
@@ -482,18 +631,20 @@ __device__ __forceinline__ double recip3(double x) { return 1.0 / x; }
 
 // One time step at every site: pull (with the wall rules), moments, source
 // term, eq:coll, U += j/rho, store.
-template <typename real, bool PX>
+template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 {
     const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
-    pull3<real, PX>(a, st, g);
+    uint32_t fl;
+    pull3<real, PX, GEO>(a, st, g, fl);
+    const bool live = st.in && !(GEO && (fl & kVoid3));  // void sites keep their (rest) state
     real dr, j[3], P[6];
     moments3(g, dr, j, P);
     real grad[3];
-    grad3<real, PX>(a, st, dr, grad);
+    grad3<real, PX, GEO>(a, st, dr, grad, fl);
     const real rho = real(1) + dr;
     const real ir = recip3(rho);
     const real c = a.ml * ir;
@@ -508,13 +659,13 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
     real o[kQ];
     collide_ghost3(g, dr, j, P, S, a.omega, a.omega_h, o);
     const bool bad = !(fabs(dr) + fabs(j[0]) + fabs(j[1]) + fabs(j[2]) < real(kDivergeBound));
-    if (st.in) {
+    if (live) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) a.dst[i * a.stride + s] = o[i];
 #pragma unroll
         for (int k = 0; k < 3; ++k) a.U[k * a.stride + s] = a.U[k * a.stride + s] + (double)(j[k] * ir);
     }
-    if (__any(bad && st.in) && (threadIdx.x & 63) == 0 && *(volatile unsigned int*)a.diverged == 0u)
+    if (__any(bad && live) && (threadIdx.x & 63) == 0 && *(volatile unsigned int*)a.diverged == 0u)
         atomicOr(a.diverged, 1u);
 }
 
@@ -522,23 +673,29 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 // delta-rho, 1-3 j (with S/2), 4-9 P, 10-15 the Cauchy stress
 // sigma = -P - (lambda - mu) drho I, 16-18 the displacement U + (j/rho)/2.
 // Needs k3_density of the same state first.
-template <typename real, bool PX>
+template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_outputs(Step3Args<real> a, double* out)
 {
     const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
-    pull3<real, PX>(a, st, g);
+    uint32_t fl;
+    pull3<real, PX, GEO>(a, st, g, fl);
     real dr, j[3], P[6];
     moments3(g, dr, j, P);
     real grad[3];
-    grad3<real, PX>(a, st, dr, grad);
+    grad3<real, PX, GEO>(a, st, dr, grad, fl);
     const real rho = real(1) + dr;
     const real c = a.ml / rho;
     if (!st.in) return;
     const unsigned s = sidx3(st.x, st.y, st.z, a.nx, a.ny);
     const long long n = a.plane;
+    if (GEO && (fl & kVoid3)) {                             // void sites report zeros (rho too)
+        out[s] = -1.0;
+        for (int k = 1; k < 19; ++k) out[k * n + s] = 0.0;
+        return;
+    }
     out[s] = (double)dr;
     for (int k = 0; k < 3; ++k) {
         const double jk = (double)j[k] + 0.5 * ((double)a.F[k] + (double)c * (double)grad[k]);
@@ -563,7 +720,7 @@ __global__ __launch_bounds__(256) void k3_set_dens(Step3Args<real> a, const doub
 // delta-rho, 1-3 j, 4-9 P, 10-12 u0; dens must hold delta-rho.  Populations
 // g = g_eq(drho, j - S/2, P) at the sites themselves (the state is "local"),
 // U = u0 - (j/rho)/2.
-template <typename real, bool PX>
+template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_init(Step3Args<real> a, const double* in)
 {
     const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -571,9 +728,17 @@ __global__ __launch_bounds__(256) void k3_init(Step3Args<real> a, const double* 
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     const unsigned s = sidx3(st.x, st.y, st.z, a.nx, a.ny);
     const long long n = a.plane;
+    const uint32_t fl = GEO ? a.flags[s] : 0u;
+    if (GEO && (fl & kVoid3)) {                             // void: the rest state, no displacement
+        if (st.in) {
+            for (int k = 0; k < kQ; ++k) a.dst[k * a.stride + s] = real(0);
+            for (int k = 0; k < 3; ++k) a.U[k * a.stride + s] = 0.0;
+        }
+        return;
+    }
     const real dr = (real)in[s];
     real grad[3];
-    grad3<real, PX>(a, st, dr, grad);
+    grad3<real, PX, GEO>(a, st, dr, grad, fl);
     const double rho = 1.0 + in[s];
     const real c = a.ml / (real)rho;
     real j[3], P[6];

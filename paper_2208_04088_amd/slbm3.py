@@ -19,6 +19,15 @@ class Wall(C.Structure):
     _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("q", C.c_double)]
 
 
+class Link(C.Structure):
+    _fields_ = [("site", C.c_int32), ("dir", C.c_int32), ("q", C.c_double), ("group", C.c_int32),
+                ("normal", C.c_double * 3)]
+
+
+class BCGroup(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("pressure", C.c_double)]
+
+
 class Params3(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
@@ -27,6 +36,8 @@ class Params3(C.Structure):
         ("periodic_x", C.c_int32),
         ("walls", Wall * 2),
         ("neumann_order", C.c_int32),
+        ("mask", C.c_void_p), ("n_links", C.c_int64), ("links", C.c_void_p),
+        ("n_groups", C.c_int32), ("groups", C.c_void_p),
         ("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
     ]
 
@@ -62,8 +73,12 @@ def lib():
     return L
 
 
+LINK_FIELDS = ("site", "dir", "q", "group", "normal")
+
+
 def marshal(box, precision=S.FP32, device=0, stream=None):
-    """slbm3_params for a :class:`slbm_workloads.box3d.Box3`."""
+    """(slbm3_params, keep) for a :class:`slbm_workloads.box3d.Box3`; `keep`
+    holds the arrays the params point to until slbm3_create has copied them."""
     if isinstance(precision, str):
         precision = S.PRECISION[precision]
     walls = (Wall * 2)()
@@ -72,10 +87,29 @@ def marshal(box, precision=S.FP32, device=0, stream=None):
     if box.x_walls is not None:
         for k, w in enumerate(box.x_walls):
             walls[k] = Wall(int(w.kind), (C.c_double * 3)(*w.value), float(w.q))
-    return Params3(nx=box.nx, ny=box.ny, nz=box.nz, lam=box.lam, mu=box.mu, rho=box.rho, tau=box.tau,
-                   body_force=(C.c_double * 3)(*box.force), periodic_x=int(box.x_walls is None),
-                   walls=walls, neumann_order=int(box.neumann_order), precision=int(precision),
-                   device=int(device), stream=stream)
+    prm = Params3(nx=box.nx, ny=box.ny, nz=box.nz, lam=box.lam, mu=box.mu, rho=box.rho, tau=box.tau,
+                  body_force=(C.c_double * 3)(*box.force), periodic_x=int(box.x_walls is None),
+                  walls=walls, neumann_order=int(box.neumann_order), precision=int(precision),
+                  device=int(device), stream=stream)
+    keep = []
+    if box.mask is not None:
+        mask = np.ascontiguousarray(box.mask, dtype=np.uint8)
+        if mask.shape != (box.nz, box.ny, box.nx):
+            raise ValueError("mask shape must be (nz, ny, nx)")
+        links = np.zeros(0 if box.links is None else len(box.links), dtype=Link)
+        if box.links is not None:
+            for f in LINK_FIELDS:
+                links[f] = box.links[f]
+        groups = (BCGroup * max(1, len(box.groups or [])))()
+        for k, g in enumerate(box.groups or []):
+            groups[k] = BCGroup(int(g.kind), (C.c_double * 3)(*g.value), float(getattr(g, "pressure", 0.0)))
+        prm.mask = mask.ctypes.data
+        prm.n_links = len(links)
+        prm.links = links.ctypes.data if len(links) else None
+        prm.n_groups = len(box.groups or [])
+        prm.groups = C.cast(groups, C.c_void_p)
+        keep = [mask, links, groups]
+    return prm, keep
 
 
 class Solver3:
@@ -84,9 +118,10 @@ class Solver3:
     def __init__(self, box, precision="fp32", device=0, stream=None):
         L = lib()
         self.box = box
-        prm = marshal(box, precision, device, stream)
+        prm, keep = marshal(box, precision, device, stream)
         h = C.c_void_p()
         S._check(L.slbm3_create(C.byref(prm), C.byref(h)))
+        del keep
         self.h = h
         self.n = box.nx * box.ny * box.nz
         self.shape = (box.nz, box.ny, box.nx)

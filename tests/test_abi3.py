@@ -7,6 +7,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2208_04088_amd import slbm as S
@@ -38,7 +39,13 @@ def test_struct_layout_matches_header(tmp_path):
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "slbm3.h"', "int main(void){",
              'printf("slbm3_params %zu\\n", sizeof(slbm3_params));',
              'printf("slbm3_wall %zu\\n", sizeof(slbm3_wall));',
-             'printf("slbm3_wall.value %zu\\n", offsetof(slbm3_wall, value));']
+             'printf("slbm3_wall.value %zu\\n", offsetof(slbm3_wall, value));',
+             'printf("slbm3_link %zu\\n", sizeof(slbm3_link));',
+             'printf("slbm3_bc_group %zu\\n", sizeof(slbm3_bc_group));']
+    for f, _ in S3.Link._fields_:
+        lines.append(f'printf("slbm3_link.{f} %zu\\n", offsetof(slbm3_link, {f}));')
+    for f, _ in S3.BCGroup._fields_:
+        lines.append(f'printf("slbm3_bc_group.{f} %zu\\n", offsetof(slbm3_bc_group, {f}));')
     for f, _ in S3.Params3._fields_:
         lines.append(f'printf("slbm3_params.{f} %zu\\n", offsetof(slbm3_params, {cname.get(f, f)}));')
     lines.append("return 0;}")
@@ -52,10 +59,17 @@ def test_struct_layout_matches_header(tmp_path):
     assert int(out["slbm3_wall.value"]) == S3.Wall.value.offset
     for f, _ in S3.Params3._fields_:
         assert int(out[f"slbm3_params.{f}"]) == getattr(S3.Params3, f).offset, f
+    # the link records are the workloads' LINK3_DTYPE, byte for byte
+    assert int(out["slbm3_link"]) == C.sizeof(S3.Link) == B.LINK3_DTYPE.itemsize == 48
+    for f, _ in S3.Link._fields_:
+        assert int(out[f"slbm3_link.{f}"]) == getattr(S3.Link, f).offset == B.LINK3_DTYPE.fields[f][1], f
+    assert int(out["slbm3_bc_group"]) == C.sizeof(S3.BCGroup)
+    for f, _ in S3.BCGroup._fields_:
+        assert int(out[f"slbm3_bc_group.{f}"]) == getattr(S3.BCGroup, f).offset, f
 
 
 def _create(box, **over):
-    prm = S3.marshal(box, "fp32")
+    prm, keep = S3.marshal(box, "fp32")
     for k, v in over.items():
         setattr(prm, k, v)
     h = C.c_void_p()
@@ -101,3 +115,66 @@ def test_device_outputs_reject_a_null_handle():
     L = S3.lib()
     assert L.slbm3_displacement_device(None, None) == -1
     assert L.slbm3_moments_device(None, None, None, None, None, 0) == -1
+
+
+def _cavity():
+    groups = [B.BCGroup3(B.NEUMANN, (0.0, 0.0, 0.0), 1e-4), B.BCGroup3(B.DIRICHLET)]
+    return B.sphere_box3(12, 11, 10, [B.Sphere3(5.6, 5.3, 4.8, 2.3, 0)], groups)
+
+
+def _set(box, field, i, value):
+    links = box.links.copy()
+    links[field][i] = value
+    box.links = links
+
+
+@pytest.mark.parametrize("case", ["site_range", "dir", "void_start", "material_end", "q0", "q_big", "group",
+                                  "normal", "twice", "missing", "group_kind", "walls", "no_mask"])
+def test_invalid_cut_links_are_rejected_on_the_host(case):
+    """Every check slbm3_create documents for a general geometry, one at a
+    time, on a valid cavity: the call fails with SLBM_E_INVAL and a message
+    before any device work."""
+    box = _cavity()
+    over = {}
+    void = int(np.flatnonzero(box.mask.ravel() == 0)[0])
+    if case == "site_range":
+        _set(box, "site", 3, box.n_sites)
+    elif case == "dir":
+        _set(box, "dir", 0, 19)
+    elif case == "void_start":
+        _set(box, "site", 0, void)
+    elif case == "material_end":
+        # the opposite direction from the same site ends in the material
+        d = int(box.links["dir"][0])
+        _set(box, "dir", 0, d + 1 if d % 2 else d - 1)
+    elif case == "q0":
+        _set(box, "q", 2, 0.0)
+    elif case == "q_big":
+        _set(box, "q", 2, 1.5)
+    elif case == "group":
+        _set(box, "group", 1, 2)
+    elif case == "normal":
+        _set(box, "normal", 4, (1.0, 1e-3, 0.0))
+    elif case == "twice":
+        box.links = np.concatenate([box.links, box.links[:1]])
+    elif case == "missing":
+        box.links = box.links[1:]
+    elif case == "group_kind":
+        box.groups[1] = B.BCGroup3(7)
+    elif case == "walls":
+        over = dict(periodic_x=0)
+    elif case == "no_mask":
+        over = dict(mask=None)
+    rc, msg = _create(box, **over)
+    assert rc == -1, (case, rc, msg)
+    assert msg
+
+
+def test_valid_cavity_without_a_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    box = _cavity()
+    assert len(box.links) > 0 and box.n_material < box.n_sites
+    rc, msg = _create(box)
+    assert rc == -3, (rc, msg)

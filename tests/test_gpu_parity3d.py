@@ -247,3 +247,77 @@ def test_device_outputs_match_host_outputs(S3, prec):
             w = want.astype(np.float32) if dt == "fp32" else want
             assert np.array_equal(got.cpu().numpy(), w)
     s.close()
+
+
+# ------------------------------------------------------------ cut links
+def _thin_links(box):
+    """Cut links whose opposite link at the same site is cut too."""
+    cut = {(int(s), int(d)) for s, d in zip(box.links["site"], box.links["dir"])}
+    return sum((s, d + 1 if d % 2 else d - 1) in cut for s, d in cut)
+
+
+def _cavities(order, pressure=2e-4):
+    """A box ragged against the 64-site rows (70 x 14 x 12) with two spherical
+    cavities one site apart along x (the site between them has both x links
+    cut: no site behind), one pressurised with a shear traction (Neumann),
+    one a moving wall (Dirichlet), a body force.  lambda = mu and tau_bar =
+    0.7: the rules' interpolation at small q (links that barely leave the
+    material) stays stable there, so that a few hundred steps remain a
+    meaningful fp32 comparison (the extrapolated Neumann form, order 1, grows
+    a boundary mode even so and runs fewer steps)."""
+    groups = [B.BCGroup3(B.NEUMANN, (2e-5, -1e-5, 3e-5), pressure), B.BCGroup3(B.DIRICHLET, (2e-4, -1e-4, 5e-5))]
+    sph = [B.Sphere3(30.0, 6.6, 5.9, 3.0, 0), B.Sphere3(36.9, 7.1, 6.2, 3.0, 1)]
+    return B.sphere_box3(70, 14, 12, sph, groups, lam=0.05, mu=0.05, tau=0.7, force=(2e-6, 0.0, -1e-6),
+                         neumann_order=order)
+
+
+@pytest.mark.parametrize("prec,tol,order,steps", [("fp64", FP64_TOL, 0, 40), ("fp64", FP64_TOL, 1, 40),
+                                                  ("fp32", FP32_TOL, 0, 300), ("fp32", FP32_TOL, 1, 60)])
+def test_cavities_with_cut_links(S3, prec, tol, order, steps):
+    box = _cavities(order)
+    assert _thin_links(box) > 0 and len(set(np.round(box.links["q"], 6))) > 20
+    fields = dict(vel=B.random_velocity(box, 31 + order, 1e-3))
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"cavities {prec} order {order}", box)
+    # void sites report zeros
+    mk = ~box.mask.astype(bool)
+    assert np.all(out[0][:, mk] == 0) and np.all(out[1][0][mk] == 0) and np.all(out[1][3][:, mk] == 0)
+
+
+def test_pressurised_cavity_holds_its_hydrostatic_state(S3):
+    """The oracle's patch test on the GPU: under the uniform stress -p I a
+    cavity loaded by the pressure p stays at rest (fp64, 30 steps)."""
+    p = 2e-4
+    box = B.sphere_box3(70, 15, 14, [B.Sphere3(40.3, 6.8, 6.6, 3.7, 0)], [B.BCGroup3(B.NEUMANN, pressure=p)],
+                        lam=0.1, mu=0.05, tau=0.6, neumann_order=1)
+    sig = np.zeros((6, box.nz, box.ny, box.nx))
+    sig[:3] = -p
+    with S3.Solver3(box, "fp64") as s:
+        s.init_fields(sigma=sig)
+        s.step(30)
+        s.sync()
+        rho, j, P, sg = s.moments()
+    mk = box.mask.astype(bool)
+    assert np.abs(sg[:, mk] - sig[:, mk]).max() < 1e-12 * p / 1e-4
+    assert np.abs(j[:, mk]).max() < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mask_without_void_matches_the_periodic_box(S3, prec):
+    """A material mask with no void and no links runs the cut-link kernels
+    on a box without boundaries: the same state as the periodic box, to the
+    bit."""
+    box = B.periodic_box3(70, 9, 7, lam=0.08, mu=0.05, tau=0.6, force=(1e-6, -2e-6, 0.5e-6))
+    fields = dict(vel=B.random_velocity(box, 41, 1e-3))
+    geo = B.Box3(**{**box.__dict__, "mask": np.ones((box.nz, box.ny, box.nx), np.uint8),
+                    "links": np.zeros(0, B.LINK3_DTYPE), "groups": []})
+    res = []
+    for b in (box, geo):
+        with S3.Solver3(b, prec) as s:
+            s.init_fields(**fields)
+            s.step(25)
+            s.sync()
+            res.append((s.displacement(), s.moments()))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    for a, b in zip(res[0][1], res[1][1]):
+        np.testing.assert_array_equal(a, b)
