@@ -14,6 +14,7 @@ sub-records.
     python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
     python bench.py --workload serve       # served requests: continuous batching vs one at a time
     python bench.py --workload cube256     # the three-dimensional (D3Q19) step on a 256^3 slab
+    python bench.py --workload cavities256 # the 3-D step on a 256^3 porous solid (64 pressurised cavities)
 
 Prints one JSON line.  `value` is material-site updates per second (MLUPS)
 with the state already in device memory when the timed region starts; the
@@ -50,9 +51,19 @@ def workload(name):
         "movinghole2048": (lambda: configs.moving_hole_plate(), "fp32"),
     }
     if name not in table:
-        raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}, batch64, serve or cube<N>")
+        raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}, batch64, serve, cube<N> or cavities<N>")
     f, prec = table[name]
     return f(), prec
+
+
+def box3_workload(name):
+    """("cube" | "cavities", n) for the 3-D workloads cube<n> and cavities<n>
+    (n >= 64 for cavities), else None."""
+    for kind in ("cube", "cavities"):
+        tail = name[len(kind):]
+        if name.startswith(kind) and tail.isdigit() and int(tail) > 0 and (kind == "cube" or int(tail) >= 64):
+            return kind, int(tail)
+    return None
 
 
 def bytes_per_site(prec):
@@ -154,6 +165,20 @@ def bytes_per_site3(prec):
     return 19 * 2 * (4 if prec == "fp32" else 8) + 3 * 2 * 8
 
 
+def link_record_bytes3(prec):
+    # one cut link's record as the kernels read it: 12 reals and two 32-bit words
+    return 56 if prec == "fp32" else 104
+
+
+def bytes_per_step3(box, prec):
+    """Algorithmic HBM bytes of one 3-D step: every material site's
+    populations and displacement read and written once; with cut links also
+    each site's flags (4 B) and each link record once."""
+    if box.mask is None:
+        return box.n_sites * bytes_per_site3(prec)
+    return box.n_material * bytes_per_site3(prec) + 4 * box.n_sites + len(box.links) * link_record_bytes3(prec)
+
+
 def measured_traffic3(box, prec):
     """Calibrated counter bytes per step of the two 3-D kernels
     (profiles/traffic_<box>_<precision>.json), or None when there is none or
@@ -167,19 +192,21 @@ def measured_traffic3(box, prec):
     if d.get("kernel_fingerprint") != kernel_fingerprint("step3_kernel.h"):
         return None
     shapes = d.get("shapes", {})
-    parts = [shapes.get(k) for k in ("k3_density", "k3_step")]
+    kernels = ("k3_links", "k3_density", "k3_step") if box.mask is not None else ("k3_density", "k3_step")
+    parts = [shapes.get(k) for k in kernels]
     return None if None in parts else sum(p["traffic_bytes_per_launch"] for p in parts)
 
 
-def cpu_baseline3(box, budget_s=15.0):
+def cpu_baseline3(box, budget_s=15.0, sample=None):
     """The CPU reference (numpy, fp64) on a bounded sample: a 64^3 box of the
-    same configuration, stepped for about `budget_s` seconds."""
+    same configuration (or `sample`), stepped for about `budget_s` seconds."""
     import numpy as np
     from oracle.slbm3d import Oracle3D
     from slbm_workloads import box3d as B
-    n = min(64, box.nx)
-    sample = B.Box3(n, min(64, box.ny), min(64, box.nz), lam=box.lam, mu=box.mu, tau=box.tau, rho=box.rho,
-                    force=box.force, x_walls=box.x_walls, name=f"{box.name}-sample{n}")
+    if sample is None:
+        n = min(64, box.nx)
+        sample = B.Box3(n, min(64, box.ny), min(64, box.nz), lam=box.lam, mu=box.mu, tau=box.tau, rho=box.rho,
+                        force=box.force, x_walls=box.x_walls, name=f"{box.name}-sample{n}")
     o = Oracle3D(sample)
     o.step(1)
     t0 = time.perf_counter()
@@ -189,62 +216,78 @@ def cpu_baseline3(box, budget_s=15.0):
         k += 1
     dt = time.perf_counter() - t0
     # numpy's elementwise loops and einsum (no BLAS path) run on one thread
-    return {"value": round(sample.n_sites * k / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": round(sample.n_material * k / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{k} steps of a {sample.nx}x{sample.ny}x{sample.nz} box of the same configuration "
-                      f"({sample.n_sites} sites), numpy fp64 on one thread, {dt:.1f} s", **host_cpu()}
+                      f"({sample.n_material} material sites), numpy fp64 on one thread, {dt:.1f} s", **host_cpu()}
 
 
-def run_3d(args, torch, dev, stream, n):
-    """The three-dimensional (D3Q19) step on an n^3 slab: face x = -1/2
-    clamped, face x = n - 1/2 pulled by a step traction, periodic in y and z;
-    fp32 populations, fp64 displacement, from rest.  One bench step is one
-    time step of the whole box (two launches: density pass, step)."""
+def run_3d(args, torch, dev, stream, n, kind="cube"):
+    """The three-dimensional (D3Q19) step on an n^3 box: kind "cube", a slab
+    with face x = -1/2 clamped and face x = n - 1/2 pulled by a step
+    traction, periodic in y and z; kind "cavities", a porous solid periodic on
+    every axis with (n/64)^3 pressurised spherical cavities (cut links of
+    every q and normal).  fp32 populations, fp64 displacement, from rest.  One
+    bench step is one time step of the whole box (two launches: density pass,
+    step); the rate counts material sites."""
     import numpy as np
     from paper_2208_04088_amd import slbm3
     from slbm_workloads import box3d as B
     steps = args.steps if args.steps_given else 1000
-    box = B.cube_pulled(n, steps=steps)
+    if kind == "cavities":
+        box = B.cavities_box3(n, per_axis=max(1, n // 64), steps=steps)
+        sample = B.cavities_box3(64, per_axis=1, radius=0.3 * n / max(1, n // 64), seed=1)
+    else:
+        box = B.cube_pulled(n, steps=steps)
+        sample = None
     prec = args.precision or "fp32"
     s = slbm3.Solver3(box, prec, device=0, stream=stream.cuda_stream)
     warm = min(args.warmup, 100)
     s.step(warm)
-    s.sync()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     w0 = time.perf_counter()
     ev0.record(stream)
     s.step(steps)
     ev1.record(stream)
-    s.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     t_step = ev0.elapsed_time(ev1) / 1e3 / steps
-    assert np.isfinite(s.displacement()).all()
-    sites = box.n_sites
+    try:
+        s.sync()                          # the divergence flag (the timing does not depend on it)
+        diverged = False
+    except slbm3.S.SlbmError:
+        diverged = True
+    assert diverged or np.isfinite(s.displacement()).all()
+    sites = box.n_material
     bps = bytes_per_site3(prec)
-    achieved = sites * bps / t_step / 1e9
+    step_bytes = bytes_per_step3(box, prec)
+    achieved = step_bytes / t_step / 1e9
     from paper_2208_04088_amd import slbm
     result = {
         "metric": "MLUPS (site updates per second) of the D3Q19 solid-LBM step",
         "value": round(sites / t_step / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": round(t_step * 1e3, 6), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "sites": sites,
+        "config": {"workload": box.name, "nx": box.nx, "ny": box.ny, "nz": box.nz, "sites": box.n_sites,
+                   "material_sites": sites,
                    "precision": "fp32 populations and arithmetic, fp64 displacement" if prec == "fp32" else "fp64",
                    "lambda_over_mu": box.lam / box.mu, "tau": box.tau,
-                   "bench_step": "one D3Q19 time step of the whole box (density pass and step kernel)",
-                   "wall_s": round(wall, 4)},
+                   "bench_step": "one D3Q19 time step of the whole box (cut-link rules with a mask, density pass, "
+                                 "step kernel)",
+                   "diverged": diverged, "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic3(box, prec),
-                     "kernel": "k3_density + k3_step", "bytes_per_site": bps, "launches_per_step": 2,
+                     "kernel": ("k3_links + " if box.mask is not None else "") + "k3_density + k3_step",
+                     "bytes_per_site": bps, "bytes_per_step": step_bytes,
+                     "launches_per_step": 3 if box.mask is not None else 2,
                      "avg_step_us": round(t_step * 1e6, 3),
-                     "note": "achieved counts the step's algorithmic bytes over the time of both launches; "
+                     "note": "achieved counts the step's algorithmic bytes over the time of all its launches; "
                              "the density pass re-reads the pulled populations (traffic: measured bytes per step)"},
     }
     result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
     s.close()
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline3(box)
+        result["cpu_baseline"] = cpu_baseline3(box, sample=sample)
     print(json.dumps(result), flush=True)
 
 
@@ -617,8 +660,7 @@ def main():
         args.steps = 20 if args.workload == "hole2048" else 10000
     if args.warmup is None:
         args.warmup = 5 if args.workload == "hole2048" else 500
-    special = args.workload in ("batch64", "serve") or (
-        args.workload.startswith("cube") and args.workload[4:].isdigit() and int(args.workload[4:]) > 0)
+    special = args.workload in ("batch64", "serve") or box3_workload(args.workload) is not None
     if not special:
         workload(args.workload)          # exits with the list of workloads for an unknown name
     if args.precision not in (None, "fp32", "fp64"):
@@ -639,8 +681,8 @@ def main():
     if args.workload == "serve":
         run_serve(args, slbm, torch, dev, stream)
         return
-    if args.workload.startswith("cube"):
-        run_3d(args, torch, dev, stream, int(args.workload[4:]))
+    if box3_workload(args.workload) is not None:
+        run_3d(args, torch, dev, stream, *reversed(box3_workload(args.workload)))
         return
 
     plate, prec = workload(args.workload)

@@ -33,6 +33,7 @@ struct slbm3_s {
     uint32_t* flags = nullptr;
     int32_t* bidx = nullptr;
     void* links = nullptr;
+    void* lval = nullptr;            // rule value per link record (k3_links)
     int64_t n_links = 0;
     size_t link_bytes = 0;
 };
@@ -76,6 +77,7 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     a.flags = h->flags;
     a.bidx = h->bidx;
     a.links = (const Link3<real>*)h->links;
+    a.lval = (real*)h->lval;
     return a;
 }
 
@@ -96,6 +98,8 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
     if (p->n_links < 0 || (p->n_links > 0 && !p->links)) return fail(SLBM_E_INVAL, "links: null array");
     if (p->n_groups < 0 || (p->n_groups > 0 && !p->groups)) return fail(SLBM_E_INVAL, "groups: null array");
     if (p->n_links > 18LL * n) return fail(SLBM_E_INVAL, "more links than a box has");
+    if (p->n_links > (int64_t)INT_MAX - 255)
+        return fail(SLBM_E_UNSUPPORTED, "more than 2^31 - 256 cut links (records are indexed with 32 bits)");
     for (int k = 0; k < p->n_groups; ++k) {
         const slbm3_bc_group& gr = p->groups[k];
         if (gr.kind != SLBM_DIRICHLET && gr.kind != SLBM_NEUMANN)
@@ -151,23 +155,56 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         // section 4.2: no site behind x when the opposite link is cut too
         const bool thin = (g.flags[L.site] >> (ib - 1)) & 1u;
         const double q = L.q;
+        const double kap = thin ? 0.0 : (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
+        const double bet = thin ? 1.0 : 2.0 / (1.0 + 2.0 * q);
+        const double w = w3(i);
+        const double c[3] = {(double)kCX[i], (double)kCY[i], (double)kCZ[i]};
+        const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
         Link3<double>& R = g.recs[r];
-        R.kap = thin ? 0.0 : (1.0 - 2.0 * q) / (1.0 + 2.0 * q);
-        R.bet = thin ? 1.0 : 2.0 / (1.0 + 2.0 * q);
+        R.kap = kap;
+        R.bet2 = 2.0 * bet;
         R.q1 = 1.0 + q;
         R.q = q;
-        R.w = w3(i);
-        for (int c = 0; c < 3; ++c) {
-            R.n[c] = L.normal[c];
-            R.a[c] = gr.kind == SLBM_DIRICHLET ? gr.value[c] / h->s_v
-                                               : (gr.value[c] - gr.pressure * R.n[c]) / h->s_sigma;
+        for (int k = 0; k < 6; ++k) R.B[k] = 0.0;
+        R.K = 0.0;
+        if (gr.kind == SLBM_DIRICHLET) {
+            const double cv = (c[0] * gr.value[0] + c[1] * gr.value[1] + c[2] * gr.value[2]) / h->s_v;
+            R.c0 = bet * 6.0 * w * cv;
+        } else {
+            // the constants of e = c0 drho_bd + B:P_b - K (the record's comment)
+            const double* n = L.normal;
+            double t[3], A[3][3], Pi[3][3], T[3][3], B0[3][3];
+            for (int k = 0; k < 3; ++k) t[k] = (gr.value[k] - gr.pressure * n[k]) / h->s_sigma;
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) {
+                    A[u][v] = c[u] * c[v] - (u == v ? 1.0 / 3.0 : 0.0);
+                    Pi[u][v] = (u == v ? 1.0 : 0.0) - n[u] * n[v];
+                }
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) T[u][v] = A[u][0] * Pi[0][v] + A[u][1] * Pi[1][v] + A[u][2] * Pi[2][v];
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) B0[u][v] = Pi[u][0] * T[0][v] + Pi[u][1] * T[1][v] + Pi[u][2] * T[2][v];
+            double nAt = 0.0, nAn = 0.0;
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) {
+                    nAt += n[u] * A[u][v] * t[v];
+                    nAn += n[u] * A[u][v] * n[v];
+                }
+            const double tn = t[0] * n[0] + t[1] * n[1] + t[2] * n[2];
+            const double trB = B0[0][0] + B0[1][1] + B0[2][2];
+            const double lm = h->lamL - h->muL;
+            R.c0 = w * (2.5 - 1.5 * c2) + 4.5 * w * lm * (trB - c2 + 1.0);
+            R.B[0] = 4.5 * w * B0[0][0];
+            R.B[1] = 4.5 * w * B0[1][1];
+            R.B[2] = 4.5 * w * B0[2][2];
+            R.B[3] = 9.0 * w * B0[0][1];
+            R.B[4] = 9.0 * w * B0[0][2];
+            R.B[5] = 9.0 * w * B0[1][2];
+            R.K = 4.5 * w * (2.0 * nAt - tn * nAn);
         }
-        R.k = i;
-        R.kb = ib;
-        R.kind = gr.kind;
-        R.ext = gr.kind == SLBM_NEUMANN && h->norder == 1 && !thin ? 1 : 0;
-        R.cx = kCX[i]; R.cy = kCY[i]; R.cz = kCZ[i];
-        R.pad = 0;
+        const int ext = gr.kind == SLBM_NEUMANN && h->norder == 1 && !thin ? 1 : 0;
+        R.meta = link3_meta(i, ib, gr.kind, ext, kCX[i], kCY[i], kCZ[i]);
+        R.site = L.site;
     }
     return SLBM_OK;
 }
@@ -180,10 +217,11 @@ std::vector<Link3<real>> cast_links3(const std::vector<Link3<double>>& in)
     for (size_t r = 0; r < in.size(); ++r) {
         const Link3<double>& A = in[r];
         Link3<real>& B = out[r];
-        B.kap = (real)A.kap; B.bet = (real)A.bet; B.q1 = (real)A.q1; B.q = (real)A.q; B.w = (real)A.w;
-        for (int c = 0; c < 3; ++c) { B.a[c] = (real)A.a[c]; B.n[c] = (real)A.n[c]; }
-        B.k = A.k; B.kb = A.kb; B.kind = A.kind; B.ext = A.ext;
-        B.cx = A.cx; B.cy = A.cy; B.cz = A.cz; B.pad = 0;
+        B.kap = (real)A.kap; B.bet2 = (real)A.bet2; B.q1 = (real)A.q1; B.q = (real)A.q; B.c0 = (real)A.c0;
+        for (int k = 0; k < 6; ++k) B.B[k] = (real)A.B[k];
+        B.K = (real)A.K;
+        B.meta = A.meta;
+        B.site = A.site;
     }
     return out;
 }
@@ -206,8 +244,8 @@ int grid3(const slbm3_s* h)
     return (int)((wg + unit - 1) / unit * unit);
 }
 
-// Density pass then `what` (0 step, 1 outputs into scratch, 2 init from scratch).
-// GEO (general geometry) implies PX.
+// Rule values at the cut links (general geometry, GEO, which implies PX),
+// density pass, then `what` (0 step, 1 outputs into scratch, 2 init from scratch).
 template <typename real, bool PX, bool GEO>
 int launch3(slbm3_s* h, int what)
 {
@@ -221,6 +259,9 @@ int launch3(slbm3_s* h, int what)
         HIP_TRY(hipGetLastError());
         return SLBM_OK;
     }
+    if (GEO && !h->local && h->n_links > 0)          // the rules' values, read by both pulls
+        hipLaunchKernelGGL((k3_links<real>), dim3((unsigned)((h->n_links + 255) / 256)), blk, 0, h->stream, a,
+                           (int)h->n_links);
     hipLaunchKernelGGL((k3_density<real, PX, GEO>), grid, blk, 0, h->stream, a);
     if (what == 0)
         hipLaunchKernelGGL((k3_step<real, PX, GEO>), grid, blk, 0, h->stream, a);
@@ -250,7 +291,7 @@ int ensure_scratch3(slbm3_s* h)
 void free3(slbm3_s* h)
 {
     for (void* p : {h->buf[0], h->buf[1], (void*)h->U, h->dens, (void*)h->diverged, (void*)h->scratch,
-                    (void*)h->flags, (void*)h->bidx, h->links})
+                    (void*)h->flags, (void*)h->bidx, h->links, h->lval})
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -385,6 +426,7 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
                     TRY_OR_BAIL(hipMemcpyAsync(h->links, geo.recs.data(), h->link_bytes, hipMemcpyHostToDevice,
                                                h->stream));
                 }
+                TRY_OR_BAIL(hipMalloc(&h->lval, geo.recs.size() * h->esize));
             }
         }
         TRY_OR_BAIL(hipStreamSynchronize(h->stream));
@@ -561,7 +603,7 @@ int slbm3_device_bytes(slbm3_handle h, int64_t* bytes)
         if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
         int64_t b = 2 * (int64_t)19 * h->stride * (int64_t)h->esize + 3 * h->stride * 8 + h->plane * (int64_t)h->esize;
         if (h->scratch) b += (int64_t)19 * h->plane * 8;
-        if (h->geo) b += h->plane * 8 + (int64_t)h->link_bytes;
+        if (h->geo) b += h->plane * 8 + (int64_t)h->link_bytes + h->n_links * (int64_t)h->esize;
         *bytes = b;
         return SLBM_OK;
     });

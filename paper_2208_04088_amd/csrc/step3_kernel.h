@@ -46,19 +46,36 @@ enum { kWallNone = 0, kWallDirichlet = 1, kWallNeumann = 2 };
 constexpr uint32_t kVoid3 = 0x80000000u;
 constexpr uint32_t kCutMask3 = 0x3FFFFu;
 
-// One cut link (x, i) of a general geometry, in lattice units: the rule's
-// kappa and beta (0 and 1 when the opposite link is cut too, no site behind),
-// the extrapolation weights 1 + q and q, w_i, the wall velocity (Dirichlet)
-// or traction t* = value - pressure n (Neumann), the outward normal n, and
-// the link's direction.
+// One cut link (x, i) of a general geometry, in lattice units, with the
+// rule's constants folded on the host.  Dirichlet (eq:bbcon / eq:bbnoncon):
+//   g_ib = g_i + kappa (g_i(x - c_i) - g_ib) - rho(x) c0,  c0 = beta 6 w_i c_i.v*.
+// Neumann (eq:abbcon / eq:abbnoncon): g_ib = -g_i - kappa (g_i(x - c_i) + g_ib)
+// + 2 beta e, with e = g_eq,i(rho_bd, 0, P*) the shifted equilibrium at the
+// boundary stress sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n.  With
+// A = c_i c_i - I/3 and sigma_b = -P_b - (lambda - mu) drho_bd I this is
+// linear in the site's (or the extrapolated) drho_bd and P_b:
+//   e = c0 drho_bd + sum_k B_k P_b,k - K,
+//   c0 = w_i [5/2 - 3/2 |c_i|^2 + 9/2 (lambda - mu)(tr(Pi A Pi) - |c_i|^2 + 1)],
+//   B  = 9/2 w_i Pi A Pi (xx yy zz, then xy xz yz doubled),
+//   K  = 9/2 w_i [2 n.A.t* - (t*.n) n.A.n].
+// kappa and beta are 0 and 1 when the opposite link is cut too (no site
+// behind); ext: Neumann with rho_bd and sigma_b extrapolated along the link,
+// (1 + q) X(x) - q X(x - c_i).
 template <typename real>
 struct Link3 {
-    real kap, bet, q1, q, w;
-    real a[3];
-    real n[3];
-    int32_t k, kb, kind, ext;  // ext: Neumann with rho_bd and sigma_b extrapolated
-    int32_t cx, cy, cz, pad;
+    real kap, bet2, q1, q;         // kappa, 2 beta, 1 + q, q
+    real c0;
+    real B[6];
+    real K;
+    uint32_t meta;                 // link3_meta
+    int32_t site;                  // (z ny + y) nx + x of the material site x
 };
+// meta: direction k (5 bits), opposite (5), kind (2), ext (1), c + 1 per axis (2 each)
+__host__ __device__ constexpr uint32_t link3_meta(int k, int kb, int kind, int ext, int cx, int cy, int cz)
+{
+    return (uint32_t)k | (uint32_t)kb << 5 | (uint32_t)kind << 10 | (uint32_t)ext << 12 |
+           (uint32_t)(cx + 1) << 13 | (uint32_t)(cy + 1) << 15 | (uint32_t)(cz + 1) << 17;
+}
 
 template <typename real>
 struct Step3Args {
@@ -81,10 +98,12 @@ struct Step3Args {
     real wkap[2], wbeta[2], wq1[2], wq[2];
     int wext[2];
     // general geometry (periodic on every axis): site flags, each cut site's
-    // first link record, the records (sorted by site and direction)
+    // first link record, the records (sorted by site and direction), and the
+    // rule values of the pulled state, one per record (written by k3_links)
     const uint32_t* flags;
     const int32_t* bidx;
     const Link3<real>* links;
+    real* lval;
     real omega, omega_h;       // 1/tau, 1 - 1/(2 tau)
     real ml, lm;               // mu - lambda, lambda - mu (lattice units)
     real F[3];
@@ -329,106 +348,65 @@ __device__ __forceinline__ unsigned sidx3(int x, int y, int z, int nx, int ny)
 // returning population comes from the wall rule, from the site's own
 // post-collision populations (rho and P are those of the previous step,
 // conserved by the collision).
-// h[k] = x for a k known only at run time, by bit masks (a dynamically
-// indexed register array would go through scratch memory or LDS).
-__device__ __forceinline__ unsigned bits19(float v) { return __float_as_uint(v); }
-__device__ __forceinline__ unsigned long long bits19(double v) { return (unsigned long long)__double_as_longlong(v); }
-__device__ __forceinline__ float unbits19(unsigned v, float) { return __uint_as_float(v); }
-__device__ __forceinline__ double unbits19(unsigned long long v, double) { return __longlong_as_double((long long)v); }
-
+// The rules of section 4 at the cut links of a general geometry, from the
+// post-collision state, one thread per link (the links of a site are
+// neighbouring threads and share the loads of the site's populations): the
+// population that returns to the link's site in the opposite direction,
+// into lval, where the pulls of the next density pass and step read it.  The
+// record's folded constants carry the link's own q, normal and group.
 template <typename real>
-__device__ __forceinline__ void put19(real h[kQ], int k, real x)
+__global__ __launch_bounds__(256) void k3_links(Step3Args<real> a, int n_links)
 {
-    using B = decltype(bits19(real(0)));
-    const B b = bits19(x);
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= n_links) return;
+    const Link3<real> L = a.links[l];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned s = (unsigned)L.site;
+    const int x = (int)(s % (unsigned)nx), y = (int)((s / (unsigned)nx) % (unsigned)ny),
+              z = (int)(s / ((unsigned)nx * (unsigned)ny));
+    const uint32_t meta = L.meta;
+    const int i = (int)(meta & 31u), ib = (int)((meta >> 5) & 31u);
+    const int cx = (int)((meta >> 13) & 3u) - 1, cy = (int)((meta >> 15) & 3u) - 1, cz = (int)((meta >> 17) & 3u) - 1;
+    // the site behind x along the link, x - c_i (periodic axes)
+    const unsigned sb = sidx3(wrap(x - cx, nx), wrap(y - cy, ny), wrap(z - cz, nz), nx, ny);
+    const real hi = a.src[i * a.stride + s], hib = a.src[ib * a.stride + s];
+    const real hy = L.kap != real(0) ? a.src[i * a.stride + sb] : real(0);
+    real h[kQ];
 #pragma unroll
-    for (int j = 0; j < kQ; ++j) {
-        const B m = (B)(0 - (B)(k == j));
-        h[j] = unbits19((bits19(h[j]) & ~m) | (b & m), real(0));
+    for (int k = 0; k < kQ; ++k) h[k] = a.src[k * a.stride + s];
+    real dr, j[3], P[6];
+    moments3(h, dr, j, P);
+    real val;
+    if (((meta >> 10) & 3u) == kWallDirichlet) {
+        val = hi + L.kap * (hy - hib) - (real(1) + dr) * L.c0;
+    } else {
+        real drb = dr;
+        if ((meta >> 12) & 1u) {                 // ext: rho_bd and P_b extrapolated along the link
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) h[k] = a.src[k * a.stride + sb];
+            real dry, Py[6];
+            moments3(h, dry, j, Py);
+            drb = L.q1 * dr - L.q * dry;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) P[c] = L.q1 * P[c] - L.q * Py[c];
+        }
+        const real e = L.c0 * drb + (L.B[0] * P[0] + L.B[1] * P[1] + L.B[2] * P[2]) +
+                       (L.B[3] * P[3] + L.B[4] * P[4] + L.B[5] * P[5]) - L.K;
+        val = -hi - L.kap * (hy + hib) + L.bet2 * e;
     }
+    a.lval[l] = val;
 }
 
-// The rules of section 4 at the cut links of a general geometry's site: each
-// link's own q, normal and group (eq:bbcon / eq:bbnoncon, eq:abbcon /
-// eq:abbnoncon with sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n).
+// A cut site's pulls along its cut links: the rule values of k3_links (the
+// site's records are consecutive, in direction order, from bidx).
 template <typename real>
-__device__ __forceinline__ void cut_links3(const Step3Args<real>& a, const Site3& st, unsigned s, uint32_t fl, real g[kQ])
+__device__ __forceinline__ void cut_links3(const Step3Args<real>& a, unsigned s, uint32_t fl, real g[kQ])
 {
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    real dr, j[3], P[6];
-    {
-        real h[kQ];
+    const int li = a.bidx[s];
+    const uint32_t m = fl & kCutMask3;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) h[i] = a.src[i * a.stride + s];
-        moments3(h, dr, j, P);
-    }
-    const real rho = real(1) + dr;
-    int li = a.bidx[s];
-    uint32_t m = fl & kCutMask3;
-    while (m) {
-        m &= m - 1;
-        const Link3<real> L = a.links[li++];
-        const int i = L.k, ib = L.kb;
-        // the site behind x along the link, x - c_i (periodic axes)
-        const unsigned sb = sidx3(wrap(st.x - L.cx, nx), wrap(st.y - L.cy, ny), wrap(st.z - L.cz, nz), nx, ny);
-        const real hi = a.src[i * a.stride + s], hib = a.src[ib * a.stride + s];
-        const real hy = L.kap != real(0) ? a.src[i * a.stride + sb] : real(0);
-        real val;
-        if (L.kind == kWallDirichlet) {
-            const real cv = real(L.cx) * L.a[0] + real(L.cy) * L.a[1] + real(L.cz) * L.a[2];
-            val = hi + L.kap * (hy - hib) - L.bet * (real(6) * L.w * rho * cv);
-        } else {
-            // sigma_b = -P_b - (lambda - mu) drho_b I at the site, or
-            // extrapolated along the link; rho_bd likewise
-            real drb = dr, Pb[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) Pb[c] = P[c];
-            if (L.ext) {
-                real hb[kQ];
-#pragma unroll
-                for (int k = 0; k < kQ; ++k) hb[k] = a.src[k * a.stride + sb];
-                real dry, jy[3], Py[6];
-                moments3(hb, dry, jy, Py);
-                drb = L.q1 * dr - L.q * dry;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) Pb[c] = L.q1 * P[c] - L.q * Py[c];
-            }
-            // full 3 x 3 of sigma_b (xx yy zz xy xz yz)
-            real sb3[3][3];
-            sb3[0][0] = -Pb[0] - a.lm * drb; sb3[1][1] = -Pb[1] - a.lm * drb; sb3[2][2] = -Pb[2] - a.lm * drb;
-            sb3[0][1] = sb3[1][0] = -Pb[3];
-            sb3[0][2] = sb3[2][0] = -Pb[4];
-            sb3[1][2] = sb3[2][1] = -Pb[5];
-            const real n[3] = {L.n[0], L.n[1], L.n[2]};
-            real Pi[3][3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) Pi[r][c] = (r == c ? real(1) : real(0)) - n[r] * n[c];
-            real tmp[3][3], st3[3][3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) tmp[r][c] = Pi[r][0] * sb3[0][c] + Pi[r][1] * sb3[1][c] + Pi[r][2] * sb3[2][c];
-            const real tn = L.a[0] * n[0] + L.a[1] * n[1] + L.a[2] * n[2];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    st3[r][c] = (tmp[r][0] * Pi[0][c] + tmp[r][1] * Pi[1][c] + tmp[r][2] * Pi[2][c])
-                                + n[r] * L.a[c] + L.a[r] * n[c] - tn * n[r] * n[c];
-            // P* = -sigma* - (lambda - mu) drho_bd I; g_eq,i(drho_bd, 0, P*)
-            const real cx = real(L.cx), cy = real(L.cy), cz = real(L.cz);
-            const real c2 = cx * cx + cy * cy + cz * cz;
-            const real third = real(1.0 / 3.0);
-            const real pxx = -st3[0][0] - a.lm * drb, pyy = -st3[1][1] - a.lm * drb, pzz = -st3[2][2] - a.lm * drb;
-            const real quad = pxx * (cx * cx - third) + pyy * (cy * cy - third) + pzz * (cz * cz - third)
-                              + real(2) * (-st3[0][1] * cx * cy - st3[0][2] * cx * cz - st3[1][2] * cy * cz);
-            const real e = L.w * (drb * (real(2.5) - real(1.5) * c2) + real(4.5) * quad);
-            val = -hi - L.kap * (hy + hib) + L.bet * (real(2) * e);
-        }
-        put19(g, ib, val);
-    }
+    for (int k = 1; k < kQ; ++k)
+        if ((m >> (k - 1)) & 1u) g[opp3(k)] = a.lval[li + __builtin_popcount(m & ((1u << (k - 1)) - 1u))];
 }
 
 template <typename real, bool PX, bool GEO = false>
@@ -437,14 +415,13 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned s = sidx3(st.x, st.y, st.z, nx, ny);
     fl = GEO ? a.flags[s] : 0u;
-    if (GEO && (fl & kVoid3)) {                 // void: nothing to pull
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) g[i] = real(0);
-        return;
-    }
     if (a.local) {
 #pragma unroll
         for (int i = 0; i < kQ; ++i) g[i] = a.src[i * a.stride + s];
+        if (GEO && (fl & kVoid3)) {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) g[i] = real(0);
+        }
         return;
     }
     const int ym = wrap(st.y - 1, ny), yp = wrap(st.y + 1, ny);
@@ -465,7 +442,14 @@ __device__ __forceinline__ void pull3(const Step3Args<real>& a, const Site3& st,
         g[i] = a.src[i * a.stride + sidx3(xx, yy, zz, nx, ny)];
     }
     if constexpr (GEO) {
-        if ((fl & kCutMask3) != 0u) cut_links3<real>(a, st, s, fl, g);
+        // the pulls above are issued for every lane (in-grid addresses), so
+        // that they do not wait for the flags
+        if (fl & kVoid3) {                      // void: nothing to pull
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) g[i] = real(0);
+        } else if ((fl & kCutMask3) != 0u) {
+            cut_links3<real>(a, s, fl, g);
+        }
         return;
     }
     if (!PX && (st.x == 0 || st.x == nx - 1)) {
@@ -640,7 +624,7 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
     real g[kQ];
     uint32_t fl;
     pull3<real, PX, GEO>(a, st, g, fl);
-    const bool live = st.in && !(GEO && (fl & kVoid3));  // void sites keep their (rest) state
+    const bool live = st.in && !(GEO && (fl & kVoid3));  // void sites stay at rest
     real dr, j[3], P[6];
     moments3(g, dr, j, P);
     real grad[3];
@@ -659,11 +643,14 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
     real o[kQ];
     collide_ghost3(g, dr, j, P, S, a.omega, a.omega_h, o);
     const bool bad = !(fabs(dr) + fabs(j[0]) + fabs(j[1]) + fabs(j[2]) < real(kDivergeBound));
-    if (live) {
+    // void sites store the rest state (zeros) rather than nothing: whole
+    // lines reach HBM, where a partly written line costs a read-modify-write
+    if (st.in) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) a.dst[i * a.stride + s] = o[i];
+        for (int i = 0; i < kQ; ++i) a.dst[i * a.stride + s] = live ? o[i] : real(0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a.U[k * a.stride + s] = a.U[k * a.stride + s] + (double)(j[k] * ir);
+        for (int k = 0; k < 3; ++k)
+            a.U[k * a.stride + s] = live ? a.U[k * a.stride + s] + (double)(j[k] * ir) : 0.0;
     }
     if (__any(bad && live) && (threadIdx.x & 63) == 0 && *(volatile unsigned int*)a.diverged == 0u)
         atomicOr(a.diverged, 1u);

@@ -100,39 +100,69 @@ def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho
                 force=(0.0, 0.0, 0.0), neumann_order=0, name="", steps=0) -> Box3:
     """A box periodic on every axis with spherical cavities (each inside the
     box, away from its faces).  A link from a material site x whose far end
-    x + c_i lies in a cavity is cut where it first enters it: q = that
-    fraction of the link, normal = the material's outward normal there
-    (towards the centre)."""
-    zz, yy, xx = np.mgrid[0:nz, 0:ny, 0:nx]
+    x + c_i lies in a cavity (the first listed that holds it) is cut where it
+    first enters that cavity: q = that fraction of the link, normal = the
+    material's outward normal there (towards the centre)."""
+    zz, yy, xx = np.ogrid[0:nz, 0:ny, 0:nx]
     mask = np.ones((nz, ny, nx), dtype=np.uint8)
-    for sp in spheres:
+    label = np.full((nz, ny, nx), -1, dtype=np.int32)
+    for k in range(len(spheres) - 1, -1, -1):          # the first listed wins
+        sp = spheres[k]
         if not (sp.R < sp.cx < nx - 1 - sp.R and sp.R < sp.cy < ny - 1 - sp.R and sp.R < sp.cz < nz - 1 - sp.R):
             raise ValueError("a cavity must lie inside the box")
         inside = (xx - sp.cx) ** 2 + (yy - sp.cy) ** 2 + (zz - sp.cz) ** 2 < sp.R ** 2
         mask[inside] = 0
-    recs = []
-    mat = np.argwhere(mask == 1)
+        label[inside] = k
+    cen = np.array([[sp.cx, sp.cy, sp.cz] for sp in spheres], dtype=float).reshape(-1, 3)
+    rad = np.array([sp.R for sp in spheres], dtype=float)
+    grp = np.array([sp.group for sp in spheres], dtype=np.int64)
+    parts = []
     for i in range(1, len(C3)):
         c = C3[i]
-        fz, fy, fx = (mat[:, 0] + c[2]) % nz, (mat[:, 1] + c[1]) % ny, (mat[:, 2] + c[0]) % nx
-        cut = mask[fz, fy, fx] == 0
-        for z, y, x in mat[cut]:
-            far = np.array([x + c[0], y + c[1], z + c[2]], dtype=float)
-            for sp in spheres:
-                d = far - (sp.cx, sp.cy, sp.cz)
-                if d @ d < sp.R ** 2:
-                    break
-            p0 = np.array([x, y, z], dtype=float) - (sp.cx, sp.cy, sp.cz)
-            a, b, cc = float(c @ c), float(p0 @ c), float(p0 @ p0) - sp.R ** 2
-            t = (-b - np.sqrt(max(b * b - a * cc, 0.0))) / a
-            t = min(max(t, 1e-9), 1.0)
-            w = np.array([x, y, z], dtype=float) + t * c
-            n = (np.array([sp.cx, sp.cy, sp.cz]) - w) / sp.R
-            recs.append(((z * ny + y) * nx + x, i, t, sp.group, tuple(n / np.linalg.norm(n))))
-    links = np.array(sorted(recs, key=lambda r: (r[0], r[1])), dtype=LINK3_DTYPE)
+        far = np.roll(label, (-c[2], -c[1], -c[0]), axis=(0, 1, 2))
+        z, y, x = np.nonzero((mask == 1) & (far >= 0))
+        if len(z) == 0:
+            continue
+        k = far[z, y, x]
+        p = np.stack([x, y, z], axis=1).astype(float)
+        p0 = p - cen[k]
+        a = float(c @ c)
+        b = p0 @ c.astype(float)
+        cc = (p0 * p0).sum(1) - rad[k] ** 2
+        t = (-b - np.sqrt(np.maximum(b * b - a * cc, 0.0))) / a
+        t = np.clip(t, 1e-9, 1.0)
+        n = (cen[k] - (p + t[:, None] * c)) / rad[k][:, None]
+        n = n / np.linalg.norm(n, axis=1)[:, None]
+        rec = np.zeros(len(z), dtype=LINK3_DTYPE)
+        rec["site"] = (z * ny + y) * nx + x
+        rec["dir"] = i
+        rec["q"] = t
+        rec["group"] = grp[k]
+        rec["normal"] = n
+        parts.append(rec)
+    links = np.concatenate(parts) if parts else np.zeros(0, dtype=LINK3_DTYPE)
+    links = links[np.lexsort((links["dir"], links["site"]))]
     return Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, rho=rho, force=tuple(force), name=name or
                 f"spheres{nx}x{ny}x{nz}", steps=steps, neumann_order=neumann_order, mask=mask, links=links,
                 groups=list(groups))
+
+
+def cavities_box3(n=256, *, per_axis=4, radius=None, pressure=1e-3, mu=0.05, lam=0.05, tau=0.7, seed=0,
+                  steps=1000) -> Box3:
+    """n^3 porous solid, periodic on every axis: per_axis^3 spherical cavities
+    on a jittered cubic grid (seeded), radius 0.3 of the spacing by default,
+    every cavity wall loaded by the pressure pressure*mu (Neumann, order 0)."""
+    rng = np.random.default_rng(seed)
+    h = n / per_axis
+    R = 0.3 * h if radius is None else radius
+    sph = []
+    for iz in range(per_axis):
+        for iy in range(per_axis):
+            for ix in range(per_axis):
+                j = rng.uniform(-0.1 * h, 0.1 * h, 3)
+                sph.append(Sphere3((ix + 0.5) * h + j[0], (iy + 0.5) * h + j[1], (iz + 0.5) * h + j[2], R, 0))
+    return sphere_box3(n, n, n, sph, [BCGroup3(NEUMANN, (0.0, 0.0, 0.0), pressure * mu)], lam=lam, mu=mu, tau=tau,
+                       neumann_order=0, name=f"cavities{n}", steps=steps)
 
 
 def periodic_box3(nx, ny, nz, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0, force=(0.0, 0.0, 0.0),
