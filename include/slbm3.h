@@ -35,10 +35,12 @@
  *   15-18 (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).
  *
  *   General geometry: a box periodic on every axis with a material mask;
- *   void sites (cavities, cracks) hold no material.  Each link from a
+ *   void sites (cavities, notches) hold no material.  Each link from a
  *   material site into the void is cut where it leaves the material, at its
- *   own fraction q, with its own outward normal and boundary group, and takes
- *   the rule of its group as above (Dirichlet: eq:bbcon / eq:bbnoncon;
+ *   own fraction q, with its own outward normal and boundary group; a link
+ *   between two material sites may be cut too (a crack of zero thickness),
+ *   listed from both sides, each face with its own q, normal and group.  A
+ *   cut link takes the rule of its group as above (Dirichlet: eq:bbcon / eq:bbnoncon;
  *   Neumann: eq:abbcon / eq:abbnoncon with the traction t* = value -
  *   pressure n).  Where the opposite link at the same site is cut too there
  *   is no site behind: kappa = 0, beta = 1 and no extrapolation.  The density
@@ -78,8 +80,8 @@ typedef struct {
 } slbm3_wall;
 
 /* One cut link of a general geometry (48 bytes): the link from the material
- * site x to x + c_dir, whose far end is void, crossing the boundary at the
- * fraction q of its length. */
+ * site x to x + c_dir, whose far end is void (or material across a crack),
+ * crossing the boundary at the fraction q of its length. */
 typedef struct {
     int32_t site;                /* (iz*ny + iy)*nx + ix of x, a material site */
     int32_t dir;                 /* direction i of the link, 1..18 (order above) */
@@ -105,7 +107,7 @@ typedef struct {
     int32_t neumann_order;       /* 0: rho_bd and the tangential stress at the boundary site; 1: extrapolated */
     /* General geometry (needs periodic_x = 1; NULL mask: none): */
     const uint8_t* mask;         /* [nz][ny][nx], nonzero: material, 0: void */
-    int64_t n_links;             /* every link from a material site into the void, once */
+    int64_t n_links;             /* every link from a material site into the void, and both sides of each crack, once */
     const slbm3_link* links;     /* any order */
     int32_t n_groups;
     const slbm3_bc_group* groups;
@@ -118,10 +120,11 @@ typedef struct {
  * for invalid parameters, SLBM_E_UNSUPPORTED above 2^29 sites, SLBM_E_NOMEM
  * or SLBM_E_DEVICE if allocation fails; *out is NULL on failure.  With a mask
  * SLBM_E_INVAL also names the first invalid link: a site out of range or
- * void, a direction out of 1..18, a far end that is material, q outside
- * (0, 1], a group out of range, a normal that is not a unit vector (to
- * 1e-9), a link listed twice, or a link from the material into the void
- * that is not listed; and an invalid group kind.  The arrays are copied. */
+ * void, a direction out of 1..18, q outside (0, 1], a group out of range, a
+ * normal that is not a unit vector (to 1e-9), a link listed twice, a link
+ * into the material whose link back is not listed, or a link from the
+ * material into the void that is not listed; and an invalid group kind.
+ * The arrays are copied. */
 int slbm3_create(const slbm3_params* params, slbm3_handle* out);
 
 /* Sets the state from fields (any pointer may be NULL: density rho, velocity

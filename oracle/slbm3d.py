@@ -157,7 +157,9 @@ class Oracle3D:
 
     def _general(self, b):
         """A box with cut links (periodic on every axis): the material mask,
-        the links, their groups in lattice units."""
+        the links, their groups in lattice units.  A cut link ends in the void
+        (a cavity's wall), or in the material across a crack: then the link
+        back from the far site must be listed too (the crack's other face)."""
         if b.x_walls is not None:
             raise ValueError("a box with a material mask is periodic on every axis")
         mask = np.asarray(b.mask).astype(bool)
@@ -172,15 +174,19 @@ class Oracle3D:
         if not mask[z, y, x].all():
             raise ValueError("a cut link starts at a void site")
         fz, fy, fx = (z + C[k, 2]) % b.nz, (y + C[k, 1]) % b.ny, (x + C[k, 0]) % b.nx
-        if mask[fz, fy, fx].any():
-            raise ValueError("a cut link ends at a material site")
         q = L["q"]
         if not ((q > 0) & (q <= 1)).all():
             raise ValueError("q must be in (0, 1]")
         n = np.asarray(L["normal"], dtype=float)
         if np.abs(np.linalg.norm(n, axis=1) - 1).max() > 1e-9:
             raise ValueError("normals must be unit vectors")
+        if len(set(zip(site.tolist(), k.tolist()))) != len(site):
+            raise ValueError("a cut link is listed twice")
         self.cut[k, z, y, x] = True
+        # a link into the material crosses a crack: both faces list their link
+        crack = mask[fz, fy, fx]
+        if not self.cut[OPP[k[crack]], fz[crack], fy[crack], fx[crack]].all():
+            raise ValueError("a cut link into the material needs the link back (the crack's other face)")
         # every link from the material into the void must be listed
         for i in range(1, Q):
             far_void = ~np.roll(mask, (-C[i, 2], -C[i, 1], -C[i, 0]), axis=(0, 1, 2))

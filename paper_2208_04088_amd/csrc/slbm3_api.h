@@ -121,7 +121,6 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         if (L.site < 0 || (long long)L.site >= n) return fail(SLBM_E_INVAL, "link %lld: site out of range", (long long)l);
         if (L.dir < 1 || L.dir > 18) return fail(SLBM_E_INVAL, "link %lld: direction must be in 1..18", (long long)l);
         if (!p->mask[L.site]) return fail(SLBM_E_INVAL, "link %lld: starts at a void site", (long long)l);
-        if (p->mask[far_site(L.site, L.dir)]) return fail(SLBM_E_INVAL, "link %lld: ends at a material site", (long long)l);
         if (!(L.q > 0.0 && L.q <= 1.0)) return fail(SLBM_E_INVAL, "link %lld: q must be in (0, 1]", (long long)l);
         if (L.group < 0 || L.group >= p->n_groups) return fail(SLBM_E_INVAL, "link %lld: group out of range", (long long)l);
         const double nn = std::sqrt(L.normal[0] * L.normal[0] + L.normal[1] * L.normal[1] + L.normal[2] * L.normal[2]);
@@ -129,6 +128,14 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         const uint32_t bit = 1u << (L.dir - 1);
         if (g.flags[L.site] & bit) return fail(SLBM_E_INVAL, "link %lld: listed twice", (long long)l);
         g.flags[L.site] |= bit;
+    }
+    // a link into the material crosses a crack: the link back is listed too
+    for (int64_t l = 0; l < p->n_links; ++l) {
+        const slbm3_link& L = p->links[l];
+        const long long f = far_site(L.site, L.dir);
+        if (p->mask[f] && !(g.flags[f] & (1u << (opp3(L.dir) - 1))))
+            return fail(SLBM_E_INVAL, "link %lld: ends in the material but the link back (the crack's other face) "
+                                      "is not listed", (long long)l);
     }
     // every link from the material into the void is listed
     for (long long s = 0; s < n; ++s) {

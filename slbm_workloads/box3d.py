@@ -3,7 +3,10 @@ periodic in x or closed by two walls, planes normal to x that cross the links
 leaving the material at a fraction q of their length (q = 1/2: the
 lattice-conforming planes x = -1/2 and x = nx - 1/2; in general x = -q and
 x = nx - 1 + q).  Each wall carries a Dirichlet wall velocity or a Neumann
-traction (user units), applied from the first step.
+traction (user units), applied from the first step.  Or a box periodic on
+every axis with a general geometry: a material mask and cut links, each with
+its own q, normal and boundary group (spherical cavities, penny-shaped
+cracks).
 
 Description only: no arithmetic of the method.  Seeded initial fields for
 tests and benchmarks come from :func:`random_velocity`.
@@ -85,6 +88,21 @@ class Sphere3:
     group: int
 
 
+@dataclass
+class PennyCrack3:
+    """Crack of zero thickness: the disk of radius R around (cx, cy) in the
+    plane z = zc (zc not an integer, so that no site lies on it).  Every
+    link between two material sites that crosses the disk is cut from both
+    sides, each face with its own group: `lower` for the material below
+    (outward normal +z), `upper` for the material above (-z)."""
+    cx: float
+    cy: float
+    zc: float
+    R: float
+    lower: int
+    upper: int
+
+
 # D3Q19 directions in the order of the kernels and the reference
 C3 = np.array([[0, 0, 0],
                [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
@@ -97,12 +115,15 @@ LINK3_DTYPE = np.dtype([("site", "<i4"), ("dir", "<i4"), ("q", "<f8"), ("group",
 
 
 def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0,
-                force=(0.0, 0.0, 0.0), neumann_order=0, name="", steps=0) -> Box3:
+                force=(0.0, 0.0, 0.0), neumann_order=0, name="", steps=0, cracks=()) -> Box3:
     """A box periodic on every axis with spherical cavities (each inside the
-    box, away from its faces).  A link from a material site x whose far end
-    x + c_i lies in a cavity (the first listed that holds it) is cut where it
-    first enters that cavity: q = that fraction of the link, normal = the
-    material's outward normal there (towards the centre)."""
+    box, away from its faces) and penny-shaped cracks (PennyCrack3, each
+    inside the box and clear of the cavities).  A link from a material site
+    x whose far end x + c_i lies in a cavity (the first listed that holds it)
+    is cut where it first enters that cavity: q = that fraction of the link,
+    normal = the material's outward normal there (towards the centre).  A
+    link between material sites that crosses a crack is cut where it
+    crosses, with the face's normal and group."""
     zz, yy, xx = np.ogrid[0:nz, 0:ny, 0:nx]
     mask = np.ones((nz, ny, nx), dtype=np.uint8)
     label = np.full((nz, ny, nx), -1, dtype=np.int32)
@@ -140,6 +161,27 @@ def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho
         rec["group"] = grp[k]
         rec["normal"] = n
         parts.append(rec)
+    for ck in cracks:
+        if not (ck.R < ck.cx < nx - 1 - ck.R and ck.R < ck.cy < ny - 1 - ck.R and 0 < ck.zc < nz - 1
+                and ck.zc != int(ck.zc)):
+            raise ValueError("a crack must lie inside the box, off the lattice planes")
+        for i in range(1, len(C3)):
+            c = C3[i]
+            if c[2] == 0:
+                continue
+            z0 = int(np.floor(ck.zc)) if c[2] > 0 else int(np.floor(ck.zc)) + 1    # the sites whose link crosses
+            y, x = np.mgrid[0:ny, 0:nx]
+            t = (ck.zc - z0) / c[2]
+            hit = (x + t * c[0] - ck.cx) ** 2 + (y + t * c[1] - ck.cy) ** 2 < ck.R ** 2
+            both = (mask[z0] == 1) & (mask[z0 + c[2], (y + c[1]) % ny, (x + c[0]) % nx] == 1)
+            yy, xx = np.nonzero(hit & both)
+            rec = np.zeros(len(yy), dtype=LINK3_DTYPE)
+            rec["site"] = (z0 * ny + yy) * nx + xx
+            rec["dir"] = i
+            rec["q"] = t
+            rec["group"] = ck.lower if c[2] > 0 else ck.upper
+            rec["normal"] = (0.0, 0.0, float(c[2]))
+            parts.append(rec)
     links = np.concatenate(parts) if parts else np.zeros(0, dtype=LINK3_DTYPE)
     links = links[np.lexsort((links["dir"], links["site"]))]
     return Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, rho=rho, force=tuple(force), name=name or

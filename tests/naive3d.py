@@ -60,6 +60,13 @@ def naive_step(box, f, U, order):
     def wrap(x, y, z):
         return (x % nx, y % ny, z % nz)
 
+    def open_link(x, y, z, c):
+        """The link from material site (x, y, z) along c reaches material
+        without crossing a wall, a cavity's wall or a crack."""
+        if not material(x + c[0], y + c[1], z + c[2]):
+            return False
+        return mask is None or (x, y, z, c) not in links
+
     rho = np.zeros((nz, ny, nx))
     J = np.zeros((3, nz, ny, nx))
     PP = np.zeros((3, 3, nz, ny, nx))
@@ -82,10 +89,11 @@ def naive_step(box, f, U, order):
         for c in vel:
             if c == (0, 0, 0):
                 continue
-            if material(x + c[0], y + c[1], z + c[2]):
+            cb = tuple(-a for a in c)
+            if open_link(x, y, z, c):
                 xx, yy, zz = wrap(x + c[0], y + c[1], z + c[2])
                 rn = rho[zz, yy, xx]
-            elif material(x - c[0], y - c[1], z - c[2]):
+            elif open_link(x, y, z, cb):
                 xx, yy, zz = wrap(x - c[0], y - c[1], z - c[2])
                 rn = 2 * r - rho[zz, yy, xx]
             else:
@@ -113,13 +121,13 @@ def naive_step(box, f, U, order):
         if not material(x, y, z):
             continue
         for c in vel:
-            if material(x + c[0], y + c[1], z + c[2]):
+            if open_link(x, y, z, c):
                 xx, yy, zz = wrap(x + c[0], y + c[1], z + c[2])
                 fnew[idx[c], zz, yy, xx] = fcol[idx[c], z, y, x]
                 continue
             if mask is not None:
                 fnew[idx[tuple(-a for a in c)], z, y, x] = _cut_link(box, fcol, idx, vel, links[(x, y, z, c)],
-                                                                     x, y, z, c, material, wrap, lamL, muL,
+                                                                     x, y, z, c, open_link, wrap, lamL, muL,
                                                                      s_v, s_sigma)
                 continue
             # the link leaves through a wall: the population returns to x
@@ -171,7 +179,7 @@ def naive_step(box, f, U, order):
     return fnew, Un
 
 
-def _cut_link(box, fcol, idx, vel, L, x, y, z, c, material, wrap, lamL, muL, s_v, s_sigma):
+def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_v, s_sigma):
     """The population returning to material site (x, y, z) along the cut link
     in direction c, with the link's own q, outward normal and group."""
     q = float(L["q"])
@@ -188,7 +196,7 @@ def _cut_link(box, fcol, idx, vel, L, x, y, z, c, material, wrap, lamL, muL, s_v
 
     r, Pm = mom(x, y, z)
     # no site behind x when the opposite link is cut as well
-    has_b = material(x - c[0], y - c[1], z - c[2])
+    has_b = open_link(x, y, z, cb)
     if has_b:
         bx, by, bz = wrap(x - c[0], y - c[1], z - c[2])
         fb = fcol[idx[c], bz, by, bx]

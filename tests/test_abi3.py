@@ -144,7 +144,8 @@ def test_invalid_cut_links_are_rejected_on_the_host(case):
     elif case == "void_start":
         _set(box, "site", 0, void)
     elif case == "material_end":
-        # the opposite direction from the same site ends in the material
+        # the opposite direction from the same site ends in the material,
+        # whose link back is not listed (a crack with one face)
         d = int(box.links["dir"][0])
         _set(box, "dir", 0, d + 1 if d % 2 else d - 1)
     elif case == "q0":
@@ -170,11 +171,27 @@ def test_invalid_cut_links_are_rejected_on_the_host(case):
     assert msg
 
 
-def test_valid_cavity_without_a_gpu_fails_loudly():
+def _cracked():
+    groups = [B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN, (1e-5, 0.0, 0.0))]
+    return B.sphere_box3(12, 11, 10, [B.Sphere3(3.6, 5.3, 4.8, 2.1, 0)], groups,
+                         cracks=[B.PennyCrack3(8.2, 5.1, 4.5, 2.4, 0, 1)])
+
+
+def test_one_sided_crack_is_rejected_on_the_host():
+    box = _cracked()
+    box.links = box.links[box.links["group"] != 1]    # the crack's upper face missing
+    rc, msg = _create(box)
+    assert rc == -1 and "link back" in msg, (rc, msg)
+
+
+@pytest.mark.parametrize("make", [_cavity, _cracked])
+def test_valid_geometry_without_a_gpu_fails_loudly(make):
+    """A valid cavity, or cavity and crack, passes the host checks and then
+    fails for want of a device."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    box = _cavity()
+    box = make()
     assert len(box.links) > 0 and box.n_material < box.n_sites
     rc, msg = _create(box)
     assert rc == -3, (rc, msg)

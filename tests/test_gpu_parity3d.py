@@ -321,3 +321,50 @@ def test_mask_without_void_matches_the_periodic_box(S3, prec):
     np.testing.assert_array_equal(res[0][0], res[1][0])
     for a, b in zip(res[0][1], res[1][1]):
         np.testing.assert_array_equal(a, b)
+
+
+def _crack_links(box):
+    """Cut links whose far end is material (a crack's faces)."""
+    z, r = np.divmod(box.links["site"].astype(np.int64), box.ny * box.nx)
+    y, x = np.divmod(r, box.nx)
+    c = B.C3[box.links["dir"]]
+    far = box.mask[(z + c[:, 2]) % box.nz, (y + c[:, 1]) % box.ny, (x + c[:, 0]) % box.nx]
+    return int(far.sum())
+
+
+def _cracked(order):
+    """A ragged box (70 x 13 x 11) with a spherical cavity (Dirichlet, moving)
+    and a penny-shaped crack of zero thickness (faces: traction-free below,
+    a shear traction and pressure above), lambda = mu, tau_bar = 0.7."""
+    groups = [B.BCGroup3(B.DIRICHLET, (2e-4, -1e-4, 5e-5)), B.BCGroup3(B.NEUMANN),
+              B.BCGroup3(B.NEUMANN, (2e-5, -1e-5, 0.0), 1e-4)]
+    return B.sphere_box3(70, 13, 11, [B.Sphere3(18.2, 6.4, 5.3, 3.2, 0)], groups, lam=0.05, mu=0.05, tau=0.7,
+                         force=(0.0, 1e-6, -1e-6), neumann_order=order,
+                         cracks=[B.PennyCrack3(45.3, 6.1, 5.4, 4.6, 1, 2)])
+
+
+@pytest.mark.parametrize("prec,tol,order,steps", [("fp64", FP64_TOL, 0, 40), ("fp64", FP64_TOL, 1, 40),
+                                                  ("fp32", FP32_TOL, 0, 300), ("fp32", FP32_TOL, 1, 60)])
+def test_cavity_and_crack(S3, prec, tol, order, steps):
+    box = _cracked(order)
+    assert _crack_links(box) > 100
+    assert _crack_links(box) < len(box.links)         # the cavity's links as well
+    fields = dict(vel=B.random_velocity(box, 51 + order, 1e-3))
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"cavity and crack {prec} order {order}", box)
+
+
+def test_penny_crack_leaves_an_in_plane_stress_alone_on_the_gpu(S3):
+    """The oracle's crack patch test on the GPU (fp64, 30 steps): traction-free
+    faces under a uniform stress in the crack's plane keep it exactly."""
+    box = B.sphere_box3(70, 13, 10, [], [B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN)], lam=0.1, mu=0.05, tau=0.6,
+                        neumann_order=1, cracks=[B.PennyCrack3(40.6, 6.2, 4.3, 4.1, 0, 1)])
+    sig = np.zeros((6, box.nz, box.ny, box.nx))
+    sig[0], sig[1], sig[3] = 3e-4, -1e-4, 2e-4
+    with S3.Solver3(box, "fp64") as s:
+        s.init_fields(sigma=sig)
+        s.step(30)
+        s.sync()
+        rho, j, P, sg = s.moments()
+    assert np.abs(sg - sig).max() < 1e-12
+    assert np.abs(j).max() < 1e-13

@@ -445,6 +445,119 @@ def test_brute_force_loops_with_a_cavity(order):
         assert np.abs(o.U - Un).max() < 1e-14
 
 
+def _plane_crack(nx, ny, nz, walls, order, lam=0.09, mu=0.05, tau=0.6):
+    """The slab of `walls` (at q_left, q_right) written as a crack of zero
+    thickness across a box of nx columns periodic in x, with no void: the
+    links between columns nx - 1 and 0 are cut, column 0 seeing the first
+    wall (normal -x) and column nx - 1 the second (+x).  With q_left +
+    q_right = 1 the two faces are one plane; otherwise each face still sits
+    at its own q."""
+    mask = np.ones((nz, ny, nx), dtype=np.uint8)
+    recs = []
+    for z in range(nz):
+        for y in range(ny):
+            for side, x in ((0, 0), (1, nx - 1)):
+                for i in range(1, Q):
+                    if C[i, 0] == (-1 if side == 0 else 1):
+                        recs.append(((z * ny + y) * nx + x, i, walls[side].q, side,
+                                     (-1.0 if side == 0 else 1.0, 0.0, 0.0)))
+    links = np.array(sorted(recs, key=lambda r: (r[0], r[1])), dtype=B.LINK3_DTYPE)
+    groups = [B.BCGroup3(w.kind, w.value) for w in walls]
+    return B.Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, mask=mask, links=links, groups=groups,
+                  neumann_order=order)
+
+
+@pytest.mark.parametrize("nx,qs,order", [(5, (0.5, 0.5), 0), (6, (0.3, 0.7), 1), (4, (0.9, 0.15), 0)])
+def test_plane_crack_reproduces_the_wall_planes(nx, qs, order):
+    """Cut links between two material sites (a crack, both faces listed)
+    reduce to the pinned wall planes: a crack across a box periodic in x,
+    without any void, gives the state of the slab with the two walls."""
+    walls = (B.Wall3(B.NEUMANN, (-1e-4, 3e-4, 0.0), q=qs[0]), B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3), q=qs[1]))
+    plane = B.slab3(nx, 4, 3, *walls, lam=0.09, mu=0.05, tau=0.6, neumann_order=order)
+    crack = _plane_crack(nx, 4, 3, walls, order)
+    o1, o2 = Oracle3D(plane), Oracle3D(crack)
+    rng = np.random.default_rng(12)
+    v = 1e-3 * rng.normal(size=(3,) + o1.shape)
+    o1.init_fields(vel=v)
+    o2.init_fields(vel=v)
+    o1.step(9)
+    o2.step(9)
+    assert np.abs(o1.populations() - o2.populations()).max() < 1e-14
+    assert np.abs(o1.displacement() - o2.displacement()).max() < 1e-13
+
+
+def _penny(order, groups, lam=0.1):
+    return B.sphere_box3(14, 13, 10, [], groups, lam=lam, mu=0.05, tau=0.6, neumann_order=order,
+                         cracks=[B.PennyCrack3(6.6, 6.2, 4.3, 4.1, 0, 1)])
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_penny_crack_leaves_an_in_plane_stress_alone(order):
+    """Patch test of eq:abbnoncon at a crack: traction-free faces normal to z
+    carry no load under a uniform stress in the crack's plane (sigma_xx,
+    sigma_yy, sigma_xy), which is therefore an exact steady state; a
+    crack that transmitted normal or shear stress, or a wrong q, would
+    disturb it by the order of the stress."""
+    b = _penny(order, [B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN)])
+    assert len(b.links) > 100 and b.n_material == b.n_sites
+    o = Oracle3D(b)
+    sig = np.zeros((6,) + o.shape)
+    sig[0], sig[1], sig[3] = 3e-4, -1e-4, 2e-4
+    o.init_fields(sigma=sig)
+    o.step(8)
+    m = o.moments()
+    assert np.abs(m[3] - sig).max() < 1e-13
+    assert np.abs(m[1]).max() < 1e-13
+
+
+def test_penny_crack_opens_under_normal_tension():
+    """The same crack under a normal tension sigma_zz (traction-free faces):
+    the faces move apart (the material below moves down, above moves up),
+    unlike the uncracked box, which stays at rest."""
+    b = _penny(0, [B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN)])
+    o = Oracle3D(b)
+    sig = np.zeros((6,) + o.shape)
+    sig[2] = 2e-4
+    o.init_fields(sigma=sig)
+    o.step(12)
+    u = o.displacement()
+    uz_below, uz_above = u[2, 4, 6, 6], u[2, 5, 6, 6]            # either side of the crack's centre
+    assert uz_below < -1e-6 and uz_above > 1e-6
+    ref = Oracle3D(B.periodic_box3(14, 13, 10, lam=0.1, mu=0.05, tau=0.6))
+    ref.init_fields(sigma=sig)
+    ref.step(12)
+    assert np.abs(ref.displacement()).max() < 1e-15
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_brute_force_loops_with_a_crack(order):
+    """One step with a penny crack (both faces, with pressure and shear
+    traction, and a moving face) against the per-site loop form."""
+    b = B.sphere_box3(7, 7, 5, [], [B.BCGroup3(B.NEUMANN, (1e-4, -2e-4, 5e-5), pressure=3e-4),
+                                  B.BCGroup3(B.DIRICHLET, (1e-3, 2e-3, -1e-3))],
+                      lam=0.09, mu=0.05, tau=0.6, force=(1e-5, 0.0, -2e-5), neumann_order=order,
+                      cracks=[B.PennyCrack3(3.1, 2.9, 2.35, 1.8, 0, 1)])
+    assert len(b.links) > 10
+    rng = np.random.default_rng(10)
+    o = Oracle3D(b)
+    f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
+    o.set_populations(f)
+    U0 = rng.normal(size=(3,) + o.shape)
+    o.U = U0.copy()
+    o.step(1)
+    fn, Un = naive_step(b, f, U0, [tuple(int(a) for a in c) for c in C])
+    assert np.abs(o.populations() - fn).max() < 1e-14
+    assert np.abs(o.U - Un).max() < 1e-14
+
+
+def test_one_sided_crack_is_refused():
+    b = _penny(0, [B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN)])
+    lower = b.links[b.links["group"] == 0]
+    b.links = lower                                  # the upper face missing
+    with pytest.raises(ValueError):
+        Oracle3D(b)
+
+
 def test_inconsistent_cut_links_are_refused():
     b = B.sphere_box3(10, 9, 8, [B.Sphere3(4.4, 4.2, 3.9, 2.2, 0)], [B.BCGroup3(B.NEUMANN)])
     for bad in ("missing", "material_far_end", "q"):
