@@ -368,3 +368,34 @@ def test_penny_crack_leaves_an_in_plane_stress_alone_on_the_gpu(S3):
         rho, j, P, sg = s.moments()
     assert np.abs(sg - sig).max() < 1e-12
     assert np.abs(j).max() < 1e-13
+
+
+@pytest.mark.slow
+def test_cavities256_holds_its_hydrostatic_state(S3):
+    """The benchmark's porous solid at full size, in its precision and launch
+    configuration (256^3, 64 cavities, 1.7 M cut links, fp32): under the
+    uniform stress -p I, with p the pressure on every cavity wall, the state
+    is exact at any size (the oracle's patch test), so after 100 steps sigma
+    is still -p I at every material site to fp32 rounding and j is 0; a wrong
+    q, normal, group or record would disturb it by the order of p."""
+    import torch
+    box = B.cavities_box3(256)
+    p = box.groups[0].pressure
+    n = box.n_sites
+    sig = np.zeros((6, n))
+    sig[:3] = -p
+    with S3.Solver3(box, "fp32") as s:
+        s.init_fields(sigma=sig.reshape(6, box.nz, box.ny, box.nx))
+        s.step(100)
+        s.sync()
+        dev = torch.device("cuda:0")
+        sg = torch.empty((6, n), dtype=torch.float64, device=dev)
+        j = torch.empty((3, n), dtype=torch.float64, device=dev)
+        s.moments_device(j=j.data_ptr(), sigma=sg.data_ptr())
+        torch.cuda.synchronize()
+    mk = torch.from_numpy(box.mask.ravel().astype(bool)).to(dev)
+    target = torch.tensor([-p, -p, -p, 0.0, 0.0, 0.0], dtype=torch.float64, device=dev)[:, None]
+    err_s = float((sg - target)[:, mk].abs().max())
+    err_j = float(j[:, mk].abs().max())
+    print(f"cavities256 hydrostatic: max |sigma + p I| = {err_s:.3e} (p = {p:.1e}), max |j| = {err_j:.3e}", flush=True)
+    assert err_s < 1e-4 * p and err_j < 1e-4 * p
