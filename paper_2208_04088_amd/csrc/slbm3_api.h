@@ -137,12 +137,54 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
             return fail(SLBM_E_INVAL, "link %lld: ends in the material but the link back (the crack's other face) "
                                       "is not listed", (long long)l);
     }
-    // every link from the material into the void is listed
-    for (long long s = 0; s < n; ++s) {
-        if (!p->mask[s]) continue;
-        for (int i = 1; i < kQ; ++i)
-            if (!p->mask[far_site(s, i)] && !(g.flags[s] & (1u << (i - 1))))
-                return fail(SLBM_E_INVAL, "site %lld: link %d into the void is not listed", s, i);
+    // every link from the material into the void is listed: planes of z on
+    // several host threads, each site's 18 neighbours through the 9 rows
+    // around it; the first offending site (lowest index) is reported
+    {
+        const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<long long> first((size_t)nthreads, -1);
+        std::vector<int> first_dir((size_t)nthreads, 0);
+        auto scan = [&](int t) {
+            for (int z = t; z < nz; z += nthreads) {
+                for (int y = 0; y < ny; ++y) {
+                    const uint8_t* row[3][3];
+                    for (int dz = -1; dz <= 1; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            row[dz + 1][dy + 1] = p->mask + (((long long)((z + dz + nz) % nz) * ny + (y + dy + ny) % ny) * nx);
+                    const long long base = ((long long)z * ny + y) * nx;
+                    for (int x = 0; x < nx; ++x) {
+                        if (!p->mask[base + x]) continue;
+                        const uint32_t fl = g.flags[base + x];
+                        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+                        for (int i = 1; i < kQ; ++i) {
+                            const int fx = kCX[i] < 0 ? xm : (kCX[i] > 0 ? xp : x);
+                            if (!row[kCZ[i] + 1][kCY[i] + 1][fx] && !(fl & (1u << (i - 1)))) {
+                                if (first[t] < 0 || base + x < first[t]) {
+                                    first[t] = base + x;
+                                    first_dir[t] = i;
+                                }
+                                break;
+                            }
+                        }
+                        if (first[t] >= 0) break;
+                    }
+                    if (first[t] >= 0) break;
+                }
+                if (first[t] >= 0) break;              // later planes of this thread have higher indices
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthreads; ++t) pool.emplace_back(scan, t);
+        scan(0);
+        for (std::thread& th : pool) th.join();
+        long long bad = -1;
+        int bad_dir = 0;
+        for (int t = 0; t < nthreads; ++t)
+            if (first[t] >= 0 && (bad < 0 || first[t] < bad)) {
+                bad = first[t];
+                bad_dir = first_dir[t];
+            }
+        if (bad >= 0) return fail(SLBM_E_INVAL, "site %lld: link %d into the void is not listed", bad, bad_dir);
     }
     // records sorted by site, then direction (the kernel walks a site's cut
     // bits upwards from its first record)
