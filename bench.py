@@ -179,6 +179,14 @@ def bytes_per_step3(box, prec):
     return box.n_material * bytes_per_site3(prec) + 4 * box.n_sites + len(box.links) * link_record_bytes3(prec)
 
 
+def has_ext_links3(box):
+    """Whether the box has Neumann cut links whose data are extrapolated along
+    the link (neumann_order 1, not thin): those take a launch of their own."""
+    if box.mask is None or not len(box.links) or box.neumann_order != 1:
+        return False
+    return any(box.groups[g].kind == 2 for g in set(box.links["group"].tolist()))
+
+
 def measured_traffic3(box, prec):
     """Calibrated counter bytes per step of the two 3-D kernels
     (profiles/traffic_<box>_<precision>.json), or None when there is none or
@@ -192,7 +200,8 @@ def measured_traffic3(box, prec):
     if d.get("kernel_fingerprint") != kernel_fingerprint("step3_kernel.h"):
         return None
     shapes = d.get("shapes", {})
-    kernels = ("k3_links", "k3_density", "k3_step") if box.mask is not None else ("k3_density", "k3_step")
+    kernels = ("k3_links_ext",) if has_ext_links3(box) else ()
+    kernels += ("k3_density", "k3_step")
     parts = [shapes.get(k) for k in kernels]
     return None if None in parts else sum(p["traffic_bytes_per_launch"] for p in parts)
 
@@ -272,14 +281,14 @@ def run_3d(args, torch, dev, stream, n, kind="cube"):
                    "material_sites": sites,
                    "precision": "fp32 populations and arithmetic, fp64 displacement" if prec == "fp32" else "fp64",
                    "lambda_over_mu": box.lam / box.mu, "tau": box.tau,
-                   "bench_step": "one D3Q19 time step of the whole box (cut-link rules with a mask, density pass, "
-                                 "step kernel)",
+                   "bench_step": "one D3Q19 time step of the whole box (density pass and step kernel; "
+                                 "with cut links the step also forms the next step's rule values)",
                    "diverged": diverged, "wall_s": round(wall, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic3(box, prec),
-                     "kernel": ("k3_links + " if box.mask is not None else "") + "k3_density + k3_step",
+                     "kernel": ("k3_links_ext + " if has_ext_links3(box) else "") + "k3_density + k3_step",
                      "bytes_per_site": bps, "bytes_per_step": step_bytes,
-                     "launches_per_step": 3 if box.mask is not None else 2,
+                     "launches_per_step": 3 if has_ext_links3(box) else 2,
                      "avg_step_us": round(t_step * 1e6, 3),
                      "note": "achieved counts the step's algorithmic bytes over the time of all its launches; "
                              "the density pass re-reads the pulled populations (traffic: measured bytes per step)"},

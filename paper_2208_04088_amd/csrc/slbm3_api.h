@@ -33,7 +33,10 @@ struct slbm3_s {
     uint32_t* flags = nullptr;
     int32_t* bidx = nullptr;
     void* links = nullptr;
-    void* lval = nullptr;            // rule value per link record (k3_links)
+    void* lval = nullptr;            // per link record: (A, s_kappa) of the rule (k3_step, k3_links_ext)
+    int32_t* wrec = nullptr;         // per workgroup of k3_step: first record
+    int32_t* elink = nullptr;        // the records whose Neumann data are extrapolated
+    int64_t n_ext = 0;
     int64_t n_links = 0;
     size_t link_bytes = 0;
 };
@@ -78,6 +81,7 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     a.bidx = h->bidx;
     a.links = (const Link3<real>*)h->links;
     a.lval = (real*)h->lval;
+    a.wrec = h->wrec;
     return a;
 }
 
@@ -89,6 +93,9 @@ struct Geo3 {
     std::vector<uint32_t> flags;
     std::vector<int32_t> bidx;
     std::vector<Link3<double>> recs;
+    std::vector<double> skap;        // per record: kappa (Dirichlet), -kappa (Neumann) or 0 (ext)
+    std::vector<int32_t> elink;      // the ext records
+    std::vector<int32_t> wrec;       // per workgroup of k3_step: its first record, then the count
 };
 
 int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
@@ -196,6 +203,7 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
     });
     g.bidx.assign((size_t)n, 0);
     g.recs.resize(order.size());
+    g.skap.resize(order.size());
     for (size_t r = 0; r < order.size(); ++r) {
         const slbm3_link& L = p->links[order[r]];
         if (r == 0 || p->links[order[r - 1]].site != L.site) g.bidx[L.site] = (int32_t)r;
@@ -254,6 +262,22 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         const int ext = gr.kind == SLBM_NEUMANN && h->norder == 1 && !thin ? 1 : 0;
         R.meta = link3_meta(i, ib, gr.kind, ext, kCX[i], kCY[i], kCZ[i]);
         R.site = L.site;
+        g.skap[r] = ext ? 0.0 : (gr.kind == SLBM_DIRICHLET ? kap : -kap);
+        if (ext) g.elink.push_back((int32_t)r);
+    }
+    // k3_step's workgroups take four 64-site row chunks each, a contiguous
+    // range of sites from the first site of their first chunk
+    {
+        const long long chunks = (nx + 63) / 64, ntiles = chunks * ny * nz, nwg = (ntiles + 3) / 4;
+        g.wrec.resize((size_t)nwg + 1);
+        size_t r = 0;
+        for (long long w = 0; w < nwg; ++w) {
+            const long long t = 4 * w, row = t / chunks;
+            const long long first = row * nx + 64 * (t % chunks);
+            while (r < g.recs.size() && g.recs[r].site < first) ++r;
+            g.wrec[(size_t)w] = (int32_t)r;
+        }
+        g.wrec[(size_t)nwg] = (int32_t)g.recs.size();
     }
     return SLBM_OK;
 }
@@ -293,8 +317,9 @@ int grid3(const slbm3_s* h)
     return (int)((wg + unit - 1) / unit * unit);
 }
 
-// Rule values at the cut links (general geometry, GEO, which implies PX),
-// density pass, then `what` (0 step, 1 outputs into scratch, 2 init from scratch).
+// The extrapolating rules (general geometry, GEO, which implies PX; the other
+// cut links' parts come from the previous k3_step), density pass, then
+// `what` (0 step, 1 outputs into scratch, 2 init from scratch).
 template <typename real, bool PX, bool GEO>
 int launch3(slbm3_s* h, int what)
 {
@@ -308,9 +333,9 @@ int launch3(slbm3_s* h, int what)
         HIP_TRY(hipGetLastError());
         return SLBM_OK;
     }
-    if (GEO && !h->local && h->n_links > 0)          // the rules' values, read by both pulls
-        hipLaunchKernelGGL((k3_links<real>), dim3((unsigned)((h->n_links + 255) / 256)), blk, 0, h->stream, a,
-                           (int)h->n_links);
+    if (GEO && !h->local && h->n_ext > 0)            // the extrapolating rules, read by both pulls
+        hipLaunchKernelGGL((k3_links_ext<real>), dim3((unsigned)((h->n_ext + 255) / 256)), blk, 0, h->stream, a,
+                           (const int32_t*)h->elink, (int)h->n_ext);
     hipLaunchKernelGGL((k3_density<real, PX, GEO>), grid, blk, 0, h->stream, a);
     if (what == 0)
         hipLaunchKernelGGL((k3_step<real, PX, GEO>), grid, blk, 0, h->stream, a);
@@ -340,7 +365,7 @@ int ensure_scratch3(slbm3_s* h)
 void free3(slbm3_s* h)
 {
     for (void* p : {h->buf[0], h->buf[1], (void*)h->U, h->dens, (void*)h->diverged, (void*)h->scratch,
-                    (void*)h->flags, (void*)h->bidx, h->links, h->lval})
+                    (void*)h->flags, (void*)h->bidx, h->links, h->lval, (void*)h->wrec, (void*)h->elink})
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -431,6 +456,7 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
             if (rc) { delete h; return rc; }
             h->geo = true;
             h->n_links = (int64_t)geo.recs.size();
+            h->n_ext = (int64_t)geo.elink.size();
         }
         DeviceGuard dg(h->device);
     #define TRY_OR_BAIL(expr)                                \
@@ -462,6 +488,9 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
                                        hipMemcpyHostToDevice, h->stream));
             TRY_OR_BAIL(hipMemcpyAsync(h->bidx, geo.bidx.data(), (size_t)plane * sizeof(int32_t),
                                        hipMemcpyHostToDevice, h->stream));
+            TRY_OR_BAIL(hipMalloc((void**)&h->wrec, geo.wrec.size() * sizeof(int32_t)));
+            TRY_OR_BAIL(hipMemcpyAsync(h->wrec, geo.wrec.data(), geo.wrec.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, h->stream));
             if (!geo.recs.empty()) {
                 if (h->precision == SLBM_FP32) {
                     const std::vector<Link3<float>> r = cast_links3<float>(geo.recs);
@@ -475,7 +504,25 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
                     TRY_OR_BAIL(hipMemcpyAsync(h->links, geo.recs.data(), h->link_bytes, hipMemcpyHostToDevice,
                                                h->stream));
                 }
-                TRY_OR_BAIL(hipMalloc(&h->lval, geo.recs.size() * h->esize));
+                // (A, s_kappa) per record: the parts come from the steps, s_kappa from here
+                std::vector<double> lv(2 * geo.recs.size(), 0.0);
+                for (size_t r = 0; r < geo.recs.size(); ++r) lv[2 * r + 1] = geo.skap[r];
+                TRY_OR_BAIL(hipMalloc(&h->lval, lv.size() * h->esize));
+                if (h->precision == SLBM_FP32) {
+                    const std::vector<float> lf(lv.begin(), lv.end());
+                    TRY_OR_BAIL(hipMemcpyAsync(h->lval, lf.data(), lf.size() * sizeof(float), hipMemcpyHostToDevice,
+                                               h->stream));
+                    TRY_OR_BAIL(hipStreamSynchronize(h->stream));
+                } else {
+                    TRY_OR_BAIL(hipMemcpyAsync(h->lval, lv.data(), lv.size() * sizeof(double), hipMemcpyHostToDevice,
+                                               h->stream));
+                    TRY_OR_BAIL(hipStreamSynchronize(h->stream));
+                }
+                if (h->n_ext > 0) {
+                    TRY_OR_BAIL(hipMalloc((void**)&h->elink, geo.elink.size() * sizeof(int32_t)));
+                    TRY_OR_BAIL(hipMemcpyAsync(h->elink, geo.elink.data(), geo.elink.size() * sizeof(int32_t),
+                                               hipMemcpyHostToDevice, h->stream));
+                }
             }
         }
         TRY_OR_BAIL(hipStreamSynchronize(h->stream));
@@ -652,7 +699,11 @@ int slbm3_device_bytes(slbm3_handle h, int64_t* bytes)
         if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
         int64_t b = 2 * (int64_t)19 * h->stride * (int64_t)h->esize + 3 * h->stride * 8 + h->plane * (int64_t)h->esize;
         if (h->scratch) b += (int64_t)19 * h->plane * 8;
-        if (h->geo) b += h->plane * 8 + (int64_t)h->link_bytes + h->n_links * (int64_t)h->esize;
+        if (h->geo) {
+            const long long nwg = (((long long)(h->nx + 63) / 64) * h->ny * h->nz + 3) / 4;
+            b += h->plane * 8 + (int64_t)h->link_bytes + 2 * h->n_links * (int64_t)h->esize + (nwg + 1) * 4 +
+                 h->n_ext * 4;
+        }
         *bytes = b;
         return SLBM_OK;
     });

@@ -4,18 +4,23 @@
 // to a link, and this is their D3Q19 form: the same moments (eq:moments),
 // source term (eq:sourceterm), equilibrium with the populations' own second
 // moment (eq:fieq) and forced BGK collision (eq:coll), with c_s^2 = 1/3 and
-// weights 1/3, 1/18, 1/36.  Walls are lattice-conforming planes at
-// x = -1/2 and x = nx - 1/2 (q = 1/2), y and z periodic; the Dirichlet rule
-// is eq:bbcon, the Neumann rule eq:abbcon with the boundary stress
-// sigma* = Pi sigma(x) Pi + n t* + t* n - (t*.n) n n (Pi = I - n n).
+// weights 1/3, 1/18, 1/36.  Boundaries: either two planes normal to x that
+// cut the links leaving the material at a fraction q (y and z periodic), or
+// (GEO) a general geometry periodic on every axis -- a material mask and cut
+// links, each with its own q, outward normal and group (cavities, cracks).
+// The Dirichlet rule is eq:bbcon / eq:bbnoncon, the Neumann rule eq:abbcon /
+// eq:abbnoncon with the boundary stress
+// sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n (Pi = I - n n).
 //
 // State: shifted post-collision populations g = f - r (r the rest state),
 // SoA planes g[i][z][y][x], site offset (z ny + y) nx + x; consecutive planes
 // are `stride` elements apart, a little more than a plane, so that the 19
 // streams of a pull do not all start on the same HBM channel.  One step is two
 // launches: k3_density (delta-rho of the pulled state, needed by the
-// gradient stencil of every neighbour) and k3_step (pull with the wall
-// rules, moments, source term, collision, U, store).
+// gradient stencil of every neighbour) and k3_step (pull with the rules,
+// moments, source term, collision, U, store; with a general geometry also
+// the next step's rule values at the cut links), and with extrapolating
+// Neumann links k3_links_ext before them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,12 +103,12 @@ struct Step3Args {
     real wkap[2], wbeta[2], wq1[2], wq[2];
     int wext[2];
     // general geometry (periodic on every axis): site flags, each cut site's
-    // first link record, the records (sorted by site and direction), and the
-    // rule values of the pulled state, one per record (written by k3_links)
+    // first link record, the records (sorted by site and direction)
     const uint32_t* flags;
     const int32_t* bidx;
     const Link3<real>* links;
-    real* lval;
+    real* lval;                // per record: (A, s_kappa), see cut_links3
+    const int32_t* wrec;       // per workgroup of k3_step: its first record (one more: the count)
     real omega, omega_h;       // 1/tau, 1 - 1/(2 tau)
     real ml, lm;               // mu - lambda, lambda - mu (lattice units)
     real F[3];
@@ -348,65 +353,80 @@ __device__ __forceinline__ unsigned sidx3(int x, int y, int z, int nx, int ny)
 // returning population comes from the wall rule, from the site's own
 // post-collision populations (rho and P are those of the previous step,
 // conserved by the collision).
-// The rules of section 4 at the cut links of a general geometry, from the
-// post-collision state, one thread per link (the links of a site are
-// neighbouring threads and share the loads of the site's populations): the
-// population that returns to the link's site in the opposite direction,
-// into lval, where the pulls of the next density pass and step read it.  The
-// record's folded constants carry the link's own q, normal and group.
+// The rules of section 4 at the cut links of a general geometry.  The value
+// a cut link (x, i) returns to x in direction ibar is A + s_kappa g_i(x - c_i):
+// A takes only the post-collision state at x, s_kappa is kappa (Dirichlet) or
+// -kappa (Neumann), and g_i(x - c_i) is the population the pull of direction
+// i brings to x anyway (a thin link has kappa = 0 and needs none).  k3_step
+// evaluates A at every cut link of its workgroup's sites as soon as it has
+// their post-collision populations (one thread per link, through LDS), so
+// the rules take no pass of their own over the state.  A link whose Neumann
+// data are extrapolated along it (ext) needs the state at x - c_i as well:
+// k3_links_ext evaluates its whole value, with s_kappa = 0.  lval holds
+// (A, s_kappa) per record; s_kappa is set on the host.
+//
+// A from the record's folded constants (its own q, normal and group), g_i
+// and g_ib at x, drho and (or, ext, rho_bd and P_b) at x.
 template <typename real>
-__global__ __launch_bounds__(256) void k3_links(Step3Args<real> a, int n_links)
+__device__ __forceinline__ real link_part3(const Link3<real>& L, real hi, real hib, real dr, real drb, const real Pb[6])
 {
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= n_links) return;
+    if (((L.meta >> 10) & 3u) == kWallDirichlet) return hi - L.kap * hib - (real(1) + dr) * L.c0;
+    const real e = L.c0 * drb + (L.B[0] * Pb[0] + L.B[1] * Pb[1] + L.B[2] * Pb[2]) +
+                   (L.B[3] * Pb[3] + L.B[4] * Pb[4] + L.B[5] * Pb[5]) - L.K;
+    return -hi - L.kap * hib + L.bet2 * e;
+}
+
+// The whole value of each ext link from the post-collision state, one thread
+// per link (elink: the records' indices).
+template <typename real>
+__global__ __launch_bounds__(256) void k3_links_ext(Step3Args<real> a, const int32_t* elink, int n_ext)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_ext) return;
+    const int l = elink[t];
     const Link3<real> L = a.links[l];
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const unsigned s = (unsigned)L.site;
     const int x = (int)(s % (unsigned)nx), y = (int)((s / (unsigned)nx) % (unsigned)ny),
               z = (int)(s / ((unsigned)nx * (unsigned)ny));
-    const uint32_t meta = L.meta;
-    const int i = (int)(meta & 31u), ib = (int)((meta >> 5) & 31u);
-    const int cx = (int)((meta >> 13) & 3u) - 1, cy = (int)((meta >> 15) & 3u) - 1, cz = (int)((meta >> 17) & 3u) - 1;
+    const int i = (int)(L.meta & 31u), ib = (int)((L.meta >> 5) & 31u);
+    const int cx = (int)((L.meta >> 13) & 3u) - 1, cy = (int)((L.meta >> 15) & 3u) - 1, cz = (int)((L.meta >> 17) & 3u) - 1;
     // the site behind x along the link, x - c_i (periodic axes)
     const unsigned sb = sidx3(wrap(x - cx, nx), wrap(y - cy, ny), wrap(z - cz, nz), nx, ny);
-    const real hi = a.src[i * a.stride + s], hib = a.src[ib * a.stride + s];
-    const real hy = L.kap != real(0) ? a.src[i * a.stride + sb] : real(0);
     real h[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; ++k) h[k] = a.src[k * a.stride + s];
     real dr, j[3], P[6];
     moments3(h, dr, j, P);
-    real val;
-    if (((meta >> 10) & 3u) == kWallDirichlet) {
-        val = hi + L.kap * (hy - hib) - (real(1) + dr) * L.c0;
-    } else {
-        real drb = dr;
-        if ((meta >> 12) & 1u) {                 // ext: rho_bd and P_b extrapolated along the link
+    const real hi = a.src[i * a.stride + s], hib = a.src[ib * a.stride + s], hy = a.src[i * a.stride + sb];
 #pragma unroll
-            for (int k = 0; k < kQ; ++k) h[k] = a.src[k * a.stride + sb];
-            real dry, Py[6];
-            moments3(h, dry, j, Py);
-            drb = L.q1 * dr - L.q * dry;
+    for (int k = 0; k < kQ; ++k) h[k] = a.src[k * a.stride + sb];
+    real dry, Py[6];
+    moments3(h, dry, j, Py);
+    const real drb = L.q1 * dr - L.q * dry;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) P[c] = L.q1 * P[c] - L.q * Py[c];
-        }
-        const real e = L.c0 * drb + (L.B[0] * P[0] + L.B[1] * P[1] + L.B[2] * P[2]) +
-                       (L.B[3] * P[3] + L.B[4] * P[4] + L.B[5] * P[5]) - L.K;
-        val = -hi - L.kap * (hy + hib) + L.bet2 * e;
-    }
-    a.lval[l] = val;
+    for (int c = 0; c < 6; ++c) P[c] = L.q1 * P[c] - L.q * Py[c];
+    a.lval[2 * l] = link_part3(L, hi, hib, dr, drb, P) - L.kap * hy;
 }
 
-// A cut site's pulls along its cut links: the rule values of k3_links (the
-// site's records are consecutive, in direction order, from bidx).
+// A cut site's pulls along its cut links (the site's records are consecutive,
+// in direction order, from bidx): A + s_kappa g_i(x - c_i), every value
+// formed from the pulled populations before any is replaced.
 template <typename real>
 __device__ __forceinline__ void cut_links3(const Step3Args<real>& a, unsigned s, uint32_t fl, real g[kQ])
 {
     const int li = a.bidx[s];
     const uint32_t m = fl & kCutMask3;
+    real v[kQ];
 #pragma unroll
     for (int k = 1; k < kQ; ++k)
-        if ((m >> (k - 1)) & 1u) g[opp3(k)] = a.lval[li + __builtin_popcount(m & ((1u << (k - 1)) - 1u))];
+        if ((m >> (k - 1)) & 1u) {
+            const int l = li + __builtin_popcount(m & ((1u << (k - 1)) - 1u));
+            v[k] = a.lval[2 * l] + a.lval[2 * l + 1] * g[k];
+        }
+#pragma unroll
+    for (int k = 1; k < kQ; ++k)
+        if ((m >> (k - 1)) & 1u) g[opp3(k)] = v[k];
 }
 
 template <typename real, bool PX, bool GEO = false>
@@ -618,9 +638,16 @@ __device__ __forceinline__ double recip3(double x) { return 1.0 / x; }
 template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 {
-    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (tile >= a.ntiles) return;
-    const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
+    const int wg = xcd_group3(blockIdx.x);
+    int tile = wg * 4 + (threadIdx.x >> 6);
+    if (wg * 4 >= a.ntiles) return;                     // uniform over the workgroup
+    const bool tvalid = tile < a.ntiles;
+    if (!tvalid) {
+        if constexpr (!GEO) return;
+        tile = a.ntiles - 1;                            // GEO: stays for the barrier, stores nothing
+    }
+    Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
+    if (!tvalid) st.in = false;
     real g[kQ];
     uint32_t fl;
     pull3<real, PX, GEO>(a, st, g, fl);
@@ -654,6 +681,34 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
     }
     if (__any(bad && live) && (threadIdx.x & 63) == 0 && *(volatile unsigned int*)a.diverged == 0u)
         atomicOr(a.diverged, 1u);
+    if constexpr (GEO) {
+        // A at the cut links of the workgroup's sites (a contiguous range of
+        // at most 256 from the first site of its first tile), one thread per
+        // record, from the post-collision populations staged in LDS
+        const int r0 = a.wrec[wg], nrec = a.wrec[wg + 1] - r0;   // uniform over the workgroup
+        if (nrec > 0) {
+            __shared__ real lo[kQ][256];
+            const Site3 b0 = site_of(wg * 4, 0, a.nx, a.ny);
+            const unsigned base = sidx3(b0.x, b0.y, b0.z, a.nx, a.ny);
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) lo[i][s - base] = o[i];
+            }
+            __syncthreads();
+            for (int r = threadIdx.x; r < nrec; r += 256) {
+                const Link3<real> L = a.links[r0 + r];
+                if ((L.meta >> 12) & 1u) continue;              // ext: k3_links_ext
+                const int slot = (int)((unsigned)L.site - base);
+                real h[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) h[i] = lo[i][slot];
+                real hd, hj[3], hP[6];
+                moments3(h, hd, hj, hP);
+                const int k = (int)(L.meta & 31u), kb = (int)((L.meta >> 5) & 31u);
+                a.lval[2 * (r0 + r)] = link_part3(L, lo[k][slot], lo[kb][slot], hd, hd, hP);
+            }
+        }
+    }
 }
 
 // Outputs at every site (lattice units, double, planes of `out`): 0
