@@ -399,3 +399,19 @@ def test_cavities256_holds_its_hydrostatic_state(S3):
     err_j = float(j[:, mk].abs().max())
     print(f"cavities256 hydrostatic: max |sigma + p I| = {err_s:.3e} (p = {p:.1e}), max |j| = {err_j:.3e}", flush=True)
     assert err_s < 1e-4 * p and err_j < 1e-4 * p
+
+
+@pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 30), ("fp32", FP32_TOL, 200)])
+def test_narrow_box_with_cut_links(S3, prec, tol, steps):
+    """A box narrower than one 64-site chunk (30 x 15 x 13: each workgroup of
+    the step takes four rows, across z planes too, and the last one is
+    partial) with a cavity and a crack: the workgroups' record ranges and the
+    staging of their sites' populations."""
+    groups = [B.BCGroup3(B.NEUMANN, (0.0, 0.0, 0.0), 1e-4), B.BCGroup3(B.DIRICHLET, (1e-4, 0.0, -2e-4)),
+              B.BCGroup3(B.NEUMANN)]
+    box = B.sphere_box3(30, 15, 13, [B.Sphere3(9.3, 7.2, 6.1, 3.4, 0)], groups, lam=0.05, mu=0.05, tau=0.7,
+                        neumann_order=0, cracks=[B.PennyCrack3(21.4, 7.6, 6.5, 4.2, 1, 2)])
+    assert ((box.nx + 63) // 64 * box.ny * box.nz) % 4 != 0 and _crack_links(box) > 50
+    fields = dict(vel=B.random_velocity(box, 61, 1e-3))
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"narrow box {prec}", box)
