@@ -56,7 +56,7 @@ typedef enum {
     SLBM_E_NOMEM = -2,       /* device or host allocation failed */
     SLBM_E_DEVICE = -3,      /* a HIP call failed */
     SLBM_E_DIVERGED = -4,    /* a non-finite value, or |drho| + |j| >= rho0 (lattice units), appeared */
-    SLBM_E_UNSUPPORTED = -5, /* valid request this build does not handle */
+    SLBM_E_UNSUPPORTED = -5, /* valid request the library does not handle */
     SLBM_E_BUDGET = -6       /* a batch has no room for the plate */
 } slbm_status;
 
