@@ -99,6 +99,41 @@ def test_axis_permutation_symmetry():
         assert np.allclose(np.moveaxis(u1[k], (0, 1, 2), (2, 0, 1)), u2[kp], atol=1e-16, rtol=1e-11)
 
 
+@pytest.mark.parametrize("order", [0, 1])
+def test_cavities_are_equivariant_under_axis_relabelling(order):
+    """The cyclic relabelling x -> y -> z -> x of a box with cavities (one
+    pressurised with a shear traction, one moving), of its groups' vectors and
+    of the initial field relabels the solution: the per-link directions,
+    normals, q and group values are handled alike along every axis (a
+    transposed normal or traction component breaks it)."""
+    n = 12
+    groups = [B.BCGroup3(B.NEUMANN, (2e-4, -1e-4, 3e-4), 1e-4), B.BCGroup3(B.DIRICHLET, (1e-3, -2e-3, 5e-4))]
+    sph = [(3.7, 4.4, 5.2, 2.3, 0), (8.1, 7.2, 6.3, 2.1, 1)]
+
+    def rot(v):                      # (x, y, z) -> (z, x, y): component x goes to y
+        return (v[2], v[0], v[1])
+
+    def box(spheres, grps):
+        return B.sphere_box3(n, n, n, [B.Sphere3(*c, R, g) for *c, R, g in spheres], grps, lam=0.08, mu=0.05,
+                             tau=0.6, neumann_order=order)
+
+    b1 = box(sph, groups)
+    b2 = box([(*rot(c[:3]), c[3], c[4]) for c in sph],
+             [B.BCGroup3(g.kind, rot(g.value), g.pressure) for g in groups])
+    v = B.random_velocity(b1, 6, 1e-3)
+    vp = np.empty_like(v)
+    vp[1], vp[2], vp[0] = (np.moveaxis(v[k], (0, 1, 2), (2, 0, 1)) for k in range(3))
+    o1, o2 = Oracle3D(b1), Oracle3D(b2)
+    o1.init_fields(vel=v)
+    o2.init_fields(vel=vp)
+    o1.step(6)
+    o2.step(6)
+    u1, u2 = o1.displacement(), o2.displacement()
+    assert np.abs(u1).max() > 1e-4
+    for k, kp in ((0, 1), (1, 2), (2, 0)):
+        assert np.allclose(np.moveaxis(u1[k], (0, 1, 2), (2, 0, 1)), u2[kp], atol=1e-15, rtol=1e-10)
+
+
 def _mode_frequency(o, kvec, comp, steps):
     """Angular frequency (per step) of the standing mode sum_x j(x) sin(k.x)
     along `comp`: the slope of its zero-crossing times, each located by
