@@ -182,9 +182,10 @@ def bytes_per_step3(box, prec):
 def has_ext_links3(box):
     """Whether the box has Neumann cut links whose data are extrapolated along
     the link (neumann_order 1, not thin): those take a launch of their own."""
+    from slbm_workloads.box3d import NEUMANN
     if box.mask is None or not len(box.links) or box.neumann_order != 1:
         return False
-    return any(box.groups[g].kind == 2 for g in set(box.links["group"].tolist()))
+    return any(box.groups[g].kind == NEUMANN for g in set(box.links["group"].tolist()))
 
 
 def measured_traffic3(box, prec):
