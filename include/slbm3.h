@@ -79,15 +79,22 @@ typedef struct {
     double q;                    /* fraction of a cut link inside the material, (0, 1]; 1/2: lattice-conforming */
 } slbm3_wall;
 
-/* One cut link of a general geometry (48 bytes): the link from the material
+/* One cut link of a general geometry (80 bytes): the link from the material
  * site x to x + c_dir, whose far end is void (or material across a crack),
- * crossing the boundary at the fraction q of its length. */
+ * crossing the boundary at the fraction q of its length.  A link that leaves
+ * through the edge where two faces meet (both crossed at the same point)
+ * carries the second face too: there the Dirichlet face wins, and two
+ * Neumann faces fix the rows of both normals of sigma* (in the frame n, n2,
+ * e = n x n2, the shear between them averaged), sigma*_ee taken from the
+ * material as the tangential block is for one face. */
 typedef struct {
     int32_t site;                /* (iz*ny + iy)*nx + ix of x, a material site */
     int32_t dir;                 /* direction i of the link, 1..18 (order above) */
     double q;                    /* (0, 1] */
     int32_t group;               /* index into slbm3_params.groups */
     double normal[3];            /* outward unit normal of the material where the link crosses */
+    int32_t group2;              /* the second face's group at an edge, or -1 */
+    double normal2[3];           /* its outward unit normal, orthogonal to normal (ignored when group2 = -1) */
 } slbm3_link;
 
 /* Boundary data shared by a group of cut links, user units. */
@@ -121,7 +128,8 @@ typedef struct {
  * or SLBM_E_DEVICE if allocation fails; *out is NULL on failure.  With a mask
  * SLBM_E_INVAL also names the first invalid link: a site out of range or
  * void, a direction out of 1..18, q outside (0, 1], a group out of range, a
- * normal that is not a unit vector (to 1e-9), a link listed twice, a link
+ * normal that is not a unit vector (to 1e-9), a second group out of range
+ * or its normal not a unit vector orthogonal to the first, a link listed twice, a link
  * into the material whose link back is not listed, or a link from the
  * material into the void that is not listed; and an invalid group kind.
  * The arrays are copied. */

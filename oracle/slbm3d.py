@@ -180,6 +180,19 @@ class Oracle3D:
         n = np.asarray(L["normal"], dtype=float)
         if np.abs(np.linalg.norm(n, axis=1) - 1).max() > 1e-9:
             raise ValueError("normals must be unit vectors")
+        g = L["group"].astype(np.int64)
+        has2 = "group2" in L.dtype.names
+        g2 = L["group2"].astype(np.int64) if has2 else np.full(len(site), -1)
+        n2 = np.asarray(L["normal2"], dtype=float) if has2 else np.zeros((len(site), 3))
+        ng = len(b.groups)
+        if ((g < 0) | (g >= ng)).any() or ((g2 < -1) | (g2 >= ng)).any():
+            raise ValueError("a cut link's group is out of range")
+        two = g2 >= 0
+        if two.any():
+            if np.abs(np.linalg.norm(n2[two], axis=1) - 1).max() > 1e-9:
+                raise ValueError("second normals must be unit vectors")
+            if np.abs(np.einsum("ma,ma->m", n[two], n2[two])).max() > 1e-9:
+                raise ValueError("a link through an edge needs orthogonal normals")
         if len(set(zip(site.tolist(), k.tolist()))) != len(site):
             raise ValueError("a cut link is listed twice")
         self.cut[k, z, y, x] = True
@@ -192,8 +205,8 @@ class Oracle3D:
             far_void = ~np.roll(mask, (-C[i, 2], -C[i, 1], -C[i, 0]), axis=(0, 1, 2))
             if (far_void & mask & ~self.cut[i]).any():
                 raise ValueError("a link from the material into the void is not listed")
-        self.links = dict(z=z, y=y, x=x, k=k, q=q.astype(self.dt), g=L["group"].astype(np.int64),
-                          n=n.astype(self.dt))
+        self.links = dict(z=z, y=y, x=x, k=k, q=q.astype(self.dt), g=g, n=n.astype(self.dt), g2=g2,
+                          n2=n2.astype(self.dt))
         self.gkind = np.array([g.kind for g in b.groups])
         self.gval = []
         for g in b.groups:
@@ -333,7 +346,10 @@ class Oracle3D:
         """The cut links of a general geometry, each with its own q, outward
         normal and group (section 4.2, as `_walls` for planes): the population
         returning to x in direction ibar.  A link whose opposite link at x is
-        cut too has no site behind x (kappa = 0, beta = 1, no extrapolation)."""
+        cut too has no site behind x (kappa = 0, beta = 1, no extrapolation).
+        A link through the edge where two faces meet carries both faces'
+        groups and normals (the two-dimensional corner reading in three
+        dimensions)."""
         rho, _, P = self._moments(fcol)
         L = self.links
         z, y, x, k, q = L["z"], L["y"], L["x"], L["k"], L["q"]
@@ -349,20 +365,22 @@ class Oracle3D:
         r = rho[z, y, x]
         c = C[k].astype(self.dt)                                   # [m, 3]
         out = np.empty_like(fk)
+        g, g2 = L["g"], L["g2"]
+        dirichlet = self.gkind == DIRICHLET
+        # where two faces meet on the link (an edge), the Dirichlet face wins
+        gd = np.where(dirichlet[g], g, np.where((g2 >= 0) & dirichlet[np.maximum(g2, 0)], g2, -1))
         for gi, (val, pres) in enumerate(self.gval):
-            sel = L["g"] == gi
-            if not sel.any():
-                continue
-            if self.gkind[gi] == DIRICHLET:
+            sel = gd == gi
+            if sel.any():
                 # eq:bbcon / eq:bbnoncon with j* = rho(x) v*
                 cj = (c[sel] @ val) * r[sel]
                 out[sel] = (fk[sel] + kappa[sel] * (fky[sel] - fkb[sel])
                             - beta[sel] * 2 * self.W[k[sel]] * cj / self.cs2)
-                continue
-            # eq:abbcon / eq:abbnoncon: t* = value - pressure n; sigma* =
-            # Pi sigma_b Pi + n t* + t* n - (t*.n) n n, sigma_b and rho_bd at
-            # the site or extrapolated along the link (order 1, not thin)
-            sz, sy, sx, sq, sn = z[sel], y[sel], x[sel], q[sel], L["n"][sel]
+        sel = gd < 0
+        if sel.any():
+            # eq:abbcon / eq:abbnoncon.  sigma_b and rho_bd at the site or
+            # extrapolated along the link (order 1, not thin)
+            sz, sy, sx, sq = z[sel], y[sel], x[sel], q[sel]
             Ps = P[:, :, sz, sy, sx]                              # [3, 3, m]
             rs = rho[sz, sy, sx]
             sig = self._cauchy(rs, Ps)
@@ -374,12 +392,39 @@ class Oracle3D:
                 sig_y = self._cauchy(ry, Py)
                 sig = np.where(ext[None, None], (1 + sq) * sig - sq * sig_y, sig)
                 rbd = np.where(ext, (1 + sq) * rs - sq * ry, rs)
-            t = val[None, :] - pres * sn                           # [m, 3]
-            Pi = np.eye(3, dtype=self.dt)[:, :, None] - np.einsum("ma,mb->abm", sn, sn)
-            st = np.einsum("abm,bcm,cdm->adm", Pi, sig, Pi)
-            tn = np.einsum("ma,ma->m", t, sn)
-            st = st + np.einsum("ma,mb->abm", sn, t) + np.einsum("ma,mb->abm", t, sn) \
-                - tn[None, None] * np.einsum("ma,mb->abm", sn, sn)
+            gv = np.array([v for v, _ in self.gval], dtype=self.dt).reshape(-1, 3)
+            gp = np.array([pp for _, pp in self.gval], dtype=self.dt)
+            na, ga = L["n"][sel], g[sel]
+            ta = gv[ga] - gp[ga][:, None] * na                      # t* = value - pressure n
+            st = np.empty_like(sig)
+            one = g2[sel] < 0
+            if one.any():
+                # one face: sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n
+                n1, t1, s1 = na[one], ta[one], sig[:, :, one]
+                Pi = np.eye(3, dtype=self.dt)[:, :, None] - np.einsum("ma,mb->abm", n1, n1)
+                tn = np.einsum("ma,ma->m", t1, n1)
+                st[:, :, one] = (np.einsum("abm,bcm,cdm->adm", Pi, s1, Pi) + np.einsum("ma,mb->abm", n1, t1)
+                                 + np.einsum("ma,mb->abm", t1, n1) - tn[None, None] * np.einsum("ma,mb->abm", n1, n1))
+            if (~one).any():
+                # two faces meeting at an edge: in the frame (n_A, n_B, e =
+                # n_A x n_B) the tractions fix the rows of n_A and n_B (the
+                # shear between them averaged), the edge's own sigma_ee is
+                # sigma_b's
+                two = ~one
+                nA, tA, s2 = na[two], ta[two], sig[:, :, two]
+                gb = g2[sel][two]
+                nB = L["n2"][sel][two]
+                tB = gv[gb] - gp[gb][:, None] * nB
+                e = np.cross(nA, nB)
+                u = (nA, nB, e)
+                dot = lambda a_, b_: np.einsum("ma,ma->m", a_, b_)
+                S = {(0, 0): dot(tA, nA), (1, 1): dot(tB, nB), (0, 1): (dot(tA, nB) + dot(tB, nA)) / 2,
+                     (0, 2): dot(tA, e), (1, 2): dot(tB, e), (2, 2): np.einsum("ma,abm,mb->m", e, s2, e)}
+                acc = np.zeros_like(s2)
+                for (i_, j_), v_ in S.items():
+                    term = v_[None, None] * np.einsum("ma,mb->abm", u[i_], u[j_])
+                    acc = acc + (term if i_ == j_ else term + np.swapaxes(term, 0, 1))
+                st[:, :, two] = acc
             Pstar = -st
             for a in range(3):
                 Pstar[a, a] = Pstar[a, a] + (self.lam - self.mu) * (1.0 - rbd)

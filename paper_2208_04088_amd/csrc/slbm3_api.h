@@ -132,6 +132,17 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         if (L.group < 0 || L.group >= p->n_groups) return fail(SLBM_E_INVAL, "link %lld: group out of range", (long long)l);
         const double nn = std::sqrt(L.normal[0] * L.normal[0] + L.normal[1] * L.normal[1] + L.normal[2] * L.normal[2]);
         if (!(std::fabs(nn - 1.0) <= 1e-9)) return fail(SLBM_E_INVAL, "link %lld: normal is not a unit vector", (long long)l);
+        if (L.group2 < -1 || L.group2 >= p->n_groups)
+            return fail(SLBM_E_INVAL, "link %lld: second group out of range", (long long)l);
+        if (L.group2 >= 0) {
+            const double* m2 = L.normal2;
+            const double n2 = std::sqrt(m2[0] * m2[0] + m2[1] * m2[1] + m2[2] * m2[2]);
+            if (!(std::fabs(n2 - 1.0) <= 1e-9))
+                return fail(SLBM_E_INVAL, "link %lld: second normal is not a unit vector", (long long)l);
+            const double d = L.normal[0] * m2[0] + L.normal[1] * m2[1] + L.normal[2] * m2[2];
+            if (!(std::fabs(d) <= 1e-9))
+                return fail(SLBM_E_INVAL, "link %lld: the two faces' normals are not orthogonal", (long long)l);
+        }
         const uint32_t bit = 1u << (L.dir - 1);
         if (g.flags[L.site] & bit) return fail(SLBM_E_INVAL, "link %lld: listed twice", (long long)l);
         g.flags[L.site] |= bit;
@@ -207,7 +218,11 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
     for (size_t r = 0; r < order.size(); ++r) {
         const slbm3_link& L = p->links[order[r]];
         if (r == 0 || p->links[order[r - 1]].site != L.site) g.bidx[L.site] = (int32_t)r;
-        const slbm3_bc_group& gr = p->groups[L.group];
+        // a link through the edge of two faces: the Dirichlet face wins
+        const bool two = L.group2 >= 0;
+        const bool d1 = p->groups[L.group].kind == SLBM_DIRICHLET;
+        const bool d2 = two && p->groups[L.group2].kind == SLBM_DIRICHLET;
+        const slbm3_bc_group& gr = p->groups[(!d1 && d2) ? L.group2 : L.group];
         const int i = L.dir, ib = opp3(i);
         // section 4.2: no site behind x when the opposite link is cut too
         const bool thin = (g.flags[L.site] >> (ib - 1)) & 1u;
@@ -228,26 +243,51 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
             const double cv = (c[0] * gr.value[0] + c[1] * gr.value[1] + c[2] * gr.value[2]) / h->s_v;
             R.c0 = bet * 6.0 * w * cv;
         } else {
-            // the constants of e = c0 drho_bd + B:P_b - K (the record's comment)
+            // the constants of e = c0 drho_bd + B:P_b - K (the record's
+            // comment): sigma* = Pi sigma_b Pi + N, with N fixed by the
+            // traction(s).  One face: Pi = I - n n, N = n t + t n - (t.n) n n.
+            // Two faces (an edge): Pi = e e with e = n_A x n_B, and N holds the
+            // rows of n_A and n_B in the frame (n_A, n_B, e), their shear
+            // averaged.
             const double* n = L.normal;
-            double t[3], A[3][3], Pi[3][3], T[3][3], B0[3][3];
+            double t[3], A[3][3], Pi[3][3], N[3][3], T[3][3], B0[3][3];
             for (int k = 0; k < 3; ++k) t[k] = (gr.value[k] - gr.pressure * n[k]) / h->s_sigma;
             for (int u = 0; u < 3; ++u)
-                for (int v = 0; v < 3; ++v) {
-                    A[u][v] = c[u] * c[v] - (u == v ? 1.0 / 3.0 : 0.0);
-                    Pi[u][v] = (u == v ? 1.0 : 0.0) - n[u] * n[v];
-                }
+                for (int v = 0; v < 3; ++v) A[u][v] = c[u] * c[v] - (u == v ? 1.0 / 3.0 : 0.0);
+            if (!two) {
+                const double tn = t[0] * n[0] + t[1] * n[1] + t[2] * n[2];
+                for (int u = 0; u < 3; ++u)
+                    for (int v = 0; v < 3; ++v) {
+                        Pi[u][v] = (u == v ? 1.0 : 0.0) - n[u] * n[v];
+                        N[u][v] = n[u] * t[v] + t[u] * n[v] - tn * n[u] * n[v];
+                    }
+            } else {
+                const slbm3_bc_group& g2r = p->groups[L.group2];
+                const double* nb = L.normal2;
+                double tb[3];
+                for (int k = 0; k < 3; ++k) tb[k] = (g2r.value[k] - g2r.pressure * nb[k]) / h->s_sigma;
+                const double e[3] = {n[1] * nb[2] - n[2] * nb[1], n[2] * nb[0] - n[0] * nb[2], n[0] * nb[1] - n[1] * nb[0]};
+                auto dot = [](const double* a_, const double* b_) { return a_[0] * b_[0] + a_[1] * b_[1] + a_[2] * b_[2]; };
+                const double* u3[3] = {n, nb, e};
+                double S[3][3] = {{dot(t, n), 0.5 * (dot(t, nb) + dot(tb, n)), dot(t, e)},
+                                  {0.5 * (dot(t, nb) + dot(tb, n)), dot(tb, nb), dot(tb, e)},
+                                  {dot(t, e), dot(tb, e), 0.0}};
+                for (int u = 0; u < 3; ++u)
+                    for (int v = 0; v < 3; ++v) {
+                        Pi[u][v] = e[u] * e[v];
+                        double acc = 0.0;
+                        for (int X = 0; X < 3; ++X)
+                            for (int Y = 0; Y < 3; ++Y) acc += S[X][Y] * u3[X][u] * u3[Y][v];
+                        N[u][v] = acc;
+                    }
+            }
             for (int u = 0; u < 3; ++u)
                 for (int v = 0; v < 3; ++v) T[u][v] = A[u][0] * Pi[0][v] + A[u][1] * Pi[1][v] + A[u][2] * Pi[2][v];
             for (int u = 0; u < 3; ++u)
                 for (int v = 0; v < 3; ++v) B0[u][v] = Pi[u][0] * T[0][v] + Pi[u][1] * T[1][v] + Pi[u][2] * T[2][v];
-            double nAt = 0.0, nAn = 0.0;
+            double NA = 0.0;
             for (int u = 0; u < 3; ++u)
-                for (int v = 0; v < 3; ++v) {
-                    nAt += n[u] * A[u][v] * t[v];
-                    nAn += n[u] * A[u][v] * n[v];
-                }
-            const double tn = t[0] * n[0] + t[1] * n[1] + t[2] * n[2];
+                for (int v = 0; v < 3; ++v) NA += N[u][v] * A[u][v];
             const double trB = B0[0][0] + B0[1][1] + B0[2][2];
             const double lm = h->lamL - h->muL;
             R.c0 = w * (2.5 - 1.5 * c2) + 4.5 * w * lm * (trB - c2 + 1.0);
@@ -257,7 +297,7 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
             R.B[3] = 9.0 * w * B0[0][1];
             R.B[4] = 9.0 * w * B0[0][2];
             R.B[5] = 9.0 * w * B0[1][2];
-            R.K = 4.5 * w * (2.0 * nAt - tn * nAn);
+            R.K = 4.5 * w * NA;
         }
         const int ext = gr.kind == SLBM_NEUMANN && h->norder == 1 && !thin ? 1 : 0;
         R.meta = link3_meta(i, ib, gr.kind, ext, kCX[i], kCY[i], kCZ[i]);

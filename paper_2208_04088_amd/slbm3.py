@@ -21,7 +21,7 @@ class Wall(C.Structure):
 
 class Link(C.Structure):
     _fields_ = [("site", C.c_int32), ("dir", C.c_int32), ("q", C.c_double), ("group", C.c_int32),
-                ("normal", C.c_double * 3)]
+                ("normal", C.c_double * 3), ("group2", C.c_int32), ("normal2", C.c_double * 3)]
 
 
 class BCGroup(C.Structure):
@@ -73,7 +73,7 @@ def lib():
     return L
 
 
-LINK_FIELDS = ("site", "dir", "q", "group", "normal")
+LINK_FIELDS = ("site", "dir", "q", "group", "normal", "group2", "normal2")
 
 
 def marshal(box, precision=S.FP32, device=0, stream=None):
@@ -97,9 +97,11 @@ def marshal(box, precision=S.FP32, device=0, stream=None):
         if mask.shape != (box.nz, box.ny, box.nx):
             raise ValueError("mask shape must be (nz, ny, nx)")
         links = np.zeros(0 if box.links is None else len(box.links), dtype=Link)
+        links["group2"] = -1
         if box.links is not None:
             for f in LINK_FIELDS:
-                links[f] = box.links[f]
+                if f in box.links.dtype.names:
+                    links[f] = box.links[f]
         groups = (BCGroup * max(1, len(box.groups or [])))()
         for k, g in enumerate(box.groups or []):
             groups[k] = BCGroup(int(g.kind), (C.c_double * 3)(*g.value), float(getattr(g, "pressure", 0.0)))

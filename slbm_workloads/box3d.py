@@ -110,8 +110,22 @@ C3 = np.array([[0, 0, 0],
                [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1],
                [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=np.int64)
 
+# one cut link: its site, direction, q, group and outward normal; a link
+# through the edge where two faces meet carries the second face's group and
+# normal too (group2 = -1: none)
 LINK3_DTYPE = np.dtype([("site", "<i4"), ("dir", "<i4"), ("q", "<f8"), ("group", "<i4"),
-                        ("normal", "<f8", (3,))], align=True)
+                        ("normal", "<f8", (3,)), ("group2", "<i4"), ("normal2", "<f8", (3,))], align=True)
+
+
+def link_records3(rows):
+    """LINK3_DTYPE records from (site, dir, q, group, normal) tuples, sorted
+    by site and direction, with no second group."""
+    rows = sorted(rows, key=lambda r: (r[0], r[1]))
+    rec = np.zeros(len(rows), dtype=LINK3_DTYPE)
+    for k, (site, d, q, g, n) in enumerate(rows):
+        rec[k]["site"], rec[k]["dir"], rec[k]["q"], rec[k]["group"], rec[k]["normal"] = site, d, q, g, n
+    rec["group2"] = -1
+    return rec
 
 
 def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0,
@@ -160,6 +174,7 @@ def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho
         rec["q"] = t
         rec["group"] = grp[k]
         rec["normal"] = n
+        rec["group2"] = -1
         parts.append(rec)
     for ck in cracks:
         if not (ck.R < ck.cx < nx - 1 - ck.R and ck.R < ck.cy < ny - 1 - ck.R and 0 < ck.zc < nz - 1
@@ -181,11 +196,70 @@ def sphere_box3(nx, ny, nz, spheres, groups, *, lam=0.05, mu=0.05, tau=0.55, rho
             rec["q"] = t
             rec["group"] = ck.lower if c[2] > 0 else ck.upper
             rec["normal"] = (0.0, 0.0, float(c[2]))
+            rec["group2"] = -1
             parts.append(rec)
     links = np.concatenate(parts) if parts else np.zeros(0, dtype=LINK3_DTYPE)
     links = links[np.lexsort((links["dir"], links["site"]))]
     return Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, rho=rho, force=tuple(force), name=name or
                 f"spheres{nx}x{ny}x{nz}", steps=steps, neumann_order=neumann_order, mask=mask, links=links,
+                groups=list(groups))
+
+
+def block_box3(nx, ny, nz, lo, hi, face_groups, groups, *, lam=0.05, mu=0.05, tau=0.55, rho=1.0,
+               force=(0.0, 0.0, 0.0), neumann_order=0, name="", steps=0) -> Box3:
+    """A rectangular block of material, sites lo..hi (inclusive, (x, y, z)),
+    in a box periodic on every axis with void around it (at least one site
+    on every side).  Its six faces are the lattice-conforming planes half a
+    link beyond its outer sites (q = 1/2), each with a group: face_groups
+    in the order -x, +x, -y, +y, -z, +z.  A link from an edge site that
+    leaves through two faces (a face diagonal at the block's edge) crosses
+    both at once, at the edge: it carries both faces' groups and normals."""
+    lo, hi = np.asarray(lo), np.asarray(hi)
+    if not ((lo >= 1).all() and (hi <= np.array([nx, ny, nz]) - 2).all() and (lo <= hi).all()):
+        raise ValueError("the block must leave void on every side")
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] = 1
+    z, y, x = np.nonzero(mask)
+    p = np.stack([x, y, z], axis=1)
+    parts = []
+    for i in range(1, len(C3)):
+        c = C3[i]
+        # the faces the link leaves through, per axis
+        leaves = np.zeros((len(p), 3), dtype=bool)
+        for a in range(3):
+            if c[a] > 0:
+                leaves[:, a] = p[:, a] == hi[a]
+            elif c[a] < 0:
+                leaves[:, a] = p[:, a] == lo[a]
+        cut = leaves.any(axis=1)
+        if not cut.any():
+            continue
+        L = leaves[cut]
+        rec = np.zeros(int(cut.sum()), dtype=LINK3_DTYPE)
+        rec["site"] = (z[cut] * ny + y[cut]) * nx + x[cut]
+        rec["dir"] = i
+        rec["q"] = 0.5
+        rec["group2"] = -1
+        first = np.full(len(rec), -1)
+        for a in range(3):
+            if c[a] == 0:
+                continue
+            side = 1 if c[a] > 0 else 0
+            nrm = np.zeros(3)
+            nrm[a] = 1.0 if side else -1.0
+            g = face_groups[2 * a + side]
+            sel1 = L[:, a] & (first < 0)
+            sel2 = L[:, a] & (first >= 0)
+            rec["group"][sel1] = g
+            rec["normal"][sel1] = nrm
+            first[sel1] = a
+            rec["group2"][sel2] = g
+            rec["normal2"][sel2] = nrm
+        parts.append(rec)
+    links = np.concatenate(parts)
+    links = links[np.lexsort((links["dir"], links["site"]))]
+    return Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, rho=rho, force=tuple(force), name=name or
+                f"block{nx}x{ny}x{nz}", steps=steps, neumann_order=neumann_order, mask=mask, links=links,
                 groups=list(groups))
 
 

@@ -185,6 +185,10 @@ def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_
     q = float(L["q"])
     n = [float(v) for v in L["normal"]]
     G = box.groups[int(L["group"])]
+    g2 = int(L["group2"]) if "group2" in L.dtype.names else -1
+    G2 = box.groups[g2] if g2 >= 0 else None
+    if G.kind != DIRICHLET and G2 is not None and G2.kind == DIRICHLET:
+        G = G2                       # an edge of a Dirichlet and a Neumann face: Dirichlet
     cb = tuple(-a for a in c)
     fc = fcol[idx[c], z, y, x]
     fcb = fcol[idx[cb], z, y, x]
@@ -218,9 +222,24 @@ def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_
         sig = [[(1 + q) * sig[a][b] - q * sb[a][b] for b in range(3)] for a in range(3)]
         rbd = (1 + q) * r - q * rb
     t = [G.value[a] / s_sigma - G.pressure / s_sigma * n[a] for a in range(3)]
-    tn = sum(t[a] * n[a] for a in range(3))
-    Pi = [[(a == b) - n[a] * n[b] for b in range(3)] for a in range(3)]
-    st = [[sum(Pi[a][e] * sig[e][f] * Pi[f][b] for e in range(3) for f in range(3))
-           + n[a] * t[b] + t[a] * n[b] - tn * n[a] * n[b] for b in range(3)] for a in range(3)]
+    if G2 is None:
+        tn = sum(t[a] * n[a] for a in range(3))
+        Pi = [[(a == b) - n[a] * n[b] for b in range(3)] for a in range(3)]
+        st = [[sum(Pi[a][e] * sig[e][f] * Pi[f][b] for e in range(3) for f in range(3))
+               + n[a] * t[b] + t[a] * n[b] - tn * n[a] * n[b] for b in range(3)] for a in range(3)]
+    else:
+        # an edge of two Neumann faces: in the basis (n, n2, e = n x n2), the
+        # rows of n and n2 from the tractions (their shear averaged), the
+        # edge component from the material
+        n2 = [float(v) for v in L["normal2"]]
+        t2 = [G2.value[a] / s_sigma - G2.pressure / s_sigma * n2[a] for a in range(3)]
+        e = [n[1] * n2[2] - n[2] * n2[1], n[2] * n2[0] - n[0] * n2[2], n[0] * n2[1] - n[1] * n2[0]]
+        d = lambda u, v: sum(u[a] * v[a] for a in range(3))
+        basis = [n, n2, e]
+        comp = [[d(t, n), (d(t, n2) + d(t2, n)) / 2, d(t, e)],
+                [(d(t, n2) + d(t2, n)) / 2, d(t2, n2), d(t2, e)],
+                [d(t, e), d(t2, e), sum(e[a] * sig[a][b] * e[b] for a in range(3) for b in range(3))]]
+        st = [[sum(comp[i][j] * basis[i][a] * basis[j][b] for i in range(3) for j in range(3)) for b in range(3)]
+              for a in range(3)]
     Ps = [[-st[a][b] + (lamL - muL) * (1 - rbd) * (a == b) for b in range(3)] for a in range(3)]
     return -fc - kap * (fb + fcb) + bet * 2 * _feq(c, rbd, [0.0, 0.0, 0.0], Ps)

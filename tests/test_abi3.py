@@ -60,7 +60,7 @@ def test_struct_layout_matches_header(tmp_path):
     for f, _ in S3.Params3._fields_:
         assert int(out[f"slbm3_params.{f}"]) == getattr(S3.Params3, f).offset, f
     # the link records are the workloads' LINK3_DTYPE, byte for byte
-    assert int(out["slbm3_link"]) == C.sizeof(S3.Link) == B.LINK3_DTYPE.itemsize == 48
+    assert int(out["slbm3_link"]) == C.sizeof(S3.Link) == B.LINK3_DTYPE.itemsize == 80
     for f, _ in S3.Link._fields_:
         assert int(out[f"slbm3_link.{f}"]) == getattr(S3.Link, f).offset == B.LINK3_DTYPE.fields[f][1], f
     assert int(out["slbm3_bc_group"]) == C.sizeof(S3.BCGroup)
@@ -184,7 +184,28 @@ def test_one_sided_crack_is_rejected_on_the_host():
     assert rc == -1 and "link back" in msg, (rc, msg)
 
 
-@pytest.mark.parametrize("make", [_cavity, _cracked])
+def _block():
+    return B.block_box3(9, 8, 7, (2, 2, 2), (6, 5, 4), list(range(6)),
+                        [B.BCGroup3(B.NEUMANN)] * 3 + [B.BCGroup3(B.DIRICHLET)] * 3)
+
+
+@pytest.mark.parametrize("case", ["group2_range", "normal2_unit", "normal2_skew"])
+def test_invalid_edge_links_are_rejected_on_the_host(case):
+    box = _block()
+    edge = int(np.flatnonzero(box.links["group2"] >= 0)[0])
+    if case == "group2_range":
+        _set(box, "group2", edge, 6)
+    elif case == "normal2_unit":
+        _set(box, "normal2", edge, (0.0, 1.1, 0.0))
+    else:
+        n = box.links["normal"][edge]
+        m = box.links["normal2"][edge]
+        _set(box, "normal2", edge, tuple((m + 0.5 * n) / np.linalg.norm(m + 0.5 * n)))
+    rc, msg = _create(box)
+    assert rc == -1 and msg, (case, rc, msg)
+
+
+@pytest.mark.parametrize("make", [_cavity, _cracked, _block])
 def test_valid_geometry_without_a_gpu_fails_loudly(make):
     """A valid cavity, or cavity and crack, passes the host checks and then
     fails for want of a device."""

@@ -292,9 +292,10 @@ def test_pressurised_cavity_holds_its_hydrostatic_state(S3):
                         lam=0.1, mu=0.05, tau=0.6, neumann_order=1)
     sig = np.zeros((6, box.nz, box.ny, box.nx))
     sig[:3] = -p
+    rho0 = np.full((box.nz, box.ny, box.nx), 1.0 + 3e-4)     # the lambda - mu terms act on drho
     with S3.Solver3(box, "fp64") as s:
-        s.init_fields(sigma=sig)
-        s.step(30)
+        s.init_fields(rho=rho0, sigma=sig)
+        s.step(12)
         s.sync()
         rho, j, P, sg = s.moments()
     mk = box.mask.astype(bool)
@@ -415,3 +416,48 @@ def test_narrow_box_with_cut_links(S3, prec, tol, steps):
     fields = dict(vel=B.random_velocity(box, 61, 1e-3))
     out, ref = run_both(S3, box, prec, steps, fields)
     check(out, ref, tol, f"narrow box {prec}", box)
+
+
+def _block(order):
+    """A 64 x 9 x 8 block in a 70 x 13 x 12 box (ragged rows, a partial last
+    workgroup), one group per face: clamped and moving Dirichlet faces,
+    loaded and free Neumann faces; its edges carry two faces' groups."""
+    groups = [B.BCGroup3(B.DIRICHLET, (2e-4, 0.0, 0.0)), B.BCGroup3(B.NEUMANN, (3e-5, 0.0, 0.0)),
+              B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN, (0.0, 1e-5, 2e-5), 5e-5),
+              B.BCGroup3(B.NEUMANN), B.BCGroup3(B.DIRICHLET)]
+    return B.block_box3(70, 13, 12, (3, 2, 2), (66, 10, 9), list(range(6)), groups, lam=0.05, mu=0.05, tau=0.7,
+                        force=(0.0, 1e-6, 0.0), neumann_order=order)
+
+
+@pytest.mark.parametrize("prec,tol,order,steps", [("fp64", FP64_TOL, 0, 40), ("fp64", FP64_TOL, 1, 40),
+                                                  ("fp32", FP32_TOL, 0, 300), ("fp32", FP32_TOL, 1, 60)])
+def test_block_with_edges(S3, prec, tol, order, steps):
+    box = _block(order)
+    assert (box.links["group2"] >= 0).sum() > 100
+    fields = dict(vel=B.random_velocity(box, 71, 1e-3) * box.mask)
+    out, ref = run_both(S3, box, prec, steps, fields)
+    check(out, ref, tol, f"block {prec} order {order}", box)
+
+
+def test_block_holds_a_uniform_stress_on_the_gpu(S3):
+    """The oracle's block patch test on the GPU (fp64, order 1, 12 steps, at
+    lambda/mu = 1.3 so that the lambda - mu terms of the edge rule count):
+    faces and edges loaded by sigma.n keep the uniform stress sigma.  (The
+    extrapolated rule's free-wall mode amplifies rounding quickly above
+    lambda = mu, in the reference as here, hence the short run.)"""
+    sig3 = np.array([[3e-4, 1e-4, -2e-4], [1e-4, -1e-4, 1.5e-4], [-2e-4, 1.5e-4, 2e-4]])
+    faces = [(-1.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, -1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, -1.0), (0.0, 0.0, 1.0)]
+    groups = [B.BCGroup3(B.NEUMANN, tuple(sig3 @ np.array(n))) for n in faces]
+    box = B.block_box3(70, 13, 12, (3, 2, 2), (66, 10, 9), list(range(6)), groups, lam=0.065, mu=0.05, tau=0.6,
+                       neumann_order=1)
+    sig = np.zeros((6, box.nz, box.ny, box.nx))
+    for k, (i, j) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        sig[k] = sig3[i, j]
+    with S3.Solver3(box, "fp64") as s:
+        s.init_fields(sigma=sig)
+        s.step(30)
+        s.sync()
+        rho, j, P, sg = s.moments()
+    mk = box.mask.astype(bool)
+    assert np.abs(sg[:, mk] - sig[:, mk]).max() < 1e-12
+    assert np.abs(j[:, mk]).max() < 1e-13

@@ -388,7 +388,7 @@ def _planes_as_links(nx, ny, nz, walls, order, lam=0.09, mu=0.05, tau=0.6):
                     if C[i, 0] == (-1 if side == 0 else 1):
                         recs.append(((z * ny + y) * NX + x, i, walls[side].q, side,
                                      (-1.0 if side == 0 else 1.0, 0.0, 0.0)))
-    links = np.array(sorted(recs, key=lambda r: (r[0], r[1])), dtype=B.LINK3_DTYPE)
+    links = B.link_records3(recs)
     groups = [B.BCGroup3(w.kind, w.value) for w in walls]
     return B.Box3(NX, ny, nz, lam=lam, mu=mu, tau=tau, mask=mask, links=links, groups=groups,
                   neumann_order=order)
@@ -496,7 +496,7 @@ def _plane_crack(nx, ny, nz, walls, order, lam=0.09, mu=0.05, tau=0.6):
                     if C[i, 0] == (-1 if side == 0 else 1):
                         recs.append(((z * ny + y) * nx + x, i, walls[side].q, side,
                                      (-1.0 if side == 0 else 1.0, 0.0, 0.0)))
-    links = np.array(sorted(recs, key=lambda r: (r[0], r[1])), dtype=B.LINK3_DTYPE)
+    links = B.link_records3(recs)
     groups = [B.BCGroup3(w.kind, w.value) for w in walls]
     return B.Box3(nx, ny, nz, lam=lam, mu=mu, tau=tau, mask=mask, links=links, groups=groups,
                   neumann_order=order)
@@ -591,6 +591,79 @@ def test_one_sided_crack_is_refused():
     b.links = lower                                  # the upper face missing
     with pytest.raises(ValueError):
         Oracle3D(b)
+
+
+FACES = [(-1.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, -1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, -1.0), (0.0, 0.0, 1.0)]
+
+
+def _block(groups, order, lam=0.065):
+    """A 5 x 4 x 4 block in an 8 x 7 x 7 periodic box, one group per face."""
+    return B.block_box3(8, 7, 7, (1, 2, 1), (5, 5, 4), list(range(6)), groups, lam=lam, mu=0.05, tau=0.6,
+                        neumann_order=order)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_block_holds_a_uniform_stress(order):
+    """Patch test of the rules on a block's faces, edges included: every face
+    loaded by the traction sigma.n of one uniform stress sigma (all six
+    components non-zero) keeps that stress exactly.  At the edges the links
+    carry two faces' groups and normals; a wrong combination of the two
+    tractions (their shear, or the edge's own component) disturbs it by the
+    order of sigma."""
+    sig3 = np.array([[3e-4, 1e-4, -2e-4], [1e-4, -1e-4, 1.5e-4], [-2e-4, 1.5e-4, 2e-4]])
+    groups = [B.BCGroup3(B.NEUMANN, tuple(sig3 @ np.array(n))) for n in FACES]
+    b = _block(groups, order)
+    assert (b.links["group2"] >= 0).sum() > 20
+    o = Oracle3D(b)
+    sig = np.zeros((6,) + o.shape)
+    for k, (i, j) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        sig[k] = sig3[i, j]
+    # a uniform density change too: the (lambda - mu) drho terms of the rules
+    o.init_fields(rho=np.full(o.shape, 1.0 + 3e-4), sigma=sig)
+    o.step(8)
+    m = o.moments()
+    mk = b.mask.astype(bool)
+    assert np.abs(m[3][:, mk] - sig[:, mk]).max() < 1e-13
+    assert np.abs(m[1][:, mk]).max() < 1e-13
+
+
+def test_block_with_a_moving_face_translates():
+    """A block moving at v0 with one Dirichlet face (wall velocity v0) and
+    five traction-free faces keeps its uniform translation: at the edges of
+    the moving face the Dirichlet face wins."""
+    v0 = np.array([2e-4, -1e-4, 3e-4])
+    groups = [B.BCGroup3(B.DIRICHLET, tuple(v0))] + [B.BCGroup3(B.NEUMANN)] * 5
+    b = _block(groups, 0)
+    o = Oracle3D(b)
+    o.init_fields(vel=np.broadcast_to(v0[:, None, None, None], (3,) + o.shape))
+    o.step(7)
+    rho, j, P, sg = o.moments()
+    mk = b.mask.astype(bool)
+    assert np.abs(j[:, mk] - v0[:, None]).max() < 1e-13
+    assert np.abs(sg[:, mk]).max() < 1e-13
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_brute_force_loops_with_a_block(order):
+    """One step of a block with faces of both kinds, loaded and moving (edges
+    of two Neumann faces, of two Dirichlet faces and of one of each) against
+    the per-site loop form."""
+    groups = [B.BCGroup3(B.NEUMANN, (1e-4, -2e-4, 5e-5), pressure=3e-4), B.BCGroup3(B.DIRICHLET, (1e-3, 0.0, -1e-3)),
+              B.BCGroup3(B.NEUMANN, (0.0, 2e-4, 1e-4)), B.BCGroup3(B.DIRICHLET, (-1e-3, 2e-3, 0.0)),
+              B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN, (3e-4, 0.0, 0.0), pressure=-1e-4)]
+    b = B.block_box3(6, 6, 6, (1, 1, 1), (4, 3, 4), list(range(6)), groups, lam=0.09, mu=0.05, tau=0.6,
+                     force=(1e-5, 0.0, -2e-5), neumann_order=order)
+    rng = np.random.default_rng(13)
+    o = Oracle3D(b)
+    f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
+    f[:, ~b.mask.astype(bool)] = o.populations()[:, ~b.mask.astype(bool)]
+    o.set_populations(f)
+    U0 = rng.normal(size=(3,) + o.shape) * b.mask
+    o.U = U0.copy()
+    o.step(1)
+    fn, Un = naive_step(b, f, U0, [tuple(int(a) for a in c) for c in C])
+    assert np.abs(o.populations() - fn).max() < 1e-14
+    assert np.abs(o.U - Un).max() < 1e-14
 
 
 def test_inconsistent_cut_links_are_refused():
