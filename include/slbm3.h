@@ -27,8 +27,10 @@
  *   (neumann_order 0) or extrapolated along the link from the site behind,
  *   (1 + q) X(x) - q X(x - c_i) (neumann_order 1, the paper's form).  The
  *   rules at q != 1/2 read the population at x - c_i, the next site inward;
- *   a one-site-wide slab has none and takes kappa = 0, beta = 1.  Both
- *   walls apply from the first step.
+ *   a one-site-wide slab has none and takes kappa = 0, beta = 1.  A wall's or
+ *   group's value is on from the first step (SLBM_PROFILE_STEP) or ramped,
+ *   scaled by min(t_n / ramp_time, 1) where t_n is the time of the
+ *   post-collision state the rule reads (the rule that completes step n + 1).
  *
  *   Directions c_i (D3Q19): 0 rest; 1-6 +x -x +y -y +z -z; 7-10 (1,1,0)
  *   (-1,-1,0) (1,-1,0) (-1,1,0); 11-14 (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1);
@@ -77,6 +79,8 @@ typedef struct {
     int32_t kind;                /* SLBM_DIRICHLET (value: wall velocity) or SLBM_NEUMANN (value: traction) */
     double value[3];             /* user units */
     double q;                    /* fraction of a cut link inside the material, (0, 1]; 1/2: lattice-conforming */
+    int32_t profile;             /* SLBM_PROFILE_STEP (on from t = 0) or SLBM_PROFILE_RAMP */
+    double ramp_time;            /* RAMP: value scaled by min(t / ramp_time, 1), user units, > 0 */
 } slbm3_wall;
 
 /* One cut link of a general geometry (80 bytes): the link from the material
@@ -102,6 +106,8 @@ typedef struct {
     int32_t kind;                /* SLBM_DIRICHLET (value: wall velocity) or SLBM_NEUMANN */
     double value[3];             /* Dirichlet: wall velocity; Neumann: traction, t* = value - pressure n */
     double pressure;             /* Neumann: uniform pressure on the boundary (0: none); ignored for Dirichlet */
+    int32_t profile;             /* SLBM_PROFILE_STEP or SLBM_PROFILE_RAMP (value and pressure scaled) */
+    double ramp_time;            /* RAMP: min(t / ramp_time, 1), user units, > 0 */
 } slbm3_bc_group;
 
 typedef struct {
@@ -129,7 +135,9 @@ typedef struct {
  * SLBM_E_INVAL also names the first invalid link: a site out of range or
  * void, a direction out of 1..18, q outside (0, 1], a group out of range, a
  * normal that is not a unit vector (to 1e-9), a second group out of range
- * or its normal not a unit vector orthogonal to the first, a link listed twice, a link
+ * or its normal not a unit vector orthogonal to the first, the two faces of
+ * an edge with different time profiles, more than 15 distinct ramp times, a
+ * bad profile or a ramp time that is not positive, a link listed twice, a link
  * into the material whose link back is not listed, or a link from the
  * material into the void that is not listed; and an invalid group kind.
  * The arrays are copied. */

@@ -48,6 +48,8 @@ import numpy as np
 
 DIRICHLET = 1
 NEUMANN = 2
+STEP = 0
+RAMP = 1
 
 # D3Q19: rest, the six axis links, the twelve face diagonals
 C = np.array([[0, 0, 0],
@@ -137,6 +139,7 @@ class Oracle3D:
                 scale = self.s_v if wall.kind == DIRICHLET else self.s_sigma
                 self.walls.append((wall.kind, np.array(wall.value, dtype=self.dt) / self.dt(scale),
                                    self.dt(wall.q)))
+            self.wprof = [self._profile_of(w) for w in b.x_walls]
         # cut[i] marks the sites whose link i leaves the material through a wall
         self.cut = np.zeros((Q,) + self.shape, dtype=bool)
         if self.walls is not None:
@@ -208,6 +211,7 @@ class Oracle3D:
         self.links = dict(z=z, y=y, x=x, k=k, q=q.astype(self.dt), g=g, n=n.astype(self.dt), g2=g2,
                           n2=n2.astype(self.dt))
         self.gkind = np.array([g.kind for g in b.groups])
+        self.gprof = [self._profile_of(g) for g in b.groups]
         self.gval = []
         for g in b.groups:
             if g.kind not in (DIRICHLET, NEUMANN):
@@ -215,6 +219,21 @@ class Oracle3D:
             scale = self.s_v if g.kind == DIRICHLET else self.s_sigma
             self.gval.append((np.array(g.value, dtype=self.dt) / self.dt(scale),
                               self.dt(getattr(g, "pressure", 0.0)) / self.dt(self.s_sigma)))
+
+    def _profile_of(self, w):
+        """(profile, ramp length in steps) of a wall or group."""
+        prof = getattr(w, "profile", STEP)
+        if prof == STEP:
+            return (STEP, self.dt(1))
+        if prof != RAMP or not getattr(w, "ramp_time", 0.0) > 0:
+            raise ValueError("a profile is STEP, or RAMP with a positive ramp time")
+        return (RAMP, self.dt(w.ramp_time) / self.dt(self.dt_user))
+
+    def _factor(self, prof):
+        """The profile's factor at the current step n (the rule applied to the
+        post-collision state of step n takes the value at t_n = n dt)."""
+        kind, T = prof
+        return self.dt(1) if kind == STEP else min(self.dt(self.n) / T, self.dt(1))
 
     # -------------------------------------------------------------- steps
     def _moments(self, f):
@@ -294,6 +313,7 @@ class Oracle3D:
         nx = self.shape[2]
         behind = nx >= 2
         for side, (kind, value, q) in enumerate(self.walls):
+            value = value * self._factor(self.wprof[side])
             xs = 0 if side == 0 else -1
             normal = np.array([-1.0, 0.0, 0.0]) if side == 0 else np.array([1.0, 0.0, 0.0])
             kappa = (1 - 2 * q) / (1 + 2 * q) if behind else self.dt(0)
@@ -365,11 +385,12 @@ class Oracle3D:
         r = rho[z, y, x]
         c = C[k].astype(self.dt)                                   # [m, 3]
         out = np.empty_like(fk)
+        gvals = [(v * self._factor(pf), pp * self._factor(pf)) for (v, pp), pf in zip(self.gval, self.gprof)]
         g, g2 = L["g"], L["g2"]
         dirichlet = self.gkind == DIRICHLET
         # where two faces meet on the link (an edge), the Dirichlet face wins
         gd = np.where(dirichlet[g], g, np.where((g2 >= 0) & dirichlet[np.maximum(g2, 0)], g2, -1))
-        for gi, (val, pres) in enumerate(self.gval):
+        for gi, (val, pres) in enumerate(gvals):
             sel = gd == gi
             if sel.any():
                 # eq:bbcon / eq:bbnoncon with j* = rho(x) v*
@@ -392,8 +413,8 @@ class Oracle3D:
                 sig_y = self._cauchy(ry, Py)
                 sig = np.where(ext[None, None], (1 + sq) * sig - sq * sig_y, sig)
                 rbd = np.where(ext, (1 + sq) * rs - sq * ry, rs)
-            gv = np.array([v for v, _ in self.gval], dtype=self.dt).reshape(-1, 3)
-            gp = np.array([pp for _, pp in self.gval], dtype=self.dt)
+            gv = np.array([v for v, _ in gvals], dtype=self.dt).reshape(-1, 3)
+            gp = np.array([pp for _, pp in gvals], dtype=self.dt)
             na, ga = L["n"][sel], g[sel]
             ta = gv[ga] - gp[ga][:, None] * na                      # t* = value - pressure n
             st = np.empty_like(sig)

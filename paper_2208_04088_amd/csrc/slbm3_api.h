@@ -17,6 +17,10 @@ struct slbm3_s {
     int wkind[2] = {0, 0};
     double wval[2][3] = {{0, 0, 0}, {0, 0, 0}};   // lattice units
     double wq[2] = {0.5, 0.5};
+    // time profiles: the walls' (RAMP: ramp length in steps, else 0) and the
+    // general geometry's ramp slots (slot 0: constant)
+    double wramp[2] = {0.0, 0.0};
+    double slot_ramp[slbm3_dev::kProfileSlots3] = {};
     int norder = 0;
     double lamL = 0, muL = 1.0 / 3.0, tau = 0.55, FL[3] = {0, 0, 0};
     double dt_user = 1, s_sigma = 1, s_v = 1, rho_user = 1;
@@ -60,9 +64,17 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
     a.px = h->px;
     a.local = h->local ? 1 : 0;
     a.ntiles = ((h->nx + 63) / 64) * h->ny * h->nz;
+    // time profiles at the step of the state the pulls read (the previous
+    // step's post-collision state) and of the state this step produces
+    const double n_pull = h->step >= 1 ? (double)(h->step - 1) : 0.0, n_next = (double)h->step;
+    auto ramp = [](double n, double len) { return len > 0.0 ? std::min(n / len, 1.0) : 1.0; };
+    for (int k = 0; k < kProfileSlots3; ++k) {
+        a.pf_pull[k] = (real)ramp(n_pull, h->slot_ramp[k]);
+        a.pf_next[k] = (real)ramp(n_next, h->slot_ramp[k]);
+    }
     for (int s = 0; s < 2; ++s) {
         a.wkind[s] = h->wkind[s];
-        for (int k = 0; k < 3; ++k) a.wval[s][k] = (real)h->wval[s][k];
+        for (int k = 0; k < 3; ++k) a.wval[s][k] = (real)(h->wval[s][k] * ramp(n_pull, h->wramp[s]));
         // section 4.2: a site behind x along the cut link exists unless nx = 1
         const bool behind = h->nx >= 2;
         const double q = h->wq[s];
@@ -90,6 +102,8 @@ Step3Args<real> make_args3(const slbm3_s* h, int src)
 // and the records sorted by site and direction, in lattice units.  Validates
 // what slbm3_create documents; the host arrays are the caller's.
 struct Geo3 {
+    std::vector<int> gslot;          // per group: its time-profile slot
+    std::vector<double> slot_ramp;   // per slot: ramp length in steps (0: constant)
     std::vector<uint32_t> flags;
     std::vector<int32_t> bidx;
     std::vector<Link3<double>> recs;
@@ -114,6 +128,28 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         if (!std::isfinite(gr.value[0]) || !std::isfinite(gr.value[1]) || !std::isfinite(gr.value[2]) ||
             !std::isfinite(gr.pressure))
             return fail(SLBM_E_INVAL, "group %d: values must be finite", k);
+        if (gr.profile != SLBM_PROFILE_STEP && gr.profile != SLBM_PROFILE_RAMP)
+            return fail(SLBM_E_INVAL, "group %d: profile must be SLBM_PROFILE_STEP or SLBM_PROFILE_RAMP", k);
+        if (gr.profile == SLBM_PROFILE_RAMP && !(gr.ramp_time > 0.0))
+            return fail(SLBM_E_INVAL, "group %d: ramp time must be positive", k);
+    }
+    // each group's time-profile slot: 0 for STEP, one slot per distinct ramp time
+    g.gslot.assign((size_t)p->n_groups, 0);
+    g.slot_ramp.assign(kProfileSlots3, 0.0);
+    {
+        int nslots = 1;
+        for (int k = 0; k < p->n_groups; ++k) {
+            if (p->groups[k].profile != SLBM_PROFILE_RAMP) continue;
+            const double len = p->groups[k].ramp_time / h->dt_user;
+            int sl = 1;
+            while (sl < nslots && g.slot_ramp[(size_t)sl] != len) ++sl;
+            if (sl == nslots) {
+                if (nslots == kProfileSlots3)
+                    return fail(SLBM_E_UNSUPPORTED, "more than %d distinct ramp times", kProfileSlots3 - 1);
+                g.slot_ramp[(size_t)nslots++] = len;
+            }
+            g.gslot[(size_t)k] = sl;
+        }
     }
     g.flags.assign((size_t)n, 0u);
     for (long long s = 0; s < n; ++s)
@@ -142,6 +178,8 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
             const double d = L.normal[0] * m2[0] + L.normal[1] * m2[1] + L.normal[2] * m2[2];
             if (!(std::fabs(d) <= 1e-9))
                 return fail(SLBM_E_INVAL, "link %lld: the two faces' normals are not orthogonal", (long long)l);
+            if (g.gslot[(size_t)L.group] != g.gslot[(size_t)L.group2])
+                return fail(SLBM_E_INVAL, "link %lld: the two faces of an edge need the same time profile", (long long)l);
         }
         const uint32_t bit = 1u << (L.dir - 1);
         if (g.flags[L.site] & bit) return fail(SLBM_E_INVAL, "link %lld: listed twice", (long long)l);
@@ -300,7 +338,7 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
             R.K = 4.5 * w * NA;
         }
         const int ext = gr.kind == SLBM_NEUMANN && h->norder == 1 && !thin ? 1 : 0;
-        R.meta = link3_meta(i, ib, gr.kind, ext, kCX[i], kCY[i], kCZ[i]);
+        R.meta = link3_meta(i, ib, gr.kind, ext, kCX[i], kCY[i], kCZ[i], g.gslot[(size_t)(&gr - p->groups)]);
         R.site = L.site;
         g.skap[r] = ext ? 0.0 : (gr.kind == SLBM_DIRICHLET ? kap : -kap);
         if (ext) g.elink.push_back((int32_t)r);
@@ -461,6 +499,10 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
                     return fail(SLBM_E_INVAL, "wall %d: kind must be SLBM_DIRICHLET or SLBM_NEUMANN", s);
                 if (!(p->walls[s].q > 0.0 && p->walls[s].q <= 1.0))
                     return fail(SLBM_E_INVAL, "wall %d: q must be in (0, 1]", s);
+                if (p->walls[s].profile != SLBM_PROFILE_STEP && p->walls[s].profile != SLBM_PROFILE_RAMP)
+                    return fail(SLBM_E_INVAL, "wall %d: profile must be SLBM_PROFILE_STEP or SLBM_PROFILE_RAMP", s);
+                if (p->walls[s].profile == SLBM_PROFILE_RAMP && !(p->walls[s].ramp_time > 0.0))
+                    return fail(SLBM_E_INVAL, "wall %d: ramp time must be positive", s);
             }
         }
         slbm3_s* h = new (std::nothrow) slbm3_s();
@@ -487,6 +529,7 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
                 const double scale = p->walls[s].kind == SLBM_DIRICHLET ? h->s_v : h->s_sigma;
                 for (int k = 0; k < 3; ++k) h->wval[s][k] = p->walls[s].value[k] / scale;
                 h->wq[s] = p->walls[s].q;
+                h->wramp[s] = p->walls[s].profile == SLBM_PROFILE_RAMP ? p->walls[s].ramp_time / h->dt_user : 0.0;
             }
         }
         h->norder = p->neumann_order;
@@ -495,6 +538,7 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
             const int rc = build_geo3(p, h, geo);
             if (rc) { delete h; return rc; }
             h->geo = true;
+            for (int k = 0; k < kProfileSlots3; ++k) h->slot_ramp[k] = geo.slot_ramp[(size_t)k];
             h->n_links = (int64_t)geo.recs.size();
             h->n_ext = (int64_t)geo.elink.size();
         }

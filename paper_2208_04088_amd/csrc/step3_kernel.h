@@ -53,19 +53,20 @@ constexpr uint32_t kCutMask3 = 0x3FFFFu;
 
 // One cut link (x, i) of a general geometry, in lattice units, with the
 // rule's constants folded on the host.  Dirichlet (eq:bbcon / eq:bbnoncon):
-//   g_ib = g_i + kappa (g_i(x - c_i) - g_ib) - rho(x) c0,  c0 = beta 6 w_i c_i.v*.
+//   g_ib = g_i + kappa (g_i(x - c_i) - g_ib) - rho(x) a c0,  c0 = beta 6 w_i c_i.v*.
 // Neumann (eq:abbcon / eq:abbnoncon): g_ib = -g_i - kappa (g_i(x - c_i) + g_ib)
 // + 2 beta e, with e = g_eq,i(rho_bd, 0, P*) the shifted equilibrium at the
 // boundary stress sigma* = Pi sigma_b Pi + n t* + t* n - (t*.n) n n.  With
 // A = c_i c_i - I/3 and sigma_b = -P_b - (lambda - mu) drho_bd I this is
 // linear in the site's (or the extrapolated) drho_bd and P_b:
-//   e = c0 drho_bd + sum_k B_k P_b,k - K,
+//   e = c0 drho_bd + sum_k B_k P_b,k - a K,
 //   c0 = w_i [5/2 - 3/2 |c_i|^2 + 9/2 (lambda - mu)(tr(Pi A Pi) - |c_i|^2 + 1)],
 //   B  = 9/2 w_i Pi A Pi (xx yy zz, then xy xz yz doubled),
 //   K  = 9/2 w_i [2 n.A.t* - (t*.n) n.A.n].
-// kappa and beta are 0 and 1 when the opposite link is cut too (no site
-// behind); ext: Neumann with rho_bd and sigma_b extrapolated along the link,
-// (1 + q) X(x) - q X(x - c_i).
+// a is the time profile of the link's group (1, or a ramp: slot s of the
+// launch's factor tables).  kappa and beta are 0 and 1 when the opposite link
+// is cut too (no site behind); ext: Neumann with rho_bd and sigma_b
+// extrapolated along the link, (1 + q) X(x) - q X(x - c_i).
 template <typename real>
 struct Link3 {
     real kap, bet2, q1, q;         // kappa, 2 beta, 1 + q, q
@@ -75,11 +76,13 @@ struct Link3 {
     uint32_t meta;                 // link3_meta
     int32_t site;                  // (z ny + y) nx + x of the material site x
 };
-// meta: direction k (5 bits), opposite (5), kind (2), ext (1), c + 1 per axis (2 each)
-__host__ __device__ constexpr uint32_t link3_meta(int k, int kb, int kind, int ext, int cx, int cy, int cz)
+// meta: direction k (5 bits), opposite (5), kind (2), ext (1), c + 1 per axis
+// (2 each), time-profile slot (4)
+constexpr int kProfileSlots3 = 16;          // slot 0: constant; 1..15: ramps
+__host__ __device__ constexpr uint32_t link3_meta(int k, int kb, int kind, int ext, int cx, int cy, int cz, int slot)
 {
     return (uint32_t)k | (uint32_t)kb << 5 | (uint32_t)kind << 10 | (uint32_t)ext << 12 |
-           (uint32_t)(cx + 1) << 13 | (uint32_t)(cy + 1) << 15 | (uint32_t)(cz + 1) << 17;
+           (uint32_t)(cx + 1) << 13 | (uint32_t)(cy + 1) << 15 | (uint32_t)(cz + 1) << 17 | (uint32_t)slot << 19;
 }
 
 template <typename real>
@@ -109,6 +112,9 @@ struct Step3Args {
     const Link3<real>* links;
     real* lval;                // per record: (A, s_kappa), see cut_links3
     const int32_t* wrec;       // per workgroup of k3_step: its first record (one more: the count)
+    // the groups' time profiles per slot, at the time of the state the pulls
+    // read (pf_pull) and of the state the step produces (pf_next)
+    real pf_pull[kProfileSlots3], pf_next[kProfileSlots3];
     real omega, omega_h;       // 1/tau, 1 - 1/(2 tau)
     real ml, lm;               // mu - lambda, lambda - mu (lattice units)
     real F[3];
@@ -368,11 +374,12 @@ __device__ __forceinline__ unsigned sidx3(int x, int y, int z, int nx, int ny)
 // A from the record's folded constants (its own q, normal and group), g_i
 // and g_ib at x, drho and (or, ext, rho_bd and P_b) at x.
 template <typename real>
-__device__ __forceinline__ real link_part3(const Link3<real>& L, real hi, real hib, real dr, real drb, const real Pb[6])
+__device__ __forceinline__ real link_part3(const Link3<real>& L, real hi, real hib, real dr, real drb, const real Pb[6],
+                                           real at)
 {
-    if (((L.meta >> 10) & 3u) == kWallDirichlet) return hi - L.kap * hib - (real(1) + dr) * L.c0;
+    if (((L.meta >> 10) & 3u) == kWallDirichlet) return hi - L.kap * hib - (real(1) + dr) * (at * L.c0);
     const real e = L.c0 * drb + (L.B[0] * Pb[0] + L.B[1] * Pb[1] + L.B[2] * Pb[2]) +
-                   (L.B[3] * Pb[3] + L.B[4] * Pb[4] + L.B[5] * Pb[5]) - L.K;
+                   (L.B[3] * Pb[3] + L.B[4] * Pb[4] + L.B[5] * Pb[5]) - at * L.K;
     return -hi - L.kap * hib + L.bet2 * e;
 }
 
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(256) void k3_links_ext(Step3Args<real> a, const int
     const real drb = L.q1 * dr - L.q * dry;
 #pragma unroll
     for (int c = 0; c < 6; ++c) P[c] = L.q1 * P[c] - L.q * Py[c];
-    a.lval[2 * l] = link_part3(L, hi, hib, dr, drb, P) - L.kap * hy;
+    a.lval[2 * l] = link_part3(L, hi, hib, dr, drb, P, a.pf_pull[(L.meta >> 19) & 15u]) - L.kap * hy;
 }
 
 // A cut site's pulls along its cut links (the site's records are consecutive,
@@ -705,7 +712,8 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
                 real hd, hj[3], hP[6];
                 moments3(h, hd, hj, hP);
                 const int k = (int)(L.meta & 31u), kb = (int)((L.meta >> 5) & 31u);
-                a.lval[2 * (r0 + r)] = link_part3(L, lo[k][slot], lo[kb][slot], hd, hd, hP);
+                a.lval[2 * (r0 + r)] =
+                    link_part3(L, lo[k][slot], lo[kb][slot], hd, hd, hP, a.pf_next[(L.meta >> 19) & 15u]);
             }
         }
     }

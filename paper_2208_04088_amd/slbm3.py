@@ -16,7 +16,8 @@ EXPORTS = ["slbm3_create", "slbm3_init_fields", "slbm3_step", "slbm3_sync", "slb
 
 
 class Wall(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("q", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("q", C.c_double), ("profile", C.c_int32),
+                ("ramp_time", C.c_double)]
 
 
 class Link(C.Structure):
@@ -25,7 +26,8 @@ class Link(C.Structure):
 
 
 class BCGroup(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("pressure", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("value", C.c_double * 3), ("pressure", C.c_double), ("profile", C.c_int32),
+                ("ramp_time", C.c_double)]
 
 
 class Params3(C.Structure):
@@ -83,10 +85,11 @@ def marshal(box, precision=S.FP32, device=0, stream=None):
         precision = S.PRECISION[precision]
     walls = (Wall * 2)()
     for k in range(2):
-        walls[k] = Wall(0, (C.c_double * 3)(0.0, 0.0, 0.0), 0.5)
+        walls[k] = Wall(0, (C.c_double * 3)(0.0, 0.0, 0.0), 0.5, 0, 0.0)
     if box.x_walls is not None:
         for k, w in enumerate(box.x_walls):
-            walls[k] = Wall(int(w.kind), (C.c_double * 3)(*w.value), float(w.q))
+            walls[k] = Wall(int(w.kind), (C.c_double * 3)(*w.value), float(w.q), int(getattr(w, "profile", 0)),
+                            float(getattr(w, "ramp_time", 0.0)))
     prm = Params3(nx=box.nx, ny=box.ny, nz=box.nz, lam=box.lam, mu=box.mu, rho=box.rho, tau=box.tau,
                   body_force=(C.c_double * 3)(*box.force), periodic_x=int(box.x_walls is None),
                   walls=walls, neumann_order=int(box.neumann_order), precision=int(precision),
@@ -104,7 +107,8 @@ def marshal(box, precision=S.FP32, device=0, stream=None):
                     links[f] = box.links[f]
         groups = (BCGroup * max(1, len(box.groups or [])))()
         for k, g in enumerate(box.groups or []):
-            groups[k] = BCGroup(int(g.kind), (C.c_double * 3)(*g.value), float(getattr(g, "pressure", 0.0)))
+            groups[k] = BCGroup(int(g.kind), (C.c_double * 3)(*g.value), float(getattr(g, "pressure", 0.0)),
+                                int(getattr(g, "profile", 0)), float(getattr(g, "ramp_time", 0.0)))
         prm.mask = mask.ctypes.data
         prm.n_links = len(links)
         prm.links = links.ctypes.data if len(links) else None

@@ -20,6 +20,10 @@ import numpy as np
 
 DIRICHLET = 1
 NEUMANN = 2
+# time profiles of a wall's or group's value: on from t = 0 (STEP), or scaled
+# by min(t / ramp_time, 1) (RAMP)
+STEP = 0
+RAMP = 1
 
 Vec3 = Tuple[float, float, float]
 
@@ -29,6 +33,8 @@ class Wall3:
     kind: int                      # DIRICHLET (value: wall velocity) or NEUMANN (value: traction)
     value: Vec3 = (0.0, 0.0, 0.0)
     q: float = 0.5                 # fraction of a cut link inside the material, (0, 1]
+    profile: int = STEP            # STEP or RAMP (over ramp_time, user units)
+    ramp_time: float = 0.0
 
 
 @dataclass
@@ -76,6 +82,8 @@ class BCGroup3:
     kind: int
     value: Vec3 = (0.0, 0.0, 0.0)
     pressure: float = 0.0
+    profile: int = STEP            # STEP or RAMP (value and pressure scaled by min(t / ramp_time, 1))
+    ramp_time: float = 0.0
 
 
 @dataclass

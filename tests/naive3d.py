@@ -25,9 +25,18 @@ def _feq(c, rho, j, P):
     return _w(c) * v
 
 
-def naive_step(box, f, U, order):
+def _factor(w, step, dt_user):
+    """A wall's or group's time profile at step `step`: 1, or min(t / ramp_time, 1)
+    with t = step dt_user (RAMP, profile 1)."""
+    if getattr(w, "profile", 0) == 1:
+        return min(step * dt_user / w.ramp_time, 1.0)
+    return 1.0
+
+
+def naive_step(box, f, U, order, step=0):
     """f [19, nz, ny, nx] in the direction order `order` (tuples), U [3, ...]:
-    returns (f, U) after one step."""
+    returns (f, U) after one step from step index `step` (the time of the
+    boundary values)."""
     nz, ny, nx = f.shape[1:]
     vel = list(itertools.product((-1, 0, 1), repeat=3))
     vel = [c for c in vel if sum(a * a for a in c) <= 2]
@@ -128,11 +137,13 @@ def naive_step(box, f, U, order):
             if mask is not None:
                 fnew[idx[tuple(-a for a in c)], z, y, x] = _cut_link(box, fcol, idx, vel, links[(x, y, z, c)],
                                                                      x, y, z, c, open_link, wrap, lamL, muL,
-                                                                     s_v, s_sigma)
+                                                                     s_v, s_sigma, step)
                 continue
             # the link leaves through a wall: the population returns to x
             side = 0 if x + c[0] < 0 else 1
-            kind, value, q = walls[side].kind, walls[side].value, walls[side].q
+            kind, q = walls[side].kind, walls[side].q
+            a_t = _factor(walls[side], step, math.sqrt(box.rho / (3 * box.mu)))
+            value = [v * a_t for v in walls[side].value]
             cb = tuple(-a for a in c)
             fc = fcol[idx[c], z, y, x]
             fcb = fcol[idx[cb], z, y, x]
@@ -179,7 +190,7 @@ def naive_step(box, f, U, order):
     return fnew, Un
 
 
-def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_v, s_sigma):
+def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_v, s_sigma, step=0):
     """The population returning to material site (x, y, z) along the cut link
     in direction c, with the link's own q, outward normal and group."""
     q = float(L["q"])
@@ -208,7 +219,7 @@ def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_
     else:
         fb, kap, bet = 0.0, 0.0, 1.0
     if G.kind == DIRICHLET:
-        vL = [v / s_v for v in G.value]
+        vL = [v / s_v * _factor(G, step, 1 / s_v) for v in G.value]
         return fc + kap * (fb - fcb) - bet * 6 * _w(c) * sum(c[a] * r * vL[a] for a in range(3))
 
     def cauchy(rr, PP_):
@@ -221,7 +232,8 @@ def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_
         sb = cauchy(rb, Pb)
         sig = [[(1 + q) * sig[a][b] - q * sb[a][b] for b in range(3)] for a in range(3)]
         rbd = (1 + q) * r - q * rb
-    t = [G.value[a] / s_sigma - G.pressure / s_sigma * n[a] for a in range(3)]
+    aG = _factor(G, step, 1 / s_v)
+    t = [(G.value[a] / s_sigma - G.pressure / s_sigma * n[a]) * aG for a in range(3)]
     if G2 is None:
         tn = sum(t[a] * n[a] for a in range(3))
         Pi = [[(a == b) - n[a] * n[b] for b in range(3)] for a in range(3)]
@@ -232,7 +244,8 @@ def _cut_link(box, fcol, idx, vel, L, x, y, z, c, open_link, wrap, lamL, muL, s_
         # rows of n and n2 from the tractions (their shear averaged), the
         # edge component from the material
         n2 = [float(v) for v in L["normal2"]]
-        t2 = [G2.value[a] / s_sigma - G2.pressure / s_sigma * n2[a] for a in range(3)]
+        aG2 = _factor(G2, step, 1 / s_v)
+        t2 = [(G2.value[a] / s_sigma - G2.pressure / s_sigma * n2[a]) * aG2 for a in range(3)]
         e = [n[1] * n2[2] - n[2] * n2[1], n[2] * n2[0] - n[0] * n2[2], n[0] * n2[1] - n[1] * n2[0]]
         d = lambda u, v: sum(u[a] * v[a] for a in range(3))
         basis = [n, n2, e]

@@ -205,6 +205,34 @@ def test_invalid_edge_links_are_rejected_on_the_host(case):
     assert rc == -1 and msg, (case, rc, msg)
 
 
+@pytest.mark.parametrize("case", ["group_profile", "group_ramp", "wall_profile", "wall_ramp", "edge_profiles",
+                                  "many_ramps"])
+def test_invalid_time_profiles_are_rejected_on_the_host(case):
+    if case in ("wall_profile", "wall_ramp"):
+        box = _slab()
+        w = box.x_walls[1]
+        box.x_walls = (box.x_walls[0], B.Wall3(w.kind, w.value, profile=5 if case == "wall_profile" else B.RAMP,
+                                               ramp_time=0.0))
+        rc, msg = _create(box)
+        assert rc == -1 and msg, (case, rc, msg)
+        return
+    box = _block() if case == "edge_profiles" else _cavity()
+    if case == "group_profile":
+        box.groups[0] = B.BCGroup3(B.NEUMANN, profile=3)
+    elif case == "group_ramp":
+        box.groups[0] = B.BCGroup3(B.NEUMANN, profile=B.RAMP, ramp_time=-1.0)
+    elif case == "edge_profiles":
+        # the -x face ramped, the -y face (which shares an edge with it) not
+        box.groups[0] = B.BCGroup3(B.NEUMANN, profile=B.RAMP, ramp_time=3.0)
+    else:
+        box.groups = [B.BCGroup3(B.NEUMANN, profile=B.RAMP, ramp_time=1.0 + k) for k in range(16)]
+        rc, msg = _create(box)
+        assert rc == -5 and msg, (case, rc, msg)
+        return
+    rc, msg = _create(box)
+    assert rc == -1 and msg, (case, rc, msg)
+
+
 @pytest.mark.parametrize("make", [_cavity, _cracked, _block])
 def test_valid_geometry_without_a_gpu_fails_loudly(make):
     """A valid cavity, or cavity and crack, passes the host checks and then

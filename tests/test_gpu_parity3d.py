@@ -461,3 +461,35 @@ def test_block_holds_a_uniform_stress_on_the_gpu(S3):
     mk = box.mask.astype(bool)
     assert np.abs(sg[:, mk] - sig[:, mk]).max() < 1e-12
     assert np.abs(j[:, mk]).max() < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 40), ("fp32", FP32_TOL, 300)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_ramped_walls(S3, prec, tol, steps, order):
+    """Wall planes off the lattice whose values ramp up over 25 and 60 steps
+    (the wall values at the time of the state each rule reads)."""
+    dt = np.sqrt(1.0 / (3 * 0.05))
+    walls = (B.Wall3(B.DIRICHLET, (1e-4, -2e-4, 5e-5), q=0.3, profile=B.RAMP, ramp_time=25 * dt),
+             B.Wall3(B.NEUMANN, (5e-5, 1e-5, -2e-5), q=0.8, profile=B.RAMP, ramp_time=60 * dt))
+    box = B.slab3(70, 6, 5, *walls, lam=0.05, mu=0.05, tau=0.6, neumann_order=order)
+    out, ref = run_both(S3, box, prec, steps if order == 0 else min(steps, 60))
+    check(out, ref, tol, f"ramped walls {prec} order {order}", box)
+
+
+@pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 40), ("fp32", FP32_TOL, 300)])
+def test_ramped_groups(S3, prec, tol, steps):
+    """Cut links whose groups ramp over different times (a pressurised cavity,
+    a moving cavity, a loaded crack face, a block's faces and edges sharing
+    one ramp), from rest."""
+    dt = np.sqrt(1.0 / (3 * 0.05))
+    R = lambda T: dict(profile=B.RAMP, ramp_time=T * dt)
+    groups = [B.BCGroup3(B.NEUMANN, (0.0, 0.0, 0.0), 2e-4, **R(30)), B.BCGroup3(B.DIRICHLET, (2e-4, -1e-4, 0.0), **R(12)),
+              B.BCGroup3(B.NEUMANN), B.BCGroup3(B.NEUMANN, (3e-5, 0.0, 1e-5), **R(45))]
+    box = B.sphere_box3(70, 14, 12, [B.Sphere3(14.2, 6.6, 5.9, 3.0, 0), B.Sphere3(30.4, 7.1, 6.2, 2.8, 1)], groups,
+                        lam=0.05, mu=0.05, tau=0.7, cracks=[B.PennyCrack3(50.3, 6.8, 5.4, 4.1, 2, 3)])
+    out, ref = run_both(S3, box, prec, steps)
+    check(out, ref, tol, f"ramped groups {prec}", box)
+    bgroups = [B.BCGroup3(B.NEUMANN, (2e-5, 0.0, 0.0), **R(20))] * 5 + [B.BCGroup3(B.NEUMANN, (0.0, 0.0, 1e-5), **R(20))]
+    block = B.block_box3(70, 11, 10, (3, 2, 2), (66, 8, 7), list(range(6)), bgroups, lam=0.05, mu=0.05, tau=0.7)
+    out, ref = run_both(S3, block, prec, steps)
+    check(out, ref, tol, f"ramped block {prec}", block)

@@ -666,6 +666,77 @@ def test_brute_force_loops_with_a_block(order):
     assert np.abs(o.U - Un).max() < 1e-14
 
 
+def _ramped(make, T_steps, step):
+    """Oracle on make(profile kwargs), populations at a random state, its
+    step counter at `step`: one step."""
+    rng = np.random.default_rng(17)
+    b = make()
+    o = Oracle3D(b)
+    f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
+    if b.mask is not None:
+        f[:, ~b.mask.astype(bool)] = o.populations()[:, ~b.mask.astype(bool)]
+    o.set_populations(f)
+    o.n = step
+    o.step(1)
+    return o.populations()
+
+
+@pytest.mark.parametrize("geometry", ["walls", "links"])
+def test_ramped_values_take_the_time_of_the_step(geometry):
+    """A RAMP profile scales a wall's or group's value by min(t_n / T, 1), t_n
+    the time of the post-collision state the rule reads: from the same state,
+    one step at n = 0 equals the step with the value zero, at n = 3 of a
+    10-step ramp the step with 0.3 of the value, and past the ramp the STEP
+    profile's step."""
+    dt = np.sqrt(1.0 / (3 * 0.05))
+    T = 10 * dt
+    vd, vn = (1e-3, -2e-3, 5e-4), (2e-4, 1e-4, -3e-4)
+
+    def make(scale=1.0, ramp=True):
+        kw = dict(profile=B.RAMP, ramp_time=T) if ramp else {}
+        if geometry == "walls":
+            return B.slab3(5, 4, 3, B.Wall3(B.DIRICHLET, tuple(scale * v for v in vd), q=0.3, **kw),
+                           B.Wall3(B.NEUMANN, tuple(scale * v for v in vn), q=0.8, **kw), lam=0.09, mu=0.05,
+                           tau=0.6, neumann_order=1)
+        groups = [B.BCGroup3(B.NEUMANN, tuple(scale * v for v in vn), scale * 2e-4, **kw),
+                  B.BCGroup3(B.DIRICHLET, tuple(scale * v for v in vd), **kw)]
+        return B.sphere_box3(8, 7, 7, [B.Sphere3(3.4, 3.2, 3.1, 1.7, 0)], groups, lam=0.09, mu=0.05, tau=0.6,
+                             neumann_order=1, cracks=[])
+
+    ref0 = _ramped(lambda: make(0.0, False), 10, 0)
+    assert np.abs(_ramped(make, 10, 0) - ref0).max() == 0.0
+    assert np.abs(_ramped(make, 10, 3) - _ramped(lambda: make(0.3, False), 10, 3)).max() < 1e-17
+    assert np.abs(_ramped(make, 10, 14) - _ramped(lambda: make(1.0, False), 10, 14)).max() == 0.0
+    assert np.abs(_ramped(make, 10, 3) - ref0).max() > 1e-6
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_brute_force_loops_with_ramped_groups(order):
+    """One step at step index 4 of ramped walls and groups against the
+    per-site loop form (which applies the profile itself)."""
+    dt = np.sqrt(1.0 / (3 * 0.05))
+    rng = np.random.default_rng(19)
+    boxes = [B.slab3(4, 4, 3, B.Wall3(B.DIRICHLET, (1e-3, 2e-3, -1e-3), q=0.3, profile=B.RAMP, ramp_time=9 * dt),
+                     B.Wall3(B.NEUMANN, (2e-4, -1e-4, 3e-4), q=0.7, profile=B.RAMP, ramp_time=6 * dt),
+                     lam=0.09, mu=0.05, tau=0.6, neumann_order=order),
+             B.sphere_box3(6, 6, 5, [B.Sphere3(2.6, 2.4, 2.1, 1.3, 0)],
+                           [B.BCGroup3(B.NEUMANN, (1e-4, -2e-4, 5e-5), 3e-4, profile=B.RAMP, ramp_time=7 * dt)],
+                           lam=0.09, mu=0.05, tau=0.6, neumann_order=order)]
+    for box in boxes:
+        o = Oracle3D(box)
+        f = o.populations() + rng.normal(size=o.populations().shape) * 1e-3
+        if box.mask is not None:
+            f[:, ~box.mask.astype(bool)] = o.populations()[:, ~box.mask.astype(bool)]
+        o.set_populations(f)
+        U0 = rng.normal(size=(3,) + o.shape) * (1 if box.mask is None else box.mask)
+        o.U = U0.copy()
+        o.n = 4
+        o.step(1)
+        fn, Un = naive_step(box, f, U0, [tuple(int(a) for a in c) for c in C], step=4)
+        assert np.abs(o.populations() - fn).max() < 1e-14
+        assert np.abs(o.U - Un).max() < 1e-14
+
+
 def test_inconsistent_cut_links_are_refused():
     b = B.sphere_box3(10, 9, 8, [B.Sphere3(4.4, 4.2, 3.9, 2.2, 0)], [B.BCGroup3(B.NEUMANN)])
     for bad in ("missing", "material_far_end", "q"):
