@@ -65,6 +65,7 @@
 #ifndef SLBM3_H
 #define SLBM3_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "slbm.h"
@@ -188,6 +189,17 @@ int slbm3_time(slbm3_handle h, int64_t* step, double* t_user);
 
 /* Device memory held by the handle, in bytes. */
 int slbm3_device_bytes(slbm3_handle h, int64_t* bytes);
+
+/* Checkpoint and resume: slbm3_save writes the whole state (populations,
+ * the displacement sums, the step count, the divergence flag and, with cut
+ * links, the rule values the next step reads) into the caller's host buffer
+ * of *bytes bytes and sets *bytes to the size used; with buf NULL it only
+ * reports the size.  SLBM_E_INVAL when *bytes is too small.  slbm3_load
+ * restores a checkpoint on a handle created with the same box, geometry and
+ * precision (SLBM_E_INVAL otherwise), so that stepping on gives results
+ * bit-identical to an uninterrupted run.  Both synchronise. */
+int slbm3_save(slbm3_handle h, void* buf, size_t* bytes);
+int slbm3_load(slbm3_handle h, const void* buf, size_t bytes);
 
 /* Frees the handle and its device memory after the queued work; NULL is a
  * no-op. */

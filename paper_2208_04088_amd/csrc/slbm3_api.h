@@ -793,4 +793,77 @@ int slbm3_device_bytes(slbm3_handle h, int64_t* bytes)
     });
 }
 
+namespace {
+struct Save3Header {
+    uint64_t magic;
+    int32_t nx, ny, nz, precision;
+    int64_t step, n_links, stride;
+    int32_t local, diverged;
+};
+constexpr uint64_t kMagic3 = 0x3364335f6d626c73ull;    // "slbm_3d3"
+
+size_t save3_bytes(const slbm3_s* h)
+{
+    return sizeof(Save3Header) + (size_t)19 * h->stride * h->esize + (size_t)3 * h->stride * sizeof(double) +
+           (size_t)2 * h->n_links * h->esize;
+}
+}  // namespace
+
+int slbm3_save(slbm3_handle h, void* buf, size_t* bytes)
+{
+    return guarded([&]() -> int {
+        if (!h || !bytes) return fail(SLBM_E_INVAL, "null argument");
+        const size_t need = save3_bytes(h);
+        if (!buf) { *bytes = need; return SLBM_OK; }
+        if (*bytes < need) return fail(SLBM_E_INVAL, "buffer too small: %zu < %zu", *bytes, need);
+        DeviceGuard dg(h->device);
+        const size_t pop = (size_t)19 * h->stride * h->esize, ub = (size_t)3 * h->stride * sizeof(double);
+        Save3Header hd{kMagic3, h->nx, h->ny, h->nz, h->precision, h->step, h->n_links, h->stride,
+                       h->local ? 1 : 0, 0};
+        unsigned int flag = 0;
+        char* p = (char*)buf;
+        HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(p + sizeof hd, h->buf[h->cur], pop, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(p + sizeof hd + pop, h->U, ub, hipMemcpyDeviceToHost, h->stream));
+        if (h->n_links > 0)
+            HIP_TRY(hipMemcpyAsync(p + sizeof hd + pop + ub, h->lval, (size_t)2 * h->n_links * h->esize,
+                                   hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        hd.diverged = (int32_t)flag;
+        std::memcpy(p, &hd, sizeof hd);
+        *bytes = need;
+        return SLBM_OK;
+    });
+}
+
+int slbm3_load(slbm3_handle h, const void* buf, size_t bytes)
+{
+    return guarded([&]() -> int {
+        if (!h || !buf) return fail(SLBM_E_INVAL, "null argument");
+        Save3Header hd;
+        if (bytes < save3_bytes(h)) return fail(SLBM_E_INVAL, "checkpoint too short");
+        std::memcpy(&hd, buf, sizeof hd);
+        if (hd.magic != kMagic3 || hd.nx != h->nx || hd.ny != h->ny || hd.nz != h->nz ||
+            hd.precision != h->precision || hd.n_links != h->n_links || hd.stride != h->stride)
+            return fail(SLBM_E_INVAL, "checkpoint does not match this box");
+        DeviceGuard dg(h->device);
+        const size_t pop = (size_t)19 * h->stride * h->esize, ub = (size_t)3 * h->stride * sizeof(double);
+        const char* p = (const char*)buf;
+        // the other buffer, which the next step writes, keeps the rest state
+        // at void sites from creation
+        h->cur = 0;
+        HIP_TRY(hipMemcpyAsync(h->buf[0], p + sizeof hd, pop, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->U, p + sizeof hd + pop, ub, hipMemcpyHostToDevice, h->stream));
+        if (h->n_links > 0)
+            HIP_TRY(hipMemcpyAsync(h->lval, p + sizeof hd + pop + ub, (size_t)2 * h->n_links * h->esize,
+                                   hipMemcpyHostToDevice, h->stream));
+        unsigned int flag = (unsigned int)hd.diverged;
+        HIP_TRY(hipMemcpyAsync(h->diverged, &flag, sizeof flag, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->step = hd.step;
+        h->local = hd.local != 0;
+        return SLBM_OK;
+    });
+}
+
 }  // extern "C"

@@ -12,7 +12,7 @@ from . import slbm as S
 
 EXPORTS = ["slbm3_create", "slbm3_init_fields", "slbm3_step", "slbm3_sync", "slbm3_moments",
            "slbm3_displacement", "slbm3_displacement_device", "slbm3_moments_device", "slbm3_time",
-           "slbm3_device_bytes", "slbm3_destroy"]
+           "slbm3_device_bytes", "slbm3_save", "slbm3_load", "slbm3_destroy"]
 
 
 class Wall(C.Structure):
@@ -65,6 +65,8 @@ def lib():
         "slbm3_moments_device": [vp, vp, vp, vp, vp, C.c_int32],
         "slbm3_time": [vp, C.POINTER(i64), C.POINTER(C.c_double)],
         "slbm3_device_bytes": [vp, C.POINTER(i64)],
+        "slbm3_save": [vp, vp, C.POINTER(C.c_size_t)],
+        "slbm3_load": [vp, vp, C.c_size_t],
         "slbm3_destroy": [vp],
     }
     for name, args in sig.items():
@@ -198,3 +200,17 @@ class Solver3:
         b = C.c_int64()
         S._check(lib().slbm3_device_bytes(self.h, C.byref(b)))
         return b.value
+
+    def save(self):
+        """The whole state as a host byte array (slbm3_save)."""
+        n = C.c_size_t(0)
+        S._check(lib().slbm3_save(self.h, None, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        S._check(lib().slbm3_save(self.h, buf.ctypes.data, C.byref(n)))
+        return buf
+
+    def load(self, buf):
+        """Restores a state from save() on a box of the same shape, geometry
+        and precision (slbm3_load)."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        S._check(lib().slbm3_load(self.h, buf.ctypes.data, buf.size))

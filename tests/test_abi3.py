@@ -27,7 +27,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     L = S3.lib()
     names = declared_functions()
-    assert len(names) == 11
+    assert len(names) == 13
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert sorted(S3.EXPORTS) == names
@@ -115,6 +115,9 @@ def test_device_outputs_reject_a_null_handle():
     L = S3.lib()
     assert L.slbm3_displacement_device(None, None) == -1
     assert L.slbm3_moments_device(None, None, None, None, None, 0) == -1
+    n = C.c_size_t(0)
+    assert L.slbm3_save(None, None, C.byref(n)) == -1
+    assert L.slbm3_load(None, None, 0) == -1
 
 
 def _cavity():

@@ -493,3 +493,39 @@ def test_ramped_groups(S3, prec, tol, steps):
     block = B.block_box3(70, 11, 10, (3, 2, 2), (66, 8, 7), list(range(6)), bgroups, lam=0.05, mu=0.05, tau=0.7)
     out, ref = run_both(S3, block, prec, steps)
     check(out, ref, tol, f"ramped block {prec}", block)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["slab", "geometry"])
+def test_checkpoint_resume_is_bit_identical(S3, prec, kind):
+    """slbm3_save after k steps, slbm3_load into a fresh handle of the same
+    box, m more steps: the same state, to the bit, as k + m steps without
+    interruption (ramped values, extrapolated rules and, with cut links, the
+    rule values the next step reads are part of the state)."""
+    dt = np.sqrt(1.0 / (3 * 0.05))
+    if kind == "slab":
+        box = B.slab3(70, 6, 5, B.Wall3(B.DIRICHLET, (1e-4, 0.0, 2e-5), q=0.3, profile=B.RAMP, ramp_time=20 * dt),
+                      B.Wall3(B.NEUMANN, (5e-5, 1e-5, 0.0), q=0.7), lam=0.05, mu=0.05, tau=0.6, neumann_order=1)
+    else:
+        box = _block(1)
+    k, m = 13, 11
+    fields = dict(vel=B.random_velocity(box, 81, 1e-3) * (1 if box.mask is None else box.mask))
+    with S3.Solver3(box, prec) as a:
+        a.init_fields(**fields)
+        a.step(k + m)
+        a.sync()
+        u_ref, mom_ref = a.displacement(), a.moments()
+    with S3.Solver3(box, prec) as b:
+        b.init_fields(**fields)
+        b.step(k)
+        b.sync()
+        ck = b.save()
+    with S3.Solver3(box, prec) as c:
+        c.load(ck)
+        assert c.time()[0] == k
+        c.step(m)
+        c.sync()
+        u, mom = c.displacement(), c.moments()
+    assert np.array_equal(u, u_ref)
+    for x, y in zip(mom, mom_ref):
+        assert np.array_equal(x, y)
