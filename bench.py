@@ -7,8 +7,9 @@ the fused kernel.  The default workload is the 2048 x 2048 plate with a
 centred hole of radius 256 (curved traction-free wall, lambda/mu = 2,
 tau_bar = 0.6, fp32 populations, fp64 displacement).  Its line also carries
 the fp64-plain step on the same plate, a 4096^2 plate, a 2048^2 plate with a
-moving curved Dirichlet wall and the served trace (p50/p99 latency) as
-sub-records.
+moving curved Dirichlet wall, the served trace (p50/p99 latency) and the
+three-dimensional step on two 256^3 boxes (the pulled slab and the porous
+solid) as sub-records.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-extras]
     python bench.py --workload batch64     # 64 uneven plates, batched vs one at a time
@@ -231,27 +232,26 @@ def cpu_baseline3(box, budget_s=15.0, sample=None):
                       f"({sample.n_material} material sites), numpy fp64 on one thread, {dt:.1f} s", **host_cpu()}
 
 
-def run_3d(args, torch, dev, stream, n, kind="cube"):
-    """The three-dimensional (D3Q19) step on an n^3 box: kind "cube", a slab
-    with face x = -1/2 clamped and face x = n - 1/2 pulled by a step
-    traction, periodic in y and z; kind "cavities", a porous solid periodic on
-    every axis with (n/64)^3 pressurised spherical cavities (cut links of
-    every q and normal).  fp32 populations, fp64 displacement, from rest.  One
-    bench step is one time step of the whole box (two launches: density pass,
-    step); the rate counts material sites."""
-    import numpy as np
-    from paper_2208_04088_amd import slbm3
+STEPS3_SUB, WARMUP3_SUB = 200, 20     # the 3-D sub-records of the default line
+
+
+def box3_of(kind, n, steps):
+    """The n^3 box of a 3-D workload and, for the cavities, the smaller box
+    the CPU baseline samples."""
     from slbm_workloads import box3d as B
-    steps = args.steps if args.steps_given else 1000
     if kind == "cavities":
         box = B.cavities_box3(n, per_axis=max(1, n // 64), steps=steps)
         sample = B.cavities_box3(64, per_axis=1, radius=0.3 * n / max(1, n // 64), seed=1)
-    else:
-        box = B.cube_pulled(n, steps=steps)
-        sample = None
-    prec = args.precision or "fp32"
+        return box, sample
+    return B.cube_pulled(n, steps=steps), None
+
+
+def time_box3(torch, stream, box, prec, steps, warm):
+    """Times `steps` steps of `box` after `warm` untimed ones; returns the
+    record (value, config, roofline) without the copy ceiling."""
+    import numpy as np
+    from paper_2208_04088_amd import slbm3
     s = slbm3.Solver3(box, prec, device=0, stream=stream.cuda_stream)
-    warm = min(args.warmup, 100)
     s.step(warm)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -272,7 +272,6 @@ def run_3d(args, torch, dev, stream, n, kind="cube"):
     bps = bytes_per_site3(prec)
     step_bytes = bytes_per_step3(box, prec)
     achieved = step_bytes / t_step / 1e9
-    from paper_2208_04088_amd import slbm
     result = {
         "metric": "MLUPS (site updates per second) of the D3Q19 solid-LBM step",
         "value": round(sites / t_step / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warm,
@@ -294,8 +293,23 @@ def run_3d(args, torch, dev, stream, n, kind="cube"):
                      "note": "achieved counts the step's algorithmic bytes over the time of all its launches; "
                              "the density pass re-reads the pulled populations (traffic: measured bytes per step)"},
     }
-    result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
     s.close()
+    return result
+
+
+def run_3d(args, torch, dev, stream, n, kind="cube"):
+    """The three-dimensional (D3Q19) step on an n^3 box: kind "cube", a slab
+    with face x = -1/2 clamped and face x = n - 1/2 pulled by a step
+    traction, periodic in y and z; kind "cavities", a porous solid periodic on
+    every axis with (n/64)^3 pressurised spherical cavities (cut links of
+    every q and normal).  fp32 populations, fp64 displacement, from rest.  One
+    bench step is one time step of the whole box (two launches: density pass,
+    step); the rate counts material sites."""
+    from paper_2208_04088_amd import slbm
+    steps = args.steps if args.steps_given else 1000
+    box, sample = box3_of(kind, n, steps)
+    result = time_box3(torch, stream, box, args.precision or "fp32", steps, min(args.warmup, 100))
+    result["roofline"]["copy_kernel_gbs"] = copy_ceiling(slbm, torch, dev, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline3(box, sample=sample)
     print(json.dumps(result), flush=True)
@@ -655,7 +669,7 @@ def main():
                          "g interleaved groups of g")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="the hole plate alone, without the fp64, 4096^2 and served sub-records")
+                    help="the hole plate alone, without the fp64, 4096^2, moving-wall, served and 3-D sub-records")
     ap.add_argument("--requests", type=int, default=256, help="served workload: requests of the trace")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -732,6 +746,12 @@ def main():
         rmov = time_plate(args, slbm, torch, stream, mov, "fp32", args.steps, args.warmup)
         result["movinghole2048"] = sub_record(rmov, args.steps, args.warmup)
         result["served"], _ = serve_record(args, slbm, torch, stream)
+        # the three-dimensional step: the pulled slab and the porous solid
+        # with pressurised cavities (cut links of every q and normal), 256^3
+        for kind in ("cube", "cavities"):
+            box, _ = box3_of(kind, 256, STEPS3_SUB)
+            r3 = time_box3(torch, stream, box, "fp32", STEPS3_SUB, WARMUP3_SUB)
+            result[f"{kind}256"] = sub_record(r3, STEPS3_SUB, WARMUP3_SUB)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(plate)
     print(json.dumps(result), flush=True)
