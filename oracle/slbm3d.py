@@ -171,9 +171,13 @@ class Oracle3D:
         self.mask = mask
         L = b.links
         site = L["site"].astype(np.int64)
+        k = L["dir"].astype(np.int64)
+        if ((site < 0) | (site >= mask.size)).any():
+            raise ValueError("a cut link's site is out of range")
+        if ((k < 1) | (k >= Q)).any():
+            raise ValueError("a cut link's direction must be one of the 18 moving ones")
         z, rem = np.divmod(site, b.ny * b.nx)
         y, x = np.divmod(rem, b.nx)
-        k = L["dir"].astype(np.int64)
         if not mask[z, y, x].all():
             raise ValueError("a cut link starts at a void site")
         fz, fy, fx = (z + C[k, 2]) % b.nz, (y + C[k, 1]) % b.ny, (x + C[k, 0]) % b.nx

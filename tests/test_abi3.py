@@ -247,3 +247,73 @@ def test_valid_geometry_without_a_gpu_fails_loudly(make):
     assert len(box.links) > 0 and box.n_material < box.n_sites
     rc, msg = _create(box)
     assert rc == -3, (rc, msg)
+
+
+def _mutate(box, rng):
+    """One seeded change to a valid geometry: a field of one link record
+    (site, direction, q, group, second group, a normal), a record dropped,
+    repeated, added with a changed site or direction, the records shuffled,
+    a record moved to a neighbouring site, or one site of the mask flipped.
+    Some changes keep the geometry valid (a shuffle, a new unit normal on a
+    face link), most do not."""
+    L = box.links.copy()
+    n, ng = box.n_sites, len(box.groups)
+    kind = str(rng.choice(["site", "dir", "q", "group", "group2", "normal", "normal2", "drop", "repeat",
+                           "shuffle", "mask", "move", "add_site", "add_dir"]))
+    i = int(rng.integers(len(L)))
+    if kind.startswith("add_"):
+        L = np.concatenate([L, L[i:i + 1]])
+        i, kind = len(L) - 1, kind[4:]
+    if kind == "site":
+        L["site"][i] = int(rng.integers(-5, n + 5))
+    elif kind == "dir":
+        L["dir"][i] = int(rng.integers(-1, 21))
+    elif kind == "q":
+        L["q"][i] = rng.choice([-0.1, 0.0, 1e-6, 0.3, 1.0, 1.0000001, 2.0])
+    elif kind == "group":
+        L["group"][i] = int(rng.integers(-2, ng + 2))
+    elif kind == "group2":
+        L["group2"][i] = int(rng.integers(-3, ng + 2))
+    elif kind in ("normal", "normal2"):
+        if rng.random() < 0.5:
+            v = rng.normal(size=3)
+            L[kind][i] = v / np.linalg.norm(v)
+        else:
+            L[kind][i] = L[kind][i] * (1 + rng.choice([1e-7, -1e-7, 1e-11]))
+    elif kind == "drop":
+        L = np.delete(L, i)
+    elif kind == "repeat":
+        L = np.concatenate([L, L[i:i + 1]])
+    elif kind == "shuffle":
+        L = L[rng.permutation(len(L))]
+    elif kind == "mask":
+        m = box.mask.copy()
+        m.ravel()[int(rng.integers(n))] ^= 1
+        box.mask = m
+    else:                                               # move
+        L["site"][i] = (int(L["site"][i]) + int(rng.choice([-1, 1, -box.nx, box.nx]))) % n
+    box.links = L
+
+
+def test_host_checks_agree_with_the_reference():
+    """The library's host checks of a general geometry and the CPU
+    reference's, written apart, accept and refuse the same geometries: 900
+    seeded changes (one or two each) to a cavity, a cavity with a crack and a
+    block with edges."""
+    from oracle.slbm3d import Oracle3D
+    rng = np.random.default_rng(2208)
+    verdicts = {True: 0, False: 0}
+    for it in range(900):
+        box = (_cavity, _cracked, _block)[it % 3]()
+        for _ in range(int(rng.integers(1, 3))):
+            _mutate(box, rng)
+        try:
+            Oracle3D(box)
+            ref_ok = True
+        except ValueError:
+            ref_ok = False
+        rc, msg = _create(box)
+        assert rc in (0, -3, -1), (it, rc, msg)
+        assert (rc != -1) == ref_ok, (it, rc, msg)
+        verdicts[ref_ok] += 1
+    assert min(verdicts.values()) > 50, verdicts
