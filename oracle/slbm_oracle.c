@@ -185,7 +185,7 @@ oracle_t* oracle_create(const oracle_problem* p, char* err, int errlen)
         if (k < 1 || k > 8) FAIL("link %d: direction must be 1..8", l);
         if (!(p->link_q[l] > 0 && p->link_q[l] <= 1)) FAIL("link %d: q outside (0,1]", l);
         if (p->link_group[l] < 0 || p->link_group[l] >= o->ng) FAIL("link %d: bad group", l);
-        if (p->link_group2[l] >= o->ng) FAIL("link %d: bad second group", l);
+        if (p->link_group2[l] < -1 || p->link_group2[l] >= o->ng) FAIL("link %d: bad second group", l);
         if (o->link_at[(size_t)k * n + s] >= 0) FAIL("link %d: duplicate", l);
         double nn = p->link_normal[2 * l] * p->link_normal[2 * l] + p->link_normal[2 * l + 1] * p->link_normal[2 * l + 1];
         if (fabs(nn - 1.0) > 1e-9) FAIL("link %d: normal is not a unit vector", l);

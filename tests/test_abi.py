@@ -165,3 +165,80 @@ def test_launch_configuration_calls_reject_a_null_handle():
     assert L.slbm_set_xcd_group(None, 8) == -1
     assert L.slbm_get_launch(None, None, None, None) == -1
     assert L.slbm_batch_set_xcd_group(None, 8) == -1
+
+
+def _cracked_plate():
+    """A 14 x 10 plate with an edge crack entering from the left edge (links
+    through the crack's mouth carry two walls)."""
+    walls = G.edge_walls(14, 10, left=0, right=0, bottom=1, top=2)
+    walls.append(G.HLine(4.5, -0.5, 6.5, 0))
+    return G.build_plate(14, 10, lam=0.05, mu=0.05, tau=0.55, walls=walls,
+                         groups=[G.BCGroup(G.NEUMANN), G.BCGroup(G.NEUMANN, (0.0, -1e-5)),
+                                 G.BCGroup(G.NEUMANN, (0.0, 1e-5))])
+
+
+def _mutate(p, rng):
+    """One seeded change to a valid plate: a field of one link record (site,
+    direction, q, group, second group, a normal), a record dropped, repeated,
+    added with a changed site or direction, the records shuffled, a record
+    moved to a neighbouring site, or one site of the mask flipped."""
+    L = p.links.copy()
+    n, ng = p.nx * p.ny, len(p.groups)
+    kind = str(rng.choice(["site", "dir", "q", "group", "group2", "normal", "normal2", "drop", "repeat",
+                           "shuffle", "mask", "move", "add_site", "add_dir"]))
+    i = int(rng.integers(len(L)))
+    if kind.startswith("add_"):
+        L = np.concatenate([L, L[i:i + 1]])
+        i, kind = len(L) - 1, kind[4:]
+    if kind == "site":
+        L["site"][i] = int(rng.integers(-5, n + 5))
+    elif kind == "dir":
+        L["dir"][i] = int(rng.integers(-1, 11))
+    elif kind == "q":
+        L["q"][i] = rng.choice([-0.1, 0.0, 1e-6, 0.3, 1.0, 1.0000001, 2.0])
+    elif kind == "group":
+        L["group"][i] = int(rng.integers(-2, ng + 2))
+    elif kind == "group2":
+        L["group2"][i] = int(rng.integers(-3, ng + 2))
+    elif kind in ("normal", "normal2"):
+        if rng.random() < 0.5:
+            v = rng.normal(size=2)
+            L[kind][i] = v / np.linalg.norm(v)
+        else:
+            L[kind][i] = L[kind][i] * (1 + rng.choice([1e-7, -1e-7, 1e-11]))
+    elif kind == "drop":
+        L = np.delete(L, i)
+    elif kind == "repeat":
+        L = np.concatenate([L, L[i:i + 1]])
+    elif kind == "shuffle":
+        L = L[rng.permutation(len(L))]
+    elif kind == "mask":
+        m = p.mask.copy()
+        m.ravel()[int(rng.integers(n))] ^= 1
+        p.mask = m
+    else:                                               # move
+        L["site"][i] = (int(L["site"][i]) + int(rng.choice([-1, 1, -p.nx, p.nx]))) % n
+    p.links = L
+
+
+def test_host_checks_agree_with_the_reference():
+    """The library's host checks of a plate and the CPU reference's, written
+    apart, accept and refuse the same plates: 1200 seeded changes (one or two
+    each) to a plate with a hole and to a plate with an edge crack."""
+    from oracle import Oracle
+    rng = np.random.default_rng(2208)
+    verdicts = {True: 0, False: 0}
+    for it in range(1200):
+        p = (_plate, _cracked_plate)[it % 2]()
+        for _ in range(int(rng.integers(1, 3))):
+            _mutate(p, rng)
+        try:
+            Oracle(p)
+            ref_ok = True
+        except ValueError:
+            ref_ok = False
+        rc, msg = _create(p)
+        assert rc in (0, -3, -1), (it, rc, msg)
+        assert (rc != -1) == ref_ok, (it, rc, msg)
+        verdicts[ref_ok] += 1
+    assert min(verdicts.values()) > 100, verdicts
