@@ -118,8 +118,10 @@ typedef struct slbm_s* slbm_handle;
 /* Validates and copies the problem, uploads it and sets the rest state
  * (zero displacement and velocity, unstressed).  SLBM_E_INVAL when a cut link
  * names a void site, an uncut link leaves the material, q is outside (0, 1],
- * a normal is not a unit vector, a group index is out of range, tau <= 1/2,
- * or mu, rho <= 0.  SLBM_E_UNSUPPORTED above 2^28 sites; SLBM_E_NOMEM or
+ * a normal is not a unit vector, a group index is out of range, a material
+ * site has all 8 links cut (an isolated site: the kernels keep one flag byte
+ * per site, whose all-ones value marks a void site), tau <= 1/2, or mu,
+ * rho <= 0.  SLBM_E_UNSUPPORTED above 2^28 sites; SLBM_E_NOMEM or
  * SLBM_E_DEVICE if allocation fails. */
 int slbm_create(const slbm_params* params, slbm_handle* out);
 

@@ -184,8 +184,8 @@ class Oracle3D:
         q = L["q"]
         if not ((q > 0) & (q <= 1)).all():
             raise ValueError("q must be in (0, 1]")
-        n = np.asarray(L["normal"], dtype=float)
-        if np.abs(np.linalg.norm(n, axis=1) - 1).max() > 1e-9:
+        n = np.asarray(L["normal"], dtype=float).reshape(-1, 3)
+        if (np.abs(np.linalg.norm(n, axis=1) - 1) > 1e-9).any():
             raise ValueError("normals must be unit vectors")
         g = L["group"].astype(np.int64)
         has2 = "group2" in L.dtype.names
@@ -196,9 +196,9 @@ class Oracle3D:
             raise ValueError("a cut link's group is out of range")
         two = g2 >= 0
         if two.any():
-            if np.abs(np.linalg.norm(n2[two], axis=1) - 1).max() > 1e-9:
+            if (np.abs(np.linalg.norm(n2[two], axis=1) - 1) > 1e-9).any():
                 raise ValueError("second normals must be unit vectors")
-            if np.abs(np.einsum("ma,ma->m", n[two], n2[two])).max() > 1e-9:
+            if (np.abs(np.einsum("ma,ma->m", n[two], n2[two])) > 1e-9).any():
                 raise ValueError("a link through an edge needs orthogonal normals")
         if len(set(zip(site.tolist(), k.tolist()))) != len(site):
             raise ValueError("a cut link is listed twice")

@@ -242,3 +242,27 @@ def test_host_checks_agree_with_the_reference():
         assert (rc != -1) == ref_ok, (it, rc, msg)
         verdicts[ref_ok] += 1
     assert min(verdicts.values()) > 100, verdicts
+
+
+def test_isolated_site_is_refused_on_the_host():
+    """A material site with all 8 links cut (an island of one site) is
+    refused: the kernels' per-site flag byte would read as void.  A pair of
+    sites, each keeping one uncut link, is accepted."""
+    def islands(sites):
+        nx, ny = 9, 7
+        mask = np.zeros((ny, nx), np.uint8)
+        for x, y in sites:
+            mask[y, x] = 1
+        recs = []
+        for x, y in sites:
+            for k in range(1, 9):
+                if mask[(y + G.CY[k]) % ny, (x + G.CX[k]) % nx]:
+                    continue
+                c = np.array([G.CX[k], G.CY[k]], dtype=float)
+                recs.append((y * nx + x, k, 0.5, 0, -1, tuple(c / np.linalg.norm(c)), (0.0, 0.0)))
+        return G.Plate(nx, ny, 0.05, 0.05, 1.0, 0.55, mask, np.array(recs, dtype=G.LINK_DTYPE),
+                       [G.BCGroup(G.DIRICHLET)], periodic_x=True, periodic_y=True)
+    rc, msg = _create(islands([(3, 3)]))
+    assert rc == -1 and "every link is cut" in msg, (rc, msg)
+    rc, msg = _create(islands([(3, 3), (4, 3)]))
+    assert rc in (0, -3), (rc, msg)
