@@ -281,3 +281,31 @@ def test_batch_divergence_is_per_plate(slbm):
     assert np.array_equal(b.solver(sg).displacement(), u_ref)
     print(f"diverged plate retired after {stopped} of 20000 steps")
     b.close()
+
+
+def test_empty_batch_is_a_no_op(slbm):
+    """A batch with no plates steps, polls, autotunes and syncs as a no-op,
+    before its first plate arrives and after its last one leaves; the plates
+    in between, one of them asked for zero steps, give their solo results."""
+    b = slbm.Batch(1 << 30)
+    b.step(10)
+    assert b.poll() == []
+    b.sync()
+    shape = b.launch()
+    assert b.autotune(200) == (*shape, 0.0)          # nothing to time: the shape stays
+    p, p0 = [dataclasses.replace(q, neumann_order=0) for q in oracle_plates(4, 3)[:2]]
+    sl = b.add(p, 30, "fp32")
+    sl0 = b.add(p0, 0, "fp32")                      # a plate asked for zero steps
+    assert b.poll() == [sl0]
+    b.step(40)
+    assert sorted(b.poll()) == sorted([sl, sl0])
+    assert check_like_alone(slbm, p, 30, "fp32", b.solver(sl), b.displacement(sl))
+    assert check_like_alone(slbm, p0, 0, "fp32", b.solver(sl0), b.displacement(sl0))
+    assert b.solver(sl0).time()[0] == 0
+    b.remove(sl)
+    b.remove(sl0)
+    b.step(10)
+    assert b.poll() == []
+    b.sync()
+    assert b.bytes()[0] == 0
+    b.close()

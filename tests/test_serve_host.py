@@ -194,3 +194,19 @@ def test_round_length_follows_the_resident_sites(monkeypatch):
             sleep=clock.sleep)
     # 10 ms at 40e3 sites per microsecond over 1e6 sites: 400 steps a round
     assert b.steps_called[0] == 384
+
+
+def test_empty_trace_and_zero_step_request(monkeypatch):
+    """No requests: nothing is admitted and the summary reports none.  A
+    request for zero steps completes with its rest state, alongside others."""
+    srv, b, clock = server(monkeypatch, budget=10 ** 12)
+    assert srv.run([], clock=clock, sleep=clock.sleep) == []
+    assert b.order == []
+    st = serve.summary([])
+    assert st["requests"] == 0 and st["diverged"] == 0 and st["makespan_s"] == 0.0
+    srv, b, clock = server(monkeypatch, budget=10 ** 12)
+    reqs = [serve.Request(0.0, P("zero", 300), 0), serve.Request(0.0, P("ten", 300), 10)]
+    res = srv.run(reqs, clock=clock, sleep=clock.sleep)
+    assert [r.rejected or r.diverged for r in res] == [False, False]
+    assert all(r.arrival <= r.admitted <= r.finished for r in res)
+    assert serve.summary(res)["requests"] == 2
