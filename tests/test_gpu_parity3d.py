@@ -462,6 +462,67 @@ def test_loaded_islands_few_steps(S3, prec, tol, order):
     check(out, ref, tol, f"loaded islands {prec} order {order}", box)
 
 
+def random_groups(rng, count):
+    """Boundary groups of either kind with small seeded values (user units),
+    a pressure on some Neumann groups, a ramp on some groups."""
+    groups = []
+    for _ in range(count):
+        kind = int(rng.choice([B.DIRICHLET, B.NEUMANN]))
+        value = tuple(float(v) for v in rng.uniform(-5e-5, 5e-5, 3))
+        pressure = float(rng.uniform(0.0, 2e-4)) if kind == B.NEUMANN and rng.random() < 0.5 else 0.0
+        ramp = rng.random() < 0.3
+        groups.append(B.BCGroup3(kind, value, pressure, profile=B.RAMP if ramp else B.STEP,
+                                 ramp_time=float(rng.uniform(3.0, 20.0)) if ramp else 0.0))
+    return groups
+
+
+def random_box(rng, block):
+    """A seeded general geometry: one to three spherical cavities and up to
+    two penny cracks in a box ragged against the 64-site rows, or (block) a
+    rectangular block with a group per face (edges of both kinds, where the
+    two faces share a profile); lambda/mu in [0.5, 1], tau_bar in
+    [0.55, 0.8], a body force, either Neumann order."""
+    nx, ny, nz = int(rng.integers(14, 90)), int(rng.integers(10, 17)), int(rng.integers(10, 15))
+    lm, mu = float(rng.uniform(0.5, 1.0)), 0.05
+    common = dict(lam=lm * mu, mu=mu, tau=float(rng.uniform(0.55, 0.8)),
+                  force=tuple(float(v) for v in rng.uniform(-2e-6, 2e-6, 3)), neumann_order=int(rng.integers(2)))
+    if block:
+        groups = random_groups(rng, 6)
+        for g in groups:                     # faces meeting at an edge share one profile
+            g.profile, g.ramp_time = B.STEP, 0.0
+        lo = [int(rng.integers(1, 4)) for _ in range(3)]
+        hi = [int(rng.integers(l + 1, n - 1)) for l, n in zip(lo, (nx, ny, nz))]
+        return B.block_box3(nx, ny, nz, lo, hi, list(range(6)), groups, **common)
+    groups = random_groups(rng, int(rng.integers(1, 5)))
+    sph = []
+    for _ in range(int(rng.integers(1, 4))):
+        R = float(rng.uniform(1.2, min(ny, nz) / 3.2))
+        c = [float(rng.uniform(R + 1, n - R - 2)) for n in (nx, ny, nz)]
+        sph.append(B.Sphere3(*c, R, int(rng.integers(len(groups)))))
+    cracks = []
+    for _ in range(int(rng.integers(0, 3))):
+        R = float(rng.uniform(1.5, min(ny, nz) / 3.0))
+        cx, cy = float(rng.uniform(R + 1, nx - R - 2)), float(rng.uniform(R + 1, ny - R - 2))
+        cracks.append(B.PennyCrack3(cx, cy, int(rng.integers(2, nz - 2)) + 0.5, R,
+                                    int(rng.integers(len(groups))), int(rng.integers(len(groups)))))
+    return B.sphere_box3(nx, ny, nz, sph, groups, cracks=cracks, **common)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_random_geometries(S3, prec, tol):
+    """Twelve seeded geometries (cavities, cracks, blocks; groups of both
+    kinds, pressures, ramps, either Neumann order) from a seeded velocity
+    field, 12 steps each, against the reference."""
+    rng = np.random.default_rng(2208)
+    for i in range(12):
+        box = random_box(rng, block=(i % 3 == 2))
+        fields = dict(vel=B.random_velocity(box, 500 + i, 1e-4))
+        print(f"random geometry {i}: {box.nx}x{box.ny}x{box.nz}, {len(box.links)} links, "
+              f"{int((box.links['group2'] >= 0).sum())} on edges, order {box.neumann_order}", flush=True)
+        out, ref = run_both(S3, box, prec, 12, fields)
+        check(out, ref, tol, f"random geometry {i} {prec}", box)
+
+
 @pytest.mark.parametrize("prec,tol,steps", [("fp64", FP64_TOL, 30), ("fp32", FP32_TOL, 200)])
 def test_narrow_box_with_cut_links(S3, prec, tol, steps):
     """A box narrower than one 64-site chunk (30 x 15 x 13: each workgroup of
