@@ -392,7 +392,8 @@ int slbm_batch_wait(slbm_batch b, int32_t in_flight);
  * blocks of removed plates not yet reusable) and the budget. */
 int slbm_batch_bytes(slbm_batch b, int64_t* used, int64_t* budget);
 
-/* Waits for the batch's work, then frees every plate and the budget. */
+/* Waits for the batch's work, then frees every plate and the budget.  NULL
+ * is a no-op. */
 int slbm_batch_destroy(slbm_batch b);
 
 /* Plain device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned

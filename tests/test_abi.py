@@ -266,3 +266,43 @@ def test_isolated_site_is_refused_on_the_host():
     assert rc == -1 and "every link is cut" in msg, (rc, msg)
     rc, msg = _create(islands([(3, 3), (4, 3)]))
     assert rc in (0, -3), (rc, msg)
+
+
+def _declared(header):
+    """(name, parameter types) of every function a header declares."""
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", header)).read(), flags=re.S)
+    out = []
+    for m in re.finditer(r"\bint\s+(slbm3?_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+        out.append((m.group(1), [p.strip().rsplit(" ", 1)[0] for p in m.group(2).split(",")]))
+    return out
+
+
+@pytest.mark.parametrize("header", ["slbm.h", "slbm3.h"])
+def test_every_entry_point_refuses_a_null_handle(header):
+    """Every function of the two headers that takes a handle or a batch (or,
+    for the create calls, the parameter block) returns SLBM_E_INVAL with a
+    message when given NULL for it, NULL for every pointer and zero for every
+    number, before any device call; the destroy calls take NULL as a no-op."""
+    L = C.CDLL(S.LIB_PATH)                         # no argument types: plain C calls
+    L.slbm_last_error.restype = C.c_char_p
+    seen = 0
+    for name, types in _declared(header):
+        if name in ("slbm_tile_list_layout", "slbm_copy"):
+            continue                               # no handle (host layout; a plain copy)
+        args = []
+        for t in types:
+            if "*" in t or t in ("slbm_handle", "slbm3_handle", "slbm_batch"):
+                args.append(C.c_void_p(None))
+            elif t in ("int64_t", "size_t"):
+                args.append(C.c_int64(0))
+            else:
+                args.append(C.c_int32(0))
+        f = getattr(L, name)
+        f.restype = C.c_int
+        rc = f(*args)
+        if name.endswith("_destroy"):
+            assert rc == 0, name
+        else:
+            assert rc == -1 and L.slbm_last_error(), (name, rc)
+        seen += 1
+    assert seen == (35 if header == "slbm.h" else 13)
