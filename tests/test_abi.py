@@ -227,7 +227,7 @@ def test_host_checks_agree_with_the_reference():
     each) to a plate with a hole and to a plate with an edge crack."""
     from oracle import Oracle
     rng = np.random.default_rng(2208)
-    verdicts = {True: 0, False: 0}
+    outcomes = {True: 0, False: 0}
     for it in range(1200):
         p = (_plate, _cracked_plate)[it % 2]()
         for _ in range(int(rng.integers(1, 3))):
@@ -240,8 +240,8 @@ def test_host_checks_agree_with_the_reference():
         rc, msg = _create(p)
         assert rc in (0, -3, -1), (it, rc, msg)
         assert (rc != -1) == ref_ok, (it, rc, msg)
-        verdicts[ref_ok] += 1
-    assert min(verdicts.values()) > 100, verdicts
+        outcomes[ref_ok] += 1
+    assert min(outcomes.values()) > 100, outcomes
 
 
 def test_isolated_site_is_refused_on_the_host():

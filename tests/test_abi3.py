@@ -302,7 +302,7 @@ def test_host_checks_agree_with_the_reference():
     block with edges."""
     from oracle.slbm3d import Oracle3D
     rng = np.random.default_rng(2208)
-    verdicts = {True: 0, False: 0}
+    outcomes = {True: 0, False: 0}
     for it in range(900):
         box = (_cavity, _cracked, _block)[it % 3]()
         for _ in range(int(rng.integers(1, 3))):
@@ -315,5 +315,5 @@ def test_host_checks_agree_with_the_reference():
         rc, msg = _create(box)
         assert rc in (0, -3, -1), (it, rc, msg)
         assert (rc != -1) == ref_ok, (it, rc, msg)
-        verdicts[ref_ok] += 1
-    assert min(verdicts.values()) > 50, verdicts
+        outcomes[ref_ok] += 1
+    assert min(outcomes.values()) > 50, outcomes
