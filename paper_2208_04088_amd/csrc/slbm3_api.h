@@ -391,7 +391,7 @@ int grid3(const slbm3_s* h)
 {
     const long long tiles = (long long)((h->nx + 63) / 64) * h->ny * h->nz;
     const long long wg = (tiles + 3) / 4;
-    const long long unit = 8LL * kXcdGroup;           // xcd_group3 permutes whole units
+    const long long unit = 8LL * xcd_group_size3(h->geo);   // xcd_group3 permutes whole units
     return (int)((wg + unit - 1) / unit * unit);
 }
 

@@ -610,20 +610,25 @@ __device__ __forceinline__ void grad3(const Step3Args<real>& a, const Site3& st,
 // kXcdGroup consecutive workgroups, and the groups of the 8 XCDs interleave:
 // the chip streams through one region of the box at a time (one set of 19
 // plane streams rather than one per XCD), while rows that share neighbours
-// stay in one L2.  The grid size is a multiple of 8 kXcdGroup, which makes
-// the map a permutation of the workgroup indices.
-constexpr int kXcdGroup = 16;
+// stay in one L2.  The grid size is a multiple of 8 groups, which makes the
+// map a permutation of the workgroup indices.  Groups of 16 suit the plane
+// walls; a general geometry runs best with groups of 64 (its flags, link
+// records and rule values stay longer in one L2: 0.98 against 1.09 ms per
+// step on the 256^3 porous solid, while the slab is the same within 0.2 %).
+__host__ __device__ constexpr int xcd_group_size3(bool geo) { return geo ? 64 : 16; }
+template <bool GEO>
 __device__ __forceinline__ int xcd_group3(int b)
 {
+    constexpr int G = xcd_group_size3(GEO);
     const int x = b & 7, l = b >> 3;
-    return ((l / kXcdGroup) * 8 + x) * kXcdGroup + l % kXcdGroup;
+    return ((l / G) * 8 + x) * G + l % G;
 }
 
 // delta-rho of the pulled state at every site.
 template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_density(Step3Args<real> a)
 {
-    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3<GEO>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
@@ -645,7 +650,7 @@ __device__ __forceinline__ double recip3(double x) { return 1.0 / x; }
 template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 {
-    const int wg = xcd_group3(blockIdx.x);
+    const int wg = xcd_group3<GEO>(blockIdx.x);
     int tile = wg * 4 + (threadIdx.x >> 6);
     if (wg * 4 >= a.ntiles) return;                     // uniform over the workgroup
     const bool tvalid = tile < a.ntiles;
@@ -726,7 +731,7 @@ __global__ __launch_bounds__(256) void k3_step(Step3Args<real> a)
 template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_outputs(Step3Args<real> a, double* out)
 {
-    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3<GEO>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     real g[kQ];
@@ -773,7 +778,7 @@ __global__ __launch_bounds__(256) void k3_set_dens(Step3Args<real> a, const doub
 template <typename real, bool PX, bool GEO = false>
 __global__ __launch_bounds__(256) void k3_init(Step3Args<real> a, const double* in)
 {
-    const int tile = xcd_group3(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_group3<GEO>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= a.ntiles) return;
     const Site3 st = site_of(tile, threadIdx.x & 63, a.nx, a.ny);
     const unsigned s = sidx3(st.x, st.y, st.z, a.nx, a.ny);
