@@ -196,8 +196,11 @@ int slbm3_device_bytes(slbm3_handle h, int64_t* bytes);
  * of *bytes bytes and sets *bytes to the size used; with buf NULL it only
  * reports the size.  SLBM_E_INVAL when *bytes is too small.  slbm3_load
  * restores a checkpoint on a handle created with the same box, geometry and
- * precision (SLBM_E_INVAL otherwise), so that stepping on gives results
- * bit-identical to an uninterrupted run.  Both synchronise. */
+ * precision (SLBM_E_INVAL otherwise: the checkpoint carries a fingerprint of
+ * the mask and the cut links, or of the walls), so that stepping on gives
+ * results bit-identical to an uninterrupted run.  Loads and time profiles
+ * may differ; the rule values saved with the state were formed with the
+ * saving handle's.  Both synchronise. */
 int slbm3_save(slbm3_handle h, void* buf, size_t* bytes);
 int slbm3_load(slbm3_handle h, const void* buf, size_t bytes);
 

@@ -41,6 +41,7 @@ struct slbm3_s {
     int32_t* wrec = nullptr;         // per workgroup of k3_step: first record
     int32_t* elink = nullptr;        // the records whose Neumann data are extrapolated
     int64_t n_ext = 0;
+    uint64_t geo_hash = 0;           // the geometry a checkpoint must match (mask and cut links, or the walls)
     int64_t n_links = 0;
     size_t link_bytes = 0;
 };
@@ -110,6 +111,19 @@ struct Geo3 {
     std::vector<double> skap;        // per record: kappa (Dirichlet), -kappa (Neumann) or 0 (ext)
     std::vector<int32_t> elink;      // the ext records
     std::vector<int32_t> wrec;       // per workgroup of k3_step: its first record, then the count
+    uint64_t hash = 0;               // FNV-1a of the mask and of each cut link's site, direction, q,
+                                     // groups and normals, in record order
+};
+
+// 64-bit FNV-1a, fed value by value (no struct padding enters it).
+struct Fnv64 {
+    uint64_t h = 0xcbf29ce484222325ull;
+    void bytes(const void* p, size_t n)
+    {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+    }
+    template <typename T> void put(T v) { bytes(&v, sizeof v); }
 };
 
 int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
@@ -250,6 +264,16 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
         const slbm3_link &A = p->links[u], &B = p->links[v];
         return A.site != B.site ? A.site < B.site : A.dir < B.dir;
     });
+    {
+        Fnv64 f;
+        f.bytes(p->mask, (size_t)n);
+        for (int64_t l : order) {
+            const slbm3_link& L = p->links[l];
+            f.put(L.site); f.put(L.dir); f.put(L.q); f.put(L.group); f.put(L.group2);
+            for (int k = 0; k < 3; ++k) { f.put(L.normal[k]); f.put(L.normal2[k]); }
+        }
+        g.hash = f.h;
+    }
     g.bidx.assign((size_t)n, 0);
     g.recs.resize(order.size());
     g.skap.resize(order.size());
@@ -533,11 +557,19 @@ int slbm3_create(const slbm3_params* p, slbm3_handle* out)
             }
         }
         h->norder = p->neumann_order;
+        {
+            // the geometry without cut links: periodic in x, or the two walls' kinds and q
+            Fnv64 f;
+            f.put(h->px);
+            for (int s = 0; s < 2 && !h->px; ++s) { f.put(h->wkind[s]); f.put(h->wq[s]); }
+            h->geo_hash = f.h;
+        }
         Geo3 geo;
         if (p->mask) {
             const int rc = build_geo3(p, h, geo);
             if (rc) { delete h; return rc; }
             h->geo = true;
+            h->geo_hash = geo.hash;
             for (int k = 0; k < kProfileSlots3; ++k) h->slot_ramp[k] = geo.slot_ramp[(size_t)k];
             h->n_links = (int64_t)geo.recs.size();
             h->n_ext = (int64_t)geo.elink.size();
@@ -799,8 +831,9 @@ struct Save3Header {
     int32_t nx, ny, nz, precision;
     int64_t step, n_links, stride;
     int32_t local, diverged;
+    uint64_t geo_hash;
 };
-constexpr uint64_t kMagic3 = 0x3364335f6d626c73ull;    // "slbm_3d3"
+constexpr uint64_t kMagic3 = 0x3464335f6d626c73ull;    // "slbm_3d4"
 
 size_t save3_bytes(const slbm3_s* h)
 {
@@ -819,7 +852,7 @@ int slbm3_save(slbm3_handle h, void* buf, size_t* bytes)
         DeviceGuard dg(h->device);
         const size_t pop = (size_t)19 * h->stride * h->esize, ub = (size_t)3 * h->stride * sizeof(double);
         Save3Header hd{kMagic3, h->nx, h->ny, h->nz, h->precision, h->step, h->n_links, h->stride,
-                       h->local ? 1 : 0, 0};
+                       h->local ? 1 : 0, 0, h->geo_hash};
         unsigned int flag = 0;
         char* p = (char*)buf;
         HIP_TRY(hipMemcpyAsync(&flag, h->diverged, sizeof flag, hipMemcpyDeviceToHost, h->stream));
@@ -846,6 +879,7 @@ int slbm3_load(slbm3_handle h, const void* buf, size_t bytes)
         if (hd.magic != kMagic3 || hd.nx != h->nx || hd.ny != h->ny || hd.nz != h->nz ||
             hd.precision != h->precision || hd.n_links != h->n_links || hd.stride != h->stride)
             return fail(SLBM_E_INVAL, "checkpoint does not match this box");
+        if (hd.geo_hash != h->geo_hash) return fail(SLBM_E_INVAL, "checkpoint of another geometry");
         DeviceGuard dg(h->device);
         const size_t pop = (size_t)19 * h->stride * h->esize, ub = (size_t)3 * h->stride * sizeof(double);
         const char* p = (const char*)buf;

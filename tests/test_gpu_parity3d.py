@@ -650,3 +650,27 @@ def test_checkpoint_resume_is_bit_identical(S3, prec, kind):
     assert np.array_equal(u, u_ref)
     for x, y in zip(mom, mom_ref):
         assert np.array_equal(x, y)
+
+
+def test_checkpoint_of_another_geometry_is_refused(S3):
+    """A checkpoint loads only into a handle of the same geometry: a cavity
+    moved by one site (same box, same number of cut links, so the state has
+    the same size) and a slab whose wall sits at another q are refused."""
+    from paper_2208_04088_amd import slbm
+    groups = [B.BCGroup3(B.NEUMANN, (0.0, 0.0, 0.0), 1e-4)]
+    a = B.sphere_box3(30, 14, 12, [B.Sphere3(10.3, 6.6, 5.8, 3.1, 0)], groups)
+    b = B.sphere_box3(30, 14, 12, [B.Sphere3(11.3, 6.6, 5.8, 3.1, 0)], groups)
+    assert len(a.links) == len(b.links) and not np.array_equal(a.mask, b.mask)
+    s1 = B.slab3(20, 6, 5, B.Wall3(B.DIRICHLET), B.Wall3(B.NEUMANN, q=0.5))
+    s2 = B.slab3(20, 6, 5, B.Wall3(B.DIRICHLET), B.Wall3(B.NEUMANN, q=0.3))
+    for x, y in ((a, b), (s1, s2)):
+        with S3.Solver3(x, "fp32") as s:
+            s.step(3)
+            ck = s.save()
+        with S3.Solver3(y, "fp32") as t:
+            with pytest.raises(slbm.SlbmError) as e:
+                t.load(ck)
+            assert e.value.code == -1 and "geometry" in str(e.value)
+        with S3.Solver3(x, "fp32") as t:
+            t.load(ck)
+            assert t.time()[0] == 3
