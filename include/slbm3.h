@@ -131,16 +131,17 @@ typedef struct {
 } slbm3_params;
 
 /* Creates a box at rest (f = f_eq(rho, 0, 0), U = 0, step 0).  SLBM_E_INVAL
- * for invalid parameters, SLBM_E_UNSUPPORTED above 2^29 sites, SLBM_E_NOMEM
- * or SLBM_E_DEVICE if allocation fails; *out is NULL on failure.  With a mask
+ * for invalid parameters, SLBM_E_UNSUPPORTED above 2^29 sites or with more
+ * than 15 distinct ramp times among the groups, SLBM_E_NOMEM or
+ * SLBM_E_DEVICE if allocation fails; *out is NULL on failure.  With a mask
  * SLBM_E_INVAL also names the first invalid link: a site out of range or
  * void, a direction out of 1..18, q outside (0, 1], a group out of range, a
  * normal that is not a unit vector (to 1e-9), a second group out of range
  * or its normal not a unit vector orthogonal to the first, the two faces of
- * an edge with different time profiles, more than 15 distinct ramp times, a
- * bad profile or a ramp time that is not positive, a link listed twice, a link
- * into the material whose link back is not listed, or a link from the
- * material into the void that is not listed; and an invalid group kind.
+ * an edge with different time profiles, a link listed twice, a link into the
+ * material whose link back is not listed, or a link from the material into
+ * the void that is not listed; and a group with an invalid kind, a bad
+ * profile or a ramp time that is not positive.
  * The arrays are copied. */
 int slbm3_create(const slbm3_params* params, slbm3_handle* out);
 
