@@ -266,7 +266,7 @@ int build_geo3(const slbm3_params* p, const slbm3_s* h, Geo3& g)
     });
     {
         Fnv64 f;
-        f.bytes(p->mask, (size_t)n);
+        for (long long i = 0; i < n; ++i) f.put((uint8_t)(p->mask[i] != 0));   // any nonzero is material
         for (int64_t l : order) {
             const slbm3_link& L = p->links[l];
             f.put(L.site); f.put(L.dir); f.put(L.q); f.put(L.group); f.put(L.group2);
